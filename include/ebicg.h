@@ -1,0 +1,156 @@
+/*
+ * ebicg.h -- C ABI of the MI355X (gfx950) incremental eigBiCG library.
+ *
+ * The library solves A x_i = b_i, i = 1..N_r, for the Wilson-Dirac operator A
+ * (Sec. 1, the main linear problem), grows left and right eigenvectors of A
+ * from a window of BiCG residuals (Alg. eigBiCG with Alg. BiCG-eigen),
+ * accumulates them into a deflation space (Alg. Incremental eigBiCG, step 2)
+ * and deflates the initial guesses of later solves, which run BiCGStab with
+ * the DefTol restart (Alg. Incremental eigBiCG, step 3, and the text after
+ * the listings).
+ *
+ * Conventions shared by every call
+ *  - Plain C: no C++ types and no exceptions cross this boundary.  Every call
+ *    returns an eb_status; on a non-OK status eb_last_error() gives a message.
+ *  - Dot product (w, v) := w^+ v (Sec. 1, end).
+ *  - Site index s = x + Lx*(y + Ly*(z + Lz*t)); directions mu = 0..3 <-> x,y,z,t.
+ *  - Canonical spinor layout (every spinor argument): [V][4 spin][3 colour]
+ *    complex numbers, interleaved (re, im).  Element type by precision:
+ *    EB_FP64 -> two doubles, EB_FP32 -> two floats, EB_BF16 -> two bfloat16.
+ *  - Canonical gauge layout: [4 mu][V][3][3] complex128, U[mu][s][a][b] is
+ *    row a, column b of U_mu(s).
+ *  - Operator: (D psi)(x) = psi(x) - kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *    + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ], periodic in x, y, z; every hop
+ *    across the t boundary is multiplied by bc_t.  Gamma matrices: chiral basis,
+ *    gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]],
+ *    gamma5 = diag(1, 1, -1, -1).  D^+ = gamma5 D gamma5 (Sec. 4).
+ *  - Device pointers are HIP device addresses (e.g. torch tensors'
+ *    data_ptr()); `stream` is a hipStream_t (NULL = the null stream).  Solves
+ *    synchronise their stream before returning; op_apply calls do not.
+ *  - Ownership: the library copies the gauge field and owns the deflation
+ *    space and all work buffers; the caller owns b, x and the outputs.
+ *  - One eb_op is not re-entrant: calls on the same op must not overlap.
+ */
+#ifndef EBICG_H
+#define EBICG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eb_op eb_op;
+
+typedef enum {
+  EB_OK = 0,
+  EB_ERR_INVALID = -1,       /* bad argument (sizes, null pointers, m <= 2 nev, ...) */
+  EB_ERR_OOM = -2,           /* device allocation failed */
+  EB_ERR_BREAKDOWN = -3,     /* (rhat, r) or (phat, A p) vanished (Alg. eigBiCG, step 2) */
+  EB_ERR_NOT_CONVERGED = -4, /* maxiter reached; x holds the last iterate, stats are filled */
+  EB_ERR_HIP = -5,           /* a HIP runtime call failed */
+  EB_ERR_EIG = -6,           /* the small dense eigensolver did not converge */
+  EB_ERR_CAPACITY = -7       /* the deflation space would exceed its capacity */
+} eb_status;
+
+typedef enum { EB_FP64 = 0, EB_FP32 = 1, EB_BF16 = 2 } eb_prec;
+
+/* Parameters of one eigBiCG solve (Alg. eigBiCG). */
+typedef struct {
+  int32_t nev;     /* eigenpairs kept per restart and returned (2 nev < m) */
+  int32_t m;       /* window size */
+  double tol;      /* stop when ||r_j|| <= tol ||b|| (Alg. eigBiCG, last test of the loop) */
+  int32_t maxiter; /* iteration cap */
+  int32_t rhat;    /* shadow residual: 0 -> rhat_0 = r_0 (Sec. 2 "Normally"); 1 -> gamma5 r_0 (Sec. 4) */
+} eb_eig_params;
+
+/* Parameters of a deflated solve (Alg. Incremental eigBiCG, step 3). */
+typedef struct {
+  double tol;       /* target ||b - A x|| / ||b|| (true residual, checked in FP64) */
+  double deftol;    /* DefTol: 0 disables the deflation restart (the setting of Fig. 1) */
+  int32_t maxiter;  /* cap on inner iterations summed over restarts and refinement steps */
+  int32_t method;   /* 0: BiCGStab (the paper's choice), 1: BiCG */
+  eb_prec inner;    /* working precision of the inner iteration; FP32/BF16 run inside FP64 refinement */
+  double inner_tol; /* relative residual reduction per refinement step (ignored for EB_FP64) */
+  int32_t nrhs;     /* right-hand sides solved together (b, x hold nrhs spinors back to back) */
+} eb_solve_params;
+
+/* Per-call statistics. */
+typedef struct {
+  int32_t iters;              /* iterations (summed over the nrhs columns for batched solves) */
+  int32_t matvec_d;           /* applications of D */
+  int32_t matvec_ddag;        /* applications of D^+ */
+  int32_t window_restarts;    /* Alg. BiCG-eigen calls */
+  int32_t defl_restarts;      /* DefTol restarts */
+  int32_t breakdown_restarts; /* reserved */
+  int32_t outer_steps;        /* FP64 refinement steps (mixed precision) */
+  int32_t nev_added;          /* pairs absorbed into the deflation space by this call */
+  double true_rel_resid;      /* max over columns of ||b - A x|| / ||b|| in FP64 */
+  double rec_rel_resid;       /* last recursive residual / ||b|| */
+  double seconds;             /* wall time of the call */
+} eb_stats;
+
+/* Create an operator: copies gauge (host, canonical layout) to the device.
+ * dims: Lx, Ly, Lz, Lt, each >= 2.  bc_t: -1 antiperiodic, +1 periodic in t.
+ * defl_capacity: maximum number K of left/right pairs the deflation space holds
+ * (its 2 K FP64 spinors are allocated on first use).  Device: the current HIP device. */
+eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t,
+                       int32_t defl_capacity, eb_op **out);
+eb_status eb_op_destroy(eb_op *op);
+
+/* out = D in, and out = D^+ in (Alg. eigBiCG, first step of the loop).  in/out:
+ * device, canonical layout, element type given by prec; they must not overlap.
+ * Asynchronous on `stream`. */
+eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
+eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
+
+/* One solve of the first phase of Alg. Incremental eigBiCG (step 2): deflate
+ * x0 with the current space (if K > 0), run eigBiCG in FP64, continue with
+ * BiCGStab if the FP64 true residual is above tol, then biorthogonalise the nev
+ * new pairs against the space and extend H = U_l^+ A U_r.
+ * b: device, FP64 canonical; x: device, FP64 canonical, in: x0, out: solution.
+ * ritz (host, may be NULL): receives the nev Ritz values of this solve as
+ * complex128 (re, im pairs), ordered by |lambda| ascending. */
+eb_status eb_eigbicg_solve(eb_op *op, const void *b, void *x, const eb_eig_params *p, double *ritz,
+                           eb_stats *st, void *stream);
+
+/* A solve of the second phase (step 3): x0 += U_r H^{-1} U_l^+ (b - A x0),
+ * then BiCGStab (or BiCG) with the DefTol restart; FP32/BF16 inner precision
+ * runs inside FP64 iterative refinement.  b, x: device, FP64 canonical,
+ * p->nrhs spinors back to back.  Does not change the deflation space. */
+eb_status eb_deflated_bicg_solve(eb_op *op, const void *b, void *x, const eb_solve_params *p,
+                                 eb_stats *st, void *stream);
+
+/* Eigenpairs of A from the deflation space by Rayleigh-Ritz (text after the
+ * listings): eig(H), H = U_l^+ A U_r.  On input *k is the capacity of the
+ * outputs, on output the number written (min(*k, K)), ordered by |lambda|.
+ * evals: host complex128[k]; right/left: device FP64 canonical, k spinors each,
+ * or NULL.  Right vectors have unit norm and left_i^+ right_i = 1. */
+eb_status eb_get_eigenpairs(eb_op *op, int32_t *k, double *evals, void *right, void *left, void *stream);
+
+/* Current size K of the deflation space, and a copy of H (host complex128
+ * K x K, row-major; may be NULL). */
+eb_status eb_defl_info(eb_op *op, int32_t *K, double *H);
+/* Empty the deflation space (K = 0). */
+eb_status eb_defl_reset(eb_op *op);
+
+/* The small dense eigenproblem [y, z, lambda] = eig(C) of Sec. 1 (end), as
+ * used on the window matrix: C host complex128 n x n row-major; lambda host
+ * complex128[n]; y, z host complex128 n x n row-major, column i the right /
+ * left vector of lambda_i (may be NULL).  Sorted by |lambda| ascending, ties
+ * by imaginary part descending; ||y_i|| = 1 and z_i^+ y_i = 1.  Host-only,
+ * needs no GPU.  EB_ERR_EIG if the QR iteration does not converge. */
+eb_status eb_small_eig(int32_t n, const double *C, double *lambda, double *y, double *z);
+
+/* Message of the last non-OK status on this thread (empty if none). */
+void eb_last_error(char *buf, size_t len);
+
+/* Library version string. */
+const char *eb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBICG_H */

@@ -1,0 +1,1270 @@
+// C ABI of the library (include/ebicg.h): operator creation, D / D^+
+// application, eigBiCG solves that grow the deflation space, deflated
+// BiCGStab solves (FP64, or FP32 inner inside FP64 refinement), and the
+// Rayleigh-Ritz eigenpairs of the space.
+//
+// Host-side orchestration only: every vector operation runs in kernels.hip.
+// The BiCG scalars stay on the device; the host polls a stop flag every few
+// iterations and, for eigBiCG, assembles the window matrix H from the scalar
+// history (Alg. eigBiCG: H needs no extra matvecs) in a worker thread, so the
+// m x m eigenproblems of Alg. BiCG-eigen overlap the GPU iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ebicg.h"
+#include "hostla.h"
+#include "kernels.h"
+
+using namespace ebicg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct EbError {
+  eb_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(eb_status code, const std::string &msg) { throw EbError{code, msg}; }
+
+void hipchk(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(EB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(expr) hipchk((expr), #expr)
+
+template <typename F>
+eb_status guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return EB_OK;
+  } catch (const EbError &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return EB_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return EB_ERR_INVALID;
+  }
+}
+
+inline double2 d2(cd z) { return make_double2(z.real(), z.imag()); }
+inline cd c2(double2 z) { return cd(z.x, z.y); }
+
+// Device allocation owned by the op.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      fail(EB_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+struct PinnedBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) fail(EB_ERR_OOM, "hipHostMalloc failed");
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+}  // namespace
+
+// ============================================================================
+// the operator object
+// ============================================================================
+struct eb_op {
+  Geom g{};
+  size_t N = 0;
+  double kappa = 0;
+  int bc_t = -1;
+  int device = 0;
+  DevBuf U64, U32;
+  // deflation space: Ul, Ur hold Kcap FP64 SoA spinors each; H = Ul^+ A Ur on the host
+  int Kcap = 0, K = 0;
+  DevBuf Ul, Ur;
+  CMat H;
+  // reduction scratch and solver state
+  DevBuf partials, tickets, state, res, hist;
+  int hist_cap = 0;
+  PinnedBuf hstate, hres, hhist;
+  std::map<std::string, DevBuf> bufs;
+  RedScratch rs() { return RedScratch{partials.as<double>(), tickets.as<unsigned>()}; }
+  KrylovState *S() { return state.as<KrylovState>(); }
+  double2 *vec(const std::string &name, size_t count = 1) {
+    DevBuf &b = bufs[name];
+    b.ensure(count * N * sizeof(double2));
+    return b.as<double2>();
+  }
+  template <typename T>
+  T *raw(const std::string &name, size_t bytes) {
+    DevBuf &b = bufs[name];
+    b.ensure(bytes);
+    return b.as<T>();
+  }
+  KrylovHistory history(int need) {
+    if (need > hist_cap) {
+      hist_cap = std::max(need, 2 * hist_cap);
+      size_t bytes = size_t(hist_cap) * (3 * sizeof(double2) + sizeof(double));
+      hist.release();
+      hist.ensure(bytes);
+      hhist.release();
+      hhist.ensure(bytes);
+    }
+    return view(hist.p);
+  }
+  KrylovHistory view(void *base) const {
+    char *b = static_cast<char *>(base);
+    KrylovHistory h;
+    h.alpha = reinterpret_cast<double2 *>(b);
+    h.beta = reinterpret_cast<double2 *>(b + size_t(hist_cap) * sizeof(double2));
+    h.rho = reinterpret_cast<double2 *>(b + 2 * size_t(hist_cap) * sizeof(double2));
+    h.rn = reinterpret_cast<double *>(b + 3 * size_t(hist_cap) * sizeof(double2));
+    return h;
+  }
+  void free_all() {
+    U64.release();
+    U32.release();
+    Ul.release();
+    Ur.release();
+    partials.release();
+    tickets.release();
+    state.release();
+    res.release();
+    hist.release();
+    hstate.release();
+    hres.release();
+    hhist.release();
+    for (auto &kv : bufs) kv.second.release();
+    bufs.clear();
+  }
+};
+
+namespace {
+
+void set_device(eb_op *op) { HIPCHK(hipSetDevice(op->device)); }
+
+void fetch_state(eb_op *op, hipStream_t s, KrylovState &out) {
+  HIPCHK(hipMemcpyAsync(op->hstate.p, op->state.p, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  out = *op->hstate.as<KrylovState>();
+}
+
+// Watches the device stop flag without draining the queue: each step() first
+// waits for the copy issued at the previous step (poll interval iterations
+// ago), then issues a new one.
+struct Poller {
+  const KrylovState *dev = nullptr;
+  hipStream_t s = nullptr;
+  PinnedBuf host;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int issued = 0;
+  Poller(const KrylovState *d, hipStream_t st) : dev(d), s(st) {
+    host.ensure(2 * sizeof(KrylovState));
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  }
+  ~Poller() {
+    if (issued > 0) (void)hipEventSynchronize(ev[(issued - 1) & 1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    host.release();
+  }
+  bool step(KrylovState &out) {
+    if (issued > 0) {
+      const int k = (issued - 1) & 1;
+      HIPCHK(hipEventSynchronize(ev[k]));
+      const KrylovState &h = host.as<KrylovState>()[k];
+      if (h.stopped) {
+        out = h;
+        return true;
+      }
+    }
+    const int k = issued & 1;
+    HIPCHK(hipMemcpyAsync(host.as<KrylovState>() + k, dev, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ev[k], s));
+    ++issued;
+    return false;
+  }
+};
+
+// r = b - D x in FP64; returns (||r||, ||b||).
+std::pair<double, double> residual(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s) {
+  launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+  HIPCHK(hipMemcpyAsync(op->hres.p, op->res.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double *h = op->hres.as<double>();
+  return {std::sqrt(h[0]), std::sqrt(h[1])};
+}
+
+// x <- x + U_r d with H d = U_l^+ (b - A x)  (Alg. Incremental eigBiCG, step 2
+// first item and step 3 first item).  Returns ||b - A x|| before the update.
+double deflate_guess(eb_op *op, const double2 *b, double2 *x, hipStream_t s) {
+  double2 *r = op->vec("defl_r");
+  auto [rn, bn] = residual(op, r, b, x, s);
+  (void)bn;
+  if (op->K == 0) return rn;
+  const int K = op->K;
+  double2 *c = op->raw<double2>("defl_c", size_t(K) * sizeof(double2));
+  launch_ts_dot(c, op->Ul.as<double2>(), op->N, K, r, op->N, 1, op->N, op->rs(), s);
+  std::vector<double2> hc(K);
+  HIPCHK(hipMemcpyAsync(hc.data(), c, K * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<cd> d(K);
+  for (int i = 0; i < K; ++i) d[i] = c2(hc[i]);
+  if (!lu_solve(op->H, d)) fail(EB_ERR_EIG, "deflation matrix H is singular");
+  for (int i = 0; i < K; ++i) hc[i] = d2(d[i]);
+  HIPCHK(hipMemcpyAsync(c, hc.data(), K * sizeof(double2), hipMemcpyHostToDevice, s));
+  launch_ts_update(x, op->N, 1, op->Ur.as<double2>(), op->N, K, c, 1.0, op->N, s);
+  HIPCHK(hipStreamSynchronize(s));
+  return rn;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab driver (storage S).  Solves A x = b from the current x with the
+// given residual r = b - A x already in `r`; stops on convergence
+// (||r|| <= tol_abs), on the DefTol threshold, on breakdown or maxiter.
+// ---------------------------------------------------------------------------
+struct StabResult {
+  int iters = 0;
+  int reason = 0;
+  double rnorm = 0;
+};
+
+template <typename S>
+StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, double def_thr, int maxiter,
+                        const std::string &tag, hipStream_t s) {
+  const size_t N = op->N;
+  S *rhat = op->raw<S>(tag + "rhat", N * sizeof(S));
+  S *p = op->raw<S>(tag + "p", N * sizeof(S));
+  S *v = op->raw<S>(tag + "v", N * sizeof(S));
+  S *sv = op->raw<S>(tag + "s", N * sizeof(S));
+  S *t = op->raw<S>(tag + "t", N * sizeof(S));
+  KrylovState *K = op->S();
+  launch_stab_init<S>(rhat, p, r, N, tol_abs, def_thr, maxiter, K, op->rs(), s);
+  KrylovState hs;
+  fetch_state(op, s, hs);
+  StabResult out;
+  if (hs.stopped) {
+    out.reason = hs.reason;
+    out.rnorm = hs.rnorm;
+    return out;
+  }
+  const int poll = 8;
+  int j = 0;
+  bool stopped = false;
+  {
+    Poller pl(K, s);
+    while (j < maxiter) {
+      ++j;
+      launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, op->rs(), s);
+      launch_stab_s<S>(sv, r, v, N, j, K, s);
+      launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, op->rs(), s);
+      launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, op->rs(), s);
+      launch_stab_p<S>(p, r, v, N, j, K, s);
+      if (j % poll == 0 && pl.step(hs)) {
+        stopped = true;
+        break;
+      }
+    }
+  }
+  if (!stopped) fetch_state(op, s, hs);
+  out.iters = hs.stopped ? hs.stop_at : j;
+  out.reason = hs.stopped ? hs.reason : 4;
+  out.rnorm = hs.rnorm;
+  return out;
+}
+
+// FP64 BiCGStab with the DefTol deflation restarts and the true-residual
+// check; x is the (already deflated) start.  Accumulates into st.
+void deflated_stab_f64(eb_op *op, const double2 *b, double2 *x, double tol, double deftol, int maxiter,
+                       eb_stats &st, hipStream_t s) {
+  double2 *r = op->vec("stab_r");
+  double thr_factor = deftol;
+  while (true) {
+    auto [rn, bn] = residual(op, r, b, x, s);
+    st.matvec_d += 1;
+    if (bn == 0.0) {
+      HIPCHK(hipMemsetAsync(x, 0, op->N * sizeof(double2), s));
+      st.true_rel_resid = 0;
+      return;
+    }
+    st.true_rel_resid = rn / bn;
+    if (rn <= tol * bn) return;
+    int left = maxiter - st.iters;
+    if (left <= 0) fail(EB_ERR_NOT_CONVERGED, "deflated solve: maxiter reached");
+    const double def_thr = (op->K > 0 && deftol > 0) ? thr_factor * bn : 0.0;
+    StabResult R = run_bicgstab<double2>(op, op->U64.as<double2>(), x, r, tol * bn, def_thr, left, "f64_", s);
+    st.iters += R.iters;
+    st.matvec_d += 2 * R.iters;
+    st.rec_rel_resid = R.rnorm / bn;
+    if (R.reason == 2) fail(EB_ERR_BREAKDOWN, "BiCGStab breakdown");
+    if (R.reason == 3) {
+      deflate_guess(op, b, x, s);
+      st.defl_restarts += 1;
+      thr_factor *= deftol;
+    }
+  }
+}
+
+// FP32 inner BiCGStab inside FP64 iterative refinement (defect correction).
+void mixed_stab_f32(eb_op *op, const double2 *b, double2 *x, double tol, double inner_tol, int maxiter,
+                    eb_stats &st, hipStream_t s) {
+  const size_t N = op->N;
+  if (!op->U32.p) {
+    op->U32.ensure(size_t(36) * op->g.V * sizeof(float2));
+    launch_convert_f64_f32(op->U32.as<float2>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
+  }
+  double2 *r = op->vec("mix_r");
+  double2 *e64 = op->vec("mix_e64");
+  float2 *r32 = op->raw<float2>("mix_r32", N * sizeof(float2));
+  float2 *e32 = op->raw<float2>("mix_e32", N * sizeof(float2));
+  int outer = 0;
+  while (true) {
+    if (op->K > 0) deflate_guess(op, b, x, s);
+    auto [rn, bn] = residual(op, r, b, x, s);
+    st.matvec_d += 1;
+    if (bn == 0.0) {
+      st.true_rel_resid = 0;
+      return;
+    }
+    st.true_rel_resid = rn / bn;
+    if (rn <= tol * bn) return;
+    int left = maxiter - st.iters;
+    if (left <= 0 || outer > 200) fail(EB_ERR_NOT_CONVERGED, "mixed-precision solve: maxiter reached");
+    launch_convert_f64_f32(r32, r, N, s);
+    HIPCHK(hipMemsetAsync(e32, 0, N * sizeof(float2), s));
+    // inner target: reduce this residual by inner_tol, but not below what FP64 needs
+    const double inner_abs = std::max(inner_tol * rn, 0.5 * tol * bn);
+    StabResult R = run_bicgstab<float2>(op, op->U32.as<float2>(), e32, r32, inner_abs, 0.0, left, "f32_", s);
+    st.iters += R.iters;
+    st.matvec_d += 2 * R.iters;
+    if (R.reason == 2 && R.iters == 0) fail(EB_ERR_BREAKDOWN, "inner BiCGStab breakdown");
+    launch_convert_f32_f64(e64, e32, N, s);
+    launch_add_f64(x, e64, N, s);
+    ++outer;
+    st.outer_steps = outer;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// eigBiCG (Alg. eigBiCG with Alg. BiCG-eigen), FP64
+// ---------------------------------------------------------------------------
+// A window column: a stored BiCG residual (raw r_i in V, raw rhat_i in W) or a
+// Ritz vector written by a restart.  Stored residuals carry their scale in H's
+// coefficients: v = r_i / ||r_i||, w = (||r_i|| / conj(rho_i)) rhat_i.
+struct Col {
+  int ritz;  // 1: Ritz column k of the current block, 0: residual
+  int idx;   // Ritz index, or the iteration i of r_i
+  int slot;  // physical slot (-1: placeholder of a pending restart)
+};
+
+// The latest applied restart: its Ritz values and the raw arrow dots.
+struct RitzBlock {
+  int jr = 0;  // restart iteration
+  std::vector<cd> lam;
+  std::vector<cd> dV, dW;  // GA^+ V_new[:,k] and W_new[:,k]^+ GB
+};
+
+struct HostHist {
+  const double2 *alpha, *beta, *rho;
+  const double *rn;
+};
+
+// H^(n) of the window described by cols (Alg. eigBiCG, H assembly steps;
+// arrow entries from the dots of the last restart).
+CMat build_H(const std::vector<Col> &cols, const HostHist &h, const RitzBlock &rb) {
+  const int n = int(cols.size());
+  CMat H(n, n);
+  for (int c = 0; c < n; ++c) {
+    const Col &C = cols[c];
+    if (C.ritz) {
+      H(c, c) = rb.lam[C.idx];
+      continue;
+    }
+    const int i = C.idx;
+    cd d = 1.0 / c2(h.alpha[i]);
+    if (i >= 1) d += c2(h.beta[i - 1]) / c2(h.alpha[i - 1]);
+    H(c, c) = d;
+    if (c + 1 < n && !cols[c + 1].ritz) {
+      const cd a = c2(h.alpha[i]), be = c2(h.beta[i]);
+      H(c, c + 1) = -(h.rn[i] / h.rn[i + 1]) * be / a;
+      H(c + 1, c) = -(h.rn[i + 1] / h.rn[i]) / a;
+    }
+    if (c > 0 && cols[c - 1].ritz) {
+      // first residual after the Ritz block: the arrow row and column
+      const double rn = h.rn[i];
+      const cd rho = c2(h.rho[i]);
+      for (int k = 0; k < c; ++k) {
+        const int rk = cols[k].idx;
+        H(c, k) = (rn / rho) * rb.dV[rk];
+        H(k, c) = rb.dW[rk] / rn;
+      }
+    }
+  }
+  return H;
+}
+
+// Two-sided Gram-Schmidt (twice) of columns start.. of Y, Z against the
+// earlier ones (which satisfy Z^+ Y = I); pairs with a tiny pivot are dropped.
+void biorth_coeff(CMat &Y, CMat &Z, int start) {
+  const int n = Y.rows;
+  std::vector<std::vector<cd>> ys, zs;
+  for (int k = 0; k < start; ++k) {
+    ys.emplace_back(Y.col(k), Y.col(k) + n);
+    zs.emplace_back(Z.col(k), Z.col(k) + n);
+  }
+  for (int k = start; k < Y.cols; ++k) {
+    std::vector<cd> y(Y.col(k), Y.col(k) + n), z(Z.col(k), Z.col(k) + n);
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t q = 0; q < ys.size(); ++q) {
+        cd a = 0, b = 0;
+        for (int i = 0; i < n; ++i) {
+          a += std::conj(zs[q][i]) * y[i];
+          b += std::conj(ys[q][i]) * z[i];
+        }
+        for (int i = 0; i < n; ++i) {
+          y[i] -= ys[q][i] * a;
+          z[i] -= zs[q][i] * b;
+        }
+      }
+    cd piv = 0;
+    double ny = 0, nz = 0;
+    for (int i = 0; i < n; ++i) {
+      piv += std::conj(z[i]) * y[i];
+      ny += std::norm(y[i]);
+      nz += std::norm(z[i]);
+    }
+    ny = std::sqrt(ny);
+    nz = std::sqrt(nz);
+    if (std::abs(piv) <= 1e-12 * ny * nz) continue;
+    for (auto &e : y) e /= ny;
+    piv /= ny;
+    for (auto &e : z) e /= std::conj(piv);
+    ys.push_back(y);
+    zs.push_back(z);
+  }
+  const int kept = int(ys.size());
+  CMat Yo(n, kept), Zo(n, kept);
+  for (int k = 0; k < kept; ++k)
+    for (int i = 0; i < n; ++i) {
+      Yo(i, k) = ys[k][i];
+      Zo(i, k) = zs[k][i];
+    }
+  Y = Yo;
+  Z = Zo;
+}
+
+// Column scales of the stored vectors: V = V_stored diag(eta), W = W_stored diag(zeta).
+void col_scales(const std::vector<Col> &cols, const HostHist &h, std::vector<cd> &eta, std::vector<cd> &zeta) {
+  eta.resize(cols.size());
+  zeta.resize(cols.size());
+  for (size_t c = 0; c < cols.size(); ++c) {
+    if (cols[c].ritz) {
+      eta[c] = zeta[c] = 1.0;
+    } else {
+      const int i = cols[c].idx;
+      eta[c] = 1.0 / h.rn[i];
+      zeta[c] = h.rn[i] / std::conj(c2(h.rho[i]));
+    }
+  }
+}
+
+struct RestartJob {
+  int jr = 0, nev = 0;
+  std::vector<Col> cols;
+  RitzBlock prev;
+  HostHist h{};
+  // results
+  bool ok = false;
+  std::string err;
+  int kept = 0;
+  std::vector<cd> lam;
+  std::vector<double2> CVraw, CWraw;  // m x kept, column-major
+  std::atomic<bool> done{false};
+  std::thread th;
+
+  void run() {
+    try {
+      const int m = int(cols.size());
+      CMat H = build_H(cols, h, prev);
+      std::vector<cd> l1, l2;
+      CMat y1, z1, y2, z2;
+      if (!eig_small(H, l1, y1, z1)) throw std::runtime_error("eig(H^(m)) failed");
+      CMat Hm1(m - 1, m - 1);
+      for (int jj = 0; jj < m - 1; ++jj)
+        for (int i = 0; i < m - 1; ++i) Hm1(i, jj) = H(i, jj);
+      if (!eig_small(Hm1, l2, y2, z2)) throw std::runtime_error("eig(H^(m-1)) failed");
+      // [y^(m)_1..nev, y^(m-1)_1..nev] with a zero appended to the latter
+      CMat Y(m, 2 * nev), Z(m, 2 * nev);
+      for (int k = 0; k < nev; ++k)
+        for (int i = 0; i < m; ++i) {
+          Y(i, k) = y1(i, k);
+          Z(i, k) = z1(i, k);
+          Y(i, nev + k) = (i < m - 1) ? y2(i, k) : cd(0);
+          Z(i, nev + k) = (i < m - 1) ? z2(i, k) : cd(0);
+        }
+      biorth_coeff(Y, Z, nev);
+      // T = Zt^+ H Yt, [u, q, Lambda] = eig(T)
+      CMat T = matmul(adjoint(Z), matmul(H, Y));
+      CMat u, q;
+      if (!eig_small(T, lam, u, q)) throw std::runtime_error("eig(T) failed");
+      CMat CV = matmul(Y, u), CW = matmul(Z, q);
+      kept = CV.cols;
+      std::vector<cd> eta, zeta;
+      col_scales(cols, h, eta, zeta);
+      CVraw.resize(size_t(m) * kept);
+      CWraw.resize(size_t(m) * kept);
+      for (int k = 0; k < kept; ++k) {
+        double nrm = 0;
+        for (int i = 0; i < m; ++i) nrm += std::norm(CV(i, k));
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < m; ++i) {
+          CVraw[i + size_t(k) * m] = d2(eta[i] * CV(i, k) / nrm);
+          CWraw[i + size_t(k) * m] = d2(zeta[i] * CW(i, k) * nrm);
+        }
+      }
+      ok = true;
+    } catch (const std::exception &e) {
+      err = e.what();
+      ok = false;
+    }
+    done.store(true, std::memory_order_release);
+  }
+};
+
+struct EigBiCGOut {
+  int iters = 0;
+  int restarts = 0;
+  int reason = 0;
+  double rnorm = 0;
+  std::vector<cd> ritz;
+  int nvec = 0;  // Ritz pairs written to Ur[:, K..), Ul[:, K..)
+};
+
+EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_params &P, hipStream_t s) {
+  const size_t N = op->N;
+  const int m = P.m, nev = P.nev;
+  const int lag = 8;
+  const int nslots = m + 1 + lag + 2 * nev;
+  const size_t ncoef = size_t(m + 1) * 2 * nev;  // one coefficient block (m x 2nev complex)
+  double2 *Vw = op->vec("win_V", nslots);
+  double2 *Ww = op->vec("win_W", nslots);
+  double2 *p = op->vec("bicg_p"), *ph = op->vec("bicg_ph");
+  double2 *Ap = op->vec("bicg_Ap", 2), *Adp = op->vec("bicg_Adp", 2);
+  double2 *GA = op->vec("bicg_GA"), *GB = op->vec("bicg_GB");
+  double2 *coef = op->raw<double2>("rot_coef", 4 * ncoef * sizeof(double2));  // 2 ring slots x (V, W)
+  double2 *dots = op->raw<double2>("rot_dots", 2 * size_t(2 * nev) * sizeof(double2));
+  KrylovHistory dh = op->history(P.maxiter + 4);
+  const KrylovHistory hv = op->view(op->hhist.p);
+  const HostHist hh{hv.alpha, hv.beta, hv.rho, hv.rn};
+  KrylovState *S = op->S();
+  auto V = [&](int slot) { return Vw + size_t(slot) * N; };
+  auto W = [&](int slot) { return Ww + size_t(slot) * N; };
+
+  EigBiCGOut out;
+  // r_0 in V slot 0, rhat_0 in W slot 0
+  launch_residual_f64(V(0), b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+  launch_bicg_init(W(0), p, ph, V(0), op->res.as<double>(), N, P.rhat, op->g, P.tol, P.maxiter, S, dh, op->rs(), s);
+  KrylovState hs;
+  fetch_state(op, s, hs);
+  if (hs.stopped) {
+    out.reason = hs.reason;
+    out.rnorm = hs.rnorm;
+    if (hs.reason == 2) fail(EB_ERR_BREAKDOWN, "eigBiCG: (rhat_0, r_0) = 0");
+    return out;
+  }
+
+  std::deque<int> free_slots;
+  for (int k = 1; k < nslots; ++k) free_slots.push_back(k);
+  std::vector<int> slot_of_r(size_t(P.maxiter) + 2, -1);
+  slot_of_r[0] = 0;
+  std::vector<Col> cols;
+  RitzBlock rb;
+  std::unique_ptr<RestartJob> job;
+  // host mirror of the history: after iteration j the device holds alpha, beta
+  // for indices < j and rho, rn for indices <= j
+  int ab_copied = 0, rr_copied = 0;
+
+  // pinned staging: [0] state at a restart point, [1..] arrow dots, coefficient ring
+  PinnedBuf pstate, pdots, pcoef;
+  pstate.ensure(sizeof(KrylovState));
+  pdots.ensure(2 * size_t(2 * nev) * sizeof(double2));
+  pcoef.ensure(4 * ncoef * sizeof(double2));
+  hipEvent_t ev_hist = nullptr, ev_coef[2] = {nullptr, nullptr};
+  bool coef_used[2] = {false, false};
+  int coef_ring = 0;
+  HIPCHK(hipEventCreateWithFlags(&ev_hist, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ev_coef[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ev_coef[1], hipEventDisableTiming));
+  struct Cleanup {
+    std::function<void()> f;
+    ~Cleanup() { f(); }
+  } cleanup{[&]() {
+    if (job && job->th.joinable()) job->th.join();
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev_hist);
+    (void)hipEventDestroy(ev_coef[0]);
+    (void)hipEventDestroy(ev_coef[1]);
+    pstate.release();
+    pdots.release();
+    pcoef.release();
+  }};
+
+  // Upload a (V, W) pair of coefficient blocks through the pinned ring; returns device pointers.
+  auto upload_coef = [&](const std::vector<double2> &cv, const std::vector<double2> &cw) {
+    const int r = coef_ring;
+    coef_ring ^= 1;
+    if (coef_used[r]) HIPCHK(hipEventSynchronize(ev_coef[r]));
+    double2 *hc = pcoef.as<double2>() + size_t(r) * 2 * ncoef;
+    std::copy(cv.begin(), cv.end(), hc);
+    std::copy(cw.begin(), cw.end(), hc + ncoef);
+    double2 *dc = coef + size_t(r) * 2 * ncoef;
+    HIPCHK(hipMemcpyAsync(dc, hc, cv.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dc + ncoef, hc + ncoef, cw.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(ev_coef[r], s));
+    coef_used[r] = true;
+    return std::make_pair(dc, dc + ncoef);
+  };
+  auto copy_history = [&](int jdone) {  // the history as it stands after iteration jdone -> host
+    const int ab = jdone - ab_copied, rr = jdone + 1 - rr_copied;
+    if (ab > 0) {
+      HIPCHK(hipMemcpyAsync(hv.alpha + ab_copied, dh.alpha + ab_copied, ab * sizeof(double2), hipMemcpyDeviceToHost,
+                            s));
+      HIPCHK(hipMemcpyAsync(hv.beta + ab_copied, dh.beta + ab_copied, ab * sizeof(double2), hipMemcpyDeviceToHost,
+                            s));
+      ab_copied = jdone;
+    }
+    if (rr > 0) {
+      HIPCHK(hipMemcpyAsync(hv.rho + rr_copied, dh.rho + rr_copied, rr * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hv.rn + rr_copied, dh.rn + rr_copied, rr * sizeof(double), hipMemcpyDeviceToHost, s));
+      rr_copied = jdone + 1;
+    }
+  };
+  auto copy_dots = [&]() {
+    if (rb.lam.empty()) return;
+    HIPCHK(hipMemcpyAsync(pdots.p, dots, 2 * size_t(2 * nev) * sizeof(double2), hipMemcpyDeviceToHost, s));
+  };
+  auto load_dots = [&]() {  // after an event that followed copy_dots
+    if (rb.lam.empty()) return;
+    const double2 *pd = pdots.as<double2>();
+    const int kept = int(rb.lam.size());
+    rb.dV.resize(kept);
+    rb.dW.resize(kept);
+    for (int k = 0; k < kept; ++k) {
+      rb.dV[k] = c2(pd[k]);
+      rb.dW[k] = c2(pd[2 * nev + k]);
+    }
+  };
+  // Apply a finished restart: rotate the old window into `kept` fresh slots
+  // (with the arrow dots), free the old slots, replace the placeholders.
+  auto apply_job = [&]() {
+    if (!job) return;
+    if (job->th.joinable()) job->th.join();
+    if (!job->ok) fail(EB_ERR_EIG, "window restart: " + job->err);
+    const int kept = job->kept, mm = int(job->cols.size());
+    SlotList in{}, outl{};
+    in.n = mm;
+    for (int c = 0; c < mm; ++c) in.idx[c] = job->cols[c].slot;
+    outl.n = kept;
+    for (int k = 0; k < kept; ++k) {
+      if (free_slots.empty()) fail(EB_ERR_INVALID, "window slots exhausted");
+      outl.idx[k] = free_slots.front();
+      free_slots.pop_front();
+    }
+    auto [cV, cW] = upload_coef(job->CVraw, job->CWraw);
+    launch_rotate(Vw, outl, Vw, in, cV, N, GA, 0, dots, job->jr, S, op->rs(), s);
+    launch_rotate(Ww, outl, Ww, in, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s);
+    for (int c = 0; c < mm; ++c) free_slots.push_back(job->cols[c].slot);
+    std::vector<Col> nc;
+    for (int k = 0; k < kept; ++k) nc.push_back(Col{1, k, outl.idx[k]});
+    for (const Col &c : cols)
+      if (!(c.ritz && c.slot < 0)) nc.push_back(c);
+    cols.swap(nc);
+    rb.jr = job->jr;
+    rb.lam = job->lam;
+    rb.dV.clear();
+    rb.dW.clear();
+    out.restarts += 1;
+    job.reset();
+  };
+
+  const int poll = 8;
+  int j = 0;
+  bool stopped = false;
+  int stop_at = 0, reason = 0;
+  double rnorm = 0;
+  {
+    Poller pl(S, s);
+    while (true) {
+      ++j;
+      if (j > P.maxiter + 1) break;
+      const int cur = j & 1, prv = cur ^ 1;
+      if (int(cols.size()) == m) {
+        // Restart at iteration j (vs = m).  History through j-1 was shipped at
+        // the end of iteration j-1; the iterate itself is never held up.
+        HIPCHK(hipEventSynchronize(ev_hist));
+        const KrylovState *ps = pstate.as<KrylovState>();
+        if (ps->stopped) {
+          stopped = true;
+          stop_at = ps->stop_at;
+          reason = ps->reason;
+          rnorm = ps->rnorm;
+          break;
+        }
+        load_dots();
+        launch_bicg_matvec(Ap + cur * N, Adp + cur * N, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
+                           op->rs(), s);
+        // q = A p and s = A^+ phat were kept from iteration j-1 (vs = m-1)
+        launch_arrow_vectors(GA, GB, Adp + cur * N, Adp + prv * N, Ap + cur * N, Ap + prv * N, N, j, S, dh, s);
+        job.reset(new RestartJob);
+        job->jr = j;
+        job->nev = nev;
+        job->cols = cols;
+        job->prev = rb;
+        job->h = hh;
+        job->th = std::thread([jp = job.get()]() { jp->run(); });
+        cols.clear();
+        for (int k = 0; k < 2 * nev; ++k) cols.push_back(Col{1, k, -1});
+      } else {
+        launch_bicg_matvec(Ap + cur * N, Adp + cur * N, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
+                           op->rs(), s);
+      }
+      // vs = vs + 1: the window gains r_{j-1} (already stored raw in its slot)
+      cols.push_back(Col{0, j - 1, slot_of_r[j - 1]});
+      if (free_slots.empty()) apply_job();
+      if (free_slots.empty()) fail(EB_ERR_INVALID, "window slots exhausted");
+      const int snew = free_slots.front();
+      free_slots.pop_front();
+      slot_of_r[j] = snew;
+      const int sold = slot_of_r[j - 1];
+      launch_bicg_update_r(V(snew), W(snew), V(sold), W(sold), Ap + cur * N, Adp + cur * N, N, j, S, dh, op->rs(),
+                           s);
+      if (job && job->done.load(std::memory_order_acquire)) apply_job();
+      if (int(cols.size()) == m) {
+        // the next iteration restarts: the previous restart must be applied
+        // first; then ship the history through j and the arrow dots
+        apply_job();
+        if (int(cols.size()) == m) {
+          copy_history(j);
+          copy_dots();
+          HIPCHK(hipMemcpyAsync(pstate.p, S, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipEventRecord(ev_hist, s));
+        }
+      }
+      launch_bicg_update_p(x, p, ph, V(snew), W(snew), N, j, S, s);
+      if (j % poll == 0 && pl.step(hs)) {
+        stopped = true;
+        stop_at = hs.stop_at;
+        reason = hs.reason;
+        rnorm = hs.rnorm;
+        break;
+      }
+    }
+  }
+  if (!stopped) {
+    fetch_state(op, s, hs);
+    stop_at = hs.stopped ? hs.stop_at : std::min(j, P.maxiter);
+    reason = hs.stopped ? hs.reason : 4;
+    rnorm = hs.rnorm;
+  }
+  // roll the window back to iteration stop_at: columns r_i with i >= stop_at
+  // were appended by iterations that did not run
+  {
+    std::vector<Col> nc;
+    for (const Col &c : cols)
+      if (c.ritz || c.idx < stop_at) nc.push_back(c);
+    cols.swap(nc);
+  }
+  if (job) apply_job();
+  out.iters = stop_at;
+  out.reason = reason;
+  out.rnorm = rnorm;
+  if (reason == 2) return out;
+  // final eigenpairs from V^(vs), W^(vs), H^(vs) (Alg. eigBiCG, last step)
+  copy_history(stop_at);
+  copy_dots();
+  HIPCHK(hipStreamSynchronize(s));
+  load_dots();
+  const int vs = int(cols.size());
+  if (vs > 0) {
+    CMat H = build_H(cols, hh, rb);
+    std::vector<cd> lam;
+    CMat y, z;
+    if (!eig_small(H, lam, y, z)) fail(EB_ERR_EIG, "final eig(H^(vs)) failed");
+    const int k = std::min(nev, vs);
+    out.ritz.assign(lam.begin(), lam.begin() + k);
+    if (op->Kcap - op->K >= k) {
+      std::vector<cd> eta, zeta;
+      col_scales(cols, hh, eta, zeta);
+      std::vector<double2> cv(size_t(vs) * k), cw(size_t(vs) * k);
+      for (int c = 0; c < k; ++c)
+        for (int i = 0; i < vs; ++i) {
+          cv[i + size_t(c) * vs] = d2(eta[i] * y(i, c));
+          cw[i + size_t(c) * vs] = d2(zeta[i] * z(i, c));
+        }
+      auto [cV, cW] = upload_coef(cv, cw);
+      SlotList in{}, o1{};
+      in.n = vs;
+      for (int c = 0; c < vs; ++c) in.idx[c] = cols[c].slot;
+      o1.n = k;
+      for (int c = 0; c < k; ++c) o1.idx[c] = op->K + c;
+      launch_rotate(op->Ur.as<double2>(), o1, Vw, in, cV, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
+      launch_rotate(op->Ul.as<double2>(), o1, Ww, in, cW, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
+      HIPCHK(hipStreamSynchronize(s));
+      out.nvec = k;
+    }
+  }
+  return out;
+}
+
+// Biorthogonalise the nnew pairs in Ur[:, K..K+nnew), Ul[:, K..) against the
+// space and among themselves, extend H = Ul^+ A Ur, and grow K (Alg.
+// Incremental eigBiCG, step 2, items 3-5).  Returns the number kept.
+int absorb(eb_op *op, int nnew, eb_stats &st, hipStream_t s) {
+  const size_t N = op->N;
+  const int K = op->K;
+  double2 *Ur = op->Ur.as<double2>(), *Ul = op->Ul.as<double2>();
+  double2 *C = op->raw<double2>("abs_C", size_t(op->Kcap) * 4 * sizeof(double2));
+  std::vector<double2> hbuf(size_t(op->Kcap) * 4);
+  auto col_r = [&](int c) { return Ur + size_t(c) * N; };
+  auto col_l = [&](int c) { return Ul + size_t(c) * N; };
+  int kept = 0;
+  for (int k = 0; k < nnew; ++k) {
+    double2 *v = col_r(K + k), *w = col_l(K + k);
+    // move the candidate into position K + kept
+    if (kept != k) {
+      launch_copy_f64(col_r(K + kept), v, N, s);
+      launch_copy_f64(col_l(K + kept), w, N, s);
+      v = col_r(K + kept);
+      w = col_l(K + kept);
+    }
+    const int nprev = K + kept;  // columns the pair is made biorthogonal to
+    for (int pass = 0; pass < 2 && nprev > 0; ++pass) {
+      // v -= Ur (Ul^+ v);  w -= Ul (Ur^+ w)
+      launch_ts_dot(C, Ul, N, nprev, v, N, 1, N, op->rs(), s);
+      launch_ts_dot(C + op->Kcap, Ur, N, nprev, w, N, 1, N, op->rs(), s);
+      launch_ts_update(v, N, 1, Ur, N, nprev, C, -1.0, N, s);
+      launch_ts_update(w, N, 1, Ul, N, nprev, C + op->Kcap, -1.0, N, s);
+    }
+    // pivot w^+ v, ||v||^2, ||w||^2
+    launch_ts_dot(C, w, N, 1, v, N, 1, N, op->rs(), s);
+    launch_ts_dot(C + 1, v, N, 1, v, N, 1, N, op->rs(), s);
+    launch_ts_dot(C + 2, w, N, 1, w, N, 1, N, op->rs(), s);
+    HIPCHK(hipMemcpyAsync(hbuf.data(), C, 3 * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const cd piv = c2(hbuf[0]);
+    const double nv = std::sqrt(hbuf[1].x), nw = std::sqrt(hbuf[2].x);
+    if (!(std::abs(piv) > 1e-12 * nv * nw)) continue;
+    // v /= ||v||, w /= conj(w^+ v / ||v||)
+    launch_scale_f64(v, make_double2(1.0 / nv, 0.0), N, s);
+    const cd sw = 1.0 / std::conj(piv / nv);
+    launch_scale_f64(w, d2(sw), N, s);
+    ++kept;
+  }
+  if (kept == 0) return 0;
+  // A V', A^+ W'
+  double2 *AV = op->vec("abs_AV", kept), *AdW = op->vec("abs_AdW", kept);
+  for (int k = 0; k < kept; ++k) {
+    launch_dslash_f64(AV + size_t(k) * N, col_r(K + k), op->U64.as<double2>(), op->g, op->kappa, false, s);
+    launch_dslash_f64(AdW + size_t(k) * N, col_l(K + k), op->U64.as<double2>(), op->g, op->kappa, true, s);
+  }
+  st.matvec_d += kept;
+  st.matvec_ddag += kept;
+  const int Kn = K + kept;
+  double2 *blk = op->raw<double2>("abs_blk", size_t(Kn) * kept * sizeof(double2));
+  double2 *blk2 = op->raw<double2>("abs_blk2", size_t(Kn) * kept * sizeof(double2));
+  // Ul_all^+ (A V') : Kn x kept  (rows < K: the new column block; rows >= K: W'^+ A V')
+  launch_ts_dot(blk, Ul, N, Kn, AV, N, kept, N, op->rs(), s);
+  // (A^+ W')^+ Ur = conj of Ur^+ (A^+ W'):  K x kept, transposed-conjugated below
+  if (K > 0) launch_ts_dot(blk2, Ur, N, K, AdW, N, kept, N, op->rs(), s);
+  std::vector<double2> h1(size_t(Kn) * kept), h2(size_t(K) * kept);
+  HIPCHK(hipMemcpyAsync(h1.data(), blk, h1.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  if (K > 0) HIPCHK(hipMemcpyAsync(h2.data(), blk2, h2.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  CMat Hn(Kn, Kn);
+  for (int jj = 0; jj < K; ++jj)
+    for (int i = 0; i < K; ++i) Hn(i, jj) = op->H(i, jj);
+  for (int c = 0; c < kept; ++c) {
+    for (int i = 0; i < Kn; ++i) Hn(i, K + c) = c2(h1[i + size_t(c) * Kn]);
+    for (int i = 0; i < K; ++i) Hn(K + c, i) = std::conj(c2(h2[i + size_t(c) * K]));
+  }
+  op->H = Hn;
+  op->K = Kn;
+  return kept;
+}
+
+eb_stats zero_stats() {
+  eb_stats st;
+  std::memset(&st, 0, sizeof(st));
+  return st;
+}
+
+void ensure_space(eb_op *op) {
+  if (op->Kcap > 0 && !op->Ur.p) {
+    op->Ur.ensure(size_t(op->Kcap) * op->N * sizeof(double2));
+    op->Ul.ensure(size_t(op->Kcap) * op->N * sizeof(double2));
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t, int32_t defl_capacity,
+                       eb_op **out) {
+  return guarded([&]() {
+    if (!out || !gauge || !dims) fail(EB_ERR_INVALID, "null argument");
+    *out = nullptr;
+    for (int i = 0; i < 4; ++i)
+      if (dims[i] < 2) fail(EB_ERR_INVALID, "every lattice extent must be >= 2");
+    if (!std::isfinite(kappa)) fail(EB_ERR_INVALID, "kappa must be finite");
+    if (bc_t != 1 && bc_t != -1) fail(EB_ERR_INVALID, "bc_t must be +1 or -1");
+    if (defl_capacity < 0 || defl_capacity > kMaxCols) fail(EB_ERR_INVALID, "defl_capacity out of range [0, 128]");
+    const long long V = 1LL * dims[0] * dims[1] * dims[2] * dims[3];
+    if (V * 12 >= (1LL << 31)) fail(EB_ERR_INVALID, "lattice too large");
+    std::unique_ptr<eb_op> op(new eb_op);
+    HIPCHK(hipGetDevice(&op->device));
+    op->g = Geom{dims[0], dims[1], dims[2], dims[3], int(V)};
+    op->N = size_t(V) * 12;
+    op->kappa = kappa;
+    op->bc_t = bc_t;
+    op->Kcap = defl_capacity;
+    op->partials.ensure(kMaxPartials * sizeof(double));
+    op->tickets.ensure(kMaxTickets * sizeof(unsigned));
+    HIPCHK(hipMemset(op->tickets.p, 0, kMaxTickets * sizeof(unsigned)));
+    op->state.ensure(sizeof(KrylovState));
+    op->res.ensure(4 * sizeof(double));
+    op->hstate.ensure(sizeof(KrylovState));
+    op->hres.ensure(4 * sizeof(double));
+    op->U64.ensure(size_t(36) * V * sizeof(double2));
+    DevBuf tmp;
+    tmp.ensure(size_t(36) * V * sizeof(double2));
+    HIPCHK(hipMemcpy(tmp.p, gauge, size_t(36) * V * sizeof(double2), hipMemcpyHostToDevice));
+    launch_pack_gauge_f64(op->U64.as<double2>(), tmp.as<double2>(), op->g, bc_t, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    tmp.release();
+    *out = op.release();
+  });
+}
+
+eb_status eb_op_destroy(eb_op *op) {
+  return guarded([&]() {
+    if (!op) return;
+    (void)hipSetDevice(op->device);
+    (void)hipDeviceSynchronize();
+    op->free_all();
+    delete op;
+  });
+}
+
+static eb_status apply_impl(eb_op *op, void *out, const void *in, eb_prec prec, void *stream, bool dagger) {
+  return guarded([&]() {
+    if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
+    if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t N = op->N;
+    if (prec == EB_FP64) {
+      double2 *a = op->vec("apply_a"), *b = op->vec("apply_b");
+      launch_to_soa_f64(a, static_cast<const double2 *>(in), op->g, s);
+      launch_dslash_f64(b, a, op->U64.as<double2>(), op->g, op->kappa, dagger, s);
+      launch_from_soa_f64(static_cast<double2 *>(out), b, op->g, s);
+    } else if (prec == EB_FP32) {
+      if (!op->U32.p) {
+        op->U32.ensure(size_t(36) * op->g.V * sizeof(float2));
+        launch_convert_f64_f32(op->U32.as<float2>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
+      }
+      float2 *a = op->raw<float2>("apply_a32", N * sizeof(float2));
+      float2 *b = op->raw<float2>("apply_b32", N * sizeof(float2));
+      launch_to_soa_f32(a, static_cast<const float2 *>(in), op->g, s);
+      launch_dslash_f32(b, a, op->U32.as<float2>(), op->g, op->kappa, dagger, s);
+      launch_from_soa_f32(static_cast<float2 *>(out), b, op->g, s);
+    } else {
+      fail(EB_ERR_INVALID, "precision not supported by op_apply");
+    }
+    HIPCHK(hipGetLastError());
+  });
+}
+
+eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *stream) {
+  return apply_impl(op, out, in, prec, stream, false);
+}
+eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream) {
+  return apply_impl(op, out, in, prec, stream, true);
+}
+
+eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_eig_params *P, double *ritz,
+                           eb_stats *stats, void *stream) {
+  eb_stats st = zero_stats();
+  auto t0 = std::chrono::steady_clock::now();
+  eb_status rc = guarded([&]() {
+    if (!op || !b_can || !x_can || !P) fail(EB_ERR_INVALID, "null argument");
+    if (P->nev < 1 || P->m <= 2 * P->nev) fail(EB_ERR_INVALID, "need nev >= 1 and m > 2 nev");
+    if (P->m + 1 > kMaxCols || 2 * P->nev > 64) fail(EB_ERR_INVALID, "window too large (m <= 127, nev <= 32)");
+    if (!(P->tol > 0) || P->maxiter < 1) fail(EB_ERR_INVALID, "tol > 0 and maxiter >= 1 required");
+    if (P->rhat != 0 && P->rhat != 1) fail(EB_ERR_INVALID, "rhat must be 0 or 1");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ensure_space(op);
+    double2 *b = op->vec("solve_b"), *x = op->vec("solve_x");
+    launch_to_soa_f64(b, static_cast<const double2 *>(b_can), op->g, s);
+    launch_to_soa_f64(x, static_cast<const double2 *>(x_can), op->g, s);
+    if (op->K > 0) deflate_guess(op, b, x, s);
+    EigBiCGOut R = run_eigbicg(op, b, x, *P, s);
+    st.iters = R.iters;
+    st.matvec_d = R.iters + 1;
+    st.matvec_ddag = R.iters;
+    st.window_restarts = R.restarts;
+    if (R.reason == 2) fail(EB_ERR_BREAKDOWN, "eigBiCG breakdown");
+    if (ritz)
+      for (size_t i = 0; i < R.ritz.size(); ++i) {
+        ritz[2 * i] = R.ritz[i].real();
+        ritz[2 * i + 1] = R.ritz[i].imag();
+      }
+    // true residual in FP64; continue with BiCGStab if the recursion drifted
+    double2 *r = op->vec("solve_r");
+    auto [rn, bn] = residual(op, r, b, x, s);
+    st.rec_rel_resid = bn > 0 ? R.rnorm / bn : 0;
+    st.true_rel_resid = bn > 0 ? rn / bn : 0;
+    if (bn > 0 && rn > P->tol * bn) {
+      const int K0 = op->K;
+      op->K = 0;  // the pairs of this solve are not absorbed yet; continue undeflated
+      try {
+        deflated_stab_f64(op, b, x, P->tol, 0.0, P->maxiter + st.iters, st, s);
+      } catch (...) {
+        op->K = K0;
+        throw;
+      }
+      op->K = K0;
+    }
+    if (R.reason == 4 && st.true_rel_resid > P->tol) {
+      launch_from_soa_f64(static_cast<double2 *>(x_can), x, op->g, s);
+      HIPCHK(hipStreamSynchronize(s));
+      fail(EB_ERR_NOT_CONVERGED, "eigBiCG: maxiter reached");
+    }
+    if (R.nvec > 0) st.nev_added = absorb(op, R.nvec, st, s);
+    launch_from_soa_f64(static_cast<double2 *>(x_can), x, op->g, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  });
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  return rc;
+}
+
+eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_solve_params *P,
+                                 eb_stats *stats, void *stream) {
+  eb_stats st = zero_stats();
+  auto t0 = std::chrono::steady_clock::now();
+  eb_status rc = guarded([&]() {
+    if (!op || !b_can || !x_can || !P) fail(EB_ERR_INVALID, "null argument");
+    if (!(P->tol > 0) || P->maxiter < 1 || P->nrhs < 1) fail(EB_ERR_INVALID, "tol > 0, maxiter >= 1, nrhs >= 1");
+    if (P->deftol < 0 || P->deftol >= 1) fail(EB_ERR_INVALID, "deftol must be in [0, 1)");
+    if (P->method != 0) fail(EB_ERR_INVALID, "only method 0 (BiCGStab) is available");
+    if (P->inner != EB_FP64 && P->inner != EB_FP32) fail(EB_ERR_INVALID, "inner precision not available");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ensure_space(op);
+    double2 *b = op->vec("solve_b"), *x = op->vec("solve_x");
+    double worst = 0;
+    for (int c = 0; c < P->nrhs; ++c) {
+      const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c) * op->N;
+      double2 *xc = static_cast<double2 *>(x_can) + size_t(c) * op->N;
+      launch_to_soa_f64(b, bc, op->g, s);
+      launch_to_soa_f64(x, xc, op->g, s);
+      eb_stats sc = zero_stats();
+      auto merge = [&]() {
+        st.iters += sc.iters;
+        st.matvec_d += sc.matvec_d;
+        st.defl_restarts += sc.defl_restarts;
+        st.outer_steps += sc.outer_steps;
+        st.rec_rel_resid = std::max(st.rec_rel_resid, sc.rec_rel_resid);
+        worst = std::max(worst, sc.true_rel_resid);
+        st.true_rel_resid = worst;
+      };
+      try {
+        if (P->inner == EB_FP64) {
+          if (op->K > 0) deflate_guess(op, b, x, s);
+          deflated_stab_f64(op, b, x, P->tol, P->deftol, P->maxiter, sc, s);
+        } else {
+          mixed_stab_f32(op, b, x, P->tol, P->inner_tol > 0 ? P->inner_tol : 1e-6, P->maxiter, sc, s);
+        }
+      } catch (...) {
+        // x holds the last iterate and the stats are filled
+        launch_from_soa_f64(xc, x, op->g, s);
+        (void)hipStreamSynchronize(s);
+        merge();
+        throw;
+      }
+      launch_from_soa_f64(xc, x, op->g, s);
+      merge();
+    }
+    st.true_rel_resid = worst;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  });
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  return rc;
+}
+
+eb_status eb_get_eigenpairs(eb_op *op, int32_t *k, double *evals, void *right, void *left, void *stream) {
+  return guarded([&]() {
+    if (!op || !k) fail(EB_ERR_INVALID, "null argument");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int K = op->K;
+    const int kk = std::min<int>(*k, K);
+    *k = kk;
+    if (kk == 0) return;
+    std::vector<cd> lam;
+    CMat y, z;
+    if (!eig_small(op->H, lam, y, z)) fail(EB_ERR_EIG, "eig(H) failed");
+    if (evals)
+      for (int i = 0; i < kk; ++i) {
+        evals[2 * i] = lam[i].real();
+        evals[2 * i + 1] = lam[i].imag();
+      }
+    if (!right && !left) return;
+    const size_t N = op->N;
+    double2 *R = op->vec("eig_R", kk), *L = op->vec("eig_L", kk);
+    double2 *C = op->raw<double2>("eig_C", size_t(K) * kk * sizeof(double2));
+    std::vector<double2> hc(size_t(K) * kk);
+    // right = Ur y, left = Ul z; then ||right|| = 1, left^+ right = 1
+    for (int side = 0; side < 2; ++side) {
+      for (int c = 0; c < kk; ++c)
+        for (int i = 0; i < K; ++i) hc[i + size_t(c) * K] = d2(side == 0 ? y(i, c) : z(i, c));
+      HIPCHK(hipMemcpyAsync(C, hc.data(), hc.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+      double2 *dst = side == 0 ? R : L;
+      HIPCHK(hipMemsetAsync(dst, 0, size_t(kk) * N * sizeof(double2), s));
+      launch_ts_update(dst, N, kk, side == 0 ? op->Ur.as<double2>() : op->Ul.as<double2>(), N, K, C, 1.0, N, s);
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    double2 *d = op->raw<double2>("eig_d", 2 * sizeof(double2));
+    std::vector<double2> hd(2);
+    for (int c = 0; c < kk; ++c) {
+      double2 *rc = R + size_t(c) * N, *lc = L + size_t(c) * N;
+      launch_ts_dot(d, rc, N, 1, rc, N, 1, N, op->rs(), s);
+      launch_ts_dot(d + 1, lc, N, 1, rc, N, 1, N, op->rs(), s);
+      HIPCHK(hipMemcpyAsync(hd.data(), d, 2 * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const double nr = std::sqrt(hd[0].x);
+      const cd q = c2(hd[1]) / nr;
+      launch_scale_f64(rc, make_double2(1.0 / nr, 0), N, s);
+      launch_scale_f64(lc, d2(1.0 / std::conj(q)), N, s);
+      if (right) launch_from_soa_f64(static_cast<double2 *>(right) + size_t(c) * N, rc, op->g, s);
+      if (left) launch_from_soa_f64(static_cast<double2 *>(left) + size_t(c) * N, lc, op->g, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+eb_status eb_defl_info(eb_op *op, int32_t *K, double *H) {
+  return guarded([&]() {
+    if (!op || !K) fail(EB_ERR_INVALID, "null argument");
+    *K = op->K;
+    if (H)
+      for (int i = 0; i < op->K; ++i)
+        for (int j = 0; j < op->K; ++j) {
+          H[2 * (i * op->K + j)] = op->H(i, j).real();
+          H[2 * (i * op->K + j) + 1] = op->H(i, j).imag();
+        }
+  });
+}
+
+eb_status eb_defl_reset(eb_op *op) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    op->K = 0;
+    op->H = CMat();
+  });
+}
+
+eb_status eb_small_eig(int32_t n, const double *Cin, double *lambda, double *y, double *z) {
+  return guarded([&]() {
+    if (n < 0 || (n > 0 && (!Cin || !lambda))) fail(EB_ERR_INVALID, "bad arguments");
+    CMat C(n, n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) C(i, j) = cd(Cin[2 * (i * n + j)], Cin[2 * (i * n + j) + 1]);
+    std::vector<cd> lam;
+    CMat Y, Z;
+    if (!eig_small(C, lam, Y, Z)) fail(EB_ERR_EIG, "QR iteration did not converge");
+    for (int i = 0; i < n; ++i) {
+      lambda[2 * i] = lam[i].real();
+      lambda[2 * i + 1] = lam[i].imag();
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        if (y) {
+          y[2 * (i * n + j)] = Y(i, j).real();
+          y[2 * (i * n + j) + 1] = Y(i, j).imag();
+        }
+        if (z) {
+          z[2 * (i * n + j)] = Z(i, j).real();
+          z[2 * (i * n + j) + 1] = Z(i, j).imag();
+        }
+      }
+  });
+}
+
+void eb_last_error(char *buf, size_t len) {
+  if (!buf || len == 0) return;
+  std::snprintf(buf, len, "%s", g_last_error.c_str());
+}
+
+const char *eb_version(void) { return "ebicg 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+"""Python binding of libebicg.so (include/ebicg.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module checks tensor
+shapes, dtypes and devices, passes raw pointers and the current torch HIP
+stream, and turns status codes into exceptions.  It raises if the built
+library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libebicg.so")
+
+EB_OK = 0
+STATUS = {
+    0: "EB_OK",
+    -1: "EB_ERR_INVALID",
+    -2: "EB_ERR_OOM",
+    -3: "EB_ERR_BREAKDOWN",
+    -4: "EB_ERR_NOT_CONVERGED",
+    -5: "EB_ERR_HIP",
+    -6: "EB_ERR_EIG",
+    -7: "EB_ERR_CAPACITY",
+}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class EbicgError(RuntimeError):
+    def __init__(self, status, msg, stats=None):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.stats = stats
+
+
+class _EigParams(ctypes.Structure):
+    _fields_ = [
+        ("nev", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("rhat", ctypes.c_int32),
+    ]
+
+
+class _SolveParams(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("deftol", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("inner", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
+        ("nrhs", ctypes.c_int32),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("matvec_d", ctypes.c_int32),
+        ("matvec_ddag", ctypes.c_int32),
+        ("window_restarts", ctypes.c_int32),
+        ("defl_restarts", ctypes.c_int32),
+        ("breakdown_restarts", ctypes.c_int32),
+        ("outer_steps", ctypes.c_int32),
+        ("nev_added", ctypes.c_int32),
+        ("true_rel_resid", ctypes.c_double),
+        ("rec_rel_resid", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# (name, restype, argtypes) of every symbol declared in include/ebicg.h
+_P = ctypes.c_void_p
+_SIGNATURES = [
+    ("eb_op_create", ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    ("eb_op_destroy", ctypes.c_int, [_P]),
+    ("eb_op_apply", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    ("eb_op_apply_dagger", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    ("eb_eigbicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_EigParams), _P, ctypes.POINTER(_Stats), _P]),
+    ("eb_deflated_bicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_SolveParams), ctypes.POINTER(_Stats), _P]),
+    ("eb_get_eigenpairs", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]),
+    ("eb_defl_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+    ("eb_defl_reset", ctypes.c_int, [_P]),
+    ("eb_small_eig", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
+    ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
+    ("eb_version", ctypes.c_char_p, []),
+]
+SYMBOLS = [n for n, _, _ in _SIGNATURES]
+
+
+def lib():
+    """Load libebicg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_0911_2285_amd.build` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _last_error():
+    buf = ctypes.create_string_buffer(1024)
+    lib().eb_last_error(buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(status, stats=None):
+    if status != EB_OK:
+        raise EbicgError(status, _last_error(), stats)
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, numel, dtype, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be contiguous with {numel} elements, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version():
+    return lib().eb_version().decode()
+
+
+def small_eig(C):
+    """[y, z, lambda] of the library's host eigensolver (eig(C) of the paper's conventions)."""
+    C = np.ascontiguousarray(C, dtype=np.complex128)
+    n = C.shape[0]
+    lam = np.zeros(n, np.complex128)
+    y = np.zeros((n, n), np.complex128)
+    z = np.zeros((n, n), np.complex128)
+    _check(lib().eb_small_eig(n, C.ctypes.data, lam.ctypes.data, y.ctypes.data, z.ctypes.data))
+    return y, z, lam
+
+
+@dataclass
+class Operator:
+    """An eb_op: the Wilson-Dirac operator on one gauge field plus its deflation space."""
+
+    handle: ctypes.c_void_p
+    dims: tuple
+    kappa: float
+    V: int
+
+    @property
+    def N(self):
+        return 12 * self.V
+
+    def __del__(self):
+        try:
+            op_destroy(self)
+        except Exception:
+            pass
+
+
+def op_create(gauge, kappa, dims, bc_t=-1, defl_capacity=0):
+    """gauge: complex128 array [4][V][3][3] on the host."""
+    dims = tuple(int(d) for d in dims)
+    V = int(np.prod(dims))
+    g = np.ascontiguousarray(gauge, dtype=np.complex128)
+    if g.size != 36 * V:
+        raise ValueError(f"gauge must have 36*V = {36 * V} complex entries")
+    d = (ctypes.c_int32 * 4)(*dims)
+    h = ctypes.c_void_p()
+    _check(lib().eb_op_create(g.ctypes.data, float(kappa), d, int(bc_t), int(defl_capacity), ctypes.byref(h)))
+    return Operator(h, dims, float(kappa), V)
+
+
+def op_destroy(op):
+    if op.handle and op.handle.value:
+        _check(lib().eb_op_destroy(op.handle))
+        op.handle = ctypes.c_void_p()
+
+
+def _spinor_dtype(prec):
+    import torch
+
+    return {"fp64": torch.complex128, "fp32": torch.complex64}[prec]
+
+
+def op_apply(op, out, inp, prec="fp64", stream=None):
+    """out = D inp (device tensors in the canonical [V][4][3] layout)."""
+    dt = _spinor_dtype(prec)
+    _check(
+        lib().eb_op_apply(
+            op.handle, _dev_ptr(out, op.N, dt, "out"), _dev_ptr(inp, op.N, dt, "in"), PREC[prec], _stream(stream)
+        )
+    )
+
+
+def op_apply_dagger(op, out, inp, prec="fp64", stream=None):
+    """out = D^+ inp."""
+    dt = _spinor_dtype(prec)
+    _check(
+        lib().eb_op_apply_dagger(
+            op.handle, _dev_ptr(out, op.N, dt, "out"), _dev_ptr(inp, op.N, dt, "in"), PREC[prec], _stream(stream)
+        )
+    )
+
+
+def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):
+    """One eigBiCG solve that grows the deflation space; returns (stats, ritz values)."""
+    import torch
+
+    p = _EigParams(int(nev), int(m), float(tol), int(maxiter), int(rhat))
+    st = _Stats()
+    ritz = np.zeros(int(nev), np.complex128)
+    rc = lib().eb_eigbicg_solve(
+        op.handle,
+        _dev_ptr(b, op.N, torch.complex128, "b"),
+        _dev_ptr(x, op.N, torch.complex128, "x"),
+        ctypes.byref(p),
+        ritz.ctypes.data,
+        ctypes.byref(st),
+        _stream(stream),
+    )
+    _check(rc, st.as_dict())
+    return st.as_dict(), ritz
+
+
+def deflated_bicg_solve(op, b, x, tol, deftol=0.0, maxiter=10000, method=0, inner="fp64", inner_tol=0.0, nrhs=1,
+                        stream=None):
+    """Deflated BiCGStab solve(s); b, x hold nrhs spinors back to back.  Returns stats."""
+    import torch
+
+    p = _SolveParams(float(tol), float(deftol), int(maxiter), int(method), PREC[inner], float(inner_tol), int(nrhs))
+    st = _Stats()
+    rc = lib().eb_deflated_bicg_solve(
+        op.handle,
+        _dev_ptr(b, op.N * nrhs, torch.complex128, "b"),
+        _dev_ptr(x, op.N * nrhs, torch.complex128, "x"),
+        ctypes.byref(p),
+        ctypes.byref(st),
+        _stream(stream),
+    )
+    _check(rc, st.as_dict())
+    return st.as_dict()
+
+
+def get_eigenpairs(op, k, right=None, left=None, stream=None):
+    """Rayleigh-Ritz eigenpairs of the deflation space; returns the eigenvalues."""
+    import torch
+
+    kk = ctypes.c_int32(int(k))
+    ev = np.zeros(int(k), np.complex128)
+    rp = _dev_ptr(right, op.N * k, torch.complex128, "right") if right is not None else None
+    lp = _dev_ptr(left, op.N * k, torch.complex128, "left") if left is not None else None
+    _check(lib().eb_get_eigenpairs(op.handle, ctypes.byref(kk), ev.ctypes.data, rp, lp, _stream(stream)))
+    return ev[: kk.value]
+
+
+def defl_info(op):
+    """(K, H) of the deflation space; H = U_l^+ A U_r as a K x K numpy array."""
+    K = ctypes.c_int32(0)
+    _check(lib().eb_defl_info(op.handle, ctypes.byref(K), None))
+    H = np.zeros((K.value, K.value), np.complex128)
+    _check(lib().eb_defl_info(op.handle, ctypes.byref(K), H.ctypes.data if K.value else None))
+    return K.value, H
+
+
+def defl_reset(op):
+    _check(lib().eb_defl_reset(op.handle))

@@ -1,0 +1,153 @@
+"""GPU parity of eigBiCG, the incremental deflation space and deflated BiCGStab against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov as K
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ops(U, kappa, dims):
+    V = synth.volume(dims)
+    A = lambda v: W.apply_D(U, v.reshape(V, 4, 3), kappa, dims).ravel()
+    Ad = lambda v: W.apply_Ddag(U, v.reshape(V, 4, 3), kappa, dims).ravel()
+    return A, Ad
+
+
+def _rel_match(a, b):
+    """max over a of min_b |a - b| / |a| (nearest-neighbour relative distance)."""
+    return max(np.min(np.abs(np.asarray(b) - v)) / abs(v) for v in a)
+
+
+@pytest.fixture(scope="module")
+def cfg0(gpu_lib):
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(0))
+    return dims, kappa, U
+
+
+def test_eigbicg_first_solve_parity(gpu_lib, cfg0):
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    A, Ad = _ops(U, kappa, dims)
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=16)
+    b_np = synth.z2_source(V, synth.rhs_seed(0, 0))
+    b = torch.from_numpy(b_np).to("cuda:0")
+    x = torch.zeros_like(b)
+    st, ritz = gpu_lib.eigbicg_solve(op, b, x, nev=4, m=16, tol=1e-10)
+    orc = K.eigbicg(A, Ad, b_np.ravel(), np.zeros(12 * V, complex), 4, 16, 1e-10)
+    print("gpu", st, ritz)
+    print("oracle iters", orc.iters, orc.lam)
+    assert abs(st["iters"] - orc.iters) <= 1
+    assert st["window_restarts"] == len(orc.restarts)
+    tr = np.linalg.norm(b_np.ravel() - A(x.cpu().numpy().ravel())) / np.linalg.norm(b_np)
+    assert tr <= 1e-10
+    assert _rel_match(ritz, orc.lam) < 1e-8 and _rel_match(orc.lam, ritz) < 1e-8
+    xo = orc.x
+    assert np.linalg.norm(x.cpu().numpy().ravel() - xo) / np.linalg.norm(xo) < 1e-8
+    K_, H = gpu_lib.defl_info(op)
+    assert K_ == 4
+
+
+def test_incremental_parity_small_config(gpu_lib, cfg0):
+    """4 eigBiCG solves then deflated BiCGStab (4^4, nev=4, m=16): the space matches the oracle's."""
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    A, Ad = _ops(U, kappa, dims)
+    B = [synth.z2_source(V, synth.rhs_seed(0, i)) for i in range(6)]
+    X0 = [np.zeros(12 * V, complex)] * 6
+    xs_o, info_o, space_o = K.incremental_eigbicg(A, Ad, [b.ravel() for b in B], X0, 4, 16, 1e-10, n1=4)
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=16)
+    for i, bnp in enumerate(B):
+        b = torch.from_numpy(bnp).to("cuda:0")
+        x = torch.zeros_like(b)
+        if i < 4:
+            st, ritz = gpu_lib.eigbicg_solve(op, b, x, nev=4, m=16, tol=1e-10)
+            print(i, st["iters"], info_o[i]["iters"], ritz, info_o[i]["lam"])
+            assert _rel_match(ritz, info_o[i]["lam"]) < 1e-8
+        else:
+            st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10)
+            print(i, st["iters"], info_o[i]["iters"])
+            assert abs(st["iters"] - info_o[i]["iters"]) <= max(2, 0.1 * info_o[i]["iters"])
+        tr = np.linalg.norm(bnp.ravel() - A(x.cpu().numpy().ravel())) / np.linalg.norm(bnp)
+        assert tr <= 1e-10
+        assert st["true_rel_resid"] <= 1e-10
+    K_, H = gpu_lib.defl_info(op)
+    assert K_ == space_o.K == 16
+    lam_g = np.linalg.eigvals(H)
+    lam_o = np.linalg.eigvals(space_o.H)
+    assert _rel_match(lam_g, lam_o) < 1e-7 and _rel_match(lam_o, lam_g) < 1e-7
+    # Rayleigh-Ritz eigenpairs: values and residuals agree with the oracle's
+    right = torch.zeros(16 * 12 * V, dtype=torch.complex128, device="cuda:0")
+    left = torch.zeros_like(right)
+    ev = gpu_lib.get_eigenpairs(op, 16, right, left)
+    lam_rr, Ur, Ul = K.rayleigh_ritz(space_o)
+    assert _rel_match(ev, lam_rr) < 1e-7
+    R = right.cpu().numpy().reshape(16, -1).T
+    L = left.cpu().numpy().reshape(16, -1).T
+    assert np.allclose(np.linalg.norm(R, axis=0), 1)
+    assert np.allclose(np.einsum("ij,ij->j", L.conj(), R), 1)
+    rr_g, _ = K.ritz_residuals(A, Ad, ev, R, L)
+    rr_o, _ = K.ritz_residuals(A, Ad, lam_rr, Ur, Ul)
+    assert np.allclose(np.sort(rr_g), np.sort(rr_o), rtol=1e-5, atol=1e-9)
+
+
+def test_mixed_precision_solve(gpu_lib, cfg0):
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    A, _ = _ops(U, kappa, dims)
+    op = gpu_lib.op_create(U, kappa, dims)
+    bnp = synth.z2_source(V, synth.rhs_seed(0, 9))
+    b = torch.from_numpy(bnp).to("cuda:0")
+    x = torch.zeros_like(b)
+    st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, inner="fp32", inner_tol=1e-5)
+    tr = np.linalg.norm(bnp.ravel() - A(x.cpu().numpy().ravel())) / np.linalg.norm(bnp)
+    print(st, tr)
+    assert tr <= 1e-10 and st["outer_steps"] >= 1
+
+
+def test_error_paths(gpu_lib, cfg0):
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8)
+    b = torch.from_numpy(synth.z2_source(V, 1)).to("cuda:0")
+    x = torch.zeros_like(b)
+    with pytest.raises(gpu_lib.EbicgError) as e:
+        gpu_lib.eigbicg_solve(op, b, x, nev=4, m=8, tol=1e-10)
+    assert e.value.status == -1
+    # gamma5 shadow residual with a Z2 source and x0 = 0: (rhat0, r0) = 0 exactly
+    with pytest.raises(gpu_lib.EbicgError) as e:
+        gpu_lib.eigbicg_solve(op, b, x, nev=2, m=8, tol=1e-10, rhat=1)
+    assert e.value.status == -3
+    x.zero_()
+    with pytest.raises(gpu_lib.EbicgError) as e:
+        gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, maxiter=2)
+    assert e.value.status == -4
+    assert e.value.stats["iters"] >= 1
+
+
+def test_solves_are_deterministic(gpu_lib, cfg0):
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    outs = []
+    for _ in range(2):
+        op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8)
+        b = torch.from_numpy(synth.z2_source(V, 5)).to("cuda:0")
+        x = torch.zeros_like(b)
+        gpu_lib.eigbicg_solve(op, b, x, nev=4, m=16, tol=1e-10)
+        x2 = torch.zeros_like(b)
+        gpu_lib.deflated_bicg_solve(op, b, x2, tol=1e-10)
+        outs.append((x.clone(), x2.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
