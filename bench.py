@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark: incremental eigBiCG on one MI355X.
+
+Workload (one "step" = the whole hot path over one batch of right-hand sides):
+16^3 x 32 Wilson-Dirac operator, kappa = 0.122, SU(3) links exp(i 0.3 H)
+(seeded), 24 Z2-noise sources resident in HBM.  The first 8 sources run
+eigBiCG (nev = 10, m = 40), each growing the deflation space (up to 80
+left/right pairs); the remaining 16 run deflated BiCGStab.  Every solve
+reaches ||b - A x|| / ||b|| <= 1e-10 (checked in FP64 by the library).
+
+Prints ONE JSON line on stdout: solves/s of the FP64 step, the dominant
+kernel's roofline (achieved algorithmic GB/s from HIP events inside the
+library, over the timed region), per-solve p50/p99 latency, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+# Algorithmic HBM bytes per lattice site and launch, in units of one FP64
+# spinor (192 B/site): vectors each kernel must read or write once, links
+# (4 x 9 complex = 576 B/site = 3 units) read once per stencil launch.
+UNIT_BYTES_FP64 = 192
+KERNEL_UNITS = {
+    "bicg_matvec": 7,    # in p, phat; out Ap, A^+ phat; links (shared by D and D^+)
+    "bicg_update_r": 6,  # in r, rhat, Ap, A^+ phat; out r, rhat
+    "bicg_update_p": 8,  # in x, p, phat, r, rhat; out x, p, phat
+    "stab_v": 6,         # in p, rhat; out v; links
+    "stab_s": 3,         # in r, v; out s
+    "stab_t": 5,         # in s; out t; links
+    "stab_xr": 7,        # in x, p, s, t, rhat; out x, r
+    "stab_p": 4,         # in r, p, v; out p
+    "residual": 6,       # in x, b; out r; links
+}
+
+WORKLOADS = {
+    # the incremental-eigBiCG workload: 16^3 x 32, 8 eigBiCG + 16 deflated solves
+    "inc16x32": dict(dims=(16, 16, 16, 32), kappa=0.122, nrhs=24, n1=8, nev=10, m=40, tol=1e-10, cfg=1),
+    # the small parity workload (4^4), for quick runs
+    "inc4": dict(dims=(4, 4, 4, 4), kappa=0.115, nrhs=4, n1=4, nev=4, m=16, tol=1e-10, cfg=0),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    import numpy as np
+
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def run_step(eb, op, B, X, W, lat, iters):
+    eb.defl_reset(op)
+    for i, (b, x) in enumerate(zip(B, X)):
+        x.zero_()
+        t0 = time.perf_counter()
+        if i < W["n1"]:
+            st, _ = eb.eigbicg_solve(op, b, x, nev=W["nev"], m=W["m"], tol=W["tol"], maxiter=20000)
+        else:
+            st = eb.deflated_bicg_solve(op, b, x, tol=W["tol"], maxiter=20000)
+        lat.append(time.perf_counter() - t0)
+        iters.append(st["iters"])
+        if st["true_rel_resid"] > W["tol"]:
+            raise RuntimeError(f"solve {i} missed the tolerance: {st}")
+
+
+def cpu_baseline(W, U, b_np, eig_iters, stab_iters, n_eig_it=5, n_stab_it=3):
+    """The FP64 oracle on the host: a bounded sample, extrapolated to one step."""
+    import numpy as np
+
+    from oracle import krylov as K
+    from oracle import wilson as Wl
+
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    dims, kappa = W["dims"], W["kappa"]
+    V = int(np.prod(dims))
+    A = lambda v: Wl.apply_D(U, v.reshape(V, 4, 3), kappa, dims).ravel()
+    Ad = lambda v: Wl.apply_Ddag(U, v.reshape(V, 4, 3), kappa, dims).ravel()
+    b = b_np.ravel()
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        if ctx:
+            ctx.__enter__()
+        t0 = time.perf_counter()
+        K.eigbicg(A, Ad, b, np.zeros_like(b), W["nev"], W["m"], W["tol"], maxiter=n_eig_it)
+        t1 = time.perf_counter()
+        K.bicgstab(A, b, np.zeros_like(b), W["tol"], maxiter=n_stab_it)
+        t2 = time.perf_counter()
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    t_eig = (t1 - t0) / n_eig_it
+    t_stab = (t2 - t1) / n_stab_it
+    est = t_eig * eig_iters + t_stab * stab_iters
+    return {
+        "value": W["nrhs"] / est,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle eigBiCG {n_eig_it} iterations and BiCGStab {n_stab_it} iterations on the same lattice "
+                   f"and source ({t1 - t0:.1f} s + {t2 - t1:.1f} s, BLAS limited to 1 thread), extrapolated with the "
+                   f"step's iteration counts ({eig_iters} eigBiCG + {stab_iters} BiCGStab)"),
+        "seconds_per_eigbicg_iter": t_eig,
+        "seconds_per_bicgstab_iter": t_stab,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="inc16x32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU path is design-only",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0911_2285_amd import ebicg as eb
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    W = WORKLOADS[args.workload]
+    dims = W["dims"]
+    V = synth.volume(dims)
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {args.workload}: dims={dims} kappa={W['kappa']} nrhs={W['nrhs']} n1={W['n1']}")
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
+    op = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"])
+    B_np = [synth.z2_source(V, synth.rhs_seed(0, i)) for i in range(W["nrhs"])]
+    B = [torch.from_numpy(b).to(dev) for b in B_np]
+    X = [torch.zeros_like(b) for b in B]
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        lat, its = [], []
+        run_step(eb, op, B, X, W, lat, its)
+        log(f"[bench] warmup step {w}: {sum(lat):.3f} s, iterations {its}")
+
+    if not args.no_timing:
+        eb.timing_enable(op, True)
+    lat, its = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        run_step(eb, op, B, X, W, lat, its)
+        log(f"[bench] step {k} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktimes = eb.timing_read(op) if not args.no_timing else {}
+    eb.timing_enable(op, False)
+
+    n_solves = W["nrhs"] * args.steps
+    value = n_solves / elapsed
+    per_step_its = its[: W["nrhs"]]
+    eig_its = sum(per_step_its[: W["n1"]])
+    stab_its = sum(per_step_its[W["n1"]:])
+    log(f"[bench] {n_solves} solves in {elapsed:.3f} s -> {value:.2f} solves/s; iterations/RHS {per_step_its}")
+
+    # roofline of the dominant kernel: algorithmic bytes / average launch time
+    roof = None
+    kernels = {}
+    for name, (n, ms) in ktimes.items():
+        if n == 0:
+            continue
+        rec = {"launches": n, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / n, 2)}
+        if name in KERNEL_UNITS:
+            bytes_per_launch = KERNEL_UNITS[name] * UNIT_BYTES_FP64 * V
+            rec["GBps"] = round(bytes_per_launch / (ms / n * 1e-3) / 1e9, 1)
+        kernels[name] = rec
+    if kernels:
+        dom = max((k for k in kernels if k in KERNEL_UNITS), key=lambda k: kernels[k]["total_ms"])
+        bpl = KERNEL_UNITS[dom] * UNIT_BYTES_FP64 * V
+        ach = kernels[dom]["GBps"]
+        roof = {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": ach,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4),
+            "traffic": None,
+            "bytes_per_launch": bpl,
+            "avg_launch_us": kernels[dom]["avg_us"],
+        }
+        log(f"[bench] kernel times: {json.dumps(kernels)}")
+
+    # deflated phase in mixed precision (FP32 inner, FP64 refinement) vs FP64,
+    # with the space grown by the last step still in place
+    extra = {}
+    mixed_t, fp64_t = 0.0, 0.0
+    for i in range(W["n1"], W["nrhs"]):
+        X[i].zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000, inner="fp32", inner_tol=1e-6)
+        mixed_t += time.perf_counter() - t1
+        assert st["true_rel_resid"] <= W["tol"], st
+        X[i].zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000)
+        fp64_t += time.perf_counter() - t1
+    nd = W["nrhs"] - W["n1"]
+    extra["deflated_solves_per_s"] = {"fp64": round(nd / fp64_t, 3), "mixed_fp32_inner": round(nd / mixed_t, 3)}
+    # undeflated FP64 BiCGStab on the same sources, for the deflation speed-up
+    eb.defl_reset(op)
+    plain_its = []
+    for i in range(W["n1"], min(W["nrhs"], W["n1"] + 4)):
+        X[i].zero_()
+        st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000)
+        plain_its.append(st["iters"])
+    extra["undeflated_bicgstab_iters"] = plain_its
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(W, U, B_np[0], eig_its, stab_its)
+        log(f"[bench] cpu baseline {cpu['value']:.4g} solves/s")
+
+    out = {
+        "metric": "solves/s at 1e-10 rel. resid (mixed vs FP64), dslash HBM GB/s, p50/p99",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"incremental eigBiCG, Wilson-Dirac {'x'.join(map(str, dims))}, kappa {W['kappa']}, "
+                        f"eps 0.3 SU(3) links, {W['nrhs']} Z2 sources: {W['n1']} eigBiCG (nev {W['nev']}, "
+                        f"m {W['m']}) + {W['nrhs'] - W['n1']} deflated BiCGStab, tol {W['tol']}",
+            "lattice": list(dims),
+            "nrhs": W["nrhs"],
+            "parallelism": "single GPU",
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "dslash_GBps": roof["achieved"] if roof else None,
+        "p50_ms": round(1e3 * percentile(lat, 50), 3),
+        "p99_ms": round(1e3 * percentile(lat, 99), 3),
+        "iters_per_rhs": per_step_its,
+        "kernels": kernels,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

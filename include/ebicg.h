@@ -143,6 +143,27 @@ eb_status eb_defl_reset(eb_op *op);
  * needs no GPU.  EB_ERR_EIG if the QR iteration does not converge. */
 eb_status eb_small_eig(int32_t n, const double *C, double *lambda, double *y, double *z);
 
+/* Kernel timing, for benchmarks.  While enabled, every launch of the solver
+ * kernels is bracketed by HIP events on the solve's stream; eb_timing_read
+ * returns, per kernel class, the launches and their summed duration (ms)
+ * since the last eb_timing_enable.  Classes: */
+enum {
+  EB_K_BICG_MATVEC = 0, /* D p and D^+ phat with sigma (one launch per BiCG iteration) */
+  EB_K_BICG_UPDATE_R,   /* r, rhat updates with rho and ||r|| */
+  EB_K_BICG_UPDATE_P,   /* x, p, phat updates */
+  EB_K_STAB_V,          /* BiCGStab v = D p with (rhat, v) */
+  EB_K_STAB_S,          /* s = r - alpha v */
+  EB_K_STAB_T,          /* t = D s with (t, s), (t, t) */
+  EB_K_STAB_XR,         /* x, r updates with (rhat, r), ||r|| */
+  EB_K_STAB_P,          /* p = r + beta (p - omega v) */
+  EB_K_ROTATE,          /* window rotation (Alg. BiCG-eigen) */
+  EB_K_RESIDUAL,        /* b - D x in FP64 */
+  EB_K_PROJ,            /* deflation projections (tall-skinny products) */
+  EB_K_COUNT
+};
+eb_status eb_timing_enable(eb_op *op, int32_t enable);
+eb_status eb_timing_read(eb_op *op, int32_t kclass, int64_t *launches, double *total_ms);
+
 /* Message of the last non-OK status on this thread (empty if none). */
 void eb_last_error(char *buf, size_t len);
 

@@ -133,11 +133,41 @@ struct eb_op {
   DevBuf Ul, Ur;
   CMat H;
   // reduction scratch and solver state
-  DevBuf partials, tickets, state, res, hist;
+  DevBuf partials, state, res, hist;
   int hist_cap = 0;
   PinnedBuf hstate, hres, hhist;
   std::map<std::string, DevBuf> bufs;
-  RedScratch rs() { return RedScratch{partials.as<double>(), tickets.as<unsigned>()}; }
+  // kernel timing (eb_timing_enable)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct TimedLaunch {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<TimedLaunch> pending;
+  int64_t t_launch[EB_K_COUNT] = {};
+  double t_ms[EB_K_COUNT] = {};
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  void flush_timing() {
+    for (auto &t : pending) {
+      HIPCHK(hipEventSynchronize(t.b));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+      t_launch[t.cls] += 1;
+      t_ms[t.cls] += ms;
+    }
+    pending.clear();
+    ev_used = 0;
+  }
+  RedScratch rs() { return RedScratch{partials.as<double>()}; }
   KrylovState *S() { return state.as<KrylovState>(); }
   double2 *vec(const std::string &name, size_t count = 1) {
     DevBuf &b = bufs[name];
@@ -153,7 +183,7 @@ struct eb_op {
   KrylovHistory history(int need) {
     if (need > hist_cap) {
       hist_cap = std::max(need, 2 * hist_cap);
-      size_t bytes = size_t(hist_cap) * (3 * sizeof(double2) + sizeof(double));
+      size_t bytes = size_t(hist_cap) * (4 * sizeof(double2) + sizeof(double));
       hist.release();
       hist.ensure(bytes);
       hhist.release();
@@ -167,7 +197,8 @@ struct eb_op {
     h.alpha = reinterpret_cast<double2 *>(b);
     h.beta = reinterpret_cast<double2 *>(b + size_t(hist_cap) * sizeof(double2));
     h.rho = reinterpret_cast<double2 *>(b + 2 * size_t(hist_cap) * sizeof(double2));
-    h.rn = reinterpret_cast<double *>(b + 3 * size_t(hist_cap) * sizeof(double2));
+    h.omega = reinterpret_cast<double2 *>(b + 3 * size_t(hist_cap) * sizeof(double2));
+    h.rn = reinterpret_cast<double *>(b + 4 * size_t(hist_cap) * sizeof(double2));
     return h;
   }
   void free_all() {
@@ -176,7 +207,6 @@ struct eb_op {
     Ul.release();
     Ur.release();
     partials.release();
-    tickets.release();
     state.release();
     res.release();
     hist.release();
@@ -185,12 +215,31 @@ struct eb_op {
     hhist.release();
     for (auto &kv : bufs) kv.second.release();
     bufs.clear();
+    pending.clear();
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    ev_pool.clear();
   }
 };
 
 namespace {
 
 void set_device(eb_op *op) { HIPCHK(hipSetDevice(op->device)); }
+
+// Launch through `f`, bracketed by timing events when the op records kernel times.
+template <typename F>
+void timed(eb_op *op, int cls, hipStream_t s, F &&f) {
+  if (!op->timing) {
+    f();
+    return;
+  }
+  if (op->pending.size() > 16384) op->flush_timing();
+  hipEvent_t a = op->next_event(), b = op->next_event();
+  HIPCHK(hipEventRecord(a, s));
+  f();
+  HIPCHK(hipEventRecord(b, s));
+  op->pending.push_back({cls, a, b});
+}
+#define TIMED(cls, stream, call) timed(op, cls, stream, [&]() { call; })
 
 void fetch_state(eb_op *op, hipStream_t s, KrylovState &out) {
   HIPCHK(hipMemcpyAsync(op->hstate.p, op->state.p, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
@@ -238,7 +287,8 @@ struct Poller {
 
 // r = b - D x in FP64; returns (||r||, ||b||).
 std::pair<double, double> residual(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s) {
-  launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+  TIMED(EB_K_RESIDUAL, s,
+        launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s));
   HIPCHK(hipMemcpyAsync(op->hres.p, op->res.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const double *h = op->hres.as<double>();
@@ -254,7 +304,7 @@ double deflate_guess(eb_op *op, const double2 *b, double2 *x, hipStream_t s) {
   if (op->K == 0) return rn;
   const int K = op->K;
   double2 *c = op->raw<double2>("defl_c", size_t(K) * sizeof(double2));
-  launch_ts_dot(c, op->Ul.as<double2>(), op->N, K, r, op->N, 1, op->N, op->rs(), s);
+  TIMED(EB_K_PROJ, s, launch_ts_dot(c, op->Ul.as<double2>(), op->N, K, r, op->N, 1, op->N, op->rs(), s));
   std::vector<double2> hc(K);
   HIPCHK(hipMemcpyAsync(hc.data(), c, K * sizeof(double2), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -263,7 +313,7 @@ double deflate_guess(eb_op *op, const double2 *b, double2 *x, hipStream_t s) {
   if (!lu_solve(op->H, d)) fail(EB_ERR_EIG, "deflation matrix H is singular");
   for (int i = 0; i < K; ++i) hc[i] = d2(d[i]);
   HIPCHK(hipMemcpyAsync(c, hc.data(), K * sizeof(double2), hipMemcpyHostToDevice, s));
-  launch_ts_update(x, op->N, 1, op->Ur.as<double2>(), op->N, K, c, 1.0, op->N, s);
+  TIMED(EB_K_PROJ, s, launch_ts_update(x, op->N, 1, op->Ur.as<double2>(), op->N, K, c, 1.0, op->N, s));
   HIPCHK(hipStreamSynchronize(s));
   return rn;
 }
@@ -289,7 +339,8 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
   S *sv = op->raw<S>(tag + "s", N * sizeof(S));
   S *t = op->raw<S>(tag + "t", N * sizeof(S));
   KrylovState *K = op->S();
-  launch_stab_init<S>(rhat, p, r, N, tol_abs, def_thr, maxiter, K, op->rs(), s);
+  KrylovHistory h = op->history(maxiter + 4);
+  launch_stab_init<S>(rhat, p, r, N, tol_abs, def_thr, maxiter, K, h, op->rs(), s);
   KrylovState hs;
   fetch_state(op, s, hs);
   StabResult out;
@@ -305,11 +356,11 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
     Poller pl(K, s);
     while (j < maxiter) {
       ++j;
-      launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, op->rs(), s);
-      launch_stab_s<S>(sv, r, v, N, j, K, s);
-      launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, op->rs(), s);
-      launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, op->rs(), s);
-      launch_stab_p<S>(p, r, v, N, j, K, s);
+      TIMED(EB_K_STAB_V, s, launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_S, s, launch_stab_s<S>(sv, r, v, N, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_T, s, launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_XR, s, launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_P, s, launch_stab_p<S>(p, r, v, N, j, K, h, op->rs(), s));
       if (j % poll == 0 && pl.step(hs)) {
         stopped = true;
         break;
@@ -721,8 +772,8 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       free_slots.pop_front();
     }
     auto [cV, cW] = upload_coef(job->CVraw, job->CWraw);
-    launch_rotate(Vw, outl, Vw, in, cV, N, GA, 0, dots, job->jr, S, op->rs(), s);
-    launch_rotate(Ww, outl, Ww, in, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s);
+    TIMED(EB_K_ROTATE, s, launch_rotate(Vw, outl, Vw, in, cV, N, GA, 0, dots, job->jr, S, op->rs(), s));
+    TIMED(EB_K_ROTATE, s, launch_rotate(Ww, outl, Ww, in, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s));
     for (int c = 0; c < mm; ++c) free_slots.push_back(job->cols[c].slot);
     std::vector<Col> nc;
     for (int k = 0; k < kept; ++k) nc.push_back(Col{1, k, outl.idx[k]});
@@ -748,9 +799,15 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       ++j;
       if (j > P.maxiter + 1) break;
       const int cur = j & 1, prv = cur ^ 1;
+      TIMED(EB_K_BICG_MATVEC, s,
+            launch_bicg_matvec(Ap + cur * N, Adp + cur * N, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
+                               op->rs(), s));
       if (int(cols.size()) == m) {
-        // Restart at iteration j (vs = m).  History through j-1 was shipped at
-        // the end of iteration j-1; the iterate itself is never held up.
+        // Restart at iteration j (vs = m).  q = A p and s = A^+ phat were kept
+        // from iteration j-1 (vs = m-1) in the other buffer.
+        launch_arrow_vectors(GA, GB, Adp + cur * N, Adp + prv * N, Ap + cur * N, Ap + prv * N, N, j, S, dh, s);
+        // history through j-1 was shipped at the end of iteration j-1; the GPU
+        // keeps working on this iteration's matvec meanwhile
         HIPCHK(hipEventSynchronize(ev_hist));
         const KrylovState *ps = pstate.as<KrylovState>();
         if (ps->stopped) {
@@ -761,10 +818,6 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
           break;
         }
         load_dots();
-        launch_bicg_matvec(Ap + cur * N, Adp + cur * N, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
-                           op->rs(), s);
-        // q = A p and s = A^+ phat were kept from iteration j-1 (vs = m-1)
-        launch_arrow_vectors(GA, GB, Adp + cur * N, Adp + prv * N, Ap + cur * N, Ap + prv * N, N, j, S, dh, s);
         job.reset(new RestartJob);
         job->jr = j;
         job->nev = nev;
@@ -774,24 +827,26 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
         job->th = std::thread([jp = job.get()]() { jp->run(); });
         cols.clear();
         for (int k = 0; k < 2 * nev; ++k) cols.push_back(Col{1, k, -1});
-      } else {
-        launch_bicg_matvec(Ap + cur * N, Adp + cur * N, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
-                           op->rs(), s);
       }
       // vs = vs + 1: the window gains r_{j-1} (already stored raw in its slot)
       cols.push_back(Col{0, j - 1, slot_of_r[j - 1]});
-      if (free_slots.empty()) apply_job();
+      // a pending restart needs 2 nev free slots for its rotated columns: once
+      // the lag has used up the spare slots, wait for it
+      if (job && free_slots.size() <= size_t(2 * nev)) apply_job();
       if (free_slots.empty()) fail(EB_ERR_INVALID, "window slots exhausted");
       const int snew = free_slots.front();
       free_slots.pop_front();
       slot_of_r[j] = snew;
       const int sold = slot_of_r[j - 1];
-      launch_bicg_update_r(V(snew), W(snew), V(sold), W(sold), Ap + cur * N, Adp + cur * N, N, j, S, dh, op->rs(),
-                           s);
+      TIMED(EB_K_BICG_UPDATE_R, s,
+            launch_bicg_update_r(V(snew), W(snew), V(sold), W(sold), Ap + cur * N, Adp + cur * N, N, j, S, dh,
+                                 op->rs(), s));
       if (job && job->done.load(std::memory_order_acquire)) apply_job();
+      TIMED(EB_K_BICG_UPDATE_P, s, launch_bicg_update_p(x, p, ph, V(snew), W(snew), N, j, S, dh, op->rs(), s));
       if (int(cols.size()) == m) {
         // the next iteration restarts: the previous restart must be applied
-        // first; then ship the history through j and the arrow dots
+        // first; then ship the history through j (complete after update_p)
+        // and the arrow dots
         apply_job();
         if (int(cols.size()) == m) {
           copy_history(j);
@@ -800,7 +855,6 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
           HIPCHK(hipEventRecord(ev_hist, s));
         }
       }
-      launch_bicg_update_p(x, p, ph, V(snew), W(snew), N, j, S, s);
       if (j % poll == 0 && pl.step(hs)) {
         stopped = true;
         stop_at = hs.stop_at;
@@ -973,7 +1027,7 @@ eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4],
     if (bc_t != 1 && bc_t != -1) fail(EB_ERR_INVALID, "bc_t must be +1 or -1");
     if (defl_capacity < 0 || defl_capacity > kMaxCols) fail(EB_ERR_INVALID, "defl_capacity out of range [0, 128]");
     const long long V = 1LL * dims[0] * dims[1] * dims[2] * dims[3];
-    if (V * 12 >= (1LL << 31)) fail(EB_ERR_INVALID, "lattice too large");
+    if (V > kMaxVolume) fail(EB_ERR_INVALID, "lattice too large (V > " + std::to_string(kMaxVolume) + ")");
     std::unique_ptr<eb_op> op(new eb_op);
     HIPCHK(hipGetDevice(&op->device));
     op->g = Geom{dims[0], dims[1], dims[2], dims[3], int(V)};
@@ -982,8 +1036,6 @@ eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4],
     op->bc_t = bc_t;
     op->Kcap = defl_capacity;
     op->partials.ensure(kMaxPartials * sizeof(double));
-    op->tickets.ensure(kMaxTickets * sizeof(unsigned));
-    HIPCHK(hipMemset(op->tickets.p, 0, kMaxTickets * sizeof(unsigned)));
     op->state.ensure(sizeof(KrylovState));
     op->res.ensure(4 * sizeof(double));
     op->hstate.ensure(sizeof(KrylovState));
@@ -1257,6 +1309,29 @@ eb_status eb_small_eig(int32_t n, const double *Cin, double *lambda, double *y, 
           z[2 * (i * n + j) + 1] = Z(i, j).imag();
         }
       }
+  });
+}
+
+eb_status eb_timing_enable(eb_op *op, int32_t enable) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    set_device(op);
+    op->flush_timing();
+    for (int k = 0; k < EB_K_COUNT; ++k) {
+      op->t_launch[k] = 0;
+      op->t_ms[k] = 0;
+    }
+    op->timing = enable != 0;
+  });
+}
+
+eb_status eb_timing_read(eb_op *op, int32_t kclass, int64_t *launches, double *total_ms) {
+  return guarded([&]() {
+    if (!op || !launches || !total_ms || kclass < 0 || kclass >= EB_K_COUNT) fail(EB_ERR_INVALID, "bad argument");
+    set_device(op);
+    op->flush_timing();
+    *launches = op->t_launch[kclass];
+    *total_ms = op->t_ms[kclass];
   });
 }
 

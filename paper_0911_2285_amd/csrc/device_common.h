@@ -167,40 +167,44 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   }
 }
 
-// Grid-wide deterministic sum of NV doubles.  Every block writes its partial;
-// the last block to arrive (atomic ticket) sums the partials in a fixed order,
-// so the result does not depend on which block finishes last.  Returns true in
-// thread 0 of the last block, with the totals in v.  The ticket is reset for
-// the next launch.  nblk = number of participating blocks, bid = linear id.
+// Write this block's partial sums (record of NV doubles at part[bid * NV]).
 template <int NV, int BS>
-__device__ bool grid_sum(double (&v)[NV], double *partials, unsigned *ticket, int bid, int nblk) {
-  __shared__ bool last;
+__device__ __forceinline__ void block_partial(double (&v)[NV], double *__restrict__ part, int bid) {
   block_sum<NV, BS>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) partials[size_t(bid) * NV + i] = v[i];
-    __threadfence();
-    unsigned prev = atomicAdd(ticket, 1u);
-    last = (prev == unsigned(nblk - 1));
+    for (int i = 0; i < NV; ++i) part[size_t(bid) * NV + i] = v[i];
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  double acc[NV];
+}
+
+// Sum of the nblk partial records written by the previous kernel, in a fixed
+// order, so every block of the consuming kernel obtains the same totals (in
+// every thread).  Kernel boundaries make the partials visible: no fences and
+// no atomics are needed.
+template <int NV, int BS>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ part, int nblk, double (&out)[NV]) {
+  __shared__ double sm[BS / kWave][NV];
+  double v[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NV; ++i) v[i] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += BS) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-      acc[i] += __hip_atomic_load(&partials[size_t(b) * NV + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = 0; i < NV; ++i) v[i] += part[size_t(b) * NV + i];
   }
-  block_sum<NV, BS>(acc);
-  if (threadIdx.x == 0) {
+  wave_sum<NV>(v);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = acc[i];
-    atomicExch(ticket, 0u);
+    for (int i = 0; i < NV; ++i) sm[w][i] = v[i];
   }
-  return threadIdx.x == 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0;
+    for (int k = 0; k < BS / kWave; ++k) s += sm[k][i];
+    out[i] = s;
+  }
 }
 
 }  // namespace ebicg

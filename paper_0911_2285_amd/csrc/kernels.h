@@ -16,40 +16,44 @@ struct Geom {
   int V;
 };
 
-// Scalars of one Krylov solve, resident in device memory and updated by the
-// last block of each reducing kernel (so the iteration needs no host round
-// trip).  Kernels tagged with iteration j do nothing once stopped && j > stop_at.
+// Flags of one Krylov solve in device memory.  The scalars of iteration j
+// live in KrylovHistory at index j; the kernel that reduces a quantity's
+// partial sums (the consumer, in its prologue) writes them, so no kernel ever
+// reads a slot that another block of the same launch writes.  Kernels tagged
+// with iteration j do nothing once stopped && j > stop_at.
 struct KrylovState {
-  double2 rho;    // BiCG: rho_{j-1} = (rhat_{j-1}, r_{j-1});  BiCGStab: (rhat_0, r)
-  double2 alpha;  // BiCG: alpha_{j-1}
-  double2 beta;   // BiCG: beta_{j-1}
-  double2 omega;  // BiCGStab
-  double rnorm;   // recursive residual norm
-  double bnorm;   // ||b||
-  double tol_abs; // stop when rnorm <= tol_abs
-  double def_thr; // BiCGStab: stop (reason 3) when rnorm < def_thr; 0 = off
-  int stopped;    // 1 once the iteration has stopped
-  int stop_at;    // last iteration whose updates count
-  int reason;     // 1 converged, 2 breakdown, 3 DefTol threshold, 4 maxiter
+  double bnorm;    // ||b||
+  double tol_abs;  // stop when the recursive residual norm <= tol_abs
+  double def_thr;  // BiCGStab: stop (reason 3) when it drops below def_thr; 0 = off
+  double rnorm;    // last recursive residual norm
+  int stopped;     // 1 once the iteration has stopped
+  int stop_at;     // last iteration whose updates count
+  int reason;      // 1 converged, 2 breakdown, 3 DefTol threshold, 4 maxiter
   int maxiter;
 };
 
-// Per-iteration BiCG scalars (the window matrix H is built from them on the host).
+// Per-iteration scalars.  BiCG: alpha[i] = alpha_i, beta[i] = rho_{i+1}/rho_i,
+// rho[i] = (rhat_i, r_i), rn[i] = ||r_i||.  BiCGStab (iteration j = 1, 2, ...):
+// rho[j] = (rhat_0, r_j), alpha[j], omega[j], beta[j] (for p_{j+1}), rn[j].
 struct KrylovHistory {
-  double2 *alpha;  // alpha[i] = alpha_i
-  double2 *beta;   // beta[i]  = beta_i = rho_{i+1} / rho_i
-  double2 *rho;    // rho[i]   = (rhat_i, r_i)
-  double *rn;      // rn[i]    = ||r_i||
+  double2 *alpha;
+  double2 *beta;
+  double2 *rho;
+  double2 *omega;
+  double *rn;
 };
 
-// Scratch for grid-wide reductions: partial sums and tickets.  Tickets must
-// start at zero; every reducing kernel returns its ticket to zero.
+// Scratch for reductions: per-block partial sums written by a producing
+// kernel and summed, in a fixed order, by the kernel that consumes them.
 struct RedScratch {
-  double *partials;   // >= kMaxPartials doubles
-  unsigned *tickets;  // >= kMaxTickets
+  double *partials;  // >= kMaxPartials doubles
 };
 constexpr size_t kMaxPartials = size_t(1) << 22;
-constexpr int kMaxTickets = 1024;
+constexpr int kMaxRedBlocks = 2048;         // grid cap of the streaming reducing kernels
+constexpr size_t kRegionDoubles = 1 << 16;  // partial records per producer region (doubles)
+// Largest volume whose stencil kernels (one block of 256 sites, two for the
+// D / D^+ pair, records of <= 3 doubles) fit their partial records in a region.
+constexpr long long kMaxVolume = (long long)(kRegionDoubles / 4) * 256;
 
 constexpr int kMaxCols = 128;  // columns addressed by one rotation / projection launch
 struct SlotList {
@@ -58,20 +62,16 @@ struct SlotList {
 };
 
 // ---- layouts --------------------------------------------------------------
-// canonical [V][12] complex128 <-> internal SoA [12][V] (FP64 / FP32 / BF16)
+// canonical [V][12] complex <-> internal SoA [12][V] (FP64 / FP32 / BF16)
 void launch_to_soa_f64(double2 *dst, const double2 *src, const Geom &g, hipStream_t st);
 void launch_from_soa_f64(double2 *dst, const double2 *src, const Geom &g, hipStream_t st);
 void launch_to_soa_f32(float2 *dst, const float2 *src, const Geom &g, hipStream_t st);
 void launch_from_soa_f32(float2 *dst, const float2 *src, const Geom &g, hipStream_t st);
-void launch_to_soa_bf16(bf16c *dst, const bf16c *src, const Geom &g, hipStream_t st);
-void launch_from_soa_bf16(bf16c *dst, const bf16c *src, const Geom &g, hipStream_t st);
 // canonical gauge [4][V][3][3] complex128 -> SoA [4][9][V], t-boundary sign folded in
 void launch_pack_gauge_f64(double2 *dst, const double2 *src, const Geom &g, int bc_t, hipStream_t st);
 // precision conversions of SoA fields (n complex entries)
 void launch_convert_f64_f32(float2 *dst, const double2 *src, size_t n, hipStream_t st);
-void launch_convert_f64_bf16(bf16c *dst, const double2 *src, size_t n, hipStream_t st);
 void launch_convert_f32_f64(double2 *dst, const float2 *src, size_t n, hipStream_t st);
-void launch_convert_bf16_f64(double2 *dst, const bf16c *src, size_t n, hipStream_t st);
 
 // ---- operator ---------------------------------------------------------------
 // out = D in, or D^+ in when dagger; internal SoA layout.
@@ -79,29 +79,28 @@ void launch_dslash_f64(double2 *out, const double2 *in, const double2 *U, const 
                        hipStream_t st);
 void launch_dslash_f32(float2 *out, const float2 *in, const float2 *U, const Geom &g, double kappa, bool dagger,
                        hipStream_t st);
-void launch_dslash_bf16(bf16c *out, const bf16c *in, const bf16c *U, const Geom &g, double kappa, bool dagger,
-                        hipStream_t st);
 // r = b - D x (FP64); res[0] = ||r||^2, res[1] = ||b||^2 (device)
 void launch_residual_f64(double2 *r, const double2 *b, const double2 *x, const double2 *U, const Geom &g, double kappa,
                          double *res, const RedScratch &rs, hipStream_t st);
 
 // ---- BiCG (FP64, window slots) ------------------------------------------------
 // Initial state: rhat_0 = r_0 (rhat_mode 0) or gamma5 r_0 (1); p = r_0, phat = rhat_0;
-// rho_0 and ||r_0|| into state/history; res = {||r0||^2, ||b||^2} from launch_residual.
+// rho_0, ||r_0||, ||b|| into state/history; res = {||r0||^2, ||b||^2} from launch_residual.
 void launch_bicg_init(double2 *rhat, double2 *p, double2 *phat, const double2 *r, const double *res, size_t N,
                       int rhat_mode, const Geom &g, double tol, int maxiter, KrylovState *S, KrylovHistory h,
                       const RedScratch &rs, hipStream_t st);
-// Ap = D p, Adp = D^+ phat; sigma = (phat, Ap); alpha = rho / sigma.
+// Ap = D p, Adp = D^+ phat; partials of sigma = (phat, Ap).
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *phat, const double2 *U,
                         const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory h, const RedScratch &rs,
                         hipStream_t st);
-// r_out = r_in - alpha Ap; rhat_out = rhat_in - conj(alpha) Adp; rho_j, ||r_j||, beta_{j-1}.
+// alpha_{j-1} = rho_{j-1} / sigma; r_out = r_in - alpha Ap; rhat_out = rhat_in - conj(alpha) Adp;
+// partials of rho_j and ||r_j||^2.
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
                           const RedScratch &rs, hipStream_t st);
-// x += alpha p; p = r + beta p; phat = rhat + conj(beta) phat.
+// beta_{j-1}, rho_j, ||r_j|| and the stop test; x += alpha p; p = r + beta p; phat = rhat + conj(beta) phat.
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
-                          const KrylovState *S, hipStream_t st);
+                          KrylovState *S, KrylovHistory h, const RedScratch &rs, hipStream_t st);
 // GA = Adp - conj(beta_{j-2}) s ; GB = Ap - beta_{j-2} q  (the arrow vectors of a restart)
 void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const double2 *s, const double2 *Ap,
                           const double2 *q, size_t N, int j, const KrylovState *S, KrylovHistory h, hipStream_t st);
@@ -125,22 +124,30 @@ void launch_scale_f64(double2 *x, double2 a, size_t n, hipStream_t st);
 // y += x
 void launch_add_f64(double2 *y, const double2 *x, size_t n, hipStream_t st);
 
-// ---- BiCGStab (storage S: FP64, FP32 or BF16; reductions in FP64) -------------------
+// ---- BiCGStab (storage S: FP64 or FP32; reductions and scalars in FP64) -----------
+// rhat = p = r; rho_0 = ||r||^2; flags.
 template <typename S>
 void launch_stab_init(S *rhat, S *p, const S *r, size_t N, double tol_abs, double def_thr, int maxiter,
-                      KrylovState *K, const RedScratch &rs, hipStream_t st);
+                      KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st);
+// v = D p; partials of (rhat, v)
 template <typename S>
 void launch_stab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, KrylovState *K,
-                   const RedScratch &rs, hipStream_t st);
+                   KrylovHistory h, const RedScratch &rs, hipStream_t st);
+// alpha_j = rho_{j-1} / (rhat, v); s = r - alpha v
 template <typename S>
-void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, const KrylovState *K, hipStream_t st);
-template <typename S>
-void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, KrylovState *K,
+void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
                    const RedScratch &rs, hipStream_t st);
+// t = D s; partials of (t, s), (t, t)
+template <typename S>
+void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, KrylovState *K, KrylovHistory h,
+                   const RedScratch &rs, hipStream_t st);
+// omega_j; x += alpha p + omega s; r = s - omega t; partials of (rhat, r), ||r||^2
 template <typename S>
 void launch_stab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, size_t N, int j, KrylovState *K,
-                    const RedScratch &rs, hipStream_t st);
+                    KrylovHistory h, const RedScratch &rs, hipStream_t st);
+// rho_j, beta_j, the stop tests; p = r + beta (p - omega v)
 template <typename S>
-void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, const KrylovState *K, hipStream_t st);
+void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
+                   const RedScratch &rs, hipStream_t st);
 
 }  // namespace ebicg

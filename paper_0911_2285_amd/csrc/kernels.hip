@@ -5,9 +5,13 @@
 // Internal layout (HBM): a spinor is SoA [12][V] complex (component c =
 // spin*3 + colour), so every load instruction of a wavefront reads 64
 // consecutive complex numbers; links are SoA [4][9][V] complex with the
-// t-boundary factor folded into U_t at t = Lt-1.  Reductions accumulate in
-// FP64 whatever the storage precision, and finish deterministically in the
-// last block (no host round trip per iteration).
+// t-boundary factor folded into U_t at t = Lt-1.
+//
+// Reductions: a reducing kernel writes one partial record per block; the next
+// kernel on the stream sums the records in a fixed order in its prologue (the
+// same totals in every block, deterministic run to run) and its block 0
+// records the resulting scalars.  There are no grid-wide fences or atomics,
+// and no extra launches on the iteration path.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -19,14 +23,41 @@ namespace ebicg {
 
 namespace {
 
+// Partial-sum regions of the reduction scratch, one per producer so that a
+// record is never overwritten before its consumer has read it.
+enum Region : int { RG_SIGMA = 0, RG_RR, RG_V, RG_T, RG_XR, RG_INIT, RG_RES, RG_GEN };
+constexpr size_t kRegion = kRegionDoubles;
+inline double *region(const RedScratch &rs, Region r) { return rs.partials + size_t(r) * kRegion; }
+
 inline int nblocks_for(size_t n, int per_thread = 1) {
   size_t t = (n + per_thread - 1) / per_thread;
   return int((t + kBlock - 1) / kBlock);
 }
-
-__device__ __forceinline__ bool skip_iter(const KrylovState *S, int j) {
-  return S->stopped && j > S->stop_at;
+// grid of the streaming kernels with reductions: a function of n only
+inline int red_grid(size_t n) {
+  int nb = nblocks_for(n, 4);
+  return nb < 1 ? 1 : (nb > kMaxRedBlocks ? kMaxRedBlocks : nb);
 }
+// stencil kernels with reductions: one block per kBlock sites, capped; the
+// kernels loop over site blocks beyond the cap
+constexpr int kMaxStencilBlocks = 1024;
+inline int stencil_grid(int V) {
+  int nb = nblocks_for(size_t(V));
+  return nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
+}
+inline int stream_grid(size_t n) {
+  int nb = nblocks_for(n, 4);
+  return nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
+}
+
+__device__ __forceinline__ bool skip_iter(const KrylovState *S, int j) { return S->stopped && j > S->stop_at; }
+
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+__device__ __forceinline__ cx<double> c2(double2 v) { return {v.x, v.y}; }
+__device__ __forceinline__ double2 d2(cx<double> v) { return make_double2(v.x, v.y); }
 
 // ----------------------------------------------------------------------------
 // Wilson hopping term.  Gamma basis (chiral): gamma_k = [[0,-i s_k],[i s_k,0]],
@@ -37,17 +68,24 @@ __device__ __forceinline__ bool skip_iter(const KrylovState *S, int j) {
 //   mu=y: h0 = p0 - sg p3,   h1 = p1 + sg p2;    lower = (sg h1,   -sg h0)
 //   mu=z: h0 = p0 - sg i p2, h1 = p1 + sg i p3;  lower = (sg i h0, -sg i h1)
 //   mu=t: h0 = p0 + sg p2,   h1 = p1 + sg p3;    lower = (sg h0,    sg h1)
+// The colour matrix acts on the two-component half spinor only (half the
+// flops), and one output colour row is finished at a time so that only one
+// row of the link is live.
 // ----------------------------------------------------------------------------
 template <int SG, typename R>
 __device__ __forceinline__ cx<R> sgn(cx<R> a) {
   return SG > 0 ? a : -a;
 }
 
-template <int MU, int SG, typename R>
-__device__ __forceinline__ void project(const cx<R> (&p)[12], cx<R> (&h)[6]) {
+template <int MU, int SG, typename S>
+__device__ __forceinline__ void load_project(cx<typename Store<S>::R> (&h)[6], const S *__restrict__ in, int V,
+                                             int sn) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cx<R> p0 = p[a], p1 = p[3 + a], p2 = p[6 + a], p3 = p[9 + a];
+    const auto p0 = Store<S>::ld(in, size_t(a) * V + sn);
+    const auto p1 = Store<S>::ld(in, size_t(3 + a) * V + sn);
+    const auto p2 = Store<S>::ld(in, size_t(6 + a) * V + sn);
+    const auto p3 = Store<S>::ld(in, size_t(9 + a) * V + sn);
     if constexpr (MU == 0) {
       h[a] = p0 - sgn<SG>(ci(p3));
       h[3 + a] = p1 - sgn<SG>(ci(p2));
@@ -64,34 +102,57 @@ __device__ __forceinline__ void project(const cx<R> (&p)[12], cx<R> (&h)[6]) {
   }
 }
 
-template <int MU, int SG, typename R>
-__device__ __forceinline__ void accum(cx<R> (&acc)[12], const cx<R> (&u)[6]) {
+// acc += (spin reconstruction of) U h  (ADJ: U^+ h), U = U_mu at site sl.
+template <int MU, int SG, bool ADJ, typename S>
+__device__ __forceinline__ void mult_accum(cx<typename Store<S>::R> (&acc)[12], const cx<typename Store<S>::R> (&h)[6],
+                                           const S *__restrict__ U, int V, int sl) {
+  using R = typename Store<S>::R;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cx<R> u0 = u[a], u1 = u[3 + a];
-    acc[a] = acc[a] + u0;
-    acc[3 + a] = acc[3 + a] + u1;
+    cx<R> t0, t1;
+    if constexpr (!ADJ) {  // row a of U
+      const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 0) * V + sl);
+      const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 1) * V + sl);
+      const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 2) * V + sl);
+      t0 = u0 * h[0];
+      cfma(t0, u1, h[1]);
+      cfma(t0, u2, h[2]);
+      t1 = u0 * h[3];
+      cfma(t1, u1, h[4]);
+      cfma(t1, u2, h[5]);
+    } else {  // column a of U, conjugated
+      const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + 0 + a) * V + sl);
+      const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + 3 + a) * V + sl);
+      const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + 6 + a) * V + sl);
+      t0 = cmulc(u0, h[0]);
+      cfmac(t0, u1, h[1]);
+      cfmac(t0, u2, h[2]);
+      t1 = cmulc(u0, h[3]);
+      cfmac(t1, u1, h[4]);
+      cfmac(t1, u2, h[5]);
+    }
+    acc[a] = acc[a] + t0;
+    acc[3 + a] = acc[3 + a] + t1;
     if constexpr (MU == 0) {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(ci(u1));
-      acc[9 + a] = acc[9 + a] + sgn<SG>(ci(u0));
+      acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t1));
+      acc[9 + a] = acc[9 + a] + sgn<SG>(ci(t0));
     } else if constexpr (MU == 1) {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(u1);
-      acc[9 + a] = acc[9 + a] - sgn<SG>(u0);
+      acc[6 + a] = acc[6 + a] + sgn<SG>(t1);
+      acc[9 + a] = acc[9 + a] - sgn<SG>(t0);
     } else if constexpr (MU == 2) {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(ci(u0));
-      acc[9 + a] = acc[9 + a] - sgn<SG>(ci(u1));
+      acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t0));
+      acc[9 + a] = acc[9 + a] - sgn<SG>(ci(t1));
     } else {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(u0);
-      acc[9 + a] = acc[9 + a] + sgn<SG>(u1);
+      acc[6 + a] = acc[6 + a] + sgn<SG>(t0);
+      acc[9 + a] = acc[9 + a] + sgn<SG>(t1);
     }
   }
 }
 
-template <typename S>
-__device__ __forceinline__ void load_spinor(cx<typename Store<S>::R> (&p)[12], const S *__restrict__ in, int V, int s) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) p[c] = Store<S>::ld(in, size_t(c) * V + s);
-}
+// Keeps the compiler from hoisting the next hop's loads above this point, so
+// the live state stays at one hop (half spinor + link row + accumulator) and
+// the kernel runs several waves per SIMD instead of spilling.
+__device__ __forceinline__ void hop_fence() { asm volatile("" ::: "memory"); }
 
 // One direction mu: forward hop with projector (1 + SF gamma_mu) and U_mu(x),
 // backward hop with (1 - SF gamma_mu) and U_mu(x - mu)^+.
@@ -99,37 +160,13 @@ template <int MU, int SF, typename S>
 __device__ __forceinline__ void hop_dir(cx<typename Store<S>::R> (&acc)[12], const S *__restrict__ in,
                                         const S *__restrict__ U, int V, int s, int sf, int sb) {
   using R = typename Store<S>::R;
-  cx<R> p[12], h[6], uh[6], u[9];
-  // forward
-  load_spinor<S>(p, in, V, sf);
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = Store<S>::ld(U, size_t(MU * 9 + e) * V + s);
-  project<MU, SF>(p, h);
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      cx<R> t = u[a * 3] * h[k * 3];
-      cfma(t, u[a * 3 + 1], h[k * 3 + 1]);
-      cfma(t, u[a * 3 + 2], h[k * 3 + 2]);
-      uh[k * 3 + a] = t;
-    }
-  accum<MU, SF>(acc, uh);
-  // backward
-  load_spinor<S>(p, in, V, sb);
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = Store<S>::ld(U, size_t(MU * 9 + e) * V + sb);
-  project<MU, -SF>(p, h);
-#pragma unroll
-  for (int k = 0; k < 2; ++k)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      cx<R> t = cmulc(u[a], h[k * 3]);
-      cfmac(t, u[3 + a], h[k * 3 + 1]);
-      cfmac(t, u[6 + a], h[k * 3 + 2]);
-      uh[k * 3 + a] = t;
-    }
-  accum<MU, -SF>(acc, uh);
+  cx<R> h[6];
+  load_project<MU, SF, S>(h, in, V, sf);
+  mult_accum<MU, SF, false, S>(acc, h, U, V, s);
+  hop_fence();
+  load_project<MU, -SF, S>(h, in, V, sb);
+  mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
+  hop_fence();
 }
 
 // Hopping sum at site s: sum_mu [ (1 + SF g) U psi(x+mu) + (1 - SF g) U^+ psi(x-mu) ].
@@ -139,11 +176,11 @@ __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], con
                                         const S *__restrict__ U, const Geom &g, int s) {
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
   const int x = s % g.lx;
-  const int y = (s / g.lx) % g.ly;
-  const int z = (s / (g.lx * g.ly)) % g.lz;
-  const int t = s / (g.lx * g.ly * g.lz);
-  const int sy = g.lx, sz = g.lx * g.ly, stt = g.lx * g.ly * g.lz;
+  const int y = (s / sy) % g.ly;
+  const int z = (s / sz) % g.lz;
+  const int t = s / stt;
   hop_dir<0, SF, S>(acc, in, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
   hop_dir<1, SF, S>(acc, in, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
                     y == 0 ? s + (g.ly - 1) * sy : s - sy);
@@ -204,26 +241,25 @@ __global__ void __launch_bounds__(kBlock)
     k_dslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa) {
   using R = typename Store<S>::R;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = lb * kBlock + threadIdx.x;
-  if (s >= g.V) return;
-  cx<R> acc[12];
-  hopping<SF, S>(acc, in, U, g, s);
   const R k = R(kappa);
+  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
+    cx<R> acc[12];
+    hopping<SF, S>(acc, in, U, g, s);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    cx<R> v = Store<S>::ld(in, size_t(c) * g.V + s);
-    Store<S>::st(out, size_t(c) * g.V + s, v - k * acc[c]);
+    for (int c = 0; c < 12; ++c) {
+      cx<R> v = Store<S>::ld(in, size_t(c) * g.V + s);
+      Store<S>::st(out, size_t(c) * g.V + s, v - k * acc[c]);
+    }
   }
 }
 
-// r = b - D x with ||r||^2 and ||b||^2 (FP64)
+// r = b - D x with partials of ||r||^2 and ||b||^2 (FP64)
 __global__ void __launch_bounds__(kBlock)
     k_residual(double2 *__restrict__ r, const double2 *__restrict__ b, const double2 *__restrict__ xin,
-               const double2 *__restrict__ U, Geom g, double kappa, double *res, RedScratch rs) {
+               const double2 *__restrict__ U, Geom g, double kappa, double *__restrict__ part) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = lb * kBlock + threadIdx.x;
   double v[2] = {0.0, 0.0};
-  if (s < g.V) {
+  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
     cx<double> acc[12];
     hopping<-1, double2>(acc, xin, U, g, s);
 #pragma unroll
@@ -236,22 +272,26 @@ __global__ void __launch_bounds__(kBlock)
       v[1] += bv.x * bv.x + bv.y * bv.y;
     }
   }
-  if (grid_sum<2, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    res[0] = v[0];
-    res[1] = v[1];
-  }
+  block_partial<2, kBlock>(v, part, blockIdx.x);
+}
+
+// sum of partial records -> out (one block)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ part, int nblk, double *out) {
+  double v[NV];
+  sum_partials<NV, kBlock>(part, nblk, v);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NV; ++i) out[i] = v[i];
 }
 
 // ----------------------------------------------------------------------------
-// BiCG (Alg. eigBiCG loop), FP64
+// BiCG (Alg. eigBiCG loop), FP64.  Iteration j: matvec -> update_r -> update_p.
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
     k_bicg_init(double2 *__restrict__ rhat, double2 *__restrict__ p, double2 *__restrict__ ph,
-                const double2 *__restrict__ r, const double *res, size_t N, int V, int rhat_mode, double tol,
-                int maxiter, KrylovState *S, KrylovHistory h, RedScratch rs) {
-  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+                const double2 *__restrict__ r, size_t N, int V, int rhat_mode, double *__restrict__ part) {
   double v[2] = {0.0, 0.0};
-  if (i < N) {
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> rv = Store<double2>::ld(r, i);
     // gamma5 = diag(1, 1, -1, -1): components 6..11 of the SoA layout flip sign
     cx<double> hv = (rhat_mode == 1 && i >= size_t(6) * V) ? -rv : rv;
@@ -259,47 +299,51 @@ __global__ void __launch_bounds__(kBlock)
     Store<double2>::st(p, i, rv);
     Store<double2>::st(ph, i, hv);
     cx<double> d = cmulc(hv, rv);
-    v[0] = d.x;
-    v[1] = d.y;
+    v[0] += d.x;
+    v[1] += d.y;
   }
-  if (grid_sum<2, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    const double rn = sqrt(res[0]), bn = sqrt(res[1]);
-    S->rho = make_double2(v[0], v[1]);
-    S->alpha = S->beta = S->omega = make_double2(0, 0);
-    S->rnorm = rn;
-    S->bnorm = bn;
-    S->tol_abs = tol * bn;
-    S->def_thr = 0;
-    S->maxiter = maxiter;
-    h.rho[0] = S->rho;
-    h.rn[0] = rn;
-    S->stopped = 0;
-    S->stop_at = 0;
-    S->reason = 0;
-    if (rn <= S->tol_abs) {
-      S->stopped = 1;
-      S->reason = 1;
-    } else if (v[0] == 0.0 && v[1] == 0.0) {
-      S->stopped = 1;
-      S->reason = 2;
-    }
+  block_partial<2, kBlock>(v, part, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_bicg_init_finish(const double *__restrict__ part_rho, int nb_rho, const double *__restrict__ res, double tol,
+                       int maxiter, KrylovState *S, KrylovHistory h) {
+  double v[2];
+  sum_partials<2, kBlock>(part_rho, nb_rho, v);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(res[0]), bn = sqrt(res[1]);
+  h.rho[0] = make_double2(v[0], v[1]);
+  h.rn[0] = rn;
+  S->bnorm = bn;
+  S->tol_abs = tol * bn;
+  S->def_thr = 0;
+  S->rnorm = rn;
+  S->maxiter = maxiter;
+  S->stopped = 0;
+  S->stop_at = 0;
+  S->reason = 0;
+  if (rn <= S->tol_abs) {
+    S->stopped = 1;
+    S->reason = 1;
+  } else if (v[0] == 0.0 && v[1] == 0.0) {
+    S->stopped = 1;
+    S->reason = 2;
   }
 }
 
-// Blocks [0, nb) compute Ap = D p (and the sigma partial), blocks [nb, 2nb)
-// compute Adp = D^+ phat.  Linear block b -> (site block b/2, half b%2) after
-// the XCD remap, so both halves of one site block run on the same XCD and the
-// links they share are read from HBM once.
+// Blocks with an even logical index compute Ap = D p (and the sigma partial),
+// odd ones Adp = D^+ phat for the same sites.  After the XCD remap both halves
+// of a site block run on the same XCD, so the links they share come from HBM
+// once.
 __global__ void __launch_bounds__(kBlock)
     k_bicg_matvec(double2 *__restrict__ Ap, double2 *__restrict__ Adp, const double2 *__restrict__ p,
                   const double2 *__restrict__ ph, const double2 *__restrict__ U, Geom g, double kappa, int j,
-                  KrylovState *S, KrylovHistory h, RedScratch rs) {
+                  const KrylovState *S, double *__restrict__ part) {
   if (skip_iter(S, j)) return;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int half = lb & 1;
-  const int s = (lb >> 1) * kBlock + threadIdx.x;
   double v[2] = {0.0, 0.0};
-  if (s < g.V) {
+  for (int s = (lb >> 1) * kBlock + threadIdx.x; s < g.V; s += (gridDim.x >> 1) * kBlock) {
     cx<double> acc[12];
     if (half == 0) {
       hopping<-1, double2>(acc, p, U, g, s);
@@ -321,31 +365,30 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   }
-  if (grid_sum<2, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    const cx<double> sig{v[0], v[1]};
-    const double2 rho = S->rho;
-    const double den = sig.x * sig.x + sig.y * sig.y;
-    if (!(den > 0.0) || !isfinite(den)) {
-      S->stopped = 1;
-      S->stop_at = j - 1;
-      S->reason = 2;
-    } else {
-      // alpha = rho / sigma
-      cx<double> a{(rho.x * sig.x + rho.y * sig.y) / den, (rho.y * sig.x - rho.x * sig.y) / den};
-      S->alpha = make_double2(a.x, a.y);
-      h.alpha[j - 1] = S->alpha;
-    }
-  }
+  block_partial<2, kBlock>(v, part, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kBlock)
     k_bicg_update_r(double2 *__restrict__ r_out, double2 *__restrict__ rh_out, const double2 *__restrict__ r_in,
                     const double2 *__restrict__ rh_in, const double2 *__restrict__ Ap,
                     const double2 *__restrict__ Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                    RedScratch rs) {
+                    const double *__restrict__ part_sigma, int nb_sigma, double *__restrict__ part) {
   if (skip_iter(S, j)) return;
-  const double2 a2 = S->alpha;
-  const cx<double> a{a2.x, a2.y}, ac{a2.x, -a2.y};
+  double sg[2];
+  sum_partials<2, kBlock>(part_sigma, nb_sigma, sg);
+  const cx<double> sigma{sg[0], sg[1]};
+  const double den = sigma.x * sigma.x + sigma.y * sigma.y;
+  if (!(den > 0.0) || !isfinite(den)) {  // (phat, A p) = 0: breakdown
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S->stopped = 1;
+      S->stop_at = j - 1;
+      S->reason = 2;
+    }
+    return;
+  }
+  const cx<double> a = cdiv(c2(h.rho[j - 1]), sigma);
+  if (blockIdx.x == 0 && threadIdx.x == 0) h.alpha[j - 1] = d2(a);
+  const cx<double> ac = cconj(a);
   double v[3] = {0.0, 0.0, 0.0};
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> r = Store<double2>::ld(r_in, i) - a * Store<double2>::ld(Ap, i);
@@ -357,23 +400,30 @@ __global__ void __launch_bounds__(kBlock)
     v[1] += d.y;
     v[2] += r.x * r.x + r.y * r.y;
   }
-  if (grid_sum<3, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    const double2 rho0 = S->rho;
-    const cx<double> rn{v[0], v[1]};
-    const double den = rho0.x * rho0.x + rho0.y * rho0.y;
-    cx<double> beta{(rn.x * rho0.x + rn.y * rho0.y) / den, (rn.y * rho0.x - rn.x * rho0.y) / den};
-    const double rnorm = sqrt(v[2]);
-    S->beta = make_double2(beta.x, beta.y);
-    S->rho = make_double2(rn.x, rn.y);
-    S->rnorm = rnorm;
-    h.beta[j - 1] = S->beta;
-    h.rho[j] = S->rho;
+  block_partial<3, kBlock>(v, part, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_bicg_update_p(double2 *__restrict__ x, double2 *__restrict__ p, double2 *__restrict__ ph,
+                    const double2 *__restrict__ r, const double2 *__restrict__ rh, size_t N, int j, KrylovState *S,
+                    KrylovHistory h, const double *__restrict__ part_rr, int nb_rr) {
+  if (skip_iter(S, j)) return;
+  double rr[3];
+  sum_partials<3, kBlock>(part_rr, nb_rr, rr);
+  const cx<double> rho_new{rr[0], rr[1]};
+  const cx<double> a = c2(h.alpha[j - 1]);
+  const cx<double> b = cdiv(rho_new, c2(h.rho[j - 1]));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double rnorm = sqrt(rr[2]);
+    h.beta[j - 1] = d2(b);
+    h.rho[j] = d2(rho_new);
     h.rn[j] = rnorm;
+    S->rnorm = rnorm;
     if (rnorm <= S->tol_abs) {
       S->stopped = 1;
       S->stop_at = j;
       S->reason = 1;
-    } else if (rn.x == 0.0 && rn.y == 0.0) {
+    } else if (rho_new.x == 0.0 && rho_new.y == 0.0) {
       S->stopped = 1;
       S->stop_at = j;
       S->reason = 2;
@@ -383,15 +433,7 @@ __global__ void __launch_bounds__(kBlock)
       S->reason = 4;
     }
   }
-}
-
-__global__ void __launch_bounds__(kBlock)
-    k_bicg_update_p(double2 *__restrict__ x, double2 *__restrict__ p, double2 *__restrict__ ph,
-                    const double2 *__restrict__ r, const double2 *__restrict__ rh, size_t N, int j,
-                    const KrylovState *S) {
-  if (skip_iter(S, j)) return;
-  const double2 a2 = S->alpha, b2 = S->beta;
-  const cx<double> a{a2.x, a2.y}, b{b2.x, b2.y}, bc{b2.x, -b2.y};
+  const cx<double> bc = cconj(b);
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> pv = Store<double2>::ld(p, i);
     Store<double2>::st(x, i, Store<double2>::ld(x, i) + a * pv);
@@ -405,20 +447,20 @@ __global__ void __launch_bounds__(kBlock)
                     const double2 *__restrict__ s, const double2 *__restrict__ Ap, const double2 *__restrict__ q,
                     size_t N, int j, const KrylovState *S, KrylovHistory h) {
   if (skip_iter(S, j)) return;
-  const double2 b2 = h.beta[j - 2];
-  const cx<double> b{b2.x, b2.y}, bc{b2.x, -b2.y};
+  const cx<double> b = c2(h.beta[j - 2]), bc = cconj(b);
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     Store<double2>::st(GA, i, Store<double2>::ld(Adp, i) - bc * Store<double2>::ld(s, i));
     Store<double2>::st(GB, i, Store<double2>::ld(Ap, i) - b * Store<double2>::ld(q, i));
   }
 }
 
-// out[k] = sum_c in[c] C[c + k*nin], k in this block's output tile of NT.
+// out[k] = sum_c in[c] C[c + k*nin] for the k of this block's tile (NT
+// outputs), one element per thread; with g, partials of the dots.
 template <int NT>
 __global__ void __launch_bounds__(kBlock)
     k_rotate(double2 *__restrict__ out_base, SlotList out_slots, const double2 *__restrict__ in_base,
              SlotList in_slots, const double2 *__restrict__ C, size_t N, const double2 *__restrict__ g,
-             int conj_out, double2 *dots, int jtag, const KrylovState *S, RedScratch rs) {
+             int conj_out, int jtag, const KrylovState *S, double *__restrict__ part) {
   if (S && skip_iter(S, jtag)) return;
   extern __shared__ double2 sC[];  // nin x NT tile of C
   const int nin = in_slots.n;
@@ -429,14 +471,25 @@ __global__ void __launch_bounds__(kBlock)
     sC[e] = (k < nk) ? C[c + size_t(k0 + k) * nin] : make_double2(0, 0);
   }
   __syncthreads();
-  double dv[2 * NT];
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  cx<double> acc[NT];
 #pragma unroll
-  for (int k = 0; k < 2 * NT; ++k) dv[k] = 0.0;
-  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
-    cx<double> acc[NT];
+  for (int k = 0; k < NT; ++k) acc[k] = {0, 0};
+  if (i < N) {
+    int c = 0;
+    for (; c + 4 <= nin; c += 4) {
+      cx<double> v[4];
 #pragma unroll
-    for (int k = 0; k < NT; ++k) acc[k] = {0, 0};
-    for (int c = 0; c < nin; ++c) {
+      for (int u = 0; u < 4; ++u) v[u] = Store<double2>::ld(in_base + size_t(in_slots.idx[c + u]) * N, i);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          const double2 cc = sC[(c + u) + k * nin];
+          cfma(acc[k], v[u], cx<double>{cc.x, cc.y});
+        }
+    }
+    for (; c < nin; ++c) {
       const cx<double> v = Store<double2>::ld(in_base + size_t(in_slots.idx[c]) * N, i);
 #pragma unroll
       for (int k = 0; k < NT; ++k) {
@@ -444,31 +497,41 @@ __global__ void __launch_bounds__(kBlock)
         cfma(acc[k], v, cx<double>{cc.x, cc.y});
       }
     }
-    cx<double> gv{0, 0};
-    if (g) gv = Store<double2>::ld(g, i);
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      if (k < nk) {
-        Store<double2>::st(out_base + size_t(out_slots.idx[k0 + k]) * N, i, acc[k]);
-        cx<double> d = conj_out ? cmulc(acc[k], gv) : cmulc(gv, acc[k]);
-        dv[2 * k] += d.x;
-        dv[2 * k + 1] += d.y;
-      }
-    }
+    for (int k = 0; k < NT; ++k)
+      if (k < nk) Store<double2>::st(out_base + size_t(out_slots.idx[k0 + k]) * N, i, acc[k]);
   }
   if (!g) return;
-  const int nblk = gridDim.x;
-  if (grid_sum<2 * NT, kBlock>(dv, rs.partials + size_t(blockIdx.y) * nblk * 2 * NT, rs.tickets + blockIdx.y,
-                               blockIdx.x, nblk)) {
-    for (int k = 0; k < nk; ++k) dots[k0 + k] = make_double2(dv[2 * k], dv[2 * k + 1]);
+  // the dot contributions replace the outputs in the same registers
+  const cx<double> gv = (i < N) ? Store<double2>::ld(g, i) : cx<double>{0, 0};
+  double dv[2 * NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const cx<double> d = conj_out ? cmulc(acc[k], gv) : cmulc(gv, acc[k]);
+    dv[2 * k] = d.x;
+    dv[2 * k + 1] = d.y;
   }
+  block_partial<2 * NT, kBlock>(dv, part + size_t(blockIdx.y) * gridDim.x * 2 * NT, blockIdx.x);
 }
 
-// out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i] over a tile XT x YT.
+// dots[k0 + k] from the partials of tile blockIdx.x
+template <int NT>
+__global__ void __launch_bounds__(kBlock)
+    k_rotate_finish(const double *__restrict__ part, int nblk, int nout, double2 *dots, int jtag,
+                    const KrylovState *S) {
+  if (S && skip_iter(S, jtag)) return;
+  double v[2 * NT];
+  sum_partials<2 * NT, kBlock>(part + size_t(blockIdx.x) * nblk * 2 * NT, nblk, v);
+  const int k0 = blockIdx.x * NT;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NT && k0 + k < nout; ++k) dots[k0 + k] = make_double2(v[2 * k], v[2 * k + 1]);
+}
+
+// partials of out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i] over a tile XT x YT.
 template <int XT, int YT>
 __global__ void __launch_bounds__(kBlock)
-    k_ts_dot(double2 *out, const double2 *__restrict__ X, size_t ldx, int nx, const double2 *__restrict__ Y,
-             size_t ldy, int ny, size_t N, RedScratch rs) {
+    k_ts_dot(const double2 *__restrict__ X, size_t ldx, int nx, const double2 *__restrict__ Y, size_t ldy, int ny,
+             size_t N, double *__restrict__ part) {
   const int a0 = blockIdx.y * XT, b0 = blockIdx.z * YT;
   double v[2 * XT * YT];
 #pragma unroll
@@ -476,7 +539,8 @@ __global__ void __launch_bounds__(kBlock)
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> yv[YT];
 #pragma unroll
-    for (int b = 0; b < YT; ++b) yv[b] = (b0 + b < ny) ? Store<double2>::ld(Y + size_t(b0 + b) * ldy, i) : cx<double>{0, 0};
+    for (int b = 0; b < YT; ++b)
+      yv[b] = (b0 + b < ny) ? Store<double2>::ld(Y + size_t(b0 + b) * ldy, i) : cx<double>{0, 0};
 #pragma unroll
     for (int a = 0; a < XT; ++a) {
       if (a0 + a < nx) {
@@ -491,14 +555,21 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
   const int tile = blockIdx.y + gridDim.y * blockIdx.z;
-  const int nblk = gridDim.x;
-  if (grid_sum<2 * XT * YT, kBlock>(v, rs.partials + size_t(tile) * nblk * 2 * XT * YT, rs.tickets + tile,
-                                    blockIdx.x, nblk)) {
+  block_partial<2 * XT * YT, kBlock>(v, part + size_t(tile) * gridDim.x * 2 * XT * YT, blockIdx.x);
+}
+
+template <int XT, int YT>
+__global__ void __launch_bounds__(kBlock)
+    k_ts_dot_finish(double2 *out, const double *__restrict__ part, int nblk, int nx, int ny, int tiles_x) {
+  double v[2 * XT * YT];
+  const int tile = blockIdx.x;
+  sum_partials<2 * XT * YT, kBlock>(part + size_t(tile) * nblk * 2 * XT * YT, nblk, v);
+  const int a0 = (tile % tiles_x) * XT, b0 = (tile / tiles_x) * YT;
+  if (threadIdx.x == 0)
     for (int a = 0; a < XT; ++a)
       for (int b = 0; b < YT; ++b)
         if (a0 + a < nx && b0 + b < ny)
           out[(a0 + a) + size_t(b0 + b) * nx] = make_double2(v[2 * (a * YT + b)], v[2 * (a * YT + b) + 1]);
-  }
 }
 
 // Y_b += sgn * sum_a X_a C[a + b*nx] for b in this block's tile of YT.
@@ -549,12 +620,13 @@ __global__ void __launch_bounds__(kBlock) k_add(double2 *__restrict__ y, const d
 }
 
 // ----------------------------------------------------------------------------
-// BiCGStab (van der Vorst), storage S, FP64 reductions and scalars
+// BiCGStab (van der Vorst), storage S, FP64 reductions and scalars.
+// Iteration j: v -> s -> t -> xr -> p.
 // ----------------------------------------------------------------------------
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
-    k_stab_init(S *__restrict__ rhat, S *__restrict__ p, const S *__restrict__ r, size_t N, double tol_abs,
-                double def_thr, int maxiter, KrylovState *K, RedScratch rs) {
+    k_stab_init(S *__restrict__ rhat, S *__restrict__ p, const S *__restrict__ r, size_t N,
+                double *__restrict__ part) {
   double v[1] = {0.0};
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     auto rv = Store<S>::ld(r, i);
@@ -562,36 +634,40 @@ __global__ void __launch_bounds__(kBlock)
     Store<S>::st(p, i, rv);
     v[0] += double(rv.x) * rv.x + double(rv.y) * rv.y;
   }
-  if (grid_sum<1, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    K->rho = make_double2(v[0], 0.0);
-    K->alpha = make_double2(1, 0);
-    K->omega = make_double2(1, 0);
-    K->beta = make_double2(0, 0);
-    K->rnorm = sqrt(v[0]);
-    K->tol_abs = tol_abs;
-    K->def_thr = def_thr;
-    K->maxiter = maxiter;
-    K->stopped = 0;
-    K->stop_at = 0;
-    K->reason = 0;
-    if (K->rnorm <= tol_abs) {
-      K->stopped = 1;
-      K->reason = 1;
-    }
+  block_partial<1, kBlock>(v, part, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_stab_init_finish(const double *__restrict__ part, int nblk, double tol_abs, double def_thr, int maxiter,
+                       KrylovState *K, KrylovHistory h) {
+  double v[1];
+  sum_partials<1, kBlock>(part, nblk, v);
+  if (threadIdx.x != 0) return;
+  h.rho[0] = make_double2(v[0], 0.0);
+  h.rn[0] = sqrt(v[0]);
+  K->rnorm = sqrt(v[0]);
+  K->tol_abs = tol_abs;
+  K->def_thr = def_thr;
+  K->maxiter = maxiter;
+  K->stopped = 0;
+  K->stop_at = 0;
+  K->reason = 0;
+  if (K->rnorm <= tol_abs) {
+    K->stopped = 1;
+    K->reason = 1;
   }
 }
 
-// v = D p ; alpha = rho / (rhat, v)
+// v = D p ; partials of (rhat, v)
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
     k_stab_v(S *__restrict__ vout, const S *__restrict__ p, const S *__restrict__ rhat, const S *__restrict__ U,
-             Geom g, double kappa, int j, KrylovState *K, RedScratch rs) {
+             Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
   if (skip_iter(K, j)) return;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = lb * kBlock + threadIdx.x;
   double v[2] = {0.0, 0.0};
-  if (s < g.V) {
+  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
     cx<R> acc[12];
     hopping<-1, S>(acc, p, U, g, s);
     const R k = R(kappa);
@@ -600,48 +676,50 @@ __global__ void __launch_bounds__(kBlock)
       const size_t i = size_t(c) * g.V + s;
       cx<R> o = Store<S>::ld(p, i) - k * acc[c];
       Store<S>::st(vout, i, o);
-      o = Store<S>::ld(vout, i);  // the stored (rounded) v enters the dot, as in later passes
-      cx<R> h = Store<S>::ld(rhat, i);
-      v[0] += double(h.x) * o.x + double(h.y) * o.y;
-      v[1] += double(h.x) * o.y - double(h.y) * o.x;
+      cx<R> hh = Store<S>::ld(rhat, i);
+      v[0] += double(hh.x) * o.x + double(hh.y) * o.y;
+      v[1] += double(hh.x) * o.y - double(hh.y) * o.x;
     }
   }
-  if (grid_sum<2, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    const double den = v[0] * v[0] + v[1] * v[1];
-    if (!(den > 0.0) || !isfinite(den)) {
+  block_partial<2, kBlock>(v, part, blockIdx.x);
+}
+
+// alpha_j = rho_{j-1} / (rhat, v) ; s = r - alpha v
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+    k_stab_s(S *__restrict__ sv, const S *__restrict__ r, const S *__restrict__ v, size_t N, int j, KrylovState *K,
+             KrylovHistory h, const double *__restrict__ part_v, int nb_v) {
+  using R = typename Store<S>::R;
+  if (skip_iter(K, j)) return;
+  double d[2];
+  sum_partials<2, kBlock>(part_v, nb_v, d);
+  const cx<double> den{d[0], d[1]};
+  const double dd = den.x * den.x + den.y * den.y;
+  if (!(dd > 0.0) || !isfinite(dd)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       K->stopped = 1;
       K->stop_at = j - 1;
       K->reason = 2;
-    } else {
-      const double2 rho = K->rho;
-      K->alpha = make_double2((rho.x * v[0] + rho.y * v[1]) / den, (rho.y * v[0] - rho.x * v[1]) / den);
     }
+    return;
   }
-}
-
-template <typename S>
-__global__ void __launch_bounds__(kBlock)
-    k_stab_s(S *__restrict__ sv, const S *__restrict__ r, const S *__restrict__ v, size_t N, int j,
-             const KrylovState *K) {
-  using R = typename Store<S>::R;
-  if (skip_iter(K, j)) return;
-  const double2 a2 = K->alpha;
-  const cx<R> a{R(a2.x), R(a2.y)};
+  const cx<double> al = cdiv(c2(h.rho[j - 1]), den);
+  if (blockIdx.x == 0 && threadIdx.x == 0) h.alpha[j] = d2(al);
+  const cx<R> a{R(al.x), R(al.y)};
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock)
     Store<S>::st(sv, i, Store<S>::ld(r, i) - a * Store<S>::ld(v, i));
 }
 
-// t = D s ; omega = (t, s) / (t, t)
+// t = D s ; partials of (t, s), (t, t)
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
     k_stab_t(S *__restrict__ tout, const S *__restrict__ sv, const S *__restrict__ U, Geom g, double kappa, int j,
-             KrylovState *K, RedScratch rs) {
+             const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
   if (skip_iter(K, j)) return;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = lb * kBlock + threadIdx.x;
   double v[3] = {0.0, 0.0, 0.0};
-  if (s < g.V) {
+  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
     cx<R> acc[12];
     hopping<-1, S>(acc, sv, U, g, s);
     const R k = R(kappa);
@@ -651,55 +729,67 @@ __global__ void __launch_bounds__(kBlock)
       cx<R> si = Store<S>::ld(sv, i);
       cx<R> o = si - k * acc[c];
       Store<S>::st(tout, i, o);
-      o = Store<S>::ld(tout, i);
       v[0] += double(o.x) * si.x + double(o.y) * si.y;
       v[1] += double(o.x) * si.y - double(o.y) * si.x;
       v[2] += double(o.x) * o.x + double(o.y) * o.y;
     }
   }
-  if (grid_sum<3, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    if (!(v[2] > 0.0)) {
-      K->omega = make_double2(0, 0);
-      K->stopped = 1;
-      K->stop_at = j - 1;
-      K->reason = 2;
-    } else {
-      K->omega = make_double2(v[0] / v[2], v[1] / v[2]);
-    }
-  }
+  block_partial<3, kBlock>(v, part, blockIdx.x);
 }
 
-// x += alpha p + omega s ; r = s - omega t ; rho' = (rhat, r), ||r||
+// omega_j = (t, s) / (t, t) ; x += alpha p + omega s ; r = s - omega t ; partials of (rhat, r), ||r||^2
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
     k_stab_xr(S *__restrict__ x, S *__restrict__ r, const S *__restrict__ p, const S *__restrict__ sv,
-              const S *__restrict__ t, const S *__restrict__ rhat, size_t N, int j, KrylovState *K, RedScratch rs) {
+              const S *__restrict__ t, const S *__restrict__ rhat, size_t N, int j, KrylovState *K,
+              KrylovHistory h, const double *__restrict__ part_t, int nb_t, double *__restrict__ part) {
   using R = typename Store<S>::R;
   if (skip_iter(K, j)) return;
-  const double2 a2 = K->alpha, w2 = K->omega;
-  const cx<R> a{R(a2.x), R(a2.y)}, w{R(w2.x), R(w2.y)};
+  double d[3];
+  sum_partials<3, kBlock>(part_t, nb_t, d);
+  if (!(d[2] > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      K->stopped = 1;
+      K->stop_at = j - 1;
+      K->reason = 2;
+    }
+    return;
+  }
+  const cx<double> om{d[0] / d[2], d[1] / d[2]};
+  if (blockIdx.x == 0 && threadIdx.x == 0) h.omega[j] = d2(om);
+  const cx<double> al = c2(h.alpha[j]);
+  const cx<R> a{R(al.x), R(al.y)}, w{R(om.x), R(om.y)};
   double v[3] = {0.0, 0.0, 0.0};
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     const cx<R> si = Store<S>::ld(sv, i);
     Store<S>::st(x, i, Store<S>::ld(x, i) + a * Store<S>::ld(p, i) + w * si);
-    Store<S>::st(r, i, si - w * Store<S>::ld(t, i));
-    const cx<R> ri = Store<S>::ld(r, i), h = Store<S>::ld(rhat, i);
-    v[0] += double(h.x) * ri.x + double(h.y) * ri.y;
-    v[1] += double(h.x) * ri.y - double(h.y) * ri.x;
+    const cx<R> ri = si - w * Store<S>::ld(t, i);
+    Store<S>::st(r, i, ri);
+    const cx<R> hh = Store<S>::ld(rhat, i);
+    v[0] += double(hh.x) * ri.x + double(hh.y) * ri.y;
+    v[1] += double(hh.x) * ri.y - double(hh.y) * ri.x;
     v[2] += double(ri.x) * ri.x + double(ri.y) * ri.y;
   }
-  if (grid_sum<3, kBlock>(v, rs.partials, rs.tickets, blockIdx.x, gridDim.x)) {
-    const double2 rho0 = K->rho, al = K->alpha, om = K->omega;
-    const cx<double> rn{v[0], v[1]};
-    // beta = (rho'/rho) (alpha/omega)
-    const double d0 = rho0.x * rho0.x + rho0.y * rho0.y;
-    const cx<double> q{(rn.x * rho0.x + rn.y * rho0.y) / d0, (rn.y * rho0.x - rn.x * rho0.y) / d0};
-    const double d1 = om.x * om.x + om.y * om.y;
-    const cx<double> ao{(al.x * om.x + al.y * om.y) / d1, (al.y * om.x - al.x * om.y) / d1};
-    const cx<double> beta = q * ao;
-    K->beta = make_double2(beta.x, beta.y);
-    K->rho = make_double2(rn.x, rn.y);
-    const double rnorm = sqrt(v[2]);
+  block_partial<3, kBlock>(v, part, blockIdx.x);
+}
+
+// rho_j, beta_j = (rho_j / rho_{j-1}) (alpha_j / omega_j), stop tests ; p = r + beta (p - omega v)
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+    k_stab_p(S *__restrict__ p, const S *__restrict__ r, const S *__restrict__ v, size_t N, int j, KrylovState *K,
+             KrylovHistory h, const double *__restrict__ part_xr, int nb_xr) {
+  using R = typename Store<S>::R;
+  if (skip_iter(K, j)) return;
+  double d[3];
+  sum_partials<3, kBlock>(part_xr, nb_xr, d);
+  const cx<double> rho{d[0], d[1]};
+  const cx<double> om = c2(h.omega[j]);
+  const cx<double> be = cdiv(rho, c2(h.rho[j - 1])) * cdiv(c2(h.alpha[j]), om);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double rnorm = sqrt(d[2]);
+    h.rho[j] = d2(rho);
+    h.beta[j] = d2(be);
+    h.rn[j] = rnorm;
     K->rnorm = rnorm;
     if (rnorm <= K->tol_abs) {
       K->stopped = 1;
@@ -709,7 +799,7 @@ __global__ void __launch_bounds__(kBlock)
       K->stopped = 1;
       K->stop_at = j;
       K->reason = 3;
-    } else if (rn.x == 0.0 && rn.y == 0.0) {
+    } else if (rho.x == 0.0 && rho.y == 0.0) {
       K->stopped = 1;
       K->stop_at = j;
       K->reason = 2;
@@ -719,26 +809,9 @@ __global__ void __launch_bounds__(kBlock)
       K->reason = 4;
     }
   }
-}
-
-// p = r + beta (p - omega v)
-template <typename S>
-__global__ void __launch_bounds__(kBlock)
-    k_stab_p(S *__restrict__ p, const S *__restrict__ r, const S *__restrict__ v, size_t N, int j,
-             const KrylovState *K) {
-  using R = typename Store<S>::R;
-  if (skip_iter(K, j)) return;
-  const double2 b2 = K->beta, w2 = K->omega;
-  const cx<R> b{R(b2.x), R(b2.y)}, w{R(w2.x), R(w2.y)};
+  const cx<R> b{R(be.x), R(be.y)}, w{R(om.x), R(om.y)};
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock)
     Store<S>::st(p, i, Store<S>::ld(r, i) + b * (Store<S>::ld(p, i) - w * Store<S>::ld(v, i)));
-}
-
-// grid size of the streaming (grid-stride) kernels: a function of n only, so
-// reductions are reproducible run to run
-inline int stream_grid(size_t n) {
-  int nb = nblocks_for(n, 4);
-  return nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
 }
 
 }  // namespace
@@ -760,26 +833,14 @@ void launch_to_soa_f32(float2 *d, const float2 *s, const Geom &g, hipStream_t st
 void launch_from_soa_f32(float2 *d, const float2 *s, const Geom &g, hipStream_t st) {
   EB_LAUNCH(k_from_soa<float2>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);
 }
-void launch_to_soa_bf16(bf16c *d, const bf16c *s, const Geom &g, hipStream_t st) {
-  EB_LAUNCH(k_to_soa<bf16c>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);
-}
-void launch_from_soa_bf16(bf16c *d, const bf16c *s, const Geom &g, hipStream_t st) {
-  EB_LAUNCH(k_from_soa<bf16c>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);
-}
 void launch_pack_gauge_f64(double2 *d, const double2 *s, const Geom &g, int bc_t, hipStream_t st) {
   EB_LAUNCH(k_pack_gauge, dim3(nblocks_for(size_t(g.V) * 36)), dim3(kBlock), 0, st, d, s, g, bc_t);
 }
 void launch_convert_f64_f32(float2 *d, const double2 *s, size_t n, hipStream_t st) {
   EB_LAUNCH((k_convert<float2, double2>), dim3(nblocks_for(n)), dim3(kBlock), 0, st, d, s, n);
 }
-void launch_convert_f64_bf16(bf16c *d, const double2 *s, size_t n, hipStream_t st) {
-  EB_LAUNCH((k_convert<bf16c, double2>), dim3(nblocks_for(n)), dim3(kBlock), 0, st, d, s, n);
-}
 void launch_convert_f32_f64(double2 *d, const float2 *s, size_t n, hipStream_t st) {
   EB_LAUNCH((k_convert<double2, float2>), dim3(nblocks_for(n)), dim3(kBlock), 0, st, d, s, n);
-}
-void launch_convert_bf16_f64(double2 *d, const bf16c *s, size_t n, hipStream_t st) {
-  EB_LAUNCH((k_convert<double2, bf16c>), dim3(nblocks_for(n)), dim3(kBlock), 0, st, d, s, n);
 }
 
 template <typename S>
@@ -796,35 +857,39 @@ void launch_dslash_f64(double2 *o, const double2 *i, const double2 *U, const Geo
 void launch_dslash_f32(float2 *o, const float2 *i, const float2 *U, const Geom &g, double k, bool d, hipStream_t st) {
   dslash_any(o, i, U, g, k, d, st);
 }
-void launch_dslash_bf16(bf16c *o, const bf16c *i, const bf16c *U, const Geom &g, double k, bool d, hipStream_t st) {
-  dslash_any(o, i, U, g, k, d, st);
-}
 
 void launch_residual_f64(double2 *r, const double2 *b, const double2 *x, const double2 *U, const Geom &g, double kappa,
                          double *res, const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_residual, dim3(nblocks_for(g.V)), dim3(kBlock), 0, st, r, b, x, U, g, kappa, res, rs);
+  const int nb = stencil_grid(g.V);
+  EB_LAUNCH(k_residual, dim3(nb), dim3(kBlock), 0, st, r, b, x, U, g, kappa, region(rs, RG_RES));
+  EB_LAUNCH(k_finish<2>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_RES), nb, res);
 }
 
 void launch_bicg_init(double2 *rhat, double2 *p, double2 *ph, const double2 *r, const double *res, size_t N,
                       int rhat_mode, const Geom &g, double tol, int maxiter, KrylovState *S, KrylovHistory h,
                       const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_bicg_init, dim3(nblocks_for(N)), dim3(kBlock), 0, st, rhat, p, ph, r, res, N, g.V, rhat_mode, tol,
-            maxiter, S, h, rs);
+  const int nb = red_grid(N);
+  EB_LAUNCH(k_bicg_init, dim3(nb), dim3(kBlock), 0, st, rhat, p, ph, r, N, g.V, rhat_mode, region(rs, RG_INIT));
+  EB_LAUNCH(k_bicg_init_finish, dim3(1), dim3(kBlock), 0, st, region(rs, RG_INIT), nb, res, tol, maxiter, S, h);
 }
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
-                        const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory h, const RedScratch &rs,
+                        const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory, const RedScratch &rs,
                         hipStream_t st) {
-  EB_LAUNCH(k_bicg_matvec, dim3(2 * nblocks_for(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S, h, rs);
+  EB_LAUNCH(k_bicg_matvec, dim3(2 * stencil_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
+            region(rs, RG_SIGMA));
 }
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
                           const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_bicg_update_r, dim3(stream_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N, j, S,
-            h, rs);
+  // the matvec wrote 2 * stencil_grid(V) sigma records; N = 12 V
+  const int nb_sigma = 2 * stencil_grid(int(N / 12));
+  EB_LAUNCH(k_bicg_update_r, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N, j, S, h,
+            region(rs, RG_SIGMA), nb_sigma, region(rs, RG_RR));
 }
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
-                          const KrylovState *S, hipStream_t st) {
-  EB_LAUNCH(k_bicg_update_p, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, p, ph, r, rh, N, j, S);
+                          KrylovState *S, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+  EB_LAUNCH(k_bicg_update_p, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, p, ph, r, rh, N, j, S, h,
+            region(rs, RG_RR), red_grid(N));
 }
 void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const double2 *s, const double2 *Ap,
                           const double2 *q, size_t N, int j, const KrylovState *S, KrylovHistory h, hipStream_t st) {
@@ -835,22 +900,27 @@ void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *
                    const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
                    const KrylovState *S, const RedScratch &rs, hipStream_t st) {
   const int nout = out_slots.n;
-  const int nb = stream_grid(N);
+  const int nb = nblocks_for(N);
+  double *part = region(rs, RG_GEN);
   auto go = [&](auto nt_tag) {
     constexpr int NT = decltype(nt_tag)::value;
-    dim3 grid(nb, (nout + NT - 1) / NT);
+    const int tiles = (nout + NT - 1) / NT;
+    dim3 grid(nb, tiles);
     size_t sh = size_t(in_slots.n) * NT * sizeof(double2);
     EB_LAUNCH(k_rotate<NT>, grid, dim3(kBlock), sh, st, out_base, out_slots, in_base, in_slots, C, N, g, conj_out,
-              dots, jtag, S, rs);
+              jtag, S, part);
+    if (g) EB_LAUNCH(k_rotate_finish<NT>, dim3(tiles), dim3(kBlock), 0, st, part, nb, nout, dots, jtag, S);
   };
   if (nout <= 4)
     go(std::integral_constant<int, 4>{});
   else if (nout <= 8)
     go(std::integral_constant<int, 8>{});
+  else if (nout <= 12)
+    go(std::integral_constant<int, 12>{});
   else if (nout <= 16)
     go(std::integral_constant<int, 16>{});
   else
-    go(std::integral_constant<int, 24>{});
+    go(std::integral_constant<int, 20>{});
 }
 
 void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny, size_t N,
@@ -858,14 +928,16 @@ void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const dou
   constexpr int XT = 8, YT = 2;
   const int tx = (nx + XT - 1) / XT, ty = (ny + YT - 1) / YT;
   const int tiles = tx * ty;
-  if (tiles > kMaxTickets) return;  // callers stay within kMaxCols x kMaxCols
-  // every tile keeps nb partials of 2 XT YT doubles in the shared scratch
+  // every tile keeps nb partial records of 2 XT YT doubles
+  double *part = region(rs, RG_GEN);
+  const size_t avail = kMaxPartials - size_t(RG_GEN) * kRegion;
   int nb = stream_grid(N);
-  const int cap = int(kMaxPartials / (size_t(tiles) * 2 * XT * YT));
+  const int cap = int(avail / (size_t(tiles) * 2 * XT * YT));
   nb = nb < 1024 ? nb : 1024;
   nb = nb < cap ? nb : cap;
-  dim3 grid(nb, tx, ty);
-  EB_LAUNCH((k_ts_dot<XT, YT>), grid, dim3(kBlock), 0, st, out, X, ldx, nx, Y, ldy, ny, N, rs);
+  nb = nb < 1 ? 1 : nb;
+  EB_LAUNCH((k_ts_dot<XT, YT>), dim3(nb, tx, ty), dim3(kBlock), 0, st, X, ldx, nx, Y, ldy, ny, N, part);
+  EB_LAUNCH((k_ts_dot_finish<XT, YT>), dim3(tiles), dim3(kBlock), 0, st, out, part, nb, nx, ny, tx);
 }
 void launch_ts_update(double2 *Y, size_t ldy, int ny, const double2 *X, size_t ldx, int nx, const double2 *C,
                       double sgn, size_t N, hipStream_t st) {
@@ -887,45 +959,55 @@ void launch_add_f64(double2 *y, const double2 *x, size_t n, hipStream_t st) {
 
 template <typename S>
 void launch_stab_init(S *rhat, S *p, const S *r, size_t N, double tol_abs, double def_thr, int maxiter,
-                      KrylovState *K, const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_stab_init<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, rhat, p, r, N, tol_abs, def_thr, maxiter, K,
-            rs);
+                      KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+  const int nb = red_grid(N);
+  EB_LAUNCH(k_stab_init<S>, dim3(nb), dim3(kBlock), 0, st, rhat, p, r, N, region(rs, RG_INIT));
+  EB_LAUNCH(k_stab_init_finish, dim3(1), dim3(kBlock), 0, st, region(rs, RG_INIT), nb, tol_abs, def_thr, maxiter, K,
+            h);
 }
 template <typename S>
 void launch_stab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, KrylovState *K,
-                   const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_stab_v<S>, dim3(nblocks_for(g.V)), dim3(kBlock), 0, st, v, p, rhat, U, g, kappa, j, K, rs);
+                   KrylovHistory, const RedScratch &rs, hipStream_t st) {
+  EB_LAUNCH(k_stab_v<S>, dim3(stencil_grid(g.V)), dim3(kBlock), 0, st, v, p, rhat, U, g, kappa, j, K,
+            region(rs, RG_V));
 }
 template <typename S>
-void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, const KrylovState *K, hipStream_t st) {
-  EB_LAUNCH(k_stab_s<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, s, r, v, N, j, K);
+void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
+                   const RedScratch &rs, hipStream_t st) {
+  EB_LAUNCH(k_stab_s<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, s, r, v, N, j, K, h, region(rs, RG_V),
+            stencil_grid(int(N / 12)));
 }
 template <typename S>
-void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, KrylovState *K,
+void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, KrylovState *K, KrylovHistory,
                    const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_stab_t<S>, dim3(nblocks_for(g.V)), dim3(kBlock), 0, st, t, s, U, g, kappa, j, K, rs);
+  EB_LAUNCH(k_stab_t<S>, dim3(stencil_grid(g.V)), dim3(kBlock), 0, st, t, s, U, g, kappa, j, K, region(rs, RG_T));
 }
 template <typename S>
 void launch_stab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, size_t N, int j, KrylovState *K,
-                    const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_stab_xr<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, r, p, s, t, rhat, N, j, K, rs);
+                    KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+  EB_LAUNCH(k_stab_xr<S>, dim3(red_grid(N)), dim3(kBlock), 0, st, x, r, p, s, t, rhat, N, j, K, h, region(rs, RG_T),
+            stencil_grid(int(N / 12)), region(rs, RG_XR));
 }
 template <typename S>
-void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, const KrylovState *K, hipStream_t st) {
-  EB_LAUNCH(k_stab_p<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, p, r, v, N, j, K);
+void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
+                   const RedScratch &rs, hipStream_t st) {
+  EB_LAUNCH(k_stab_p<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, p, r, v, N, j, K, h, region(rs, RG_XR),
+            red_grid(N));
 }
 
 #define EB_STAB_INST(S)                                                                                              \
-  template void launch_stab_init<S>(S *, S *, const S *, size_t, double, double, int, KrylovState *,               \
+  template void launch_stab_init<S>(S *, S *, const S *, size_t, double, double, int, KrylovState *, KrylovHistory, \
                                     const RedScratch &, hipStream_t);                                                \
   template void launch_stab_v<S>(S *, const S *, const S *, const S *, const Geom &, double, int, KrylovState *,    \
+                                 KrylovHistory, const RedScratch &, hipStream_t);                                    \
+  template void launch_stab_s<S>(S *, const S *, const S *, size_t, int, KrylovState *, KrylovHistory,              \
                                  const RedScratch &, hipStream_t);                                                   \
-  template void launch_stab_s<S>(S *, const S *, const S *, size_t, int, const KrylovState *, hipStream_t);         \
-  template void launch_stab_t<S>(S *, const S *, const S *, const Geom &, double, int, KrylovState *,               \
+  template void launch_stab_t<S>(S *, const S *, const S *, const Geom &, double, int, KrylovState *, KrylovHistory, \
                                  const RedScratch &, hipStream_t);                                                   \
   template void launch_stab_xr<S>(S *, S *, const S *, const S *, const S *, const S *, size_t, int, KrylovState *, \
-                                  const RedScratch &, hipStream_t);                                                  \
-  template void launch_stab_p<S>(S *, const S *, const S *, size_t, int, const KrylovState *, hipStream_t);
+                                  KrylovHistory, const RedScratch &, hipStream_t);                                   \
+  template void launch_stab_p<S>(S *, const S *, const S *, size_t, int, KrylovState *, KrylovHistory,              \
+                                 const RedScratch &, hipStream_t);
 EB_STAB_INST(double2)
 EB_STAB_INST(float2)
 

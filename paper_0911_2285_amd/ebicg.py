@@ -17,6 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libebicg.so")
 
 EB_OK = 0
+# kernel classes of eb_timing_read (include/ebicg.h)
+KERNEL_CLASSES = ["bicg_matvec", "bicg_update_r", "bicg_update_p", "stab_v", "stab_s", "stab_t", "stab_xr", "stab_p",
+                  "rotate", "residual", "proj"]
 STATUS = {
     0: "EB_OK",
     -1: "EB_ERR_INVALID",
@@ -93,6 +96,9 @@ _SIGNATURES = [
     ("eb_defl_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
     ("eb_defl_reset", ctypes.c_int, [_P]),
     ("eb_small_eig", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
+    ("eb_timing_enable", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("eb_timing_read", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_double)]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
     ("eb_version", ctypes.c_char_p, []),
 ]
@@ -287,3 +293,19 @@ def defl_info(op):
 
 def defl_reset(op):
     _check(lib().eb_defl_reset(op.handle))
+
+
+def timing_enable(op, enable=True):
+    """Start (and reset) or stop per-kernel HIP-event timing inside the library's solves."""
+    _check(lib().eb_timing_enable(op.handle, int(bool(enable))))
+
+
+def timing_read(op):
+    """{kernel class: (launches, total ms)} since the last timing_enable."""
+    out = {}
+    for k, name in enumerate(KERNEL_CLASSES):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0)
+        _check(lib().eb_timing_read(op.handle, k, ctypes.byref(n), ctypes.byref(ms)))
+        out[name] = (n.value, ms.value)
+    return out
