@@ -159,6 +159,7 @@ enum {
   EB_K_ROTATE,          /* window rotation (Alg. BiCG-eigen) */
   EB_K_RESIDUAL,        /* b - D x in FP64 */
   EB_K_PROJ,            /* deflation projections (tall-skinny products) */
+  EB_K_DSLASH,          /* plain D or D^+ applications (extending H) */
   EB_K_COUNT
 };
 eb_status eb_timing_enable(eb_op *op, int32_t enable);

@@ -30,6 +30,7 @@ HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fcx-limited-range"]
 SOURCES = [
     ("kernels.hip", "hip"),
     ("api.hip", "hip"),
+    ("tsmm.hip", "hip"),
     ("hostla.cpp", "host"),
 ]
 

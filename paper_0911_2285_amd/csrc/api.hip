@@ -923,63 +923,118 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
 // Biorthogonalise the nnew pairs in Ur[:, K..K+nnew), Ul[:, K..) against the
 // space and among themselves, extend H = Ul^+ A Ur, and grow K (Alg.
 // Incremental eigBiCG, step 2, items 3-5).  Returns the number kept.
+//
+// Against the space: two block passes V' -= Ur (Ul^+ V'), W' -= Ul (Ur^+ W')
+// (tall-skinny products that read each column once per pass).  Among
+// themselves: a two-sided Gram-Schmidt (twice) carried out in coefficient
+// space on the small Gram matrices W'^+ V', V'^+ V', W'^+ W', then applied
+// with one out-of-place combination.  In exact arithmetic this gives the same
+// vectors as projecting each new pair against the space and the earlier new
+// pairs in turn, since the oblique projector onto the complement of the space
+// is idempotent and leaves the earlier new pairs unchanged.
 int absorb(eb_op *op, int nnew, eb_stats &st, hipStream_t s) {
   const size_t N = op->N;
   const int K = op->K;
   double2 *Ur = op->Ur.as<double2>(), *Ul = op->Ul.as<double2>();
-  double2 *C = op->raw<double2>("abs_C", size_t(op->Kcap) * 4 * sizeof(double2));
-  std::vector<double2> hbuf(size_t(op->Kcap) * 4);
-  auto col_r = [&](int c) { return Ur + size_t(c) * N; };
-  auto col_l = [&](int c) { return Ul + size_t(c) * N; };
-  int kept = 0;
-  for (int k = 0; k < nnew; ++k) {
-    double2 *v = col_r(K + k), *w = col_l(K + k);
-    // move the candidate into position K + kept
-    if (kept != k) {
-      launch_copy_f64(col_r(K + kept), v, N, s);
-      launch_copy_f64(col_l(K + kept), w, N, s);
-      v = col_r(K + kept);
-      w = col_l(K + kept);
+  double2 *Vn = Ur + size_t(K) * N, *Wn = Ul + size_t(K) * N;
+  double2 *C = op->raw<double2>("abs_C", size_t(op->Kcap) * nnew * 2 * sizeof(double2));
+  if (K > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      TIMED(EB_K_PROJ, s, launch_ts_dot(C, Ul, N, K, Vn, N, nnew, N, op->rs(), s));
+      TIMED(EB_K_PROJ, s, launch_ts_dot(C + size_t(K) * nnew, Ur, N, K, Wn, N, nnew, N, op->rs(), s));
+      TIMED(EB_K_PROJ, s, launch_ts_update(Vn, N, nnew, Ur, N, K, C, -1.0, N, s));
+      TIMED(EB_K_PROJ, s, launch_ts_update(Wn, N, nnew, Ul, N, K, C + size_t(K) * nnew, -1.0, N, s));
     }
-    const int nprev = K + kept;  // columns the pair is made biorthogonal to
-    for (int pass = 0; pass < 2 && nprev > 0; ++pass) {
-      // v -= Ur (Ul^+ v);  w -= Ul (Ur^+ w)
-      launch_ts_dot(C, Ul, N, nprev, v, N, 1, N, op->rs(), s);
-      launch_ts_dot(C + op->Kcap, Ur, N, nprev, w, N, 1, N, op->rs(), s);
-      launch_ts_update(v, N, 1, Ur, N, nprev, C, -1.0, N, s);
-      launch_ts_update(w, N, 1, Ul, N, nprev, C + op->Kcap, -1.0, N, s);
-    }
-    // pivot w^+ v, ||v||^2, ||w||^2
-    launch_ts_dot(C, w, N, 1, v, N, 1, N, op->rs(), s);
-    launch_ts_dot(C + 1, v, N, 1, v, N, 1, N, op->rs(), s);
-    launch_ts_dot(C + 2, w, N, 1, w, N, 1, N, op->rs(), s);
-    HIPCHK(hipMemcpyAsync(hbuf.data(), C, 3 * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const cd piv = c2(hbuf[0]);
-    const double nv = std::sqrt(hbuf[1].x), nw = std::sqrt(hbuf[2].x);
-    if (!(std::abs(piv) > 1e-12 * nv * nw)) continue;
-    // v /= ||v||, w /= conj(w^+ v / ||v||)
-    launch_scale_f64(v, make_double2(1.0 / nv, 0.0), N, s);
-    const cd sw = 1.0 / std::conj(piv / nv);
-    launch_scale_f64(w, d2(sw), N, s);
-    ++kept;
   }
+  // Gram matrices of the new block: M = W'^+ V', G = V'^+ V', F = W'^+ W'
+  const size_t n2 = size_t(nnew) * nnew;
+  double2 *gram = op->raw<double2>("abs_gram", 3 * n2 * sizeof(double2));
+  TIMED(EB_K_PROJ, s, launch_ts_dot(gram, Wn, N, nnew, Vn, N, nnew, N, op->rs(), s));
+  TIMED(EB_K_PROJ, s, launch_ts_dot(gram + n2, Vn, N, nnew, Vn, N, nnew, N, op->rs(), s));
+  TIMED(EB_K_PROJ, s, launch_ts_dot(gram + 2 * n2, Wn, N, nnew, Wn, N, nnew, N, op->rs(), s));
+  std::vector<double2> hg(3 * n2);
+  HIPCHK(hipMemcpyAsync(hg.data(), gram, hg.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  CMat M(nnew, nnew), G(nnew, nnew), F(nnew, nnew);
+  for (int b2 = 0; b2 < nnew; ++b2)
+    for (int a2 = 0; a2 < nnew; ++a2) {
+      M(a2, b2) = c2(hg[a2 + size_t(b2) * nnew]);
+      G(a2, b2) = c2(hg[n2 + a2 + size_t(b2) * nnew]);
+      F(a2, b2) = c2(hg[2 * n2 + a2 + size_t(b2) * nnew]);
+    }
+  // inner products of combinations: w^+ v = cw^+ M cv, v^+ v = cv^+ G cv, w^+ w = cw^+ F cw
+  auto quad = [&](const CMat &A, const std::vector<cd> &x, const std::vector<cd> &y) {
+    cd acc = 0;
+    for (int i2 = 0; i2 < nnew; ++i2) {
+      cd row = 0;
+      for (int j2 = 0; j2 < nnew; ++j2) row += A(i2, j2) * y[j2];
+      acc += std::conj(x[i2]) * row;
+    }
+    return acc;
+  };
+  std::vector<std::vector<cd>> cvs, cws;
+  for (int k = 0; k < nnew; ++k) {
+    std::vector<cd> cv(nnew, 0.0), cw(nnew, 0.0);
+    cv[k] = cw[k] = 1.0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t q = 0; q < cvs.size(); ++q) {
+        const cd a1 = quad(M, cws[q], cv);                 // w_q^+ v
+        const cd b1 = std::conj(quad(M, cw, cvs[q]));      // v_q^+ w = conj(w^+ v_q)
+        for (int i2 = 0; i2 < nnew; ++i2) {
+          cv[i2] -= cvs[q][i2] * a1;
+          cw[i2] -= cws[q][i2] * b1;
+        }
+      }
+    const cd piv = quad(M, cw, cv);
+    const double nv = std::sqrt(std::max(0.0, quad(G, cv, cv).real()));
+    const double nw = std::sqrt(std::max(0.0, quad(F, cw, cw).real()));
+    if (!(std::abs(piv) > 1e-12 * nv * nw)) continue;
+    for (auto &e : cv) e /= nv;
+    const cd pn = piv / nv;
+    for (auto &e : cw) e /= std::conj(pn);
+    cvs.push_back(cv);
+    cws.push_back(cw);
+  }
+  const int kept = int(cvs.size());
   if (kept == 0) return 0;
+  std::vector<double2> cv(size_t(nnew) * kept), cw(size_t(nnew) * kept);
+  for (int k = 0; k < kept; ++k)
+    for (int i2 = 0; i2 < nnew; ++i2) {
+      cv[i2 + size_t(k) * nnew] = d2(cvs[k][i2]);
+      cw[i2 + size_t(k) * nnew] = d2(cws[k][i2]);
+    }
+  double2 *dc = op->raw<double2>("abs_coef", 2 * size_t(nnew) * kept * sizeof(double2));
+  HIPCHK(hipMemcpyAsync(dc, cv.data(), cv.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dc + cv.size(), cw.data(), cw.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  double2 *tv = op->vec("abs_tv", kept), *tw = op->vec("abs_tw", kept);
+  SlotList in{}, o{};
+  in.n = nnew;
+  for (int i2 = 0; i2 < nnew; ++i2) in.idx[i2] = K + i2;
+  o.n = kept;
+  for (int k = 0; k < kept; ++k) o.idx[k] = k;
+  TIMED(EB_K_ROTATE, s, launch_rotate(tv, o, Ur, in, dc, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s));
+  TIMED(EB_K_ROTATE, s, launch_rotate(tw, o, Ul, in, dc + cv.size(), N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s));
+  HIPCHK(hipMemcpyAsync(Vn, tv, size_t(kept) * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(Wn, tw, size_t(kept) * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
   // A V', A^+ W'
   double2 *AV = op->vec("abs_AV", kept), *AdW = op->vec("abs_AdW", kept);
   for (int k = 0; k < kept; ++k) {
-    launch_dslash_f64(AV + size_t(k) * N, col_r(K + k), op->U64.as<double2>(), op->g, op->kappa, false, s);
-    launch_dslash_f64(AdW + size_t(k) * N, col_l(K + k), op->U64.as<double2>(), op->g, op->kappa, true, s);
+    TIMED(EB_K_DSLASH, s,
+          launch_dslash_f64(AV + size_t(k) * N, Vn + size_t(k) * N, op->U64.as<double2>(), op->g, op->kappa, false,
+                            s));
+    TIMED(EB_K_DSLASH, s,
+          launch_dslash_f64(AdW + size_t(k) * N, Wn + size_t(k) * N, op->U64.as<double2>(), op->g, op->kappa, true,
+                            s));
   }
   st.matvec_d += kept;
   st.matvec_ddag += kept;
   const int Kn = K + kept;
   double2 *blk = op->raw<double2>("abs_blk", size_t(Kn) * kept * sizeof(double2));
-  double2 *blk2 = op->raw<double2>("abs_blk2", size_t(Kn) * kept * sizeof(double2));
-  // Ul_all^+ (A V') : Kn x kept  (rows < K: the new column block; rows >= K: W'^+ A V')
-  launch_ts_dot(blk, Ul, N, Kn, AV, N, kept, N, op->rs(), s);
-  // (A^+ W')^+ Ur = conj of Ur^+ (A^+ W'):  K x kept, transposed-conjugated below
-  if (K > 0) launch_ts_dot(blk2, Ur, N, K, AdW, N, kept, N, op->rs(), s);
+  double2 *blk2 = op->raw<double2>("abs_blk2", size_t(std::max(K, 1)) * kept * sizeof(double2));
+  // Ul_all^+ (A V'): rows < K give the new column block, rows >= K give W'^+ A V'
+  TIMED(EB_K_PROJ, s, launch_ts_dot(blk, Ul, N, Kn, AV, N, kept, N, op->rs(), s));
+  // Ur^+ (A^+ W'): its conjugate transpose is W'^+ A Ur
+  if (K > 0) TIMED(EB_K_PROJ, s, launch_ts_dot(blk2, Ur, N, K, AdW, N, kept, N, op->rs(), s));
   std::vector<double2> h1(size_t(Kn) * kept), h2(size_t(K) * kept);
   HIPCHK(hipMemcpyAsync(h1.data(), blk, h1.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
   if (K > 0) HIPCHK(hipMemcpyAsync(h2.data(), blk2, h2.size() * sizeof(double2), hipMemcpyDeviceToHost, s));

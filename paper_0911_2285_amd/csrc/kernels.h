@@ -48,12 +48,13 @@ struct KrylovHistory {
 struct RedScratch {
   double *partials;  // >= kMaxPartials doubles
 };
-constexpr size_t kMaxPartials = size_t(1) << 22;
+constexpr size_t kMaxPartials = size_t(1) << 23;
 constexpr int kMaxRedBlocks = 2048;         // grid cap of the streaming reducing kernels
 constexpr size_t kRegionDoubles = 1 << 16;  // partial records per producer region (doubles)
-// Largest volume whose stencil kernels (one block of 256 sites, two for the
-// D / D^+ pair, records of <= 3 doubles) fit their partial records in a region.
-constexpr long long kMaxVolume = (long long)(kRegionDoubles / 4) * 256;
+// Largest volume the library accepts: the window rotation keeps one partial
+// record of up to 40 doubles per block of 256 entries of a spinor (12 V
+// entries) in the general region of the scratch.
+constexpr long long kMaxVolume = 4LL << 20;
 
 constexpr int kMaxCols = 128;  // columns addressed by one rotation / projection launch
 struct SlotList {
@@ -114,9 +115,21 @@ void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *
 // out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i];  X_a = X + a*ldx, Y_b = Y + b*ldy.
 void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny, size_t N,
                    const RedScratch &rs, hipStream_t st);
-// Y_b += sgn * sum_a X_a C[a + b*nx]
+// Y_b += sgn * sum_a X_a C[a + b*nx]  (nx, ny <= kMaxCols)
 void launch_ts_update(double2 *Y, size_t ldy, int ny, const double2 *X, size_t ldx, int nx, const double2 *C,
                       double sgn, size_t N, hipStream_t st);
+
+// Matrix-core forms (tsmm.hip).  gram: out = X^+ Y for nx <= 128 (any ny);
+// part: scratch for per-block records, part_cap doubles.
+void launch_gram_mfma(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny,
+                      size_t N, double *part, size_t part_cap, hipStream_t st);
+// combine: out_k (+)= sgn sum_c in_c C[c + k*nin], column c at in_base + in_slots.idx[c]*ldi and
+// out_k at out_base + out_slots.idx[k]*ldo; with g, dots[k] = g^+ out_k (conj_out 0) or out_k^+ g (1).
+// Skipped when S && S->stopped && jtag > S->stop_at.
+void launch_combine_mfma(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
+                         const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
+                         const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
+                         size_t part_cap, hipStream_t st);
 
 // ---- BLAS-1 (FP64) ---------------------------------------------------------------
 void launch_copy_f64(double2 *dst, const double2 *src, size_t n, hipStream_t st);

@@ -190,6 +190,77 @@ __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], con
                     t == 0 ? s + (g.lt - 1) * stt : s - stt);
 }
 
+// acc_sg += (spin reconstruction with sign SG of) t for output colour row a.
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void recon_row(cx<R> (&acc)[12], int a, cx<R> t0, cx<R> t1) {
+  acc[a] = acc[a] + t0;
+  acc[3 + a] = acc[3 + a] + t1;
+  if constexpr (MU == 0) {
+    acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t1));
+    acc[9 + a] = acc[9 + a] + sgn<SG>(ci(t0));
+  } else if constexpr (MU == 1) {
+    acc[6 + a] = acc[6 + a] + sgn<SG>(t1);
+    acc[9 + a] = acc[9 + a] - sgn<SG>(t0);
+  } else if constexpr (MU == 2) {
+    acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t0));
+    acc[9 + a] = acc[9 + a] - sgn<SG>(ci(t1));
+  } else {
+    acc[6 + a] = acc[6 + a] + sgn<SG>(t0);
+    acc[9 + a] = acc[9 + a] + sgn<SG>(t1);
+  }
+}
+
+// D p and D^+ ph hops of direction mu in one thread: every link row is
+// loaded once and applied to both half spinors (D uses 1 - gamma forward and
+// 1 + gamma backward; D^+ the opposite).
+template <int MU, typename S>
+__device__ __forceinline__ void pair_dir(cx<typename Store<S>::R> (&ad)[12], cx<typename Store<S>::R> (&aa)[12],
+                                         const S *__restrict__ p, const S *__restrict__ ph, const S *__restrict__ U,
+                                         int V, int s, int sf, int sb) {
+  using R = typename Store<S>::R;
+  cx<R> h1[6], h2[6];
+  load_project<MU, -1, S>(h1, p, V, sf);
+  load_project<MU, +1, S>(h2, ph, V, sf);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 0) * V + s);
+    const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 1) * V + s);
+    const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 2) * V + s);
+    cx<R> t0 = u0 * h1[0], t1 = u0 * h1[3], q0 = u0 * h2[0], q1 = u0 * h2[3];
+    cfma(t0, u1, h1[1]);
+    cfma(t0, u2, h1[2]);
+    cfma(t1, u1, h1[4]);
+    cfma(t1, u2, h1[5]);
+    cfma(q0, u1, h2[1]);
+    cfma(q0, u2, h2[2]);
+    cfma(q1, u1, h2[4]);
+    cfma(q1, u2, h2[5]);
+    recon_row<MU, -1>(ad, a, t0, t1);
+    recon_row<MU, +1>(aa, a, q0, q1);
+  }
+  hop_fence();
+  load_project<MU, +1, S>(h1, p, V, sb);
+  load_project<MU, -1, S>(h2, ph, V, sb);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + 0 + a) * V + sb);
+    const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + 3 + a) * V + sb);
+    const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + 6 + a) * V + sb);
+    cx<R> t0 = cmulc(u0, h1[0]), t1 = cmulc(u0, h1[3]), q0 = cmulc(u0, h2[0]), q1 = cmulc(u0, h2[3]);
+    cfmac(t0, u1, h1[1]);
+    cfmac(t0, u2, h1[2]);
+    cfmac(t1, u1, h1[4]);
+    cfmac(t1, u2, h1[5]);
+    cfmac(q0, u1, h2[1]);
+    cfmac(q0, u2, h2[2]);
+    cfmac(q1, u1, h2[4]);
+    cfmac(q1, u2, h2[5]);
+    recon_row<MU, +1>(ad, a, t0, t1);
+    recon_row<MU, -1>(aa, a, q0, q1);
+  }
+  hop_fence();
+}
+
 // ----------------------------------------------------------------------------
 // Layout kernels
 // ----------------------------------------------------------------------------
@@ -331,38 +402,40 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Blocks with an even logical index compute Ap = D p (and the sigma partial),
-// odd ones Adp = D^+ phat for the same sites.  After the XCD remap both halves
-// of a site block run on the same XCD, so the links they share come from HBM
-// once.
+// Ap = D p and Adp = D^+ phat in one pass over the lattice (each link loaded
+// once for both), with the partials of sigma = (phat, Ap): phat(x) is loaded
+// for the diagonal term of D^+ anyway.
 __global__ void __launch_bounds__(kBlock)
     k_bicg_matvec(double2 *__restrict__ Ap, double2 *__restrict__ Adp, const double2 *__restrict__ p,
                   const double2 *__restrict__ ph, const double2 *__restrict__ U, Geom g, double kappa, int j,
                   const KrylovState *S, double *__restrict__ part) {
   if (skip_iter(S, j)) return;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int half = lb & 1;
   double v[2] = {0.0, 0.0};
-  for (int s = (lb >> 1) * kBlock + threadIdx.x; s < g.V; s += (gridDim.x >> 1) * kBlock) {
-    cx<double> acc[12];
-    if (half == 0) {
-      hopping<-1, double2>(acc, p, U, g, s);
+  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
+  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
+    cx<double> ad[12], aa[12];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const size_t i = size_t(c) * g.V + s;
-        cx<double> o = Store<double2>::ld(p, i) - kappa * acc[c];
-        Store<double2>::st(Ap, i, o);
-        cx<double> d = cmulc(Store<double2>::ld(ph, i), o);
-        v[0] += d.x;
-        v[1] += d.y;
-      }
-    } else {
-      hopping<+1, double2>(acc, ph, U, g, s);
+    for (int c = 0; c < 12; ++c) ad[c] = aa[c] = {0, 0};
+    const int x = s % g.lx, y = (s / sy) % g.ly, z = (s / sz) % g.lz, t = s / stt;
+    pair_dir<0, double2>(ad, aa, p, ph, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1,
+                         x == 0 ? s + (g.lx - 1) : s - 1);
+    pair_dir<1, double2>(ad, aa, p, ph, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
+                         y == 0 ? s + (g.ly - 1) * sy : s - sy);
+    pair_dir<2, double2>(ad, aa, p, ph, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
+                         z == 0 ? s + (g.lz - 1) * sz : s - sz);
+    pair_dir<3, double2>(ad, aa, p, ph, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
+                         t == 0 ? s + (g.lt - 1) * stt : s - stt);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const size_t i = size_t(c) * g.V + s;
-        Store<double2>::st(Adp, i, Store<double2>::ld(ph, i) - kappa * acc[c]);
-      }
+    for (int c = 0; c < 12; ++c) {
+      const size_t i = size_t(c) * g.V + s;
+      const cx<double> phv = Store<double2>::ld(ph, i);
+      const cx<double> o = Store<double2>::ld(p, i) - kappa * ad[c];
+      Store<double2>::st(Ap, i, o);
+      Store<double2>::st(Adp, i, phv - kappa * aa[c]);
+      const cx<double> d = cmulc(phv, o);
+      v[0] += d.x;
+      v[1] += d.y;
     }
   }
   block_partial<2, kBlock>(v, part, blockIdx.x);
@@ -454,79 +527,6 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// out[k] = sum_c in[c] C[c + k*nin] for the k of this block's tile (NT
-// outputs), one element per thread; with g, partials of the dots.
-template <int NT>
-__global__ void __launch_bounds__(kBlock)
-    k_rotate(double2 *__restrict__ out_base, SlotList out_slots, const double2 *__restrict__ in_base,
-             SlotList in_slots, const double2 *__restrict__ C, size_t N, const double2 *__restrict__ g,
-             int conj_out, int jtag, const KrylovState *S, double *__restrict__ part) {
-  if (S && skip_iter(S, jtag)) return;
-  extern __shared__ double2 sC[];  // nin x NT tile of C
-  const int nin = in_slots.n;
-  const int k0 = blockIdx.y * NT;
-  const int nk = min(NT, out_slots.n - k0);
-  for (int e = threadIdx.x; e < nin * NT; e += kBlock) {
-    const int c = e % nin, k = e / nin;
-    sC[e] = (k < nk) ? C[c + size_t(k0 + k) * nin] : make_double2(0, 0);
-  }
-  __syncthreads();
-  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  cx<double> acc[NT];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) acc[k] = {0, 0};
-  if (i < N) {
-    int c = 0;
-    for (; c + 4 <= nin; c += 4) {
-      cx<double> v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = Store<double2>::ld(in_base + size_t(in_slots.idx[c + u]) * N, i);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-          const double2 cc = sC[(c + u) + k * nin];
-          cfma(acc[k], v[u], cx<double>{cc.x, cc.y});
-        }
-    }
-    for (; c < nin; ++c) {
-      const cx<double> v = Store<double2>::ld(in_base + size_t(in_slots.idx[c]) * N, i);
-#pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        const double2 cc = sC[c + k * nin];
-        cfma(acc[k], v, cx<double>{cc.x, cc.y});
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NT; ++k)
-      if (k < nk) Store<double2>::st(out_base + size_t(out_slots.idx[k0 + k]) * N, i, acc[k]);
-  }
-  if (!g) return;
-  // the dot contributions replace the outputs in the same registers
-  const cx<double> gv = (i < N) ? Store<double2>::ld(g, i) : cx<double>{0, 0};
-  double dv[2 * NT];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) {
-    const cx<double> d = conj_out ? cmulc(acc[k], gv) : cmulc(gv, acc[k]);
-    dv[2 * k] = d.x;
-    dv[2 * k + 1] = d.y;
-  }
-  block_partial<2 * NT, kBlock>(dv, part + size_t(blockIdx.y) * gridDim.x * 2 * NT, blockIdx.x);
-}
-
-// dots[k0 + k] from the partials of tile blockIdx.x
-template <int NT>
-__global__ void __launch_bounds__(kBlock)
-    k_rotate_finish(const double *__restrict__ part, int nblk, int nout, double2 *dots, int jtag,
-                    const KrylovState *S) {
-  if (S && skip_iter(S, jtag)) return;
-  double v[2 * NT];
-  sum_partials<2 * NT, kBlock>(part + size_t(blockIdx.x) * nblk * 2 * NT, nblk, v);
-  const int k0 = blockIdx.x * NT;
-  if (threadIdx.x == 0)
-    for (int k = 0; k < NT && k0 + k < nout; ++k) dots[k0 + k] = make_double2(v[2 * k], v[2 * k + 1]);
-}
-
 // partials of out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i] over a tile XT x YT.
 template <int XT, int YT>
 __global__ void __launch_bounds__(kBlock)
@@ -572,37 +572,20 @@ __global__ void __launch_bounds__(kBlock)
           out[(a0 + a) + size_t(b0 + b) * nx] = make_double2(v[2 * (a * YT + b)], v[2 * (a * YT + b) + 1]);
 }
 
-// Y_b += sgn * sum_a X_a C[a + b*nx] for b in this block's tile of YT.
-template <int YT>
+// y += sgn * sum_a X_a c[a] (one column; wider blocks use the matrix cores)
 __global__ void __launch_bounds__(kBlock)
-    k_ts_update(double2 *__restrict__ Y, size_t ldy, int ny, const double2 *__restrict__ X, size_t ldx, int nx,
-                const double2 *__restrict__ C, double sgn, size_t N) {
-  extern __shared__ double2 sC[];  // nx x YT
-  const int b0 = blockIdx.y * YT;
-  for (int e = threadIdx.x; e < nx * YT; e += kBlock) {
-    const int a = e % nx, b = e / nx;
-    const double2 c = (b0 + b < ny) ? C[a + size_t(b0 + b) * nx] : make_double2(0, 0);
-    sC[e] = make_double2(sgn * c.x, sgn * c.y);
-  }
+    k_ts_update1(double2 *__restrict__ y, int nx, const double2 *__restrict__ X, size_t ldx,
+                 const double2 *__restrict__ c, double sgn, size_t N) {
+  __shared__ double2 sC[kMaxCols];
+  for (int a = threadIdx.x; a < nx; a += kBlock) sC[a] = make_double2(sgn * c[a].x, sgn * c[a].y);
   __syncthreads();
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
-    cx<double> acc[YT];
-#pragma unroll
-    for (int b = 0; b < YT; ++b) acc[b] = {0, 0};
+    cx<double> acc{0, 0};
     for (int a = 0; a < nx; ++a) {
-      const cx<double> xv = Store<double2>::ld(X + size_t(a) * ldx, i);
-#pragma unroll
-      for (int b = 0; b < YT; ++b) {
-        const double2 c = sC[a + b * nx];
-        cfma(acc[b], xv, cx<double>{c.x, c.y});
-      }
+      const double2 cc = sC[a];
+      cfma(acc, Store<double2>::ld(X + size_t(a) * ldx, i), cx<double>{cc.x, cc.y});
     }
-#pragma unroll
-    for (int b = 0; b < YT; ++b)
-      if (b0 + b < ny) {
-        double2 *yb = Y + size_t(b0 + b) * ldy;
-        Store<double2>::st(yb, i, Store<double2>::ld(yb, i) + acc[b]);
-      }
+    Store<double2>::st(y, i, Store<double2>::ld(y, i) + acc);
   }
 }
 
@@ -875,14 +858,14 @@ void launch_bicg_init(double2 *rhat, double2 *p, double2 *ph, const double2 *r, 
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
                         const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory, const RedScratch &rs,
                         hipStream_t st) {
-  EB_LAUNCH(k_bicg_matvec, dim3(2 * stencil_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
+  EB_LAUNCH(k_bicg_matvec, dim3(stencil_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
             region(rs, RG_SIGMA));
 }
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
                           const RedScratch &rs, hipStream_t st) {
-  // the matvec wrote 2 * stencil_grid(V) sigma records; N = 12 V
-  const int nb_sigma = 2 * stencil_grid(int(N / 12));
+  // the matvec wrote stencil_grid(V) sigma records; N = 12 V
+  const int nb_sigma = stencil_grid(int(N / 12));
   EB_LAUNCH(k_bicg_update_r, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N, j, S, h,
             region(rs, RG_SIGMA), nb_sigma, region(rs, RG_RR));
 }
@@ -899,33 +882,13 @@ void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const do
 void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *in_base, const SlotList &in_slots,
                    const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
                    const KrylovState *S, const RedScratch &rs, hipStream_t st) {
-  const int nout = out_slots.n;
-  const int nb = nblocks_for(N);
-  double *part = region(rs, RG_GEN);
-  auto go = [&](auto nt_tag) {
-    constexpr int NT = decltype(nt_tag)::value;
-    const int tiles = (nout + NT - 1) / NT;
-    dim3 grid(nb, tiles);
-    size_t sh = size_t(in_slots.n) * NT * sizeof(double2);
-    EB_LAUNCH(k_rotate<NT>, grid, dim3(kBlock), sh, st, out_base, out_slots, in_base, in_slots, C, N, g, conj_out,
-              jtag, S, part);
-    if (g) EB_LAUNCH(k_rotate_finish<NT>, dim3(tiles), dim3(kBlock), 0, st, part, nb, nout, dots, jtag, S);
-  };
-  if (nout <= 4)
-    go(std::integral_constant<int, 4>{});
-  else if (nout <= 8)
-    go(std::integral_constant<int, 8>{});
-  else if (nout <= 12)
-    go(std::integral_constant<int, 12>{});
-  else if (nout <= 16)
-    go(std::integral_constant<int, 16>{});
-  else
-    go(std::integral_constant<int, 20>{});
+  launch_combine_mfma(out_base, out_slots, N, in_base, in_slots, N, C, 1.0, false, N, g, conj_out, dots, jtag, S,
+                      region(rs, RG_GEN), kMaxPartials - size_t(RG_GEN) * kRegion, st);
 }
 
-void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny, size_t N,
-                   const RedScratch &rs, hipStream_t st) {
-  constexpr int XT = 8, YT = 2;
+template <int XT, int YT>
+static void ts_dot_tiled(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny,
+                         size_t N, const RedScratch &rs, hipStream_t st) {
   const int tx = (nx + XT - 1) / XT, ty = (ny + YT - 1) / YT;
   const int tiles = tx * ty;
   // every tile keeps nb partial records of 2 XT YT doubles
@@ -939,12 +902,31 @@ void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const dou
   EB_LAUNCH((k_ts_dot<XT, YT>), dim3(nb, tx, ty), dim3(kBlock), 0, st, X, ldx, nx, Y, ldy, ny, N, part);
   EB_LAUNCH((k_ts_dot_finish<XT, YT>), dim3(tiles), dim3(kBlock), 0, st, out, part, nb, nx, ny, tx);
 }
+// One or two Y columns: VALU tiles of 8 X columns (the products are HBM-bound
+// and a matrix-core tile would be mostly padding); wider blocks: matrix cores.
+void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny, size_t N,
+                   const RedScratch &rs, hipStream_t st) {
+  if (ny == 1)
+    ts_dot_tiled<8, 1>(out, X, ldx, nx, Y, ldy, ny, N, rs, st);
+  else if (ny == 2 || nx > kMaxCols)
+    ts_dot_tiled<8, 2>(out, X, ldx, nx, Y, ldy, ny, N, rs, st);
+  else
+    launch_gram_mfma(out, X, ldx, nx, Y, ldy, ny, N, region(rs, RG_GEN), kMaxPartials - size_t(RG_GEN) * kRegion,
+                     st);
+}
 void launch_ts_update(double2 *Y, size_t ldy, int ny, const double2 *X, size_t ldx, int nx, const double2 *C,
                       double sgn, size_t N, hipStream_t st) {
-  constexpr int YT = 4;
-  dim3 grid(stream_grid(N), (ny + YT - 1) / YT);
-  EB_LAUNCH(k_ts_update<YT>, grid, dim3(kBlock), size_t(nx) * YT * sizeof(double2), st, Y, ldy, ny, X, ldx, nx, C,
-            sgn, N);
+  if (nx < 1 || ny < 1) return;
+  if (ny == 1) {
+    EB_LAUNCH(k_ts_update1, dim3(stream_grid(N)), dim3(kBlock), 0, st, Y, nx, X, ldx, C, sgn, N);
+    return;
+  }
+  SlotList in{}, out{};
+  in.n = nx;
+  for (int a = 0; a < nx; ++a) in.idx[a] = a;
+  out.n = ny;
+  for (int b = 0; b < ny; ++b) out.idx[b] = b;
+  launch_combine_mfma(Y, out, ldy, X, in, ldx, C, sgn, true, N, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, st);
 }
 
 void launch_copy_f64(double2 *d, const double2 *s, size_t n, hipStream_t st) {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libebicg.so")
 EB_OK = 0
 # kernel classes of eb_timing_read (include/ebicg.h)
 KERNEL_CLASSES = ["bicg_matvec", "bicg_update_r", "bicg_update_p", "stab_v", "stab_s", "stab_t", "stab_xr", "stab_p",
-                  "rotate", "residual", "proj"]
+                  "rotate", "residual", "proj", "dslash"]
 STATUS = {
     0: "EB_OK",
     -1: "EB_ERR_INVALID",
