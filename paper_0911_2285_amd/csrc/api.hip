@@ -127,7 +127,7 @@ struct eb_op {
   double kappa = 0;
   int bc_t = -1;
   int device = 0;
-  DevBuf U64, U32;
+  DevBuf U64, U32, U16;  // links: FP64, and FP32 / BF16 copies made on first use
   // deflation space: Ul, Ur hold Kcap FP64 SoA spinors each; H = Ul^+ A Ur on the host
   int Kcap = 0, K = 0;
   DevBuf Ul, Ur;
@@ -136,6 +136,8 @@ struct eb_op {
   DevBuf partials, state, res, hist;
   int hist_cap = 0;
   PinnedBuf hstate, hres, hhist;
+  PinnedBuf hpoll;                          // stop-flag polling (Poller)
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::map<std::string, DevBuf> bufs;
   // kernel timing (eb_timing_enable)
   bool timing = false;
@@ -187,6 +189,9 @@ struct eb_op {
       hist.release();
       hist.ensure(bytes);
       hhist.release();
+    hpoll.release();
+    for (auto &e : poll_ev)
+      if (e) (void)hipEventDestroy(e);
       hhist.ensure(bytes);
     }
     return view(hist.p);
@@ -204,6 +209,7 @@ struct eb_op {
   void free_all() {
     U64.release();
     U32.release();
+    U16.release();
     Ul.release();
     Ur.release();
     partials.release();
@@ -253,37 +259,38 @@ void fetch_state(eb_op *op, hipStream_t s, KrylovState &out) {
 struct Poller {
   const KrylovState *dev = nullptr;
   hipStream_t s = nullptr;
-  PinnedBuf host;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  KrylovState *host = nullptr;  // two pinned slots owned by the op
+  hipEvent_t *ev = nullptr;     // two events owned by the op
   int issued = 0;
-  Poller(const KrylovState *d, hipStream_t st) : dev(d), s(st) {
-    host.ensure(2 * sizeof(KrylovState));
-    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  }
+  Poller(eb_op *op, const KrylovState *d, hipStream_t st);
   ~Poller() {
     if (issued > 0) (void)hipEventSynchronize(ev[(issued - 1) & 1]);
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    host.release();
   }
   bool step(KrylovState &out) {
     if (issued > 0) {
       const int k = (issued - 1) & 1;
       HIPCHK(hipEventSynchronize(ev[k]));
-      const KrylovState &h = host.as<KrylovState>()[k];
-      if (h.stopped) {
-        out = h;
+      if (host[k].stopped) {
+        out = host[k];
         return true;
       }
     }
     const int k = issued & 1;
-    HIPCHK(hipMemcpyAsync(host.as<KrylovState>() + k, dev, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(host + k, dev, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(ev[k], s));
     ++issued;
     return false;
   }
 };
+Poller::Poller(eb_op *op, const KrylovState *d, hipStream_t st) : dev(d), s(st) {
+  if (!op->poll_ev[0]) {
+    op->hpoll.ensure(2 * sizeof(KrylovState));
+    HIPCHK(hipEventCreateWithFlags(&op->poll_ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&op->poll_ev[1], hipEventDisableTiming));
+  }
+  host = op->hpoll.as<KrylovState>();
+  ev = op->poll_ev;
+}
 
 // r = b - D x in FP64; returns (||r||, ||b||).
 std::pair<double, double> residual(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s) {
@@ -353,7 +360,7 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
   int j = 0;
   bool stopped = false;
   {
-    Poller pl(K, s);
+    Poller pl(op, K, s);
     while (j < maxiter) {
       ++j;
       TIMED(EB_K_STAB_V, s, launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s));
@@ -406,21 +413,56 @@ void deflated_stab_f64(eb_op *op, const double2 *b, double2 *x, double tol, doub
   }
 }
 
-// FP32 inner BiCGStab inside FP64 iterative refinement (defect correction).
-void mixed_stab_f32(eb_op *op, const double2 *b, double2 *x, double tol, double inner_tol, int maxiter,
-                    eb_stats &st, hipStream_t s) {
-  const size_t N = op->N;
-  if (!op->U32.p) {
-    op->U32.ensure(size_t(36) * op->g.V * sizeof(float2));
-    launch_convert_f64_f32(op->U32.as<float2>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
+// Low-precision storage of the inner solve: FP32, or BF16 with FP32 arithmetic.
+template <typename S>
+struct Inner;
+template <>
+struct Inner<float2> {
+  static constexpr const char *tag = "f32_";
+  static const float2 *links(eb_op *op, hipStream_t s) {
+    if (!op->U32.p) {
+      op->U32.ensure(size_t(36) * op->g.V * sizeof(float2));
+      launch_convert_f64_f32(op->U32.as<float2>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
+    }
+    return op->U32.as<float2>();
   }
+  static void down(float2 *d, const double2 *x, size_t n, hipStream_t s) { launch_convert_f64_f32(d, x, n, s); }
+  static void up(double2 *d, const float2 *x, size_t n, hipStream_t s) { launch_convert_f32_f64(d, x, n, s); }
+};
+template <>
+struct Inner<bf16c> {
+  static constexpr const char *tag = "bf16_";
+  static const bf16c *links(eb_op *op, hipStream_t s) {
+    if (!op->U16.p) {
+      op->U16.ensure(size_t(36) * op->g.V * sizeof(bf16c));
+      launch_convert_f64_bf16(op->U16.as<bf16c>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
+    }
+    return op->U16.as<bf16c>();
+  }
+  static void down(bf16c *d, const double2 *x, size_t n, hipStream_t s) { launch_convert_f64_bf16(d, x, n, s); }
+  static void up(double2 *d, const bf16c *x, size_t n, hipStream_t s) { launch_convert_bf16_f64(d, x, n, s); }
+};
+
+// Low-precision inner BiCGStab inside FP64 iterative refinement (defect
+// correction): every outer step computes r = b - A x in FP64, solves A e = r
+// in storage S to a relative reduction inner_tol and adds e to x in FP64.
+// Global reductions and scalars stay FP64 in every kernel.  The initial guess
+// is deflated once by the caller (Alg. Incremental eigBiCG, step 3); the
+// refinement steps are not deflated again: the oblique projector
+// I - A U_r H^-1 U_l^+ is not a contraction when the Ritz pairs are poor, and
+// applying it to every small correction residual can undo the inner solve.
+template <typename S>
+void mixed_stab(eb_op *op, const double2 *b, double2 *x, double tol, double inner_tol, int maxiter, eb_stats &st,
+                hipStream_t s) {
+  const size_t N = op->N;
+  const S *U = Inner<S>::links(op, s);
+  const std::string tag = Inner<S>::tag;
   double2 *r = op->vec("mix_r");
   double2 *e64 = op->vec("mix_e64");
-  float2 *r32 = op->raw<float2>("mix_r32", N * sizeof(float2));
-  float2 *e32 = op->raw<float2>("mix_e32", N * sizeof(float2));
+  S *rl = op->raw<S>(tag + "mix_r", N * sizeof(S));
+  S *el = op->raw<S>(tag + "mix_e", N * sizeof(S));
   int outer = 0;
   while (true) {
-    if (op->K > 0) deflate_guess(op, b, x, s);
     auto [rn, bn] = residual(op, r, b, x, s);
     st.matvec_d += 1;
     if (bn == 0.0) {
@@ -431,15 +473,15 @@ void mixed_stab_f32(eb_op *op, const double2 *b, double2 *x, double tol, double 
     if (rn <= tol * bn) return;
     int left = maxiter - st.iters;
     if (left <= 0 || outer > 200) fail(EB_ERR_NOT_CONVERGED, "mixed-precision solve: maxiter reached");
-    launch_convert_f64_f32(r32, r, N, s);
-    HIPCHK(hipMemsetAsync(e32, 0, N * sizeof(float2), s));
+    Inner<S>::down(rl, r, N, s);
+    HIPCHK(hipMemsetAsync(el, 0, N * sizeof(S), s));
     // inner target: reduce this residual by inner_tol, but not below what FP64 needs
     const double inner_abs = std::max(inner_tol * rn, 0.5 * tol * bn);
-    StabResult R = run_bicgstab<float2>(op, op->U32.as<float2>(), e32, r32, inner_abs, 0.0, left, "f32_", s);
+    StabResult R = run_bicgstab<S>(op, U, el, rl, inner_abs, 0.0, left, tag, s);
     st.iters += R.iters;
     st.matvec_d += 2 * R.iters;
     if (R.reason == 2 && R.iters == 0) fail(EB_ERR_BREAKDOWN, "inner BiCGStab breakdown");
-    launch_convert_f32_f64(e64, e32, N, s);
+    Inner<S>::up(e64, el, N, s);
     launch_add_f64(x, e64, N, s);
     ++outer;
     st.outer_steps = outer;
@@ -794,7 +836,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   int stop_at = 0, reason = 0;
   double rnorm = 0;
   {
-    Poller pl(S, s);
+    Poller pl(op, S, s);
     while (true) {
       ++j;
       if (j > P.maxiter + 1) break;
@@ -1130,17 +1172,21 @@ static eb_status apply_impl(eb_op *op, void *out, const void *in, eb_prec prec, 
       launch_dslash_f64(b, a, op->U64.as<double2>(), op->g, op->kappa, dagger, s);
       launch_from_soa_f64(static_cast<double2 *>(out), b, op->g, s);
     } else if (prec == EB_FP32) {
-      if (!op->U32.p) {
-        op->U32.ensure(size_t(36) * op->g.V * sizeof(float2));
-        launch_convert_f64_f32(op->U32.as<float2>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
-      }
+      const float2 *U = Inner<float2>::links(op, s);
       float2 *a = op->raw<float2>("apply_a32", N * sizeof(float2));
       float2 *b = op->raw<float2>("apply_b32", N * sizeof(float2));
       launch_to_soa_f32(a, static_cast<const float2 *>(in), op->g, s);
-      launch_dslash_f32(b, a, op->U32.as<float2>(), op->g, op->kappa, dagger, s);
+      launch_dslash_f32(b, a, U, op->g, op->kappa, dagger, s);
       launch_from_soa_f32(static_cast<float2 *>(out), b, op->g, s);
+    } else if (prec == EB_BF16) {
+      const bf16c *U = Inner<bf16c>::links(op, s);
+      bf16c *a = op->raw<bf16c>("apply_a16", N * sizeof(bf16c));
+      bf16c *b = op->raw<bf16c>("apply_b16", N * sizeof(bf16c));
+      launch_to_soa_bf16(a, static_cast<const bf16c *>(in), op->g, s);
+      launch_dslash_bf16(b, a, U, op->g, op->kappa, dagger, s);
+      launch_from_soa_bf16(static_cast<bf16c *>(out), b, op->g, s);
     } else {
-      fail(EB_ERR_INVALID, "precision not supported by op_apply");
+      fail(EB_ERR_INVALID, "unknown precision");
     }
     HIPCHK(hipGetLastError());
   });
@@ -1221,7 +1267,8 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     if (!(P->tol > 0) || P->maxiter < 1 || P->nrhs < 1) fail(EB_ERR_INVALID, "tol > 0, maxiter >= 1, nrhs >= 1");
     if (P->deftol < 0 || P->deftol >= 1) fail(EB_ERR_INVALID, "deftol must be in [0, 1)");
     if (P->method != 0) fail(EB_ERR_INVALID, "only method 0 (BiCGStab) is available");
-    if (P->inner != EB_FP64 && P->inner != EB_FP32) fail(EB_ERR_INVALID, "inner precision not available");
+    if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
+      fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
@@ -1243,11 +1290,13 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
         st.true_rel_resid = worst;
       };
       try {
+        if (op->K > 0) deflate_guess(op, b, x, s);
         if (P->inner == EB_FP64) {
-          if (op->K > 0) deflate_guess(op, b, x, s);
           deflated_stab_f64(op, b, x, P->tol, P->deftol, P->maxiter, sc, s);
+        } else if (P->inner == EB_FP32) {
+          mixed_stab<float2>(op, b, x, P->tol, P->inner_tol > 0 ? P->inner_tol : 1e-6, P->maxiter, sc, s);
         } else {
-          mixed_stab_f32(op, b, x, P->tol, P->inner_tol > 0 ? P->inner_tol : 1e-6, P->maxiter, sc, s);
+          mixed_stab<bf16c>(op, b, x, P->tol, P->inner_tol > 0 ? P->inner_tol : 1e-2, P->maxiter, sc, s);
         }
       } catch (...) {
         // x holds the last iterate and the stats are filled

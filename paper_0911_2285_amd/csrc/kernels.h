@@ -6,9 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
-namespace ebicg {
+#include "device_common.h"  // storage types (double2, float2, bf16c)
 
-struct bf16c;
+namespace ebicg {
 
 // Lattice geometry; V = lx*ly*lz*lt, N = 12 V complex entries per spinor.
 struct Geom {
@@ -73,6 +73,11 @@ void launch_pack_gauge_f64(double2 *dst, const double2 *src, const Geom &g, int 
 // precision conversions of SoA fields (n complex entries)
 void launch_convert_f64_f32(float2 *dst, const double2 *src, size_t n, hipStream_t st);
 void launch_convert_f32_f64(double2 *dst, const float2 *src, size_t n, hipStream_t st);
+// BF16 storage: (re, im) as two bfloat16 (round to nearest even), arithmetic in FP32
+void launch_to_soa_bf16(bf16c *dst, const bf16c *src, const Geom &g, hipStream_t st);
+void launch_from_soa_bf16(bf16c *dst, const bf16c *src, const Geom &g, hipStream_t st);
+void launch_convert_f64_bf16(bf16c *dst, const double2 *src, size_t n, hipStream_t st);
+void launch_convert_bf16_f64(double2 *dst, const bf16c *src, size_t n, hipStream_t st);
 
 // ---- operator ---------------------------------------------------------------
 // out = D in, or D^+ in when dagger; internal SoA layout.
@@ -80,6 +85,8 @@ void launch_dslash_f64(double2 *out, const double2 *in, const double2 *U, const 
                        hipStream_t st);
 void launch_dslash_f32(float2 *out, const float2 *in, const float2 *U, const Geom &g, double kappa, bool dagger,
                        hipStream_t st);
+void launch_dslash_bf16(bf16c *out, const bf16c *in, const bf16c *U, const Geom &g, double kappa, bool dagger,
+                        hipStream_t st);
 // r = b - D x (FP64); res[0] = ||r||^2, res[1] = ||b||^2 (device)
 void launch_residual_f64(double2 *r, const double2 *b, const double2 *x, const double2 *U, const Geom &g, double kappa,
                          double *res, const RedScratch &rs, hipStream_t st);

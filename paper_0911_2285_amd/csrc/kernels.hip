@@ -840,6 +840,21 @@ void launch_dslash_f64(double2 *o, const double2 *i, const double2 *U, const Geo
 void launch_dslash_f32(float2 *o, const float2 *i, const float2 *U, const Geom &g, double k, bool d, hipStream_t st) {
   dslash_any(o, i, U, g, k, d, st);
 }
+void launch_dslash_bf16(bf16c *o, const bf16c *i, const bf16c *U, const Geom &g, double k, bool d, hipStream_t st) {
+  dslash_any(o, i, U, g, k, d, st);
+}
+void launch_to_soa_bf16(bf16c *d, const bf16c *s, const Geom &g, hipStream_t st) {
+  EB_LAUNCH(k_to_soa<bf16c>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);
+}
+void launch_from_soa_bf16(bf16c *d, const bf16c *s, const Geom &g, hipStream_t st) {
+  EB_LAUNCH(k_from_soa<bf16c>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);
+}
+void launch_convert_f64_bf16(bf16c *d, const double2 *s, size_t n, hipStream_t st) {
+  EB_LAUNCH((k_convert<bf16c, double2>), dim3(nblocks_for(n)), dim3(kBlock), 0, st, d, s, n);
+}
+void launch_convert_bf16_f64(double2 *d, const bf16c *s, size_t n, hipStream_t st) {
+  EB_LAUNCH((k_convert<double2, bf16c>), dim3(nblocks_for(n)), dim3(kBlock), 0, st, d, s, n);
+}
 
 void launch_residual_f64(double2 *r, const double2 *b, const double2 *x, const double2 *U, const Geom &g, double kappa,
                          double *res, const RedScratch &rs, hipStream_t st) {
@@ -992,5 +1007,6 @@ void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K
                                  const RedScratch &, hipStream_t);
 EB_STAB_INST(double2)
 EB_STAB_INST(float2)
+EB_STAB_INST(bf16c)
 
 }  // namespace ebicg

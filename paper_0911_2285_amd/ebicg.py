@@ -205,30 +205,26 @@ def op_destroy(op):
         op.handle = ctypes.c_void_p()
 
 
-def _spinor_dtype(prec):
+def _spinor_ptr(op, t, prec, name):
+    """Device pointer of a canonical spinor: complex128 (fp64), complex64 (fp32),
+    or bfloat16 pairs (re, im) with 2 N elements (bf16)."""
     import torch
 
-    return {"fp64": torch.complex128, "fp32": torch.complex64}[prec]
+    if prec == "bf16":
+        return _dev_ptr(t, 2 * op.N, torch.bfloat16, name)
+    return _dev_ptr(t, op.N, {"fp64": torch.complex128, "fp32": torch.complex64}[prec], name)
 
 
 def op_apply(op, out, inp, prec="fp64", stream=None):
     """out = D inp (device tensors in the canonical [V][4][3] layout)."""
-    dt = _spinor_dtype(prec)
-    _check(
-        lib().eb_op_apply(
-            op.handle, _dev_ptr(out, op.N, dt, "out"), _dev_ptr(inp, op.N, dt, "in"), PREC[prec], _stream(stream)
-        )
-    )
+    _check(lib().eb_op_apply(op.handle, _spinor_ptr(op, out, prec, "out"), _spinor_ptr(op, inp, prec, "in"),
+                             PREC[prec], _stream(stream)))
 
 
 def op_apply_dagger(op, out, inp, prec="fp64", stream=None):
     """out = D^+ inp."""
-    dt = _spinor_dtype(prec)
-    _check(
-        lib().eb_op_apply_dagger(
-            op.handle, _dev_ptr(out, op.N, dt, "out"), _dev_ptr(inp, op.N, dt, "in"), PREC[prec], _stream(stream)
-        )
-    )
+    _check(lib().eb_op_apply_dagger(op.handle, _spinor_ptr(op, out, prec, "out"), _spinor_ptr(op, inp, prec, "in"),
+                                    PREC[prec], _stream(stream)))
 
 
 def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):

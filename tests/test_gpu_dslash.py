@@ -74,6 +74,29 @@ def test_dslash_fp32_error(gpu_lib):
     assert err < 5e-7
 
 
+def test_dslash_bf16_error(gpu_lib):
+    """BF16-stored links and spinors, FP32 arithmetic: error against the FP64
+    oracle applied to the same (rounded) input.  Links and the output are
+    rounded to 8 significant bits (relative 2^-9), so the bound is a few 2^-9
+    of the largest entry."""
+    import torch
+
+    dims, kappa = (8, 4, 4, 8), 0.122
+    U, op, dev = _setup(gpu_lib, dims, kappa)
+    V = synth.volume(dims)
+    psi = synth.gaussian_spinor(V, 5)
+    x = torch.view_as_real(torch.from_numpy(psi)).to(torch.bfloat16).contiguous().to(dev)
+    psi_r = torch.view_as_complex(x.cpu().to(torch.float64)).numpy()
+    for dag in (False, True):
+        y = torch.empty_like(x)
+        (gpu_lib.op_apply_dagger if dag else gpu_lib.op_apply)(op, y, x, prec="bf16")
+        got = torch.view_as_complex(y.cpu().to(torch.float64)).numpy()
+        ref = (W.apply_Ddag if dag else W.apply_D)(U, psi_r, kappa, dims)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"bf16 dslash dagger={dag}: max rel err vs FP64 oracle {err:.2e}")
+        assert 1e-5 < err < 4 * 2.0**-9
+
+
 def test_dslash_full_size_sampled(gpu_lib):
     """16^3 x 32 (the incremental-eigBiCG workload): sampled sites against the per-site oracle."""
     import torch

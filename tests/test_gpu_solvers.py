@@ -114,6 +114,33 @@ def test_mixed_precision_solve(gpu_lib, cfg0):
     assert tr <= 1e-10 and st["outer_steps"] >= 1
 
 
+@pytest.mark.parametrize("inner,inner_tol", [("fp32", 1e-5), ("bf16", 1e-2)])
+def test_mixed_precision_error_vs_fp64_solution(gpu_lib, cfg0, inner, inner_tol):
+    """FP32 / BF16 inner solves inside FP64 refinement: every solve reaches the
+    FP64 true residual 1e-10, and the solution's error against the dense FP64
+    solve is stated and bounded by cond(D) times the residual."""
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    A, _ = _ops(U, kappa, dims)
+    D = W.dense_D(U, kappa, dims)
+    op = gpu_lib.op_create(U, kappa, dims)
+    for i in range(2):
+        bnp = synth.z2_source(V, synth.rhs_seed(0, 20 + i))
+        xs = np.linalg.solve(D, bnp.ravel())
+        b = torch.from_numpy(bnp).to("cuda:0")
+        x = torch.zeros_like(b)
+        st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, inner=inner, inner_tol=inner_tol)
+        xg = x.cpu().numpy().ravel()
+        tr = np.linalg.norm(bnp.ravel() - A(xg)) / np.linalg.norm(bnp)
+        err = np.linalg.norm(xg - xs) / np.linalg.norm(xs)
+        print(f"{inner}: iters {st['iters']} outer {st['outer_steps']} true resid {tr:.2e} error vs FP64 solve {err:.2e}")
+        assert tr <= 1e-10 and st["true_rel_resid"] <= 1e-10
+        assert st["outer_steps"] >= (3 if inner == "bf16" else 1)
+        assert err <= 1e-8
+
+
 def test_error_paths(gpu_lib, cfg0):
     import torch
 
