@@ -73,7 +73,10 @@ typedef struct {
   int32_t method;   /* 0: BiCGStab (the paper's choice), 1: BiCG */
   eb_prec inner;    /* working precision of the inner iteration; FP32/BF16 run inside FP64 refinement */
   double inner_tol; /* relative residual reduction per refinement step (ignored for EB_FP64) */
-  int32_t nrhs;     /* right-hand sides solved together (b, x hold nrhs spinors back to back) */
+  int32_t nrhs;     /* right-hand sides (b, x hold nrhs spinors back to back) */
+  int32_t batch;    /* columns per batched iteration: 1 = one at a time; 2, 4, 8, 16; 0 = the
+                       library's choice (timed once per operator and precision). Batching needs
+                       deftol = 0; with deftol > 0 the columns run one at a time. */
 } eb_solve_params;
 
 /* Per-call statistics. */
@@ -105,6 +108,13 @@ eb_status eb_op_destroy(eb_op *op);
 eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
 eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
 
+/* out_i = D in_i (dagger = 0) or D^+ in_i (dagger = 1) for k right-hand sides
+ * at once, k in {1, 2, 4, 8, 16}: one pass over the links serves all k
+ * (multi-RHS stencil).  in/out: device, k canonical spinors back to back,
+ * element type by prec; they must not overlap.  Asynchronous on `stream`. */
+eb_status eb_op_apply_block(eb_op *op, void *out, const void *in, int32_t k, int32_t dagger, eb_prec prec,
+                            void *stream);
+
 /* One solve of the first phase of Alg. Incremental eigBiCG (step 2): deflate
  * x0 with the current space (if K > 0), run eigBiCG in FP64, continue with
  * BiCGStab if the FP64 true residual is above tol, then biorthogonalise the nev
@@ -116,9 +126,12 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b, void *x, const eb_eig_param
                            eb_stats *st, void *stream);
 
 /* A solve of the second phase (step 3): x0 += U_r H^{-1} U_l^+ (b - A x0),
- * then BiCGStab (or BiCG) with the DefTol restart; FP32/BF16 inner precision
- * runs inside FP64 iterative refinement.  b, x: device, FP64 canonical,
- * p->nrhs spinors back to back.  Does not change the deflation space. */
+ * then BiCGStab with the DefTol restart; FP32/BF16 inner precision runs
+ * inside FP64 iterative refinement.  b, x: device, FP64 canonical, p->nrhs
+ * spinors back to back.  With p->batch != 1 the right-hand sides run in
+ * batches of k columns that share every link load (multi-RHS stencil); each
+ * column keeps its own BiCGStab scalars and stops on its own.  Does not
+ * change the deflation space. */
 eb_status eb_deflated_bicg_solve(eb_op *op, const void *b, void *x, const eb_solve_params *p,
                                  eb_stats *st, void *stream);
 
@@ -160,6 +173,12 @@ enum {
   EB_K_RESIDUAL,        /* b - D x in FP64 */
   EB_K_PROJ,            /* deflation projections (tall-skinny products) */
   EB_K_DSLASH,          /* plain D or D^+ applications (extending H) */
+  EB_K_BSTAB_V,         /* batched BiCGStab: v = D p for k columns with (rhat, v) */
+  EB_K_BSTAB_S,         /* batched: alpha (one block) and s = r - alpha v */
+  EB_K_BSTAB_T,         /* batched: t = D s with (t, s), (t, t) */
+  EB_K_BSTAB_XR,        /* batched: omega (one block), x and r updates with (rhat, r), ||r|| */
+  EB_K_BSTAB_P,         /* batched: beta and stop tests (one block), p update */
+  EB_K_BDSLASH,         /* eb_op_apply_block stencil */
   EB_K_COUNT
 };
 eb_status eb_timing_enable(eb_op *op, int32_t enable);

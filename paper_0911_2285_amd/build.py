@@ -31,6 +31,7 @@ SOURCES = [
     ("kernels.hip", "hip"),
     ("api.hip", "hip"),
     ("tsmm.hip", "hip"),
+    ("batch.hip", "hip"),
     ("hostla.cpp", "host"),
 ]
 

@@ -137,6 +137,10 @@ struct eb_op {
   int hist_cap = 0;
   PinnedBuf hstate, hres, hhist;
   PinnedBuf hpoll;                          // stop-flag polling (Poller)
+  // multi-RHS: chosen columns per batch per precision (0: not tuned yet) and
+  // the measured stencil time per right-hand side of each candidate
+  int batch_choice[3] = {0, 0, 0};
+  double batch_ms[3][kMaxBatch + 1] = {};
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::map<std::string, DevBuf> bufs;
   // kernel timing (eb_timing_enable)
@@ -189,9 +193,6 @@ struct eb_op {
       hist.release();
       hist.ensure(bytes);
       hhist.release();
-    hpoll.release();
-    for (auto &e : poll_ev)
-      if (e) (void)hipEventDestroy(e);
       hhist.ensure(bytes);
     }
     return view(hist.p);
@@ -219,6 +220,11 @@ struct eb_op {
     hstate.release();
     hres.release();
     hhist.release();
+    hpoll.release();
+    for (auto &e : poll_ev) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
     for (auto &kv : bufs) kv.second.release();
     bufs.clear();
     pending.clear();
@@ -259,32 +265,37 @@ void fetch_state(eb_op *op, hipStream_t s, KrylovState &out) {
 struct Poller {
   const KrylovState *dev = nullptr;
   hipStream_t s = nullptr;
-  KrylovState *host = nullptr;  // two pinned slots owned by the op
+  int n = 1;                    // states watched (the columns of a batch)
+  KrylovState *host = nullptr;  // two pinned slots of kMaxBatch states, owned by the op
   hipEvent_t *ev = nullptr;     // two events owned by the op
   int issued = 0;
-  Poller(eb_op *op, const KrylovState *d, hipStream_t st);
+  Poller(eb_op *op, const KrylovState *d, hipStream_t st, int nstates = 1);
   ~Poller() {
     if (issued > 0) (void)hipEventSynchronize(ev[(issued - 1) & 1]);
   }
-  bool step(KrylovState &out) {
+  // true once every watched state has stopped; then out[0..n) holds them
+  bool step(KrylovState *out) {
     if (issued > 0) {
       const int k = (issued - 1) & 1;
       HIPCHK(hipEventSynchronize(ev[k]));
-      if (host[k].stopped) {
-        out = host[k];
+      const KrylovState *h = host + size_t(k) * kMaxBatch;
+      bool all = true;
+      for (int c = 0; c < n; ++c) all = all && h[c].stopped;
+      if (all) {
+        for (int c = 0; c < n; ++c) out[c] = h[c];
         return true;
       }
     }
     const int k = issued & 1;
-    HIPCHK(hipMemcpyAsync(host + k, dev, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(host + size_t(k) * kMaxBatch, dev, n * sizeof(KrylovState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(ev[k], s));
     ++issued;
     return false;
   }
 };
-Poller::Poller(eb_op *op, const KrylovState *d, hipStream_t st) : dev(d), s(st) {
+Poller::Poller(eb_op *op, const KrylovState *d, hipStream_t st, int nstates) : dev(d), s(st), n(nstates) {
   if (!op->poll_ev[0]) {
-    op->hpoll.ensure(2 * sizeof(KrylovState));
+    op->hpoll.ensure(2 * kMaxBatch * sizeof(KrylovState));
     HIPCHK(hipEventCreateWithFlags(&op->poll_ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&op->poll_ev[1], hipEventDisableTiming));
   }
@@ -368,7 +379,7 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
       TIMED(EB_K_STAB_T, s, launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s));
       TIMED(EB_K_STAB_XR, s, launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, h, op->rs(), s));
       TIMED(EB_K_STAB_P, s, launch_stab_p<S>(p, r, v, N, j, K, h, op->rs(), s));
-      if (j % poll == 0 && pl.step(hs)) {
+      if (j % poll == 0 && pl.step(&hs)) {
         stopped = true;
         break;
       }
@@ -413,12 +424,22 @@ void deflated_stab_f64(eb_op *op, const double2 *b, double2 *x, double tol, doub
   }
 }
 
-// Low-precision storage of the inner solve: FP32, or BF16 with FP32 arithmetic.
+// Storage of the inner solve: FP64 (no refinement needed, one outer step),
+// FP32, or BF16 with FP32 arithmetic.
 template <typename S>
 struct Inner;
 template <>
+struct Inner<double2> {
+  static constexpr const char *tag = "f64_";
+  static constexpr int index = 0;
+  static const double2 *links(eb_op *op, hipStream_t) { return op->U64.as<double2>(); }
+  static void down(double2 *d, const double2 *x, size_t n, hipStream_t s) { launch_copy_f64(d, x, n, s); }
+  static void up(double2 *d, const double2 *x, size_t n, hipStream_t s) { launch_copy_f64(d, x, n, s); }
+};
+template <>
 struct Inner<float2> {
   static constexpr const char *tag = "f32_";
+  static constexpr int index = 1;
   static const float2 *links(eb_op *op, hipStream_t s) {
     if (!op->U32.p) {
       op->U32.ensure(size_t(36) * op->g.V * sizeof(float2));
@@ -432,6 +453,7 @@ struct Inner<float2> {
 template <>
 struct Inner<bf16c> {
   static constexpr const char *tag = "bf16_";
+  static constexpr int index = 2;
   static const bf16c *links(eb_op *op, hipStream_t s) {
     if (!op->U16.p) {
       op->U16.ensure(size_t(36) * op->g.V * sizeof(bf16c));
@@ -465,7 +487,8 @@ void mixed_stab(eb_op *op, const double2 *b, double2 *x, double tol, double inne
   while (true) {
     auto [rn, bn] = residual(op, r, b, x, s);
     st.matvec_d += 1;
-    if (bn == 0.0) {
+    if (bn == 0.0) {  // b = 0: the solution is x = 0
+      HIPCHK(hipMemsetAsync(x, 0, N * sizeof(double2), s));
       st.true_rel_resid = 0;
       return;
     }
@@ -483,6 +506,189 @@ void mixed_stab(eb_op *op, const double2 *b, double2 *x, double tol, double inne
     if (R.reason == 2 && R.iters == 0) fail(EB_ERR_BREAKDOWN, "inner BiCGStab breakdown");
     Inner<S>::up(e64, el, N, s);
     launch_add_f64(x, e64, N, s);
+    ++outer;
+    st.outer_steps = outer;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-RHS: kc right-hand sides solved together (batch layout of batch.hip)
+// ---------------------------------------------------------------------------
+// Deflate the initial guesses of kc FP64 columns at once (Alg. Incremental
+// eigBiCG, step 3, first item): C = U_l^+ R on the matrix cores, H D = C on
+// the host, X += U_r D on the matrix cores.
+void deflate_block(eb_op *op, const double2 *b, double2 *x, int kc, hipStream_t s) {
+  if (op->K == 0) return;
+  const size_t N = op->N;
+  const int K = op->K;
+  double2 *r = op->vec("dfb_r", kc);
+  for (int c = 0; c < kc; ++c)
+    TIMED(EB_K_RESIDUAL, s,
+          launch_residual_f64(r + c * N, b + c * N, x + c * N, op->U64.as<double2>(), op->g, op->kappa,
+                              op->res.as<double>() + 2 * c, op->rs(), s));
+  double2 *C = op->raw<double2>("dfb_c", size_t(K) * kc * sizeof(double2));
+  TIMED(EB_K_PROJ, s, launch_ts_dot(C, op->Ul.as<double2>(), N, K, r, N, kc, N, op->rs(), s));
+  std::vector<double2> hc(size_t(K) * kc);
+  HIPCHK(hipMemcpyAsync(hc.data(), C, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int c = 0; c < kc; ++c) {
+    std::vector<cd> d(K);
+    for (int i = 0; i < K; ++i) d[i] = c2(hc[i + size_t(c) * K]);
+    if (!lu_solve(op->H, d)) fail(EB_ERR_EIG, "deflation matrix H is singular");
+    for (int i = 0; i < K; ++i) hc[i + size_t(c) * K] = d2(d[i]);
+  }
+  HIPCHK(hipMemcpyAsync(C, hc.data(), hc.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  TIMED(EB_K_PROJ, s, launch_ts_update(x, N, kc, op->Ur.as<double2>(), N, K, C, 1.0, N, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// Columns per batch for the multi-RHS path: timed once per operator and
+// precision.  Each candidate k runs the batched stencil on k columns (three
+// timed repetitions after one warm-up); the k with the lowest time per
+// right-hand side wins.  Ties go to the smaller k (less memory, earlier exit
+// of converged columns).
+template <typename S>
+int tune_batch(eb_op *op, hipStream_t s) {
+  const S *U = Inner<S>::links(op, s);
+  const size_t n = op->N * size_t(kMaxBatch);
+  S *a = op->raw<S>(std::string(Inner<S>::tag) + "b_p", n * sizeof(S));
+  S *b = op->raw<S>(std::string(Inner<S>::tag) + "b_v", n * sizeof(S));
+  HIPCHK(hipMemsetAsync(a, 0, n * sizeof(S), s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = 1;
+  double best_t = HUGE_VAL;
+  for (int kc = 1; kc <= kMaxBatch; kc *= 2) {
+    launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s);
+    HIPCHK(hipEventRecord(e0, s));
+    for (int rep = 0; rep < 3; ++rep) launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    const double per_rhs = ms / (3.0 * kc);
+    op->batch_ms[Inner<S>::index][kc] = per_rhs;
+    if (per_rhs < 0.97 * best_t) {
+      best_t = per_rhs;
+      best = kc;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+int choose_batch(eb_op *op, eb_prec prec, hipStream_t s) {
+  const int i = prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2);
+  if (op->batch_choice[i] == 0)
+    op->batch_choice[i] = i == 0 ? tune_batch<double2>(op, s) : (i == 1 ? tune_batch<float2>(op, s) : tune_batch<bf16c>(op, s));
+  return op->batch_choice[i];
+}
+
+// Batched BiCGStab in storage S on kc interleaved columns: x, r are batches,
+// tol_dev the per-column absolute targets (device).  Returns when every
+// column has stopped; iters[c] = iterations of column c, reason[c] its stop.
+template <typename S>
+void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double *tol_dev, int maxiter,
+                        const std::string &tag, hipStream_t s, int *iters, int *reason) {
+  const size_t n = op->N * size_t(kc);
+  S *rhat = op->raw<S>(tag + "b_rhat", n * sizeof(S));
+  S *p = op->raw<S>(tag + "b_p", n * sizeof(S));
+  S *v = op->raw<S>(tag + "b_v", n * sizeof(S));
+  S *sv = op->raw<S>(tag + "b_s", n * sizeof(S));
+  S *t = op->raw<S>(tag + "b_t", n * sizeof(S));
+  KrylovState *K = op->S();
+  KrylovHistory h = op->history((maxiter + 4) * kc);
+  launch_bstab_init<S>(rhat, p, r, op->N, kc, tol_dev, maxiter, K, h, op->rs(), s);
+  KrylovState hs[kMaxBatch];
+  const int poll = 8;
+  int j = 0;
+  bool stopped = false;
+  {
+    Poller pl(op, K, s, kc);
+    pl.step(hs);  // a batch whose columns all stop at once needs no iteration
+    while (j < maxiter) {
+      if (j % poll == 0 && j > 0 && pl.step(hs)) {
+        stopped = true;
+        break;
+      }
+      ++j;
+      TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, op->g, j, kc, K, h, op->rs(), s));
+      TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, op->g, j, kc, K, h, op->rs(), s));
+      TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, op->g, j, kc, K, h, op->rs(), s));
+    }
+  }
+  if (!stopped) {
+    HIPCHK(hipMemcpyAsync(op->hstate.p, K, kc * sizeof(KrylovState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < kc; ++c) hs[c] = op->hstate.as<KrylovState>()[c];
+  }
+  for (int c = 0; c < kc; ++c) {
+    iters[c] = hs[c].stopped ? hs[c].stop_at : j;
+    reason[c] = hs[c].stopped ? hs[c].reason : 4;
+  }
+}
+
+// kc right-hand sides (FP64 SoA columns b, x; x holds the deflated start):
+// FP64 iterative refinement around one batched low-precision BiCGStab per
+// outer step.  Columns that have converged keep a target of +inf (they stop
+// at initialisation and their correction stays zero).
+template <typename S>
+void mixed_stab_batch(eb_op *op, const double2 *b, double2 *x, int kc, double tol, double inner_tol, int maxiter,
+                      eb_stats &st, hipStream_t s) {
+  const size_t N = op->N;
+  const S *U = Inner<S>::links(op, s);
+  const std::string tag = Inner<S>::tag;
+  double2 *r = op->vec("mb_r", kc);
+  S *rl = op->raw<S>(tag + "mb_r", N * kc * sizeof(S));
+  S *el = op->raw<S>(tag + "mb_e", N * kc * sizeof(S));
+  double *tol_dev = op->raw<double>("mb_tol", kMaxBatch * sizeof(double));
+  double *tol_host = op->hres.as<double>();  // pinned; reused after the residual norms are read
+  int outer = 0;
+  std::vector<double> rn(kc), bn(kc);
+  while (true) {
+    for (int c = 0; c < kc; ++c)
+      TIMED(EB_K_RESIDUAL, s,
+            launch_residual_f64(r + c * N, b + c * N, x + c * N, op->U64.as<double2>(), op->g, op->kappa,
+                                op->res.as<double>() + 2 * c, op->rs(), s));
+    HIPCHK(hipMemcpyAsync(op->hres.p, op->res.p, 2 * kc * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    st.matvec_d += kc;
+    bool all = true;
+    double worst = 0;
+    for (int c = 0; c < kc; ++c) {
+      rn[c] = std::sqrt(op->hres.as<double>()[2 * c]);
+      bn[c] = std::sqrt(op->hres.as<double>()[2 * c + 1]);
+      if (bn[c] == 0.0 && rn[c] > 0.0) {  // b = 0: the solution is x = 0
+        HIPCHK(hipMemsetAsync(x + c * N, 0, N * sizeof(double2), s));
+        rn[c] = 0.0;
+      }
+      const double rel = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+      worst = std::max(worst, rel);
+      all = all && rel <= tol;
+    }
+    st.true_rel_resid = worst;
+    if (all) return;
+    int left = maxiter - st.iters / kc;
+    if (left <= 0 || outer > 200) fail(EB_ERR_NOT_CONVERGED, "batched mixed-precision solve: maxiter reached");
+    for (int c = 0; c < kc; ++c)
+      tol_host[c] = (bn[c] == 0 || rn[c] <= tol * bn[c]) ? HUGE_VAL : std::max(inner_tol * rn[c], 0.5 * tol * bn[c]);
+    HIPCHK(hipMemcpyAsync(tol_dev, tol_host, kc * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_pack_batch<S>(rl, r, N, kc, s);
+    HIPCHK(hipMemsetAsync(el, 0, N * kc * sizeof(S), s));
+    int it[kMaxBatch], why[kMaxBatch];
+    run_bicgstab_batch<S>(op, U, el, rl, kc, tol_dev, left, tag, s, it, why);
+    bool progress = false;
+    for (int c = 0; c < kc; ++c) {
+      st.iters += it[c];
+      st.matvec_d += 2 * it[c];
+      progress = progress || it[c] > 0;
+    }
+    if (!progress) fail(EB_ERR_BREAKDOWN, "batched inner BiCGStab made no progress");
+    launch_unpack_add_batch<S>(x, el, N, kc, s);
     ++outer;
     st.outer_steps = outer;
   }
@@ -813,7 +1019,8 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       outl.idx[k] = free_slots.front();
       free_slots.pop_front();
     }
-    auto [cV, cW] = upload_coef(job->CVraw, job->CWraw);
+    const auto coef = upload_coef(job->CVraw, job->CWraw);
+    double2 *const cV = coef.first, *const cW = coef.second;
     TIMED(EB_K_ROTATE, s, launch_rotate(Vw, outl, Vw, in, cV, N, GA, 0, dots, job->jr, S, op->rs(), s));
     TIMED(EB_K_ROTATE, s, launch_rotate(Ww, outl, Ww, in, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s));
     for (int c = 0; c < mm; ++c) free_slots.push_back(job->cols[c].slot);
@@ -897,7 +1104,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
           HIPCHK(hipEventRecord(ev_hist, s));
         }
       }
-      if (j % poll == 0 && pl.step(hs)) {
+      if (j % poll == 0 && pl.step(&hs)) {
         stopped = true;
         stop_at = hs.stop_at;
         reason = hs.reason;
@@ -947,7 +1154,8 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
           cv[i + size_t(c) * vs] = d2(eta[i] * y(i, c));
           cw[i + size_t(c) * vs] = d2(zeta[i] * z(i, c));
         }
-      auto [cV, cW] = upload_coef(cv, cw);
+      const auto coef = upload_coef(cv, cw);
+      double2 *const cV = coef.first, *const cW = coef.second;
       SlotList in{}, o1{};
       in.n = vs;
       for (int c = 0; c < vs; ++c) in.idx[c] = cols[c].slot;
@@ -1133,10 +1341,10 @@ eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4],
     op->bc_t = bc_t;
     op->Kcap = defl_capacity;
     op->partials.ensure(kMaxPartials * sizeof(double));
-    op->state.ensure(sizeof(KrylovState));
-    op->res.ensure(4 * sizeof(double));
-    op->hstate.ensure(sizeof(KrylovState));
-    op->hres.ensure(4 * sizeof(double));
+    op->state.ensure(kMaxBatch * sizeof(KrylovState));
+    op->res.ensure(2 * kMaxBatch * sizeof(double));
+    op->hstate.ensure(kMaxBatch * sizeof(KrylovState));
+    op->hres.ensure(2 * kMaxBatch * sizeof(double));
     op->U64.ensure(size_t(36) * V * sizeof(double2));
     DevBuf tmp;
     tmp.ensure(size_t(36) * V * sizeof(double2));
@@ -1269,44 +1477,65 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     if (P->method != 0) fail(EB_ERR_INVALID, "only method 0 (BiCGStab) is available");
     if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
       fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
+    if (P->batch != 0 && !batch_size_ok(P->batch)) fail(EB_ERR_INVALID, "batch must be 0, 1, 2, 4, 8 or 16");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
-    double2 *b = op->vec("solve_b"), *x = op->vec("solve_x");
+    const double inner_tol = P->inner_tol > 0 ? P->inner_tol : (P->inner == EB_BF16 ? 1e-2 : 1e-6);
     double worst = 0;
-    for (int c = 0; c < P->nrhs; ++c) {
-      const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c) * op->N;
-      double2 *xc = static_cast<double2 *>(x_can) + size_t(c) * op->N;
-      launch_to_soa_f64(b, bc, op->g, s);
-      launch_to_soa_f64(x, xc, op->g, s);
+    auto merge = [&](const eb_stats &sc) {
+      st.iters += sc.iters;
+      st.matvec_d += sc.matvec_d;
+      st.defl_restarts += sc.defl_restarts;
+      st.outer_steps += sc.outer_steps;
+      st.rec_rel_resid = std::max(st.rec_rel_resid, sc.rec_rel_resid);
+      worst = std::max(worst, sc.true_rel_resid);
+      st.true_rel_resid = worst;
+    };
+    const int kmax = (P->deftol > 0 || P->nrhs == 1) ? 1 : (P->batch ? P->batch : choose_batch(op, P->inner, s));
+    int c0 = 0;
+    while (c0 < P->nrhs) {
+      int kc = 1;
+      while (kc * 2 <= kmax && c0 + kc * 2 <= P->nrhs) kc *= 2;
+      const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c0) * op->N;
+      double2 *xc = static_cast<double2 *>(x_can) + size_t(c0) * op->N;
+      double2 *b = op->vec("solve_b", kc), *x = op->vec("solve_x", kc);
+      for (int c = 0; c < kc; ++c) {
+        launch_to_soa_f64(b + c * op->N, bc + c * op->N, op->g, s);
+        launch_to_soa_f64(x + c * op->N, xc + c * op->N, op->g, s);
+      }
       eb_stats sc = zero_stats();
-      auto merge = [&]() {
-        st.iters += sc.iters;
-        st.matvec_d += sc.matvec_d;
-        st.defl_restarts += sc.defl_restarts;
-        st.outer_steps += sc.outer_steps;
-        st.rec_rel_resid = std::max(st.rec_rel_resid, sc.rec_rel_resid);
-        worst = std::max(worst, sc.true_rel_resid);
-        st.true_rel_resid = worst;
+      auto store = [&]() {
+        for (int c = 0; c < kc; ++c) launch_from_soa_f64(xc + c * op->N, x + c * op->N, op->g, s);
       };
       try {
-        if (op->K > 0) deflate_guess(op, b, x, s);
-        if (P->inner == EB_FP64) {
-          deflated_stab_f64(op, b, x, P->tol, P->deftol, P->maxiter, sc, s);
-        } else if (P->inner == EB_FP32) {
-          mixed_stab<float2>(op, b, x, P->tol, P->inner_tol > 0 ? P->inner_tol : 1e-6, P->maxiter, sc, s);
+        if (kc == 1) {
+          if (op->K > 0) deflate_guess(op, b, x, s);
+          if (P->inner == EB_FP64)
+            deflated_stab_f64(op, b, x, P->tol, P->deftol, P->maxiter, sc, s);
+          else if (P->inner == EB_FP32)
+            mixed_stab<float2>(op, b, x, P->tol, inner_tol, P->maxiter, sc, s);
+          else
+            mixed_stab<bf16c>(op, b, x, P->tol, inner_tol, P->maxiter, sc, s);
         } else {
-          mixed_stab<bf16c>(op, b, x, P->tol, P->inner_tol > 0 ? P->inner_tol : 1e-2, P->maxiter, sc, s);
+          deflate_block(op, b, x, kc, s);
+          if (P->inner == EB_FP64)
+            mixed_stab_batch<double2>(op, b, x, kc, P->tol, 0.5 * P->tol, P->maxiter, sc, s);
+          else if (P->inner == EB_FP32)
+            mixed_stab_batch<float2>(op, b, x, kc, P->tol, inner_tol, P->maxiter, sc, s);
+          else
+            mixed_stab_batch<bf16c>(op, b, x, kc, P->tol, inner_tol, P->maxiter, sc, s);
         }
       } catch (...) {
         // x holds the last iterate and the stats are filled
-        launch_from_soa_f64(xc, x, op->g, s);
+        store();
         (void)hipStreamSynchronize(s);
-        merge();
+        merge(sc);
         throw;
       }
-      launch_from_soa_f64(xc, x, op->g, s);
-      merge();
+      store();
+      merge(sc);
+      c0 += kc;
     }
     st.true_rel_resid = worst;
     HIPCHK(hipGetLastError());
@@ -1315,6 +1544,35 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
   st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = st;
   return rc;
+}
+
+eb_status eb_op_apply_block(eb_op *op, void *out, const void *in, int32_t k, int32_t dagger, eb_prec prec,
+                            void *stream) {
+  return guarded([&]() {
+    if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
+    if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
+    if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n = op->N * size_t(k);
+    auto run = [&](auto *tag, const auto *U) {
+      using S = std::remove_pointer_t<decltype(tag)>;
+      S *a = op->raw<S>(std::string(Inner<S>::tag) + "blk_a", n * sizeof(S));
+      S *b = op->raw<S>(std::string(Inner<S>::tag) + "blk_b", n * sizeof(S));
+      launch_to_batch<S>(a, static_cast<const S *>(in), op->g, k, s);
+      TIMED(EB_K_BDSLASH, s, launch_bdslash<S>(b, a, U, op->g, op->kappa, dagger != 0, k, s));
+      launch_from_batch<S>(static_cast<S *>(out), b, op->g, k, s);
+    };
+    if (prec == EB_FP64)
+      run(static_cast<double2 *>(nullptr), Inner<double2>::links(op, s));
+    else if (prec == EB_FP32)
+      run(static_cast<float2 *>(nullptr), Inner<float2>::links(op, s));
+    else if (prec == EB_BF16)
+      run(static_cast<bf16c *>(nullptr), Inner<bf16c>::links(op, s));
+    else
+      fail(EB_ERR_INVALID, "unknown precision");
+    HIPCHK(hipGetLastError());
+  });
 }
 
 eb_status eb_get_eigenpairs(eb_op *op, int32_t *k, double *evals, void *right, void *left, void *stream) {

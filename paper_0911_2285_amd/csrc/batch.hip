@@ -1,0 +1,493 @@
+// Multi-RHS kernels: the Wilson-Dirac stencil and the BiCGStab passes over a
+// batch of KC right-hand sides.
+//
+// Batch layout: KC spinors interleaved as the fastest index, element
+// (component c, site s, column col) at (c V + s) KC + col.  Thread u of a
+// launch works on column u % KC of site u / KC: the KC lanes of one site read
+// the same link addresses, which the memory pipeline merges into one request,
+// so a link is fetched from HBM once for KC sources (links are 60% of a
+// single-RHS dslash's bytes); spinor accesses of a wavefront stay contiguous.
+//
+// Every column is an independent BiCGStab recurrence (Alg. Incremental
+// eigBiCG, step 3, without DefTol): its own scalars in the history at index
+// j KC + col, its own stop flag in KrylovState[col], and per-column
+// reductions (block_partial_cols / sum_partials).  A column that has stopped
+// is skipped by every later kernel; the others continue.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device_common.h"
+#include "kernel_util.h"
+#include "kernels.h"
+#include "stencil.h"
+
+namespace ebicg {
+namespace {
+
+template <int N>
+__device__ __forceinline__ double pick(const double (&v)[N], int i) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if (k == i) r = v[k];
+  return r;
+}
+
+__device__ __forceinline__ bool col_active(const KrylovState *K, int col, int j) {
+  return !(K[col].stopped && j > K[col].stop_at);
+}
+
+template <typename S, int KC, int SF>
+__global__ void __launch_bounds__(kBlock)
+    k_bdslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa) {
+  using R = typename Store<S>::R;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const R k = R(kappa);
+  const size_t n = size_t(g.V) * KC;
+  for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+    const int s = int(u / KC), col = int(u % KC);
+    cx<R> acc[12];
+    hopping<SF, S, KC>(acc, in + col, U, g, s);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const size_t i = (size_t(c) * g.V + s) * KC + col;
+      Store<S>::st(out, i, Store<S>::ld(in, i) - k * acc[c]);
+    }
+  }
+}
+
+// rhat = p = r; partials of ||r_col||^2
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_init(S *__restrict__ rhat, S *__restrict__ p, const S *__restrict__ r, size_t n,
+                 double *__restrict__ part) {
+  double v[1] = {0.0};
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+    const auto rv = Store<S>::ld(r, u);
+    Store<S>::st(rhat, u, rv);
+    Store<S>::st(p, u, rv);
+    v[0] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+  }
+  block_partial_cols<1, KC, kBlock>(v, part, blockIdx.x);
+}
+
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_init_finish(const double *__restrict__ part, int nblk, const double *__restrict__ tol_abs, int maxiter,
+                        KrylovState *K, KrylovHistory h) {
+  double v[KC];
+  sum_partials<KC, kBlock>(part, nblk, v);
+  if (threadIdx.x >= KC) return;
+  const int col = threadIdx.x;
+  const double rr = pick(v, col), rn = sqrt(rr);
+  h.rho[col] = make_double2(rr, 0.0);
+  h.rn[col] = rn;
+  KrylovState &k = K[col];
+  k.bnorm = 0.0;
+  k.tol_abs = tol_abs[col];
+  k.def_thr = 0.0;
+  k.rnorm = rn;
+  k.maxiter = maxiter;
+  k.stopped = 0;
+  k.stop_at = 0;
+  k.reason = 0;
+  if (rn <= tol_abs[col]) {
+    k.stopped = 1;
+    k.reason = 1;
+  }
+}
+
+// v = D p; partials of (rhat, v) per column
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_v(S *__restrict__ vout, const S *__restrict__ p, const S *__restrict__ rhat, const S *__restrict__ U,
+              Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  const int col = threadIdx.x % KC;
+  const bool act = col_active(K, col, j);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const R k = R(kappa);
+  const size_t n = size_t(g.V) * KC;
+  double d[2] = {0.0, 0.0};
+  if (act) {
+    for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+      const int s = int(u / KC);
+      cx<R> acc[12];
+      hopping<-1, S, KC>(acc, p + col, U, g, s);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const size_t i = (size_t(c) * g.V + s) * KC + col;
+        const cx<R> o = Store<S>::ld(p, i) - k * acc[c];
+        Store<S>::st(vout, i, o);
+        const cx<R> hh = Store<S>::ld(rhat, i);
+        d[0] += double(hh.x) * o.x + double(hh.y) * o.y;
+        d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
+      }
+    }
+  }
+  block_partial_cols<2, KC, kBlock>(d, part, blockIdx.x);
+}
+
+// alpha_j = rho_{j-1} / (rhat, v) per column (one block); a vanishing or
+// non-finite (rhat, v) stops the column (breakdown).
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bfin_alpha(const double *__restrict__ part, int nblk, int j, KrylovState *K, KrylovHistory h) {
+  double d[2 * KC];
+  sum_partials<2 * KC, kBlock>(part, nblk, d);
+  if (threadIdx.x >= KC) return;
+  const int col = threadIdx.x;
+  if (!col_active(K, col, j)) return;
+  const cx<double> den{pick(d, 2 * col), pick(d, 2 * col + 1)};
+  const double dd = den.x * den.x + den.y * den.y;
+  if (!(dd > 0.0) || !isfinite(dd)) {
+    K[col].stopped = 1;
+    K[col].stop_at = j - 1;
+    K[col].reason = 2;
+    return;
+  }
+  h.alpha[j * KC + col] = d2(cdiv(c2(h.rho[(j - 1) * KC + col]), den));
+}
+
+// s = r - alpha v
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_s(S *__restrict__ sv, const S *__restrict__ r, const S *__restrict__ v, size_t n, int j,
+              const KrylovState *K, KrylovHistory h) {
+  using R = typename Store<S>::R;
+  const int col = threadIdx.x % KC;
+  if (!col_active(K, col, j)) return;
+  const cx<double> al = c2(h.alpha[j * KC + col]);
+  const cx<R> a{R(al.x), R(al.y)};
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock)
+    Store<S>::st(sv, u, Store<S>::ld(r, u) - a * Store<S>::ld(v, u));
+}
+
+// t = D s; partials of (t, s), (t, t) per column
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_t(S *__restrict__ tout, const S *__restrict__ sv, const S *__restrict__ U, Geom g, double kappa, int j,
+              const KrylovState *K, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  const int col = threadIdx.x % KC;
+  const bool act = col_active(K, col, j);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const R k = R(kappa);
+  const size_t n = size_t(g.V) * KC;
+  double d[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+      const int s = int(u / KC);
+      cx<R> acc[12];
+      hopping<-1, S, KC>(acc, sv + col, U, g, s);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const size_t i = (size_t(c) * g.V + s) * KC + col;
+        const cx<R> si = Store<S>::ld(sv, i);
+        const cx<R> o = si - k * acc[c];
+        Store<S>::st(tout, i, o);
+        d[0] += double(o.x) * si.x + double(o.y) * si.y;
+        d[1] += double(o.x) * si.y - double(o.y) * si.x;
+        d[2] += double(o.x) * o.x + double(o.y) * o.y;
+      }
+    }
+  }
+  block_partial_cols<3, KC, kBlock>(d, part, blockIdx.x);
+}
+
+// omega_j = (t, s) / (t, t) per column (one block); (t, t) = 0 stops the column.
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bfin_omega(const double *__restrict__ part, int nblk, int j, KrylovState *K, KrylovHistory h) {
+  double d[3 * KC];
+  sum_partials<3 * KC, kBlock>(part, nblk, d);
+  if (threadIdx.x >= KC) return;
+  const int col = threadIdx.x;
+  if (!col_active(K, col, j)) return;
+  const double tt = pick(d, 3 * col + 2);
+  if (!(tt > 0.0)) {
+    K[col].stopped = 1;
+    K[col].stop_at = j - 1;
+    K[col].reason = 2;
+    return;
+  }
+  h.omega[j * KC + col] = make_double2(pick(d, 3 * col) / tt, pick(d, 3 * col + 1) / tt);
+}
+
+// x += alpha p + omega s; r = s - omega t; partials of (rhat, r), ||r||^2
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_xr(S *__restrict__ x, S *__restrict__ r, const S *__restrict__ p, const S *__restrict__ sv,
+               const S *__restrict__ t, const S *__restrict__ rhat, size_t n, int j, const KrylovState *K,
+               KrylovHistory h, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  const int col = threadIdx.x % KC;
+  double e[3] = {0.0, 0.0, 0.0};
+  if (col_active(K, col, j)) {
+    const cx<double> al = c2(h.alpha[j * KC + col]), om = c2(h.omega[j * KC + col]);
+    const cx<R> a{R(al.x), R(al.y)}, w{R(om.x), R(om.y)};
+    for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+      const cx<R> si = Store<S>::ld(sv, u);
+      Store<S>::st(x, u, Store<S>::ld(x, u) + a * Store<S>::ld(p, u) + w * si);
+      const cx<R> ri = si - w * Store<S>::ld(t, u);
+      Store<S>::st(r, u, ri);
+      const cx<R> hh = Store<S>::ld(rhat, u);
+      e[0] += double(hh.x) * ri.x + double(hh.y) * ri.y;
+      e[1] += double(hh.x) * ri.y - double(hh.y) * ri.x;
+      e[2] += double(ri.x) * ri.x + double(ri.y) * ri.y;
+    }
+  }
+  block_partial_cols<3, KC, kBlock>(e, part, blockIdx.x);
+}
+
+// rho_j, ||r_j||, beta_j = (rho_j / rho_{j-1}) (alpha_j / omega_j) and the stop
+// tests per column (one block)
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bfin_beta(const double *__restrict__ part, int nblk, int j, KrylovState *K, KrylovHistory h) {
+  double d[3 * KC];
+  sum_partials<3 * KC, kBlock>(part, nblk, d);
+  if (threadIdx.x >= KC) return;
+  const int col = threadIdx.x;
+  if (!col_active(K, col, j)) return;
+  const cx<double> rho{pick(d, 3 * col), pick(d, 3 * col + 1)};
+  const cx<double> be = cdiv(rho, c2(h.rho[(j - 1) * KC + col])) *
+                        cdiv(c2(h.alpha[j * KC + col]), c2(h.omega[j * KC + col]));
+  const double rnorm = sqrt(pick(d, 3 * col + 2));
+  KrylovState &k = K[col];
+  h.rho[j * KC + col] = d2(rho);
+  h.beta[j * KC + col] = d2(be);
+  h.rn[j * KC + col] = rnorm;
+  k.rnorm = rnorm;
+  if (rnorm <= k.tol_abs) {
+    k.stopped = 1;
+    k.stop_at = j;
+    k.reason = 1;
+  } else if (rho.x == 0.0 && rho.y == 0.0) {
+    k.stopped = 1;
+    k.stop_at = j;
+    k.reason = 2;
+  } else if (j >= k.maxiter) {
+    k.stopped = 1;
+    k.stop_at = j;
+    k.reason = 4;
+  }
+}
+
+// p = r + beta (p - omega v); a column that stopped at this j keeps its p
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_p(S *__restrict__ p, const S *__restrict__ r, const S *__restrict__ v, size_t n, int j,
+              const KrylovState *K, KrylovHistory h) {
+  using R = typename Store<S>::R;
+  const int col = threadIdx.x % KC;
+  if (K[col].stopped && j >= K[col].stop_at) return;
+  const cx<double> be = c2(h.beta[j * KC + col]), om = c2(h.omega[j * KC + col]);
+  const cx<R> b{R(be.x), R(be.y)}, w{R(om.x), R(om.y)};
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock)
+    Store<S>::st(p, u, Store<S>::ld(r, u) + b * (Store<S>::ld(p, u) - w * Store<S>::ld(v, u)));
+}
+
+// FP64 columns (column col at src + col N) <-> a batch in storage S
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_pack_batch(S *__restrict__ dst, const double2 *__restrict__ src, size_t N) {
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < N * KC; u += size_t(gridDim.x) * kBlock) {
+    const double2 v = src[(u % KC) * N + u / KC];
+    Store<S>::st(dst, u, cx<typename Store<S>::R>{typename Store<S>::R(v.x), typename Store<S>::R(v.y)});
+  }
+}
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_unpack_add_batch(double2 *__restrict__ x, const S *__restrict__ e, size_t N) {
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < N * KC; u += size_t(gridDim.x) * kBlock) {
+    const auto v = Store<S>::ld(e, u);
+    double2 &o = x[(u % KC) * N + u / KC];
+    o = make_double2(o.x + double(v.x), o.y + double(v.y));
+  }
+}
+// canonical spinors [KC][V][12] <-> batch
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock) k_to_batch(S *__restrict__ dst, const S *__restrict__ src, int V) {
+  const size_t n = size_t(V) * 12 * KC;
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+    const int col = int(u % KC);
+    const size_t cs = u / KC;  // c V + s
+    const int c = int(cs / V), s = int(cs % V);
+    dst[u] = src[(size_t(col) * V + s) * 12 + c];
+  }
+}
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock) k_from_batch(S *__restrict__ dst, const S *__restrict__ src, int V) {
+  const size_t n = size_t(V) * 12 * KC;
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+    const int col = int(u % KC);
+    const size_t cs = u / KC;
+    const int c = int(cs / V), s = int(cs % V);
+    dst[(size_t(col) * V + s) * 12 + c] = src[u];
+  }
+}
+
+// grids: records of KC * NV doubles per block must fit one scratch region
+inline int batch_stencil_grid(int V, int kc, int nv) {
+  int nb = nblocks_for(size_t(V) * kc);
+  const int cap = int(kRegion / size_t(kc * nv));
+  nb = nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
+  return nb > cap ? cap : nb;
+}
+inline int batch_red_grid(size_t n, int kc, int nv) {
+  int nb = red_grid(n);
+  const int cap = int(kRegion / size_t(kc * nv));
+  return nb > cap ? cap : nb;
+}
+
+template <typename F>
+void dispatch_kc(int kc, F &&f) {
+  switch (kc) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: break;  // the host validates kc
+  }
+}
+
+}  // namespace
+
+#define EB_LAUNCH(kernel, grid, block, shmem, st, ...) hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__)
+
+bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
+
+template <typename S>
+void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    const dim3 grid(nblocks_for(size_t(g.V) * KC));
+    if (dagger)
+      EB_LAUNCH((k_bdslash<S, KC, +1>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+    else
+      EB_LAUNCH((k_bdslash<S, KC, -1>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+  });
+}
+
+template <typename S>
+void launch_bstab_init(S *rhat, S *p, const S *r, size_t N, int kc, const double *tol_abs, int maxiter,
+                       KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    const int nb = batch_red_grid(N * KC, KC, 1);
+    EB_LAUNCH((k_bstab_init<S, KC>), dim3(nb), dim3(kBlock), 0, st, rhat, p, r, N * KC, region(rs, RG_INIT));
+    EB_LAUNCH(k_bstab_init_finish<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_INIT), nb, tol_abs, maxiter, K, h);
+  });
+}
+
+template <typename S>
+void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, int kc,
+                    KrylovState *K, const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_bstab_v<S, KC>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st, v, p, rhat, U, g, kappa,
+              j, K, region(rs, RG_V));
+  });
+}
+
+template <typename S>
+void launch_bstab_s(S *sv, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
+                    const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    const size_t n = size_t(12) * g.V * KC;
+    EB_LAUNCH(k_bfin_alpha<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_V), batch_stencil_grid(g.V, KC, 2), j, K,
+              h);
+    EB_LAUNCH((k_bstab_s<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, sv, r, v, n, j, K, h);
+  });
+}
+
+template <typename S>
+void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, int j, int kc, KrylovState *K,
+                    const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_bstab_t<S, KC>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st, t, sv, U, g, kappa, j,
+              K, region(rs, RG_T));
+  });
+}
+
+template <typename S>
+void launch_bstab_xr(S *x, S *r, const S *p, const S *sv, const S *t, const S *rhat, const Geom &g, int j, int kc,
+                     KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    const size_t n = size_t(12) * g.V * KC;
+    EB_LAUNCH(k_bfin_omega<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_T), batch_stencil_grid(g.V, KC, 3), j, K,
+              h);
+    EB_LAUNCH((k_bstab_xr<S, KC>), dim3(batch_red_grid(n, KC, 3)), dim3(kBlock), 0, st, x, r, p, sv, t, rhat, n, j, K,
+              h, region(rs, RG_XR));
+  });
+}
+
+template <typename S>
+void launch_bstab_p(S *p, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
+                    const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    const size_t n = size_t(12) * g.V * KC;
+    EB_LAUNCH(k_bfin_beta<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_XR), batch_red_grid(n, KC, 3), j, K, h);
+    EB_LAUNCH((k_bstab_p<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, p, r, v, n, j, K, h);
+  });
+}
+
+template <typename S>
+void launch_pack_batch(S *dst, const double2 *src, size_t N, int kc, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_pack_batch<S, KC>), dim3(stream_grid(N * KC)), dim3(kBlock), 0, st, dst, src, N);
+  });
+}
+template <typename S>
+void launch_unpack_add_batch(double2 *x, const S *e, size_t N, int kc, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_unpack_add_batch<S, KC>), dim3(stream_grid(N * KC)), dim3(kBlock), 0, st, x, e, N);
+  });
+}
+template <typename S>
+void launch_to_batch(S *dst, const S *src, const Geom &g, int kc, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_to_batch<S, KC>), dim3(stream_grid(size_t(12) * g.V * KC)), dim3(kBlock), 0, st, dst, src, g.V);
+  });
+}
+template <typename S>
+void launch_from_batch(S *dst, const S *src, const Geom &g, int kc, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_from_batch<S, KC>), dim3(stream_grid(size_t(12) * g.V * KC)), dim3(kBlock), 0, st, dst, src, g.V);
+  });
+}
+
+#define EB_BATCH_INST(S)                                                                                           \
+  template void launch_bdslash<S>(S *, const S *, const S *, const Geom &, double, bool, int, hipStream_t);        \
+  template void launch_bstab_init<S>(S *, S *, const S *, size_t, int, const double *, int, KrylovState *,         \
+                                     KrylovHistory, const RedScratch &, hipStream_t);                              \
+  template void launch_bstab_v<S>(S *, const S *, const S *, const S *, const Geom &, double, int, int,            \
+                                  KrylovState *, const RedScratch &, hipStream_t);                                 \
+  template void launch_bstab_s<S>(S *, const S *, const S *, const Geom &, int, int, KrylovState *, KrylovHistory, \
+                                  const RedScratch &, hipStream_t);                                                \
+  template void launch_bstab_t<S>(S *, const S *, const S *, const Geom &, double, int, int, KrylovState *,        \
+                                  const RedScratch &, hipStream_t);                                                \
+  template void launch_bstab_xr<S>(S *, S *, const S *, const S *, const S *, const S *, const Geom &, int, int,   \
+                                   KrylovState *, KrylovHistory, const RedScratch &, hipStream_t);                 \
+  template void launch_bstab_p<S>(S *, const S *, const S *, const Geom &, int, int, KrylovState *, KrylovHistory, \
+                                  const RedScratch &, hipStream_t);                                                \
+  template void launch_pack_batch<S>(S *, const double2 *, size_t, int, hipStream_t);                              \
+  template void launch_unpack_add_batch<S>(double2 *, const S *, size_t, int, hipStream_t);                        \
+  template void launch_to_batch<S>(S *, const S *, const Geom &, int, hipStream_t);                                \
+  template void launch_from_batch<S>(S *, const S *, const Geom &, int, hipStream_t);
+EB_BATCH_INST(double2)
+EB_BATCH_INST(float2)
+EB_BATCH_INST(bf16c)
+
+}  // namespace ebicg

@@ -177,6 +177,35 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], double *__restric
   }
 }
 
+// Per-column block sums for KC right-hand sides interleaved as the fastest
+// index: thread t of a block always carries column t % KC.  The wave sum runs
+// over the lanes of one column (xor offsets >= KC), then over the waves; the
+// record of KC * NV doubles [col][i] goes to part[bid * KC * NV].
+template <int NV, int KC, int BS>
+__device__ __forceinline__ void block_partial_cols(double (&v)[NV], double *__restrict__ part, int bid) {
+  static_assert(KC >= 1 && KC <= kWave && (KC & (KC - 1)) == 0, "KC must be a power of two <= 64");
+  __shared__ double sm[BS / kWave][KC][NV];
+#pragma unroll
+  for (int off = kWave / 2; off >= KC; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, kWave);
+  }
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  __syncthreads();
+  if (l < KC) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sm[w][l][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < KC * NV) {
+    const int col = threadIdx.x / NV, i = threadIdx.x % NV;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < BS / kWave; ++k) s += sm[k][col][i];
+    part[size_t(bid) * KC * NV + threadIdx.x] = s;
+  }
+}
+
 // Sum of the nblk partial records written by the previous kernel, in a fixed
 // order, so every block of the consuming kernel obtains the same totals (in
 // every thread).  Kernel boundaries make the partials visible: no fences and

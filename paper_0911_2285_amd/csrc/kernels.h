@@ -170,4 +170,42 @@ template <typename S>
 void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
                    const RedScratch &rs, hipStream_t st);
 
+// ---- multi-RHS batches (batch.hip) ------------------------------------------------
+// A batch holds kc right-hand sides interleaved as the fastest index: element
+// (component c, site s, column col) at (c V + s) kc + col; kc in {1, 2, 4, 8, 16}.
+// Per-column solver state K[col], history entries at j kc + col.
+constexpr int kMaxBatch = 16;
+bool batch_size_ok(int kc);
+template <typename S>
+void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st);
+// rhat = p = r; rho_0, ||r_0|| per column; column col stops at once if ||r_0|| <= tol_abs[col] (device)
+template <typename S>
+void launch_bstab_init(S *rhat, S *p, const S *r, size_t N, int kc, const double *tol_abs, int maxiter,
+                       KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, int kc,
+                    KrylovState *K, const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_bstab_s(S *s, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
+                    const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_bstab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, int kc, KrylovState *K,
+                    const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_bstab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, const Geom &g, int j, int kc,
+                     KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_bstab_p(S *p, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
+                    const RedScratch &rs, hipStream_t st);
+// kc FP64 SoA columns (column col at src + col N) -> batch in storage S; x_col += batch column col
+template <typename S>
+void launch_pack_batch(S *dst, const double2 *src, size_t N, int kc, hipStream_t st);
+template <typename S>
+void launch_unpack_add_batch(double2 *x, const S *e, size_t N, int kc, hipStream_t st);
+// canonical spinors back to back [kc][V][12] <-> batch
+template <typename S>
+void launch_to_batch(S *dst, const S *src, const Geom &g, int kc, hipStream_t st);
+template <typename S>
+void launch_from_batch(S *dst, const S *src, const Geom &g, int kc, hipStream_t st);
+
 }  // namespace ebicg

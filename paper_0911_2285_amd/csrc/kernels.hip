@@ -18,179 +18,14 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "kernel_util.h"
+#include "stencil.h"
 
 namespace ebicg {
 
 namespace {
 
-// Partial-sum regions of the reduction scratch, one per producer so that a
-// record is never overwritten before its consumer has read it.
-enum Region : int { RG_SIGMA = 0, RG_RR, RG_V, RG_T, RG_XR, RG_INIT, RG_RES, RG_GEN };
-constexpr size_t kRegion = kRegionDoubles;
-inline double *region(const RedScratch &rs, Region r) { return rs.partials + size_t(r) * kRegion; }
 
-inline int nblocks_for(size_t n, int per_thread = 1) {
-  size_t t = (n + per_thread - 1) / per_thread;
-  return int((t + kBlock - 1) / kBlock);
-}
-// grid of the streaming kernels with reductions: a function of n only
-inline int red_grid(size_t n) {
-  int nb = nblocks_for(n, 4);
-  return nb < 1 ? 1 : (nb > kMaxRedBlocks ? kMaxRedBlocks : nb);
-}
-// stencil kernels with reductions: one block per kBlock sites, capped; the
-// kernels loop over site blocks beyond the cap
-constexpr int kMaxStencilBlocks = 1024;
-inline int stencil_grid(int V) {
-  int nb = nblocks_for(size_t(V));
-  return nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
-}
-inline int stream_grid(size_t n) {
-  int nb = nblocks_for(n, 4);
-  return nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
-}
-
-__device__ __forceinline__ bool skip_iter(const KrylovState *S, int j) { return S->stopped && j > S->stop_at; }
-
-__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
-  const double d = b.x * b.x + b.y * b.y;
-  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
-}
-__device__ __forceinline__ cx<double> c2(double2 v) { return {v.x, v.y}; }
-__device__ __forceinline__ double2 d2(cx<double> v) { return make_double2(v.x, v.y); }
-
-// ----------------------------------------------------------------------------
-// Wilson hopping term.  Gamma basis (chiral): gamma_k = [[0,-i s_k],[i s_k,0]],
-// gamma_t = [[0,1],[1,0]].  For the projector (1 + sg gamma_mu) the spinor
-// collapses to two spin components h0, h1 (the upper half of the result);
-// the lower half is a fixed multiple of (h0, h1):
-//   mu=x: h0 = p0 - sg i p3, h1 = p1 - sg i p2;  lower = (sg i h1,  sg i h0)
-//   mu=y: h0 = p0 - sg p3,   h1 = p1 + sg p2;    lower = (sg h1,   -sg h0)
-//   mu=z: h0 = p0 - sg i p2, h1 = p1 + sg i p3;  lower = (sg i h0, -sg i h1)
-//   mu=t: h0 = p0 + sg p2,   h1 = p1 + sg p3;    lower = (sg h0,    sg h1)
-// The colour matrix acts on the two-component half spinor only (half the
-// flops), and one output colour row is finished at a time so that only one
-// row of the link is live.
-// ----------------------------------------------------------------------------
-template <int SG, typename R>
-__device__ __forceinline__ cx<R> sgn(cx<R> a) {
-  return SG > 0 ? a : -a;
-}
-
-template <int MU, int SG, typename S>
-__device__ __forceinline__ void load_project(cx<typename Store<S>::R> (&h)[6], const S *__restrict__ in, int V,
-                                             int sn) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const auto p0 = Store<S>::ld(in, size_t(a) * V + sn);
-    const auto p1 = Store<S>::ld(in, size_t(3 + a) * V + sn);
-    const auto p2 = Store<S>::ld(in, size_t(6 + a) * V + sn);
-    const auto p3 = Store<S>::ld(in, size_t(9 + a) * V + sn);
-    if constexpr (MU == 0) {
-      h[a] = p0 - sgn<SG>(ci(p3));
-      h[3 + a] = p1 - sgn<SG>(ci(p2));
-    } else if constexpr (MU == 1) {
-      h[a] = p0 - sgn<SG>(p3);
-      h[3 + a] = p1 + sgn<SG>(p2);
-    } else if constexpr (MU == 2) {
-      h[a] = p0 - sgn<SG>(ci(p2));
-      h[3 + a] = p1 + sgn<SG>(ci(p3));
-    } else {
-      h[a] = p0 + sgn<SG>(p2);
-      h[3 + a] = p1 + sgn<SG>(p3);
-    }
-  }
-}
-
-// acc += (spin reconstruction of) U h  (ADJ: U^+ h), U = U_mu at site sl.
-template <int MU, int SG, bool ADJ, typename S>
-__device__ __forceinline__ void mult_accum(cx<typename Store<S>::R> (&acc)[12], const cx<typename Store<S>::R> (&h)[6],
-                                           const S *__restrict__ U, int V, int sl) {
-  using R = typename Store<S>::R;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    cx<R> t0, t1;
-    if constexpr (!ADJ) {  // row a of U
-      const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 0) * V + sl);
-      const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 1) * V + sl);
-      const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 2) * V + sl);
-      t0 = u0 * h[0];
-      cfma(t0, u1, h[1]);
-      cfma(t0, u2, h[2]);
-      t1 = u0 * h[3];
-      cfma(t1, u1, h[4]);
-      cfma(t1, u2, h[5]);
-    } else {  // column a of U, conjugated
-      const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + 0 + a) * V + sl);
-      const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + 3 + a) * V + sl);
-      const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + 6 + a) * V + sl);
-      t0 = cmulc(u0, h[0]);
-      cfmac(t0, u1, h[1]);
-      cfmac(t0, u2, h[2]);
-      t1 = cmulc(u0, h[3]);
-      cfmac(t1, u1, h[4]);
-      cfmac(t1, u2, h[5]);
-    }
-    acc[a] = acc[a] + t0;
-    acc[3 + a] = acc[3 + a] + t1;
-    if constexpr (MU == 0) {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t1));
-      acc[9 + a] = acc[9 + a] + sgn<SG>(ci(t0));
-    } else if constexpr (MU == 1) {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(t1);
-      acc[9 + a] = acc[9 + a] - sgn<SG>(t0);
-    } else if constexpr (MU == 2) {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t0));
-      acc[9 + a] = acc[9 + a] - sgn<SG>(ci(t1));
-    } else {
-      acc[6 + a] = acc[6 + a] + sgn<SG>(t0);
-      acc[9 + a] = acc[9 + a] + sgn<SG>(t1);
-    }
-  }
-}
-
-// Keeps the compiler from hoisting the next hop's loads above this point, so
-// the live state stays at one hop (half spinor + link row + accumulator) and
-// the kernel runs several waves per SIMD instead of spilling.
-__device__ __forceinline__ void hop_fence() { asm volatile("" ::: "memory"); }
-
-// One direction mu: forward hop with projector (1 + SF gamma_mu) and U_mu(x),
-// backward hop with (1 - SF gamma_mu) and U_mu(x - mu)^+.
-template <int MU, int SF, typename S>
-__device__ __forceinline__ void hop_dir(cx<typename Store<S>::R> (&acc)[12], const S *__restrict__ in,
-                                        const S *__restrict__ U, int V, int s, int sf, int sb) {
-  using R = typename Store<S>::R;
-  cx<R> h[6];
-  load_project<MU, SF, S>(h, in, V, sf);
-  mult_accum<MU, SF, false, S>(acc, h, U, V, s);
-  hop_fence();
-  load_project<MU, -SF, S>(h, in, V, sb);
-  mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
-  hop_fence();
-}
-
-// Hopping sum at site s: sum_mu [ (1 + SF g) U psi(x+mu) + (1 - SF g) U^+ psi(x-mu) ].
-// D uses SF = -1, D^+ uses SF = +1.
-template <int SF, typename S>
-__device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], const S *__restrict__ in,
-                                        const S *__restrict__ U, const Geom &g, int s) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
-  const int x = s % g.lx;
-  const int y = (s / sy) % g.ly;
-  const int z = (s / sz) % g.lz;
-  const int t = s / stt;
-  hop_dir<0, SF, S>(acc, in, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
-  hop_dir<1, SF, S>(acc, in, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
-                    y == 0 ? s + (g.ly - 1) * sy : s - sy);
-  hop_dir<2, SF, S>(acc, in, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
-                    z == 0 ? s + (g.lz - 1) * sz : s - sz);
-  hop_dir<3, SF, S>(acc, in, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
-                    t == 0 ? s + (g.lt - 1) * stt : s - stt);
-}
-
-// acc_sg += (spin reconstruction with sign SG of) t for output colour row a.
 template <int MU, int SG, typename R>
 __device__ __forceinline__ void recon_row(cx<R> (&acc)[12], int a, cx<R> t0, cx<R> t1) {
   acc[a] = acc[a] + t0;

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libebicg.so")
 EB_OK = 0
 # kernel classes of eb_timing_read (include/ebicg.h)
 KERNEL_CLASSES = ["bicg_matvec", "bicg_update_r", "bicg_update_p", "stab_v", "stab_s", "stab_t", "stab_xr", "stab_p",
-                  "rotate", "residual", "proj", "dslash"]
+                  "rotate", "residual", "proj", "dslash", "bstab_v", "bstab_s", "bstab_t", "bstab_xr", "bstab_p",
+                  "bdslash"]
 STATUS = {
     0: "EB_OK",
     -1: "EB_ERR_INVALID",
@@ -59,6 +60,7 @@ class _SolveParams(ctypes.Structure):
         ("inner", ctypes.c_int32),
         ("inner_tol", ctypes.c_double),
         ("nrhs", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
     ]
 
 
@@ -90,6 +92,7 @@ _SIGNATURES = [
     ("eb_op_destroy", ctypes.c_int, [_P]),
     ("eb_op_apply", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     ("eb_op_apply_dagger", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    ("eb_op_apply_block", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
     ("eb_eigbicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_EigParams), _P, ctypes.POINTER(_Stats), _P]),
     ("eb_deflated_bicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_SolveParams), ctypes.POINTER(_Stats), _P]),
     ("eb_get_eigenpairs", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]),
@@ -227,6 +230,18 @@ def op_apply_dagger(op, out, inp, prec="fp64", stream=None):
                                     PREC[prec], _stream(stream)))
 
 
+def op_apply_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
+    """out_i = D inp_i (or D^+) for k spinors back to back, one pass over the links."""
+    import torch
+
+    if prec == "bf16":
+        po, pi = _dev_ptr(out, 2 * op.N * k, torch.bfloat16, "out"), _dev_ptr(inp, 2 * op.N * k, torch.bfloat16, "in")
+    else:
+        dt = {"fp64": torch.complex128, "fp32": torch.complex64}[prec]
+        po, pi = _dev_ptr(out, op.N * k, dt, "out"), _dev_ptr(inp, op.N * k, dt, "in")
+    _check(lib().eb_op_apply_block(op.handle, po, pi, int(k), int(bool(dagger)), PREC[prec], _stream(stream)))
+
+
 def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):
     """One eigBiCG solve that grows the deflation space; returns (stats, ritz values)."""
     import torch
@@ -248,11 +263,13 @@ def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):
 
 
 def deflated_bicg_solve(op, b, x, tol, deftol=0.0, maxiter=10000, method=0, inner="fp64", inner_tol=0.0, nrhs=1,
-                        stream=None):
-    """Deflated BiCGStab solve(s); b, x hold nrhs spinors back to back.  Returns stats."""
+                        batch=1, stream=None):
+    """Deflated BiCGStab solve(s); b, x hold nrhs spinors back to back.  batch: columns per
+    multi-RHS iteration (1, 2, 4, 8, 16; 0 = the library's timed choice).  Returns stats."""
     import torch
 
-    p = _SolveParams(float(tol), float(deftol), int(maxiter), int(method), PREC[inner], float(inner_tol), int(nrhs))
+    p = _SolveParams(float(tol), float(deftol), int(maxiter), int(method), PREC[inner], float(inner_tol), int(nrhs),
+                     int(batch))
     st = _Stats()
     rc = lib().eb_deflated_bicg_solve(
         op.handle,

@@ -141,6 +141,71 @@ def test_mixed_precision_error_vs_fp64_solution(gpu_lib, cfg0, inner, inner_tol)
         assert err <= 1e-8
 
 
+@pytest.fixture(scope="module")
+def space8(gpu_lib, cfg0):
+    """cfg0 operator with a deflation space from two eigBiCG solves, and 8 sources."""
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8)
+    for i in range(2):
+        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, i))).to("cuda:0")
+        gpu_lib.eigbicg_solve(op, b, torch.zeros_like(b), nev=4, m=16, tol=1e-10)
+    B = np.stack([synth.z2_source(V, synth.rhs_seed(0, 30 + i)) for i in range(8)])
+    D = W.dense_D(U, kappa, dims)
+    Xs = np.linalg.solve(D, B.reshape(8, -1).T).T
+    return op, B, Xs
+
+
+@pytest.mark.parametrize("inner,batch", [("fp64", 4), ("fp32", 8), ("bf16", 2), ("fp32", 0)])
+def test_batched_deflated_solves(gpu_lib, cfg0, space8, inner, batch):
+    """Multi-RHS deflated solves (k columns per iteration, per-column scalars):
+    every column reaches the FP64 true residual 1e-10 and matches the dense
+    FP64 solution; the same sources solved one at a time agree."""
+    import torch
+
+    dims, kappa, U = cfg0
+    A, _ = _ops(U, kappa, dims)
+    op, B, Xs = space8
+    b = torch.from_numpy(B).to("cuda:0")
+    x = torch.zeros_like(b)
+    st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, inner=inner, nrhs=8, batch=batch)
+    X = x.cpu().numpy().reshape(8, -1)
+    for c in range(8):
+        tr = np.linalg.norm(B[c].ravel() - A(X[c])) / np.linalg.norm(B[c])
+        err = np.linalg.norm(X[c] - Xs[c]) / np.linalg.norm(Xs[c])
+        assert tr <= 1e-10 and err <= 1e-8, (c, tr, err)
+    assert st["true_rel_resid"] <= 1e-10
+    x1 = torch.zeros_like(b)
+    st1 = gpu_lib.deflated_bicg_solve(op, b, x1, tol=1e-10, inner=inner, nrhs=8, batch=1)
+    print(f"{inner} batch {batch}: iters {st['iters']} (one at a time {st1['iters']}), outer {st['outer_steps']}")
+    assert st["iters"] <= 1.5 * st1["iters"] + 8
+
+
+def test_batched_ragged_and_zero_column(gpu_lib, cfg0, space8):
+    """5 right-hand sides with batch 4 (a batch of 4, then one column alone),
+    one of them zero, and a non-zero start: the zero column returns x = 0."""
+    import torch
+
+    dims, kappa, U = cfg0
+    A, _ = _ops(U, kappa, dims)
+    op, B, Xs = space8
+    Bz = B[:5].copy()
+    Bz[2] = 0
+    b = torch.from_numpy(Bz).to("cuda:0")
+    x = torch.full_like(b, 0.25)
+    st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, inner="fp32", nrhs=5, batch=4)
+    X = x.cpu().numpy().reshape(5, -1)
+    assert np.abs(X[2]).max() == 0
+    for c in (0, 1, 3, 4):
+        assert np.linalg.norm(Bz[c].ravel() - A(X[c])) / np.linalg.norm(Bz[c]) <= 1e-10
+    assert st["true_rel_resid"] <= 1e-10
+    with pytest.raises(gpu_lib.EbicgError) as e:
+        gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, nrhs=5, batch=3)
+    assert e.value.status == -1
+
+
 def test_error_paths(gpu_lib, cfg0):
     import torch
 
