@@ -120,6 +120,80 @@ def cpu_baseline(W, U, b_np, eig_iters, stab_iters, n_eig_it=5, n_stab_it=3):
     }
 
 
+def stencil_bytes(V, k, prec):
+    """Algorithmic bytes of one k-column stencil launch: k inputs and k outputs
+    of 12 complex per site, and the 4 x 9 complex links per site read once."""
+    cb = {"fp64": 16, "fp32": 8, "bf16": 4}[prec]
+    return V * cb * (24 * k + 36)
+
+
+def multi_rhs_stencil(eb, op, V, precs=("fp64", "fp32", "bf16"), ks=(1, 2, 4, 8, 16), reps=5):
+    """GB/s of the multi-RHS stencil (HIP events inside the library) per precision and k."""
+    import torch
+
+    out = {}
+    for prec in precs:
+        out[prec] = {}
+        for k in ks:
+            if prec == "bf16":
+                x = torch.zeros(k * 24 * V, dtype=torch.bfloat16, device="cuda:0")
+            else:
+                x = torch.zeros(k * 12 * V, dtype={"fp64": torch.complex128, "fp32": torch.complex64}[prec],
+                                device="cuda:0")
+            y = torch.empty_like(x)
+            eb.op_apply_block(op, y, x, k, prec=prec)
+            torch.cuda.synchronize()
+            eb.timing_enable(op, True)
+            for _ in range(reps):
+                eb.op_apply_block(op, y, x, k, prec=prec)
+            torch.cuda.synchronize()
+            n, ms = eb.timing_read(op)["bdslash"]
+            eb.timing_enable(op, False)
+            us = 1e3 * ms / n
+            out[prec][k] = {"us": round(us, 2), "GBps": round(stencil_bytes(V, k, prec) / (us * 1e-6) / 1e9, 1)}
+            del x, y
+    return out
+
+
+def large_lattice(eb, dims, kappa, nrhs, tol):
+    """A lattice whose fields exceed the 256 MB Infinity Cache: multi-RHS stencil
+    bandwidth, and mixed-precision batched solves (FP32 and BF16 storage in FP64
+    refinement, batch size chosen by the library's timing) against plain FP64
+    BiCGStab one right-hand side at a time.  No deflation space."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    V = synth.volume(dims)
+    t0 = time.perf_counter()
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(2))
+    log(f"[bench] {dims}: links generated in {time.perf_counter() - t0:.1f} s")
+    op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=0)
+    del U
+    res = {"lattice": list(dims), "kappa": kappa, "stencil": multi_rhs_stencil(eb, op, V)}
+    B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(2, i))) for i in range(nrhs)]).to("cuda:0")
+    solves = {}
+    for name, kw in [("fp64_one_at_a_time", dict(inner="fp64", batch=1)),
+                     ("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6, batch=0)),
+                     ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2, batch=0))]:
+        X = torch.zeros_like(B)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op, B, X, tol=tol, maxiter=20000, nrhs=nrhs, **kw)
+        dt = time.perf_counter() - t1
+        assert st["true_rel_resid"] <= tol, (name, st)
+        solves[name] = {"solves_per_s": round(nrhs / dt, 3), "iters_per_rhs": round(st["iters"] / nrhs, 1),
+                        "outer_steps": st["outer_steps"], "max_true_rel_resid": st["true_rel_resid"]}
+        log(f"[bench] {dims} {name}: {solves[name]}")
+    res["solves"] = solves
+    res["nrhs"] = nrhs
+    eb.op_destroy(op)
+    del B, X
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +202,7 @@ def main():
     ap.add_argument("--workload", default="inc16x32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    ap.add_argument("--no-large", action="store_true", help="skip the 24^3 x 64 multi-RHS / precision section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU path is design-only",
@@ -225,6 +300,19 @@ def main():
     nd = W["nrhs"] - W["n1"]
     extra["deflated_solves_per_s"] = {k: round(nd / dt[k], 3) for k in modes}
     extra["deflated_iters_outer"] = {k: mode_its[k][:4] for k in modes}
+    # multi-RHS: the 16 deflated sources in batches (FP32 / BF16 inner, batch chosen by the library)
+    nd = W["nrhs"] - W["n1"]
+    Bd = torch.stack(B[W["n1"]:])
+    for name, kw in [("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
+                     ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
+        Xd = torch.zeros_like(Bd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
+        dt_b = time.perf_counter() - t1
+        assert st["true_rel_resid"] <= W["tol"], (name, st)
+        extra["deflated_solves_per_s"][name] = round(nd / dt_b, 3)
+    extra["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
     # undeflated FP64 BiCGStab on the same sources, for the deflation speed-up
     eb.defl_reset(op)
     plain_its = []
@@ -233,6 +321,9 @@ def main():
         st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000)
         plain_its.append(st["iters"])
     extra["undeflated_bicgstab_iters"] = plain_its
+
+    if not args.no_large:
+        extra["large_lattice"] = large_lattice(eb, (24, 24, 24, 64), 0.123, 16, W["tol"])
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1377,21 +1377,21 @@ static eb_status apply_impl(eb_op *op, void *out, const void *in, eb_prec prec, 
     if (prec == EB_FP64) {
       double2 *a = op->vec("apply_a"), *b = op->vec("apply_b");
       launch_to_soa_f64(a, static_cast<const double2 *>(in), op->g, s);
-      launch_dslash_f64(b, a, op->U64.as<double2>(), op->g, op->kappa, dagger, s);
+      TIMED(EB_K_DSLASH, s, launch_dslash_f64(b, a, op->U64.as<double2>(), op->g, op->kappa, dagger, s));
       launch_from_soa_f64(static_cast<double2 *>(out), b, op->g, s);
     } else if (prec == EB_FP32) {
       const float2 *U = Inner<float2>::links(op, s);
       float2 *a = op->raw<float2>("apply_a32", N * sizeof(float2));
       float2 *b = op->raw<float2>("apply_b32", N * sizeof(float2));
       launch_to_soa_f32(a, static_cast<const float2 *>(in), op->g, s);
-      launch_dslash_f32(b, a, U, op->g, op->kappa, dagger, s);
+      TIMED(EB_K_DSLASH, s, launch_dslash_f32(b, a, U, op->g, op->kappa, dagger, s));
       launch_from_soa_f32(static_cast<float2 *>(out), b, op->g, s);
     } else if (prec == EB_BF16) {
       const bf16c *U = Inner<bf16c>::links(op, s);
       bf16c *a = op->raw<bf16c>("apply_a16", N * sizeof(bf16c));
       bf16c *b = op->raw<bf16c>("apply_b16", N * sizeof(bf16c));
       launch_to_soa_bf16(a, static_cast<const bf16c *>(in), op->g, s);
-      launch_dslash_bf16(b, a, U, op->g, op->kappa, dagger, s);
+      TIMED(EB_K_DSLASH, s, launch_dslash_bf16(b, a, U, op->g, op->kappa, dagger, s));
       launch_from_soa_bf16(static_cast<bf16c *>(out), b, op->g, s);
     } else {
       fail(EB_ERR_INVALID, "unknown precision");
