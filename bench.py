@@ -194,6 +194,116 @@ def large_lattice(eb, dims, kappa, nrhs, tol):
     return res
 
 
+# ---------------------------------------------------------------------------
+# HBM traffic of the roofline kernel from rocprofv3 counters.
+#   1. rocprofv3 --pmc FETCH_SIZE -d D1 -o run -- python3 bench.py --pmc-pass
+#   2. rocprofv3 --pmc WRITE_SIZE -d D2 -o run -- python3 bench.py --pmc-pass
+#   (--pmc-pass runs one eigBiCG solve of the workload, then a plain copy of
+#   COPY_BYTES so the counters can be calibrated against a known size)
+#   3. python3 bench.py --summarize-pmc D1/run_counter_collection.csv D2/run_counter_collection.csv
+# writes profiles/pmc_<kernel>_<workload>.json.  The summary records a hash of
+# the kernel sources; bench.py reports traffic only while the hash matches.
+# ---------------------------------------------------------------------------
+COPY_BYTES = 1 << 28
+KERNEL_SOURCES = ["kernels.hip", "stencil.h", "kernel_util.h", "device_common.h", "kernels.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0911_2285_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_pass(workload):
+    """One eigBiCG solve (its BiCG matvec launches are the roofline kernel), then a
+    plain device copy of COPY_BYTES for the counter calibration."""
+    import torch
+
+    import synth
+    from paper_0911_2285_amd import ebicg as eb
+
+    W = WORKLOADS[workload]
+    dims = W["dims"]
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
+    op = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["nev"])
+    b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, 0))).to("cuda:0")
+    eb.eigbicg_solve(op, b, torch.zeros_like(b), nev=W["nev"], m=W["m"], tol=W["tol"])
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("[bench] pmc pass done")
+
+
+def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="bicg_matvec"):
+    import csv
+
+    def per_dispatch(path, counter, match):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Counter_Name"].startswith(counter) and match(r["Kernel_Name"])]
+        return sum(vals) / len(vals), len(vals)
+
+    def calibration(path, counter):
+        # the pass ends with three device-to-device copies of COPY_BYTES (the runtime's blit kernel)
+        rows = [r for r in csv.DictReader(open(path))
+                if r["Counter_Name"].startswith(counter) and "copyBuffer" in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        vals = [float(r["Counter_Value"]) for r in rows[-3:]]
+        return sum(vals) / len(vals)
+
+    is_kernel = lambda n: kernel + "(" in n
+    f_k, n_f = per_dispatch(fetch_csv, "FETCH_SIZE", is_kernel)
+    w_k, n_w = per_dispatch(write_csv, "WRITE_SIZE", is_kernel)
+    f_c = calibration(fetch_csv, "FETCH_SIZE")
+    w_c = calibration(write_csv, "WRITE_SIZE")
+    fetch_scale = COPY_BYTES / (f_c * 1024.0)
+    write_scale = COPY_BYTES / (w_c * 1024.0)
+    traffic = f_k * 1024.0 * fetch_scale + w_k * 1024.0 * write_scale
+    W = WORKLOADS[workload]
+    V = 1
+    for d in W["dims"]:
+        V *= d
+    out = {
+        "kernel": kernel, "class": cls, "workload": workload, "source_hash": kernel_source_hash(),
+        "dispatches": {"fetch": n_f, "write": n_w},
+        "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
+        "copy_calibration": {"bytes_read_and_written": COPY_BYTES, "fetch_kib": round(f_c, 1),
+                             "write_kib": round(w_c, 1), "fetch_scale": round(fetch_scale, 4),
+                             "write_scale": round(write_scale, 4)},
+        "traffic_bytes_per_launch": round(traffic),
+        "algorithmic_bytes_per_launch": KERNEL_UNITS[cls] * UNIT_BYTES_FP64 * V,
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass",
+            "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass",
+            "python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
+            "gpurun_out/pmc_write/run_counter_collection.csv",
+        ],
+    }
+    path = os.path.join(ROOT, "profiles", f"pmc_{cls}_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def measured_traffic(workload, cls):
+    """Traffic per launch from the committed counter summary, if the kernel sources
+    are unchanged since it was taken; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{cls}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,7 +313,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--no-large", action="store_true", help="skip the 24^3 x 64 multi-RHS / precision section")
+    ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
+        return
+    if args.pmc_pass:
+        pmc_pass(args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU path is design-only",
               file=sys.stderr)
@@ -275,7 +394,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, dom),
             "bytes_per_launch": bpl,
             "avg_launch_us": kernels[dom]["avg_us"],
         }
