@@ -25,77 +25,6 @@ namespace ebicg {
 
 namespace {
 
-
-template <int MU, int SG, typename R>
-__device__ __forceinline__ void recon_row(cx<R> (&acc)[12], int a, cx<R> t0, cx<R> t1) {
-  acc[a] = acc[a] + t0;
-  acc[3 + a] = acc[3 + a] + t1;
-  if constexpr (MU == 0) {
-    acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t1));
-    acc[9 + a] = acc[9 + a] + sgn<SG>(ci(t0));
-  } else if constexpr (MU == 1) {
-    acc[6 + a] = acc[6 + a] + sgn<SG>(t1);
-    acc[9 + a] = acc[9 + a] - sgn<SG>(t0);
-  } else if constexpr (MU == 2) {
-    acc[6 + a] = acc[6 + a] + sgn<SG>(ci(t0));
-    acc[9 + a] = acc[9 + a] - sgn<SG>(ci(t1));
-  } else {
-    acc[6 + a] = acc[6 + a] + sgn<SG>(t0);
-    acc[9 + a] = acc[9 + a] + sgn<SG>(t1);
-  }
-}
-
-// D p and D^+ ph hops of direction mu in one thread: every link row is
-// loaded once and applied to both half spinors (D uses 1 - gamma forward and
-// 1 + gamma backward; D^+ the opposite).
-template <int MU, typename S>
-__device__ __forceinline__ void pair_dir(cx<typename Store<S>::R> (&ad)[12], cx<typename Store<S>::R> (&aa)[12],
-                                         const S *__restrict__ p, const S *__restrict__ ph, const S *__restrict__ U,
-                                         int V, int s, int sf, int sb) {
-  using R = typename Store<S>::R;
-  cx<R> h1[6], h2[6];
-  load_project<MU, -1, S>(h1, p, V, sf);
-  load_project<MU, +1, S>(h2, ph, V, sf);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 0) * V + s);
-    const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 1) * V + s);
-    const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + a * 3 + 2) * V + s);
-    cx<R> t0 = u0 * h1[0], t1 = u0 * h1[3], q0 = u0 * h2[0], q1 = u0 * h2[3];
-    cfma(t0, u1, h1[1]);
-    cfma(t0, u2, h1[2]);
-    cfma(t1, u1, h1[4]);
-    cfma(t1, u2, h1[5]);
-    cfma(q0, u1, h2[1]);
-    cfma(q0, u2, h2[2]);
-    cfma(q1, u1, h2[4]);
-    cfma(q1, u2, h2[5]);
-    recon_row<MU, -1>(ad, a, t0, t1);
-    recon_row<MU, +1>(aa, a, q0, q1);
-  }
-  hop_fence();
-  load_project<MU, +1, S>(h1, p, V, sb);
-  load_project<MU, -1, S>(h2, ph, V, sb);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const cx<R> u0 = Store<S>::ld(U, size_t(MU * 9 + 0 + a) * V + sb);
-    const cx<R> u1 = Store<S>::ld(U, size_t(MU * 9 + 3 + a) * V + sb);
-    const cx<R> u2 = Store<S>::ld(U, size_t(MU * 9 + 6 + a) * V + sb);
-    cx<R> t0 = cmulc(u0, h1[0]), t1 = cmulc(u0, h1[3]), q0 = cmulc(u0, h2[0]), q1 = cmulc(u0, h2[3]);
-    cfmac(t0, u1, h1[1]);
-    cfmac(t0, u2, h1[2]);
-    cfmac(t1, u1, h1[4]);
-    cfmac(t1, u2, h1[5]);
-    cfmac(q0, u1, h2[1]);
-    cfmac(q0, u2, h2[2]);
-    cfmac(q1, u1, h2[4]);
-    cfmac(q1, u2, h2[5]);
-    recon_row<MU, +1>(ad, a, t0, t1);
-    recon_row<MU, -1>(aa, a, q0, q1);
-  }
-  hop_fence();
-}
-
 // ----------------------------------------------------------------------------
 // Layout kernels
 // ----------------------------------------------------------------------------
@@ -146,15 +75,23 @@ template <typename S, int SF>
 __global__ void __launch_bounds__(kBlock)
     k_dslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa) {
   using R = typename Store<S>::R;
+  __shared__ S tile[12 * kBlock];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const R k = R(kappa);
-  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
-    cx<R> acc[12];
-    hopping<SF, S>(acc, in, U, g, s);
+  const int ntiles = (g.V + kBlock - 1) / kBlock;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int s0 = T * kBlock, s = s0 + threadIdx.x;
+    __syncthreads();  // the previous tile's readers are done
+    stage_tile(tile, in, s0, g.V);
+    __syncthreads();
+    if (s < g.V) {
+      cx<R> acc[12];
+      hopping_t<SF, S>(acc, TileSrc<S>{in, tile, s0, g.V}, U, g, s);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      cx<R> v = Store<S>::ld(in, size_t(c) * g.V + s);
-      Store<S>::st(out, size_t(c) * g.V + s, v - k * acc[c]);
+      for (int c = 0; c < 12; ++c) {
+        const cx<R> v = Store<S>::ld(tile, size_t(c) * kBlock + threadIdx.x);
+        Store<S>::st(out, size_t(c) * g.V + s, v - k * acc[c]);
+      }
     }
   }
 }
@@ -163,16 +100,23 @@ __global__ void __launch_bounds__(kBlock)
 __global__ void __launch_bounds__(kBlock)
     k_residual(double2 *__restrict__ r, const double2 *__restrict__ b, const double2 *__restrict__ xin,
                const double2 *__restrict__ U, Geom g, double kappa, double *__restrict__ part) {
+  __shared__ double2 tile[12 * kBlock];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   double v[2] = {0.0, 0.0};
-  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
+  const int ntiles = (g.V + kBlock - 1) / kBlock;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int s0 = T * kBlock, s = s0 + threadIdx.x;
+    __syncthreads();
+    stage_tile(tile, xin, s0, g.V);
+    __syncthreads();
+    if (s >= g.V) continue;
     cx<double> acc[12];
-    hopping<-1, double2>(acc, xin, U, g, s);
+    hopping_t<-1, double2>(acc, TileSrc<double2>{xin, tile, s0, g.V}, U, g, s);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const size_t i = size_t(c) * g.V + s;
-      cx<double> xv = Store<double2>::ld(xin, i), bv = Store<double2>::ld(b, i);
-      cx<double> rv = bv - (xv - kappa * acc[c]);
+      const cx<double> xv = Store<double2>::ld(tile, size_t(c) * kBlock + threadIdx.x), bv = Store<double2>::ld(b, i);
+      const cx<double> rv = bv - (xv - kappa * acc[c]);
       Store<double2>::st(r, i, rv);
       v[0] += rv.x * rv.x + rv.y * rv.y;
       v[1] += bv.x * bv.x + bv.y * bv.y;
@@ -240,37 +184,44 @@ __global__ void __launch_bounds__(kBlock)
 // Ap = D p and Adp = D^+ phat in one pass over the lattice (each link loaded
 // once for both), with the partials of sigma = (phat, Ap): phat(x) is loaded
 // for the diagonal term of D^+ anyway.
+// Two LDS-staged passes per tile: D p with sigma = (phat, Ap), then D^+ phat.
 __global__ void __launch_bounds__(kBlock)
     k_bicg_matvec(double2 *__restrict__ Ap, double2 *__restrict__ Adp, const double2 *__restrict__ p,
                   const double2 *__restrict__ ph, const double2 *__restrict__ U, Geom g, double kappa, int j,
                   const KrylovState *S, double *__restrict__ part) {
   if (skip_iter(S, j)) return;
+  __shared__ double2 tile[12 * kBlock];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   double v[2] = {0.0, 0.0};
-  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
-  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
-    cx<double> ad[12], aa[12];
+  const int ntiles = (g.V + kBlock - 1) / kBlock;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int s0 = T * kBlock, s = s0 + threadIdx.x;
+    __syncthreads();
+    stage_tile(tile, p, s0, g.V);
+    __syncthreads();
+    if (s < g.V) {
+      cx<double> acc[12];
+      hopping_t<-1, double2>(acc, TileSrc<double2>{p, tile, s0, g.V}, U, g, s);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ad[c] = aa[c] = {0, 0};
-    const int x = s % g.lx, y = (s / sy) % g.ly, z = (s / sz) % g.lz, t = s / stt;
-    pair_dir<0, double2>(ad, aa, p, ph, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1,
-                         x == 0 ? s + (g.lx - 1) : s - 1);
-    pair_dir<1, double2>(ad, aa, p, ph, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
-                         y == 0 ? s + (g.ly - 1) * sy : s - sy);
-    pair_dir<2, double2>(ad, aa, p, ph, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
-                         z == 0 ? s + (g.lz - 1) * sz : s - sz);
-    pair_dir<3, double2>(ad, aa, p, ph, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
-                         t == 0 ? s + (g.lt - 1) * stt : s - stt);
+      for (int c = 0; c < 12; ++c) {
+        const size_t i = size_t(c) * g.V + s;
+        const cx<double> o = Store<double2>::ld(tile, size_t(c) * kBlock + threadIdx.x) - kappa * acc[c];
+        Store<double2>::st(Ap, i, o);
+        const cx<double> d = cmulc(Store<double2>::ld(ph, i), o);
+        v[0] += d.x;
+        v[1] += d.y;
+      }
+    }
+    __syncthreads();
+    stage_tile(tile, ph, s0, g.V);
+    __syncthreads();
+    if (s < g.V) {
+      cx<double> acc[12];
+      hopping_t<+1, double2>(acc, TileSrc<double2>{ph, tile, s0, g.V}, U, g, s);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const size_t i = size_t(c) * g.V + s;
-      const cx<double> phv = Store<double2>::ld(ph, i);
-      const cx<double> o = Store<double2>::ld(p, i) - kappa * ad[c];
-      Store<double2>::st(Ap, i, o);
-      Store<double2>::st(Adp, i, phv - kappa * aa[c]);
-      const cx<double> d = cmulc(phv, o);
-      v[0] += d.x;
-      v[1] += d.y;
+      for (int c = 0; c < 12; ++c)
+        Store<double2>::st(Adp, size_t(c) * g.V + s,
+                           Store<double2>::ld(tile, size_t(c) * kBlock + threadIdx.x) - kappa * acc[c]);
     }
   }
   block_partial<2, kBlock>(v, part, blockIdx.x);
@@ -483,18 +434,25 @@ __global__ void __launch_bounds__(kBlock)
              Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
   if (skip_iter(K, j)) return;
+  __shared__ S tile[12 * kBlock];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const R k = R(kappa);
   double v[2] = {0.0, 0.0};
-  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
+  const int ntiles = (g.V + kBlock - 1) / kBlock;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int s0 = T * kBlock, s = s0 + threadIdx.x;
+    __syncthreads();
+    stage_tile(tile, p, s0, g.V);
+    __syncthreads();
+    if (s >= g.V) continue;
     cx<R> acc[12];
-    hopping<-1, S>(acc, p, U, g, s);
-    const R k = R(kappa);
+    hopping_t<-1, S>(acc, TileSrc<S>{p, tile, s0, g.V}, U, g, s);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const size_t i = size_t(c) * g.V + s;
-      cx<R> o = Store<S>::ld(p, i) - k * acc[c];
+      const cx<R> o = Store<S>::ld(tile, size_t(c) * kBlock + threadIdx.x) - k * acc[c];
       Store<S>::st(vout, i, o);
-      cx<R> hh = Store<S>::ld(rhat, i);
+      const cx<R> hh = Store<S>::ld(rhat, i);
       v[0] += double(hh.x) * o.x + double(hh.y) * o.y;
       v[1] += double(hh.x) * o.y - double(hh.y) * o.x;
     }
@@ -535,17 +493,24 @@ __global__ void __launch_bounds__(kBlock)
              const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
   if (skip_iter(K, j)) return;
+  __shared__ S tile[12 * kBlock];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const R k = R(kappa);
   double v[3] = {0.0, 0.0, 0.0};
-  for (int s = lb * kBlock + threadIdx.x; s < g.V; s += gridDim.x * kBlock) {
+  const int ntiles = (g.V + kBlock - 1) / kBlock;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int s0 = T * kBlock, s = s0 + threadIdx.x;
+    __syncthreads();
+    stage_tile(tile, sv, s0, g.V);
+    __syncthreads();
+    if (s >= g.V) continue;
     cx<R> acc[12];
-    hopping<-1, S>(acc, sv, U, g, s);
-    const R k = R(kappa);
+    hopping_t<-1, S>(acc, TileSrc<S>{sv, tile, s0, g.V}, U, g, s);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const size_t i = size_t(c) * g.V + s;
-      cx<R> si = Store<S>::ld(sv, i);
-      cx<R> o = si - k * acc[c];
+      const cx<R> si = Store<S>::ld(tile, size_t(c) * kBlock + threadIdx.x);
+      const cx<R> o = si - k * acc[c];
       Store<S>::st(tout, i, o);
       v[0] += double(o.x) * si.x + double(o.y) * si.y;
       v[1] += double(o.x) * si.y - double(o.y) * si.x;

@@ -140,6 +140,90 @@ __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], con
                     t == 0 ? s + (g.lt - 1) * stt : s - stt);
 }
 
-// acc_sg += (spin reconstruction with sign SG of) t for output colour row a.
+// ---------------------------------------------------------------------------
+// LDS-staged form.  A block stages its tile of 256 consecutive sites of the
+// input field into LDS (component-major [12][256]) in one coalesced sweep and
+// takes every neighbour inside the tile from LDS; neighbours outside the tile
+// come from global memory, where the neighbouring blocks' own staging sweeps
+// have just brought them into L2.  Without staging, every hop of every
+// resident wave sweeps the whole per-XCD share of the field, which does not
+// fit in L2, and each neighbour read misses.
+// ---------------------------------------------------------------------------
+template <typename S>
+struct TileSrc {
+  const S *__restrict__ glob;
+  const S *lds;
+  int s0, V;
+  __device__ __forceinline__ cx<typename Store<S>::R> ld(int c, int sn) const {
+    const unsigned d = unsigned(sn - s0);
+    return d < unsigned(kBlock) ? Store<S>::ld(lds, size_t(c) * kBlock + d) : Store<S>::ld(glob, size_t(c) * V + sn);
+  }
+};
+
+// Stage sites [s0, s0 + kBlock) of `in` (those < V); the caller synchronises.
+template <typename S>
+__device__ __forceinline__ void stage_tile(S *lds, const S *__restrict__ in, int s0, int V) {
+  const int s = s0 + int(threadIdx.x);
+  if (s < V) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) lds[c * kBlock + threadIdx.x] = in[size_t(c) * V + s];
+  }
+}
+
+template <int MU, int SG, typename S>
+__device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6], const TileSrc<S> &src, int sn) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const auto p0 = src.ld(a, sn);
+    const auto p1 = src.ld(3 + a, sn);
+    const auto p2 = src.ld(6 + a, sn);
+    const auto p3 = src.ld(9 + a, sn);
+    if constexpr (MU == 0) {
+      h[a] = p0 - sgn<SG>(ci(p3));
+      h[3 + a] = p1 - sgn<SG>(ci(p2));
+    } else if constexpr (MU == 1) {
+      h[a] = p0 - sgn<SG>(p3);
+      h[3 + a] = p1 + sgn<SG>(p2);
+    } else if constexpr (MU == 2) {
+      h[a] = p0 - sgn<SG>(ci(p2));
+      h[3 + a] = p1 + sgn<SG>(ci(p3));
+    } else {
+      h[a] = p0 + sgn<SG>(p2);
+      h[3 + a] = p1 + sgn<SG>(p3);
+    }
+  }
+}
+
+template <int MU, int SF, typename S>
+__device__ __forceinline__ void hop_dir_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S> &src,
+                                          const S *__restrict__ U, int V, int s, int sf, int sb) {
+  using R = typename Store<S>::R;
+  cx<R> h[6];
+  load_project_t<MU, SF, S>(h, src, sf);
+  mult_accum<MU, SF, false, S>(acc, h, U, V, s);
+  hop_fence();
+  load_project_t<MU, -SF, S>(h, src, sb);
+  mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
+  hop_fence();
+}
+
+template <int SF, typename S>
+__device__ __forceinline__ void hopping_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S> &src,
+                                          const S *__restrict__ U, const Geom &g, int s) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
+  const int x = s % g.lx;
+  const int y = (s / sy) % g.ly;
+  const int z = (s / sz) % g.lz;
+  const int t = s / stt;
+  hop_dir_t<0, SF, S>(acc, src, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
+  hop_dir_t<1, SF, S>(acc, src, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
+                      y == 0 ? s + (g.ly - 1) * sy : s - sy);
+  hop_dir_t<2, SF, S>(acc, src, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
+                      z == 0 ? s + (g.lz - 1) * sz : s - sz);
+  hop_dir_t<3, SF, S>(acc, src, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
+                      t == 0 ? s + (g.lt - 1) * stt : s - stt);
+}
 
 }  // namespace ebicg
