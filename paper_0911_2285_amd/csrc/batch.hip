@@ -38,21 +38,47 @@ __device__ __forceinline__ bool col_active(const KrylovState *K, int col, int j)
   return !(K[col].stopped && j > K[col].stop_at);
 }
 
+// LDS staging (stencil.h) pays when a tile holds many sites or the entries
+// are small: measured on MI355X it helps for one column at every precision
+// and for BF16 at every batch size, and slows FP64/FP32 batches (a tile of
+// 256 / KC sites leaves most neighbours outside it).
+template <typename S, int KC>
+constexpr bool kStage = KC == 1 || std::is_same<S, bf16c>::value;
+
 template <typename S, int KC, int SF>
 __global__ void __launch_bounds__(kBlock)
     k_bdslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa) {
   using R = typename Store<S>::R;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const R k = R(kappa);
-  const size_t n = size_t(g.V) * KC;
-  for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
-    const int s = int(u / KC), col = int(u % KC);
-    cx<R> acc[12];
-    hopping<SF, S, KC>(acc, in + col, U, g, s);
+  if constexpr (kStage<S, KC>) {
+    __shared__ S tile[12 * kBlock];
+    constexpr int spt = kBlock / KC;  // sites per tile
+    const int ntiles = (g.V + spt - 1) / spt, col = threadIdx.x % KC;
+    for (int T = lb; T < ntiles; T += gridDim.x) {
+      const int s0 = T * spt, s = s0 + threadIdx.x / KC;
+      __syncthreads();
+      stage_tile<S, KC>(tile, in, s0, g.V);
+      __syncthreads();
+      if (s >= g.V) continue;
+      cx<R> acc[12];
+      hopping_t<SF, S>(acc, TileSrc<S, KC>{in + col, tile + col, s0, g.V}, U, g, s);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const size_t i = (size_t(c) * g.V + s) * KC + col;
-      Store<S>::st(out, i, Store<S>::ld(in, i) - k * acc[c]);
+      for (int c = 0; c < 12; ++c)
+        Store<S>::st(out, (size_t(c) * g.V + s) * KC + col,
+                     Store<S>::ld(tile, size_t(c) * kBlock + threadIdx.x) - k * acc[c]);
+    }
+  } else {
+    const size_t n = size_t(g.V) * KC;
+    for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+      const int s = int(u / KC), col = int(u % KC);
+      cx<R> acc[12];
+      hopping<SF, S, KC>(acc, in + col, U, g, s);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const size_t i = (size_t(c) * g.V + s) * KC + col;
+        Store<S>::st(out, i, Store<S>::ld(in, i) - k * acc[c]);
+      }
     }
   }
 }
@@ -108,22 +134,39 @@ __global__ void __launch_bounds__(kBlock)
   const bool act = col_active(K, col, j);
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const R k = R(kappa);
-  const size_t n = size_t(g.V) * KC;
   double d[2] = {0.0, 0.0};
-  if (act) {
+  auto epilogue = [&](int s, const cx<R> (&acc)[12], auto center) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const size_t i = (size_t(c) * g.V + s) * KC + col;
+      const cx<R> o = center(c, i) - k * acc[c];
+      Store<S>::st(vout, i, o);
+      const cx<R> hh = Store<S>::ld(rhat, i);
+      d[0] += double(hh.x) * o.x + double(hh.y) * o.y;
+      d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
+    }
+  };
+  if constexpr (kStage<S, KC>) {
+    __shared__ S tile[12 * kBlock];
+    constexpr int spt = kBlock / KC;
+    const int ntiles = (g.V + spt - 1) / spt;
+    for (int T = lb; T < ntiles; T += gridDim.x) {
+      const int s0 = T * spt, s = s0 + threadIdx.x / KC;
+      __syncthreads();
+      stage_tile<S, KC>(tile, p, s0, g.V);
+      __syncthreads();
+      if (!act || s >= g.V) continue;
+      cx<R> acc[12];
+      hopping_t<-1, S>(acc, TileSrc<S, KC>{p + col, tile + col, s0, g.V}, U, g, s);
+      epilogue(s, acc, [&](int c, size_t) { return Store<S>::ld(tile, size_t(c) * kBlock + threadIdx.x); });
+    }
+  } else if (act) {
+    const size_t n = size_t(g.V) * KC;
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
       const int s = int(u / KC);
       cx<R> acc[12];
       hopping<-1, S, KC>(acc, p + col, U, g, s);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t(c) * g.V + s) * KC + col;
-        const cx<R> o = Store<S>::ld(p, i) - k * acc[c];
-        Store<S>::st(vout, i, o);
-        const cx<R> hh = Store<S>::ld(rhat, i);
-        d[0] += double(hh.x) * o.x + double(hh.y) * o.y;
-        d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
-      }
+      epilogue(s, acc, [&](int, size_t i) { return Store<S>::ld(p, i); });
     }
   }
   block_partial_cols<2, KC, kBlock>(d, part, blockIdx.x);
@@ -174,23 +217,40 @@ __global__ void __launch_bounds__(kBlock)
   const bool act = col_active(K, col, j);
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const R k = R(kappa);
-  const size_t n = size_t(g.V) * KC;
   double d[3] = {0.0, 0.0, 0.0};
-  if (act) {
+  auto epilogue = [&](int s, const cx<R> (&acc)[12], auto center) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const size_t i = (size_t(c) * g.V + s) * KC + col;
+      const cx<R> si = center(c, i);
+      const cx<R> o = si - k * acc[c];
+      Store<S>::st(tout, i, o);
+      d[0] += double(o.x) * si.x + double(o.y) * si.y;
+      d[1] += double(o.x) * si.y - double(o.y) * si.x;
+      d[2] += double(o.x) * o.x + double(o.y) * o.y;
+    }
+  };
+  if constexpr (kStage<S, KC>) {
+    __shared__ S tile[12 * kBlock];
+    constexpr int spt = kBlock / KC;
+    const int ntiles = (g.V + spt - 1) / spt;
+    for (int T = lb; T < ntiles; T += gridDim.x) {
+      const int s0 = T * spt, s = s0 + threadIdx.x / KC;
+      __syncthreads();
+      stage_tile<S, KC>(tile, sv, s0, g.V);
+      __syncthreads();
+      if (!act || s >= g.V) continue;
+      cx<R> acc[12];
+      hopping_t<-1, S>(acc, TileSrc<S, KC>{sv + col, tile + col, s0, g.V}, U, g, s);
+      epilogue(s, acc, [&](int c, size_t) { return Store<S>::ld(tile, size_t(c) * kBlock + threadIdx.x); });
+    }
+  } else if (act) {
+    const size_t n = size_t(g.V) * KC;
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
       const int s = int(u / KC);
       cx<R> acc[12];
       hopping<-1, S, KC>(acc, sv + col, U, g, s);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t(c) * g.V + s) * KC + col;
-        const cx<R> si = Store<S>::ld(sv, i);
-        const cx<R> o = si - k * acc[c];
-        Store<S>::st(tout, i, o);
-        d[0] += double(o.x) * si.x + double(o.y) * si.y;
-        d[1] += double(o.x) * si.y - double(o.y) * si.x;
-        d[2] += double(o.x) * o.x + double(o.y) * o.y;
-      }
+      epilogue(s, acc, [&](int, size_t i) { return Store<S>::ld(sv, i); });
     }
   }
   block_partial_cols<3, KC, kBlock>(d, part, blockIdx.x);

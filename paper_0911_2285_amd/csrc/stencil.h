@@ -149,29 +149,34 @@ __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], con
 // resident wave sweeps the whole per-XCD share of the field, which does not
 // fit in L2, and each neighbour read misses.
 // ---------------------------------------------------------------------------
-template <typename S>
+// With KC interleaved right-hand sides (batch layout), a tile is kBlock / KC
+// sites times KC columns; glob and lds point at this thread's column.
+template <typename S, int KC = 1>
 struct TileSrc {
   const S *__restrict__ glob;
   const S *lds;
   int s0, V;
   __device__ __forceinline__ cx<typename Store<S>::R> ld(int c, int sn) const {
     const unsigned d = unsigned(sn - s0);
-    return d < unsigned(kBlock) ? Store<S>::ld(lds, size_t(c) * kBlock + d) : Store<S>::ld(glob, size_t(c) * V + sn);
+    return d < unsigned(kBlock / KC) ? Store<S>::ld(lds, size_t(c) * kBlock + d * KC)
+                                     : Store<S>::ld(glob, (size_t(c) * V + sn) * KC);
   }
 };
 
-// Stage sites [s0, s0 + kBlock) of `in` (those < V); the caller synchronises.
-template <typename S>
+// Stage sites [s0, s0 + kBlock / KC) of `in` (all KC columns; sites < V); the
+// caller synchronises.  Entry (c, site, col) goes to lds[c kBlock + (site - s0) KC + col].
+template <typename S, int KC = 1>
 __device__ __forceinline__ void stage_tile(S *lds, const S *__restrict__ in, int s0, int V) {
-  const int s = s0 + int(threadIdx.x);
+  const int s = s0 + int(threadIdx.x) / KC;
   if (s < V) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) lds[c * kBlock + threadIdx.x] = in[size_t(c) * V + s];
+    for (int c = 0; c < 12; ++c)
+      lds[c * kBlock + threadIdx.x] = in[(size_t(c) * V + s0) * KC + threadIdx.x];
   }
 }
 
-template <int MU, int SG, typename S>
-__device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6], const TileSrc<S> &src, int sn) {
+template <int MU, int SG, typename S, int KC>
+__device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6], const TileSrc<S, KC> &src, int sn) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const auto p0 = src.ld(a, sn);
@@ -194,21 +199,21 @@ __device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6],
   }
 }
 
-template <int MU, int SF, typename S>
-__device__ __forceinline__ void hop_dir_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S> &src,
+template <int MU, int SF, typename S, int KC>
+__device__ __forceinline__ void hop_dir_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S, KC> &src,
                                           const S *__restrict__ U, int V, int s, int sf, int sb) {
   using R = typename Store<S>::R;
   cx<R> h[6];
-  load_project_t<MU, SF, S>(h, src, sf);
+  load_project_t<MU, SF, S, KC>(h, src, sf);
   mult_accum<MU, SF, false, S>(acc, h, U, V, s);
   hop_fence();
-  load_project_t<MU, -SF, S>(h, src, sb);
+  load_project_t<MU, -SF, S, KC>(h, src, sb);
   mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
   hop_fence();
 }
 
-template <int SF, typename S>
-__device__ __forceinline__ void hopping_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S> &src,
+template <int SF, typename S, int KC>
+__device__ __forceinline__ void hopping_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S, KC> &src,
                                           const S *__restrict__ U, const Geom &g, int s) {
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
@@ -217,12 +222,12 @@ __device__ __forceinline__ void hopping_t(cx<typename Store<S>::R> (&acc)[12], c
   const int y = (s / sy) % g.ly;
   const int z = (s / sz) % g.lz;
   const int t = s / stt;
-  hop_dir_t<0, SF, S>(acc, src, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
-  hop_dir_t<1, SF, S>(acc, src, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
+  hop_dir_t<0, SF, S, KC>(acc, src, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
+  hop_dir_t<1, SF, S, KC>(acc, src, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
                       y == 0 ? s + (g.ly - 1) * sy : s - sy);
-  hop_dir_t<2, SF, S>(acc, src, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
+  hop_dir_t<2, SF, S, KC>(acc, src, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
                       z == 0 ? s + (g.lz - 1) * sz : s - sz);
-  hop_dir_t<3, SF, S>(acc, src, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
+  hop_dir_t<3, SF, S, KC>(acc, src, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
                       t == 0 ? s + (g.lt - 1) * stt : s - stt);
 }
 
