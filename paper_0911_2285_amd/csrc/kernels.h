@@ -126,17 +126,17 @@ void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const dou
 void launch_ts_update(double2 *Y, size_t ldy, int ny, const double2 *X, size_t ldx, int nx, const double2 *C,
                       double sgn, size_t N, hipStream_t st);
 
-// Matrix-core forms (tsmm.hip).  gram: out = X^+ Y for nx <= 128 (any ny);
+// Tall-skinny forms (tsmm.hip).  gram (matrix cores): out = X^+ Y for nx <= 128 (any ny);
 // part: scratch for per-block records, part_cap doubles.
 void launch_gram_mfma(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny,
                       size_t N, double *part, size_t part_cap, hipStream_t st);
 // combine: out_k (+)= sgn sum_c in_c C[c + k*nin], column c at in_base + in_slots.idx[c]*ldi and
 // out_k at out_base + out_slots.idx[k]*ldo; with g, dots[k] = g^+ out_k (conj_out 0) or out_k^+ g (1).
 // Skipped when S && S->stopped && jtag > S->stop_at.
-void launch_combine_mfma(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
-                         const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
-                         const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
-                         size_t part_cap, hipStream_t st);
+void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
+                    const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
+                    size_t part_cap, hipStream_t st);
 
 // ---- BLAS-1 (FP64) ---------------------------------------------------------------
 void launch_copy_f64(double2 *dst, const double2 *src, size_t n, hipStream_t st);

@@ -697,7 +697,7 @@ void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const do
 void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *in_base, const SlotList &in_slots,
                    const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
                    const KrylovState *S, const RedScratch &rs, hipStream_t st) {
-  launch_combine_mfma(out_base, out_slots, N, in_base, in_slots, N, C, 1.0, false, N, g, conj_out, dots, jtag, S,
+  launch_combine(out_base, out_slots, N, in_base, in_slots, N, C, 1.0, false, N, g, conj_out, dots, jtag, S,
                       region(rs, RG_GEN), kMaxPartials - size_t(RG_GEN) * kRegion, st);
 }
 
@@ -741,7 +741,7 @@ void launch_ts_update(double2 *Y, size_t ldy, int ny, const double2 *X, size_t l
   for (int a = 0; a < nx; ++a) in.idx[a] = a;
   out.n = ny;
   for (int b = 0; b < ny; ++b) out.idx[b] = b;
-  launch_combine_mfma(Y, out, ldy, X, in, ldx, C, sgn, true, N, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, st);
+  launch_combine(Y, out, ldy, X, in, ldx, C, sgn, true, N, nullptr, 0, nullptr, 0, nullptr, nullptr, 0, st);
 }
 
 void launch_copy_f64(double2 *d, const double2 *s, size_t n, hipStream_t st) {

@@ -1,7 +1,7 @@
-// Tall-skinny complex products on the FP64 matrix cores (gfx950 MFMA).
+// Tall-skinny complex products.
 //
-//   gram:    out = X^+ Y              X: N x nx, Y: N x ny, out: nx x ny
-//   combine: out = [out +] In C       In: N x nin, C: nin x nout, out: N x nout
+//   gram:    out = X^+ Y              X: N x nx, Y: N x ny, out: nx x ny  (FP64 matrix cores)
+//   combine: out = [out +] In C       In: N x nin, C: nin x nout, out: N x nout  (FP64 VALU)
 //
 // N is the length of a spinor (12 V complex entries) and the other sizes are
 // at most 128, so both products are long contractions into small tiles or
@@ -147,158 +147,103 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// combine: out_k = [out_k +] sum_c in_c C[c + k nin] over the output columns
-// 16 TB blockIdx.y .. + 16 TB.  A wave owns RT row tiles of 16 entries and
-// TB column tiles; lane (r, q) reads entry e0 + 16 t + r of input column
-// c0 + q (64 lanes: four 256-byte runs) and coefficient C[c0 + q][k0 + 16 u + r]
-// from LDS.  With g: partial dots g^+ out_k (conj_out = 0) or out_k^+ g
-// (conj_out = 1), one record of 32 TB doubles per block.
+// combine: out_k = [out_k +] sgn sum_c in_c C[c + k nin] for the NT output
+// columns k0 = NT blockIdx.y .. of this block, one entry per thread.  The
+// coefficient C[c, k] is the same for every lane, so it reaches the FMAs
+// through scalar loads and no tile is padded: on this chip the FP64 matrix
+// cores sustain about half the FP64 vector rate on these shapes, and padding
+// 20 output columns to a 32-wide tile wastes another third.  With g: partial
+// dots g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1), element-major
+// records part[(blockIdx.y 2NT + e) gridDim.x + blockIdx.x].
 // ---------------------------------------------------------------------------
-template <int RT, int TB, bool ADD>
+template <int NT, bool ADD>
 __global__ void __launch_bounds__(kBlock)
-    k_combine_mfma(double2 *out_base, SlotList out_slots, size_t ldo, const double2 *in_base, SlotList in_slots,
-                   size_t ldi, const double2 *__restrict__ C, double sgn, size_t N, const double2 *__restrict__ g,
-                   int conj_out, int jtag, const KrylovState *S, double *__restrict__ part) {
+    k_combine(double2 *out_base, SlotList out_slots, size_t ldo, const double2 *in_base, SlotList in_slots,
+              size_t ldi, const double2 *__restrict__ C, double sgn, size_t N, int jtag, const KrylovState *S) {
   if (S && S->stopped && jtag > S->stop_at) return;
-  extern __shared__ double2 sB[];  // [nin padded to 4][16 TB]
-  __shared__ double sd[kBlock / kWave][2 * kTile * TB];
-  constexpr int KW = kTile * TB;
   const int nin = in_slots.n, nout = out_slots.n;
-  const int nin4 = (nin + 3) & ~3;
-  const int k0 = blockIdx.y * KW;
-  for (int e = threadIdx.x; e < nin4 * KW; e += kBlock) {
-    const int c = e / KW, kk = e % KW;
-    double2 v = make_double2(0.0, 0.0);
-    if (c < nin && k0 + kk < nout) {
-      const double2 cc = C[c + size_t(k0 + kk) * nin];
-      v = make_double2(sgn * cc.x, sgn * cc.y);
-    }
-    sB[e] = v;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int r = lane % kTile, q = lane / kTile;
-  constexpr int ENT = RT * kTile;  // entries per wave tile
-  const size_t ntile = (N + ENT - 1) / ENT;
-  double dr[TB], di[TB];
+  const int k0 = blockIdx.y * NT;
+  const int nk = nout - k0 < NT ? nout - k0 : NT;
+  const double2 *__restrict__ Ck = C + size_t(k0) * nin;  // coefficient (c, k0 + k) at Ck[c + k nin]
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
+    cx<double> acc[NT];
 #pragma unroll
-  for (int u = 0; u < TB; ++u) dr[u] = di[u] = 0.0;
+    for (int k = 0; k < NT; ++k) acc[k] = {0.0, 0.0};
+    int c = 0;
+    for (; c + 2 <= nin; c += 2) {
+      const double2 v0 = in_base[size_t(in_slots.idx[c]) * ldi + i];
+      const double2 v1 = in_base[size_t(in_slots.idx[c + 1]) * ldi + i];
+#pragma unroll
+      for (int k = 0; k < NT; ++k)
+        if (k < nk) {
+          const double2 w0 = Ck[c + size_t(k) * nin], w1 = Ck[c + 1 + size_t(k) * nin];
+          cfma(acc[k], cx<double>{v0.x, v0.y}, cx<double>{w0.x, w0.y});
+          cfma(acc[k], cx<double>{v1.x, v1.y}, cx<double>{w1.x, w1.y});
+        }
+    }
+    if (c < nin) {
+      const double2 v0 = in_base[size_t(in_slots.idx[c]) * ldi + i];
+#pragma unroll
+      for (int k = 0; k < NT; ++k)
+        if (k < nk) {
+          const double2 w0 = Ck[c + size_t(k) * nin];
+          cfma(acc[k], cx<double>{v0.x, v0.y}, cx<double>{w0.x, w0.y});
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      if (k >= nk) continue;
+      double2 *oc = out_base + size_t(out_slots.idx[k0 + k]) * ldo;
+      double2 o = make_double2(sgn * acc[k].x, sgn * acc[k].y);
+      if (ADD) {
+        const double2 old = oc[i];
+        o = make_double2(old.x + o.x, old.y + o.y);
+      }
+      oc[i] = o;
+    }
+  }
+}
 
-  for (size_t tile = size_t(blockIdx.x) * (kBlock / kWave) + w; tile < ntile;
-       tile += size_t(gridDim.x) * (kBlock / kWave)) {
-    const size_t e0 = tile * ENT;
-    dx4 re[RT][TB], im[RT][TB];
+// Partial dots of g with NT output columns of a rotation (column group
+// blockIdx.y): g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1); records
+// element-major, part[(blockIdx.y 2NT + e) gridDim.x + blockIdx.x].
+template <int NT>
+__global__ void __launch_bounds__(kBlock)
+    k_slot_dots(const double2 *base, SlotList slots, size_t ld, const double2 *__restrict__ g, size_t N, int conj_out,
+                int jtag, const KrylovState *S, double *__restrict__ part) {
+  if (S && S->stopped && jtag > S->stop_at) return;
+  const int k0 = blockIdx.y * NT;
+  const int nk = slots.n - k0 < NT ? slots.n - k0 : NT;
+  double dv[2 * NT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+  for (int e = 0; e < 2 * NT; ++e) dv[e] = 0.0;
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
+    const double2 gv = g[i];
 #pragma unroll
-      for (int u = 0; u < TB; ++u) re[t][u] = im[t][u] = dx4{0.0, 0.0, 0.0, 0.0};
-    // groups of CS k-steps: all loads of a group are issued before its MFMAs
-    constexpr int CS = 4;
-    for (int cg = 0; cg < nin4; cg += 4 * CS) {
-      double2 av[CS][RT];
-#pragma unroll
-      for (int s = 0; s < CS; ++s) {
-        const int c = cg + 4 * s + q;
-        const double2 *col = in_base + size_t(c < nin ? in_slots.idx[c] : 0) * ldi;
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const size_t i = e0 + t * kTile + r;
-          av[s][t] = (c < nin && i < N) ? col[i] : make_double2(0.0, 0.0);
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < CS; ++s) {
-        const int c = cg + 4 * s + q;
-        if (cg + 4 * s >= nin4) break;
-        double2 bv[TB];
-#pragma unroll
-        for (int u = 0; u < TB; ++u) bv[u] = sB[c * KW + u * kTile + r];
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int u = 0; u < TB; ++u) {
-            re[t][u] = mfma16(av[s][t].x, bv[u].x, re[t][u]);
-            im[t][u] = mfma16(av[s][t].x, bv[u].y, im[t][u]);
-            re[t][u] = mfma16(av[s][t].y, -bv[u].y, re[t][u]);
-            im[t][u] = mfma16(av[s][t].y, bv[u].x, im[t][u]);
-          }
-      }
-    }
-    // lane holds entries e0 + 16 t + q + 4 v of output column k0 + 16 u + r
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      double2 gv[4];
-      if (g) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const size_t i = e0 + t * kTile + q + 4 * v;
-          gv[v] = i < N ? g[i] : make_double2(0.0, 0.0);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < TB; ++u) {
-        const int k = k0 + u * kTile + r;
-        if (k >= nout) continue;
-        double2 *oc = out_base + size_t(out_slots.idx[k]) * ldo;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const size_t i = e0 + t * kTile + q + 4 * v;
-          if (i >= N) continue;
-          double2 o = make_double2(re[t][u][v], im[t][u][v]);
-          if (ADD) {
-            const double2 old = oc[i];
-            o = make_double2(old.x + o.x, old.y + o.y);
-          }
-          oc[i] = o;
-          if (g) {
-            // conj(g) o, or conj(o) g
-            const double gx = gv[v].x, gy = gv[v].y;
-            if (conj_out) {
-              dr[u] += o.x * gx + o.y * gy;
-              di[u] += o.x * gy - o.y * gx;
-            } else {
-              dr[u] += gx * o.x + gy * o.y;
-              di[u] += gx * o.y - gy * o.x;
-            }
-          }
-        }
+    for (int k = 0; k < NT; ++k) {
+      if (k >= nk) continue;
+      const double2 o = base[size_t(slots.idx[k0 + k]) * ld + i];
+      if (conj_out) {  // conj(o) g
+        dv[2 * k] += o.x * gv.x + o.y * gv.y;
+        dv[2 * k + 1] += o.x * gv.y - o.y * gv.x;
+      } else {  // conj(g) o
+        dv[2 * k] += gv.x * o.x + gv.y * o.y;
+        dv[2 * k + 1] += gv.x * o.y - gv.y * o.x;
       }
     }
   }
-  if (!g) return;
-  // sum over the four lanes of a column (q), then over the block's waves
-#pragma unroll
-  for (int u = 0; u < TB; ++u) {
-    dr[u] += __shfl_xor(dr[u], 16, kWave);
-    di[u] += __shfl_xor(di[u], 16, kWave);
-    dr[u] += __shfl_xor(dr[u], 32, kWave);
-    di[u] += __shfl_xor(di[u], 32, kWave);
-  }
-  if (q == 0) {
-#pragma unroll
-    for (int u = 0; u < TB; ++u) {
-      sd[w][2 * (u * kTile + r)] = dr[u];
-      sd[w][2 * (u * kTile + r) + 1] = di[u];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * KW) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < kBlock / kWave; ++k) s += sd[k][threadIdx.x];
-    // element-major records: element e of column group y at part[(y 2KW + e) nblk + block]
-    part[(size_t(blockIdx.y) * 2 * KW + threadIdx.x) * gridDim.x + blockIdx.x] = s;
-  }
+  block_sum<2 * NT, kBlock>(dv);
+  if (threadIdx.x == 0)
+    for (int e = 0; e < 2 * NT; ++e) part[(size_t(blockIdx.y) * 2 * NT + e) * gridDim.x + blockIdx.x] = dv[e];
 }
 
 // One block per record element (blockIdx.x = group * 2KW + e): thread t sums
 // the blocks t, t + 256, ... and the block adds the 256 sums in a fixed tree.
-template <int TB>
+template <int KW>
 __global__ void __launch_bounds__(kBlock)
     k_combine_dots(const double *__restrict__ part, int nblk, int nout, double2 *dots, int jtag,
                    const KrylovState *S) {
   if (S && S->stopped && jtag > S->stop_at) return;
-  constexpr int KW = kTile * TB;
   const double *rec = part + size_t(blockIdx.x) * nblk;
   double v[1] = {0.0};
   for (int k = threadIdx.x; k < nblk; k += kBlock) v[0] += rec[k];
@@ -342,42 +287,49 @@ void launch_gram_mfma(double2 *out, const double2 *X, size_t ldx, int nx, const 
   EB_LAUNCH(k_gram_finish, dim3(TA * TB, kTile), dim3(kBlock), 0, st, out, part, int(nb), TA, nx, ny);
 }
 
-void launch_combine_mfma(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
-                         const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
-                         const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
-                         size_t part_cap, hipStream_t st) {
+void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
+                    const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
+                    size_t part_cap, hipStream_t st) {
   const int nin = in_slots.n, nout = out_slots.n;
   if (nin < 1 || nout < 1 || N == 0) return;
-  const int nin4 = (nin + 3) & ~3;
-  // two column tiles per wave when the coefficient block fits in 48 KB of LDS
-  const bool two = nout > kTile && size_t(nin4) * 2 * kTile * sizeof(double2) <= 48 * 1024;
-  auto go = [&](auto rt_tag, auto tb_tag) {
-    constexpr int RT = decltype(rt_tag)::value, TB = decltype(tb_tag)::value;
-    constexpr int KW = kTile * TB;
-    const int groups = (nout + KW - 1) / KW;
-    const size_t ntile = (N + RT * kTile - 1) / (RT * kTile);
-    size_t nb = (ntile + 3) / 4;
-    size_t cap = (2048 + groups - 1) / groups;
-    if (g) {
-      const size_t by_space = part_cap / (size_t(groups) * 2 * KW);
-      cap = cap < by_space ? cap : by_space;
-    }
+  auto go = [&](auto nt_tag) {
+    constexpr int NT = decltype(nt_tag)::value;
+    const int groups = (nout + NT - 1) / NT;
+    size_t nb = (N + kBlock - 1) / kBlock;
+    const size_t cap = (4096 + groups - 1) / groups;
     nb = nb < cap ? nb : cap;
-    if (nb < 1) nb = 1;
     const dim3 grid = dim3(unsigned(nb), unsigned(groups));
-    const size_t sh = size_t(nin4) * KW * sizeof(double2);
     if (add)
-      EB_LAUNCH((k_combine_mfma<RT, TB, true>), grid, dim3(kBlock), sh, st, out_base, out_slots, ldo, in_base,
-                in_slots, ldi, C, sgn, N, g, conj_out, jtag, S, part);
+      EB_LAUNCH((k_combine<NT, true>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots, ldi, C,
+                sgn, N, jtag, S);
     else
-      EB_LAUNCH((k_combine_mfma<RT, TB, false>), grid, dim3(kBlock), sh, st, out_base, out_slots, ldo, in_base,
-                in_slots, ldi, C, sgn, N, g, conj_out, jtag, S, part);
-    if (g) EB_LAUNCH(k_combine_dots<TB>, dim3(groups * 2 * KW), dim3(kBlock), 0, st, part, int(nb), nout, dots, jtag, S);
+      EB_LAUNCH((k_combine<NT, false>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots, ldi,
+                C, sgn, N, jtag, S);
+    if (g) {
+      // dots of the fresh outputs with g, a light second pass (nout + 1 columns)
+      size_t nd = (N + kBlock - 1) / kBlock;
+      size_t dcap = part_cap / (size_t(groups) * 2 * NT);
+      dcap = dcap < 1024 ? dcap : 1024;
+      nd = nd < dcap ? nd : dcap;
+      if (nd < 1) nd = 1;
+      EB_LAUNCH(k_slot_dots<NT>, dim3(unsigned(nd), unsigned(groups)), dim3(kBlock), 0, st, out_base, out_slots, ldo,
+                g, N, conj_out, jtag, S, part);
+      EB_LAUNCH(k_combine_dots<NT>, dim3(groups * 2 * NT), dim3(kBlock), 0, st, part, int(nd), nout, dots, jtag, S);
+    }
   };
-  if (two)
-    go(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+  if (nout <= 4)
+    go(std::integral_constant<int, 4>{});
+  else if (nout <= 8)
+    go(std::integral_constant<int, 8>{});
+  else if (nout <= 12)
+    go(std::integral_constant<int, 12>{});
+  else if (nout <= 16)
+    go(std::integral_constant<int, 16>{});
+  else if (nout <= 20)
+    go(std::integral_constant<int, 20>{});
   else
-    go(std::integral_constant<int, 4>{}, std::integral_constant<int, 1>{});
+    go(std::integral_constant<int, 24>{});
 }
 
 }  // namespace ebicg
