@@ -182,6 +182,10 @@ enum {
   EB_K_COUNT
 };
 eb_status eb_timing_enable(eb_op *op, int32_t enable);
+/* Classes recorded while timing is enabled: bit k for class k (default: all).
+ * Each recorded launch costs two event records on the host, which slows
+ * solves made of short kernels; select only the classes you need. */
+eb_status eb_timing_classes(eb_op *op, uint32_t mask);
 eb_status eb_timing_read(eb_op *op, int32_t kclass, int64_t *launches, double *total_ms);
 
 /* Message of the last non-OK status on this thread (empty if none). */

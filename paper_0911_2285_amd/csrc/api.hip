@@ -143,8 +143,9 @@ struct eb_op {
   double batch_ms[3][kMaxBatch + 1] = {};
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::map<std::string, DevBuf> bufs;
-  // kernel timing (eb_timing_enable)
+  // kernel timing (eb_timing_enable, eb_timing_classes)
   bool timing = false;
+  uint32_t timing_mask = ~0u;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   struct TimedLaunch {
@@ -240,7 +241,7 @@ void set_device(eb_op *op) { HIPCHK(hipSetDevice(op->device)); }
 // Launch through `f`, bracketed by timing events when the op records kernel times.
 template <typename F>
 void timed(eb_op *op, int cls, hipStream_t s, F &&f) {
-  if (!op->timing) {
+  if (!op->timing || !((op->timing_mask >> cls) & 1u)) {
     f();
     return;
   }
@@ -1684,6 +1685,13 @@ eb_status eb_timing_enable(eb_op *op, int32_t enable) {
       op->t_ms[k] = 0;
     }
     op->timing = enable != 0;
+  });
+}
+
+eb_status eb_timing_classes(eb_op *op, uint32_t mask) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    op->timing_mask = mask;
   });
 }
 

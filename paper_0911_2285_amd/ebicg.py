@@ -100,6 +100,7 @@ _SIGNATURES = [
     ("eb_defl_reset", ctypes.c_int, [_P]),
     ("eb_small_eig", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
     ("eb_timing_enable", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("eb_timing_classes", ctypes.c_int, [_P, ctypes.c_uint32]),
     ("eb_timing_read", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_double)]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -311,6 +312,12 @@ def defl_reset(op):
 def timing_enable(op, enable=True):
     """Start (and reset) or stop per-kernel HIP-event timing inside the library's solves."""
     _check(lib().eb_timing_enable(op.handle, int(bool(enable))))
+
+
+def timing_classes(op, names=None):
+    """Record only these kernel classes while timing is enabled (None: all)."""
+    mask = 0xFFFFFFFF if names is None else sum(1 << KERNEL_CLASSES.index(n) for n in names)
+    _check(lib().eb_timing_classes(op.handle, mask))
 
 
 def timing_read(op):
