@@ -117,6 +117,69 @@ def test_dslash_full_size_sampled(gpu_lib):
         assert err <= 1e-12, err
 
 
+@pytest.fixture(scope="module")
+def lattice_24x64(gpu_lib):
+    """24^3 x 64 (the precision / batching lattice: fields beyond the Infinity Cache)."""
+    dims, kappa = (24, 24, 24, 64), 0.123
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(2))
+    op = gpu_lib.op_create(U, kappa, dims)
+    return dims, kappa, U, op
+
+
+def _sample_sites(dims, n=48, seed=0):
+    V = synth.volume(dims)
+    plane = dims[0] * dims[1] * dims[2]
+    rng = np.random.default_rng(seed)
+    # corners of the lattice and of the t boundary, tile boundaries, then random sites
+    fixed = [0, dims[0] - 1, plane - 1, V - 1, V - plane, 255, 256, 511]
+    return np.concatenate([fixed, rng.integers(0, V, n)])
+
+
+def test_dslash_24x64_sampled(gpu_lib, lattice_24x64):
+    """FP64 D and D^+ on 24^3 x 64 at sampled sites against the per-site oracle (1e-12)."""
+    import torch
+
+    dims, kappa, U, op = lattice_24x64
+    V = synth.volume(dims)
+    psi = synth.gaussian_spinor(V, 11)
+    x = torch.from_numpy(psi).to("cuda:0")
+    sites = _sample_sites(dims)
+    for dag in (False, True):
+        y = torch.empty_like(x)
+        (gpu_lib.op_apply_dagger if dag else gpu_lib.op_apply)(op, y, x)
+        got = y.cpu().numpy()[sites]
+        ref = W.apply_D_sites(U, psi, kappa, dims, sites, dagger=dag)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"24^3x64 dagger={dag}: sampled max rel err {err:.2e}")
+        assert err <= 1e-12, err
+
+
+def test_dslash_block_24x64_sampled(gpu_lib, lattice_24x64):
+    """FP32 multi-RHS stencil (k = 4) on 24^3 x 64: every column at sampled sites
+    against the oracle on the rounded inputs; timing of the block stencil class."""
+    import torch
+
+    dims, kappa, U, op = lattice_24x64
+    V = synth.volume(dims)
+    k = 4
+    psi = np.stack([synth.z2_source(V, synth.rhs_seed(2, c)) for c in range(k)]).astype(np.complex64)
+    x = torch.from_numpy(psi).to("cuda:0")
+    y = torch.empty_like(x)
+    gpu_lib.timing_classes(op, ["bdslash"])
+    gpu_lib.timing_enable(op, True)
+    gpu_lib.op_apply_block(op, y, x, k, prec="fp32")
+    n, ms = gpu_lib.timing_read(op)["bdslash"]
+    assert n == 1 and ms > 0 and gpu_lib.timing_read(op)["dslash"][0] == 0
+    gpu_lib.timing_enable(op, False)
+    gpu_lib.timing_classes(op, None)
+    sites = _sample_sites(dims, n=24, seed=1)
+    got = y.cpu().numpy()
+    for c in range(k):
+        ref = W.apply_D_sites(U, psi[c].astype(np.complex128), kappa, dims, sites)
+        err = np.abs(got[c][sites] - ref).max() / np.abs(ref).max()
+        assert err < 5e-7, (c, err)
+
+
 def test_gamma5_hermiticity_on_gpu(gpu_lib):
     """gamma5 D gamma5 = D^+ and <y, D x> = <D^+ y, x> at a size the dense oracle cannot hold."""
     import torch
