@@ -30,6 +30,8 @@ inline int stencil_grid(int V) {
   int nb = nblocks_for(size_t(V));
   return nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
 }
+// the BiCG matvec: one work item per (tile, pass)
+inline int matvec_grid(int V) { return 2 * stencil_grid(V); }
 inline int stream_grid(size_t n) {
   int nb = nblocks_for(n, 4);
   return nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);

@@ -181,11 +181,13 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Ap = D p and Adp = D^+ phat in one pass over the lattice (each link loaded
-// once for both), with the partials of sigma = (phat, Ap): phat(x) is loaded
-// for the diagonal term of D^+ anyway.
-// Two LDS-staged passes per tile: D p with sigma = (phat, Ap), then D^+ phat.
-__global__ void __launch_bounds__(kBlock)
+// Ap = D p with the partials of sigma = (phat, Ap), and Adp = D^+ phat.
+// Work item w is one LDS-staged pass over tile w / 2: D p for even w, D^+ phat
+// for odd w, so both passes of a tile run on the same XCD (the links stay in
+// its L2) and a 16^3 x 32 lattice gives 1024 blocks instead of 512.  The
+// register budget of two waves per SIMD lets the compiler overlap the loads
+// of several hops; at this lattice size the grid holds no more waves anyway.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
     k_bicg_matvec(double2 *__restrict__ Ap, double2 *__restrict__ Adp, const double2 *__restrict__ p,
                   const double2 *__restrict__ ph, const double2 *__restrict__ U, Geom g, double kappa, int j,
                   const KrylovState *S, double *__restrict__ part) {
@@ -194,13 +196,15 @@ __global__ void __launch_bounds__(kBlock)
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   double v[2] = {0.0, 0.0};
   const int ntiles = (g.V + kBlock - 1) / kBlock;
-  for (int T = lb; T < ntiles; T += gridDim.x) {
-    const int s0 = T * kBlock, s = s0 + threadIdx.x;
+  for (int w = lb; w < 2 * ntiles; w += gridDim.x) {
+    const int T = w >> 1, s0 = T * kBlock, s = s0 + threadIdx.x;
+    const bool adj = (w & 1) != 0;
     __syncthreads();
-    stage_tile(tile, p, s0, g.V);
+    stage_tile(tile, adj ? ph : p, s0, g.V);
     __syncthreads();
-    if (s < g.V) {
-      cx<double> acc[12];
+    if (s >= g.V) continue;
+    cx<double> acc[12];
+    if (!adj) {
       hopping_t<-1, double2>(acc, TileSrc<double2>{p, tile, s0, g.V}, U, g, s);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -211,12 +215,7 @@ __global__ void __launch_bounds__(kBlock)
         v[0] += d.x;
         v[1] += d.y;
       }
-    }
-    __syncthreads();
-    stage_tile(tile, ph, s0, g.V);
-    __syncthreads();
-    if (s < g.V) {
-      cx<double> acc[12];
+    } else {
       hopping_t<+1, double2>(acc, TileSrc<double2>{ph, tile, s0, g.V}, U, g, s);
 #pragma unroll
       for (int c = 0; c < 12; ++c)
@@ -429,7 +428,7 @@ __global__ void __launch_bounds__(kBlock)
 
 // v = D p ; partials of (rhat, v)
 template <typename S>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
     k_stab_v(S *__restrict__ vout, const S *__restrict__ p, const S *__restrict__ rhat, const S *__restrict__ U,
              Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
@@ -488,7 +487,7 @@ __global__ void __launch_bounds__(kBlock)
 
 // t = D s ; partials of (t, s), (t, t)
 template <typename S>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
     k_stab_t(S *__restrict__ tout, const S *__restrict__ sv, const S *__restrict__ U, Geom g, double kappa, int j,
              const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
@@ -673,14 +672,14 @@ void launch_bicg_init(double2 *rhat, double2 *p, double2 *ph, const double2 *r, 
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
                         const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory, const RedScratch &rs,
                         hipStream_t st) {
-  EB_LAUNCH(k_bicg_matvec, dim3(stencil_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
+  EB_LAUNCH(k_bicg_matvec, dim3(matvec_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
             region(rs, RG_SIGMA));
 }
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
                           const RedScratch &rs, hipStream_t st) {
-  // the matvec wrote stencil_grid(V) sigma records; N = 12 V
-  const int nb_sigma = stencil_grid(int(N / 12));
+  // the matvec wrote matvec_grid(V) sigma records; N = 12 V
+  const int nb_sigma = matvec_grid(int(N / 12));
   EB_LAUNCH(k_bicg_update_r, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N, j, S, h,
             region(rs, RG_SIGMA), nb_sigma, region(rs, RG_RR));
 }

@@ -199,6 +199,9 @@ __device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6],
   }
 }
 
+// No fence between the hops here: with neighbours in LDS the live state is
+// smaller, and the kernels that use this form choose their register budget
+// (and so how far the scheduler may overlap the hops' loads) themselves.
 template <int MU, int SF, typename S, int KC>
 __device__ __forceinline__ void hop_dir_t(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S, KC> &src,
                                           const S *__restrict__ U, int V, int s, int sf, int sb) {
@@ -206,10 +209,8 @@ __device__ __forceinline__ void hop_dir_t(cx<typename Store<S>::R> (&acc)[12], c
   cx<R> h[6];
   load_project_t<MU, SF, S, KC>(h, src, sf);
   mult_accum<MU, SF, false, S>(acc, h, U, V, s);
-  hop_fence();
   load_project_t<MU, -SF, S, KC>(h, src, sb);
   mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
-  hop_fence();
 }
 
 template <int SF, typename S, int KC>
@@ -222,13 +223,15 @@ __device__ __forceinline__ void hopping_t(cx<typename Store<S>::R> (&acc)[12], c
   const int y = (s / sy) % g.ly;
   const int z = (s / sz) % g.lz;
   const int t = s / stt;
-  hop_dir_t<0, SF, S, KC>(acc, src, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
-  hop_dir_t<1, SF, S, KC>(acc, src, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
-                      y == 0 ? s + (g.ly - 1) * sy : s - sy);
+  // z and t first: their neighbours lie outside the tile, and right after the
+  // staging sweeps the neighbouring tiles are most likely still in L2
   hop_dir_t<2, SF, S, KC>(acc, src, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
                       z == 0 ? s + (g.lz - 1) * sz : s - sz);
   hop_dir_t<3, SF, S, KC>(acc, src, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
                       t == 0 ? s + (g.lt - 1) * stt : s - stt);
+  hop_dir_t<0, SF, S, KC>(acc, src, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
+  hop_dir_t<1, SF, S, KC>(acc, src, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
+                      y == 0 ? s + (g.ly - 1) * sy : s - sy);
 }
 
 }  // namespace ebicg
