@@ -152,21 +152,23 @@ __global__ void __launch_bounds__(kBlock)
 // coefficient C[c, k] is the same for every lane, so it reaches the FMAs
 // through scalar loads and no tile is padded: on this chip the FP64 matrix
 // cores sustain about half the FP64 vector rate on these shapes, and padding
-// 20 output columns to a 32-wide tile wastes another third.  With g: partial
-// dots g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1), element-major
+// 20 output columns to a 32-wide tile wastes another third.  DOTS: one
+// element per thread, and the block's partial dots of g with the new outputs,
+// g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1), as element-major
 // records part[(blockIdx.y 2NT + e) gridDim.x + blockIdx.x].
 // ---------------------------------------------------------------------------
-template <int NT, bool ADD>
+template <int NT, bool ADD, bool DOTS>
 __global__ void __launch_bounds__(kBlock)
     k_combine(double2 *out_base, SlotList out_slots, size_t ldo, const double2 *in_base, SlotList in_slots,
-              size_t ldi, const double2 *__restrict__ C, double sgn, size_t N, int jtag, const KrylovState *S) {
+              size_t ldi, const double2 *__restrict__ C, double sgn, size_t N, const double2 *__restrict__ g,
+              int conj_out, double *__restrict__ part, int jtag, const KrylovState *S) {
   if (S && S->stopped && jtag > S->stop_at) return;
   const int nin = in_slots.n, nout = out_slots.n;
   const int k0 = blockIdx.y * NT;
   const int nk = nout - k0 < NT ? nout - k0 : NT;
   const double2 *__restrict__ Ck = C + size_t(k0) * nin;  // coefficient (c, k0 + k) at Ck[c + k nin]
-  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
-    cx<double> acc[NT];
+  cx<double> acc[NT];
+  auto element = [&](size_t i) {
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc[k] = {0.0, 0.0};
     int c = 0;
@@ -200,6 +202,42 @@ __global__ void __launch_bounds__(kBlock)
         o = make_double2(old.x + o.x, old.y + o.y);
       }
       oc[i] = o;
+      acc[k] = {o.x, o.y};
+    }
+  };
+  if constexpr (!DOTS) {
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) element(i);
+  } else {
+    // one element per thread: the dots are formed from the finished outputs
+    // in place and reduced four outputs at a time, so they add few live
+    // registers to the contraction
+    const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc[k] = {0.0, 0.0};
+    double2 gv = make_double2(0.0, 0.0);
+    if (i < N) {
+      element(i);
+      gv = g[i];
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < NT; k4 += 4) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const cx<double> o = acc[k4 + q];
+        if (conj_out) {  // conj(o) g
+          t[2 * q] = o.x * gv.x + o.y * gv.y;
+          t[2 * q + 1] = o.x * gv.y - o.y * gv.x;
+        } else {  // conj(g) o
+          t[2 * q] = gv.x * o.x + gv.y * o.y;
+          t[2 * q + 1] = gv.x * o.y - gv.y * o.x;
+        }
+      }
+      block_sum<8, kBlock>(t);
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          part[(size_t(blockIdx.y) * 2 * NT + 2 * k4 + e) * gridDim.x + blockIdx.x] = t[e];
     }
   }
 }
@@ -300,12 +338,20 @@ void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, co
     const size_t cap = (4096 + groups - 1) / groups;
     nb = nb < cap ? nb : cap;
     const dim3 grid = dim3(unsigned(nb), unsigned(groups));
+    // a rotation with dots: one element per thread when the dot records fit
+    const size_t nfull = (N + kBlock - 1) / kBlock;
+    if (g && !add && nfull * groups * 2 * NT <= part_cap && nfull <= 0x7fffffff) {
+      EB_LAUNCH((k_combine<NT, false, true>), dim3(unsigned(nfull), unsigned(groups)), dim3(kBlock), 0, st, out_base,
+                out_slots, ldo, in_base, in_slots, ldi, C, sgn, N, g, conj_out, part, jtag, S);
+      EB_LAUNCH(k_combine_dots<NT>, dim3(groups * 2 * NT), dim3(kBlock), 0, st, part, int(nfull), nout, dots, jtag, S);
+      return;
+    }
     if (add)
-      EB_LAUNCH((k_combine<NT, true>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots, ldi, C,
-                sgn, N, jtag, S);
+      EB_LAUNCH((k_combine<NT, true, false>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots,
+                ldi, C, sgn, N, nullptr, 0, nullptr, jtag, S);
     else
-      EB_LAUNCH((k_combine<NT, false>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots, ldi,
-                C, sgn, N, jtag, S);
+      EB_LAUNCH((k_combine<NT, false, false>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots,
+                ldi, C, sgn, N, nullptr, 0, nullptr, jtag, S);
     if (g) {
       // dots of the fresh outputs with g, a light second pass (nout + 1 columns)
       size_t nd = (N + kBlock - 1) / kBlock;
