@@ -247,9 +247,16 @@ void timed(eb_op *op, int cls, hipStream_t s, F &&f) {
   }
   if (op->pending.size() > 16384) op->flush_timing();
   hipEvent_t a = op->next_event(), b = op->next_event();
-  HIPCHK(hipEventRecord(a, s));
+  struct Stamp {  // kernel-stamped events for the launches inside f
+    LaunchStamp &ls;
+    Stamp(hipEvent_t a, hipEvent_t b) : ls(launch_stamp()) { ls = LaunchStamp{a, b, false}; }
+    ~Stamp() { ls = LaunchStamp{}; }
+  } stamp(a, b);
   f();
-  HIPCHK(hipEventRecord(b, s));
+  if (!stamp.ls.started) {  // nothing launched: an empty interval
+    HIPCHK(hipEventRecord(a, s));
+    HIPCHK(hipEventRecord(b, s));
+  }
   op->pending.push_back({cls, a, b});
 }
 #define TIMED(cls, stream, call) timed(op, cls, stream, [&]() { call; })

@@ -416,8 +416,6 @@ void dispatch_kc(int kc, F &&f) {
 
 }  // namespace
 
-#define EB_LAUNCH(kernel, grid, block, shmem, st, ...) hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__)
-
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
 
 template <typename S>

@@ -2,6 +2,7 @@
 // solver drivers (api.hip).  All launches are asynchronous on `st`.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -9,6 +10,29 @@
 #include "device_common.h"  // storage types (double2, float2, bf16c)
 
 namespace ebicg {
+
+// Kernel-stamped timing.  While `stop` is set on this host thread, every
+// launch through EB_LAUNCH takes its timestamps from the dispatch itself
+// (hipExtLaunchKernel): the first launch stamps `start`, each launch stamps
+// `stop`, so the interval runs from the first kernel's start to the last
+// kernel's end and leaves out the queue gaps that stream events include.
+struct LaunchStamp {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool started = false;
+};
+LaunchStamp &launch_stamp();
+
+#define EB_LAUNCH(kernel, grid, block, shmem, st, ...)                                                       \
+  do {                                                                                                       \
+    ::ebicg::LaunchStamp &eb_ls_ = ::ebicg::launch_stamp();                                                 \
+    if (eb_ls_.stop) {                                                                                       \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, eb_ls_.started ? nullptr : eb_ls_.start, eb_ls_.stop, \
+                            0, __VA_ARGS__);                                                                 \
+      eb_ls_.started = true;                                                                                 \
+    } else {                                                                                                 \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                                       \
+    }                                                                                                        \
+  } while (0)
 
 // Lattice geometry; V = lx*ly*lz*lt, N = 12 V complex entries per spinor.
 struct Geom {

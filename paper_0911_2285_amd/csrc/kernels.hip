@@ -601,7 +601,10 @@ __global__ void __launch_bounds__(kBlock)
 // ============================================================================
 // launch wrappers
 // ============================================================================
-#define EB_LAUNCH(kernel, grid, block, shmem, st, ...) hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__)
+LaunchStamp &launch_stamp() {
+  static thread_local LaunchStamp ls;
+  return ls;
+}
 
 void launch_to_soa_f64(double2 *d, const double2 *s, const Geom &g, hipStream_t st) {
   EB_LAUNCH(k_to_soa<double2>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);

@@ -293,8 +293,6 @@ __global__ void __launch_bounds__(kBlock)
 
 }  // namespace
 
-#define EB_LAUNCH(kernel, grid, block, shmem, st, ...) hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__)
-
 void launch_gram_mfma(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny,
                       size_t N, double *part, size_t part_cap, hipStream_t st) {
   const int TA = (nx + kTile - 1) / kTile, TB = (ny + kTile - 1) / kTile;
