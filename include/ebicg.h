@@ -62,7 +62,14 @@ typedef struct {
   int32_t m;       /* window size */
   double tol;      /* stop when ||r_j|| <= tol ||b|| (Alg. eigBiCG, last test of the loop) */
   int32_t maxiter; /* iteration cap */
-  int32_t rhat;    /* shadow residual: 0 -> rhat_0 = r_0 (Sec. 2 "Normally"); 1 -> gamma5 r_0 (Sec. 4) */
+  int32_t rhat;    /* shadow residual: 0 -> rhat_0 = r_0 (Sec. 2 "Normally"); 1 -> gamma5 r_0 (Sec. 4);
+                      2 -> the gamma5-Hermitian form (Sec. 4): rhat_j = gamma5 r_j and
+                      phat_j = gamma5 p_j are never formed, D^+ phat = gamma5 D p is not
+                      applied (one D per iteration, matvec_ddag = 0), and the left window's
+                      residuals are read as gamma5 times the right window's.  Same iterates
+                      as 1 in exact arithmetic.  A source with (gamma5 r_0, r_0) = 0, such as a
+                      Z2 source (entries +-1) with x_0 = 0, breaks down at once in modes 1 and
+                      2 (EB_ERR_BREAKDOWN). */
 } eb_eig_params;
 
 /* Parameters of a deflated solve (Alg. Incremental eigBiCG, step 3). */

@@ -903,8 +903,13 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   const int lag = 8;
   const int nslots = m + 1 + lag + 2 * nev;
   const size_t ncoef = size_t(m + 1) * 2 * nev;  // one coefficient block (m x 2nev complex)
-  double2 *Vw = op->vec("win_V", nslots);
-  double2 *Ww = op->vec("win_W", nslots);
+  // one allocation for both windows, so that a rotation can read right-window
+  // columns (slot s) and left-window columns (slot nslots + s) from one base
+  double2 *Vw = op->vec("win_VW", 2 * size_t(nslots));
+  double2 *Ww = Vw + size_t(nslots) * N;
+  // gamma5-Hermitian form (Sec. 4): rhat_j = gamma5 r_j is never formed; the
+  // left window's stored residuals are read as gamma5 times the right window's
+  const bool g5 = P.rhat == 2;
   double2 *p = op->vec("bicg_p"), *ph = op->vec("bicg_ph");
   double2 *Ap = op->vec("bicg_Ap", 2), *Adp = op->vec("bicg_Adp", 2);
   double2 *GA = op->vec("bicg_GA"), *GB = op->vec("bicg_GB");
@@ -920,7 +925,8 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   EigBiCGOut out;
   // r_0 in V slot 0, rhat_0 in W slot 0
   launch_residual_f64(V(0), b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
-  launch_bicg_init(W(0), p, ph, V(0), op->res.as<double>(), N, P.rhat, op->g, P.tol, P.maxiter, S, dh, op->rs(), s);
+  launch_bicg_init(g5 ? nullptr : W(0), p, g5 ? nullptr : ph, V(0), op->res.as<double>(), N, P.rhat, op->g, P.tol,
+                   P.maxiter, S, dh, op->rs(), s);
   KrylovState hs;
   fetch_state(op, s, hs);
   if (hs.stopped) {
@@ -1011,6 +1017,16 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       rb.dW[k] = c2(pd[2 * nev + k]);
     }
   };
+  // Inputs of a left-window rotation over the columns cols: in_base = Vw, a
+  // column at window slot s is nslots + s; in the gamma5 form a stored
+  // residual is -(s + 1), i.e. gamma5 times right-window slot s.
+  auto left_inputs = [&](const std::vector<Col> &cs) {
+    SlotList in{};
+    in.n = int(cs.size());
+    for (int c = 0; c < in.n; ++c)
+      in.idx[c] = (g5 && !cs[c].ritz) ? -(cs[c].slot + 1) : nslots + cs[c].slot;
+    return in;
+  };
   // Apply a finished restart: rotate the old window into `kept` fresh slots
   // (with the arrow dots), free the old slots, replace the placeholders.
   auto apply_job = [&]() {
@@ -1030,7 +1046,8 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
     const auto coef = upload_coef(job->CVraw, job->CWraw);
     double2 *const cV = coef.first, *const cW = coef.second;
     TIMED(EB_K_ROTATE, s, launch_rotate(Vw, outl, Vw, in, cV, N, GA, 0, dots, job->jr, S, op->rs(), s));
-    TIMED(EB_K_ROTATE, s, launch_rotate(Ww, outl, Ww, in, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s));
+    const SlotList inl = left_inputs(job->cols);
+    TIMED(EB_K_ROTATE, s, launch_rotate(Ww, outl, Vw, inl, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s));
     for (int c = 0; c < mm; ++c) free_slots.push_back(job->cols[c].slot);
     std::vector<Col> nc;
     for (int k = 0; k < kept; ++k) nc.push_back(Col{1, k, outl.idx[k]});
@@ -1057,12 +1074,13 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       if (j > P.maxiter + 1) break;
       const int cur = j & 1, prv = cur ^ 1;
       TIMED(EB_K_BICG_MATVEC, s,
-            launch_bicg_matvec(Ap + cur * N, Adp + cur * N, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
-                               op->rs(), s));
+            launch_bicg_matvec(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
+                               op->U64.as<double2>(), op->g, op->kappa, j, S, dh, op->rs(), g5, s));
       if (int(cols.size()) == m) {
         // Restart at iteration j (vs = m).  q = A p and s = A^+ phat were kept
         // from iteration j-1 (vs = m-1) in the other buffer.
-        launch_arrow_vectors(GA, GB, Adp + cur * N, Adp + prv * N, Ap + cur * N, Ap + prv * N, N, j, S, dh, s);
+        launch_arrow_vectors(GA, GB, g5 ? nullptr : Adp + cur * N, g5 ? nullptr : Adp + prv * N, Ap + cur * N,
+                             Ap + prv * N, N, j, S, dh, g5, s);
         // history through j-1 was shipped at the end of iteration j-1; the GPU
         // keeps working on this iteration's matvec meanwhile
         HIPCHK(hipEventSynchronize(ev_hist));
@@ -1096,10 +1114,12 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       slot_of_r[j] = snew;
       const int sold = slot_of_r[j - 1];
       TIMED(EB_K_BICG_UPDATE_R, s,
-            launch_bicg_update_r(V(snew), W(snew), V(sold), W(sold), Ap + cur * N, Adp + cur * N, N, j, S, dh,
-                                 op->rs(), s));
+            launch_bicg_update_r(V(snew), g5 ? nullptr : W(snew), V(sold), g5 ? nullptr : W(sold), Ap + cur * N,
+                                 g5 ? nullptr : Adp + cur * N, N, j, S, dh, op->rs(), g5, s));
       if (job && job->done.load(std::memory_order_acquire)) apply_job();
-      TIMED(EB_K_BICG_UPDATE_P, s, launch_bicg_update_p(x, p, ph, V(snew), W(snew), N, j, S, dh, op->rs(), s));
+      TIMED(EB_K_BICG_UPDATE_P, s,
+            launch_bicg_update_p(x, p, g5 ? nullptr : ph, V(snew), g5 ? nullptr : W(snew), N, j, S, dh, op->rs(), g5,
+                                 s));
       if (int(cols.size()) == m) {
         // the next iteration restarts: the previous restart must be applied
         // first; then ship the history through j (complete after update_p)
@@ -1170,7 +1190,8 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       o1.n = k;
       for (int c = 0; c < k; ++c) o1.idx[c] = op->K + c;
       launch_rotate(op->Ur.as<double2>(), o1, Vw, in, cV, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
-      launch_rotate(op->Ul.as<double2>(), o1, Ww, in, cW, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
+      launch_rotate(op->Ul.as<double2>(), o1, Vw, left_inputs(cols), cW, N, nullptr, 0, nullptr, 0, nullptr, op->rs(),
+                    s);
       HIPCHK(hipStreamSynchronize(s));
       out.nvec = k;
     }
@@ -1424,7 +1445,7 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     if (P->nev < 1 || P->m <= 2 * P->nev) fail(EB_ERR_INVALID, "need nev >= 1 and m > 2 nev");
     if (P->m + 1 > kMaxCols || 2 * P->nev > 64) fail(EB_ERR_INVALID, "window too large (m <= 127, nev <= 32)");
     if (!(P->tol > 0) || P->maxiter < 1) fail(EB_ERR_INVALID, "tol > 0 and maxiter >= 1 required");
-    if (P->rhat != 0 && P->rhat != 1) fail(EB_ERR_INVALID, "rhat must be 0 or 1");
+    if (P->rhat < 0 || P->rhat > 2) fail(EB_ERR_INVALID, "rhat must be 0, 1 or 2");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
@@ -1435,7 +1456,7 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     EigBiCGOut R = run_eigbicg(op, b, x, *P, s);
     st.iters = R.iters;
     st.matvec_d = R.iters + 1;
-    st.matvec_ddag = R.iters;
+    st.matvec_ddag = P->rhat == 2 ? 0 : R.iters;
     st.window_restarts = R.restarts;
     if (R.reason == 2) fail(EB_ERR_BREAKDOWN, "eigBiCG breakdown");
     if (ritz)

@@ -116,27 +116,37 @@ void launch_residual_f64(double2 *r, const double2 *b, const double2 *x, const d
                          double *res, const RedScratch &rs, hipStream_t st);
 
 // ---- BiCG (FP64, window slots) ------------------------------------------------
-// Initial state: rhat_0 = r_0 (rhat_mode 0) or gamma5 r_0 (1); p = r_0, phat = rhat_0;
-// rho_0, ||r_0||, ||b|| into state/history; res = {||r0||^2, ||b||^2} from launch_residual.
+// g5 selects the gamma5-Hermitian form (Sec. 4, rhat_mode 2): the shadow
+// vectors rhat_j = gamma5 r_j and phat_j = gamma5 p_j are never formed, the
+// rhat/phat/Adp/s arguments are not touched (they may be null) and each
+// iteration applies D once.
+//
+// Initial state: rhat_0 = r_0 (rhat_mode 0) or gamma5 r_0 (1, 2); p = r_0, phat = rhat_0
+// (not written in mode 2); rho_0, ||r_0||, ||b|| into state/history; res = {||r0||^2, ||b||^2}
+// from launch_residual.
 void launch_bicg_init(double2 *rhat, double2 *p, double2 *phat, const double2 *r, const double *res, size_t N,
                       int rhat_mode, const Geom &g, double tol, int maxiter, KrylovState *S, KrylovHistory h,
                       const RedScratch &rs, hipStream_t st);
 // Ap = D p, Adp = D^+ phat; partials of sigma = (phat, Ap).
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *phat, const double2 *U,
                         const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory h, const RedScratch &rs,
-                        hipStream_t st);
+                        bool g5, hipStream_t st);
 // alpha_{j-1} = rho_{j-1} / sigma; r_out = r_in - alpha Ap; rhat_out = rhat_in - conj(alpha) Adp;
 // partials of rho_j and ||r_j||^2.
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                          const RedScratch &rs, hipStream_t st);
+                          const RedScratch &rs, bool g5, hipStream_t st);
 // beta_{j-1}, rho_j, ||r_j|| and the stop test; x += alpha p; p = r + beta p; phat = rhat + conj(beta) phat.
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
-                          KrylovState *S, KrylovHistory h, const RedScratch &rs, hipStream_t st);
-// GA = Adp - conj(beta_{j-2}) s ; GB = Ap - beta_{j-2} q  (the arrow vectors of a restart)
+                          KrylovState *S, KrylovHistory h, const RedScratch &rs, bool g5, hipStream_t st);
+// GA = Adp - conj(beta_{j-2}) s ; GB = Ap - beta_{j-2} q  (the arrow vectors of a restart);
+// g5: GA = gamma5 (Ap - conj(beta_{j-2}) q).
 void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const double2 *s, const double2 *Ap,
-                          const double2 *q, size_t N, int j, const KrylovState *S, KrylovHistory h, hipStream_t st);
+                          const double2 *q, size_t N, int j, const KrylovState *S, KrylovHistory h, bool g5,
+                          hipStream_t st);
 // out[k] = sum_c in[c] C[c + k*nin] for k < nout (out-of-place, slots into one base each).
+// An input slot given as -(slot + 1) is read as gamma5 in[slot] (spinor columns,
+// N = 12 V: components 6..11 flip sign).
 // If g != null: dots[k] = g^+ out[k] (conj_out = 0) or out[k]^+ g (conj_out = 1).
 void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *in_base, const SlotList &in_slots,
                    const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,

@@ -137,6 +137,8 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // ----------------------------------------------------------------------------
 // BiCG (Alg. eigBiCG loop), FP64.  Iteration j: matvec -> update_r -> update_p.
 // ----------------------------------------------------------------------------
+// rhat_mode 0: rhat_0 = r_0; 1: rhat_0 = gamma5 r_0; 2: gamma5 r_0 as well, but
+// the shadow vectors are never formed (rhat and ph are not written).
 __global__ void __launch_bounds__(kBlock)
     k_bicg_init(double2 *__restrict__ rhat, double2 *__restrict__ p, double2 *__restrict__ ph,
                 const double2 *__restrict__ r, size_t N, int V, int rhat_mode, double *__restrict__ part) {
@@ -144,10 +146,12 @@ __global__ void __launch_bounds__(kBlock)
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> rv = Store<double2>::ld(r, i);
     // gamma5 = diag(1, 1, -1, -1): components 6..11 of the SoA layout flip sign
-    cx<double> hv = (rhat_mode == 1 && i >= size_t(6) * V) ? -rv : rv;
-    Store<double2>::st(rhat, i, hv);
+    cx<double> hv = (rhat_mode != 0 && i >= size_t(6) * V) ? -rv : rv;
     Store<double2>::st(p, i, rv);
-    Store<double2>::st(ph, i, hv);
+    if (rhat_mode != 2) {
+      Store<double2>::st(rhat, i, hv);
+      Store<double2>::st(ph, i, hv);
+    }
     cx<double> d = cmulc(hv, rv);
     v[0] += d.x;
     v[1] += d.y;
@@ -182,11 +186,15 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Ap = D p with the partials of sigma = (phat, Ap), and Adp = D^+ phat.
+// G5 (the gamma5-Hermitian form, Sec. 4): phat = gamma5 p is never formed and
+// D^+ phat = gamma5 D p is not computed; sigma = (gamma5 p, Ap) takes p from
+// the staged tile, and the work items are the tiles alone.
 // Work item w is one LDS-staged pass over tile w / 2: D p for even w, D^+ phat
 // for odd w, so both passes of a tile run on the same XCD (the links stay in
 // its L2) and a 16^3 x 32 lattice gives 1024 blocks instead of 512.  The
 // register budget of two waves per SIMD lets the compiler overlap the loads
 // of several hops; at this lattice size the grid holds no more waves anyway.
+template <bool G5>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
     k_bicg_matvec(double2 *__restrict__ Ap, double2 *__restrict__ Adp, const double2 *__restrict__ p,
                   const double2 *__restrict__ ph, const double2 *__restrict__ U, Geom g, double kappa, int j,
@@ -196,9 +204,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   double v[2] = {0.0, 0.0};
   const int ntiles = (g.V + kBlock - 1) / kBlock;
-  for (int w = lb; w < 2 * ntiles; w += gridDim.x) {
-    const int T = w >> 1, s0 = T * kBlock, s = s0 + threadIdx.x;
-    const bool adj = (w & 1) != 0;
+  constexpr int kItems = G5 ? 1 : 2;  // work items per tile
+  for (int w = lb; w < kItems * ntiles; w += gridDim.x) {
+    const int T = G5 ? w : w >> 1, s0 = T * kBlock, s = s0 + threadIdx.x;
+    const bool adj = !G5 && (w & 1) != 0;
     __syncthreads();
     stage_tile(tile, adj ? ph : p, s0, g.V);
     __syncthreads();
@@ -209,9 +218,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const size_t i = size_t(c) * g.V + s;
-        const cx<double> o = Store<double2>::ld(tile, size_t(c) * kBlock + threadIdx.x) - kappa * acc[c];
+        const cx<double> pv = Store<double2>::ld(tile, size_t(c) * kBlock + threadIdx.x);
+        const cx<double> o = pv - kappa * acc[c];
         Store<double2>::st(Ap, i, o);
-        const cx<double> d = cmulc(Store<double2>::ld(ph, i), o);
+        const cx<double> d = G5 ? (c < 6 ? cmulc(pv, o) : -cmulc(pv, o)) : cmulc(Store<double2>::ld(ph, i), o);
         v[0] += d.x;
         v[1] += d.y;
       }
@@ -226,6 +236,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
   block_partial<2, kBlock>(v, part, blockIdx.x);
 }
 
+// G5: rhat = gamma5 r is not formed; rho = (gamma5 r, r).
+template <bool G5>
 __global__ void __launch_bounds__(kBlock)
     k_bicg_update_r(double2 *__restrict__ r_out, double2 *__restrict__ rh_out, const double2 *__restrict__ r_in,
                     const double2 *__restrict__ rh_in, const double2 *__restrict__ Ap,
@@ -248,19 +260,27 @@ __global__ void __launch_bounds__(kBlock)
   if (blockIdx.x == 0 && threadIdx.x == 0) h.alpha[j - 1] = d2(a);
   const cx<double> ac = cconj(a);
   double v[3] = {0.0, 0.0, 0.0};
+  const size_t half = N / 2;  // gamma5 flips components 6..11 (N = 12 V)
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> r = Store<double2>::ld(r_in, i) - a * Store<double2>::ld(Ap, i);
-    cx<double> rh = Store<double2>::ld(rh_in, i) - ac * Store<double2>::ld(Adp, i);
     Store<double2>::st(r_out, i, r);
-    Store<double2>::st(rh_out, i, rh);
-    cx<double> d = cmulc(rh, r);
-    v[0] += d.x;
-    v[1] += d.y;
-    v[2] += r.x * r.x + r.y * r.y;
+    const double rr = r.x * r.x + r.y * r.y;
+    if constexpr (G5) {
+      v[0] += i < half ? rr : -rr;
+    } else {
+      cx<double> rh = Store<double2>::ld(rh_in, i) - ac * Store<double2>::ld(Adp, i);
+      Store<double2>::st(rh_out, i, rh);
+      cx<double> d = cmulc(rh, r);
+      v[0] += d.x;
+      v[1] += d.y;
+    }
+    v[2] += rr;
   }
   block_partial<3, kBlock>(v, part, blockIdx.x);
 }
 
+// G5: phat = gamma5 p is not formed.
+template <bool G5>
 __global__ void __launch_bounds__(kBlock)
     k_bicg_update_p(double2 *__restrict__ x, double2 *__restrict__ p, double2 *__restrict__ ph,
                     const double2 *__restrict__ r, const double2 *__restrict__ rh, size_t N, int j, KrylovState *S,
@@ -296,19 +316,29 @@ __global__ void __launch_bounds__(kBlock)
     cx<double> pv = Store<double2>::ld(p, i);
     Store<double2>::st(x, i, Store<double2>::ld(x, i) + a * pv);
     Store<double2>::st(p, i, Store<double2>::ld(r, i) + b * pv);
-    Store<double2>::st(ph, i, Store<double2>::ld(rh, i) + bc * Store<double2>::ld(ph, i));
+    if constexpr (!G5) Store<double2>::st(ph, i, Store<double2>::ld(rh, i) + bc * Store<double2>::ld(ph, i));
   }
 }
 
+// G5: D^+ phat = gamma5 D p, so GA = gamma5 (Ap - conj(beta) q) from the A p
+// buffers (Adp and s are not read).
+template <bool G5>
 __global__ void __launch_bounds__(kBlock)
     k_arrow_vectors(double2 *__restrict__ GA, double2 *__restrict__ GB, const double2 *__restrict__ Adp,
                     const double2 *__restrict__ s, const double2 *__restrict__ Ap, const double2 *__restrict__ q,
                     size_t N, int j, const KrylovState *S, KrylovHistory h) {
   if (skip_iter(S, j)) return;
   const cx<double> b = c2(h.beta[j - 2]), bc = cconj(b);
+  const size_t half = N / 2;
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
-    Store<double2>::st(GA, i, Store<double2>::ld(Adp, i) - bc * Store<double2>::ld(s, i));
-    Store<double2>::st(GB, i, Store<double2>::ld(Ap, i) - b * Store<double2>::ld(q, i));
+    const cx<double> apv = Store<double2>::ld(Ap, i), qv = Store<double2>::ld(q, i);
+    if constexpr (G5) {
+      const cx<double> ga = apv - bc * qv;
+      Store<double2>::st(GA, i, i < half ? ga : -ga);
+    } else {
+      Store<double2>::st(GA, i, Store<double2>::ld(Adp, i) - bc * Store<double2>::ld(s, i));
+    }
+    Store<double2>::st(GB, i, apv - b * qv);
   }
 }
 
@@ -674,26 +704,42 @@ void launch_bicg_init(double2 *rhat, double2 *p, double2 *ph, const double2 *r, 
 }
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
                         const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory, const RedScratch &rs,
-                        hipStream_t st) {
-  EB_LAUNCH(k_bicg_matvec, dim3(matvec_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
-            region(rs, RG_SIGMA));
+                        bool g5, hipStream_t st) {
+  if (g5)
+    EB_LAUNCH(k_bicg_matvec<true>, dim3(stencil_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
+              region(rs, RG_SIGMA));
+  else
+    EB_LAUNCH(k_bicg_matvec<false>, dim3(matvec_grid(g.V)), dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, j, S,
+              region(rs, RG_SIGMA));
 }
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                          const RedScratch &rs, hipStream_t st) {
-  // the matvec wrote matvec_grid(V) sigma records; N = 12 V
-  const int nb_sigma = matvec_grid(int(N / 12));
-  EB_LAUNCH(k_bicg_update_r, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N, j, S, h,
-            region(rs, RG_SIGMA), nb_sigma, region(rs, RG_RR));
+                          const RedScratch &rs, bool g5, hipStream_t st) {
+  // the matvec wrote one sigma record per block of its grid; N = 12 V
+  const int V = int(N / 12);
+  if (g5)
+    EB_LAUNCH(k_bicg_update_r<true>, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N,
+              j, S, h, region(rs, RG_SIGMA), stencil_grid(V), region(rs, RG_RR));
+  else
+    EB_LAUNCH(k_bicg_update_r<false>, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N,
+              j, S, h, region(rs, RG_SIGMA), matvec_grid(V), region(rs, RG_RR));
 }
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
-                          KrylovState *S, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
-  EB_LAUNCH(k_bicg_update_p, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, p, ph, r, rh, N, j, S, h,
-            region(rs, RG_RR), red_grid(N));
+                          KrylovState *S, KrylovHistory h, const RedScratch &rs, bool g5, hipStream_t st) {
+  if (g5)
+    EB_LAUNCH(k_bicg_update_p<true>, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, p, ph, r, rh, N, j, S, h,
+              region(rs, RG_RR), red_grid(N));
+  else
+    EB_LAUNCH(k_bicg_update_p<false>, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, p, ph, r, rh, N, j, S, h,
+              region(rs, RG_RR), red_grid(N));
 }
 void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const double2 *s, const double2 *Ap,
-                          const double2 *q, size_t N, int j, const KrylovState *S, KrylovHistory h, hipStream_t st) {
-  EB_LAUNCH(k_arrow_vectors, dim3(stream_grid(N)), dim3(kBlock), 0, st, GA, GB, Adp, s, Ap, q, N, j, S, h);
+                          const double2 *q, size_t N, int j, const KrylovState *S, KrylovHistory h, bool g5,
+                          hipStream_t st) {
+  if (g5)
+    EB_LAUNCH(k_arrow_vectors<true>, dim3(stream_grid(N)), dim3(kBlock), 0, st, GA, GB, Adp, s, Ap, q, N, j, S, h);
+  else
+    EB_LAUNCH(k_arrow_vectors<false>, dim3(stream_grid(N)), dim3(kBlock), 0, st, GA, GB, Adp, s, Ap, q, N, j, S, h);
 }
 
 void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *in_base, const SlotList &in_slots,

@@ -157,7 +157,9 @@ __global__ void __launch_bounds__(kBlock)
 // g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1), as element-major
 // records part[(blockIdx.y 2NT + e) gridDim.x + blockIdx.x].
 // ---------------------------------------------------------------------------
-template <int NT, bool ADD, bool DOTS>
+// G5IN: an input slot -(slot + 1) is read as gamma5 times that column (spinor
+// columns of length N = 12 V: the second half, components 6..11, flips sign).
+template <int NT, bool ADD, bool DOTS, bool G5IN>
 __global__ void __launch_bounds__(kBlock)
     k_combine(double2 *out_base, SlotList out_slots, size_t ldo, const double2 *in_base, SlotList in_slots,
               size_t ldi, const double2 *__restrict__ C, double sgn, size_t N, const double2 *__restrict__ g,
@@ -167,29 +169,41 @@ __global__ void __launch_bounds__(kBlock)
   const int k0 = blockIdx.y * NT;
   const int nk = nout - k0 < NT ? nout - k0 : NT;
   const double2 *__restrict__ Ck = C + size_t(k0) * nin;  // coefficient (c, k0 + k) at Ck[c + k nin]
+  const size_t half = N / 2;
+  auto load_in = [&](int c, size_t i) -> cx<double> {
+    int sc = in_slots.idx[c];
+    if constexpr (G5IN) {
+      const bool flip = sc < 0;
+      if (flip) sc = -sc - 1;
+      const double2 t = in_base[size_t(sc) * ldi + i];
+      return (flip && i >= half) ? cx<double>{-t.x, -t.y} : cx<double>{t.x, t.y};
+    } else {
+      const double2 t = in_base[size_t(sc) * ldi + i];
+      return {t.x, t.y};
+    }
+  };
   cx<double> acc[NT];
   auto element = [&](size_t i) {
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc[k] = {0.0, 0.0};
     int c = 0;
     for (; c + 2 <= nin; c += 2) {
-      const double2 v0 = in_base[size_t(in_slots.idx[c]) * ldi + i];
-      const double2 v1 = in_base[size_t(in_slots.idx[c + 1]) * ldi + i];
+      const cx<double> v0 = load_in(c, i), v1 = load_in(c + 1, i);
 #pragma unroll
       for (int k = 0; k < NT; ++k)
         if (k < nk) {
           const double2 w0 = Ck[c + size_t(k) * nin], w1 = Ck[c + 1 + size_t(k) * nin];
-          cfma(acc[k], cx<double>{v0.x, v0.y}, cx<double>{w0.x, w0.y});
-          cfma(acc[k], cx<double>{v1.x, v1.y}, cx<double>{w1.x, w1.y});
+          cfma(acc[k], v0, cx<double>{w0.x, w0.y});
+          cfma(acc[k], v1, cx<double>{w1.x, w1.y});
         }
     }
     if (c < nin) {
-      const double2 v0 = in_base[size_t(in_slots.idx[c]) * ldi + i];
+      const cx<double> v0 = load_in(c, i);
 #pragma unroll
       for (int k = 0; k < NT; ++k)
         if (k < nk) {
           const double2 w0 = Ck[c + size_t(k) * nin];
-          cfma(acc[k], cx<double>{v0.x, v0.y}, cx<double>{w0.x, w0.y});
+          cfma(acc[k], v0, cx<double>{w0.x, w0.y});
         }
     }
 #pragma unroll
@@ -336,20 +350,34 @@ void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, co
     const size_t cap = (4096 + groups - 1) / groups;
     nb = nb < cap ? nb : cap;
     const dim3 grid = dim3(unsigned(nb), unsigned(groups));
+    bool g5in = false;
+    for (int c = 0; c < nin; ++c) g5in = g5in || in_slots.idx[c] < 0;
+    auto launch = [&](auto add_tag, auto dots_tag, auto g5_tag, dim3 gr) {
+      constexpr bool A = decltype(add_tag)::value, D = decltype(dots_tag)::value, G = decltype(g5_tag)::value;
+      EB_LAUNCH((k_combine<NT, A, D, G>), gr, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots, ldi,
+                C, sgn, N, g, conj_out, part, jtag, S);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
     // a rotation with dots: one element per thread when the dot records fit
     const size_t nfull = (N + kBlock - 1) / kBlock;
     if (g && !add && nfull * groups * 2 * NT <= part_cap && nfull <= 0x7fffffff) {
-      EB_LAUNCH((k_combine<NT, false, true>), dim3(unsigned(nfull), unsigned(groups)), dim3(kBlock), 0, st, out_base,
-                out_slots, ldo, in_base, in_slots, ldi, C, sgn, N, g, conj_out, part, jtag, S);
+      const dim3 gfull = dim3(unsigned(nfull), unsigned(groups));
+      if (g5in)
+        launch(F{}, T{}, T{}, gfull);
+      else
+        launch(F{}, T{}, F{}, gfull);
       EB_LAUNCH(k_combine_dots<NT>, dim3(groups * 2 * NT), dim3(kBlock), 0, st, part, int(nfull), nout, dots, jtag, S);
       return;
     }
-    if (add)
-      EB_LAUNCH((k_combine<NT, true, false>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots,
-                ldi, C, sgn, N, nullptr, 0, nullptr, jtag, S);
+    if (add && g5in)
+      launch(T{}, F{}, T{}, grid);
+    else if (add)
+      launch(T{}, F{}, F{}, grid);
+    else if (g5in)
+      launch(F{}, F{}, T{}, grid);
     else
-      EB_LAUNCH((k_combine<NT, false, false>), grid, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots,
-                ldi, C, sgn, N, nullptr, 0, nullptr, jtag, S);
+      launch(F{}, F{}, F{}, grid);
     if (g) {
       // dots of the fresh outputs with g, a light second pass (nout + 1 columns)
       size_t nd = (N + kBlock - 1) / kBlock;

@@ -244,7 +244,10 @@ def op_apply_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
 
 
 def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):
-    """One eigBiCG solve that grows the deflation space; returns (stats, ritz values)."""
+    """One eigBiCG solve that grows the deflation space; returns (stats, ritz values).
+
+    rhat: 0 -> rhat_0 = r_0; 1 -> gamma5 r_0; 2 -> the gamma5-Hermitian form
+    (shadow vectors implicit, one D per iteration)."""
     import torch
 
     p = _EigParams(int(nev), int(m), float(tol), int(maxiter), int(rhat))
