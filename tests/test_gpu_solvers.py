@@ -275,3 +275,46 @@ def test_solves_are_deterministic(gpu_lib, cfg0):
         gpu_lib.deflated_bicg_solve(op, b, x2, tol=1e-10)
         outs.append((x.clone(), x2.clone()))
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_deflation_speedup_near_critical(gpu_lib):
+    """Alg. Incremental eigBiCG pays off where the low spectrum separates: 4^4,
+    eps = 1.0 links, kappa = 0.2379 (0.97 of the critical value of this
+    configuration), 8 eigBiCG solves (nev 10, m 40), then deflated BiCGStab.
+    The oracle needs about two thirds of the undeflated iterations; the library
+    must match its deflated iteration counts within 10% and beat the
+    undeflated counts by the same margin."""
+    import torch
+
+    dims, kappa = (4, 4, 4, 4), 0.2379
+    V = synth.volume(dims)
+    N = 12 * V
+    U = synth.random_su3_links(dims, 1.0, 123)
+    A, Ad = _ops(U, kappa, dims)
+    B = [synth.z2_source(V, synth.rhs_seed(0, i)) for i in range(12)]
+    _, info_o, _ = K.incremental_eigbicg(A, Ad, [b.ravel() for b in B], [np.zeros(N, complex)] * 12, 10, 40,
+                                         1e-8, n1=8)
+    defl_o = [d["iters"] for d in info_o[8:]]
+    und_o = [K.bicgstab(A, b.ravel(), np.zeros(N, complex), 1e-8, 20000).iters for b in B[8:]]
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=80)
+    defl_g, und_g = [], []
+    for i, bnp in enumerate(B):
+        b = torch.from_numpy(bnp).to("cuda:0")
+        x = torch.zeros_like(b)
+        if i < 8:
+            gpu_lib.eigbicg_solve(op, b, x, nev=10, m=40, tol=1e-8, maxiter=20000)
+        else:
+            st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-8, maxiter=20000)
+            assert st["true_rel_resid"] <= 1e-8
+            defl_g.append(st["iters"])
+    gpu_lib.defl_reset(op)
+    for bnp in B[8:]:
+        b = torch.from_numpy(bnp).to("cuda:0")
+        x = torch.zeros_like(b)
+        und_g.append(gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-8, maxiter=20000)["iters"])
+    print("oracle deflated", defl_o, "undeflated", und_o)
+    print("gpu    deflated", defl_g, "undeflated", und_g)
+    assert np.mean(defl_o) <= 0.8 * np.mean(und_o)  # the premise: deflation helps here
+    assert abs(np.mean(defl_g) - np.mean(defl_o)) <= 0.1 * np.mean(defl_o)
+    assert np.mean(defl_g) <= 0.8 * np.mean(und_g)
+    gpu_lib.op_destroy(op)
