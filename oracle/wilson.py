@@ -214,3 +214,76 @@ def free_field_spectrum(kappa, dims, bc_t=-1, phases=(0.0, 0.0, 0.0, 0.0)):
     im = 2 * kappa * np.sqrt((np.sin(P) ** 2).sum(axis=1))
     lam = np.concatenate([re + 1j * im, re - 1j * im])
     return np.repeat(lam, 6)
+
+
+# --------------------------------------------------------------- even-odd
+# The paper's test matrices are even-odd preconditioned Wilson operators
+# (Sec. 3, "Results"); the paper does not spell the form out, and this is the
+# standard Schur complement.  With the sites split by parity (x+y+z+t even or
+# odd) and H the hop sum above (D = 1 - kappa H), H only connects sites of
+# opposite parity, so
+#     D = [[1, -kappa H_eo], [-kappa H_oe, 1]],
+#     Dhat = 1 - kappa^2 H_eo H_oe            (on the even sites),
+#     D x = b  <=>  Dhat x_e = b_e + kappa H_eo b_o,  x_o = b_o + kappa H_oe x_e.
+# Half-lattice vectors hold the sites of one parity in increasing site order.
+
+
+def parity(dims):
+    """(x + y + z + t) mod 2 for every site s, shape (V,)."""
+    lx, ly, lz, lt = dims
+    s = np.arange(lx * ly * lz * lt)
+    x, y, z, t = s % lx, (s // lx) % ly, (s // (lx * ly)) % lz, s // (lx * ly * lz)
+    return (x + y + z + t) % 2
+
+
+def _check_eo(dims):
+    _check(dims)
+    if any(int(d) % 2 for d in dims):
+        raise ValueError(f"even-odd ordering needs even extents, got {dims}")
+
+
+def _embed(half, par, p):
+    full = np.zeros((par.size, 4, 3), dtype=np.complex128)
+    full[par == p] = half.reshape(-1, 4, 3)
+    return full
+
+
+def _hop_full(gauge, psi, dims, bc_t, dagger):
+    one = np.eye(4)
+    g = gammas()
+    if dagger:
+        return _hop(gauge, psi, dims, bc_t, one + g, one - g)
+    return _hop(gauge, psi, dims, bc_t, one - g, one + g)
+
+
+def apply_Dhat(gauge, psi_e, kappa, dims, bc_t=-1, dagger=False):
+    """Dhat psi_e (or Dhat^+ psi_e, built from the adjoint hops) on the even sites.
+
+    psi_e: complex128 [V/2][4][3], the even sites in increasing site order.
+    """
+    _check_eo(dims)
+    par = parity(dims)
+    t = _hop_full(gauge, _embed(psi_e, par, 0), dims, bc_t, dagger)[par == 1]
+    u = _hop_full(gauge, _embed(t, par, 1), dims, bc_t, dagger)[par == 0]
+    return psi_e.reshape(-1, 4, 3) - kappa * kappa * u
+
+
+def eo_prepare(gauge, b, kappa, dims, bc_t=-1):
+    """b_e + kappa H_eo b_o: the right-hand side of the even system."""
+    _check_eo(dims)
+    par = parity(dims)
+    b = b.reshape(-1, 4, 3)
+    hb = _hop_full(gauge, _embed(b[par == 1], par, 1), dims, bc_t, False)[par == 0]
+    return b[par == 0] + kappa * hb
+
+
+def eo_reconstruct(gauge, x_e, b, kappa, dims, bc_t=-1):
+    """The full solution from x_e: x_o = b_o + kappa H_oe x_e."""
+    _check_eo(dims)
+    par = parity(dims)
+    b = b.reshape(-1, 4, 3)
+    hx = _hop_full(gauge, _embed(x_e, par, 0), dims, bc_t, False)[par == 1]
+    x = np.zeros_like(b)
+    x[par == 0] = x_e.reshape(-1, 4, 3)
+    x[par == 1] = b[par == 1] + kappa * hx
+    return x

@@ -203,3 +203,64 @@ def test_boundary_sign_matters():
     inner = (c[:, 3] > 0) & (c[:, 3] < dims[3] - 1)
     assert np.abs(a[inner] - b[inner]).max() < 1e-15
     assert np.abs(a[~inner] - b[~inner]).max() > 1e-3
+
+
+# --------------------------------------------------------------- even-odd
+def _dense_Dhat(U, kappa, dims, dagger=False):
+    Ve = synth.volume(dims) // 2
+    I = np.eye(12 * Ve, dtype=np.complex128)
+    return np.column_stack([W.apply_Dhat(U, I[:, k].reshape(Ve, 4, 3), kappa, dims, dagger=dagger).ravel()
+                            for k in range(12 * Ve)])
+
+
+def test_eo_schur_complement_solves_the_full_system():
+    """D x = b  <=>  Dhat x_e = b_e + kappa H_eo b_o and x_o = b_o + kappa H_oe x_e,
+    checked against LAPACK on the full matrix built site by site."""
+    dims, kappa = (4, 2, 2, 4), 0.12
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.5, 31)
+    b = synth.gaussian_spinor(V, 32)
+    x = np.linalg.solve(W.dense_D(U, kappa, dims), b.ravel()).reshape(V, 4, 3)
+    par = W.parity(dims)
+    be = W.eo_prepare(U, b, kappa, dims)
+    xe = x[par == 0]
+    assert np.abs(W.apply_Dhat(U, xe, kappa, dims) - be).max() <= 1e-12 * np.abs(be).max()
+    xr = W.eo_reconstruct(U, xe, b, kappa, dims)
+    assert np.abs(xr - x).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_eo_spectrum_is_lambda_times_two_minus_lambda():
+    """H anticommutes with the parity sign, so spec(D) comes in pairs (lambda,
+    2 - lambda) and spec(Dhat) = {lambda (2 - lambda)}, each value once."""
+    dims, kappa = (4, 2, 2, 4), 0.13
+    U = synth.random_su3_links(dims, 0.5, 41)
+    lam = np.linalg.eigvals(W.dense_D(U, kappa, dims))
+    mu = np.linalg.eigvals(_dense_Dhat(U, kappa, dims))
+    assert _match_spectra(lam * (2 - lam), np.concatenate([mu, mu])) < 1e-10
+
+
+def test_eo_free_field_closed_form():
+    """Unit links: spec(Dhat) = {lambda (2 - lambda)} with the free-field closed form of lambda."""
+    dims, kappa = (4, 2, 2, 4), 0.11
+    lam = W.free_field_spectrum(kappa, dims)
+    mu = np.linalg.eigvals(_dense_Dhat(synth.unit_links(dims), kappa, dims))
+    assert _match_spectra(lam * (2 - lam), np.concatenate([mu, mu])) < 1e-12
+
+
+def test_eo_adjoint_and_gamma5():
+    """<y, Dhat x> = <Dhat^+ y, x> and gamma5 Dhat gamma5 = Dhat^+ (Dhat^+ from the adjoint hops)."""
+    dims, kappa = (4, 4, 2, 4), 0.12
+    U = synth.random_su3_links(dims, 0.3, 51)
+    Ve = synth.volume(dims) // 2
+    x, y = synth.gaussian_spinor(Ve, 52), synth.gaussian_spinor(Ve, 53)
+    a = np.vdot(y, W.apply_Dhat(U, x, kappa, dims))
+    b = np.vdot(W.apply_Dhat(U, y, kappa, dims, dagger=True), x)
+    assert abs(a - b) <= 1e-13 * abs(a)
+    lhs = W.apply_gamma5(W.apply_Dhat(U, W.apply_gamma5(x), kappa, dims))
+    rhs = W.apply_Dhat(U, x, kappa, dims, dagger=True)
+    assert np.abs(lhs - rhs).max() <= 1e-14 * np.abs(rhs).max() * 10
+
+
+def test_eo_rejects_odd_extent():
+    with pytest.raises(ValueError):
+        W.apply_Dhat(synth.unit_links((3, 2, 2, 2)), np.zeros((12, 4, 3), complex), 0.1, (3, 2, 2, 2))
