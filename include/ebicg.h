@@ -107,6 +107,23 @@ typedef struct {
  * (its 2 K FP64 spinors are allocated on first use).  Device: the current HIP device. */
 eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t,
                        int32_t defl_capacity, eb_op **out);
+/* An operator whose solves run on the even-odd (Schur) form, as the paper's
+ * test matrices are even-odd preconditioned (Sec. 3).  With H the hop sum
+ * (D = 1 - kappa H; H connects sites of opposite parity x+y+z+t), the solvers
+ * work on Dhat = 1 - kappa^2 H_eo H_oe over the even sites:
+ *   Dhat x_e = b_e + kappa H_eo b_o,   x_o = b_o + kappa H_oe x_e.
+ * Every extent must be even (EB_ERR_INVALID otherwise).  The entry points
+ * keep their full-lattice canonical arguments: eb_op_apply / _dagger apply the
+ * full D; eb_eigbicg_solve and eb_deflated_bicg_solve take b and x on the full
+ * lattice (the odd part of the start x is ignored), stop when the even
+ * system's residual is tol ||b||, and report the full system's
+ * ||b - D x|| / ||b|| as true_rel_resid; their deflation space holds
+ * eigenvectors of Dhat (V/2 sites), which eb_get_eigenpairs returns as
+ * full-lattice spinors with zero odd part.  Deflated solves run in FP64
+ * (inner = EB_FP64, one right-hand side at a time); eb_op_apply_block is not
+ * available.  Memory: the FP64 links twice (full and per parity). */
+eb_status eb_op_create_eo(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t,
+                          int32_t defl_capacity, eb_op **out);
 eb_status eb_op_destroy(eb_op *op);
 
 /* out = D in, and out = D^+ in (Alg. eigBiCG, first step of the loop).  in/out:
@@ -114,6 +131,13 @@ eb_status eb_op_destroy(eb_op *op);
  * Asynchronous on `stream`. */
 eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
 eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
+
+/* For an even-odd operator (eb_op_create_eo): out = Dhat in_e (dagger = 0) or
+ * Dhat^+ in_e (dagger = 1), Dhat = 1 - kappa^2 H_eo H_oe (Sec. 3's even-odd
+ * preconditioned matrices).  in/out: device FP64 canonical full-lattice
+ * spinors; the odd sites of in are ignored and those of out are zero.
+ * EB_ERR_INVALID for an operator made by eb_op_create.  Asynchronous. */
+eb_status eb_op_apply_schur(eb_op *op, void *out, const void *in, int32_t dagger, void *stream);
 
 /* out_i = D in_i (dagger = 0) or D^+ in_i (dagger = 1) for k right-hand sides
  * at once, k in {1, 2, 4, 8, 16}: one pass over the links serves all k

@@ -32,6 +32,7 @@ SOURCES = [
     ("api.hip", "hip"),
     ("tsmm.hip", "hip"),
     ("batch.hip", "hip"),
+    ("eo.hip", "hip"),
     ("hostla.cpp", "host"),
 ]
 

@@ -123,7 +123,9 @@ struct PinnedBuf {
 // ============================================================================
 struct eb_op {
   Geom g{};
-  size_t N = 0;
+  size_t N = 0;  // length of the solvers' spinors: 12 V, or 12 V / 2 for an even-odd operator
+  bool eo = false;  // the solvers run on the even-site Schur complement (eo.hip)
+  DevBuf Ueo;       // its links, [parity][4][9][V/2]
   double kappa = 0;
   int bc_t = -1;
   int device = 0;
@@ -210,6 +212,7 @@ struct eb_op {
   }
   void free_all() {
     U64.release();
+    Ueo.release();
     U32.release();
     U16.release();
     Ul.release();
@@ -311,10 +314,25 @@ Poller::Poller(eb_op *op, const KrylovState *d, hipStream_t st, int nstates) : d
   ev = op->poll_ev;
 }
 
-// r = b - D x in FP64; returns (||r||, ||b||).
+// The operator of the solvers: the Wilson D, or for an even-odd operator the
+// Schur complement Dhat on the even sites (one odd-site scratch spinor).
+void residual_launch(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s) {
+  if (op->eo)
+    launch_residual_eo(r, b, x, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, op->res.as<double>(),
+                       op->rs(), s);
+  else
+    launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+}
+void apply64(eb_op *op, double2 *out, const double2 *in, bool dagger, hipStream_t s) {
+  if (op->eo)
+    launch_schur_eo(out, in, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, dagger, s);
+  else
+    launch_dslash_f64(out, in, op->U64.as<double2>(), op->g, op->kappa, dagger, s);
+}
+
+// r = b - A x in FP64; returns (||r||, ||b||).
 std::pair<double, double> residual(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s) {
-  TIMED(EB_K_RESIDUAL, s,
-        launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s));
+  TIMED(EB_K_RESIDUAL, s, residual_launch(op, r, b, x, s));
   HIPCHK(hipMemcpyAsync(op->hres.p, op->res.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const double *h = op->hres.as<double>();
@@ -375,6 +393,25 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
     out.rnorm = hs.rnorm;
     return out;
   }
+  // v = A p and t = A s with their dots: the Wilson stencil, or Dhat (FP64)
+  auto stab_v = [&](int j) {
+    if constexpr (std::is_same<S, double2>::value) {
+      if (op->eo) {
+        launch_stab_v_eo(v, p, rhat, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, j, K, op->rs(), s);
+        return;
+      }
+    }
+    launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s);
+  };
+  auto stab_t = [&](int j) {
+    if constexpr (std::is_same<S, double2>::value) {
+      if (op->eo) {
+        launch_stab_t_eo(t, sv, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, j, K, op->rs(), s);
+        return;
+      }
+    }
+    launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s);
+  };
   const int poll = 8;
   int j = 0;
   bool stopped = false;
@@ -382,9 +419,9 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
     Poller pl(op, K, s);
     while (j < maxiter) {
       ++j;
-      TIMED(EB_K_STAB_V, s, launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_V, s, stab_v(j));
       TIMED(EB_K_STAB_S, s, launch_stab_s<S>(sv, r, v, N, j, K, h, op->rs(), s));
-      TIMED(EB_K_STAB_T, s, launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_T, s, stab_t(j));
       TIMED(EB_K_STAB_XR, s, launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, h, op->rs(), s));
       TIMED(EB_K_STAB_P, s, launch_stab_p<S>(p, r, v, N, j, K, h, op->rs(), s));
       if (j % poll == 0 && pl.step(&hs)) {
@@ -924,7 +961,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
 
   EigBiCGOut out;
   // r_0 in V slot 0, rhat_0 in W slot 0
-  launch_residual_f64(V(0), b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+  residual_launch(op, V(0), b, x, s);
   launch_bicg_init(g5 ? nullptr : W(0), p, g5 ? nullptr : ph, V(0), op->res.as<double>(), N, P.rhat, op->g, P.tol,
                    P.maxiter, S, dh, op->rs(), s);
   KrylovState hs;
@@ -1074,8 +1111,11 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       if (j > P.maxiter + 1) break;
       const int cur = j & 1, prv = cur ^ 1;
       TIMED(EB_K_BICG_MATVEC, s,
-            launch_bicg_matvec(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
-                               op->U64.as<double2>(), op->g, op->kappa, j, S, dh, op->rs(), g5, s));
+            op->eo ? launch_bicg_matvec_eo(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
+                                           op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, j, S,
+                                           op->rs(), g5, s)
+                   : launch_bicg_matvec(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
+                                        op->U64.as<double2>(), op->g, op->kappa, j, S, dh, op->rs(), g5, s));
       if (int(cols.size()) == m) {
         // Restart at iteration j (vs = m).  q = A p and s = A^+ phat were kept
         // from iteration j-1 (vs = m-1) in the other buffer.
@@ -1298,12 +1338,8 @@ int absorb(eb_op *op, int nnew, eb_stats &st, hipStream_t s) {
   // A V', A^+ W'
   double2 *AV = op->vec("abs_AV", kept), *AdW = op->vec("abs_AdW", kept);
   for (int k = 0; k < kept; ++k) {
-    TIMED(EB_K_DSLASH, s,
-          launch_dslash_f64(AV + size_t(k) * N, Vn + size_t(k) * N, op->U64.as<double2>(), op->g, op->kappa, false,
-                            s));
-    TIMED(EB_K_DSLASH, s,
-          launch_dslash_f64(AdW + size_t(k) * N, Wn + size_t(k) * N, op->U64.as<double2>(), op->g, op->kappa, true,
-                            s));
+    TIMED(EB_K_DSLASH, s, apply64(op, AV + size_t(k) * N, Vn + size_t(k) * N, false, s));
+    TIMED(EB_K_DSLASH, s, apply64(op, AdW + size_t(k) * N, Wn + size_t(k) * N, true, s));
   }
   st.matvec_d += kept;
   st.matvec_ddag += kept;
@@ -1350,8 +1386,8 @@ void ensure_space(eb_op *op) {
 // ============================================================================
 extern "C" {
 
-eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t, int32_t defl_capacity,
-                       eb_op **out) {
+static eb_status create_impl(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t,
+                             int32_t defl_capacity, eb_op **out, bool eo) {
   return guarded([&]() {
     if (!out || !gauge || !dims) fail(EB_ERR_INVALID, "null argument");
     *out = nullptr;
@@ -1360,12 +1396,15 @@ eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4],
     if (!std::isfinite(kappa)) fail(EB_ERR_INVALID, "kappa must be finite");
     if (bc_t != 1 && bc_t != -1) fail(EB_ERR_INVALID, "bc_t must be +1 or -1");
     if (defl_capacity < 0 || defl_capacity > kMaxCols) fail(EB_ERR_INVALID, "defl_capacity out of range [0, 128]");
+    if (eo && (dims[0] % 2 || dims[1] % 2 || dims[2] % 2 || dims[3] % 2))
+      fail(EB_ERR_INVALID, "the even-odd form needs even lattice extents");
     const long long V = 1LL * dims[0] * dims[1] * dims[2] * dims[3];
     if (V > kMaxVolume) fail(EB_ERR_INVALID, "lattice too large (V > " + std::to_string(kMaxVolume) + ")");
     std::unique_ptr<eb_op> op(new eb_op);
     HIPCHK(hipGetDevice(&op->device));
     op->g = Geom{dims[0], dims[1], dims[2], dims[3], int(V)};
-    op->N = size_t(V) * 12;
+    op->eo = eo;
+    op->N = size_t(V) * 12 / (eo ? 2 : 1);
     op->kappa = kappa;
     op->bc_t = bc_t;
     op->Kcap = defl_capacity;
@@ -1379,11 +1418,24 @@ eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4],
     tmp.ensure(size_t(36) * V * sizeof(double2));
     HIPCHK(hipMemcpy(tmp.p, gauge, size_t(36) * V * sizeof(double2), hipMemcpyHostToDevice));
     launch_pack_gauge_f64(op->U64.as<double2>(), tmp.as<double2>(), op->g, bc_t, nullptr);
+    if (eo) {
+      op->Ueo.ensure(size_t(36) * V * sizeof(double2));
+      launch_pack_gauge_eo(op->Ueo.as<double2>(), tmp.as<double2>(), op->g, bc_t, nullptr);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipDeviceSynchronize());
     tmp.release();
     *out = op.release();
   });
+}
+
+eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t, int32_t defl_capacity,
+                       eb_op **out) {
+  return create_impl(gauge, kappa, dims, bc_t, defl_capacity, out, false);
+}
+eb_status eb_op_create_eo(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t,
+                          int32_t defl_capacity, eb_op **out) {
+  return create_impl(gauge, kappa, dims, bc_t, defl_capacity, out, true);
 }
 
 eb_status eb_op_destroy(eb_op *op) {
@@ -1402,9 +1454,10 @@ static eb_status apply_impl(eb_op *op, void *out, const void *in, eb_prec prec, 
     if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t N = op->N;
+    // the full lattice (an even-odd operator's solver spinors hold half of it)
+    const size_t N = size_t(op->g.V) * 12;
     if (prec == EB_FP64) {
-      double2 *a = op->vec("apply_a"), *b = op->vec("apply_b");
+      double2 *a = op->vec("apply_a", op->eo ? 2 : 1), *b = op->vec("apply_b", op->eo ? 2 : 1);
       launch_to_soa_f64(a, static_cast<const double2 *>(in), op->g, s);
       TIMED(EB_K_DSLASH, s, launch_dslash_f64(b, a, op->U64.as<double2>(), op->g, op->kappa, dagger, s));
       launch_from_soa_f64(static_cast<double2 *>(out), b, op->g, s);
@@ -1429,11 +1482,79 @@ static eb_status apply_impl(eb_op *op, void *out, const void *in, eb_prec prec, 
   });
 }
 
+eb_status eb_op_apply_schur(eb_op *op, void *out, const void *in, int32_t dagger, void *stream) {
+  return guarded([&]() {
+    if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
+    if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
+    if (!op->eo) fail(EB_ERR_INVALID, "eb_op_apply_schur needs an even-odd operator (eb_op_create_eo)");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2 *a = op->vec("schur_a"), *b = op->vec("schur_b");
+    launch_to_eo(a, op->vec("schur_odd"), static_cast<const double2 *>(in), op->g, s);
+    TIMED(EB_K_DSLASH, s, apply64(op, b, a, dagger != 0, s));
+    launch_from_eo(static_cast<double2 *>(out), b, nullptr, op->g, s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
 eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *stream) {
   return apply_impl(op, out, in, prec, stream, false);
 }
 eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream) {
   return apply_impl(op, out, in, prec, stream, true);
+}
+
+// A canonical right-hand side and start vector -> the solvers' vectors b, x.
+// Wilson D: SoA copies; returns 1.  Even-odd: b = b_e + kappa H_eo b_o and
+// x = x_e (b_o is kept for the reconstruction); returns ||b|| / ||b_hat||, the
+// factor that turns a tolerance relative to the full right-hand side into one
+// relative to the even system's (the residual of the full system with x_o
+// reconstructed equals the even system's).
+double load_system(eb_op *op, const double2 *b_can, const double2 *x_can, double2 *b, double2 *x, hipStream_t s) {
+  if (!op->eo) {
+    launch_to_soa_f64(b, b_can, op->g, s);
+    launch_to_soa_f64(x, x_can, op->g, s);
+    return 1.0;
+  }
+  const size_t N = op->N;
+  double2 *be = op->vec("eo_be"), *bo = op->vec("eo_bo"), *xo = op->vec("eo_xo");
+  launch_to_eo(be, bo, b_can, op->g, s);
+  launch_to_eo(x, xo, x_can, op->g, s);
+  launch_prep_eo(b, be, bo, op->g, op->Ueo.as<double2>(), op->kappa, 0, s);
+  double2 *nr = op->raw<double2>("eo_norms", 3 * sizeof(double2));
+  launch_ts_dot(nr, be, N, 1, be, N, 1, N, op->rs(), s);
+  launch_ts_dot(nr + 1, bo, N, 1, bo, N, 1, N, op->rs(), s);
+  launch_ts_dot(nr + 2, b, N, 1, b, N, 1, N, op->rs(), s);
+  double2 h[3];
+  HIPCHK(hipMemcpyAsync(h, nr, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double bfull = std::sqrt(h[0].x + h[1].x), bhat = std::sqrt(h[2].x);
+  return bhat > 0 ? bfull / bhat : 1.0;
+}
+
+// The solvers' x -> canonical x_can (even-odd: x_o = b_o + kappa H_oe x_e,
+// with b_o from the matching load_system).
+void store_solution(eb_op *op, const double2 *x, double2 *x_can, hipStream_t s) {
+  if (!op->eo) {
+    launch_from_soa_f64(x_can, x, op->g, s);
+    return;
+  }
+  double2 *xo = op->vec("eo_xo");
+  launch_prep_eo(xo, op->vec("eo_bo"), x, op->g, op->Ueo.as<double2>(), op->kappa, 1, s);
+  launch_from_eo(x_can, x, xo, op->g, s);
+}
+
+// ||b - D x|| / ||b|| of canonical vectors on the full lattice (FP64).
+double full_rel_residual(eb_op *op, const double2 *b_can, const double2 *x_can, hipStream_t s) {
+  const size_t halves = op->eo ? 2 : 1;
+  double2 *b = op->vec("full_b", halves), *x = op->vec("full_x", halves), *r = op->vec("full_r", halves);
+  launch_to_soa_f64(b, b_can, op->g, s);
+  launch_to_soa_f64(x, x_can, op->g, s);
+  launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, op->res.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
 }
 
 eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_eig_params *P, double *ritz,
@@ -1450,10 +1571,15 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
     double2 *b = op->vec("solve_b"), *x = op->vec("solve_x");
-    launch_to_soa_f64(b, static_cast<const double2 *>(b_can), op->g, s);
-    launch_to_soa_f64(x, static_cast<const double2 *>(x_can), op->g, s);
+    const double2 *bcan = static_cast<const double2 *>(b_can);
+    double2 *xcan = static_cast<double2 *>(x_can);
+    // tolerance on the solvers' system (the even system of an even-odd operator)
+    const double scale = load_system(op, bcan, xcan, b, x, s);
+    eb_eig_params Ps = *P;
+    Ps.tol = P->tol * scale;
+    const double tol = Ps.tol;
     if (op->K > 0) deflate_guess(op, b, x, s);
-    EigBiCGOut R = run_eigbicg(op, b, x, *P, s);
+    EigBiCGOut R = run_eigbicg(op, b, x, Ps, s);
     st.iters = R.iters;
     st.matvec_d = R.iters + 1;
     st.matvec_ddag = P->rhat == 2 ? 0 : R.iters;
@@ -1467,26 +1593,27 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     // true residual in FP64; continue with BiCGStab if the recursion drifted
     double2 *r = op->vec("solve_r");
     auto [rn, bn] = residual(op, r, b, x, s);
-    st.rec_rel_resid = bn > 0 ? R.rnorm / bn : 0;
+    st.rec_rel_resid = bn > 0 ? R.rnorm / (bn * scale) : 0;
     st.true_rel_resid = bn > 0 ? rn / bn : 0;
-    if (bn > 0 && rn > P->tol * bn) {
+    if (bn > 0 && rn > tol * bn) {
       const int K0 = op->K;
       op->K = 0;  // the pairs of this solve are not absorbed yet; continue undeflated
       try {
-        deflated_stab_f64(op, b, x, P->tol, 0.0, P->maxiter + st.iters, st, s);
+        deflated_stab_f64(op, b, x, tol, 0.0, P->maxiter + st.iters, st, s);
       } catch (...) {
         op->K = K0;
         throw;
       }
       op->K = K0;
     }
-    if (R.reason == 4 && st.true_rel_resid > P->tol) {
-      launch_from_soa_f64(static_cast<double2 *>(x_can), x, op->g, s);
+    if (R.reason == 4 && st.true_rel_resid > tol) {
+      store_solution(op, x, xcan, s);
       HIPCHK(hipStreamSynchronize(s));
       fail(EB_ERR_NOT_CONVERGED, "eigBiCG: maxiter reached");
     }
     if (R.nvec > 0) st.nev_added = absorb(op, R.nvec, st, s);
-    launch_from_soa_f64(static_cast<double2 *>(x_can), x, op->g, s);
+    store_solution(op, x, xcan, s);
+    if (op->eo) st.true_rel_resid = full_rel_residual(op, bcan, xcan, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
   });
@@ -1507,6 +1634,8 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
       fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
     if (P->batch != 0 && !batch_size_ok(P->batch)) fail(EB_ERR_INVALID, "batch must be 0, 1, 2, 4, 8 or 16");
+    if (op->eo && P->inner != EB_FP64)
+      fail(EB_ERR_INVALID, "an even-odd operator solves in FP64 only (inner = EB_FP64)");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
@@ -1521,27 +1650,37 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
       worst = std::max(worst, sc.true_rel_resid);
       st.true_rel_resid = worst;
     };
-    const int kmax = (P->deftol > 0 || P->nrhs == 1) ? 1 : (P->batch ? P->batch : choose_batch(op, P->inner, s));
+    const int kmax =
+        (op->eo || P->deftol > 0 || P->nrhs == 1) ? 1 : (P->batch ? P->batch : choose_batch(op, P->inner, s));
+    const size_t Ncan = size_t(op->g.V) * 12;  // canonical spinor length
     int c0 = 0;
     while (c0 < P->nrhs) {
       int kc = 1;
       while (kc * 2 <= kmax && c0 + kc * 2 <= P->nrhs) kc *= 2;
-      const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c0) * op->N;
-      double2 *xc = static_cast<double2 *>(x_can) + size_t(c0) * op->N;
+      const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c0) * Ncan;
+      double2 *xc = static_cast<double2 *>(x_can) + size_t(c0) * Ncan;
       double2 *b = op->vec("solve_b", kc), *x = op->vec("solve_x", kc);
-      for (int c = 0; c < kc; ++c) {
-        launch_to_soa_f64(b + c * op->N, bc + c * op->N, op->g, s);
-        launch_to_soa_f64(x + c * op->N, xc + c * op->N, op->g, s);
+      double scale = 1.0;
+      if (kc == 1) {
+        scale = load_system(op, bc, xc, b, x, s);
+      } else {
+        for (int c = 0; c < kc; ++c) {
+          launch_to_soa_f64(b + c * op->N, bc + c * op->N, op->g, s);
+          launch_to_soa_f64(x + c * op->N, xc + c * op->N, op->g, s);
+        }
       }
       eb_stats sc = zero_stats();
       auto store = [&]() {
-        for (int c = 0; c < kc; ++c) launch_from_soa_f64(xc + c * op->N, x + c * op->N, op->g, s);
+        if (kc == 1)
+          store_solution(op, x, xc, s);
+        else
+          for (int c = 0; c < kc; ++c) launch_from_soa_f64(xc + c * op->N, x + c * op->N, op->g, s);
       };
       try {
         if (kc == 1) {
           if (op->K > 0) deflate_guess(op, b, x, s);
           if (P->inner == EB_FP64)
-            deflated_stab_f64(op, b, x, P->tol, P->deftol, P->maxiter, sc, s);
+            deflated_stab_f64(op, b, x, P->tol * scale, P->deftol, P->maxiter, sc, s);
           else if (P->inner == EB_FP32)
             mixed_stab<float2>(op, b, x, P->tol, inner_tol, P->maxiter, sc, s);
           else
@@ -1563,6 +1702,10 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
         throw;
       }
       store();
+      if (op->eo) {  // the full system's residual; the recursive one relative to ||b||
+        sc.true_rel_resid = full_rel_residual(op, bc, xc, s);
+        sc.rec_rel_resid /= scale;
+      }
       merge(sc);
       c0 += kc;
     }
@@ -1581,6 +1724,7 @@ eb_status eb_op_apply_block(eb_op *op, void *out, const void *in, int32_t k, int
     if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
     if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
     if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
+    if (op->eo) fail(EB_ERR_INVALID, "eb_op_apply_block: not available for an even-odd operator");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t n = op->N * size_t(k);
@@ -1648,8 +1792,17 @@ eb_status eb_get_eigenpairs(eb_op *op, int32_t *k, double *evals, void *right, v
       const cd q = c2(hd[1]) / nr;
       launch_scale_f64(rc, make_double2(1.0 / nr, 0), N, s);
       launch_scale_f64(lc, d2(1.0 / std::conj(q)), N, s);
-      if (right) launch_from_soa_f64(static_cast<double2 *>(right) + size_t(c) * N, rc, op->g, s);
-      if (left) launch_from_soa_f64(static_cast<double2 *>(left) + size_t(c) * N, lc, op->g, s);
+      // canonical full-lattice output (even-odd: zero on the odd sites)
+      const size_t Ncan = size_t(op->g.V) * 12;
+      double2 *ro = right ? static_cast<double2 *>(right) + size_t(c) * Ncan : nullptr;
+      double2 *lo = left ? static_cast<double2 *>(left) + size_t(c) * Ncan : nullptr;
+      if (op->eo) {
+        if (ro) launch_from_eo(ro, rc, nullptr, op->g, s);
+        if (lo) launch_from_eo(lo, lc, nullptr, op->g, s);
+      } else {
+        if (ro) launch_from_soa_f64(ro, rc, op->g, s);
+        if (lo) launch_from_soa_f64(lo, lc, op->g, s);
+      }
     }
     HIPCHK(hipStreamSynchronize(s));
   });

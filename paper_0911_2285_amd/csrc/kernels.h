@@ -152,6 +152,35 @@ void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *
                    const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
                    const KrylovState *S, const RedScratch &rs, hipStream_t st);
 
+// ---- even-odd (Schur) form, FP64 (eo.hip) -------------------------------------
+// Half-lattice spinors: SoA [12][V/2] of one parity, sites in increasing order
+// (index s / 2; every extent even).  Links: [parity][4][9][V/2] (pack_gauge_eo).
+// Dhat = 1 - kappa^2 H_eo H_oe on the even sites; tmp is an odd-site scratch spinor.
+bool eo_geometry_ok(const Geom &g);
+void launch_to_eo(double2 *e, double2 *o, const double2 *canon, const Geom &g, hipStream_t st);
+// o may be null: the odd sites of the canonical output are zero
+void launch_from_eo(double2 *canon, const double2 *e, const double2 *o, const Geom &g, hipStream_t st);
+void launch_pack_gauge_eo(double2 *Ueo, const double2 *canon, const Geom &g, int bc_t, hipStream_t st);
+// out = Dhat in (dagger: Dhat^+ in)
+void launch_schur_eo(double2 *out, const double2 *in, double2 *tmp, const double2 *Ueo, const Geom &g, double kappa,
+                     bool dagger, hipStream_t st);
+// out = id + kappa H_{P,1-P} in, P = out_parity: b_hat = b_e + kappa H_eo b_o (P = 0),
+// x_o = b_o + kappa H_oe x_e (P = 1)
+void launch_prep_eo(double2 *out, const double2 *id, const double2 *in, const Geom &g, const double2 *Ueo,
+                    double kappa, int out_parity, hipStream_t st);
+// r = b - Dhat x; res = {||r||^2, ||b||^2} (device)
+void launch_residual_eo(double2 *r, const double2 *b, const double2 *x, double2 *tmp, const double2 *Ueo,
+                        const Geom &g, double kappa, double *res, const RedScratch &rs, hipStream_t st);
+// the BiCG matvec pair on Dhat with the sigma records (as launch_bicg_matvec)
+void launch_bicg_matvec_eo(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, double2 *tmp,
+                           const double2 *Ueo, const Geom &g, double kappa, int j, KrylovState *S,
+                           const RedScratch &rs, bool g5, hipStream_t st);
+// BiCGStab v = Dhat p with (rhat, v), t = Dhat s with (t, s), ||t||^2 (as launch_stab_v/t)
+void launch_stab_v_eo(double2 *v, const double2 *p, const double2 *rhat, double2 *tmp, const double2 *Ueo,
+                      const Geom &g, double kappa, int j, KrylovState *K, const RedScratch &rs, hipStream_t st);
+void launch_stab_t_eo(double2 *t, const double2 *sv, double2 *tmp, const double2 *Ueo, const Geom &g, double kappa,
+                      int j, KrylovState *K, const RedScratch &rs, hipStream_t st);
+
 // ---- tall-skinny projections (FP64) ------------------------------------------------
 // out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i];  X_a = X + a*ldx, Y_b = Y + b*ldy.
 void launch_ts_dot(double2 *out, const double2 *X, size_t ldx, int nx, const double2 *Y, size_t ldy, int ny, size_t N,

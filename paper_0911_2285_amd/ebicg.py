@@ -89,9 +89,11 @@ _lib = None
 _P = ctypes.c_void_p
 _SIGNATURES = [
     ("eb_op_create", ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    ("eb_op_create_eo", ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
     ("eb_op_destroy", ctypes.c_int, [_P]),
     ("eb_op_apply", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     ("eb_op_apply_dagger", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    ("eb_op_apply_schur", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     ("eb_op_apply_block", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
     ("eb_eigbicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_EigParams), _P, ctypes.POINTER(_Stats), _P]),
     ("eb_deflated_bicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_SolveParams), ctypes.POINTER(_Stats), _P]),
@@ -190,8 +192,9 @@ class Operator:
             pass
 
 
-def op_create(gauge, kappa, dims, bc_t=-1, defl_capacity=0):
-    """gauge: complex128 array [4][V][3][3] on the host."""
+def op_create(gauge, kappa, dims, bc_t=-1, defl_capacity=0, eo=False):
+    """gauge: complex128 array [4][V][3][3] on the host.  eo: solves run on the
+    even-odd (Schur) form (eb_op_create_eo); vectors stay full-lattice canonical."""
     dims = tuple(int(d) for d in dims)
     V = int(np.prod(dims))
     g = np.ascontiguousarray(gauge, dtype=np.complex128)
@@ -199,7 +202,8 @@ def op_create(gauge, kappa, dims, bc_t=-1, defl_capacity=0):
         raise ValueError(f"gauge must have 36*V = {36 * V} complex entries")
     d = (ctypes.c_int32 * 4)(*dims)
     h = ctypes.c_void_p()
-    _check(lib().eb_op_create(g.ctypes.data, float(kappa), d, int(bc_t), int(defl_capacity), ctypes.byref(h)))
+    create = lib().eb_op_create_eo if eo else lib().eb_op_create
+    _check(create(g.ctypes.data, float(kappa), d, int(bc_t), int(defl_capacity), ctypes.byref(h)))
     return Operator(h, dims, float(kappa), V)
 
 
@@ -229,6 +233,13 @@ def op_apply_dagger(op, out, inp, prec="fp64", stream=None):
     """out = D^+ inp."""
     _check(lib().eb_op_apply_dagger(op.handle, _spinor_ptr(op, out, prec, "out"), _spinor_ptr(op, inp, prec, "in"),
                                     PREC[prec], _stream(stream)))
+
+
+def op_apply_schur(op, out, inp, dagger=False, stream=None):
+    """out = Dhat inp_e (or Dhat^+) for an even-odd operator; full-lattice FP64
+    canonical tensors, odd sites of inp ignored and of out zero."""
+    _check(lib().eb_op_apply_schur(op.handle, _spinor_ptr(op, out, "fp64", "out"), _spinor_ptr(op, inp, "fp64", "in"),
+                                   int(bool(dagger)), _stream(stream)))
 
 
 def op_apply_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
