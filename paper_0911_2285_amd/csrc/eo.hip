@@ -64,18 +64,18 @@ __global__ void __launch_bounds__(kBlock)
 
 // One direction of the hop onto a parity-P site (half index h): the forward
 // neighbour's half spinor with U_mu(x) (own parity, index h), the backward
-// neighbour's with U_mu(x - mu)^+ (other parity, index hb).
+// neighbour's with U_mu(x - mu)^+ (other parity, index hb).  The input comes
+// through an LDS tile of the same index range as the block's outputs: x and
+// most y neighbours fall inside it.
 template <int MU, int SF>
-__device__ __forceinline__ void hop_dir_eo(cx<double> (&acc)[12], const double2 *__restrict__ in,
+__device__ __forceinline__ void hop_dir_eo(cx<double> (&acc)[12], const TileSrc<double2> &src,
                                            const double2 *__restrict__ Uf, const double2 *__restrict__ Ub, int Vh,
                                            int h, int hf, int hb) {
   cx<double> hh[6];
-  load_project<MU, SF, double2>(hh, in, Vh, hf);
+  load_project_t<MU, SF, double2>(hh, src, hf);
   mult_accum<MU, SF, false, double2>(acc, hh, Uf, Vh, h);
-  hop_fence();
-  load_project<MU, -SF, double2>(hh, in, Vh, hb);
+  load_project_t<MU, -SF, double2>(hh, src, hb);
   mult_accum<MU, -SF, true, double2>(acc, hh, Ub, Vh, hb);
-  hop_fence();
 }
 
 enum EoEpi : int {
@@ -93,22 +93,30 @@ struct EoNV {
 };
 
 // out (parity P, half index) from in (parity 1 - P); SF = -1: H, +1: H^+.
-// A grid-stride loop over the V/2 sites; producers of partial sums write one
-// record per block of the launch.
+// Blocks loop over tiles of kBlock sites; producers of partial sums write one
+// record per block of the launch (blocks beyond the tiles write zeros).
 template <int SF, int E>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
     k_hop_eo(double2 *__restrict__ out, const double2 *__restrict__ in, const double2 *__restrict__ Uf,
              const double2 *__restrict__ Ub, Geom g, int P, double a, const double2 *__restrict__ id,
              const double2 *__restrict__ dv, int j, const KrylovState *S, double *__restrict__ part) {
   if (S && skip_iter(S, j)) return;
   constexpr int NV = EoNV<E>::v;
+  __shared__ double2 tile[12 * kBlock];
   const int Vh = g.V / 2, lxh = g.lx / 2;
   const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
   double v[NV > 0 ? NV : 1];
 #pragma unroll
   for (int k = 0; k < (NV > 0 ? NV : 1); ++k) v[k] = 0.0;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  for (int h = lb * kBlock + int(threadIdx.x); h < Vh; h += int(gridDim.x) * kBlock) {
+  const int ntiles = (Vh + kBlock - 1) / kBlock;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int h0 = T * kBlock, h = h0 + int(threadIdx.x);
+    __syncthreads();  // the previous tile's readers are done
+    stage_tile(tile, in, h0, Vh);
+    __syncthreads();
+    if (h >= Vh) continue;
+    const TileSrc<double2> src{in, tile, h0, Vh};
     const int xh = h % lxh, r1 = h / lxh;
     const int y = r1 % g.ly, r2 = r1 / g.ly;
     const int z = r2 % g.lz, t = r2 / g.lz;
@@ -118,13 +126,13 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
     // z and t first, as in the full-lattice stencil
-    hop_dir_eo<2, SF>(acc, in, Uf, Ub, Vh, h, (z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz) >> 1,
+    hop_dir_eo<2, SF>(acc, src, Uf, Ub, Vh, h, (z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz) >> 1,
                       (z == 0 ? s + (g.lz - 1) * sz : s - sz) >> 1);
-    hop_dir_eo<3, SF>(acc, in, Uf, Ub, Vh, h, (t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt) >> 1,
+    hop_dir_eo<3, SF>(acc, src, Uf, Ub, Vh, h, (t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt) >> 1,
                       (t == 0 ? s + (g.lt - 1) * stt : s - stt) >> 1);
-    hop_dir_eo<0, SF>(acc, in, Uf, Ub, Vh, h, (x == g.lx - 1 ? s - (g.lx - 1) : s + 1) >> 1,
+    hop_dir_eo<0, SF>(acc, src, Uf, Ub, Vh, h, (x == g.lx - 1 ? s - (g.lx - 1) : s + 1) >> 1,
                       (x == 0 ? s + (g.lx - 1) : s - 1) >> 1);
-    hop_dir_eo<1, SF>(acc, in, Uf, Ub, Vh, h, (y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy) >> 1,
+    hop_dir_eo<1, SF>(acc, src, Uf, Ub, Vh, h, (y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy) >> 1,
                       (y == 0 ? s + (g.ly - 1) * sy : s - sy) >> 1);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
