@@ -141,12 +141,13 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // the shadow vectors are never formed (rhat and ph are not written).
 __global__ void __launch_bounds__(kBlock)
     k_bicg_init(double2 *__restrict__ rhat, double2 *__restrict__ p, double2 *__restrict__ ph,
-                const double2 *__restrict__ r, size_t N, int V, int rhat_mode, double *__restrict__ part) {
+                const double2 *__restrict__ r, size_t N, int rhat_mode, double *__restrict__ part) {
   double v[2] = {0.0, 0.0};
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> rv = Store<double2>::ld(r, i);
-    // gamma5 = diag(1, 1, -1, -1): components 6..11 of the SoA layout flip sign
-    cx<double> hv = (rhat_mode != 0 && i >= size_t(6) * V) ? -rv : rv;
+    // gamma5 = diag(1, 1, -1, -1): components 6..11 of the SoA layout, the
+    // second half of the spinor (N = 12 V, or 12 V / 2 on the even sites), flip sign
+    cx<double> hv = (rhat_mode != 0 && i >= N / 2) ? -rv : rv;
     Store<double2>::st(p, i, rv);
     if (rhat_mode != 2) {
       Store<double2>::st(rhat, i, hv);
@@ -699,7 +700,7 @@ void launch_bicg_init(double2 *rhat, double2 *p, double2 *ph, const double2 *r, 
                       int rhat_mode, const Geom &g, double tol, int maxiter, KrylovState *S, KrylovHistory h,
                       const RedScratch &rs, hipStream_t st) {
   const int nb = red_grid(N);
-  EB_LAUNCH(k_bicg_init, dim3(nb), dim3(kBlock), 0, st, rhat, p, ph, r, N, g.V, rhat_mode, region(rs, RG_INIT));
+  EB_LAUNCH(k_bicg_init, dim3(nb), dim3(kBlock), 0, st, rhat, p, ph, r, N, rhat_mode, region(rs, RG_INIT));
   EB_LAUNCH(k_bicg_init_finish, dim3(1), dim3(kBlock), 0, st, region(rs, RG_INIT), nb, res, tol, maxiter, S, h);
 }
 void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
