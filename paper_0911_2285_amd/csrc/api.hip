@@ -126,6 +126,7 @@ struct eb_op {
   size_t N = 0;  // length of the solvers' spinors: 12 V, or 12 V / 2 for an even-odd operator
   bool eo = false;  // the solvers run on the even-site Schur complement (eo.hip)
   DevBuf Ueo;       // its links, [parity][4][9][V/2]
+  DevBuf Ueo32, Ueo16;  // and FP32 / BF16 copies made on first use
   double kappa = 0;
   int bc_t = -1;
   int device = 0;
@@ -213,6 +214,8 @@ struct eb_op {
   void free_all() {
     U64.release();
     Ueo.release();
+    Ueo32.release();
+    Ueo16.release();
     U32.release();
     U16.release();
     Ul.release();
@@ -393,24 +396,20 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
     out.rnorm = hs.rnorm;
     return out;
   }
-  // v = A p and t = A s with their dots: the Wilson stencil, or Dhat (FP64)
+  // v = A p and t = A s with their dots: the Wilson stencil, or Dhat (U then
+  // holds the even-odd links in storage S, and tmp is an odd-site scratch)
+  S *tmp = op->eo ? op->raw<S>(tag + "eo_tmp", N * sizeof(S)) : nullptr;
   auto stab_v = [&](int j) {
-    if constexpr (std::is_same<S, double2>::value) {
-      if (op->eo) {
-        launch_stab_v_eo(v, p, rhat, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, j, K, op->rs(), s);
-        return;
-      }
-    }
-    launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s);
+    if (op->eo)
+      launch_stab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, K, op->rs(), s);
+    else
+      launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s);
   };
   auto stab_t = [&](int j) {
-    if constexpr (std::is_same<S, double2>::value) {
-      if (op->eo) {
-        launch_stab_t_eo(t, sv, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, j, K, op->rs(), s);
-        return;
-      }
-    }
-    launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s);
+    if (op->eo)
+      launch_stab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, K, op->rs(), s);
+    else
+      launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s);
   };
   const int poll = 8;
   int j = 0;
@@ -456,7 +455,8 @@ void deflated_stab_f64(eb_op *op, const double2 *b, double2 *x, double tol, doub
     int left = maxiter - st.iters;
     if (left <= 0) fail(EB_ERR_NOT_CONVERGED, "deflated solve: maxiter reached");
     const double def_thr = (op->K > 0 && deftol > 0) ? thr_factor * bn : 0.0;
-    StabResult R = run_bicgstab<double2>(op, op->U64.as<double2>(), x, r, tol * bn, def_thr, left, "f64_", s);
+    const double2 *U = op->eo ? op->Ueo.as<double2>() : op->U64.as<double2>();
+    StabResult R = run_bicgstab<double2>(op, U, x, r, tol * bn, def_thr, left, "f64_", s);
     st.iters += R.iters;
     st.matvec_d += 2 * R.iters;
     st.rec_rel_resid = R.rnorm / bn;
@@ -478,6 +478,10 @@ struct Inner<double2> {
   static constexpr const char *tag = "f64_";
   static constexpr int index = 0;
   static const double2 *links(eb_op *op, hipStream_t) { return op->U64.as<double2>(); }
+  // the links of the operator the solvers run on (even-odd: per parity)
+  static const double2 *solver_links(eb_op *op, hipStream_t s) {
+    return op->eo ? op->Ueo.as<double2>() : links(op, s);
+  }
   static void down(double2 *d, const double2 *x, size_t n, hipStream_t s) { launch_copy_f64(d, x, n, s); }
   static void up(double2 *d, const double2 *x, size_t n, hipStream_t s) { launch_copy_f64(d, x, n, s); }
 };
@@ -492,6 +496,14 @@ struct Inner<float2> {
     }
     return op->U32.as<float2>();
   }
+  static const float2 *solver_links(eb_op *op, hipStream_t s) {
+    if (!op->eo) return links(op, s);
+    if (!op->Ueo32.p) {
+      op->Ueo32.ensure(size_t(36) * op->g.V * sizeof(float2));
+      launch_convert_f64_f32(op->Ueo32.as<float2>(), op->Ueo.as<double2>(), size_t(36) * op->g.V, s);
+    }
+    return op->Ueo32.as<float2>();
+  }
   static void down(float2 *d, const double2 *x, size_t n, hipStream_t s) { launch_convert_f64_f32(d, x, n, s); }
   static void up(double2 *d, const float2 *x, size_t n, hipStream_t s) { launch_convert_f32_f64(d, x, n, s); }
 };
@@ -505,6 +517,14 @@ struct Inner<bf16c> {
       launch_convert_f64_bf16(op->U16.as<bf16c>(), op->U64.as<double2>(), size_t(36) * op->g.V, s);
     }
     return op->U16.as<bf16c>();
+  }
+  static const bf16c *solver_links(eb_op *op, hipStream_t s) {
+    if (!op->eo) return links(op, s);
+    if (!op->Ueo16.p) {
+      op->Ueo16.ensure(size_t(36) * op->g.V * sizeof(bf16c));
+      launch_convert_f64_bf16(op->Ueo16.as<bf16c>(), op->Ueo.as<double2>(), size_t(36) * op->g.V, s);
+    }
+    return op->Ueo16.as<bf16c>();
   }
   static void down(bf16c *d, const double2 *x, size_t n, hipStream_t s) { launch_convert_f64_bf16(d, x, n, s); }
   static void up(double2 *d, const bf16c *x, size_t n, hipStream_t s) { launch_convert_bf16_f64(d, x, n, s); }
@@ -522,7 +542,7 @@ template <typename S>
 void mixed_stab(eb_op *op, const double2 *b, double2 *x, double tol, double inner_tol, int maxiter, eb_stats &st,
                 hipStream_t s) {
   const size_t N = op->N;
-  const S *U = Inner<S>::links(op, s);
+  const S *U = Inner<S>::solver_links(op, s);
   const std::string tag = Inner<S>::tag;
   double2 *r = op->vec("mix_r");
   double2 *e64 = op->vec("mix_e64");
@@ -1634,8 +1654,6 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
       fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
     if (P->batch != 0 && !batch_size_ok(P->batch)) fail(EB_ERR_INVALID, "batch must be 0, 1, 2, 4, 8 or 16");
-    if (op->eo && P->inner != EB_FP64)
-      fail(EB_ERR_INVALID, "an even-odd operator solves in FP64 only (inner = EB_FP64)");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);

@@ -67,15 +67,15 @@ __global__ void __launch_bounds__(kBlock)
 // neighbour's with U_mu(x - mu)^+ (other parity, index hb).  The input comes
 // through an LDS tile of the same index range as the block's outputs: x and
 // most y neighbours fall inside it.
-template <int MU, int SF>
-__device__ __forceinline__ void hop_dir_eo(cx<double> (&acc)[12], const TileSrc<double2> &src,
-                                           const double2 *__restrict__ Uf, const double2 *__restrict__ Ub, int Vh,
-                                           int h, int hf, int hb) {
-  cx<double> hh[6];
-  load_project_t<MU, SF, double2>(hh, src, hf);
-  mult_accum<MU, SF, false, double2>(acc, hh, Uf, Vh, h);
-  load_project_t<MU, -SF, double2>(hh, src, hb);
-  mult_accum<MU, -SF, true, double2>(acc, hh, Ub, Vh, hb);
+template <int MU, int SF, typename S>
+__device__ __forceinline__ void hop_dir_eo(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S> &src,
+                                           const S *__restrict__ Uf, const S *__restrict__ Ub, int Vh, int h, int hf,
+                                           int hb) {
+  cx<typename Store<S>::R> hh[6];
+  load_project_t<MU, SF, S>(hh, src, hf);
+  mult_accum<MU, SF, false, S>(acc, hh, Uf, Vh, h);
+  load_project_t<MU, -SF, S>(hh, src, hb);
+  mult_accum<MU, -SF, true, S>(acc, hh, Ub, Vh, hb);
 }
 
 enum EoEpi : int {
@@ -93,16 +93,20 @@ struct EoNV {
 };
 
 // out (parity P, half index) from in (parity 1 - P); SF = -1: H, +1: H^+.
-// Blocks loop over tiles of kBlock sites; producers of partial sums write one
-// record per block of the launch (blocks beyond the tiles write zeros).
-template <int SF, int E>
+// Storage S (FP64, FP32 or BF16 with FP32 arithmetic); the partial sums are
+// FP64.  Blocks loop over tiles of kBlock sites; producers of partial sums
+// write one record per block of the launch (blocks beyond the tiles write
+// zeros).
+template <typename S, int SF, int E>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2)))
-    k_hop_eo(double2 *__restrict__ out, const double2 *__restrict__ in, const double2 *__restrict__ Uf,
-             const double2 *__restrict__ Ub, Geom g, int P, double a, const double2 *__restrict__ id,
-             const double2 *__restrict__ dv, int j, const KrylovState *S, double *__restrict__ part) {
-  if (S && skip_iter(S, j)) return;
+    k_hop_eo(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ Uf, const S *__restrict__ Ub,
+             Geom g, int P, double a_, const S *__restrict__ id, const S *__restrict__ dv, int j,
+             const KrylovState *K, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  if (K && skip_iter(K, j)) return;
   constexpr int NV = EoNV<E>::v;
-  __shared__ double2 tile[12 * kBlock];
+  const R a = R(a_);
+  __shared__ S tile[12 * kBlock];
   const int Vh = g.V / 2, lxh = g.lx / 2;
   const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
   double v[NV > 0 ? NV : 1];
@@ -116,54 +120,53 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
     stage_tile(tile, in, h0, Vh);
     __syncthreads();
     if (h >= Vh) continue;
-    const TileSrc<double2> src{in, tile, h0, Vh};
+    const TileSrc<S> src{in, tile, h0, Vh};
     const int xh = h % lxh, r1 = h / lxh;
     const int y = r1 % g.ly, r2 = r1 / g.ly;
     const int z = r2 % g.lz, t = r2 / g.lz;
     const int x = 2 * xh + ((P + y + z + t) & 1);
     const int s = x + g.lx * r1;
-    cx<double> acc[12];
+    cx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
     // z and t first, as in the full-lattice stencil
-    hop_dir_eo<2, SF>(acc, src, Uf, Ub, Vh, h, (z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz) >> 1,
+    hop_dir_eo<2, SF, S>(acc, src, Uf, Ub, Vh, h, (z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz) >> 1,
                       (z == 0 ? s + (g.lz - 1) * sz : s - sz) >> 1);
-    hop_dir_eo<3, SF>(acc, src, Uf, Ub, Vh, h, (t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt) >> 1,
+    hop_dir_eo<3, SF, S>(acc, src, Uf, Ub, Vh, h, (t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt) >> 1,
                       (t == 0 ? s + (g.lt - 1) * stt : s - stt) >> 1);
-    hop_dir_eo<0, SF>(acc, src, Uf, Ub, Vh, h, (x == g.lx - 1 ? s - (g.lx - 1) : s + 1) >> 1,
+    hop_dir_eo<0, SF, S>(acc, src, Uf, Ub, Vh, h, (x == g.lx - 1 ? s - (g.lx - 1) : s + 1) >> 1,
                       (x == 0 ? s + (g.lx - 1) : s - 1) >> 1);
-    hop_dir_eo<1, SF>(acc, src, Uf, Ub, Vh, h, (y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy) >> 1,
+    hop_dir_eo<1, SF, S>(acc, src, Uf, Ub, Vh, h, (y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy) >> 1,
                       (y == 0 ? s + (g.ly - 1) * sy : s - sy) >> 1);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const size_t i = size_t(c) * Vh + h;
       if constexpr (E == EO_TMP) {
-        out[i] = d2(acc[c]);
+        Store<S>::st(out, i, acc[c]);
       } else if constexpr (E == EO_PREP) {
-        out[i] = d2(c2(id[i]) + a * acc[c]);
+        Store<S>::st(out, i, Store<S>::ld(id, i) + a * acc[c]);
       } else if constexpr (E == EO_RESID) {
-        const cx<double> bv = c2(dv[i]);
-        const cx<double> rv = bv - (c2(id[i]) - a * acc[c]);
-        out[i] = d2(rv);
-        v[0] += rv.x * rv.x + rv.y * rv.y;
-        v[1] += bv.x * bv.x + bv.y * bv.y;
+        const cx<R> bv = Store<S>::ld(dv, i);
+        const cx<R> rv = bv - (Store<S>::ld(id, i) - a * acc[c]);
+        Store<S>::st(out, i, rv);
+        v[0] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+        v[1] += double(bv.x) * bv.x + double(bv.y) * bv.y;
       } else {
-        const cx<double> iv = c2(id[i]);
-        const cx<double> o = iv - a * acc[c];
-        out[i] = d2(o);
-        if constexpr (E == EO_SIGMA) {
-          const cx<double> d = cmulc(c2(dv[i]), o);
-          v[0] += d.x;
-          v[1] += d.y;
-        } else if constexpr (E == EO_SIGMA5) {
-          const cx<double> d = cmulc(iv, o);
-          v[0] += c < 6 ? d.x : -d.x;
-          v[1] += c < 6 ? d.y : -d.y;
-        } else if constexpr (E == EO_STABT) {
-          const cx<double> d = cmulc(o, iv);
-          v[0] += d.x;
-          v[1] += d.y;
-          v[2] += o.x * o.x + o.y * o.y;
+        const cx<R> iv = Store<S>::ld(id, i);
+        const cx<R> o = iv - a * acc[c];
+        Store<S>::st(out, i, o);
+        if constexpr (E == EO_SIGMA) {  // conj(dv) o
+          const cx<R> hv = Store<S>::ld(dv, i);
+          v[0] += double(hv.x) * o.x + double(hv.y) * o.y;
+          v[1] += double(hv.x) * o.y - double(hv.y) * o.x;
+        } else if constexpr (E == EO_SIGMA5) {  // conj(gamma5 id) o
+          const double dr = double(iv.x) * o.x + double(iv.y) * o.y, di = double(iv.x) * o.y - double(iv.y) * o.x;
+          v[0] += c < 6 ? dr : -dr;
+          v[1] += c < 6 ? di : -di;
+        } else if constexpr (E == EO_STABT) {  // conj(o) id, |o|^2
+          v[0] += double(o.x) * iv.x + double(o.y) * iv.y;
+          v[1] += double(o.x) * iv.y - double(o.y) * iv.x;
+          v[2] += double(o.x) * o.x + double(o.y) * o.y;
         }
       }
     }
@@ -180,16 +183,17 @@ __global__ void __launch_bounds__(kBlock) k_eo_finish(const double *__restrict__
 }
 
 inline int eo_grid(const Geom &g) { return stencil_grid(g.V / 2); }
-inline const double2 *links_of(const double2 *Ueo, const Geom &g, int par) {
+template <typename S>
+inline const S *links_of(const S *Ueo, const Geom &g, int par) {
   return Ueo + size_t(par) * 36 * size_t(g.V / 2);
 }
 
 // out (parity P) = epilogue(H_{P, 1-P} in) on `grid` blocks
-template <int SF, int E>
-void hop(double2 *out, const double2 *in, const double2 *Ueo, const Geom &g, int P, double a, const double2 *id,
-         const double2 *dv, int j, const KrylovState *S, double *part, int grid, hipStream_t st) {
-  EB_LAUNCH((k_hop_eo<SF, E>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P), links_of(Ueo, g, 1 - P),
-            g, P, a, id, dv, j, S, part);
+template <int SF, int E, typename S>
+void hop(S *out, const S *in, const S *Ueo, const Geom &g, int P, double a, const S *id, const S *dv, int j,
+         const KrylovState *K, double *part, int grid, hipStream_t st) {
+  EB_LAUNCH((k_hop_eo<S, SF, E>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
+            links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
 }
 
 }  // namespace
@@ -210,26 +214,19 @@ void launch_pack_gauge_eo(double2 *Ueo, const double2 *canon, const Geom &g, int
 
 void launch_schur_eo(double2 *out, const double2 *in, double2 *tmp, const double2 *Ueo, const Geom &g, double kappa,
                      bool dagger, hipStream_t st) {
-  const int G = eo_grid(g);
-  if (dagger) {
-    hop<+1, EO_TMP>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, G, st);
-    hop<+1, EO_SCHUR>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, G, st);
-  } else {
-    hop<-1, EO_TMP>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, G, st);
-    hop<-1, EO_SCHUR>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, G, st);
-  }
+  launch_schur_eo_s<double2>(out, in, tmp, Ueo, g, kappa, dagger, st);
 }
 
 void launch_prep_eo(double2 *out, const double2 *id, const double2 *in, const Geom &g, const double2 *Ueo,
                     double kappa, int out_parity, hipStream_t st) {
-  hop<-1, EO_PREP>(out, in, Ueo, g, out_parity, kappa, id, nullptr, 0, nullptr, nullptr, eo_grid(g), st);
+  hop<-1, EO_PREP, double2>(out, in, Ueo, g, out_parity, kappa, id, nullptr, 0, nullptr, nullptr, eo_grid(g), st);
 }
 
 void launch_residual_eo(double2 *r, const double2 *b, const double2 *x, double2 *tmp, const double2 *Ueo,
                         const Geom &g, double kappa, double *res, const RedScratch &rs, hipStream_t st) {
   const int G = eo_grid(g);
-  hop<-1, EO_TMP>(tmp, x, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, G, st);
-  hop<-1, EO_RESID>(r, tmp, Ueo, g, 0, kappa * kappa, x, b, 0, nullptr, region(rs, RG_RES), G, st);
+  hop<-1, EO_TMP, double2>(tmp, x, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, G, st);
+  hop<-1, EO_RESID, double2>(r, tmp, Ueo, g, 0, kappa * kappa, x, b, 0, nullptr, region(rs, RG_RES), G, st);
   EB_LAUNCH(k_eo_finish<2>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_RES), G, res);
 }
 
@@ -240,28 +237,53 @@ void launch_bicg_matvec_eo(double2 *Ap, double2 *Adp, const double2 *p, const do
   // spinors of length 12 V/2 (one per block of its matvec grid)
   const int G = eo_grid(g), Gs = g5 ? stencil_grid(g.V / 2) : matvec_grid(g.V / 2);
   const double k2 = kappa * kappa;
-  hop<-1, EO_TMP>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, S, nullptr, G, st);
+  hop<-1, EO_TMP, double2>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, S, nullptr, G, st);
   if (g5) {
-    hop<-1, EO_SIGMA5>(Ap, tmp, Ueo, g, 0, k2, p, nullptr, j, S, region(rs, RG_SIGMA), Gs, st);
+    hop<-1, EO_SIGMA5, double2>(Ap, tmp, Ueo, g, 0, k2, p, nullptr, j, S, region(rs, RG_SIGMA), Gs, st);
   } else {
-    hop<-1, EO_SIGMA>(Ap, tmp, Ueo, g, 0, k2, p, ph, j, S, region(rs, RG_SIGMA), Gs, st);
-    hop<+1, EO_TMP>(tmp, ph, Ueo, g, 1, 0.0, nullptr, nullptr, j, S, nullptr, G, st);
-    hop<+1, EO_SCHUR>(Adp, tmp, Ueo, g, 0, k2, ph, nullptr, j, S, nullptr, G, st);
+    hop<-1, EO_SIGMA, double2>(Ap, tmp, Ueo, g, 0, k2, p, ph, j, S, region(rs, RG_SIGMA), Gs, st);
+    hop<+1, EO_TMP, double2>(tmp, ph, Ueo, g, 1, 0.0, nullptr, nullptr, j, S, nullptr, G, st);
+    hop<+1, EO_SCHUR, double2>(Adp, tmp, Ueo, g, 0, k2, ph, nullptr, j, S, nullptr, G, st);
   }
 }
 
-void launch_stab_v_eo(double2 *v, const double2 *p, const double2 *rhat, double2 *tmp, const double2 *Ueo,
-                      const Geom &g, double kappa, int j, KrylovState *K, const RedScratch &rs, hipStream_t st) {
+template <typename S>
+void launch_stab_v_eo(S *v, const S *p, const S *rhat, S *tmp, const S *Ueo, const Geom &g, double kappa, int j,
+                      KrylovState *K, const RedScratch &rs, hipStream_t st) {
   const int G = eo_grid(g);
-  hop<-1, EO_TMP>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, G, st);
-  hop<-1, EO_SIGMA>(v, tmp, Ueo, g, 0, kappa * kappa, p, rhat, j, K, region(rs, RG_V), G, st);
+  hop<-1, EO_TMP, S>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, G, st);
+  hop<-1, EO_SIGMA, S>(v, tmp, Ueo, g, 0, kappa * kappa, p, rhat, j, K, region(rs, RG_V), G, st);
 }
 
-void launch_stab_t_eo(double2 *t, const double2 *sv, double2 *tmp, const double2 *Ueo, const Geom &g, double kappa,
-                      int j, KrylovState *K, const RedScratch &rs, hipStream_t st) {
+template <typename S>
+void launch_stab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, double kappa, int j, KrylovState *K,
+                      const RedScratch &rs, hipStream_t st) {
   const int G = eo_grid(g);
-  hop<-1, EO_TMP>(tmp, sv, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, G, st);
-  hop<-1, EO_STABT>(t, tmp, Ueo, g, 0, kappa * kappa, sv, nullptr, j, K, region(rs, RG_T), G, st);
+  hop<-1, EO_TMP, S>(tmp, sv, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, G, st);
+  hop<-1, EO_STABT, S>(t, tmp, Ueo, g, 0, kappa * kappa, sv, nullptr, j, K, region(rs, RG_T), G, st);
 }
+
+template <typename S>
+void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger,
+                       hipStream_t st) {
+  const int G = eo_grid(g);
+  if (dagger) {
+    hop<+1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, G, st);
+    hop<+1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, G, st);
+  } else {
+    hop<-1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, G, st);
+    hop<-1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, G, st);
+  }
+}
+
+#define EB_EO_INST(S)                                                                                              \
+  template void launch_stab_v_eo<S>(S *, const S *, const S *, S *, const S *, const Geom &, double, int,          \
+                                    KrylovState *, const RedScratch &, hipStream_t);                                \
+  template void launch_stab_t_eo<S>(S *, const S *, S *, const S *, const Geom &, double, int, KrylovState *,       \
+                                    const RedScratch &, hipStream_t);                                               \
+  template void launch_schur_eo_s<S>(S *, const S *, S *, const S *, const Geom &, double, bool, hipStream_t);
+EB_EO_INST(double2)
+EB_EO_INST(float2)
+EB_EO_INST(bf16c)
 
 }  // namespace ebicg

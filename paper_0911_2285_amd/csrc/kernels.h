@@ -175,11 +175,18 @@ void launch_residual_eo(double2 *r, const double2 *b, const double2 *x, double2 
 void launch_bicg_matvec_eo(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, double2 *tmp,
                            const double2 *Ueo, const Geom &g, double kappa, int j, KrylovState *S,
                            const RedScratch &rs, bool g5, hipStream_t st);
-// BiCGStab v = Dhat p with (rhat, v), t = Dhat s with (t, s), ||t||^2 (as launch_stab_v/t)
-void launch_stab_v_eo(double2 *v, const double2 *p, const double2 *rhat, double2 *tmp, const double2 *Ueo,
-                      const Geom &g, double kappa, int j, KrylovState *K, const RedScratch &rs, hipStream_t st);
-void launch_stab_t_eo(double2 *t, const double2 *sv, double2 *tmp, const double2 *Ueo, const Geom &g, double kappa,
-                      int j, KrylovState *K, const RedScratch &rs, hipStream_t st);
+// BiCGStab v = Dhat p with (rhat, v), t = Dhat s with (t, s), ||t||^2 (as launch_stab_v/t);
+// storage S = double2, float2 or bf16c (links in the same storage), FP64 partials.
+template <typename S>
+void launch_stab_v_eo(S *v, const S *p, const S *rhat, S *tmp, const S *Ueo, const Geom &g, double kappa, int j,
+                      KrylovState *K, const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_stab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, double kappa, int j, KrylovState *K,
+                      const RedScratch &rs, hipStream_t st);
+// out = Dhat in (dagger: Dhat^+ in) in storage S
+template <typename S>
+void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger,
+                       hipStream_t st);
 
 // ---- tall-skinny projections (FP64) ------------------------------------------------
 // out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i];  X_a = X + a*ldx, Y_b = Y + b*ldy.
