@@ -567,6 +567,16 @@ def main():
             assert st["true_rel_resid"] <= W["tol"], (name, st)
         torch.cuda.synchronize()
         eo_defl[name] = round((W["nrhs"] - W["n1"]) / (time.perf_counter() - t2), 3)
+    # and in batches (batch chosen by the library)
+    for name, kw in [("fp64_batched", dict()), ("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
+                     ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
+        Xd = torch.zeros_like(Bd)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op_eo, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
+        torch.cuda.synchronize()
+        assert st["true_rel_resid"] <= W["tol"], (name, st)
+        eo_defl[name] = round(nd / (time.perf_counter() - t2), 3)
     eb.op_destroy(op_eo)
     extra["even_odd"] = {
         "solves_per_s": round(W["nrhs"] / dt_e, 3),

@@ -119,9 +119,10 @@ eb_status eb_op_create(const double *gauge, double kappa, const int32_t dims[4],
  * system's residual is tol ||b||, and report the full system's
  * ||b - D x|| / ||b|| as true_rel_resid; their deflation space holds
  * eigenvectors of Dhat (V/2 sites), which eb_get_eigenpairs returns as
- * full-lattice spinors with zero odd part.  Deflated solves run in FP64
- * (inner = EB_FP64, one right-hand side at a time); eb_op_apply_block is not
- * available.  Memory: the FP64 links twice (full and per parity). */
+ * full-lattice spinors with zero odd part.  Deflated solves take every inner
+ * precision and batch size; eb_op_apply_block applies the full D.  Memory: the
+ * FP64 links twice (full and per parity), and per parity in FP32 / BF16 once
+ * a solve uses that inner precision. */
 eb_status eb_op_create_eo(const double *gauge, double kappa, const int32_t dims[4], int32_t bc_t,
                           int32_t defl_capacity, eb_op **out);
 eb_status eb_op_destroy(eb_op *op);
@@ -138,6 +139,17 @@ eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec,
  * spinors; the odd sites of in are ignored and those of out are zero.
  * EB_ERR_INVALID for an operator made by eb_op_create.  Asynchronous. */
 eb_status eb_op_apply_schur(eb_op *op, void *out, const void *in, int32_t dagger, void *stream);
+
+/* For an even-odd operator: out_i = Dhat in_i (dagger = 0) or Dhat^+ in_i
+ * (dagger = 1) for k right-hand sides at once, k in {1, 2, 4, 8, 16} (the
+ * multi-RHS form of eb_op_apply_schur; Sec. 3's even-odd preconditioned
+ * matrices).  in/out: device FP64 canonical full-lattice spinors, k back to
+ * back; the odd sites of in are ignored and those of out are zero.  prec is
+ * the storage of the pass (FP32 / BF16: the inputs and links rounded to it,
+ * arithmetic in FP32, results widened to FP64).  EB_ERR_INVALID for an
+ * operator made by eb_op_create, an unknown prec or k.  Asynchronous. */
+eb_status eb_op_apply_schur_block(eb_op *op, void *out, const void *in, int32_t k, int32_t dagger, eb_prec prec,
+                                  void *stream);
 
 /* out_i = D in_i (dagger = 0) or D^+ in_i (dagger = 1) for k right-hand sides
  * at once, k in {1, 2, 4, 8, 16}: one pass over the links serves all k

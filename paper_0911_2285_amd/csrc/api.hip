@@ -319,12 +319,20 @@ Poller::Poller(eb_op *op, const KrylovState *d, hipStream_t st, int nstates) : d
 
 // The operator of the solvers: the Wilson D, or for an even-odd operator the
 // Schur complement Dhat on the even sites (one odd-site scratch spinor).
-void residual_launch(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s) {
+// residual_launch writes {||r||^2, ||b||^2} to op->res[2 slot], slot < kMaxBatch.
+void residual_launch(eb_op *op, double2 *r, const double2 *b, const double2 *x, hipStream_t s, int slot = 0) {
+  double *res = op->res.as<double>() + 2 * slot;
   if (op->eo)
-    launch_residual_eo(r, b, x, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, op->res.as<double>(),
-                       op->rs(), s);
+    launch_residual_eo(r, b, x, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, res, op->rs(), s);
   else
-    launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, op->res.as<double>(), op->rs(), s);
+    launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, res, op->rs(), s);
+}
+// The geometry the vector passes of the batched BiCGStab see: they use only
+// the site count, V/2 for the even-odd form.
+Geom vector_geom(const eb_op *op) {
+  Geom g = op->g;
+  if (op->eo) g.V /= 2;
+  return g;
 }
 void apply64(eb_op *op, double2 *out, const double2 *in, bool dagger, hipStream_t s) {
   if (op->eo)
@@ -587,10 +595,7 @@ void deflate_block(eb_op *op, const double2 *b, double2 *x, int kc, hipStream_t 
   const size_t N = op->N;
   const int K = op->K;
   double2 *r = op->vec("dfb_r", kc);
-  for (int c = 0; c < kc; ++c)
-    TIMED(EB_K_RESIDUAL, s,
-          launch_residual_f64(r + c * N, b + c * N, x + c * N, op->U64.as<double2>(), op->g, op->kappa,
-                              op->res.as<double>() + 2 * c, op->rs(), s));
+  for (int c = 0; c < kc; ++c) TIMED(EB_K_RESIDUAL, s, residual_launch(op, r + c * N, b + c * N, x + c * N, s, c));
   double2 *C = op->raw<double2>("dfb_c", size_t(K) * kc * sizeof(double2));
   TIMED(EB_K_PROJ, s, launch_ts_dot(C, op->Ul.as<double2>(), N, K, r, N, kc, N, op->rs(), s));
   std::vector<double2> hc(size_t(K) * kc);
@@ -608,16 +613,24 @@ void deflate_block(eb_op *op, const double2 *b, double2 *x, int kc, hipStream_t 
 }
 
 // Columns per batch for the multi-RHS path: timed once per operator and
-// precision.  Each candidate k runs the batched stencil on k columns (three
-// timed repetitions after one warm-up); the k with the lowest time per
-// right-hand side wins.  Ties go to the smaller k (less memory, earlier exit
-// of converged columns).
+// precision.  Each candidate k runs the batched operator of the solvers (the
+// stencil, or Dhat) on k columns (three timed repetitions after one warm-up);
+// the k with the lowest time per right-hand side wins.  Ties go to the smaller
+// k (less memory, earlier exit of converged columns).
 template <typename S>
 int tune_batch(eb_op *op, hipStream_t s) {
-  const S *U = Inner<S>::links(op, s);
+  const S *U = Inner<S>::solver_links(op, s);
   const size_t n = op->N * size_t(kMaxBatch);
-  S *a = op->raw<S>(std::string(Inner<S>::tag) + "b_p", n * sizeof(S));
-  S *b = op->raw<S>(std::string(Inner<S>::tag) + "b_v", n * sizeof(S));
+  const std::string tag = Inner<S>::tag;
+  S *a = op->raw<S>(tag + "b_p", n * sizeof(S));
+  S *b = op->raw<S>(tag + "b_v", n * sizeof(S));
+  S *tmp = op->eo ? op->raw<S>(tag + "b_eo_tmp", n * sizeof(S)) : nullptr;
+  auto apply = [&](int kc) {
+    if (op->eo)
+      launch_bschur_eo<S>(b, a, tmp, U, op->g, op->kappa, false, kc, s);
+    else
+      launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s);
+  };
   HIPCHK(hipMemsetAsync(a, 0, n * sizeof(S), s));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -625,9 +638,9 @@ int tune_batch(eb_op *op, hipStream_t s) {
   int best = 1;
   double best_t = HUGE_VAL;
   for (int kc = 1; kc <= kMaxBatch; kc *= 2) {
-    launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s);
+    apply(kc);
     HIPCHK(hipEventRecord(e0, s));
-    for (int rep = 0; rep < 3; ++rep) launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s);
+    for (int rep = 0; rep < 3; ++rep) apply(kc);
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
@@ -663,6 +676,8 @@ void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double 
   S *v = op->raw<S>(tag + "b_v", n * sizeof(S));
   S *sv = op->raw<S>(tag + "b_s", n * sizeof(S));
   S *t = op->raw<S>(tag + "b_t", n * sizeof(S));
+  S *tmp = op->eo ? op->raw<S>(tag + "b_eo_tmp", n * sizeof(S)) : nullptr;
+  const Geom gv = vector_geom(op);
   KrylovState *K = op->S();
   KrylovHistory h = op->history((maxiter + 4) * kc);
   launch_bstab_init<S>(rhat, p, r, op->N, kc, tol_dev, maxiter, K, h, op->rs(), s);
@@ -679,11 +694,18 @@ void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double 
         break;
       }
       ++j;
-      TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, op->rs(), s));
-      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, op->g, j, kc, K, h, op->rs(), s));
-      TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, op->rs(), s));
-      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, op->g, j, kc, K, h, op->rs(), s));
-      TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, op->g, j, kc, K, h, op->rs(), s));
+      if (op->eo)
+        TIMED(EB_K_BSTAB_V, s,
+              launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+      else
+        TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, op->rs(), s));
+      if (op->eo)
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+      else
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, op->rs(), s));
+      TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, gv, j, kc, K, h, op->rs(), s));
     }
   }
   if (!stopped) {
@@ -699,13 +721,14 @@ void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double 
 
 // kc right-hand sides (FP64 SoA columns b, x; x holds the deflated start):
 // FP64 iterative refinement around one batched low-precision BiCGStab per
-// outer step.  Columns that have converged keep a target of +inf (they stop
-// at initialisation and their correction stays zero).
+// outer step; column c stops at ||r_c|| <= tol[c] ||b_c||.  Columns that have
+// converged keep a target of +inf (they stop at initialisation and their
+// correction stays zero).
 template <typename S>
-void mixed_stab_batch(eb_op *op, const double2 *b, double2 *x, int kc, double tol, double inner_tol, int maxiter,
-                      eb_stats &st, hipStream_t s) {
+void mixed_stab_batch(eb_op *op, const double2 *b, double2 *x, int kc, const double *tol, double inner_tol,
+                      int maxiter, eb_stats &st, hipStream_t s) {
   const size_t N = op->N;
-  const S *U = Inner<S>::links(op, s);
+  const S *U = Inner<S>::solver_links(op, s);
   const std::string tag = Inner<S>::tag;
   double2 *r = op->vec("mb_r", kc);
   S *rl = op->raw<S>(tag + "mb_r", N * kc * sizeof(S));
@@ -716,9 +739,7 @@ void mixed_stab_batch(eb_op *op, const double2 *b, double2 *x, int kc, double to
   std::vector<double> rn(kc), bn(kc);
   while (true) {
     for (int c = 0; c < kc; ++c)
-      TIMED(EB_K_RESIDUAL, s,
-            launch_residual_f64(r + c * N, b + c * N, x + c * N, op->U64.as<double2>(), op->g, op->kappa,
-                                op->res.as<double>() + 2 * c, op->rs(), s));
+      TIMED(EB_K_RESIDUAL, s, residual_launch(op, r + c * N, b + c * N, x + c * N, s, c));
     HIPCHK(hipMemcpyAsync(op->hres.p, op->res.p, 2 * kc * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     st.matvec_d += kc;
@@ -733,14 +754,15 @@ void mixed_stab_batch(eb_op *op, const double2 *b, double2 *x, int kc, double to
       }
       const double rel = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
       worst = std::max(worst, rel);
-      all = all && rel <= tol;
+      all = all && rel <= tol[c];
     }
     st.true_rel_resid = worst;
     if (all) return;
     int left = maxiter - st.iters / kc;
     if (left <= 0 || outer > 200) fail(EB_ERR_NOT_CONVERGED, "batched mixed-precision solve: maxiter reached");
     for (int c = 0; c < kc; ++c)
-      tol_host[c] = (bn[c] == 0 || rn[c] <= tol * bn[c]) ? HUGE_VAL : std::max(inner_tol * rn[c], 0.5 * tol * bn[c]);
+      tol_host[c] =
+          (bn[c] == 0 || rn[c] <= tol[c] * bn[c]) ? HUGE_VAL : std::max(inner_tol * rn[c], 0.5 * tol[c] * bn[c]);
     HIPCHK(hipMemcpyAsync(tol_dev, tol_host, kc * sizeof(double), hipMemcpyHostToDevice, s));
     launch_pack_batch<S>(rl, r, N, kc, s);
     HIPCHK(hipMemsetAsync(el, 0, N * kc * sizeof(S), s));
@@ -1526,18 +1548,19 @@ eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec,
 
 // A canonical right-hand side and start vector -> the solvers' vectors b, x.
 // Wilson D: SoA copies; returns 1.  Even-odd: b = b_e + kappa H_eo b_o and
-// x = x_e (b_o is kept for the reconstruction); returns ||b|| / ||b_hat||, the
-// factor that turns a tolerance relative to the full right-hand side into one
-// relative to the even system's (the residual of the full system with x_o
-// reconstructed equals the even system's).
-double load_system(eb_op *op, const double2 *b_can, const double2 *x_can, double2 *b, double2 *x, hipStream_t s) {
+// x = x_e, with b_o kept in bo (N entries) for the reconstruction; returns
+// ||b|| / ||b_hat||, the factor that turns a tolerance relative to the full
+// right-hand side into one relative to the even system's (the residual of the
+// full system with x_o reconstructed equals the even system's).
+double load_system(eb_op *op, const double2 *b_can, const double2 *x_can, double2 *b, double2 *x, double2 *bo,
+                   hipStream_t s) {
   if (!op->eo) {
     launch_to_soa_f64(b, b_can, op->g, s);
     launch_to_soa_f64(x, x_can, op->g, s);
     return 1.0;
   }
   const size_t N = op->N;
-  double2 *be = op->vec("eo_be"), *bo = op->vec("eo_bo"), *xo = op->vec("eo_xo");
+  double2 *be = op->vec("eo_be"), *xo = op->vec("eo_xo");
   launch_to_eo(be, bo, b_can, op->g, s);
   launch_to_eo(x, xo, x_can, op->g, s);
   launch_prep_eo(b, be, bo, op->g, op->Ueo.as<double2>(), op->kappa, 0, s);
@@ -1553,14 +1576,14 @@ double load_system(eb_op *op, const double2 *b_can, const double2 *x_can, double
 }
 
 // The solvers' x -> canonical x_can (even-odd: x_o = b_o + kappa H_oe x_e,
-// with b_o from the matching load_system).
-void store_solution(eb_op *op, const double2 *x, double2 *x_can, hipStream_t s) {
+// with b_o as kept by the matching load_system).
+void store_solution(eb_op *op, const double2 *x, const double2 *bo, double2 *x_can, hipStream_t s) {
   if (!op->eo) {
     launch_from_soa_f64(x_can, x, op->g, s);
     return;
   }
   double2 *xo = op->vec("eo_xo");
-  launch_prep_eo(xo, op->vec("eo_bo"), x, op->g, op->Ueo.as<double2>(), op->kappa, 1, s);
+  launch_prep_eo(xo, bo, x, op->g, op->Ueo.as<double2>(), op->kappa, 1, s);
   launch_from_eo(x_can, x, xo, op->g, s);
 }
 
@@ -1594,7 +1617,8 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     const double2 *bcan = static_cast<const double2 *>(b_can);
     double2 *xcan = static_cast<double2 *>(x_can);
     // tolerance on the solvers' system (the even system of an even-odd operator)
-    const double scale = load_system(op, bcan, xcan, b, x, s);
+    double2 *bo = op->eo ? op->vec("eo_bo") : nullptr;
+    const double scale = load_system(op, bcan, xcan, b, x, bo, s);
     eb_eig_params Ps = *P;
     Ps.tol = P->tol * scale;
     const double tol = Ps.tol;
@@ -1627,12 +1651,12 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
       op->K = K0;
     }
     if (R.reason == 4 && st.true_rel_resid > tol) {
-      store_solution(op, x, xcan, s);
+      store_solution(op, x, bo, xcan, s);
       HIPCHK(hipStreamSynchronize(s));
       fail(EB_ERR_NOT_CONVERGED, "eigBiCG: maxiter reached");
     }
     if (R.nvec > 0) st.nev_added = absorb(op, R.nvec, st, s);
-    store_solution(op, x, xcan, s);
+    store_solution(op, x, bo, xcan, s);
     if (op->eo) st.true_rel_resid = full_rel_residual(op, bcan, xcan, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
@@ -1668,8 +1692,7 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
       worst = std::max(worst, sc.true_rel_resid);
       st.true_rel_resid = worst;
     };
-    const int kmax =
-        (op->eo || P->deftol > 0 || P->nrhs == 1) ? 1 : (P->batch ? P->batch : choose_batch(op, P->inner, s));
+    const int kmax = (P->deftol > 0 || P->nrhs == 1) ? 1 : (P->batch ? P->batch : choose_batch(op, P->inner, s));
     const size_t Ncan = size_t(op->g.V) * 12;  // canonical spinor length
     int c0 = 0;
     while (c0 < P->nrhs) {
@@ -1678,39 +1701,36 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
       const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c0) * Ncan;
       double2 *xc = static_cast<double2 *>(x_can) + size_t(c0) * Ncan;
       double2 *b = op->vec("solve_b", kc), *x = op->vec("solve_x", kc);
-      double scale = 1.0;
-      if (kc == 1) {
-        scale = load_system(op, bc, xc, b, x, s);
-      } else {
-        for (int c = 0; c < kc; ++c) {
-          launch_to_soa_f64(b + c * op->N, bc + c * op->N, op->g, s);
-          launch_to_soa_f64(x + c * op->N, xc + c * op->N, op->g, s);
-        }
+      double2 *bo = op->eo ? op->vec("eo_bo", kc) : nullptr;
+      // per column: the tolerance on the solvers' system (even-odd: scaled by ||b|| / ||b_hat||)
+      double scale[kMaxBatch], tolc[kMaxBatch];
+      for (int c = 0; c < kc; ++c) {
+        scale[c] = load_system(op, bc + c * Ncan, xc + c * Ncan, b + c * op->N, x + c * op->N,
+                               bo ? bo + c * op->N : nullptr, s);
+        tolc[c] = P->tol * scale[c];
       }
       eb_stats sc = zero_stats();
       auto store = [&]() {
-        if (kc == 1)
-          store_solution(op, x, xc, s);
-        else
-          for (int c = 0; c < kc; ++c) launch_from_soa_f64(xc + c * op->N, x + c * op->N, op->g, s);
+        for (int c = 0; c < kc; ++c)
+          store_solution(op, x + c * op->N, bo ? bo + c * op->N : nullptr, xc + c * Ncan, s);
       };
       try {
         if (kc == 1) {
           if (op->K > 0) deflate_guess(op, b, x, s);
           if (P->inner == EB_FP64)
-            deflated_stab_f64(op, b, x, P->tol * scale, P->deftol, P->maxiter, sc, s);
+            deflated_stab_f64(op, b, x, tolc[0], P->deftol, P->maxiter, sc, s);
           else if (P->inner == EB_FP32)
-            mixed_stab<float2>(op, b, x, P->tol, inner_tol, P->maxiter, sc, s);
+            mixed_stab<float2>(op, b, x, tolc[0], inner_tol, P->maxiter, sc, s);
           else
-            mixed_stab<bf16c>(op, b, x, P->tol, inner_tol, P->maxiter, sc, s);
+            mixed_stab<bf16c>(op, b, x, tolc[0], inner_tol, P->maxiter, sc, s);
         } else {
           deflate_block(op, b, x, kc, s);
           if (P->inner == EB_FP64)
-            mixed_stab_batch<double2>(op, b, x, kc, P->tol, 0.5 * P->tol, P->maxiter, sc, s);
+            mixed_stab_batch<double2>(op, b, x, kc, tolc, 0.5 * P->tol, P->maxiter, sc, s);
           else if (P->inner == EB_FP32)
-            mixed_stab_batch<float2>(op, b, x, kc, P->tol, inner_tol, P->maxiter, sc, s);
+            mixed_stab_batch<float2>(op, b, x, kc, tolc, inner_tol, P->maxiter, sc, s);
           else
-            mixed_stab_batch<bf16c>(op, b, x, kc, P->tol, inner_tol, P->maxiter, sc, s);
+            mixed_stab_batch<bf16c>(op, b, x, kc, tolc, inner_tol, P->maxiter, sc, s);
         }
       } catch (...) {
         // x holds the last iterate and the stats are filled
@@ -1720,9 +1740,12 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
         throw;
       }
       store();
-      if (op->eo) {  // the full system's residual; the recursive one relative to ||b||
-        sc.true_rel_resid = full_rel_residual(op, bc, xc, s);
-        sc.rec_rel_resid /= scale;
+      if (op->eo) {  // the full system's residuals; the recursive one relative to ||b||
+        double worst_full = 0;
+        for (int c = 0; c < kc; ++c)
+          worst_full = std::max(worst_full, full_rel_residual(op, bc + c * Ncan, xc + c * Ncan, s));
+        sc.true_rel_resid = worst_full;
+        if (kc == 1) sc.rec_rel_resid /= scale[0];
       }
       merge(sc);
       c0 += kc;
@@ -1742,10 +1765,9 @@ eb_status eb_op_apply_block(eb_op *op, void *out, const void *in, int32_t k, int
     if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
     if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
     if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
-    if (op->eo) fail(EB_ERR_INVALID, "eb_op_apply_block: not available for an even-odd operator");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t n = op->N * size_t(k);
+    const size_t n = size_t(op->g.V) * 12 * size_t(k);  // the full D, also for an even-odd operator
     auto run = [&](auto *tag, const auto *U) {
       using S = std::remove_pointer_t<decltype(tag)>;
       S *a = op->raw<S>(std::string(Inner<S>::tag) + "blk_a", n * sizeof(S));
@@ -1762,6 +1784,44 @@ eb_status eb_op_apply_block(eb_op *op, void *out, const void *in, int32_t k, int
       run(static_cast<bf16c *>(nullptr), Inner<bf16c>::links(op, s));
     else
       fail(EB_ERR_INVALID, "unknown precision");
+    HIPCHK(hipGetLastError());
+  });
+}
+
+eb_status eb_op_apply_schur_block(eb_op *op, void *out, const void *in, int32_t k, int32_t dagger, eb_prec prec,
+                                  void *stream) {
+  return guarded([&]() {
+    if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
+    if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
+    if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
+    if (!op->eo) fail(EB_ERR_INVALID, "eb_op_apply_schur_block needs an even-odd operator (eb_op_create_eo)");
+    if (prec != EB_FP64 && prec != EB_FP32 && prec != EB_BF16) fail(EB_ERR_INVALID, "unknown precision");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t N = op->N, Ncan = size_t(op->g.V) * 12;
+    double2 *e = op->vec("sblk_e", k), *odd = op->vec("schur_odd");
+    const double2 *inp = static_cast<const double2 *>(in);
+    double2 *outp = static_cast<double2 *>(out);
+    for (int c = 0; c < k; ++c) launch_to_eo(e + c * N, odd, inp + c * Ncan, op->g, s);
+    auto run = [&](auto *tag) {
+      using S = std::remove_pointer_t<decltype(tag)>;
+      const std::string tg = Inner<S>::tag;
+      const S *U = Inner<S>::solver_links(op, s);
+      S *a = op->raw<S>(tg + "sblk_a", N * k * sizeof(S));
+      S *b = op->raw<S>(tg + "sblk_b", N * k * sizeof(S));
+      S *t = op->raw<S>(tg + "sblk_t", N * k * sizeof(S));
+      launch_pack_batch<S>(a, e, N, k, s);
+      TIMED(EB_K_BDSLASH, s, launch_bschur_eo<S>(b, a, t, U, op->g, op->kappa, dagger != 0, k, s));
+      HIPCHK(hipMemsetAsync(e, 0, N * k * sizeof(double2), s));
+      launch_unpack_add_batch<S>(e, b, N, k, s);
+    };
+    if (prec == EB_FP64)
+      run(static_cast<double2 *>(nullptr));
+    else if (prec == EB_FP32)
+      run(static_cast<float2 *>(nullptr));
+    else
+      run(static_cast<bf16c *>(nullptr));
+    for (int c = 0; c < k; ++c) launch_from_eo(outp + c * Ncan, e + c * N, nullptr, op->g, s);
     HIPCHK(hipGetLastError());
   });
 }

@@ -389,31 +389,6 @@ __global__ void __launch_bounds__(kBlock) k_from_batch(S *__restrict__ dst, cons
   }
 }
 
-// grids: records of KC * NV doubles per block must fit one scratch region
-inline int batch_stencil_grid(int V, int kc, int nv) {
-  int nb = nblocks_for(size_t(V) * kc);
-  const int cap = int(kRegion / size_t(kc * nv));
-  nb = nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
-  return nb > cap ? cap : nb;
-}
-inline int batch_red_grid(size_t n, int kc, int nv) {
-  int nb = red_grid(n);
-  const int cap = int(kRegion / size_t(kc * nv));
-  return nb > cap ? cap : nb;
-}
-
-template <typename F>
-void dispatch_kc(int kc, F &&f) {
-  switch (kc) {
-    case 1: f(std::integral_constant<int, 1>{}); break;
-    case 2: f(std::integral_constant<int, 2>{}); break;
-    case 4: f(std::integral_constant<int, 4>{}); break;
-    case 8: f(std::integral_constant<int, 8>{}); break;
-    case 16: f(std::integral_constant<int, 16>{}); break;
-    default: break;  // the host validates kc
-  }
-}
-
 }  // namespace
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }

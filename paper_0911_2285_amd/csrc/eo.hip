@@ -14,6 +14,8 @@
 // at its own index h and its backward link at the neighbour's index.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "kernel_util.h"
 #include "kernels.h"
@@ -67,15 +69,42 @@ __global__ void __launch_bounds__(kBlock)
 // neighbour's with U_mu(x - mu)^+ (other parity, index hb).  The input comes
 // through an LDS tile of the same index range as the block's outputs: x and
 // most y neighbours fall inside it.
-template <int MU, int SF, typename S>
-__device__ __forceinline__ void hop_dir_eo(cx<typename Store<S>::R> (&acc)[12], const TileSrc<S> &src,
+template <int MU, int SF, typename S, typename Src>
+__device__ __forceinline__ void hop_dir_eo(cx<typename Store<S>::R> (&acc)[12], const Src &src,
                                            const S *__restrict__ Uf, const S *__restrict__ Ub, int Vh, int h, int hf,
                                            int hb) {
   cx<typename Store<S>::R> hh[6];
   load_project_t<MU, SF, S>(hh, src, hf);
   mult_accum<MU, SF, false, S>(acc, hh, Uf, Vh, h);
+  if constexpr (Src::kFence) hop_fence();
   load_project_t<MU, -SF, S>(hh, src, hb);
   mult_accum<MU, -SF, true, S>(acc, hh, Ub, Vh, hb);
+  if constexpr (Src::kFence) hop_fence();
+}
+
+// The hop sum onto the parity-P site of half index h (all four directions).
+template <int SF, typename S, typename Src>
+__device__ __forceinline__ void eo_hops(cx<typename Store<S>::R> (&acc)[12], const Src &src,
+                                        const S *__restrict__ Uf, const S *__restrict__ Ub, const Geom &g, int P,
+                                        int h) {
+  const int Vh = g.V / 2, lxh = g.lx / 2;
+  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
+  const int xh = h % lxh, r1 = h / lxh;
+  const int y = r1 % g.ly, r2 = r1 / g.ly;
+  const int z = r2 % g.lz, t = r2 / g.lz;
+  const int x = 2 * xh + ((P + y + z + t) & 1);
+  const int s = x + g.lx * r1;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+  // z and t first, as in the full-lattice stencil
+  hop_dir_eo<2, SF, S>(acc, src, Uf, Ub, Vh, h, (z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz) >> 1,
+                           (z == 0 ? s + (g.lz - 1) * sz : s - sz) >> 1);
+  hop_dir_eo<3, SF, S>(acc, src, Uf, Ub, Vh, h, (t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt) >> 1,
+                           (t == 0 ? s + (g.lt - 1) * stt : s - stt) >> 1);
+  hop_dir_eo<0, SF, S>(acc, src, Uf, Ub, Vh, h, (x == g.lx - 1 ? s - (g.lx - 1) : s + 1) >> 1,
+                           (x == 0 ? s + (g.lx - 1) : s - 1) >> 1);
+  hop_dir_eo<1, SF, S>(acc, src, Uf, Ub, Vh, h, (y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy) >> 1,
+                           (y == 0 ? s + (g.ly - 1) * sy : s - sy) >> 1);
 }
 
 enum EoEpi : int {
@@ -107,8 +136,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
   constexpr int NV = EoNV<E>::v;
   const R a = R(a_);
   __shared__ S tile[12 * kBlock];
-  const int Vh = g.V / 2, lxh = g.lx / 2;
-  const int sy = g.lx, sz = g.lx * g.ly, stt = sz * g.lz;
+  const int Vh = g.V / 2;
   double v[NV > 0 ? NV : 1];
 #pragma unroll
   for (int k = 0; k < (NV > 0 ? NV : 1); ++k) v[k] = 0.0;
@@ -120,24 +148,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 
     stage_tile(tile, in, h0, Vh);
     __syncthreads();
     if (h >= Vh) continue;
-    const TileSrc<S> src{in, tile, h0, Vh};
-    const int xh = h % lxh, r1 = h / lxh;
-    const int y = r1 % g.ly, r2 = r1 / g.ly;
-    const int z = r2 % g.lz, t = r2 / g.lz;
-    const int x = 2 * xh + ((P + y + z + t) & 1);
-    const int s = x + g.lx * r1;
     cx<R> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-    // z and t first, as in the full-lattice stencil
-    hop_dir_eo<2, SF, S>(acc, src, Uf, Ub, Vh, h, (z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz) >> 1,
-                      (z == 0 ? s + (g.lz - 1) * sz : s - sz) >> 1);
-    hop_dir_eo<3, SF, S>(acc, src, Uf, Ub, Vh, h, (t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt) >> 1,
-                      (t == 0 ? s + (g.lt - 1) * stt : s - stt) >> 1);
-    hop_dir_eo<0, SF, S>(acc, src, Uf, Ub, Vh, h, (x == g.lx - 1 ? s - (g.lx - 1) : s + 1) >> 1,
-                      (x == 0 ? s + (g.lx - 1) : s - 1) >> 1);
-    hop_dir_eo<1, SF, S>(acc, src, Uf, Ub, Vh, h, (y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy) >> 1,
-                      (y == 0 ? s + (g.ly - 1) * sy : s - sy) >> 1);
+    eo_hops<SF, S>(acc, TileSrc<S>{in, tile, h0, Vh}, Uf, Ub, g, P, h);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const size_t i = size_t(c) * Vh + h;
@@ -182,6 +194,71 @@ __global__ void __launch_bounds__(kBlock) k_eo_finish(const double *__restrict__
     for (int i = 0; i < NV; ++i) out[i] = v[i];
 }
 
+// Multi-RHS: KC half-lattice spinors in the batch layout (element
+// (c, h, col) at (c Vh + h) KC + col; the KC lanes of a site share its link
+// loads), tiles of kBlock / KC sites.  Each column is its own BiCGStab
+// recurrence: a column that has stopped (K non-null) skips the work and adds
+// nothing to its partial sums, which are per column.  The input goes through
+// LDS where the full-lattice batches found staging to pay (one column, or
+// BF16 entries); FP64 / FP32 batches read their neighbours from global memory.
+template <typename S, int KC>
+constexpr bool kStageEo = KC == 1 || std::is_same<S, bf16c>::value;
+
+template <typename S, int KC, int SF, int E>
+__global__ void __launch_bounds__(kBlock)
+    k_bhop_eo(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ Uf, const S *__restrict__ Ub,
+              Geom g, int P, double a_, const S *__restrict__ id, const S *__restrict__ dv, int j,
+              const KrylovState *K, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  static_assert(E == EO_TMP || E == EO_SCHUR || E == EO_SIGMA || E == EO_STABT, "batched epilogues");
+  constexpr int NV = EoNV<E>::v, spt = kBlock / KC;
+  const int col = int(threadIdx.x) % KC;
+  const bool act = !K || !skip_iter(K + col, j);
+  const R a = R(a_);
+  __shared__ S tile[12 * kBlock];
+  const int Vh = g.V / 2;
+  double v[NV > 0 ? NV : 1];
+#pragma unroll
+  for (int k = 0; k < (NV > 0 ? NV : 1); ++k) v[k] = 0.0;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntiles = (Vh + spt - 1) / spt;
+  for (int T = lb; T < ntiles; T += gridDim.x) {
+    const int h0 = T * spt, h = h0 + int(threadIdx.x) / KC;
+    if constexpr (kStageEo<S, KC>) {
+      __syncthreads();  // the previous tile's readers are done
+      stage_tile<S, KC>(tile, in, h0, Vh);
+      __syncthreads();
+    }
+    if (!act || h >= Vh) continue;
+    cx<R> acc[12];
+    if constexpr (kStageEo<S, KC>)
+      eo_hops<SF, S>(acc, TileSrc<S, KC>{in + col, tile + col, h0, Vh}, Uf, Ub, g, P, h);
+    else
+      eo_hops<SF, S>(acc, GlobSrc<S, KC>{in + col, Vh}, Uf, Ub, g, P, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const size_t i = (size_t(c) * Vh + h) * KC + col;
+      if constexpr (E == EO_TMP) {
+        Store<S>::st(out, i, acc[c]);
+      } else {
+        const cx<R> iv = Store<S>::ld(id, i);
+        const cx<R> o = iv - a * acc[c];
+        Store<S>::st(out, i, o);
+        if constexpr (E == EO_SIGMA) {  // conj(dv) o
+          const cx<R> hv = Store<S>::ld(dv, i);
+          v[0] += double(hv.x) * o.x + double(hv.y) * o.y;
+          v[1] += double(hv.x) * o.y - double(hv.y) * o.x;
+        } else if constexpr (E == EO_STABT) {  // conj(o) id, |o|^2
+          v[0] += double(o.x) * iv.x + double(o.y) * iv.y;
+          v[1] += double(o.x) * iv.y - double(o.y) * iv.x;
+          v[2] += double(o.x) * o.x + double(o.y) * o.y;
+        }
+      }
+    }
+  }
+  if constexpr (NV > 0) block_partial_cols<NV, KC, kBlock>(v, part, blockIdx.x);
+}
+
 inline int eo_grid(const Geom &g) { return stencil_grid(g.V / 2); }
 template <typename S>
 inline const S *links_of(const S *Ueo, const Geom &g, int par) {
@@ -194,6 +271,21 @@ void hop(S *out, const S *in, const S *Ueo, const Geom &g, int P, double a, cons
          const KrylovState *K, double *part, int grid, hipStream_t st) {
   EB_LAUNCH((k_hop_eo<S, SF, E>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
             links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
+}
+
+// batched: out (parity P) = epilogue(H_{P, 1-P} in) for kc columns; a
+// producer of partial sums uses batch_stencil_grid(V/2, kc, NV) blocks, the
+// count the batched BiCGStab's consumers read for spinors of V/2 sites
+template <int SF, int E, typename S>
+void bhop(S *out, const S *in, const S *Ueo, const Geom &g, int P, double a, const S *id, const S *dv, int j,
+          const KrylovState *K, double *part, int kc, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    constexpr int NV = EoNV<E>::v;
+    const int grid = batch_stencil_grid(g.V / 2, KC, NV > 0 ? NV : 1);
+    EB_LAUNCH((k_bhop_eo<S, KC, SF, E>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
+              links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
+  });
 }
 
 }  // namespace
@@ -276,12 +368,43 @@ void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g,
   }
 }
 
+template <typename S>
+void launch_bschur_eo(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger, int kc,
+                      hipStream_t st) {
+  if (dagger) {
+    bhop<+1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, kc, st);
+    bhop<+1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, kc, st);
+  } else {
+    bhop<-1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, kc, st);
+    bhop<-1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, kc, st);
+  }
+}
+
+template <typename S>
+void launch_bstab_v_eo(S *v, const S *p, const S *rhat, S *tmp, const S *Ueo, const Geom &g, double kappa, int j,
+                       int kc, KrylovState *K, const RedScratch &rs, hipStream_t st) {
+  bhop<-1, EO_TMP, S>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, kc, st);
+  bhop<-1, EO_SIGMA, S>(v, tmp, Ueo, g, 0, kappa * kappa, p, rhat, j, K, region(rs, RG_V), kc, st);
+}
+
+template <typename S>
+void launch_bstab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, double kappa, int j, int kc,
+                       KrylovState *K, const RedScratch &rs, hipStream_t st) {
+  bhop<-1, EO_TMP, S>(tmp, sv, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, kc, st);
+  bhop<-1, EO_STABT, S>(t, tmp, Ueo, g, 0, kappa * kappa, sv, nullptr, j, K, region(rs, RG_T), kc, st);
+}
+
 #define EB_EO_INST(S)                                                                                              \
   template void launch_stab_v_eo<S>(S *, const S *, const S *, S *, const S *, const Geom &, double, int,          \
                                     KrylovState *, const RedScratch &, hipStream_t);                                \
   template void launch_stab_t_eo<S>(S *, const S *, S *, const S *, const Geom &, double, int, KrylovState *,       \
                                     const RedScratch &, hipStream_t);                                               \
-  template void launch_schur_eo_s<S>(S *, const S *, S *, const S *, const Geom &, double, bool, hipStream_t);
+  template void launch_schur_eo_s<S>(S *, const S *, S *, const S *, const Geom &, double, bool, hipStream_t);    \
+  template void launch_bschur_eo<S>(S *, const S *, S *, const S *, const Geom &, double, bool, int, hipStream_t); \
+  template void launch_bstab_v_eo<S>(S *, const S *, const S *, S *, const S *, const Geom &, double, int, int,    \
+                                     KrylovState *, const RedScratch &, hipStream_t);                             \
+  template void launch_bstab_t_eo<S>(S *, const S *, S *, const S *, const Geom &, double, int, int,              \
+                                     KrylovState *, const RedScratch &, hipStream_t);
 EB_EO_INST(double2)
 EB_EO_INST(float2)
 EB_EO_INST(bf16c)

@@ -1,6 +1,8 @@
 // Launch geometry, reduction-scratch regions and small scalar helpers shared
-// by the kernel files (kernels.hip, batch.hip).
+// by the kernel files (kernels.hip, batch.hip, eo.hip).
 #pragma once
+
+#include <type_traits>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -35,6 +37,31 @@ inline int matvec_grid(int V) { return 2 * stencil_grid(V); }
 inline int stream_grid(size_t n) {
   int nb = nblocks_for(n, 4);
   return nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
+}
+
+// grids: records of KC * NV doubles per block must fit one scratch region
+inline int batch_stencil_grid(int V, int kc, int nv) {
+  int nb = nblocks_for(size_t(V) * kc);
+  const int cap = int(kRegion / size_t(kc * nv));
+  nb = nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
+  return nb > cap ? cap : nb;
+}
+inline int batch_red_grid(size_t n, int kc, int nv) {
+  int nb = red_grid(n);
+  const int cap = int(kRegion / size_t(kc * nv));
+  return nb > cap ? cap : nb;
+}
+
+template <typename F>
+void dispatch_kc(int kc, F &&f) {
+  switch (kc) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: break;  // the host validates kc
+  }
 }
 
 __device__ __forceinline__ bool skip_iter(const KrylovState *S, int j) { return S->stopped && j > S->stop_at; }

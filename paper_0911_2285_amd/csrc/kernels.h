@@ -187,6 +187,19 @@ void launch_stab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, do
 template <typename S>
 void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger,
                        hipStream_t st);
+// Multi-RHS on Dhat: kc half-lattice spinors in the batch layout (element
+// (c, h, col) at (c V/2 + h) kc + col), tmp the same size.  out = Dhat in per
+// column; the BiCGStab forms as launch_bstab_v/t, with records for the batched
+// BiCGStab passes called with a geometry of V/2 sites.
+template <typename S>
+void launch_bschur_eo(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger, int kc,
+                      hipStream_t st);
+template <typename S>
+void launch_bstab_v_eo(S *v, const S *p, const S *rhat, S *tmp, const S *Ueo, const Geom &g, double kappa, int j,
+                       int kc, KrylovState *K, const RedScratch &rs, hipStream_t st);
+template <typename S>
+void launch_bstab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, double kappa, int j, int kc,
+                       KrylovState *K, const RedScratch &rs, hipStream_t st);
 
 // ---- tall-skinny projections (FP64) ------------------------------------------------
 // out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i];  X_a = X + a*ldx, Y_b = Y + b*ldy.

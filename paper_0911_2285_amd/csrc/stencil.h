@@ -153,6 +153,7 @@ __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], con
 // sites times KC columns; glob and lds point at this thread's column.
 template <typename S, int KC = 1>
 struct TileSrc {
+  static constexpr bool kFence = false;
   const S *__restrict__ glob;
   const S *lds;
   int s0, V;
@@ -160,6 +161,18 @@ struct TileSrc {
     const unsigned d = unsigned(sn - s0);
     return d < unsigned(kBlock / KC) ? Store<S>::ld(lds, size_t(c) * kBlock + d * KC)
                                      : Store<S>::ld(glob, (size_t(c) * V + sn) * KC);
+  }
+};
+
+// The same interface without a tile: every neighbour from global memory.  Its
+// users fence between hops (kFence), as the unstaged stencil does.
+template <typename S, int KC = 1>
+struct GlobSrc {
+  static constexpr bool kFence = true;
+  const S *__restrict__ glob;
+  int V;
+  __device__ __forceinline__ cx<typename Store<S>::R> ld(int c, int sn) const {
+    return Store<S>::ld(glob, (size_t(c) * V + sn) * KC);
   }
 };
 
@@ -175,8 +188,8 @@ __device__ __forceinline__ void stage_tile(S *lds, const S *__restrict__ in, int
   }
 }
 
-template <int MU, int SG, typename S, int KC>
-__device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6], const TileSrc<S, KC> &src, int sn) {
+template <int MU, int SG, typename S, typename Src>
+__device__ __forceinline__ void load_project_t(cx<typename Store<S>::R> (&h)[6], const Src &src, int sn) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const auto p0 = src.ld(a, sn);
@@ -207,9 +220,9 @@ __device__ __forceinline__ void hop_dir_t(cx<typename Store<S>::R> (&acc)[12], c
                                           const S *__restrict__ U, int V, int s, int sf, int sb) {
   using R = typename Store<S>::R;
   cx<R> h[6];
-  load_project_t<MU, SF, S, KC>(h, src, sf);
+  load_project_t<MU, SF, S>(h, src, sf);
   mult_accum<MU, SF, false, S>(acc, h, U, V, s);
-  load_project_t<MU, -SF, S, KC>(h, src, sb);
+  load_project_t<MU, -SF, S>(h, src, sb);
   mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
 }
 

@@ -95,6 +95,7 @@ _SIGNATURES = [
     ("eb_op_apply_dagger", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     ("eb_op_apply_schur", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     ("eb_op_apply_block", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
+    ("eb_op_apply_schur_block", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
     ("eb_eigbicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_EigParams), _P, ctypes.POINTER(_Stats), _P]),
     ("eb_deflated_bicg_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_SolveParams), ctypes.POINTER(_Stats), _P]),
     ("eb_get_eigenpairs", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]),
@@ -240,6 +241,16 @@ def op_apply_schur(op, out, inp, dagger=False, stream=None):
     canonical tensors, odd sites of inp ignored and of out zero."""
     _check(lib().eb_op_apply_schur(op.handle, _spinor_ptr(op, out, "fp64", "out"), _spinor_ptr(op, inp, "fp64", "in"),
                                    int(bool(dagger)), _stream(stream)))
+
+
+def op_apply_schur_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
+    """out_i = Dhat inp_i (or Dhat^+) for k full-lattice FP64 canonical spinors
+    back to back (even-odd operator); prec is the storage of the pass."""
+    import torch
+
+    _check(lib().eb_op_apply_schur_block(op.handle, _dev_ptr(out, op.N * k, torch.complex128, "out"),
+                                         _dev_ptr(inp, op.N * k, torch.complex128, "in"), int(k),
+                                         int(bool(dagger)), PREC[prec], _stream(stream)))
 
 
 def op_apply_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
