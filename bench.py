@@ -328,7 +328,8 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
         vals = [float(r["Counter_Value"]) for r in rows[-3:]]
         return sum(vals) / len(vals)
 
-    is_kernel = lambda n: kernel + "(" in n
+    # the general form's launches (the template's gamma5 instance is another kernel)
+    is_kernel = lambda n: kernel + "(" in n or kernel + "<false>(" in n
     f_k, n_f = per_dispatch(fetch_csv, "FETCH_SIZE", is_kernel)
     w_k, n_w = per_dispatch(write_csv, "WRITE_SIZE", is_kernel)
     f_c = calibration(fetch_csv, "FETCH_SIZE")
@@ -384,6 +385,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--no-large", action="store_true", help="skip the 24^3 x 64 multi-RHS / precision section")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the side records (multi-RHS table, gamma5 and even-odd forms, sweeps)")
     ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
@@ -524,71 +527,73 @@ def main():
         dt_b = time.perf_counter() - t1
         assert st["true_rel_resid"] <= W["tol"], (name, st)
         extra["deflated_solves_per_s"][name] = round(nd / dt_b, 3)
-    extra["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
-    # the same step with eigBiCG solves 2..n1 in the gamma5-Hermitian form
-    # (Sec. 4: one D per iteration, shadow vectors implicit)
-    lat5, its5 = [], []
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    run_step(eb, op, B, X, W, lat5, its5, g5=True)
-    torch.cuda.synchronize()
-    dt5 = time.perf_counter() - t1
-    n1 = W["n1"]
-    last = slice((args.steps - 1) * W["nrhs"], args.steps * W["nrhs"])
-    lat_g, its_g = lat[last], its[last]
-    extra["gamma5_form"] = {
-        "solves_per_s": round(W["nrhs"] / dt5, 3),
-        "iters_per_rhs": its5,
-        "eigbicg_ms_per_iter_solves_2_to_n1": {
-            "general": round(1e3 * sum(lat_g[1:n1]) / sum(its_g[1:n1]), 4),
-            "gamma5": round(1e3 * sum(lat5[1:n1]) / sum(its5[1:n1]), 4),
-        },
-    }
-    log(f"[bench] gamma5 form: {extra['gamma5_form']}")
-    # the same step on the even-odd (Schur) form: the paper's test matrices are
-    # even-odd preconditioned; every solve still reaches ||b - D x|| <= tol ||b||
-    op_eo = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"], eo=True)
-    run_step(eb, op_eo, B, X, W, [], [])
-    lat_e, its_e = [], []
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    run_step(eb, op_eo, B, X, W, lat_e, its_e)
-    torch.cuda.synchronize()
-    dt_e = time.perf_counter() - t1
-    # its deflated solves with FP32 / BF16-stored inner BiCGStab in FP64 refinement
-    eo_defl = {}
-    for name, kw in [("fp64", dict()), ("mixed_fp32_inner", dict(inner="fp32", inner_tol=1e-6)),
-                     ("mixed_bf16_inner", dict(inner="bf16", inner_tol=1e-2))]:
+    # the side records (skipped with --no-side, e.g. to profile the headline workload alone)
+    if not args.no_side:
+        extra["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
+        # the same step with eigBiCG solves 2..n1 in the gamma5-Hermitian form
+        # (Sec. 4: one D per iteration, shadow vectors implicit)
+        lat5, its5 = [], []
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for i in range(W["n1"], W["nrhs"]):
-            X[i].zero_()
-            st = eb.deflated_bicg_solve(op_eo, B[i], X[i], tol=W["tol"], maxiter=20000, **kw)
+        t1 = time.perf_counter()
+        run_step(eb, op, B, X, W, lat5, its5, g5=True)
+        torch.cuda.synchronize()
+        dt5 = time.perf_counter() - t1
+        n1 = W["n1"]
+        last = slice((args.steps - 1) * W["nrhs"], args.steps * W["nrhs"])
+        lat_g, its_g = lat[last], its[last]
+        extra["gamma5_form"] = {
+            "solves_per_s": round(W["nrhs"] / dt5, 3),
+            "iters_per_rhs": its5,
+            "eigbicg_ms_per_iter_solves_2_to_n1": {
+                "general": round(1e3 * sum(lat_g[1:n1]) / sum(its_g[1:n1]), 4),
+                "gamma5": round(1e3 * sum(lat5[1:n1]) / sum(its5[1:n1]), 4),
+            },
+        }
+        log(f"[bench] gamma5 form: {extra['gamma5_form']}")
+        # the same step on the even-odd (Schur) form: the paper's test matrices are
+        # even-odd preconditioned; every solve still reaches ||b - D x|| <= tol ||b||
+        op_eo = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"], eo=True)
+        run_step(eb, op_eo, B, X, W, [], [])
+        lat_e, its_e = [], []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_step(eb, op_eo, B, X, W, lat_e, its_e)
+        torch.cuda.synchronize()
+        dt_e = time.perf_counter() - t1
+        # its deflated solves with FP32 / BF16-stored inner BiCGStab in FP64 refinement
+        eo_defl = {}
+        for name, kw in [("fp64", dict()), ("mixed_fp32_inner", dict(inner="fp32", inner_tol=1e-6)),
+                         ("mixed_bf16_inner", dict(inner="bf16", inner_tol=1e-2))]:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for i in range(W["n1"], W["nrhs"]):
+                X[i].zero_()
+                st = eb.deflated_bicg_solve(op_eo, B[i], X[i], tol=W["tol"], maxiter=20000, **kw)
+                assert st["true_rel_resid"] <= W["tol"], (name, st)
+            torch.cuda.synchronize()
+            eo_defl[name] = round((W["nrhs"] - W["n1"]) / (time.perf_counter() - t2), 3)
+        # and in batches (batch chosen by the library)
+        for name, kw in [("fp64_batched", dict()), ("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
+                         ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
+            Xd = torch.zeros_like(Bd)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            st = eb.deflated_bicg_solve(op_eo, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
+            torch.cuda.synchronize()
             assert st["true_rel_resid"] <= W["tol"], (name, st)
-        torch.cuda.synchronize()
-        eo_defl[name] = round((W["nrhs"] - W["n1"]) / (time.perf_counter() - t2), 3)
-    # and in batches (batch chosen by the library)
-    for name, kw in [("fp64_batched", dict()), ("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
-                     ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
-        Xd = torch.zeros_like(Bd)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        st = eb.deflated_bicg_solve(op_eo, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
-        torch.cuda.synchronize()
-        assert st["true_rel_resid"] <= W["tol"], (name, st)
-        eo_defl[name] = round(nd / (time.perf_counter() - t2), 3)
-    eb.op_destroy(op_eo)
-    extra["even_odd"] = {
-        "solves_per_s": round(W["nrhs"] / dt_e, 3),
-        "ms_per_step": round(1e3 * dt_e, 3),
-        "iters_per_rhs": its_e,
-        "p50_ms": round(1e3 * percentile(lat_e, 50), 3),
-        "deflated_solves_per_s": eo_defl,
-    }
-    log(f"[bench] even-odd form: {extra['even_odd']}")
-    extra["deflation_sweep"] = deflation_sweep(eb)
-    extra["table1_analogue"] = table1_analogue(eb)
-    log(f"[bench] deflation sweep: {extra['deflation_sweep']}")
+            eo_defl[name] = round(nd / (time.perf_counter() - t2), 3)
+        eb.op_destroy(op_eo)
+        extra["even_odd"] = {
+            "solves_per_s": round(W["nrhs"] / dt_e, 3),
+            "ms_per_step": round(1e3 * dt_e, 3),
+            "iters_per_rhs": its_e,
+            "p50_ms": round(1e3 * percentile(lat_e, 50), 3),
+            "deflated_solves_per_s": eo_defl,
+        }
+        log(f"[bench] even-odd form: {extra['even_odd']}")
+        extra["deflation_sweep"] = deflation_sweep(eb)
+        extra["table1_analogue"] = table1_analogue(eb)
+        log(f"[bench] deflation sweep: {extra['deflation_sweep']}")
     # undeflated FP64 BiCGStab on the same sources, for the deflation speed-up
     eb.defl_reset(op)
     plain_its = []
