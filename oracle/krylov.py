@@ -419,7 +419,9 @@ def bicgstab(A, b, x0, tol, maxiter=10000, space=None, deftol=0.0):
             rho = rho_new
             rn = nrm(r)
             out.res_hist.append(rn)
-            if space is not None and space.K and rn < thr:
+            # a residual that already meets tol ends the solve; the DefTol
+            # restart applies only above it
+            if space is not None and space.K and rn < thr and rn > tol * nb:
                 x = deflate_guess(A, space, b, x)
                 out.defl_restarts += 1
                 thr *= deftol

@@ -356,3 +356,36 @@ def test_windowed_vs_unrestarted_ritz_values(gpu_lib):
     # windowed against un-restarted (the Ritz pairs are not converged here:
     # residuals 0.12 - 0.19; the oracle's own two runs differ by <= 1.5e-5)
     assert _rel_match(r_w, orc.lam) < 5e-5 and _rel_match(orc.lam, r_w) < 5e-5
+
+
+def test_deftol_restarts_match_oracle(gpu_lib, cfg0):
+    """Deflated BiCGStab with DefTol > 0 (Alg. Incremental eigBiCG, step 3:
+    re-deflate and restart whenever the residual falls below DefTol^k ||b||)
+    after 4 eigBiCG solves: the restart count equals the oracle's, the
+    iterations agree, and every solve reaches the true residual 1e-10."""
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    A, Ad = _ops(U, kappa, dims)
+    B = [synth.z2_source(V, synth.rhs_seed(0, 50 + i)) for i in range(6)]
+    X0 = [np.zeros(12 * V, complex)] * 6
+    for deftol in (3e-3, 1e-3):
+        xs_o, info_o, _ = K.incremental_eigbicg(A, Ad, [b.ravel() for b in B], X0, 4, 16, 1e-10, n1=4,
+                                                deftol=deftol)
+        op = gpu_lib.op_create(U, kappa, dims, defl_capacity=16)
+        for i, bnp in enumerate(B):
+            b = torch.from_numpy(bnp).to("cuda:0")
+            x = torch.zeros_like(b)
+            if i < 4:
+                gpu_lib.eigbicg_solve(op, b, x, nev=4, m=16, tol=1e-10)
+                continue
+            st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, deftol=deftol)
+            io = info_o[i]
+            print(deftol, i, st["iters"], io["iters"], st["defl_restarts"], io["defl_restarts"])
+            assert st["defl_restarts"] == io["defl_restarts"] == 3
+            assert abs(st["iters"] - io["iters"]) <= max(3, 0.1 * io["iters"])
+            xg = x.cpu().numpy().ravel()
+            assert np.linalg.norm(bnp.ravel() - A(xg)) / np.linalg.norm(bnp) <= 1e-10
+            assert np.linalg.norm(xg - xs_o[i]) / np.linalg.norm(xs_o[i]) <= 1e-8
+        gpu_lib.op_destroy(op)

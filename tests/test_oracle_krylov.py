@@ -270,10 +270,15 @@ def test_deftol_restart_path():
                                         [np.zeros(N, complex)] * 2, 4, 16, 1e-10, n1=2)
     b = rng.standard_normal(N) + 0j
     x0 = K.deflate_guess(A, space, b, np.zeros(N, complex))
-    st = K.bicgstab(A, b, x0, 1e-10, space=space, deftol=1e-3)
-    assert st.defl_restarts >= 2
-    assert st.converged
-    assert np.linalg.norm(st.x - np.linalg.solve(M, b)) / np.linalg.norm(st.x) < 1e-8
+    # one restart per threshold DefTol^k ||b|| above tol ||b|| (Alg. Incremental
+    # eigBiCG, step 3; a residual already below tol ends the solve instead):
+    # 1e-3, 1e-6, 1e-9; 3e-3, 9e-6, 2.7e-8 (8.1e-11 is below tol); 1e-2 ...
+    # 1e-8 (the fifth threshold equals tol: the converged solve ends there)
+    for deftol, n in ((1e-3, 3), (3e-3, 3), (1e-2, 4)):
+        st = K.bicgstab(A, b, x0, 1e-10, space=space, deftol=deftol)
+        assert st.defl_restarts == n, (deftol, st.defl_restarts)
+        assert st.converged
+        assert np.linalg.norm(st.x - np.linalg.solve(M, b)) / np.linalg.norm(st.x) < 1e-8
 
 
 def test_wilson_incremental_small_config():
