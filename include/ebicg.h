@@ -231,6 +231,57 @@ eb_status eb_timing_enable(eb_op *op, int32_t enable);
 eb_status eb_timing_classes(eb_op *op, uint32_t mask);
 eb_status eb_timing_read(eb_op *op, int32_t kclass, int64_t *launches, double *total_ms);
 
+/* ---- Serving: continuous batching of deflated solves -------------------------
+ * A session serves solve requests on one operator with `slots` columns of the
+ * multi-RHS BiCGStab (Alg. Incremental eigBiCG, step 3, without DefTol).  A
+ * request is admitted into a free slot; at the next eb_session_step its start
+ * x0 is deflated with the operator's deflation space as it is then
+ * (x0 += U_r H^-1 U_l^+ (b - A x0)) and its column starts iterating beside
+ * the columns already running.  Each slot runs its own FP64 refinement: the
+ * inner iteration (storage `inner`) runs to inner_tol, the correction is added
+ * in FP64 and the true residual ||b - A x|| is recomputed in FP64; the request
+ * finishes when it is <= tol ||b|| (even-odd operators: the solvers' system,
+ * with the full system's residual reported), or with EB_ERR_NOT_CONVERGED
+ * after maxiter inner iterations.  Every column keeps its own BiCGStab
+ * scalars and stop test, so a request's result does not depend on which other
+ * requests share the batch.
+ *
+ * Threading and streams: a session and every other call on its operator
+ * (eigBiCG solves that grow the space, deflated solves) must use the same
+ * stream and the same host thread; sessions of different operators on
+ * different streams overlap on the device.  The session owns its reduction
+ * scratch, states and the batch (eb_session_info reports the bytes); b and x
+ * stay owned by the caller and must stay valid until the request is polled. */
+typedef struct eb_session eb_session;
+typedef struct {
+  int32_t slots;    /* columns of the batch: 1, 2, 4, 8 or 16 */
+  eb_prec inner;    /* storage of the inner iteration (EB_FP64, EB_FP32, EB_BF16) */
+  double tol;       /* target ||b - A x|| / ||b|| per request */
+  double inner_tol; /* residual reduction per refinement step; <= 0: 1e-6 (FP32), 1e-2 (BF16), none (FP64) */
+  int32_t maxiter;  /* inner iterations per request, summed over refinement steps */
+  int32_t chunk;    /* iterations launched between slot updates, 1..1024 */
+} eb_session_params;
+/* Create a session on `stream` (a hipStream_t; its device memory is allocated here). */
+eb_status eb_session_create(eb_op *op, const eb_session_params *p, void *stream, eb_session **out);
+/* Wait for the work in flight and free the session (requests still running are dropped). */
+eb_status eb_session_destroy(eb_session *s);
+/* Reserve a free slot for the request (b, x: device FP64 canonical spinors; x holds x0 and
+ * receives the solution; tag: the caller's id).  Host-only: the request starts at the next
+ * eb_session_step.  *slot (may be NULL) receives the slot.  EB_ERR_CAPACITY if every slot is busy. */
+eb_status eb_session_admit(eb_session *s, const void *b, void *x, int64_t tag, int32_t *slot);
+/* Wait for the chunk in flight; harvest the slots whose inner solve stopped (finish them or
+ * start their next refinement step); start the admitted requests; launch the next chunk of
+ * iterations and return without waiting for it.  Finished requests become pollable. */
+eb_status eb_session_step(eb_session *s);
+/* Take up to max finished requests: tags[i], status[i] (EB_OK, EB_ERR_NOT_CONVERGED,
+ * EB_ERR_BREAKDOWN) and stats[i] (may be NULL; seconds = admission to finish).  *n = taken. */
+eb_status eb_session_poll(eb_session *s, int32_t max, int64_t *tags, int32_t *status, eb_stats *stats, int32_t *n);
+/* Free and busy slots, finished requests not yet polled, device bytes the session holds
+ * (any pointer may be NULL). */
+eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int32_t *done, uint64_t *device_bytes);
+/* Device bytes the operator holds (links, deflation space, work buffers). */
+eb_status eb_op_device_bytes(eb_op *op, uint64_t *bytes);
+
 /* Message of the last non-OK status on this thread (empty if none). */
 void eb_last_error(char *buf, size_t len);
 

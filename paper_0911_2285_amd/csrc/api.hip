@@ -1972,3 +1972,423 @@ void eb_last_error(char *buf, size_t len) {
 const char *eb_version(void) { return "ebicg 0.1 (gfx950)"; }
 
 }  // extern "C"
+
+// ============================================================================
+// Serving sessions: continuous batching of deflated solves on one operator
+// ============================================================================
+// A session keeps kc slots in one batch of the multi-RHS BiCGStab.  Requests
+// are admitted into free slots between chunks of iterations: the start is
+// deflated with the operator's space as it is at admission (Alg. Incremental
+// eigBiCG, step 3, first item), then each slot runs its own FP64 refinement
+// around the inner BiCGStab in the session's precision.  A slot whose inner
+// solve stopped is harvested at the next chunk boundary (x += e in FP64, true
+// residual in FP64) and either finishes or restarts from the new residual, so
+// slots free up and refill while the other columns keep iterating.  The
+// session owns its reduction scratch, Krylov states and scalar history, so
+// other solves on the operator (eigBiCG growing the space) can run between
+// its chunks on the same stream.
+struct SessionSlot {
+  enum Phase { FREE = 0, PENDING, RUNNING } phase = FREE;
+  int64_t tag = 0;
+  const double2 *b_can = nullptr;
+  double2 *x_can = nullptr;
+  double scale = 1.0;  // tolerance factor of the solvers' system (even-odd: ||b|| / ||b_hat||)
+  int iters = 0;       // inner iterations over all refinement steps
+  int step_iters = 0;  // inner iterations of the current refinement step
+  int outer = 0;
+  int matvec = 0;
+  std::chrono::steady_clock::time_point t0;
+};
+struct SessionDone {
+  int64_t tag;
+  eb_status status;
+  eb_stats st;
+};
+
+struct eb_session {
+  eb_op *op = nullptr;
+  hipStream_t s = nullptr;
+  int kc = 1;
+  eb_prec prec = EB_FP64;
+  double tol = 0, inner_tol = 0;
+  int maxiter = 0, chunk = 8;
+  size_t selem = 0;  // bytes of one inner-storage complex entry
+  DevBuf partials, state, hist, res;
+  PinnedBuf hstate, hres;
+  DevBuf b, x, r, bo, tmp64;                     // FP64 columns of the solvers' system, kc each
+  DevBuf rl, e, rhat, p, v, sv, t, tmp;          // the batch in the inner storage
+  std::vector<SessionSlot> slot;
+  std::deque<SessionDone> done;
+  hipEvent_t ev = nullptr;
+  bool inflight = false;
+  int inflight_j = 0;
+  int64_t chunks = 0;
+  RedScratch rs() { return RedScratch{partials.as<double>()}; }
+  KrylovState *K() { return state.as<KrylovState>(); }
+  KrylovHistory view() {
+    const size_t cap = size_t(chunk + 2) * kc;
+    char *base = static_cast<char *>(hist.p);
+    KrylovHistory h;
+    h.alpha = reinterpret_cast<double2 *>(base);
+    h.beta = reinterpret_cast<double2 *>(base + cap * sizeof(double2));
+    h.rho = reinterpret_cast<double2 *>(base + 2 * cap * sizeof(double2));
+    h.omega = reinterpret_cast<double2 *>(base + 3 * cap * sizeof(double2));
+    h.rn = reinterpret_cast<double *>(base + 4 * cap * sizeof(double2));
+    return h;
+  }
+  size_t device_bytes() const {
+    size_t n = 0;
+    for (const DevBuf *d : {&partials, &state, &hist, &res, &b, &x, &r, &bo, &tmp64, &rl, &e, &rhat, &p, &v, &sv, &t,
+                            &tmp})
+      n += d->bytes;
+    return n;
+  }
+  void release() {
+    for (DevBuf *d : {&partials, &state, &hist, &res, &b, &x, &r, &bo, &tmp64, &rl, &e, &rhat, &p, &v, &sv, &t,
+                      &tmp})
+      d->release();
+    hstate.release();
+    hres.release();
+    if (ev) (void)hipEventDestroy(ev);
+    ev = nullptr;
+  }
+};
+
+namespace {
+
+// The session's inner-storage operations for storage S.
+template <typename S>
+struct SessionOps {
+  static S *at(DevBuf &d) { return d.as<S>(); }
+  static void prepare(eb_session *ss) { (void)Inner<S>::solver_links(ss->op, ss->s); }
+  // one chunk of `n` batched BiCGStab iterations (j = 1..n) on every slot
+  static void chunk(eb_session *ss, int n) {
+    eb_op *op = ss->op;
+    const S *U = Inner<S>::solver_links(op, ss->s);
+    const Geom gv = vector_geom(op);
+    KrylovState *K = ss->K();
+    KrylovHistory h = ss->view();
+    const RedScratch rs = ss->rs();
+    const int kc = ss->kc;
+    hipStream_t s = ss->s;
+    S *x = at(ss->e), *r = at(ss->rl), *rhat = at(ss->rhat), *p = at(ss->p), *v = at(ss->v), *sv = at(ss->sv),
+      *t = at(ss->t), *tmp = op->eo ? at(ss->tmp) : nullptr;
+    for (int j = 1; j <= n; ++j) {
+      if (op->eo)
+        TIMED(EB_K_BSTAB_V, s, launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, rs, s));
+      else
+        TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, rs, s));
+      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, rs, s));
+      if (op->eo)
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, rs, s));
+      else
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, rs, s));
+      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, rs, s));
+      TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, gv, j, kc, K, h, rs, s));
+    }
+  }
+  // slot c starts an inner solve from the FP64 residual in r[:, c]
+  static void start(eb_session *ss, int c, double tol_abs, int maxiter) {
+    const size_t N = ss->op->N;
+    launch_slot_load<S>(at(ss->rl), at(ss->e), ss->r.as<double2>() + c * N, N, ss->kc, c, ss->s);
+    launch_slot_init<S>(at(ss->rhat), at(ss->p), at(ss->rl), N, ss->kc, c, tol_abs, maxiter, ss->K(), ss->view(),
+                        ss->rs(), ss->s);
+  }
+  static void add(eb_session *ss, int c) {
+    const size_t N = ss->op->N;
+    launch_slot_add<S>(ss->x.as<double2>() + c * N, at(ss->e), N, ss->kc, c, ss->s);
+  }
+};
+
+template <typename F>
+void session_dispatch(eb_prec prec, F &&f) {
+  if (prec == EB_FP64)
+    f(SessionOps<double2>{});
+  else if (prec == EB_FP32)
+    f(SessionOps<float2>{});
+  else
+    f(SessionOps<bf16c>{});
+}
+
+// r[:, c] = b[:, c] - A x[:, c] in FP64 for the listed slots; returns
+// (||r||, ||b||) per listed slot (one synchronisation for all of them).
+std::vector<std::pair<double, double>> session_residuals(eb_session *ss, const std::vector<int> &cols) {
+  eb_op *op = ss->op;
+  const size_t N = op->N;
+  double *res = ss->res.as<double>();
+  for (int c : cols) {
+    double2 *r = ss->r.as<double2>() + c * N;
+    const double2 *b = ss->b.as<double2>() + c * N, *x = ss->x.as<double2>() + c * N;
+    if (op->eo)
+      TIMED(EB_K_RESIDUAL, ss->s,
+            launch_residual_eo(r, b, x, ss->tmp64.as<double2>(), op->Ueo.as<double2>(), op->g, op->kappa,
+                               res + 2 * c, ss->rs(), ss->s));
+    else
+      TIMED(EB_K_RESIDUAL, ss->s,
+            launch_residual_f64(r, b, x, op->U64.as<double2>(), op->g, op->kappa, res + 2 * c, ss->rs(), ss->s));
+  }
+  HIPCHK(hipMemcpyAsync(ss->hres.p, res, 2 * ss->kc * sizeof(double), hipMemcpyDeviceToHost, ss->s));
+  HIPCHK(hipStreamSynchronize(ss->s));
+  std::vector<std::pair<double, double>> out;
+  const double *h = ss->hres.as<double>();
+  for (int c : cols) out.push_back({std::sqrt(h[2 * c]), std::sqrt(h[2 * c + 1])});
+  return out;
+}
+
+// Slot c is done: write its solution back (even-odd: reconstruct the odd
+// sites), report the full system's residual, free the slot.
+void session_finish(eb_session *ss, int c, eb_status status, double rel) {
+  eb_op *op = ss->op;
+  SessionSlot &q = ss->slot[c];
+  const size_t N = op->N;
+  store_solution(op, ss->x.as<double2>() + c * N, op->eo ? ss->bo.as<double2>() + c * N : nullptr, q.x_can, ss->s);
+  eb_stats st = zero_stats();
+  st.iters = q.iters;
+  st.matvec_d = q.matvec;
+  st.outer_steps = q.outer;
+  st.true_rel_resid = op->eo ? full_rel_residual(op, q.b_can, q.x_can, ss->s) : rel;
+  HIPCHK(hipStreamSynchronize(ss->s));
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q.t0).count();
+  ss->done.push_back({q.tag, status, st});
+  q = SessionSlot{};
+}
+
+// After the FP64 residuals of the listed slots: finish those at their target
+// (or out of budget), start a refinement step on the others.
+void session_advance(eb_session *ss, const std::vector<int> &cols, const std::vector<int> &why) {
+  if (cols.empty()) return;
+  auto rb = session_residuals(ss, cols);
+  for (size_t i = 0; i < cols.size(); ++i) {
+    const int c = cols[i];
+    SessionSlot &q = ss->slot[c];
+    q.matvec += 1;
+    const double rn = rb[i].first, bn = rb[i].second;
+    const double tolc = ss->tol * q.scale;
+    if (bn == 0.0) {  // b = 0: the solution is x = 0
+      HIPCHK(hipMemsetAsync(ss->x.as<double2>() + c * ss->op->N, 0, ss->op->N * sizeof(double2), ss->s));
+      session_finish(ss, c, EB_OK, 0.0);
+      continue;
+    }
+    const double rel = rn / bn;
+    if (rel <= tolc) {
+      session_finish(ss, c, EB_OK, rel / q.scale);
+      continue;
+    }
+    if (q.iters >= ss->maxiter) {
+      session_finish(ss, c, EB_ERR_NOT_CONVERGED, rel / q.scale);
+      continue;
+    }
+    if (why[i] == 2 && q.step_iters == 0) {  // the inner solve broke down before its first update
+      session_finish(ss, c, EB_ERR_BREAKDOWN, rel / q.scale);
+      continue;
+    }
+    const double target = std::max(ss->inner_tol * rn, 0.5 * tolc * bn);
+    session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::start(ss, c, target, ss->maxiter - q.iters); });
+    q.step_iters = 0;
+    q.outer += 1;
+  }
+}
+
+// Wait for the chunk in flight and harvest the slots whose inner solve stopped.
+void session_harvest(eb_session *ss) {
+  if (!ss->inflight) return;
+  HIPCHK(hipEventSynchronize(ss->ev));
+  ss->inflight = false;
+  const int jl = ss->inflight_j;
+  launch_batch_rebase(ss->K(), ss->view(), ss->kc, jl, ss->s);
+  const KrylovState *hs = ss->hstate.as<KrylovState>();
+  std::vector<int> cols, why;
+  for (int c = 0; c < ss->kc; ++c) {
+    SessionSlot &q = ss->slot[c];
+    if (q.phase != SessionSlot::RUNNING) continue;
+    const int it = hs[c].stopped ? std::max(hs[c].stop_at, 0) : jl;
+    q.iters += it;
+    q.step_iters += it;
+    q.matvec += 2 * it;
+    if (hs[c].stopped) {
+      session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::add(ss, c); });
+      cols.push_back(c);
+      why.push_back(hs[c].reason);
+    }
+  }
+  session_advance(ss, cols, why);
+}
+
+// Start the admitted requests: load b and x0, deflate x0 with the operator's
+// current space, then the first refinement step (or finish at once).
+void session_admit_pending(eb_session *ss) {
+  eb_op *op = ss->op;
+  const size_t N = op->N;
+  std::vector<int> cols, why;
+  for (int c = 0; c < ss->kc; ++c) {
+    SessionSlot &q = ss->slot[c];
+    if (q.phase != SessionSlot::PENDING) continue;
+    double2 *b = ss->b.as<double2>() + c * N, *x = ss->x.as<double2>() + c * N;
+    q.scale = load_system(op, q.b_can, q.x_can, b, x, op->eo ? ss->bo.as<double2>() + c * N : nullptr, ss->s);
+    if (op->K > 0) deflate_guess(op, b, x, ss->s);
+    q.phase = SessionSlot::RUNNING;
+    cols.push_back(c);
+    why.push_back(0);
+  }
+  session_advance(ss, cols, why);
+}
+
+// Launch the next chunk if any slot is running; the states are copied to the
+// pinned mirror behind it.
+void session_launch(eb_session *ss) {
+  bool any = false;
+  for (const auto &q : ss->slot) any = any || q.phase == SessionSlot::RUNNING;
+  if (!any) return;
+  session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::chunk(ss, ss->chunk); });
+  HIPCHK(hipMemcpyAsync(ss->hstate.p, ss->state.p, ss->kc * sizeof(KrylovState), hipMemcpyDeviceToHost, ss->s));
+  HIPCHK(hipEventRecord(ss->ev, ss->s));
+  ss->inflight = true;
+  ss->inflight_j = ss->chunk;
+  ++ss->chunks;
+}
+
+size_t op_device_bytes(const eb_op *op) {
+  size_t n = 0;
+  for (const DevBuf *d : {&op->U64, &op->U32, &op->U16, &op->Ueo, &op->Ueo32, &op->Ueo16, &op->Ul, &op->Ur,
+                          &op->partials, &op->state, &op->res, &op->hist})
+    n += d->bytes;
+  for (const auto &kv : op->bufs) n += kv.second.bytes;
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+eb_status eb_session_create(eb_op *op, const eb_session_params *P, void *stream, eb_session **out) {
+  return guarded([&]() {
+    if (!op || !P || !out) fail(EB_ERR_INVALID, "null argument");
+    *out = nullptr;
+    if (!batch_size_ok(P->slots)) fail(EB_ERR_INVALID, "slots must be 1, 2, 4, 8 or 16");
+    if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
+      fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
+    if (!(P->tol > 0) || P->maxiter < 1) fail(EB_ERR_INVALID, "tol > 0 and maxiter >= 1 required");
+    if (P->chunk < 1 || P->chunk > 1024) fail(EB_ERR_INVALID, "chunk must be in [1, 1024]");
+    set_device(op);
+    std::unique_ptr<eb_session> ss(new eb_session);
+    ss->op = op;
+    ss->s = static_cast<hipStream_t>(stream);
+    ss->kc = P->slots;
+    ss->prec = P->inner;
+    ss->tol = P->tol;
+    ss->inner_tol = P->inner_tol > 0 ? P->inner_tol : (P->inner == EB_BF16 ? 1e-2 : (P->inner == EB_FP32 ? 1e-6 : 0.0));
+    ss->maxiter = P->maxiter;
+    ss->chunk = P->chunk;
+    ss->selem = P->inner == EB_FP64 ? sizeof(double2) : (P->inner == EB_FP32 ? sizeof(float2) : sizeof(bf16c));
+    ss->slot.resize(ss->kc);
+    const size_t N = op->N, kc = ss->kc;
+    ss->partials.ensure(8 * kRegionDoubles * sizeof(double));  // one record region per producer kernel
+    ss->state.ensure(kMaxBatch * sizeof(KrylovState));
+    ss->hist.ensure(size_t(ss->chunk + 2) * kc * (4 * sizeof(double2) + sizeof(double)));
+    ss->res.ensure(2 * kMaxBatch * sizeof(double));
+    ss->hstate.ensure(kMaxBatch * sizeof(KrylovState));
+    ss->hres.ensure(2 * kMaxBatch * sizeof(double));
+    for (DevBuf *d : {&ss->b, &ss->x, &ss->r}) d->ensure(kc * N * sizeof(double2));
+    if (op->eo) {
+      ss->bo.ensure(kc * N * sizeof(double2));
+      ss->tmp64.ensure(N * sizeof(double2));
+    }
+    for (DevBuf *d : {&ss->rl, &ss->e, &ss->rhat, &ss->p, &ss->v, &ss->sv, &ss->t}) d->ensure(kc * N * ss->selem);
+    if (op->eo) ss->tmp.ensure(kc * N * ss->selem);
+    // every slot starts stopped (inactive)
+    std::vector<KrylovState> idle(kMaxBatch);
+    for (auto &k : idle) {
+      std::memset(&k, 0, sizeof(k));
+      k.stopped = 1;
+      k.stop_at = -1;
+    }
+    std::memcpy(ss->hstate.p, idle.data(), kMaxBatch * sizeof(KrylovState));
+    HIPCHK(hipMemcpyAsync(ss->state.p, ss->hstate.p, kMaxBatch * sizeof(KrylovState), hipMemcpyHostToDevice, ss->s));
+    session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::prepare(ss.get()); });  // inner-precision links
+    HIPCHK(hipEventCreateWithFlags(&ss->ev, hipEventDisableTiming));
+    HIPCHK(hipStreamSynchronize(ss->s));
+    *out = ss.release();
+  });
+}
+
+eb_status eb_session_destroy(eb_session *ss) {
+  if (!ss) return EB_OK;
+  eb_status rc = guarded([&]() {
+    set_device(ss->op);
+    if (ss->inflight) HIPCHK(hipEventSynchronize(ss->ev));
+    HIPCHK(hipStreamSynchronize(ss->s));
+  });
+  ss->release();
+  delete ss;
+  return rc;
+}
+
+eb_status eb_session_admit(eb_session *ss, const void *b, void *x, int64_t tag, int32_t *slot) {
+  return guarded([&]() {
+    if (!ss || !b || !x) fail(EB_ERR_INVALID, "null argument");
+    for (int c = 0; c < ss->kc; ++c) {
+      SessionSlot &q = ss->slot[c];
+      if (q.phase != SessionSlot::FREE) continue;
+      q = SessionSlot{};
+      q.phase = SessionSlot::PENDING;
+      q.tag = tag;
+      q.b_can = static_cast<const double2 *>(b);
+      q.x_can = static_cast<double2 *>(x);
+      q.t0 = std::chrono::steady_clock::now();
+      if (slot) *slot = c;
+      return;
+    }
+    fail(EB_ERR_CAPACITY, "no free slot");
+  });
+}
+
+eb_status eb_session_step(eb_session *ss) {
+  return guarded([&]() {
+    if (!ss) fail(EB_ERR_INVALID, "null argument");
+    eb_op *op = ss->op;
+    set_device(op);
+    session_harvest(ss);
+    session_admit_pending(ss);
+    session_launch(ss);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+eb_status eb_session_poll(eb_session *ss, int32_t max, int64_t *tags, int32_t *status, eb_stats *stats,
+                          int32_t *n) {
+  return guarded([&]() {
+    if (!ss || !n || max < 0 || (max > 0 && (!tags || !status))) fail(EB_ERR_INVALID, "bad argument");
+    int k = 0;
+    while (k < max && !ss->done.empty()) {
+      const SessionDone &d = ss->done.front();
+      tags[k] = d.tag;
+      status[k] = d.status;
+      if (stats) stats[k] = d.st;
+      ss->done.pop_front();
+      ++k;
+    }
+    *n = k;
+  });
+}
+
+eb_status eb_session_info(eb_session *ss, int32_t *free_slots, int32_t *busy, int32_t *done, uint64_t *device_bytes) {
+  return guarded([&]() {
+    if (!ss) fail(EB_ERR_INVALID, "null argument");
+    int nf = 0, nb = 0;
+    for (const auto &q : ss->slot) (q.phase == SessionSlot::FREE ? nf : nb) += 1;
+    if (free_slots) *free_slots = nf;
+    if (busy) *busy = nb;
+    if (done) *done = int32_t(ss->done.size());
+    if (device_bytes) *device_bytes = ss->device_bytes();
+  });
+}
+
+eb_status eb_op_device_bytes(eb_op *op, uint64_t *bytes) {
+  return guarded([&]() {
+    if (!op || !bytes) fail(EB_ERR_INVALID, "null argument");
+    *bytes = op_device_bytes(op);
+  });
+}
+
+}  // extern "C"
+

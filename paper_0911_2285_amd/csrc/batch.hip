@@ -389,6 +389,88 @@ __global__ void __launch_bounds__(kBlock) k_from_batch(S *__restrict__ dst, cons
   }
 }
 
+// ---- one column of a batch (serving sessions) ------------------------------
+// A serving session keeps KC slots in one batch; a slot is (re)started or
+// harvested while the other columns keep iterating, so these kernels touch
+// column col only.
+// r[:, col] = src (FP64 SoA column, N entries); e[:, col] = 0
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_slot_load(S *__restrict__ r, S *__restrict__ e, const double2 *__restrict__ src, size_t N, int col) {
+  using R = typename Store<S>::R;
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < N; u += size_t(gridDim.x) * kBlock) {
+    const double2 v = src[u];
+    Store<S>::st(r, u * KC + col, cx<R>{R(v.x), R(v.y)});
+    Store<S>::st(e, u * KC + col, cx<R>{R(0), R(0)});
+  }
+}
+// rhat[:, col] = p[:, col] = r[:, col]; partials of ||r_col||^2
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_slot_init(S *__restrict__ rhat, S *__restrict__ p, const S *__restrict__ r, size_t N, int col,
+                double *__restrict__ part) {
+  double v[1] = {0.0};
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < N; u += size_t(gridDim.x) * kBlock) {
+    const size_t i = u * KC + col;
+    const auto rv = Store<S>::ld(r, i);
+    Store<S>::st(rhat, i, rv);
+    Store<S>::st(p, i, rv);
+    v[0] += double(rv.x) * rv.x + double(rv.y) * rv.y;
+  }
+  block_partial_cols<1, 1, kBlock>(v, part, blockIdx.x);
+}
+// the column's state and rho_0 at history index col (iteration 0 of the
+// session's next chunk); a column already at its target stops at once
+template <int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_slot_init_finish(const double *__restrict__ part, int nblk, int col, double tol_abs, int maxiter,
+                       KrylovState *K, KrylovHistory h) {
+  double v[1];
+  sum_partials<1, kBlock>(part, nblk, v);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(v[0]);
+  h.rho[col] = make_double2(v[0], 0.0);
+  h.rn[col] = rn;
+  KrylovState &k = K[col];
+  k.bnorm = 0.0;
+  k.tol_abs = tol_abs;
+  k.def_thr = 0.0;
+  k.rnorm = rn;
+  k.maxiter = maxiter;
+  k.stopped = 0;
+  k.stop_at = 0;
+  k.reason = 0;
+  if (rn <= tol_abs) {
+    k.stopped = 1;
+    k.reason = 1;
+  }
+}
+// x (FP64 SoA column) += e[:, col]
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_slot_add(double2 *__restrict__ x, const S *__restrict__ e, size_t N, int col) {
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < N; u += size_t(gridDim.x) * kBlock) {
+    const auto v = Store<S>::ld(e, u * KC + col);
+    x[u] = make_double2(x[u].x + double(v.x), x[u].y + double(v.y));
+  }
+}
+// End of a chunk of jl iterations: the next chunk counts from j = 1 again.  A
+// running column carries rho_jl to index 0 and jl fewer iterations of budget;
+// a stopped column stays inactive for every j >= 0.
+template <int KC>
+__global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
+  const int col = threadIdx.x;
+  if (col >= KC) return;
+  KrylovState &k = K[col];
+  if (k.stopped) {
+    k.stop_at = -1;
+    return;
+  }
+  h.rho[col] = h.rho[size_t(jl) * KC + col];
+  h.rn[col] = h.rn[size_t(jl) * KC + col];
+  k.maxiter -= jl;
+}
+
 }  // namespace
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
@@ -501,6 +583,38 @@ void launch_from_batch(S *dst, const S *src, const Geom &g, int kc, hipStream_t 
   });
 }
 
+template <typename S>
+void launch_slot_load(S *r, S *e, const double2 *src, size_t N, int kc, int col, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_slot_load<S, KC>), dim3(stream_grid(N)), dim3(kBlock), 0, st, r, e, src, N, col);
+  });
+}
+template <typename S>
+void launch_slot_init(S *rhat, S *p, const S *r, size_t N, int kc, int col, double tol_abs, int maxiter,
+                      KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    const int nb = batch_red_grid(N, 1, 1);
+    EB_LAUNCH((k_slot_init<S, KC>), dim3(nb), dim3(kBlock), 0, st, rhat, p, r, N, col, region(rs, RG_INIT));
+    EB_LAUNCH(k_slot_init_finish<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_INIT), nb, col, tol_abs, maxiter, K,
+              h);
+  });
+}
+template <typename S>
+void launch_slot_add(double2 *x, const S *e, size_t N, int kc, int col, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH((k_slot_add<S, KC>), dim3(stream_grid(N)), dim3(kBlock), 0, st, x, e, N, col);
+  });
+}
+void launch_batch_rebase(KrylovState *K, KrylovHistory h, int kc, int jl, hipStream_t st) {
+  dispatch_kc(kc, [&](auto kt) {
+    constexpr int KC = decltype(kt)::value;
+    EB_LAUNCH(k_batch_rebase<KC>, dim3(1), dim3(64), 0, st, K, h, jl);
+  });
+}
+
 #define EB_BATCH_INST(S)                                                                                           \
   template void launch_bdslash<S>(S *, const S *, const S *, const Geom &, double, bool, int, hipStream_t);        \
   template void launch_bstab_init<S>(S *, S *, const S *, size_t, int, const double *, int, KrylovState *,         \
@@ -518,7 +632,11 @@ void launch_from_batch(S *dst, const S *src, const Geom &g, int kc, hipStream_t 
   template void launch_pack_batch<S>(S *, const double2 *, size_t, int, hipStream_t);                              \
   template void launch_unpack_add_batch<S>(double2 *, const S *, size_t, int, hipStream_t);                        \
   template void launch_to_batch<S>(S *, const S *, const Geom &, int, hipStream_t);                                \
-  template void launch_from_batch<S>(S *, const S *, const Geom &, int, hipStream_t);
+  template void launch_from_batch<S>(S *, const S *, const Geom &, int, hipStream_t);                                \
+  template void launch_slot_load<S>(S *, S *, const double2 *, size_t, int, int, hipStream_t);                     \
+  template void launch_slot_init<S>(S *, S *, const S *, size_t, int, int, double, int, KrylovState *,            \
+                                    KrylovHistory, const RedScratch &, hipStream_t);                              \
+  template void launch_slot_add<S>(double2 *, const S *, size_t, int, int, hipStream_t);
 EB_BATCH_INST(double2)
 EB_BATCH_INST(float2)
 EB_BATCH_INST(bf16c)

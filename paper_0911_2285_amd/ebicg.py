@@ -83,6 +83,17 @@ class _Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class _SessionParams(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int32),
+        ("inner", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("inner_tol", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every symbol declared in include/ebicg.h
@@ -106,6 +117,14 @@ _SIGNATURES = [
     ("eb_timing_classes", ctypes.c_int, [_P, ctypes.c_uint32]),
     ("eb_timing_read", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_double)]),
+    ("eb_session_create", ctypes.c_int, [_P, ctypes.POINTER(_SessionParams), _P, ctypes.POINTER(_P)]),
+    ("eb_session_destroy", ctypes.c_int, [_P]),
+    ("eb_session_admit", ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+    ("eb_session_step", ctypes.c_int, [_P]),
+    ("eb_session_poll", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    ("eb_session_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
+    ("eb_op_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
     ("eb_version", ctypes.c_char_p, []),
 ]
@@ -354,3 +373,73 @@ def timing_read(op):
         _check(lib().eb_timing_read(op.handle, k, ctypes.byref(n), ctypes.byref(ms)))
         out[name] = (n.value, ms.value)
     return out
+
+
+def op_device_bytes(op):
+    """Device bytes the operator holds (links, deflation space, work buffers)."""
+    n = ctypes.c_uint64(0)
+    _check(lib().eb_op_device_bytes(op.handle, ctypes.byref(n)))
+    return n.value
+
+
+class Session:
+    """An eb_session: continuous batching of deflated solves on one operator.
+
+    admit() reserves a slot (host only); step() harvests the chunk in flight,
+    starts admitted requests and launches the next chunk; poll() returns the
+    finished requests as (tag, status name, stats dict)."""
+
+    def __init__(self, op, slots=8, inner="fp32", tol=1e-10, inner_tol=0.0, maxiter=20000, chunk=8, stream=None):
+        import torch
+
+        self.op = op
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        p = _SessionParams(int(slots), PREC[inner], float(tol), float(inner_tol), int(maxiter), int(chunk))
+        self.handle = ctypes.c_void_p()
+        _check(lib().eb_session_create(op.handle, ctypes.byref(p), _stream(self.stream), ctypes.byref(self.handle)))
+        self.slots = int(slots)
+        self._tags = np.zeros(self.slots, np.int64)
+        self._status = np.zeros(self.slots, np.int32)
+        self._stats = (_Stats * self.slots)()
+
+    def admit(self, b, x, tag):
+        """Reserve a slot for solving A x = b (device FP64 canonical spinors, x holds x0);
+        returns the slot, or None when every slot is busy."""
+        import torch
+
+        slot = ctypes.c_int32(-1)
+        rc = lib().eb_session_admit(self.handle, _dev_ptr(b, self.op.N, torch.complex128, "b"),
+                                    _dev_ptr(x, self.op.N, torch.complex128, "x"), int(tag), ctypes.byref(slot))
+        if rc == -7:
+            return None
+        _check(rc)
+        return slot.value
+
+    def step(self):
+        _check(lib().eb_session_step(self.handle))
+
+    def poll(self):
+        n = ctypes.c_int32(0)
+        _check(lib().eb_session_poll(self.handle, self.slots, self._tags.ctypes.data, self._status.ctypes.data,
+                                     self._stats, ctypes.byref(n)))
+        return [(int(self._tags[i]), STATUS.get(int(self._status[i]), int(self._status[i])), self._stats[i].as_dict())
+                for i in range(n.value)]
+
+    def info(self):
+        """{free, busy, done, device_bytes}."""
+        f, b, d = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        nb = ctypes.c_uint64(0)
+        _check(lib().eb_session_info(self.handle, ctypes.byref(f), ctypes.byref(b), ctypes.byref(d),
+                                     ctypes.byref(nb)))
+        return {"free": f.value, "busy": b.value, "done": d.value, "device_bytes": nb.value}
+
+    def close(self):
+        if self.handle and self.handle.value:
+            _check(lib().eb_session_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

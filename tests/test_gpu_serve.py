@@ -1,0 +1,204 @@
+"""Serving sessions (continuous batching) and the request loop over several operators.
+
+Every request must reach the FP64 true residual 1e-10 (checked here with the
+oracle's D on the CPU) and match the dense FP64 solution to 1e-8; a request's
+result must be the same alone and in a mix of requests that arrive while
+others run.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _resid(U, kappa, dims, b, x):
+    V = synth.volume(dims)
+    r = b.ravel() - W.apply_D(U, x.reshape(V, 4, 3), kappa, dims).ravel()
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def cfg0(gpu_lib):
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(0))
+    D = W.dense_D(U, kappa, dims)
+    return dims, kappa, U, D
+
+
+def _space(gpu_lib, U, kappa, dims, n1=2, nev=4, m=16, eo=False):
+    import torch
+
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=n1 * nev, eo=eo)
+    V = synth.volume(dims)
+    for i in range(n1):
+        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(9, i))).to("cuda:0")
+        x = torch.zeros_like(b)
+        gpu_lib.eigbicg_solve(op, b, x, nev=nev, m=m, tol=1e-10)
+    return op
+
+
+def _drain(sess, want):
+    out = {}
+    for _ in range(100000):
+        for tag, status, st in sess.poll():
+            out[tag] = (status, st)
+        if len(out) >= want:
+            return out
+        sess.step()
+    raise AssertionError("session did not finish")
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("eo", [False, True])
+def test_session_same_alone_and_in_the_mix(gpu_lib, cfg0, inner, eo):
+    """Six requests on a 4-slot session, admitted while others run (two at the
+    start, the rest as slots free up): each meets the residual bound, matches
+    the dense solution, and equals the same request solved alone in the
+    session (per-column arithmetic: identical up to rounding, 1e-12)."""
+    import torch
+
+    dims, kappa, U, D = cfg0
+    V = synth.volume(dims)
+    op = _space(gpu_lib, U, kappa, dims, eo=eo)
+    B = np.stack([synth.z2_source(V, synth.rhs_seed(0, 40 + i)).ravel() for i in range(6)])
+    Xs = np.linalg.solve(D, B.T).T
+    sess = gpu_lib.Session(op, slots=4, inner=inner, tol=1e-10, chunk=4)
+    b = [torch.from_numpy(B[i]).to("cuda:0") for i in range(6)]
+    x = [torch.zeros_like(b[i]) for i in range(6)]
+    print(f"session {inner} eo={eo}: admitting 2, then the rest as slots free", flush=True)
+    assert sess.admit(b[0], x[0], 0) is not None and sess.admit(b[1], x[1], 1) is not None
+    sess.step()
+    sess.step()
+    nxt, done, busy_seen = 2, {}, 0
+    for _ in range(100000):
+        for tag, status, st in sess.poll():
+            done[tag] = (status, st)
+        info = sess.info()
+        busy_seen = max(busy_seen, info["busy"])
+        while nxt < 6 and sess.admit(b[nxt], x[nxt], nxt) is not None:
+            nxt += 1
+        if len(done) == 6:
+            break
+        sess.step()
+    assert len(done) == 6 and busy_seen >= 3
+    torch.cuda.synchronize()
+    X = [xi.cpu().numpy() for xi in x]
+    for i in range(6):
+        status, st = done[i]
+        assert status == "EB_OK", (i, status, st)
+        tr = _resid(U, kappa, dims, B[i], X[i])
+        err = np.linalg.norm(X[i] - Xs[i]) / np.linalg.norm(Xs[i])
+        assert tr <= 1e-10 and err <= 1e-8, (i, tr, err)
+        assert st["true_rel_resid"] <= 1e-10
+    # alone: the same sources one by one on an otherwise empty session
+    for i in (0, 3, 5):
+        xa = torch.zeros_like(b[i])
+        assert sess.admit(b[i], xa, 100 + i) is not None
+        (status, st), = _drain(sess, 1).values()
+        assert status == "EB_OK"
+        xa = xa.cpu().numpy()
+        d = np.linalg.norm(xa - X[i]) / np.linalg.norm(X[i])
+        print(f"  request {i}: iters {st['iters']} outer {st['outer_steps']} alone-vs-mix {d:.2e}")
+        assert d <= 1e-12
+    # a full session refuses further admissions until a slot frees
+    xs = [torch.zeros_like(b[0]) for _ in range(5)]
+    assert all(sess.admit(b[0], xs[k], 200 + k) is not None for k in range(4))
+    assert sess.admit(b[0], xs[4], 204) is None
+    _drain(sess, 4)
+    sess.close()
+
+
+def test_session_edge_cases(gpu_lib, cfg0):
+    """A zero source returns x = 0; a start that already solves the system
+    finishes with no iteration; a tiny maxiter ends in EB_ERR_NOT_CONVERGED
+    with the other column unaffected; invalid parameters are rejected."""
+    import torch
+
+    dims, kappa, U, D = cfg0
+    V = synth.volume(dims)
+    op = gpu_lib.op_create(U, kappa, dims)
+    bz = torch.zeros(V * 12, dtype=torch.complex128, device="cuda:0")
+    xz = torch.full_like(bz, 0.5)
+    Bn = synth.z2_source(V, synth.rhs_seed(0, 77)).ravel()
+    bn = torch.from_numpy(Bn).to("cuda:0")
+    xs = torch.from_numpy(np.linalg.solve(D, Bn)).to("cuda:0")
+    sess = gpu_lib.Session(op, slots=2, inner="fp32", tol=1e-10, chunk=8)
+    sess.admit(bz, xz, 1)
+    sess.admit(bn, xs, 2)
+    res = _drain(sess, 2)
+    assert res[1][0] == "EB_OK" and float(xz.abs().max()) == 0.0
+    assert res[2][0] == "EB_OK" and res[2][1]["iters"] == 0
+    sess.close()
+    short = gpu_lib.Session(op, slots=2, inner="fp64", tol=1e-10, maxiter=3, chunk=2)
+    x1 = torch.zeros_like(bn)
+    short.admit(bn, x1, 5)
+    res = _drain(short, 1)
+    assert res[5][0] == "EB_ERR_NOT_CONVERGED" and res[5][1]["iters"] >= 3
+    short.close()
+    for bad in (dict(slots=3), dict(chunk=0), dict(tol=0.0)):
+        kw = dict(slots=2, inner="fp32", tol=1e-10, chunk=4)
+        kw.update(bad)
+        with pytest.raises(gpu_lib.EbicgError) as e:
+            gpu_lib.Session(op, **kw)
+        assert e.value.status == -1
+
+
+def test_server_mix_of_operators(gpu_lib):
+    """A Poisson stream over three resident operators (4^4, an even-odd
+    4^3 x 8 and 2 x 4 x 4 x 8) with an uneven mix: each operator's space grows
+    by eigBiCG over its first two requests and is then used by its session;
+    a tight device-memory budget defers admissions.  Every request meets the
+    residual bound and equals its solution alone to 1e-8."""
+    import torch
+    from paper_0911_2285_amd import serve
+
+    cases = [((4, 4, 4, 4), 0.115, False), ((4, 4, 4, 8), 0.12, True), ((2, 4, 4, 8), 0.118, False)]
+    ops, Us, specs = [], [], []
+    for o, (dims, kappa, eo) in enumerate(cases):
+        U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(4, o + 1))
+        op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8, eo=eo)
+        ops.append(op)
+        Us.append(U)
+        specs.append(serve.OperatorSpec(op, grow=2, nev=4, m=16, slots=4))
+    t, which = serve.poisson_arrivals(24, rate=400.0, mix=[0.5, 0.35, 0.15], seed=7)
+    reqs = []
+    for i, (ti, o) in enumerate(zip(t, which)):
+        V = synth.volume(cases[o][0])
+        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(int(o) + 1, i)).ravel()).pin_memory()
+        reqs.append(serve.Request(i, int(o), float(ti), b))
+    server = serve.Server(specs, inner="fp32", keep_solutions=True)
+    res = server.run(reqs)
+    resident = server.resident_bytes()
+    server.close()
+    assert len(res) == 24 and all(r.status == "EB_OK" for r in res)
+    # room for the operators, their spaces and sessions, plus two of the largest requests
+    budget = resident + 2 * (2 * 16 * 12 * 512)
+    for o in range(3):
+        gpu_lib.defl_reset(ops[o])
+    tight = serve.Server(specs, inner="fp32", keep_solutions=True, hbm_budget=budget)
+    res2 = tight.run(reqs)
+    tight.close()
+    print(f"resident {resident} B, peak unlimited {server.max_resident} B, budget {budget} B, "
+          f"peak {tight.max_resident} B, deferred {tight.deferred}")
+    assert len(res2) == 24 and all(r.status == "EB_OK" for r in res2)
+    assert tight.deferred > 0 and tight.max_resident <= budget
+    by_id = {r.rid: r for r in res2}
+    for r in res:
+        dims, kappa, _ = cases[r.op]
+        tr = _resid(Us[r.op], kappa, dims, reqs[r.rid].b.numpy(), r.x.cpu().numpy())
+        assert tr <= 1e-10, (r.rid, r.kind, tr)
+        # alone: a dense solve of the same system
+        xa = np.linalg.solve(W.dense_D(Us[r.op], kappa, dims), reqs[r.rid].b.numpy())
+        assert np.linalg.norm(r.x.cpu().numpy() - xa) / np.linalg.norm(xa) <= 1e-8
+        x2 = by_id[r.rid].x.cpu().numpy()
+        assert np.linalg.norm(x2 - xa) / np.linalg.norm(xa) <= 1e-8
+    kinds = [r.kind for r in res]
+    assert kinds.count("eigbicg") == 6
+    # the sessions saw the grown spaces
+    assert all(r.K > 0 for r in res if r.kind == "session")
+    s = serve.latency_summary(res)
+    print(s)
+    assert s["p99_ms"] >= s["p50_ms"] > 0
