@@ -302,6 +302,85 @@ def table1_analogue(eb):
     return out
 
 
+SERVING_OPS = [  # (dims, kappa, share of the arrivals)
+    ((8, 8, 8, 8), 0.11, 0.50),
+    ((16, 16, 16, 32), 0.122, 0.35),
+    ((24, 24, 24, 48), 0.123, 0.15),
+]
+
+
+def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=24, tol=1e-10):
+    """Serving: a Poisson stream of Z2-source solve requests over three resident
+    even-odd operators (8^4, 16^3 x 32, 24^3 x 48; arrival mix 50/35/15%).
+    Each operator's first `grow` requests run eigBiCG and grow its deflation
+    space; the rest are batched by its session (FP32 inner, FP64 refinement,
+    `slots` columns) with continuous admission.  A burst (every request at
+    t = 0) gives the saturation throughput; Poisson streams at fractions of it
+    give p50 / p99 latency (arrival to result) beside solves/s."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0911_2285_amd import serve
+
+    specs = []
+    for o, (dims, kappa, _) in enumerate(SERVING_OPS):
+        U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(4, o + 1))
+        op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=grow * nev, eo=True)
+        specs.append(serve.OperatorSpec(op, grow=grow, nev=nev, m=m, slots=slots))
+    mix = [w for _, _, w in SERVING_OPS]
+    _, which = serve.poisson_arrivals(n_req, 1.0, mix, seed=7)
+    sources = []
+    for i, o in enumerate(which):
+        V = synth.volume(SERVING_OPS[o][0])
+        sources.append(torch.from_numpy(synth.z2_source(V, synth.rhs_seed(int(o) + 1, i)).ravel()).pin_memory())
+    budget = 64 << 30
+
+    def run(arrivals, grow_now):
+        for sp in specs:
+            sp.grow = grow if grow_now else 0
+        srv = serve.Server(specs, inner="fp32", tol=tol, hbm_budget=budget)
+        reqs = [serve.Request(i, int(o), float(t), sources[i]) for i, (t, o) in enumerate(zip(arrivals, which))]
+        torch.cuda.synchronize()
+        res = srv.run(reqs)
+        torch.cuda.synchronize()
+        assert len(res) == n_req and all(r.status == "EB_OK" for r in res), [r.status for r in res]
+        assert all(r.stats["true_rel_resid"] <= tol for r in res)
+        summ = serve.latency_summary(res, float(np.min(arrivals)))
+        summ["per_operator_p50_ms"] = [round(1e3 * float(np.median([r.latency for r in res if r.op == o])), 3)
+                                       if any(r.op == o for r in res) else None for o in range(len(specs))]
+        summ["max_resident_bytes"] = srv.max_resident
+        summ["deferred_admissions"] = srv.deferred
+        srv.close()
+        return res, summ
+
+    out = {"operators": [{"dims": list(d), "kappa": k, "share": w, "even_odd": True} for d, k, w in SERVING_OPS],
+           "requests": n_req, "slots": slots, "inner": "fp32", "tol": tol, "hbm_budget_bytes": budget,
+           "growth": {"eigbicg_requests_per_operator": grow, "nev": nev, "m": m}}
+    # 1. a burst with online growth of the spaces: the eigBiCG phase and then the sessions
+    res, summ = run(np.zeros(n_req), True)
+    out["burst_with_growth"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+    out["deflation_space_K"] = [eb.defl_info(sp.op)[0] for sp in specs]
+    log(f"[bench] serving burst with growth: {out['burst_with_growth']}")
+    # 2. a burst on the grown spaces: the saturation throughput of the sessions
+    res, summ = run(np.zeros(n_req), False)
+    sat = summ["solves_per_s"]
+    out["burst"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+    log(f"[bench] serving burst: {out['burst']}")
+    # 3. Poisson streams at fractions of the saturation rate
+    out["poisson"] = []
+    for f in rel_rates:
+        t, _ = serve.poisson_arrivals(n_req, f * sat, mix, seed=7)
+        res, summ = run(t, False)
+        rec = {"rate_fraction": f, "arrival_rate_per_s": round(f * sat, 3)}
+        rec.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()})
+        out["poisson"].append(rec)
+        log(f"[bench] serving poisson {f}: {rec}")
+    for sp in specs:
+        eb.op_destroy(sp.op)
+    return out
+
+
 def pmc_pass(workload):
     """One eigBiCG solve (its BiCG matvec launches are the roofline kernel), then a
     plain device copy of COPY_BYTES for the counter calibration."""
@@ -400,6 +479,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 24^3 x 64 multi-RHS / precision section")
     ap.add_argument("--no-side", action="store_true",
                     help="skip the side records (multi-RHS table, gamma5 and even-odd forms, sweeps)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving (continuous batching) section")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving section and print it")
     ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
@@ -422,6 +503,9 @@ def main():
     from paper_0911_2285_amd import ebicg as eb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serving_only:
+        print(json.dumps({"serving": serving(eb)}), flush=True)
+        return
     W = WORKLOADS[args.workload]
     dims = W["dims"]
     V = synth.volume(dims)
@@ -604,6 +688,8 @@ def main():
             "deflated_solves_per_s": eo_defl,
         }
         log(f"[bench] even-odd form: {extra['even_odd']}")
+        if not args.no_serving:
+            extra["serving"] = serving(eb)
         extra["deflation_sweep"] = deflation_sweep(eb)
         extra["table1_analogue"] = table1_analogue(eb)
         log(f"[bench] deflation sweep: {extra['deflation_sweep']}")

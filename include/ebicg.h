@@ -273,6 +273,9 @@ eb_status eb_session_admit(eb_session *s, const void *b, void *x, int64_t tag, i
  * start their next refinement step); start the admitted requests; launch the next chunk of
  * iterations and return without waiting for it.  Finished requests become pollable. */
 eb_status eb_session_step(eb_session *s);
+/* *ready = 1 when eb_session_step would not wait (no chunk in flight, or it has finished),
+ * else 0.  Does not wait: a loop over several sessions steps the ready ones only. */
+eb_status eb_session_ready(eb_session *s, int32_t *ready);
 /* Take up to max finished requests: tags[i], status[i] (EB_OK, EB_ERR_NOT_CONVERGED,
  * EB_ERR_BREAKDOWN) and stats[i] (may be NULL; seconds = admission to finish).  *n = taken. */
 eb_status eb_session_poll(eb_session *s, int32_t max, int64_t *tags, int32_t *status, eb_stats *stats, int32_t *n);

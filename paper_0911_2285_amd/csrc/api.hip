@@ -2354,6 +2354,21 @@ eb_status eb_session_step(eb_session *ss) {
   });
 }
 
+eb_status eb_session_ready(eb_session *ss, int32_t *ready) {
+  return guarded([&]() {
+    if (!ss || !ready) fail(EB_ERR_INVALID, "null argument");
+    set_device(ss->op);
+    *ready = 1;
+    if (!ss->inflight) return;
+    const hipError_t e = hipEventQuery(ss->ev);
+    if (e == hipErrorNotReady) {
+      *ready = 0;
+      return;
+    }
+    HIPCHK(e);
+  });
+}
+
 eb_status eb_session_poll(eb_session *ss, int32_t max, int64_t *tags, int32_t *status, eb_stats *stats,
                           int32_t *n) {
   return guarded([&]() {

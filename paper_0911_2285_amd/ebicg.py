@@ -121,6 +121,7 @@ _SIGNATURES = [
     ("eb_session_destroy", ctypes.c_int, [_P]),
     ("eb_session_admit", ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
     ("eb_session_step", ctypes.c_int, [_P]),
+    ("eb_session_ready", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     ("eb_session_poll", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
     ("eb_session_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
@@ -417,6 +418,12 @@ class Session:
 
     def step(self):
         _check(lib().eb_session_step(self.handle))
+
+    def ready(self):
+        """True when step() would not wait for the chunk in flight."""
+        r = ctypes.c_int32(0)
+        _check(lib().eb_session_ready(self.handle, ctypes.byref(r)))
+        return bool(r.value)
 
     def poll(self):
         n = ctypes.c_int32(0)

@@ -135,6 +135,7 @@ class Server:
                 waiting[queue[qi].op].append(queue[qi])
                 qi += 1
             blocked = False   # a request waits for memory
+            admitted = False
             for i, sp in enumerate(self.specs):
                 # growth phase: eigBiCG solves one at a time, each absorbing nev pairs
                 if self.grow_left[i] > 0 and waiting[i] and not active[i]:
@@ -145,6 +146,8 @@ class Server:
                         blocked = True
                     else:
                         waiting[i].popleft()
+                        admitted = True
+                        self.max_resident = max(self.max_resident, self.resident_bytes() + inflight + nb)
                         start, K = clock(), self._defl_K(i)
                         b, x = self._upload(i, req)
                         try:
@@ -172,11 +175,15 @@ class Server:
                         raise RuntimeError("session reports no free slot for an admitted request")
                     active[i][req.rid] = _Active(req, b, x, clock(), self._defl_K(i), nb)
                     inflight += nb
+                    admitted = True
             if blocked and not any(active):
                 raise RuntimeError("a waiting request does not fit the device-memory budget with nothing running")
-            self.max_resident = max(self.max_resident, self.resident_bytes() + inflight)
+            if admitted:
+                self.max_resident = max(self.max_resident, self.resident_bytes() + inflight)
+            # step only the sessions whose chunk has finished: a small operator's
+            # slots turn over at its own pace, not at the largest operator's
             for i, sess in enumerate(self.sessions):
-                if active[i]:
+                if active[i] and sess.ready():
                     sess.step()
             for i, sess in enumerate(self.sessions):
                 for tag, status, st in sess.poll():
