@@ -336,10 +336,10 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
         sources.append(torch.from_numpy(synth.z2_source(V, synth.rhs_seed(int(o) + 1, i)).ravel()).pin_memory())
     budget = 64 << 30
 
-    def run(arrivals, grow_now):
+    def run(arrivals, grow_now, graph=True):
         for sp in specs:
             sp.grow = grow if grow_now else 0
-        srv = serve.Server(specs, inner="fp32", tol=tol, hbm_budget=budget)
+        srv = serve.Server(specs, inner="fp32", tol=tol, hbm_budget=budget, graph=graph)
         reqs = [serve.Request(i, int(o), float(t), sources[i]) for i, (t, o) in enumerate(zip(arrivals, which))]
         torch.cuda.synchronize()
         res = srv.run(reqs)
@@ -367,6 +367,10 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
     sat = summ["solves_per_s"]
     out["burst"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
     log(f"[bench] serving burst: {out['burst']}")
+    # the same burst with every chunk launched kernel by kernel (no hipGraph replay)
+    res, summ = run(np.zeros(n_req), False, graph=False)
+    out["burst_direct_launches"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+    log(f"[bench] serving burst, direct launches: {out['burst_direct_launches']}")
     # 3. Poisson streams at fractions of the saturation rate
     out["poisson"] = []
     for f in rel_rates:

@@ -260,6 +260,9 @@ typedef struct {
   double inner_tol; /* residual reduction per refinement step; <= 0: 1e-6 (FP32), 1e-2 (BF16), none (FP64) */
   int32_t maxiter;  /* inner iterations per request, summed over refinement steps */
   int32_t chunk;    /* iterations launched between slot updates, 1..1024 */
+  int32_t graph;    /* 1: the chunk's launches are captured once as a hipGraph and replayed
+                       (on a created stream, not the null stream, and not while kernel timing
+                       is enabled); 0: launched one by one */
 } eb_session_params;
 /* Create a session on `stream` (a hipStream_t; its device memory is allocated here). */
 eb_status eb_session_create(eb_op *op, const eb_session_params *p, void *stream, eb_session **out);

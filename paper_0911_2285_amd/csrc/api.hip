@@ -2023,6 +2023,8 @@ struct eb_session {
   bool inflight = false;
   int inflight_j = 0;
   int64_t chunks = 0;
+  bool use_graph = true;            // replay one captured chunk (hipGraph) instead of launching it
+  hipGraphExec_t graph = nullptr;
   RedScratch rs() { return RedScratch{partials.as<double>()}; }
   KrylovState *K() { return state.as<KrylovState>(); }
   KrylovHistory view() {
@@ -2051,6 +2053,8 @@ struct eb_session {
     hres.release();
     if (ev) (void)hipEventDestroy(ev);
     ev = nullptr;
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
   }
 };
 
@@ -2239,7 +2243,29 @@ void session_launch(eb_session *ss) {
   bool any = false;
   for (const auto &q : ss->slot) any = any || q.phase == SessionSlot::RUNNING;
   if (!any) return;
-  session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::chunk(ss, ss->chunk); });
+  auto launch = [&]() { session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::chunk(ss, ss->chunk); }); };
+  if (ss->use_graph && ss->s != nullptr && !ss->op->timing) {  // the null stream cannot be captured
+    // every chunk launches the same kernels with the same arguments (j = 1..chunk,
+    // the session's buffers and states), so one capture serves all of them
+    if (!ss->graph) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(ss->s, hipStreamCaptureModeThreadLocal));
+      try {
+        launch();
+      } catch (...) {
+        (void)hipStreamEndCapture(ss->s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(ss->s, &g));
+      const hipError_t e = hipGraphInstantiate(&ss->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(e);
+    }
+    HIPCHK(hipGraphLaunch(ss->graph, ss->s));
+  } else {
+    launch();
+  }
   HIPCHK(hipMemcpyAsync(ss->hstate.p, ss->state.p, ss->kc * sizeof(KrylovState), hipMemcpyDeviceToHost, ss->s));
   HIPCHK(hipEventRecord(ss->ev, ss->s));
   ss->inflight = true;
@@ -2279,6 +2305,7 @@ eb_status eb_session_create(eb_op *op, const eb_session_params *P, void *stream,
     ss->inner_tol = P->inner_tol > 0 ? P->inner_tol : (P->inner == EB_BF16 ? 1e-2 : (P->inner == EB_FP32 ? 1e-6 : 0.0));
     ss->maxiter = P->maxiter;
     ss->chunk = P->chunk;
+    ss->use_graph = P->graph != 0;
     ss->selem = P->inner == EB_FP64 ? sizeof(double2) : (P->inner == EB_FP32 ? sizeof(float2) : sizeof(bf16c));
     ss->slot.resize(ss->kc);
     const size_t N = op->N, kc = ss->kc;

@@ -91,6 +91,7 @@ class _SessionParams(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("maxiter", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -390,12 +391,14 @@ class Session:
     starts admitted requests and launches the next chunk; poll() returns the
     finished requests as (tag, status name, stats dict)."""
 
-    def __init__(self, op, slots=8, inner="fp32", tol=1e-10, inner_tol=0.0, maxiter=20000, chunk=8, stream=None):
+    def __init__(self, op, slots=8, inner="fp32", tol=1e-10, inner_tol=0.0, maxiter=20000, chunk=8, graph=True,
+                 stream=None):
         import torch
 
         self.op = op
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        p = _SessionParams(int(slots), PREC[inner], float(tol), float(inner_tol), int(maxiter), int(chunk))
+        p = _SessionParams(int(slots), PREC[inner], float(tol), float(inner_tol), int(maxiter), int(chunk),
+                           int(bool(graph)))
         self.handle = ctypes.c_void_p()
         _check(lib().eb_session_create(op.handle, ctypes.byref(p), _stream(self.stream), ctypes.byref(self.handle)))
         self.slots = int(slots)

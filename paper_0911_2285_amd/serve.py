@@ -72,12 +72,12 @@ class _Active:
 class Server:
     """Runs a stream of requests over the given operators.
 
-    inner / tol / maxiter / chunk: the sessions' parameters (eb_session_params);
+    inner / tol / maxiter / chunk / graph: the sessions' parameters (eb_session_params);
     hbm_budget: device bytes the server may hold (operators, sessions and the
     requests' b and x); a request waits while it would exceed it."""
 
     def __init__(self, specs, inner="fp32", tol=1e-10, maxiter=20000, chunk=8, hbm_budget=None,
-                 keep_solutions=False):
+                 keep_solutions=False, graph=True):
         import torch
 
         self.specs = list(specs)
@@ -89,7 +89,7 @@ class Server:
         self.sessions = []
         for sp, st in zip(self.specs, self.streams):
             self.sessions.append(ebicg.Session(sp.op, slots=sp.slots, inner=inner, tol=tol, maxiter=maxiter,
-                                               chunk=chunk, stream=st))
+                                               chunk=chunk, graph=graph, stream=st))
         self.grow_left = [sp.grow for sp in self.specs]
         self.max_resident = 0
         self.deferred = 0   # admissions postponed by the memory budget

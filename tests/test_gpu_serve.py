@@ -202,3 +202,44 @@ def test_server_mix_of_operators(gpu_lib):
     s = serve.latency_summary(res)
     print(s)
     assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("eo", [False, True])
+def test_session_graph_replay_matches_direct_launches(gpu_lib, cfg0, inner, eo):
+    """A session that replays one captured chunk (hipGraph) gives the same
+    solutions, bit for bit, as one that launches every chunk: five requests
+    admitted at different times, so every replay runs between eager harvests
+    and admissions, and each replay's arithmetic feeds the results."""
+    import torch
+
+    dims, kappa, U, D = cfg0
+    V = synth.volume(dims)
+    op = _space(gpu_lib, U, kappa, dims, eo=eo)
+    B = np.stack([synth.z2_source(V, synth.rhs_seed(0, 60 + i)).ravel() for i in range(5)])
+    out = {}
+    stream = torch.cuda.Stream()  # a created stream: the null stream cannot be captured
+    for graph in (True, False):
+        sess = gpu_lib.Session(op, slots=2, inner=inner, tol=1e-10, chunk=3, graph=graph, stream=stream)
+        b = [torch.from_numpy(B[i]).to("cuda:0") for i in range(5)]
+        x = [torch.zeros_like(b[i]) for i in range(5)]
+        torch.cuda.synchronize()
+        nxt, done, steps = 0, {}, 0
+        for _ in range(100000):
+            for tag, status, st in sess.poll():
+                done[tag] = (status, st)
+            while nxt < 5 and sess.admit(b[nxt], x[nxt], nxt) is not None:
+                nxt += 1
+            if len(done) == 5:
+                break
+            sess.step()
+            steps += 1
+        sess.close()
+        torch.cuda.synchronize()
+        assert all(done[i][0] == "EB_OK" for i in range(5))
+        out[graph] = ([xi.cpu().numpy() for xi in x], [done[i][1]["iters"] for i in range(5)], steps)
+    print(f"{inner} eo={eo}: iterations {out[True][1]}, steps {out[True][2]} (graph) / {out[False][2]}")
+    assert out[True][1] == out[False][1]
+    for i in range(5):
+        assert np.array_equal(out[True][0][i], out[False][0][i]), i
+        assert _resid(U, kappa, dims, B[i], out[True][0][i]) <= 1e-10
