@@ -28,6 +28,7 @@
 #include "../../include/ebicg.h"
 #include "hostla.h"
 #include "kernels.h"
+#include "slot.h"
 
 using namespace ebicg;
 

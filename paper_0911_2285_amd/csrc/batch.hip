@@ -20,6 +20,7 @@
 #include "device_common.h"
 #include "kernel_util.h"
 #include "kernels.h"
+#include "slot.h"
 #include "stencil.h"
 
 namespace ebicg {
