@@ -285,6 +285,23 @@ eb_status eb_session_poll(eb_session *s, int32_t max, int64_t *tags, int32_t *st
 /* Free and busy slots, finished requests not yet polled, device bytes the session holds
  * (any pointer may be NULL). */
 eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int32_t *done, uint64_t *device_bytes);
+/* ---- Batch autotuning (multi-RHS tile shapes) ------------------------------
+ * The batched solvers' operator (the stencil, or Dhat for an even-odd operator)
+ * has two tile forms for each k: stage = 1 stages each block's tile of
+ * 256 / k sites in LDS, stage = 0 reads every neighbour from global memory.
+ * eb_op_batch_tune runs the autotuner once per operator and precision (it
+ * times both forms for k = 1, 2, 4, 8, 16 on `stream`, three repetitions after
+ * a warm-up, and keeps per k the faster form and overall the k with the lowest
+ * time per right-hand side) and reports: *k_best; stage[5] (may be NULL) the
+ * form used for k = 1, 2, 4, 8, 16; ms_per_rhs[10] (may be NULL) the measured
+ * time per right-hand side, [2 i + stage] for k = 2^i.  Batched solves with
+ * batch = 0, sessions and eb_op_apply_block / eb_op_apply_schur_block use the
+ * forms chosen here (before tuning: LDS staging for k = 1 and for BF16). */
+eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_best, int32_t *stage,
+                           double *ms_per_rhs);
+/* Set the tile form for one precision and k (stage 1, 0, or -1 for the built-in rule);
+ * results agree to rounding between the forms.  Host-only. */
+eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage);
 /* Device bytes the operator holds (links, deflation space, work buffers). */
 eb_status eb_op_device_bytes(eb_op *op, uint64_t *bytes);
 

@@ -145,6 +145,16 @@ struct eb_op {
   // the measured stencil time per right-hand side of each candidate
   int batch_choice[3] = {0, 0, 0};
   double batch_ms[3][kMaxBatch + 1] = {};
+  // tile form of the batched stencils per precision and k (1: LDS-staged
+  // tile, 0: global neighbour reads, -1: the built-in rule), chosen by the
+  // tuner or set by the caller; the tuner's time per right-hand side (ms) of
+  // each form
+  int batch_stage[3][kMaxBatch + 1];
+  double batch_stage_ms[3][kMaxBatch + 1][2] = {};
+  eb_op() {
+    for (auto &row : batch_stage)
+      for (int &v : row) v = -1;
+  }
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::map<std::string, DevBuf> bufs;
   // kernel timing (eb_timing_enable, eb_timing_classes)
@@ -626,11 +636,11 @@ int tune_batch(eb_op *op, hipStream_t s) {
   S *a = op->raw<S>(tag + "b_p", n * sizeof(S));
   S *b = op->raw<S>(tag + "b_v", n * sizeof(S));
   S *tmp = op->eo ? op->raw<S>(tag + "b_eo_tmp", n * sizeof(S)) : nullptr;
-  auto apply = [&](int kc) {
+  auto apply = [&](int kc, int stage) {
     if (op->eo)
-      launch_bschur_eo<S>(b, a, tmp, U, op->g, op->kappa, false, kc, s);
+      launch_bschur_eo<S>(b, a, tmp, U, op->g, op->kappa, false, kc, s, stage);
     else
-      launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s);
+      launch_bdslash<S>(b, a, U, op->g, op->kappa, false, kc, s, stage);
   };
   HIPCHK(hipMemsetAsync(a, 0, n * sizeof(S), s));
   hipEvent_t e0, e1;
@@ -638,18 +648,27 @@ int tune_batch(eb_op *op, hipStream_t s) {
   HIPCHK(hipEventCreate(&e1));
   int best = 1;
   double best_t = HUGE_VAL;
+  const int pi = Inner<S>::index;
   for (int kc = 1; kc <= kMaxBatch; kc *= 2) {
-    apply(kc);
-    HIPCHK(hipEventRecord(e0, s));
-    for (int rep = 0; rep < 3; ++rep) apply(kc);
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    const double per_rhs = ms / (3.0 * kc);
-    op->batch_ms[Inner<S>::index][kc] = per_rhs;
-    if (per_rhs < 0.97 * best_t) {
-      best_t = per_rhs;
+    double t_kc = HUGE_VAL;
+    for (int stage = 0; stage < 2; ++stage) {  // both tile forms
+      apply(kc, stage);
+      HIPCHK(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 3; ++rep) apply(kc, stage);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      const double per_rhs = ms / (3.0 * kc);
+      op->batch_stage_ms[pi][kc][stage] = per_rhs;
+      if (per_rhs < t_kc) {
+        t_kc = per_rhs;
+        op->batch_stage[pi][kc] = stage;
+      }
+    }
+    op->batch_ms[pi][kc] = t_kc;
+    if (t_kc < 0.97 * best_t) {
+      best_t = t_kc;
       best = kc;
     }
   }
@@ -681,6 +700,7 @@ void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double 
   const Geom gv = vector_geom(op);
   KrylovState *K = op->S();
   KrylovHistory h = op->history((maxiter + 4) * kc);
+  const int stage = op->batch_stage[Inner<S>::index][kc];
   launch_bstab_init<S>(rhat, p, r, op->N, kc, tol_dev, maxiter, K, h, op->rs(), s);
   KrylovState hs[kMaxBatch];
   const int poll = 8;
@@ -697,14 +717,15 @@ void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double 
       ++j;
       if (op->eo)
         TIMED(EB_K_BSTAB_V, s,
-              launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+              launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
       else
-        TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+        TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
       TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, op->rs(), s));
       if (op->eo)
-        TIMED(EB_K_BSTAB_T, s, launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+        TIMED(EB_K_BSTAB_T, s,
+              launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
       else
-        TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, op->rs(), s));
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
       TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, op->rs(), s));
       TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, gv, j, kc, K, h, op->rs(), s));
     }
@@ -1774,7 +1795,8 @@ eb_status eb_op_apply_block(eb_op *op, void *out, const void *in, int32_t k, int
       S *a = op->raw<S>(std::string(Inner<S>::tag) + "blk_a", n * sizeof(S));
       S *b = op->raw<S>(std::string(Inner<S>::tag) + "blk_b", n * sizeof(S));
       launch_to_batch<S>(a, static_cast<const S *>(in), op->g, k, s);
-      TIMED(EB_K_BDSLASH, s, launch_bdslash<S>(b, a, U, op->g, op->kappa, dagger != 0, k, s));
+      TIMED(EB_K_BDSLASH, s,
+            launch_bdslash<S>(b, a, U, op->g, op->kappa, dagger != 0, k, s, op->batch_stage[Inner<S>::index][k]));
       launch_from_batch<S>(static_cast<S *>(out), b, op->g, k, s);
     };
     if (prec == EB_FP64)
@@ -1812,7 +1834,8 @@ eb_status eb_op_apply_schur_block(eb_op *op, void *out, const void *in, int32_t 
       S *b = op->raw<S>(tg + "sblk_b", N * k * sizeof(S));
       S *t = op->raw<S>(tg + "sblk_t", N * k * sizeof(S));
       launch_pack_batch<S>(a, e, N, k, s);
-      TIMED(EB_K_BDSLASH, s, launch_bschur_eo<S>(b, a, t, U, op->g, op->kappa, dagger != 0, k, s));
+      TIMED(EB_K_BDSLASH, s,
+            launch_bschur_eo<S>(b, a, t, U, op->g, op->kappa, dagger != 0, k, s, op->batch_stage[Inner<S>::index][k]));
       HIPCHK(hipMemsetAsync(e, 0, N * k * sizeof(double2), s));
       launch_unpack_add_batch<S>(e, b, N, k, s);
     };
@@ -2075,19 +2098,20 @@ struct SessionOps {
     KrylovHistory h = ss->view();
     const RedScratch rs = ss->rs();
     const int kc = ss->kc;
+    const int stage = op->batch_stage[Inner<S>::index][kc];
     hipStream_t s = ss->s;
     S *x = at(ss->e), *r = at(ss->rl), *rhat = at(ss->rhat), *p = at(ss->p), *v = at(ss->v), *sv = at(ss->sv),
       *t = at(ss->t), *tmp = op->eo ? at(ss->tmp) : nullptr;
     for (int j = 1; j <= n; ++j) {
       if (op->eo)
-        TIMED(EB_K_BSTAB_V, s, launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, rs, s));
+        TIMED(EB_K_BSTAB_V, s, launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, rs, s, stage));
       else
-        TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, rs, s));
+        TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, rs, s, stage));
       TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, rs, s));
       if (op->eo)
-        TIMED(EB_K_BSTAB_T, s, launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, rs, s));
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, rs, s, stage));
       else
-        TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, rs, s));
+        TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, rs, s, stage));
       TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, rs, s));
       TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, gv, j, kc, K, h, rs, s));
     }
@@ -2423,6 +2447,35 @@ eb_status eb_session_info(eb_session *ss, int32_t *free_slots, int32_t *busy, in
     if (busy) *busy = nb;
     if (done) *done = int32_t(ss->done.size());
     if (device_bytes) *device_bytes = ss->device_bytes();
+  });
+}
+
+eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_best, int32_t *stage,
+                           double *ms_per_rhs) {
+  return guarded([&]() {
+    if (!op || !k_best) fail(EB_ERR_INVALID, "null argument");
+    if (prec != EB_FP64 && prec != EB_FP32 && prec != EB_BF16) fail(EB_ERR_INVALID, "unknown precision");
+    set_device(op);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    *k_best = choose_batch(op, prec, s);
+    const int pi = prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2);
+    for (int i = 0, kc = 1; kc <= kMaxBatch; ++i, kc *= 2) {
+      if (stage) stage[i] = op->batch_stage[pi][kc];
+      if (ms_per_rhs) {
+        ms_per_rhs[2 * i] = op->batch_stage_ms[pi][kc][0];
+        ms_per_rhs[2 * i + 1] = op->batch_stage_ms[pi][kc][1];
+      }
+    }
+  });
+}
+
+eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    if (prec != EB_FP64 && prec != EB_FP32 && prec != EB_BF16) fail(EB_ERR_INVALID, "unknown precision");
+    if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
+    if (stage < -1 || stage > 1) fail(EB_ERR_INVALID, "stage must be -1, 0 or 1");
+    op->batch_stage[prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2)][k] = stage;
   });
 }
 

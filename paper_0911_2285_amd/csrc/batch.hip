@@ -39,20 +39,29 @@ __device__ __forceinline__ bool col_active(const KrylovState *K, int col, int j)
   return !(K[col].stopped && j > K[col].stop_at);
 }
 
-// LDS staging (stencil.h) pays when a tile holds many sites or the entries
-// are small: measured on MI355X it helps for one column at every precision
-// and for BF16 at every batch size, and slows FP64/FP32 batches (a tile of
-// 256 / KC sites leaves most neighbours outside it).
+// Tile form of the batched stencils: STG = true stages each block's tile of
+// kBlock / KC sites in LDS (stencil.h), false reads every neighbour from
+// global memory.  Staging pays when a tile holds many sites or the entries
+// are small; the default (stage < 0 at launch) is the rule measured on
+// MI355X: stage for one column at every precision and for BF16 at every
+// batch size.  The batch autotuner times both forms per precision and k.
 template <typename S, int KC>
 constexpr bool kStage = KC == 1 || std::is_same<S, bf16c>::value;
+template <typename S, int KC, typename F>
+void dispatch_stage(int stage, F &&f) {
+  if (stage < 0 ? kStage<S, KC> : stage != 0)
+    f(std::true_type{});
+  else
+    f(std::false_type{});
+}
 
-template <typename S, int KC, int SF>
+template <typename S, int KC, int SF, bool STG>
 __global__ void __launch_bounds__(kBlock)
     k_bdslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa) {
   using R = typename Store<S>::R;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const R k = R(kappa);
-  if constexpr (kStage<S, KC>) {
+  if constexpr (STG) {
     __shared__ S tile[12 * kBlock];
     constexpr int spt = kBlock / KC;  // sites per tile
     const int ntiles = (g.V + spt - 1) / spt, col = threadIdx.x % KC;
@@ -126,7 +135,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // v = D p; partials of (rhat, v) per column
-template <typename S, int KC>
+template <typename S, int KC, bool STG>
 __global__ void __launch_bounds__(kBlock)
     k_bstab_v(S *__restrict__ vout, const S *__restrict__ p, const S *__restrict__ rhat, const S *__restrict__ U,
               Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part) {
@@ -147,7 +156,7 @@ __global__ void __launch_bounds__(kBlock)
       d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
     }
   };
-  if constexpr (kStage<S, KC>) {
+  if constexpr (STG) {
     __shared__ S tile[12 * kBlock];
     constexpr int spt = kBlock / KC;
     const int ntiles = (g.V + spt - 1) / spt;
@@ -209,7 +218,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // t = D s; partials of (t, s), (t, t) per column
-template <typename S, int KC>
+template <typename S, int KC, bool STG>
 __global__ void __launch_bounds__(kBlock)
     k_bstab_t(S *__restrict__ tout, const S *__restrict__ sv, const S *__restrict__ U, Geom g, double kappa, int j,
               const KrylovState *K, double *__restrict__ part) {
@@ -231,7 +240,7 @@ __global__ void __launch_bounds__(kBlock)
       d[2] += double(o.x) * o.x + double(o.y) * o.y;
     }
   };
-  if constexpr (kStage<S, KC>) {
+  if constexpr (STG) {
     __shared__ S tile[12 * kBlock];
     constexpr int spt = kBlock / KC;
     const int ntiles = (g.V + spt - 1) / spt;
@@ -477,14 +486,18 @@ __global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
 
 template <typename S>
-void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st) {
+void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,
+                    int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
-    const dim3 grid(nblocks_for(size_t(g.V) * KC));
-    if (dagger)
-      EB_LAUNCH((k_bdslash<S, KC, +1>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
-    else
-      EB_LAUNCH((k_bdslash<S, KC, -1>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+    dispatch_stage<S, KC>(stage, [&](auto sg) {
+      constexpr bool STG = decltype(sg)::value;
+      const dim3 grid(nblocks_for(size_t(g.V) * KC));
+      if (dagger)
+        EB_LAUNCH((k_bdslash<S, KC, +1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+      else
+        EB_LAUNCH((k_bdslash<S, KC, -1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+    });
   });
 }
 
@@ -501,11 +514,13 @@ void launch_bstab_init(S *rhat, S *p, const S *r, size_t N, int kc, const double
 
 template <typename S>
 void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, int kc,
-                    KrylovState *K, const RedScratch &rs, hipStream_t st) {
+                    KrylovState *K, const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
-    EB_LAUNCH((k_bstab_v<S, KC>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st, v, p, rhat, U, g, kappa,
-              j, K, region(rs, RG_V));
+    dispatch_stage<S, KC>(stage, [&](auto sg) {
+      EB_LAUNCH((k_bstab_v<S, KC, decltype(sg)::value>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st,
+                v, p, rhat, U, g, kappa, j, K, region(rs, RG_V));
+    });
   });
 }
 
@@ -523,11 +538,13 @@ void launch_bstab_s(S *sv, const S *r, const S *v, const Geom &g, int j, int kc,
 
 template <typename S>
 void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, int j, int kc, KrylovState *K,
-                    const RedScratch &rs, hipStream_t st) {
+                    const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
-    EB_LAUNCH((k_bstab_t<S, KC>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st, t, sv, U, g, kappa, j,
-              K, region(rs, RG_T));
+    dispatch_stage<S, KC>(stage, [&](auto sg) {
+      EB_LAUNCH((k_bstab_t<S, KC, decltype(sg)::value>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st,
+                t, sv, U, g, kappa, j, K, region(rs, RG_T));
+    });
   });
 }
 
@@ -617,15 +634,15 @@ void launch_batch_rebase(KrylovState *K, KrylovHistory h, int kc, int jl, hipStr
 }
 
 #define EB_BATCH_INST(S)                                                                                           \
-  template void launch_bdslash<S>(S *, const S *, const S *, const Geom &, double, bool, int, hipStream_t);        \
+  template void launch_bdslash<S>(S *, const S *, const S *, const Geom &, double, bool, int, hipStream_t, int);   \
   template void launch_bstab_init<S>(S *, S *, const S *, size_t, int, const double *, int, KrylovState *,         \
                                      KrylovHistory, const RedScratch &, hipStream_t);                              \
   template void launch_bstab_v<S>(S *, const S *, const S *, const S *, const Geom &, double, int, int,            \
-                                  KrylovState *, const RedScratch &, hipStream_t);                                 \
+                                  KrylovState *, const RedScratch &, hipStream_t, int);                            \
   template void launch_bstab_s<S>(S *, const S *, const S *, const Geom &, int, int, KrylovState *, KrylovHistory, \
                                   const RedScratch &, hipStream_t);                                                \
   template void launch_bstab_t<S>(S *, const S *, const S *, const Geom &, double, int, int, KrylovState *,        \
-                                  const RedScratch &, hipStream_t);                                                \
+                                  const RedScratch &, hipStream_t, int);                                           \
   template void launch_bstab_xr<S>(S *, S *, const S *, const S *, const S *, const S *, const Geom &, int, int,   \
                                    KrylovState *, KrylovHistory, const RedScratch &, hipStream_t);                 \
   template void launch_bstab_p<S>(S *, const S *, const S *, const Geom &, int, int, KrylovState *, KrylovHistory, \

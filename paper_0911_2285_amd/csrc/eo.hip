@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_eo_finish(const double *__restrict__
 template <typename S, int KC>
 constexpr bool kStageEo = KC == 1 || std::is_same<S, bf16c>::value;
 
-template <typename S, int KC, int SF, int E>
+template <typename S, int KC, int SF, int E, bool STG>
 __global__ void __launch_bounds__(kBlock)
     k_bhop_eo(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ Uf, const S *__restrict__ Ub,
               Geom g, int P, double a_, const S *__restrict__ id, const S *__restrict__ dv, int j,
@@ -224,14 +224,14 @@ __global__ void __launch_bounds__(kBlock)
   const int ntiles = (Vh + spt - 1) / spt;
   for (int T = lb; T < ntiles; T += gridDim.x) {
     const int h0 = T * spt, h = h0 + int(threadIdx.x) / KC;
-    if constexpr (kStageEo<S, KC>) {
+    if constexpr (STG) {
       __syncthreads();  // the previous tile's readers are done
       stage_tile<S, KC>(tile, in, h0, Vh);
       __syncthreads();
     }
     if (!act || h >= Vh) continue;
     cx<R> acc[12];
-    if constexpr (kStageEo<S, KC>)
+    if constexpr (STG)
       eo_hops<SF, S>(acc, TileSrc<S, KC>{in + col, tile + col, h0, Vh}, Uf, Ub, g, P, h);
     else
       eo_hops<SF, S>(acc, GlobSrc<S, KC>{in + col, Vh}, Uf, Ub, g, P, h);
@@ -278,13 +278,17 @@ void hop(S *out, const S *in, const S *Ueo, const Geom &g, int P, double a, cons
 // count the batched BiCGStab's consumers read for spinors of V/2 sites
 template <int SF, int E, typename S>
 void bhop(S *out, const S *in, const S *Ueo, const Geom &g, int P, double a, const S *id, const S *dv, int j,
-          const KrylovState *K, double *part, int kc, hipStream_t st) {
+          const KrylovState *K, double *part, int kc, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     constexpr int NV = EoNV<E>::v;
     const int grid = batch_stencil_grid(g.V / 2, KC, NV > 0 ? NV : 1);
-    EB_LAUNCH((k_bhop_eo<S, KC, SF, E>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
-              links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
+    if (stage < 0 ? kStageEo<S, KC> : stage != 0)
+      EB_LAUNCH((k_bhop_eo<S, KC, SF, E, true>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
+                links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
+    else
+      EB_LAUNCH((k_bhop_eo<S, KC, SF, E, false>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
+                links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
   });
 }
 
@@ -370,28 +374,28 @@ void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g,
 
 template <typename S>
 void launch_bschur_eo(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger, int kc,
-                      hipStream_t st) {
+                      hipStream_t st, int stage) {
   if (dagger) {
-    bhop<+1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, kc, st);
-    bhop<+1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, kc, st);
+    bhop<+1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, kc, st, stage);
+    bhop<+1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, kc, st, stage);
   } else {
-    bhop<-1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, kc, st);
-    bhop<-1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, kc, st);
+    bhop<-1, EO_TMP, S>(tmp, in, Ueo, g, 1, 0.0, nullptr, nullptr, 0, nullptr, nullptr, kc, st, stage);
+    bhop<-1, EO_SCHUR, S>(out, tmp, Ueo, g, 0, kappa * kappa, in, nullptr, 0, nullptr, nullptr, kc, st, stage);
   }
 }
 
 template <typename S>
 void launch_bstab_v_eo(S *v, const S *p, const S *rhat, S *tmp, const S *Ueo, const Geom &g, double kappa, int j,
-                       int kc, KrylovState *K, const RedScratch &rs, hipStream_t st) {
-  bhop<-1, EO_TMP, S>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, kc, st);
-  bhop<-1, EO_SIGMA, S>(v, tmp, Ueo, g, 0, kappa * kappa, p, rhat, j, K, region(rs, RG_V), kc, st);
+                       int kc, KrylovState *K, const RedScratch &rs, hipStream_t st, int stage) {
+  bhop<-1, EO_TMP, S>(tmp, p, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, kc, st, stage);
+  bhop<-1, EO_SIGMA, S>(v, tmp, Ueo, g, 0, kappa * kappa, p, rhat, j, K, region(rs, RG_V), kc, st, stage);
 }
 
 template <typename S>
 void launch_bstab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, double kappa, int j, int kc,
-                       KrylovState *K, const RedScratch &rs, hipStream_t st) {
-  bhop<-1, EO_TMP, S>(tmp, sv, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, kc, st);
-  bhop<-1, EO_STABT, S>(t, tmp, Ueo, g, 0, kappa * kappa, sv, nullptr, j, K, region(rs, RG_T), kc, st);
+                       KrylovState *K, const RedScratch &rs, hipStream_t st, int stage) {
+  bhop<-1, EO_TMP, S>(tmp, sv, Ueo, g, 1, 0.0, nullptr, nullptr, j, K, nullptr, kc, st, stage);
+  bhop<-1, EO_STABT, S>(t, tmp, Ueo, g, 0, kappa * kappa, sv, nullptr, j, K, region(rs, RG_T), kc, st, stage);
 }
 
 #define EB_EO_INST(S)                                                                                              \
@@ -400,11 +404,12 @@ void launch_bstab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, d
   template void launch_stab_t_eo<S>(S *, const S *, S *, const S *, const Geom &, double, int, KrylovState *,       \
                                     const RedScratch &, hipStream_t);                                               \
   template void launch_schur_eo_s<S>(S *, const S *, S *, const S *, const Geom &, double, bool, hipStream_t);    \
-  template void launch_bschur_eo<S>(S *, const S *, S *, const S *, const Geom &, double, bool, int, hipStream_t); \
+  template void launch_bschur_eo<S>(S *, const S *, S *, const S *, const Geom &, double, bool, int, hipStream_t,  \
+                                    int);                                                                          \
   template void launch_bstab_v_eo<S>(S *, const S *, const S *, S *, const S *, const Geom &, double, int, int,    \
-                                     KrylovState *, const RedScratch &, hipStream_t);                             \
+                                     KrylovState *, const RedScratch &, hipStream_t, int);                        \
   template void launch_bstab_t_eo<S>(S *, const S *, S *, const S *, const Geom &, double, int, int,              \
-                                     KrylovState *, const RedScratch &, hipStream_t);
+                                     KrylovState *, const RedScratch &, hipStream_t, int);
 EB_EO_INST(double2)
 EB_EO_INST(float2)
 EB_EO_INST(bf16c)

@@ -191,15 +191,17 @@ void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g,
 // (c, h, col) at (c V/2 + h) kc + col), tmp the same size.  out = Dhat in per
 // column; the BiCGStab forms as launch_bstab_v/t, with records for the batched
 // BiCGStab passes called with a geometry of V/2 sites.
+// stage: tile form of the batched hops (1: the input tile staged in LDS, 0:
+// neighbours read from global memory, < 0: the built-in rule).
 template <typename S>
 void launch_bschur_eo(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger, int kc,
-                      hipStream_t st);
+                      hipStream_t st, int stage = -1);
 template <typename S>
 void launch_bstab_v_eo(S *v, const S *p, const S *rhat, S *tmp, const S *Ueo, const Geom &g, double kappa, int j,
-                       int kc, KrylovState *K, const RedScratch &rs, hipStream_t st);
+                       int kc, KrylovState *K, const RedScratch &rs, hipStream_t st, int stage = -1);
 template <typename S>
 void launch_bstab_t_eo(S *t, const S *sv, S *tmp, const S *Ueo, const Geom &g, double kappa, int j, int kc,
-                       KrylovState *K, const RedScratch &rs, hipStream_t st);
+                       KrylovState *K, const RedScratch &rs, hipStream_t st, int stage = -1);
 
 // ---- tall-skinny projections (FP64) ------------------------------------------------
 // out[a + b*nx] = sum_i conj(X_a[i]) Y_b[i];  X_a = X + a*ldx, Y_b = Y + b*ldy.
@@ -259,21 +261,24 @@ void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K
 // Per-column solver state K[col], history entries at j kc + col.
 constexpr int kMaxBatch = 16;
 bool batch_size_ok(int kc);
+// stage: tile form of the batched stencils (1: each block's tile staged in
+// LDS, 0: neighbours read from global memory, < 0: the built-in rule)
 template <typename S>
-void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st);
+void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,
+                    int stage = -1);
 // rhat = p = r; rho_0, ||r_0|| per column; column col stops at once if ||r_0|| <= tol_abs[col] (device)
 template <typename S>
 void launch_bstab_init(S *rhat, S *p, const S *r, size_t N, int kc, const double *tol_abs, int maxiter,
                        KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st);
 template <typename S>
 void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, int kc,
-                    KrylovState *K, const RedScratch &rs, hipStream_t st);
+                    KrylovState *K, const RedScratch &rs, hipStream_t st, int stage = -1);
 template <typename S>
 void launch_bstab_s(S *s, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
                     const RedScratch &rs, hipStream_t st);
 template <typename S>
 void launch_bstab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, int kc, KrylovState *K,
-                    const RedScratch &rs, hipStream_t st);
+                    const RedScratch &rs, hipStream_t st, int stage = -1);
 template <typename S>
 void launch_bstab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, const Geom &g, int j, int kc,
                      KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st);

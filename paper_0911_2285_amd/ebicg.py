@@ -127,6 +127,8 @@ _SIGNATURES = [
     ("eb_session_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
     ("eb_op_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("eb_op_batch_tune", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int32), _P, _P]),
+    ("eb_op_batch_set_tile", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
     ("eb_version", ctypes.c_char_p, []),
 ]
@@ -382,6 +384,24 @@ def op_device_bytes(op):
     n = ctypes.c_uint64(0)
     _check(lib().eb_op_device_bytes(op.handle, ctypes.byref(n)))
     return n.value
+
+
+def op_batch_tune(op, prec="fp32", stream=None):
+    """The batch autotuner's choice for one precision: {"k": best k, "stage": {k: tile form},
+    "ms_per_rhs": {k: [unstaged, LDS-staged]}} (runs the tuner once per operator and precision)."""
+    kb = ctypes.c_int32(0)
+    stage = np.zeros(5, np.int32)
+    ms = np.zeros(10, np.float64)
+    _check(lib().eb_op_batch_tune(op.handle, PREC[prec], _stream(stream), ctypes.byref(kb), stage.ctypes.data,
+                                  ms.ctypes.data))
+    ks = [1, 2, 4, 8, 16]
+    return {"k": kb.value, "stage": {k: int(stage[i]) for i, k in enumerate(ks)},
+            "ms_per_rhs": {k: [float(ms[2 * i]), float(ms[2 * i + 1])] for i, k in enumerate(ks)}}
+
+
+def op_batch_set_tile(op, prec, k, stage):
+    """Force the tile form of the batched stencil for (prec, k): 1 LDS-staged, 0 global reads, -1 built-in rule."""
+    _check(lib().eb_op_batch_set_tile(op.handle, PREC[prec], int(k), int(stage)))
 
 
 class Session:

@@ -250,3 +250,65 @@ def test_dslash_block_parity(gpu_lib, k):
     with pytest.raises(gpu_lib.EbicgError):
         gpu_lib.op_apply_block(op, torch.empty(3 * 12 * V, dtype=torch.complex128, device=dev),
                                torch.zeros(3 * 12 * V, dtype=torch.complex128, device=dev), 3)
+
+
+@pytest.mark.parametrize("eo", [False, True])
+def test_block_tile_forms_and_tuner(gpu_lib, eo):
+    """Both tile forms of the multi-RHS stencil (LDS-staged tile, global
+    neighbour reads), forced per precision and k, against the oracle: FP64 at
+    1e-12 (D, or Dhat for an even-odd operator), FP32 / BF16 storage against the
+    other form within their rounding; then the autotuner's table (both forms
+    timed for every k) names a form per k and a best k."""
+    import torch
+
+    dims, kappa = (4, 6, 4, 8), 0.122
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.3, 91)
+    op = gpu_lib.op_create(U, kappa, dims, eo=eo)
+    par = W.parity(dims)
+    for k in (2, 16):
+        psi = np.stack([synth.gaussian_spinor(V, 70 + c) for c in range(k)])
+        x = torch.from_numpy(psi).to("cuda:0")
+        if eo:
+            ref = np.stack([W.apply_Dhat(U, psi[c][par == 0], kappa, dims) for c in range(k)])
+        else:
+            ref = np.stack([W.apply_D(U, psi[c], kappa, dims) for c in range(k)])
+        scale = np.abs(ref).max()
+        for prec, bound in (("fp64", 1e-12), ("fp32", 2e-6), ("bf16", 8 * 2.0**-9)):
+            outs = []
+            for stage in (0, 1):
+                gpu_lib.op_batch_set_tile(op, prec, k, stage)
+                if eo:
+                    y = torch.full_like(x, 7.0)
+                    gpu_lib.op_apply_schur_block(op, y, x, k, prec=prec)
+                    got = y.cpu().numpy().reshape(k, V, 4, 3)
+                    assert np.abs(got[:, par == 1]).max() == 0.0
+                    got = got[:, par == 0]
+                elif prec == "bf16":
+                    xb = torch.view_as_real(x).to(torch.bfloat16).contiguous()
+                    yb = torch.empty_like(xb)
+                    gpu_lib.op_apply_block(op, yb, xb, k, prec="bf16")
+                    got = torch.view_as_complex(yb.cpu().to(torch.float64)).numpy().reshape(k, V, 4, 3)
+                else:
+                    xx = x if prec == "fp64" else x.to(torch.complex64)
+                    y = torch.empty_like(xx)
+                    gpu_lib.op_apply_block(op, y, xx, k, prec=prec)
+                    got = y.cpu().numpy().astype(np.complex128).reshape(k, V, 4, 3)
+                outs.append(got)
+                if prec == "fp64":
+                    err = np.abs(got - ref).max() / scale
+                    assert err <= 1e-12, (k, stage, err)
+            d = np.abs(outs[0] - outs[1]).max() / scale
+            print(f"eo={eo} k={k} {prec}: staged vs global reads {d:.2e}")
+            assert d <= bound, (k, prec, d)
+            gpu_lib.op_batch_set_tile(op, prec, k, -1)
+    with pytest.raises(gpu_lib.EbicgError):
+        gpu_lib.op_batch_set_tile(op, "fp32", 3, 1)
+    for prec in ("fp32", "bf16"):
+        t = gpu_lib.op_batch_tune(op, prec)
+        print(prec, t)
+        assert t["k"] in (1, 2, 4, 8, 16)
+        assert all(s in (0, 1) for s in t["stage"].values())
+        assert all(a > 0 and b > 0 for a, b in t["ms_per_rhs"].values())
+        best = t["ms_per_rhs"][t["k"]]
+        assert min(best) <= 1.0 / 0.97 * min(min(v) for v in t["ms_per_rhs"].values()) + 1e-12
