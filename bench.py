@@ -200,6 +200,86 @@ def large_lattice(eb, dims, kappa, nrhs, tol):
     return res
 
 
+def batching(eb, dims=(32, 32, 32, 64), kappa=0.123, nrhs=16, n1=4, nev=25, m=60, tol=1e-10):
+    """Batching on 32^3 x 64: the multi-RHS stencil (FP32 and BF16 storage,
+    k = 1, 4, 8, 16), the autotuner's choice of k and tile form, a deflation
+    space of n1 * nev = 100 pairs grown by eigBiCG, and mixed-precision
+    (complex64 inner, complex128 outer) batched deflated solves at k = 4, 8, 16
+    and the tuned k.  The deflation of a batch is a tall-skinny complex GEMM
+    pair on the matrix cores: C = U_l^+ R (K x N times N x k) and X += U_r C;
+    its algorithmic bytes are 2 K N + 3 k N complex128 entries and its flops
+    2 x 8 K N k."""
+    import torch
+
+    import synth
+
+    V = synth.volume(dims)
+    N = 12 * V
+    t0 = time.perf_counter()
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(3))
+    log(f"[bench] {dims}: links generated in {time.perf_counter() - t0:.1f} s")
+    op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=n1 * nev)
+    del U
+    res = {"lattice": list(dims), "kappa": kappa, "nrhs": nrhs}
+    res["stencil"] = multi_rhs_stencil(eb, op, V, precs=("fp32", "bf16"), ks=(1, 4, 8, 16))
+    res["autotune"] = {p: eb.op_batch_tune(op, p) for p in ("fp32", "bf16")}
+    log(f"[bench] {dims} autotune: {res['autotune']}")
+    grow = []
+    for i in range(n1):
+        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(3, 100 + i))).to("cuda:0")
+        x = torch.zeros_like(b)
+        st, _ = eb.eigbicg_solve(op, b, x, nev, m, tol)
+        assert st["true_rel_resid"] <= tol, st
+        grow.append({"iters": st["iters"], "restarts": st["window_restarts"], "seconds": round(st["seconds"], 3)})
+        log(f"[bench] {dims} eigBiCG {i}: {grow[-1]}")
+        del b, x
+    K = eb.defl_info(op)[0]
+    res["eigbicg"] = {"nev": nev, "m": m, "solves": grow, "K": K}
+    res["device_bytes_after_growth"] = eb.op_device_bytes(op)
+    eb.op_trim(op)  # the windows of the eigBiCG phase: about 100 GB at this size
+    res["device_bytes_trimmed"] = eb.op_device_bytes(op)
+    B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(3, i))) for i in range(nrhs)]).to("cuda:0")
+    solves = {}
+    eb.timing_classes(op, ["proj"])
+    for k in (4, 8, 16, 0):
+        X = torch.zeros_like(B)
+        eb.timing_enable(op, True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op, B, X, tol=tol, maxiter=20000, nrhs=nrhs, inner="fp32", inner_tol=1e-6,
+                                    batch=k)
+        dt = time.perf_counter() - t1
+        n_proj, ms_proj = eb.timing_read(op)["proj"]
+        eb.timing_enable(op, False)
+        assert st["true_rel_resid"] <= tol, (k, st)
+        kk = k if k else res["autotune"]["fp32"]["k"]
+        nb = -(-nrhs // kk)
+        gemm_bytes = nb * (2 * K * N + 3 * kk * N) * 16
+        gemm_flops = nb * 2 * 8 * K * N * kk
+        rec = {"solves_per_s": round(nrhs / dt, 3), "iters_per_rhs": round(st["iters"] / nrhs, 1),
+               "outer_steps": st["outer_steps"], "max_true_rel_resid": st["true_rel_resid"],
+               "deflation_gemm": {"launches": n_proj, "ms": round(ms_proj, 3),
+                                  "GBps": round(gemm_bytes / (ms_proj * 1e-3) / 1e9, 1) if ms_proj else None,
+                                  "TFLOPs_fp64": round(gemm_flops / (ms_proj * 1e-3) / 1e12, 2) if ms_proj else None}}
+        solves[f"mixed_fp32_k{k}" if k else f"mixed_fp32_tuned_k{kk}"] = rec
+        log(f"[bench] {dims} k={k}: {rec}")
+        del X
+    eb.timing_classes(op, None)
+    # FP64 deflated BiCGStab one right-hand side at a time, on 4 of the sources
+    X = torch.zeros_like(B[:4])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = eb.deflated_bicg_solve(op, B[:4].contiguous(), X, tol=tol, maxiter=20000, nrhs=4, batch=1)
+    dt = time.perf_counter() - t1
+    solves["fp64_one_at_a_time"] = {"solves_per_s": round(4 / dt, 3), "iters_per_rhs": round(st["iters"] / 4, 1),
+                                    "max_true_rel_resid": st["true_rel_resid"]}
+    res["solves"] = solves
+    eb.op_destroy(op)
+    del B, X
+    torch.cuda.empty_cache()
+    return res
+
+
 # ---------------------------------------------------------------------------
 # HBM traffic of the roofline kernel from rocprofv3 counters.
 #   1. rocprofv3 --pmc FETCH_SIZE -d D1 -o run -- python3 bench.py --pmc-pass
@@ -484,6 +564,8 @@ def main():
     ap.add_argument("--no-side", action="store_true",
                     help="skip the side records (multi-RHS table, gamma5 and even-odd forms, sweeps)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (continuous batching) section")
+    ap.add_argument("--no-batching", action="store_true", help="skip the 32^3 x 64 batching section")
+    ap.add_argument("--batching-only", action="store_true", help="run only the 32^3 x 64 batching section")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving section and print it")
     ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -509,6 +591,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serving_only:
         print(json.dumps({"serving": serving(eb)}), flush=True)
+        return
+    if args.batching_only:
+        print(json.dumps({"batching": batching(eb)}), flush=True)
         return
     W = WORKLOADS[args.workload]
     dims = W["dims"]
@@ -708,6 +793,8 @@ def main():
 
     if not args.no_large:
         extra["large_lattice"] = large_lattice(eb, (24, 24, 24, 64), 0.123, 16, W["tol"])
+    if not args.no_batching:
+        extra["batching"] = batching(eb)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -302,6 +302,10 @@ eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_bes
 /* Set the tile form for one precision and k (stage 1, 0, or -1 for the built-in rule);
  * results agree to rounding between the forms.  Host-only. */
 eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage);
+/* Release the operator's work buffers (eigBiCG windows, batch and scratch vectors; not the
+ * links, the deflation space or the reduction scratch) after waiting for `stream` and the
+ * device; later calls allocate what they need again.  Sessions keep their own buffers. */
+eb_status eb_op_trim(eb_op *op, void *stream);
 /* Device bytes the operator holds (links, deflation space, work buffers). */
 eb_status eb_op_device_bytes(eb_op *op, uint64_t *bytes);
 

@@ -2479,6 +2479,19 @@ eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage
   });
 }
 
+eb_status eb_op_trim(eb_op *op, void *stream) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    set_device(op);
+    HIPCHK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIPCHK(hipDeviceSynchronize());
+    for (auto &kv : op->bufs) kv.second.release();
+    op->bufs.clear();
+    op->hist.release();
+    op->hist_cap = 0;
+  });
+}
+
 eb_status eb_op_device_bytes(eb_op *op, uint64_t *bytes) {
   return guarded([&]() {
     if (!op || !bytes) fail(EB_ERR_INVALID, "null argument");

@@ -127,6 +127,7 @@ _SIGNATURES = [
     ("eb_session_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
     ("eb_op_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("eb_op_trim", ctypes.c_int, [_P, _P]),
     ("eb_op_batch_tune", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int32), _P, _P]),
     ("eb_op_batch_set_tile", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -384,6 +385,11 @@ def op_device_bytes(op):
     n = ctypes.c_uint64(0)
     _check(lib().eb_op_device_bytes(op.handle, ctypes.byref(n)))
     return n.value
+
+
+def op_trim(op, stream=None):
+    """Release the operator's work buffers (not its links or deflation space)."""
+    _check(lib().eb_op_trim(op.handle, _stream(stream)))
 
 
 def op_batch_tune(op, prec="fp32", stream=None):

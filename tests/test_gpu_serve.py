@@ -243,3 +243,25 @@ def test_session_graph_replay_matches_direct_launches(gpu_lib, cfg0, inner, eo):
     for i in range(5):
         assert np.array_equal(out[True][0][i], out[False][0][i]), i
         assert _resid(U, kappa, dims, B[i], out[True][0][i]) <= 1e-10
+
+
+def test_op_trim_keeps_the_space(gpu_lib, cfg0):
+    """eb_op_trim releases the work buffers of the eigBiCG phase, keeps the
+    links and the deflation space: later deflated solves still converge, with
+    the same iterations as before the trim."""
+    import torch
+
+    dims, kappa, U, D = cfg0
+    V = synth.volume(dims)
+    op = _space(gpu_lib, U, kappa, dims)
+    b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, 90))).to("cuda:0")
+    x = torch.zeros_like(b)
+    st0 = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10)
+    before = gpu_lib.op_device_bytes(op)
+    gpu_lib.op_trim(op)
+    after = gpu_lib.op_device_bytes(op)
+    assert after < before and gpu_lib.defl_info(op)[0] == 8
+    x.zero_()
+    st1 = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10)
+    assert st1["iters"] == st0["iters"] and st1["true_rel_resid"] <= 1e-10
+    assert _resid(U, kappa, dims, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
