@@ -264,7 +264,9 @@ typedef struct {
                        (on a created stream, not the null stream, and not while kernel timing
                        is enabled); 0: launched one by one */
 } eb_session_params;
-/* Create a session on `stream` (a hipStream_t; its device memory is allocated here). */
+/* Create a session on `stream` (a hipStream_t; its device memory is allocated here).  Runs
+ * the batch autotuner for the operator and `inner` once (eb_op_batch_tune), so the slots'
+ * stencils use the tuned tile form. */
 eb_status eb_session_create(eb_op *op, const eb_session_params *p, void *stream, eb_session **out);
 /* Wait for the work in flight and free the session (requests still running are dropped). */
 eb_status eb_session_destroy(eb_session *s);

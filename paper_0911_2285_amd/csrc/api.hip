@@ -2357,6 +2357,7 @@ eb_status eb_session_create(eb_op *op, const eb_session_params *P, void *stream,
     std::memcpy(ss->hstate.p, idle.data(), kMaxBatch * sizeof(KrylovState));
     HIPCHK(hipMemcpyAsync(ss->state.p, ss->hstate.p, kMaxBatch * sizeof(KrylovState), hipMemcpyHostToDevice, ss->s));
     session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::prepare(ss.get()); });  // inner-precision links
+    (void)choose_batch(op, ss->prec, ss->s);  // the batch autotuner's tile forms (once per operator and precision)
     HIPCHK(hipEventCreateWithFlags(&ss->ev, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(ss->s));
     *out = ss.release();
