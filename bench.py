@@ -465,6 +465,32 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
     return out
 
 
+def stencil_pass(dims=(32, 32, 32, 64), ks=(1, 16), reps=5):
+    """For counter runs of the multi-RHS stencil: FP32 storage, k = 1 and 16
+    columns, `reps` launches each after one warm-up (unit links: the stencil's
+    traffic does not depend on the link values), then the calibration copy."""
+    import torch
+
+    import synth
+    from paper_0911_2285_amd import ebicg as eb
+
+    V = synth.volume(dims)
+    op = eb.op_create(synth.unit_links(dims), 0.12, dims, bc_t=-1)
+    for k in ks:
+        eb.op_batch_set_tile(op, "fp32", k, 0 if k > 1 else 1)
+        x = torch.ones(k * 12 * V, dtype=torch.complex64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(reps + 1):
+            eb.op_apply_block(op, y, x, k, prec="fp32")
+        torch.cuda.synchronize()
+        del x, y
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] stencil pass done: V = {V}, k = {ks}, FP32 tile forms staged (k = 1) / global reads (k > 1)")
+
+
 def pmc_pass(workload):
     """One eigBiCG solve (its BiCG matvec launches are the roofline kernel), then a
     plain device copy of COPY_BYTES for the counter calibration."""
@@ -567,6 +593,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the 32^3 x 64 batching section")
     ap.add_argument("--batching-only", action="store_true", help="run only the 32^3 x 64 batching section")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving section and print it")
+    ap.add_argument("--stencil-pass", action="store_true", help="multi-RHS FP32 stencil launches for rocprofv3 --pmc")
     ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
@@ -576,6 +603,9 @@ def main():
         return
     if args.pmc_pass:
         pmc_pass(args.workload)
+        return
+    if args.stencil_pass:
+        stencil_pass()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU path is design-only",

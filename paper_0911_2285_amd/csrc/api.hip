@@ -150,7 +150,7 @@ struct eb_op {
   // tuner or set by the caller; the tuner's time per right-hand side (ms) of
   // each form
   int batch_stage[3][kMaxBatch + 1];
-  double batch_stage_ms[3][kMaxBatch + 1][2] = {};
+  double batch_stage_ms[3][kMaxBatch + 1][kTileForms] = {};
   eb_op() {
     for (auto &row : batch_stage)
       for (int &v : row) v = -1;
@@ -651,7 +651,8 @@ int tune_batch(eb_op *op, hipStream_t s) {
   const int pi = Inner<S>::index;
   for (int kc = 1; kc <= kMaxBatch; kc *= 2) {
     double t_kc = HUGE_VAL;
-    for (int stage = 0; stage < 2; ++stage) {  // both tile forms
+    for (int stage = 0; stage < kTileForms; ++stage) {  // every tile form this operator admits
+      if (!batch_tile_ok(op->g, op->eo, stage)) continue;
       apply(kc, stage);
       HIPCHK(hipEventRecord(e0, s));
       for (int rep = 0; rep < 3; ++rep) apply(kc, stage);
@@ -2462,10 +2463,8 @@ eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_bes
     const int pi = prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2);
     for (int i = 0, kc = 1; kc <= kMaxBatch; ++i, kc *= 2) {
       if (stage) stage[i] = op->batch_stage[pi][kc];
-      if (ms_per_rhs) {
-        ms_per_rhs[2 * i] = op->batch_stage_ms[pi][kc][0];
-        ms_per_rhs[2 * i + 1] = op->batch_stage_ms[pi][kc][1];
-      }
+      if (ms_per_rhs)
+        for (int f = 0; f < kTileForms; ++f) ms_per_rhs[kTileForms * i + f] = op->batch_stage_ms[pi][kc][f];
     }
   });
 }
@@ -2475,7 +2474,8 @@ eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage
     if (!op) fail(EB_ERR_INVALID, "null argument");
     if (prec != EB_FP64 && prec != EB_FP32 && prec != EB_BF16) fail(EB_ERR_INVALID, "unknown precision");
     if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
-    if (stage < -1 || stage > 1) fail(EB_ERR_INVALID, "stage must be -1, 0 or 1");
+    if (!batch_tile_ok(op->g, op->eo, stage))
+      fail(EB_ERR_INVALID, "tile form must be -1, 0 or 1, or 2 / 3 on a full-lattice operator whose extents the brick divides");
     op->batch_stage[prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2)][k] = stage;
   });
 }

@@ -49,15 +49,42 @@ template <typename S, int KC>
 constexpr bool kStage = KC == 1 || std::is_same<S, bf16c>::value;
 template <typename S, int KC, typename F>
 void dispatch_stage(int stage, F &&f) {
-  if (stage < 0 ? kStage<S, KC> : stage != 0)
+  if (stage < 0 ? kStage<S, KC> : stage == 1)
     f(std::true_type{});
   else
     f(std::false_type{});
 }
+// Site order of the global-read form.  Linear order (by = 0) puts a site's
+// t-neighbour Lx Ly Lz sites back in the traversal; with k columns of 12
+// entries per site that distance outgrows an XCD's L2 at large k (32^3 x 64,
+// FP32, k = 16: 48 MB), and the neighbour reads miss.  Bricks of
+// Lx x by x bz x bt sites, visited brick after brick (x fastest inside),
+// bring it down to Lx by bz sites.
+struct Brick {
+  int by, bz, bt;
+};
+inline Brick brick_of(int stage) {
+  return stage == 2 ? Brick{8, 4, 4} : (stage == 3 ? Brick{4, 4, 4} : Brick{0, 0, 0});
+}
+__device__ __forceinline__ int brick_site(int q, const Geom &g, Brick b) {
+  if (b.by == 0) return q;
+  const int bsize = g.lx * b.by * b.bz * b.bt;
+  int k = q / bsize, r = q - k * bsize;
+  const int nby = g.ly / b.by, nbz = g.lz / b.bz;
+  const int iy = k % nby;
+  k /= nby;
+  const int iz = k % nbz, it = k / nbz;
+  const int x = r % g.lx;
+  r /= g.lx;
+  const int yy = r % b.by;
+  r /= b.by;
+  const int zz = r % b.bz, tt = r / b.bz;
+  return x + g.lx * ((iy * b.by + yy) + g.ly * ((iz * b.bz + zz) + g.lz * (it * b.bt + tt)));
+}
 
 template <typename S, int KC, int SF, bool STG>
 __global__ void __launch_bounds__(kBlock)
-    k_bdslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa) {
+    k_bdslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa, Brick bk) {
   using R = typename Store<S>::R;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const R k = R(kappa);
@@ -81,7 +108,7 @@ __global__ void __launch_bounds__(kBlock)
   } else {
     const size_t n = size_t(g.V) * KC;
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
-      const int s = int(u / KC), col = int(u % KC);
+      const int s = brick_site(int(u / KC), g, bk), col = int(u % KC);
       cx<R> acc[12];
       hopping<SF, S, KC>(acc, in + col, U, g, s);
 #pragma unroll
@@ -138,7 +165,7 @@ __global__ void __launch_bounds__(kBlock)
 template <typename S, int KC, bool STG>
 __global__ void __launch_bounds__(kBlock)
     k_bstab_v(S *__restrict__ vout, const S *__restrict__ p, const S *__restrict__ rhat, const S *__restrict__ U,
-              Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part) {
+              Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part, Brick bk) {
   using R = typename Store<S>::R;
   const int col = threadIdx.x % KC;
   const bool act = col_active(K, col, j);
@@ -173,7 +200,7 @@ __global__ void __launch_bounds__(kBlock)
   } else if (act) {
     const size_t n = size_t(g.V) * KC;
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
-      const int s = int(u / KC);
+      const int s = brick_site(int(u / KC), g, bk);
       cx<R> acc[12];
       hopping<-1, S, KC>(acc, p + col, U, g, s);
       epilogue(s, acc, [&](int, size_t i) { return Store<S>::ld(p, i); });
@@ -221,7 +248,7 @@ __global__ void __launch_bounds__(kBlock)
 template <typename S, int KC, bool STG>
 __global__ void __launch_bounds__(kBlock)
     k_bstab_t(S *__restrict__ tout, const S *__restrict__ sv, const S *__restrict__ U, Geom g, double kappa, int j,
-              const KrylovState *K, double *__restrict__ part) {
+              const KrylovState *K, double *__restrict__ part, Brick bk) {
   using R = typename Store<S>::R;
   const int col = threadIdx.x % KC;
   const bool act = col_active(K, col, j);
@@ -257,7 +284,7 @@ __global__ void __launch_bounds__(kBlock)
   } else if (act) {
     const size_t n = size_t(g.V) * KC;
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
-      const int s = int(u / KC);
+      const int s = brick_site(int(u / KC), g, bk);
       cx<R> acc[12];
       hopping<-1, S, KC>(acc, sv + col, U, g, s);
       epilogue(s, acc, [&](int, size_t i) { return Store<S>::ld(sv, i); });
@@ -484,6 +511,12 @@ __global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
 }  // namespace
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
+bool batch_tile_ok(const Geom &g, bool eo, int stage) {
+  if (stage < -1 || stage >= kTileForms) return false;
+  if (stage < 2) return true;
+  const Brick b = brick_of(stage);  // bricked forms: full-lattice stencil, extents divisible by the brick
+  return !eo && g.ly % b.by == 0 && g.lz % b.bz == 0 && g.lt % b.bt == 0;
+}
 
 template <typename S>
 void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,
@@ -494,9 +527,9 @@ void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa
       constexpr bool STG = decltype(sg)::value;
       const dim3 grid(nblocks_for(size_t(g.V) * KC));
       if (dagger)
-        EB_LAUNCH((k_bdslash<S, KC, +1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+        EB_LAUNCH((k_bdslash<S, KC, +1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, brick_of(stage));
       else
-        EB_LAUNCH((k_bdslash<S, KC, -1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa);
+        EB_LAUNCH((k_bdslash<S, KC, -1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, brick_of(stage));
     });
   });
 }
@@ -519,7 +552,7 @@ void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, 
     constexpr int KC = decltype(kt)::value;
     dispatch_stage<S, KC>(stage, [&](auto sg) {
       EB_LAUNCH((k_bstab_v<S, KC, decltype(sg)::value>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st,
-                v, p, rhat, U, g, kappa, j, K, region(rs, RG_V));
+                v, p, rhat, U, g, kappa, j, K, region(rs, RG_V), brick_of(stage));
     });
   });
 }
@@ -543,7 +576,7 @@ void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, 
     constexpr int KC = decltype(kt)::value;
     dispatch_stage<S, KC>(stage, [&](auto sg) {
       EB_LAUNCH((k_bstab_t<S, KC, decltype(sg)::value>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st,
-                t, sv, U, g, kappa, j, K, region(rs, RG_T));
+                t, sv, U, g, kappa, j, K, region(rs, RG_T), brick_of(stage));
     });
   });
 }

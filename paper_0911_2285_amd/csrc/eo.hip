@@ -283,7 +283,7 @@ void bhop(S *out, const S *in, const S *Ueo, const Geom &g, int P, double a, con
     constexpr int KC = decltype(kt)::value;
     constexpr int NV = EoNV<E>::v;
     const int grid = batch_stencil_grid(g.V / 2, KC, NV > 0 ? NV : 1);
-    if (stage < 0 ? kStageEo<S, KC> : stage != 0)
+    if (stage < 0 ? kStageEo<S, KC> : stage == 1)
       EB_LAUNCH((k_bhop_eo<S, KC, SF, E, true>), dim3(grid), dim3(kBlock), 0, st, out, in, links_of(Ueo, g, P),
                 links_of(Ueo, g, 1 - P), g, P, a, id, dv, j, K, part);
     else

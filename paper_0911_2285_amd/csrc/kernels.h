@@ -192,7 +192,8 @@ void launch_schur_eo_s(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g,
 // column; the BiCGStab forms as launch_bstab_v/t, with records for the batched
 // BiCGStab passes called with a geometry of V/2 sites.
 // stage: tile form of the batched hops (1: the input tile staged in LDS, 0:
-// neighbours read from global memory, < 0: the built-in rule).
+// neighbours read from global memory, < 0: the built-in rule; the bricked
+// forms are for the full-lattice stencil only).
 template <typename S>
 void launch_bschur_eo(S *out, const S *in, S *tmp, const S *Ueo, const Geom &g, double kappa, bool dagger, int kc,
                       hipStream_t st, int stage = -1);
@@ -261,8 +262,14 @@ void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K
 // Per-column solver state K[col], history entries at j kc + col.
 constexpr int kMaxBatch = 16;
 bool batch_size_ok(int kc);
-// stage: tile form of the batched stencils (1: each block's tile staged in
-// LDS, 0: neighbours read from global memory, < 0: the built-in rule)
+// Tile forms of the multi-RHS stencil (the `stage` argument of the batched
+// launchers): 0 global neighbour reads in site order, 1 each block's tile
+// staged in LDS, 2 and 3 global reads with the sites visited in bricks of
+// Lx x 8 x 4 x 4 and Lx x 4 x 4 x 4 (full-lattice operator, extents divisible
+// by the brick); < 0 the built-in rule (LDS staging for k = 1 and for BF16).
+constexpr int kTileForms = 4;
+bool batch_tile_ok(const Geom &g, bool eo, int stage);
+// stage: tile form of the batched stencils (kTileForms above)
 template <typename S>
 void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,
                     int stage = -1);

@@ -394,19 +394,21 @@ def op_trim(op, stream=None):
 
 def op_batch_tune(op, prec="fp32", stream=None):
     """The batch autotuner's choice for one precision: {"k": best k, "stage": {k: tile form},
-    "ms_per_rhs": {k: [unstaged, LDS-staged]}} (runs the tuner once per operator and precision)."""
+    "ms_per_rhs": {k: [global reads, LDS-staged, bricks 8x4x4, bricks 4x4x4]}} (0 for a form the
+    operator does not admit; runs the tuner once per operator and precision)."""
     kb = ctypes.c_int32(0)
     stage = np.zeros(5, np.int32)
-    ms = np.zeros(10, np.float64)
+    ms = np.zeros(20, np.float64)
     _check(lib().eb_op_batch_tune(op.handle, PREC[prec], _stream(stream), ctypes.byref(kb), stage.ctypes.data,
                                   ms.ctypes.data))
     ks = [1, 2, 4, 8, 16]
     return {"k": kb.value, "stage": {k: int(stage[i]) for i, k in enumerate(ks)},
-            "ms_per_rhs": {k: [float(ms[2 * i]), float(ms[2 * i + 1])] for i, k in enumerate(ks)}}
+            "ms_per_rhs": {k: [float(v) for v in ms[4 * i: 4 * i + 4]] for i, k in enumerate(ks)}}
 
 
 def op_batch_set_tile(op, prec, k, stage):
-    """Force the tile form of the batched stencil for (prec, k): 1 LDS-staged, 0 global reads, -1 built-in rule."""
+    """Force the tile form of the batched stencil for (prec, k): 0 global reads, 1 LDS-staged,
+    2 / 3 global reads in bricks (full-lattice operators), -1 built-in rule."""
     _check(lib().eb_op_batch_set_tile(op.handle, PREC[prec], int(k), int(stage)))
 
 

@@ -254,18 +254,21 @@ def test_dslash_block_parity(gpu_lib, k):
 
 @pytest.mark.parametrize("eo", [False, True])
 def test_block_tile_forms_and_tuner(gpu_lib, eo):
-    """Both tile forms of the multi-RHS stencil (LDS-staged tile, global
-    neighbour reads), forced per precision and k, against the oracle: FP64 at
-    1e-12 (D, or Dhat for an even-odd operator), FP32 / BF16 storage against the
-    other form within their rounding; then the autotuner's table (both forms
-    timed for every k) names a form per k and a best k."""
+    """Every tile form of the multi-RHS stencil (global reads in site order,
+    LDS-staged tile, global reads in Lx x 8 x 4 x 4 and Lx x 4 x 4 x 4 bricks;
+    the even-odd hop has the first two), forced per precision and k, against
+    the oracle: FP64 at 1e-12 (D, or Dhat for an even-odd operator), FP32 / BF16
+    storage against the first form within their rounding; forms the operator
+    does not admit are rejected; then the autotuner's table names a form per k
+    and a best k."""
     import torch
 
-    dims, kappa = (4, 6, 4, 8), 0.122
+    dims, kappa = (4, 8, 4, 8), 0.122
     V = synth.volume(dims)
     U = synth.random_su3_links(dims, 0.3, 91)
     op = gpu_lib.op_create(U, kappa, dims, eo=eo)
     par = W.parity(dims)
+    forms = (0, 1) if eo else (0, 1, 2, 3)
     for k in (2, 16):
         psi = np.stack([synth.gaussian_spinor(V, 70 + c) for c in range(k)])
         x = torch.from_numpy(psi).to("cuda:0")
@@ -276,7 +279,7 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
         scale = np.abs(ref).max()
         for prec, bound in (("fp64", 1e-12), ("fp32", 2e-6), ("bf16", 8 * 2.0**-9)):
             outs = []
-            for stage in (0, 1):
+            for stage in forms:
                 gpu_lib.op_batch_set_tile(op, prec, k, stage)
                 if eo:
                     y = torch.full_like(x, 7.0)
@@ -298,17 +301,22 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
                 if prec == "fp64":
                     err = np.abs(got - ref).max() / scale
                     assert err <= 1e-12, (k, stage, err)
-            d = np.abs(outs[0] - outs[1]).max() / scale
-            print(f"eo={eo} k={k} {prec}: staged vs global reads {d:.2e}")
+            d = max(np.abs(o - outs[0]).max() / scale for o in outs[1:])
+            print(f"eo={eo} k={k} {prec}: largest difference between tile forms {d:.2e}")
             assert d <= bound, (k, prec, d)
             gpu_lib.op_batch_set_tile(op, prec, k, -1)
+    for bad in ((3, 1), (4, 2) if eo else (4, 4)):
+        with pytest.raises(gpu_lib.EbicgError):
+            gpu_lib.op_batch_set_tile(op, "fp32", *bad)
+    odd = gpu_lib.op_create(synth.random_su3_links((4, 4, 4, 8), 0.3, 92), kappa, (4, 4, 4, 8))
     with pytest.raises(gpu_lib.EbicgError):
-        gpu_lib.op_batch_set_tile(op, "fp32", 3, 1)
+        gpu_lib.op_batch_set_tile(odd, "fp32", 4, 2)  # the 8-wide brick does not divide Ly = 4
+    gpu_lib.op_batch_set_tile(odd, "fp32", 4, 3)
     for prec in ("fp32", "bf16"):
         t = gpu_lib.op_batch_tune(op, prec)
         print(prec, t)
         assert t["k"] in (1, 2, 4, 8, 16)
-        assert all(s in (0, 1) for s in t["stage"].values())
-        assert all(a > 0 and b > 0 for a, b in t["ms_per_rhs"].values())
-        best = t["ms_per_rhs"][t["k"]]
-        assert min(best) <= 1.0 / 0.97 * min(min(v) for v in t["ms_per_rhs"].values()) + 1e-12
+        assert all(s in forms for s in t["stage"].values())
+        for kk, ms in t["ms_per_rhs"].items():
+            assert all(ms[f] > 0 for f in forms) and all(ms[f] == 0 for f in range(4) if f not in forms)
+            assert ms[t["stage"][kk]] == min(ms[f] for f in forms)
