@@ -54,32 +54,41 @@ void dispatch_stage(int stage, F &&f) {
   else
     f(std::false_type{});
 }
-// Site order of the global-read form.  Linear order (by = 0) puts a site's
+// Site order of the global-read form.  Linear order puts a site's
 // t-neighbour Lx Ly Lz sites back in the traversal; with k columns of 12
 // entries per site that distance outgrows an XCD's L2 at large k (32^3 x 64,
-// FP32, k = 16: 48 MB), and the neighbour reads miss.  Bricks of
-// Lx x by x bz x bt sites, visited brick after brick (x fastest inside),
-// bring it down to Lx by bz sites.
+// FP32, k = 16: 48 MB), and the neighbour reads miss.  Visiting the lattice
+// brick after brick (bx x by x bz x bt sites, x fastest inside a brick and
+// across bricks) keeps most neighbours of the sites in flight inside the
+// brick.  At k >= 4 a site's k entries of one component fill a whole cache
+// line, so bricks narrower than Lx cost no coalescing.
 struct Brick {
-  int by, bz, bt;
+  int bx, by, bz, bt;  // bx = 0: linear order
 };
 inline Brick brick_of(int stage) {
-  return stage == 2 ? Brick{8, 4, 4} : (stage == 3 ? Brick{4, 4, 4} : Brick{0, 0, 0});
+  switch (stage) {
+    case 2: return Brick{8, 8, 4, 4};
+    case 3: return Brick{8, 8, 8, 8};
+    case 4: return Brick{4, 4, 4, 4};
+    default: return Brick{0, 0, 0, 0};
+  }
 }
 __device__ __forceinline__ int brick_site(int q, const Geom &g, Brick b) {
-  if (b.by == 0) return q;
-  const int bsize = g.lx * b.by * b.bz * b.bt;
+  if (b.bx == 0) return q;
+  const int bsize = b.bx * b.by * b.bz * b.bt;
   int k = q / bsize, r = q - k * bsize;
-  const int nby = g.ly / b.by, nbz = g.lz / b.bz;
+  const int nbx = g.lx / b.bx, nby = g.ly / b.by, nbz = g.lz / b.bz;
+  const int ix = k % nbx;
+  k /= nbx;
   const int iy = k % nby;
   k /= nby;
   const int iz = k % nbz, it = k / nbz;
-  const int x = r % g.lx;
-  r /= g.lx;
+  const int xx = r % b.bx;
+  r /= b.bx;
   const int yy = r % b.by;
   r /= b.by;
   const int zz = r % b.bz, tt = r / b.bz;
-  return x + g.lx * ((iy * b.by + yy) + g.ly * ((iz * b.bz + zz) + g.lz * (it * b.bt + tt)));
+  return (ix * b.bx + xx) + g.lx * ((iy * b.by + yy) + g.ly * ((iz * b.bz + zz) + g.lz * (it * b.bt + tt)));
 }
 
 template <typename S, int KC, int SF, bool STG>
@@ -515,7 +524,7 @@ bool batch_tile_ok(const Geom &g, bool eo, int stage) {
   if (stage < -1 || stage >= kTileForms) return false;
   if (stage < 2) return true;
   const Brick b = brick_of(stage);  // bricked forms: full-lattice stencil, extents divisible by the brick
-  return !eo && g.ly % b.by == 0 && g.lz % b.bz == 0 && g.lt % b.bt == 0;
+  return !eo && g.lx % b.bx == 0 && g.ly % b.by == 0 && g.lz % b.bz == 0 && g.lt % b.bt == 0;
 }
 
 template <typename S>

@@ -264,10 +264,11 @@ constexpr int kMaxBatch = 16;
 bool batch_size_ok(int kc);
 // Tile forms of the multi-RHS stencil (the `stage` argument of the batched
 // launchers): 0 global neighbour reads in site order, 1 each block's tile
-// staged in LDS, 2 and 3 global reads with the sites visited in bricks of
-// Lx x 8 x 4 x 4 and Lx x 4 x 4 x 4 (full-lattice operator, extents divisible
-// by the brick); < 0 the built-in rule (LDS staging for k = 1 and for BF16).
-constexpr int kTileForms = 4;
+// staged in LDS, 2, 3 and 4 global reads with the sites visited in bricks of
+// 8 x 8 x 4 x 4, 8 x 8 x 8 x 8 and 4 x 4 x 4 x 4 sites (full-lattice operator,
+// extents divisible by the brick); < 0 the built-in rule (LDS staging for
+// k = 1 and for BF16).
+constexpr int kTileForms = 5;
 bool batch_tile_ok(const Geom &g, bool eo, int stage);
 // stage: tile form of the batched stencils (kTileForms above)
 template <typename S>

@@ -255,7 +255,7 @@ def test_dslash_block_parity(gpu_lib, k):
 @pytest.mark.parametrize("eo", [False, True])
 def test_block_tile_forms_and_tuner(gpu_lib, eo):
     """Every tile form of the multi-RHS stencil (global reads in site order,
-    LDS-staged tile, global reads in Lx x 8 x 4 x 4 and Lx x 4 x 4 x 4 bricks;
+    LDS-staged tile, global reads in 8x8x4x4, 8x8x8x8 and 4x4x4x4 bricks;
     the even-odd hop has the first two), forced per precision and k, against
     the oracle: FP64 at 1e-12 (D, or Dhat for an even-odd operator), FP32 / BF16
     storage against the first form within their rounding; forms the operator
@@ -263,12 +263,12 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
     and a best k."""
     import torch
 
-    dims, kappa = (4, 8, 4, 8), 0.122
+    dims, kappa = (8, 8, 8, 8), 0.122
     V = synth.volume(dims)
     U = synth.random_su3_links(dims, 0.3, 91)
     op = gpu_lib.op_create(U, kappa, dims, eo=eo)
     par = W.parity(dims)
-    forms = (0, 1) if eo else (0, 1, 2, 3)
+    forms = (0, 1) if eo else (0, 1, 2, 3, 4)
     for k in (2, 16):
         psi = np.stack([synth.gaussian_spinor(V, 70 + c) for c in range(k)])
         x = torch.from_numpy(psi).to("cuda:0")
@@ -305,18 +305,18 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
             print(f"eo={eo} k={k} {prec}: largest difference between tile forms {d:.2e}")
             assert d <= bound, (k, prec, d)
             gpu_lib.op_batch_set_tile(op, prec, k, -1)
-    for bad in ((3, 1), (4, 2) if eo else (4, 4)):
+    for bad in ((3, 1), (4, 2) if eo else (4, 5)):
         with pytest.raises(gpu_lib.EbicgError):
             gpu_lib.op_batch_set_tile(op, "fp32", *bad)
     odd = gpu_lib.op_create(synth.random_su3_links((4, 4, 4, 8), 0.3, 92), kappa, (4, 4, 4, 8))
     with pytest.raises(gpu_lib.EbicgError):
-        gpu_lib.op_batch_set_tile(odd, "fp32", 4, 2)  # the 8-wide brick does not divide Ly = 4
-    gpu_lib.op_batch_set_tile(odd, "fp32", 4, 3)
+        gpu_lib.op_batch_set_tile(odd, "fp32", 4, 2)  # the 8-wide brick does not divide Lx = 4
+    gpu_lib.op_batch_set_tile(odd, "fp32", 4, 4)
     for prec in ("fp32", "bf16"):
         t = gpu_lib.op_batch_tune(op, prec)
         print(prec, t)
         assert t["k"] in (1, 2, 4, 8, 16)
         assert all(s in forms for s in t["stage"].values())
         for kk, ms in t["ms_per_rhs"].items():
-            assert all(ms[f] > 0 for f in forms) and all(ms[f] == 0 for f in range(4) if f not in forms)
+            assert all(ms[f] > 0 for f in forms) and all(ms[f] == 0 for f in range(5) if f not in forms)
             assert ms[t["stage"][kk]] == min(ms[f] for f in forms)
