@@ -77,26 +77,30 @@ class Server:
     requests' b and x); a request waits while it would exceed it."""
 
     def __init__(self, specs, inner="fp32", tol=1e-10, maxiter=20000, chunk=8, hbm_budget=None,
-                 keep_solutions=False, graph=True):
-        import torch
-
+                 keep_solutions=False, graph=True, backend=None):
+        self.eb = backend if backend is not None else ebicg   # the library binding (tests pass a stand-in)
         self.specs = list(specs)
         self.tol = float(tol)
         self.maxiter = int(maxiter)
         self.budget = hbm_budget
         self.keep = keep_solutions
-        self.streams = [torch.cuda.Stream() for _ in self.specs]
+        self.streams = [self._new_stream() for _ in self.specs]
         self.sessions = []
         for sp, st in zip(self.specs, self.streams):
-            self.sessions.append(ebicg.Session(sp.op, slots=sp.slots, inner=inner, tol=tol, maxiter=maxiter,
-                                               chunk=chunk, graph=graph, stream=st))
+            self.sessions.append(self.eb.Session(sp.op, slots=sp.slots, inner=inner, tol=tol, maxiter=maxiter,
+                                                 chunk=chunk, graph=graph, stream=st))
         self.grow_left = [sp.grow for sp in self.specs]
         self.max_resident = 0
         self.deferred = 0   # admissions postponed by the memory budget
 
     def resident_bytes(self):
-        return (sum(ebicg.op_device_bytes(sp.op) for sp in self.specs)
+        return (sum(self.eb.op_device_bytes(sp.op) for sp in self.specs)
                 + sum(s.info()["device_bytes"] for s in self.sessions))
+
+    def _new_stream(self):
+        import torch
+
+        return torch.cuda.Stream()
 
     @staticmethod
     def _request_bytes(op):
@@ -111,7 +115,7 @@ class Server:
         return b, x
 
     def _defl_K(self, i):
-        return ebicg.defl_info(self.specs[i].op)[0]
+        return self.eb.defl_info(self.specs[i].op)[0]
 
     def run(self, requests):
         """Serve `requests` (arrival times relative to the call); returns the Results in finish order."""
@@ -151,11 +155,11 @@ class Server:
                         start, K = clock(), self._defl_K(i)
                         b, x = self._upload(i, req)
                         try:
-                            st, _ = ebicg.eigbicg_solve(sp.op, b, x, sp.nev, sp.m, self.tol, maxiter=self.maxiter,
-                                                        stream=self.streams[i])
+                            st, _ = self.eb.eigbicg_solve(sp.op, b, x, sp.nev, sp.m, self.tol, maxiter=self.maxiter,
+                                                          stream=self.streams[i])
                             status = "EB_OK"
-                        except ebicg.EbicgError as e:
-                            st, status = e.stats or {}, ebicg.STATUS.get(e.status, str(e.status))
+                        except self.eb.EbicgError as e:
+                            st, status = e.stats or {}, self.eb.STATUS.get(e.status, str(e.status))
                         self.grow_left[i] -= 1
                         results.append(Result(req.rid, i, "eigbicg", req.arrival, start, clock(), status, st, K,
                                               x if self.keep else None))
