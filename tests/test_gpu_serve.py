@@ -265,3 +265,44 @@ def test_op_trim_keeps_the_space(gpu_lib, cfg0):
     st1 = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10)
     assert st1["iters"] == st0["iters"] and st1["true_rel_resid"] <= 1e-10
     assert _resid(U, kappa, dims, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
+
+
+def test_session_full_size_even_odd(gpu_lib):
+    """16^3 x 32 even-odd operator (the benchmark lattice), a space from one
+    eigBiCG solve, four requests on a 2-slot session with FP32 inner solves
+    (two wait for slots): every solution checked with the oracle's D over the
+    whole lattice (||b - D x|| <= 1e-10 ||b||), and one request equal bit for
+    bit to the same request solved alone."""
+    import torch
+
+    dims, kappa = (16, 16, 16, 32), 0.122
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(1))
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8, eo=True)
+    b0 = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(5, 0))).to("cuda:0")
+    gpu_lib.eigbicg_solve(op, b0, torch.zeros_like(b0), nev=8, m=24, tol=1e-10)
+    B = [synth.z2_source(V, synth.rhs_seed(5, 1 + i)).ravel() for i in range(4)]
+    b = [torch.from_numpy(v).to("cuda:0") for v in B]
+    x = [torch.zeros_like(v) for v in b]
+    sess = gpu_lib.Session(op, slots=2, inner="fp32", tol=1e-10, chunk=8, stream=torch.cuda.Stream())
+    nxt, done = 0, {}
+    for _ in range(100000):
+        for tag, status, st in sess.poll():
+            done[tag] = (status, st)
+        while nxt < 4 and sess.admit(b[nxt], x[nxt], nxt) is not None:
+            nxt += 1
+        if len(done) == 4:
+            break
+        sess.step()
+    torch.cuda.synchronize()
+    for i in range(4):
+        assert done[i][0] == "EB_OK", done[i]
+        tr = _resid(U, kappa, dims, B[i], x[i].cpu().numpy())
+        print(f"request {i}: iters {done[i][1]['iters']} outer {done[i][1]['outer_steps']} residual {tr:.2e}")
+        assert tr <= 1e-10 and done[i][1]["true_rel_resid"] <= 1e-10
+    xa = torch.zeros_like(b[3])
+    sess.admit(b[3], xa, 9)
+    _drain(sess, 1)
+    sess.close()
+    torch.cuda.synchronize()
+    assert torch.equal(xa, x[3])
