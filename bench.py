@@ -491,6 +491,29 @@ def stencil_pass(dims=(32, 32, 32, 64), ks=(1, 16), reps=5):
     log(f"[bench] stencil pass done: V = {V}, k = {ks}, FP32 tile forms staged (k = 1) / global reads (k > 1)")
 
 
+def proj_pass(dims=(16, 16, 16, 32), kappa=0.122, n1=8, nev=10, m=40, nrhs=16):
+    """For counter runs of the deflation projections on the matrix cores: the
+    headline lattice's space of n1 * nev pairs grown by eigBiCG (the absorb
+    steps' Gram blocks), then nrhs right-hand sides deflated as one batch
+    (C = U_l^+ R with K = 80, k = 16) and solved with FP32 inner BiCGStab."""
+    import torch
+
+    import synth
+    from paper_0911_2285_amd import ebicg as eb
+
+    V = synth.volume(dims)
+    op = eb.op_create(synth.random_su3_links(dims, 0.3, synth.gauge_seed(1)), kappa, dims, bc_t=-1,
+                      defl_capacity=n1 * nev)
+    for i in range(n1):
+        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, i))).to("cuda:0")
+        eb.eigbicg_solve(op, b, torch.zeros_like(b), nev, m, 1e-10)
+    B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, n1 + i))) for i in range(nrhs)]).to("cuda:0")
+    X = torch.zeros_like(B)
+    st = eb.deflated_bicg_solve(op, B, X, tol=1e-10, nrhs=nrhs, batch=nrhs, inner="fp32", inner_tol=1e-6)
+    torch.cuda.synchronize()
+    log(f"[bench] proj pass done: K = {eb.defl_info(op)[0]}, batch of {nrhs}, residual {st['true_rel_resid']:.2e}")
+
+
 def pmc_pass(workload):
     """One eigBiCG solve (its BiCG matvec launches are the roofline kernel), then a
     plain device copy of COPY_BYTES for the counter calibration."""
@@ -593,6 +616,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the 32^3 x 64 batching section")
     ap.add_argument("--batching-only", action="store_true", help="run only the 32^3 x 64 batching section")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving section and print it")
+    ap.add_argument("--proj-pass", action="store_true", help="deflation projections on the matrix cores, for --pmc")
     ap.add_argument("--stencil-pass", action="store_true", help="multi-RHS FP32 stencil launches for rocprofv3 --pmc")
     ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -606,6 +630,9 @@ def main():
         return
     if args.stencil_pass:
         stencil_pass()
+        return
+    if args.proj_pass:
+        proj_pass()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU path is design-only",
