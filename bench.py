@@ -770,6 +770,8 @@ def main():
         dt_b = time.perf_counter() - t1
         assert st["true_rel_resid"] <= W["tol"], (name, st)
         extra["deflated_solves_per_s"][name] = round(nd / dt_b, 3)
+    # the batch autotuner's choice on this operator (k and tile form per precision)
+    extra["autotune"] = {p: eb.op_batch_tune(op, p) for p in ("fp32", "bf16")}
     # the side records (skipped with --no-side, e.g. to profile the headline workload alone)
     if not args.no_side:
         extra["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
