@@ -346,3 +346,32 @@ def test_block_tile_forms_full_size_sampled(gpu_lib):
         err = max(np.abs(got[c][sites] - refs[c]).max() for c in range(k)) / scale
         print(f"tile form {stage}: {err:.2e}")
         assert err <= 1e-12, (stage, err)
+
+
+def test_dslash_block_32x64_sampled(gpu_lib):
+    """32^3 x 64 (the batching lattice), FP32 storage, k = 16 columns: the
+    form the autotuner picks there (8x8x8x8 bricks) and form 0, at sampled
+    sites of every column against the per-site oracle on the rounded input
+    (FP32 rounding bound 5e-7 of the largest entry)."""
+    import torch
+
+    dims, kappa = (32, 32, 32, 64), 0.123
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(3))
+    op = gpu_lib.op_create(U, kappa, dims)
+    k = 16
+    psi = np.stack([synth.z2_source(V, synth.rhs_seed(3, 300 + c)) for c in range(k)]).astype(np.complex64)
+    x = torch.from_numpy(psi).to("cuda:0")
+    sites = _sample_sites(dims, n=10, seed=3)
+    U32 = U.astype(np.complex64).astype(np.complex128)
+    refs = [W.apply_D_sites(U32, psi[c].astype(np.complex128), kappa, dims, sites) for c in range(k)]
+    scale = max(np.abs(r).max() for r in refs)
+    for stage in (3, 0):
+        gpu_lib.op_batch_set_tile(op, "fp32", k, stage)
+        y = torch.empty_like(x)
+        gpu_lib.op_apply_block(op, y, x, k, prec="fp32")
+        got = y.cpu().numpy().reshape(k, V, 4, 3)
+        err = max(np.abs(got[c][sites] - refs[c]).max() for c in range(k)) / scale
+        print(f"32^3 x 64, tile form {stage}: {err:.2e}")
+        assert err <= 5e-7, (stage, err)
+    gpu_lib.op_destroy(op)
