@@ -465,10 +465,11 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
     return out
 
 
-def stencil_pass(dims=(32, 32, 32, 64), ks=(1, 16), reps=5):
-    """For counter runs of the multi-RHS stencil: FP32 storage, k = 1 and 16
-    columns, `reps` launches each after one warm-up (unit links: the stencil's
-    traffic does not depend on the link values), then the calibration copy."""
+def stencil_pass(dims=(32, 32, 32, 64), ks=(1, 16), reps=5, form=0):
+    """For counter runs of the multi-RHS stencil: FP32 storage, k = 1 (LDS-staged
+    form) and 16 columns (tile form `form`), `reps` launches each after one
+    warm-up (unit links: the stencil's traffic does not depend on the link
+    values), then the calibration copy."""
     import torch
 
     import synth
@@ -477,7 +478,7 @@ def stencil_pass(dims=(32, 32, 32, 64), ks=(1, 16), reps=5):
     V = synth.volume(dims)
     op = eb.op_create(synth.unit_links(dims), 0.12, dims, bc_t=-1)
     for k in ks:
-        eb.op_batch_set_tile(op, "fp32", k, 0 if k > 1 else 1)
+        eb.op_batch_set_tile(op, "fp32", k, form if k > 1 else 1)
         x = torch.ones(k * 12 * V, dtype=torch.complex64, device="cuda:0")
         y = torch.empty_like(x)
         for _ in range(reps + 1):
@@ -488,7 +489,7 @@ def stencil_pass(dims=(32, 32, 32, 64), ks=(1, 16), reps=5):
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    log(f"[bench] stencil pass done: V = {V}, k = {ks}, FP32 tile forms staged (k = 1) / global reads (k > 1)")
+    log(f"[bench] stencil pass done: V = {V}, k = {ks}, FP32, tile form 1 (k = 1) / {form} (k > 1)")
 
 
 def proj_pass(dims=(16, 16, 16, 32), kappa=0.122, n1=8, nev=10, m=40, nrhs=16):
@@ -618,6 +619,7 @@ def main():
     ap.add_argument("--serving-only", action="store_true", help="run only the serving section and print it")
     ap.add_argument("--proj-pass", action="store_true", help="deflation projections on the matrix cores, for --pmc")
     ap.add_argument("--stencil-pass", action="store_true", help="multi-RHS FP32 stencil launches for rocprofv3 --pmc")
+    ap.add_argument("--stencil-form", type=int, default=0, help="tile form of the k > 1 launches of --stencil-pass")
     ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
@@ -629,7 +631,7 @@ def main():
         pmc_pass(args.workload)
         return
     if args.stencil_pass:
-        stencil_pass()
+        stencil_pass(form=args.stencil_form)
         return
     if args.proj_pass:
         proj_pass()
