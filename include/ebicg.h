@@ -294,19 +294,21 @@ eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int
  * in LDS; 2, 3 and 4 read from global memory with the sites visited in bricks
  * of 8 x 8 x 4 x 4, 8 x 8 x 8 x 8 and 4 x 4 x 4 x 4 sites (full-lattice stencil
  * only, extents divisible by the brick), which keeps more of a site's
- * neighbours in L2 when k columns make each site's record large.  eb_op_batch_tune runs the
+ * neighbours in L2 when k columns make each site's record large; 5 reads from
+ * global memory in site order with the loads of several hops in flight
+ * (full-lattice stencil only).  eb_op_batch_tune runs the
  * autotuner once per operator and precision (it times every form the
  * operator admits for k = 1, 2, 4, 8, 16 on `stream`, three repetitions after
  * a warm-up, and keeps per k the fastest form and overall the k with the
  * lowest time per right-hand side) and reports: *k_best; stage[5] (may be
- * NULL) the form used for k = 1, 2, 4, 8, 16; ms_per_rhs[25] (may be NULL) the
- * measured time per right-hand side, [5 i + form] for k = 2^i (0 for a form
+ * NULL) the form used for k = 1, 2, 4, 8, 16; ms_per_rhs[30] (may be NULL) the
+ * measured time per right-hand side, [6 i + form] for k = 2^i (0 for a form
  * not admitted).  Batched solves with batch = 0, sessions and
  * eb_op_apply_block / eb_op_apply_schur_block use the forms chosen here
  * (before tuning: LDS staging for k = 1 and for BF16, else form 0). */
 eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_best, int32_t *stage,
                            double *ms_per_rhs);
-/* Set the tile form for one precision and k (0..4 as above, or -1 for the built-in rule);
+/* Set the tile form for one precision and k (0..5 as above, or -1 for the built-in rule);
  * results agree to rounding between the forms.  EB_ERR_INVALID for a form the operator does
  * not admit.  Host-only; a later first run of the tuner replaces it. */
 eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage);

@@ -47,12 +47,17 @@ __device__ __forceinline__ bool col_active(const KrylovState *K, int col, int j)
 // batch size.  The batch autotuner times both forms per precision and k.
 template <typename S, int KC>
 constexpr bool kStage = KC == 1 || std::is_same<S, bf16c>::value;
+// (staged, fenced) for a tile form: form 1 (or the rule) stages in LDS;
+// form 5 reads globally without fences between the hops; the rest read
+// globally with one hop's loads in flight at a time.
 template <typename S, int KC, typename F>
 void dispatch_stage(int stage, F &&f) {
   if (stage < 0 ? kStage<S, KC> : stage == 1)
-    f(std::true_type{});
+    f(std::true_type{}, std::true_type{});
+  else if (stage == 5)
+    f(std::false_type{}, std::false_type{});
   else
-    f(std::false_type{});
+    f(std::false_type{}, std::true_type{});
 }
 // Site order of the global-read form.  Linear order puts a site's
 // t-neighbour Lx Ly Lz sites back in the traversal; with k columns of 12
@@ -91,7 +96,7 @@ __device__ __forceinline__ int brick_site(int q, const Geom &g, Brick b) {
   return (ix * b.bx + xx) + g.lx * ((iy * b.by + yy) + g.ly * ((iz * b.bz + zz) + g.lz * (it * b.bt + tt)));
 }
 
-template <typename S, int KC, int SF, bool STG>
+template <typename S, int KC, int SF, bool STG, bool FENCE>
 __global__ void __launch_bounds__(kBlock)
     k_bdslash(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa, Brick bk) {
   using R = typename Store<S>::R;
@@ -119,7 +124,7 @@ __global__ void __launch_bounds__(kBlock)
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
       const int s = brick_site(int(u / KC), g, bk), col = int(u % KC);
       cx<R> acc[12];
-      hopping<SF, S, KC>(acc, in + col, U, g, s);
+      hopping<SF, S, KC, FENCE>(acc, in + col, U, g, s);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const size_t i = (size_t(c) * g.V + s) * KC + col;
@@ -171,7 +176,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // v = D p; partials of (rhat, v) per column
-template <typename S, int KC, bool STG>
+template <typename S, int KC, bool STG, bool FENCE>
 __global__ void __launch_bounds__(kBlock)
     k_bstab_v(S *__restrict__ vout, const S *__restrict__ p, const S *__restrict__ rhat, const S *__restrict__ U,
               Geom g, double kappa, int j, const KrylovState *K, double *__restrict__ part, Brick bk) {
@@ -211,7 +216,7 @@ __global__ void __launch_bounds__(kBlock)
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
       const int s = brick_site(int(u / KC), g, bk);
       cx<R> acc[12];
-      hopping<-1, S, KC>(acc, p + col, U, g, s);
+      hopping<-1, S, KC, FENCE>(acc, p + col, U, g, s);
       epilogue(s, acc, [&](int, size_t i) { return Store<S>::ld(p, i); });
     }
   }
@@ -254,7 +259,7 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // t = D s; partials of (t, s), (t, t) per column
-template <typename S, int KC, bool STG>
+template <typename S, int KC, bool STG, bool FENCE>
 __global__ void __launch_bounds__(kBlock)
     k_bstab_t(S *__restrict__ tout, const S *__restrict__ sv, const S *__restrict__ U, Geom g, double kappa, int j,
               const KrylovState *K, double *__restrict__ part, Brick bk) {
@@ -295,7 +300,7 @@ __global__ void __launch_bounds__(kBlock)
     for (size_t u = size_t(lb) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
       const int s = brick_site(int(u / KC), g, bk);
       cx<R> acc[12];
-      hopping<-1, S, KC>(acc, sv + col, U, g, s);
+      hopping<-1, S, KC, FENCE>(acc, sv + col, U, g, s);
       epilogue(s, acc, [&](int, size_t i) { return Store<S>::ld(sv, i); });
     }
   }
@@ -523,6 +528,7 @@ bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || 
 bool batch_tile_ok(const Geom &g, bool eo, int stage) {
   if (stage < -1 || stage >= kTileForms) return false;
   if (stage < 2) return true;
+  if (stage == 5) return !eo;
   const Brick b = brick_of(stage);  // bricked forms: full-lattice stencil, extents divisible by the brick
   return !eo && g.lx % b.bx == 0 && g.ly % b.by == 0 && g.lz % b.bz == 0 && g.lt % b.bt == 0;
 }
@@ -532,13 +538,15 @@ void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa
                     int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
-    dispatch_stage<S, KC>(stage, [&](auto sg) {
-      constexpr bool STG = decltype(sg)::value;
+    dispatch_stage<S, KC>(stage, [&](auto sg, auto fg) {
+      constexpr bool STG = decltype(sg)::value, FENCE = decltype(fg)::value;
       const dim3 grid(nblocks_for(size_t(g.V) * KC));
       if (dagger)
-        EB_LAUNCH((k_bdslash<S, KC, +1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, brick_of(stage));
+        EB_LAUNCH((k_bdslash<S, KC, +1, STG, FENCE>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa,
+                  brick_of(stage));
       else
-        EB_LAUNCH((k_bdslash<S, KC, -1, STG>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, brick_of(stage));
+        EB_LAUNCH((k_bdslash<S, KC, -1, STG, FENCE>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa,
+                  brick_of(stage));
     });
   });
 }
@@ -559,8 +567,8 @@ void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, 
                     KrylovState *K, const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
-    dispatch_stage<S, KC>(stage, [&](auto sg) {
-      EB_LAUNCH((k_bstab_v<S, KC, decltype(sg)::value>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st,
+    dispatch_stage<S, KC>(stage, [&](auto sg, auto fg) {
+      EB_LAUNCH((k_bstab_v<S, KC, decltype(sg)::value, decltype(fg)::value>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st,
                 v, p, rhat, U, g, kappa, j, K, region(rs, RG_V), brick_of(stage));
     });
   });
@@ -583,8 +591,8 @@ void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, 
                     const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
-    dispatch_stage<S, KC>(stage, [&](auto sg) {
-      EB_LAUNCH((k_bstab_t<S, KC, decltype(sg)::value>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st,
+    dispatch_stage<S, KC>(stage, [&](auto sg, auto fg) {
+      EB_LAUNCH((k_bstab_t<S, KC, decltype(sg)::value, decltype(fg)::value>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st,
                 t, sv, U, g, kappa, j, K, region(rs, RG_T), brick_of(stage));
     });
   });

@@ -266,9 +266,10 @@ bool batch_size_ok(int kc);
 // launchers): 0 global neighbour reads in site order, 1 each block's tile
 // staged in LDS, 2, 3 and 4 global reads with the sites visited in bricks of
 // 8 x 8 x 4 x 4, 8 x 8 x 8 x 8 and 4 x 4 x 4 x 4 sites (full-lattice operator,
-// extents divisible by the brick); < 0 the built-in rule (LDS staging for
-// k = 1 and for BF16).
-constexpr int kTileForms = 5;
+// extents divisible by the brick), 5 global reads in site order with the
+// loads of several hops in flight (no fence between hops; full-lattice
+// operator); < 0 the built-in rule (LDS staging for k = 1 and for BF16).
+constexpr int kTileForms = 6;
 bool batch_tile_ok(const Geom &g, bool eo, int stage);
 // stage: tile form of the batched stencils (kTileForms above)
 template <typename S>

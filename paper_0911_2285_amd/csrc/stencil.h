@@ -105,23 +105,24 @@ __device__ __forceinline__ void mult_accum(cx<typename Store<S>::R> (&acc)[12], 
 __device__ __forceinline__ void hop_fence() { asm volatile("" ::: "memory"); }
 
 // One direction mu: forward hop with projector (1 + SF gamma_mu) and U_mu(x),
-// backward hop with (1 - SF gamma_mu) and U_mu(x - mu)^+.
-template <int MU, int SF, typename S, int KC = 1>
+// backward hop with (1 - SF gamma_mu) and U_mu(x - mu)^+.  FENCE = false
+// lets the compiler overlap the loads of several hops (more registers).
+template <int MU, int SF, typename S, int KC = 1, bool FENCE = true>
 __device__ __forceinline__ void hop_dir(cx<typename Store<S>::R> (&acc)[12], const S *__restrict__ in,
                                         const S *__restrict__ U, int V, int s, int sf, int sb) {
   using R = typename Store<S>::R;
   cx<R> h[6];
   load_project<MU, SF, S, KC>(h, in, V, sf);
   mult_accum<MU, SF, false, S>(acc, h, U, V, s);
-  hop_fence();
+  if constexpr (FENCE) hop_fence();
   load_project<MU, -SF, S, KC>(h, in, V, sb);
   mult_accum<MU, -SF, true, S>(acc, h, U, V, sb);
-  hop_fence();
+  if constexpr (FENCE) hop_fence();
 }
 
 // Hopping sum at site s: sum_mu [ (1 + SF g) U psi(x+mu) + (1 - SF g) U^+ psi(x-mu) ].
 // D uses SF = -1, D^+ uses SF = +1.
-template <int SF, typename S, int KC = 1>
+template <int SF, typename S, int KC = 1, bool FENCE = true>
 __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], const S *__restrict__ in,
                                         const S *__restrict__ U, const Geom &g, int s) {
 #pragma unroll
@@ -131,12 +132,12 @@ __device__ __forceinline__ void hopping(cx<typename Store<S>::R> (&acc)[12], con
   const int y = (s / sy) % g.ly;
   const int z = (s / sz) % g.lz;
   const int t = s / stt;
-  hop_dir<0, SF, S, KC>(acc, in, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
-  hop_dir<1, SF, S, KC>(acc, in, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
+  hop_dir<0, SF, S, KC, FENCE>(acc, in, U, g.V, s, x == g.lx - 1 ? s - (g.lx - 1) : s + 1, x == 0 ? s + (g.lx - 1) : s - 1);
+  hop_dir<1, SF, S, KC, FENCE>(acc, in, U, g.V, s, y == g.ly - 1 ? s - (g.ly - 1) * sy : s + sy,
                     y == 0 ? s + (g.ly - 1) * sy : s - sy);
-  hop_dir<2, SF, S, KC>(acc, in, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
+  hop_dir<2, SF, S, KC, FENCE>(acc, in, U, g.V, s, z == g.lz - 1 ? s - (g.lz - 1) * sz : s + sz,
                     z == 0 ? s + (g.lz - 1) * sz : s - sz);
-  hop_dir<3, SF, S, KC>(acc, in, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
+  hop_dir<3, SF, S, KC, FENCE>(acc, in, U, g.V, s, t == g.lt - 1 ? s - (g.lt - 1) * stt : s + stt,
                     t == 0 ? s + (g.lt - 1) * stt : s - stt);
 }
 

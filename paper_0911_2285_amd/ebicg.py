@@ -394,21 +394,22 @@ def op_trim(op, stream=None):
 
 def op_batch_tune(op, prec="fp32", stream=None):
     """The batch autotuner's choice for one precision: {"k": best k, "stage": {k: tile form},
-    "ms_per_rhs": {k: [global reads, LDS-staged, bricks 8x8x4x4, 8x8x8x8, 4x4x4x4]}} (0 for a form the
+    "ms_per_rhs": {k: [global reads, LDS-staged, bricks 8x8x4x4, 8x8x8x8, 4x4x4x4, unfenced]}} (0 for a form the
     operator does not admit; runs the tuner once per operator and precision)."""
     kb = ctypes.c_int32(0)
     stage = np.zeros(5, np.int32)
-    ms = np.zeros(25, np.float64)
+    ms = np.zeros(30, np.float64)
     _check(lib().eb_op_batch_tune(op.handle, PREC[prec], _stream(stream), ctypes.byref(kb), stage.ctypes.data,
                                   ms.ctypes.data))
     ks = [1, 2, 4, 8, 16]
     return {"k": kb.value, "stage": {k: int(stage[i]) for i, k in enumerate(ks)},
-            "ms_per_rhs": {k: [float(v) for v in ms[5 * i: 5 * i + 5]] for i, k in enumerate(ks)}}
+            "ms_per_rhs": {k: [float(v) for v in ms[6 * i: 6 * i + 6]] for i, k in enumerate(ks)}}
 
 
 def op_batch_set_tile(op, prec, k, stage):
     """Force the tile form of the batched stencil for (prec, k): 0 global reads, 1 LDS-staged,
-    2 / 3 / 4 global reads in bricks (full-lattice operators), -1 built-in rule."""
+    2 / 3 / 4 global reads in bricks, 5 global reads without fences between hops (full-lattice
+    operators), -1 built-in rule."""
     _check(lib().eb_op_batch_set_tile(op.handle, PREC[prec], int(k), int(stage)))
 
 

@@ -268,7 +268,7 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
     U = synth.random_su3_links(dims, 0.3, 91)
     op = gpu_lib.op_create(U, kappa, dims, eo=eo)
     par = W.parity(dims)
-    forms = (0, 1) if eo else (0, 1, 2, 3, 4)
+    forms = (0, 1) if eo else (0, 1, 2, 3, 4, 5)
     for k in (2, 16):
         psi = np.stack([synth.gaussian_spinor(V, 70 + c) for c in range(k)])
         x = torch.from_numpy(psi).to("cuda:0")
@@ -305,7 +305,7 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
             print(f"eo={eo} k={k} {prec}: largest difference between tile forms {d:.2e}")
             assert d <= bound, (k, prec, d)
             gpu_lib.op_batch_set_tile(op, prec, k, -1)
-    for bad in ((3, 1), (4, 2) if eo else (4, 5)):
+    for bad in ((3, 1), (4, 2) if eo else (4, 6)):
         with pytest.raises(gpu_lib.EbicgError):
             gpu_lib.op_batch_set_tile(op, "fp32", *bad)
     odd = gpu_lib.op_create(synth.random_su3_links((4, 4, 4, 8), 0.3, 92), kappa, (4, 4, 4, 8))
@@ -318,7 +318,7 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
         assert t["k"] in (1, 2, 4, 8, 16)
         assert all(s in forms for s in t["stage"].values())
         for kk, ms in t["ms_per_rhs"].items():
-            assert all(ms[f] > 0 for f in forms) and all(ms[f] == 0 for f in range(5) if f not in forms)
+            assert all(ms[f] > 0 for f in forms) and all(ms[f] == 0 for f in range(6) if f not in forms)
             assert ms[t["stage"][kk]] == min(ms[f] for f in forms)
 
 
@@ -338,7 +338,7 @@ def test_block_tile_forms_full_size_sampled(gpu_lib):
     sites = _sample_sites(dims, n=12)
     refs = [W.apply_D_sites(U, psi[c], kappa, dims, sites) for c in range(k)]
     scale = max(np.abs(r).max() for r in refs)
-    for stage in (0, 1, 2, 3, 4):
+    for stage in (0, 1, 2, 3, 4, 5):
         gpu_lib.op_batch_set_tile(op, "fp64", k, stage)
         y = torch.empty_like(x)
         gpu_lib.op_apply_block(op, y, x, k)
@@ -366,7 +366,7 @@ def test_dslash_block_32x64_sampled(gpu_lib):
     U32 = U.astype(np.complex64).astype(np.complex128)
     refs = [W.apply_D_sites(U32, psi[c].astype(np.complex128), kappa, dims, sites) for c in range(k)]
     scale = max(np.abs(r).max() for r in refs)
-    for stage in (3, 0):
+    for stage in (3, 0, 5):
         gpu_lib.op_batch_set_tile(op, "fp32", k, stage)
         y = torch.empty_like(x)
         gpu_lib.op_apply_block(op, y, x, k, prec="fp32")
