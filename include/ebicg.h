@@ -298,9 +298,10 @@ eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int
  * global memory in site order with the loads of several hops in flight
  * (full-lattice stencil only).  eb_op_batch_tune runs the
  * autotuner once per operator and precision (it times every form the
- * operator admits for k = 1, 2, 4, 8, 16 on `stream`, three repetitions after
- * a warm-up, and keeps per k the fastest form and overall the k with the
- * lowest time per right-hand side) and reports: *k_best; stage[5] (may be
+ * operator admits for k = 2, 4, 8, 16, and the LDS-staged form for k = 1,
+ * the form of the one-at-a-time solver that a single column runs, on
+ * `stream`, three repetitions after a warm-up, and keeps per k the fastest
+ * form and overall the k with the lowest time per right-hand side) and reports: *k_best; stage[5] (may be
  * NULL) the form used for k = 1, 2, 4, 8, 16; ms_per_rhs[30] (may be NULL) the
  * measured time per right-hand side, [6 i + form] for k = 2^i (0 for a form
  * not admitted).  Batched solves with batch = 0, sessions and

@@ -653,6 +653,9 @@ int tune_batch(eb_op *op, hipStream_t s) {
     double t_kc = HUGE_VAL;
     for (int stage = 0; stage < kTileForms; ++stage) {  // every tile form this operator admits
       if (!batch_tile_ok(op->g, op->eo, stage)) continue;
+      // one column runs the one-at-a-time solver, whose stencils stage their
+      // tiles in LDS: time k = 1 in that form only
+      if (kc == 1 && stage != 1) continue;
       apply(kc, stage);
       HIPCHK(hipEventRecord(e0, s));
       for (int rep = 0; rep < 3; ++rep) apply(kc, stage);
