@@ -405,12 +405,13 @@ SERVING_OPS = [  # (dims, kappa, share of the arrivals)
 ]
 
 
-def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=24, tol=1e-10):
+def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=24, tol=1e-10, inner="bf16"):
     """Serving: a Poisson stream of Z2-source solve requests over three resident
     even-odd operators (8^4, 16^3 x 32, 24^3 x 48; arrival mix 50/35/15%).
     Each operator's first `grow` requests run eigBiCG and grow its deflation
-    space; the rest are batched by its session (FP32 inner, FP64 refinement,
-    `slots` columns) with continuous admission.  A burst (every request at
+    space; the rest are batched by its session (BF16-stored inner solves,
+    FP64 refinement, `slots` columns; one burst with FP32 inner for
+    comparison) with continuous admission.  A burst (every request at
     t = 0) gives the saturation throughput; Poisson streams at fractions of it
     give p50 / p99 latency (arrival to result) beside solves/s."""
     import numpy as np
@@ -432,10 +433,10 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
         sources.append(torch.from_numpy(synth.z2_source(V, synth.rhs_seed(int(o) + 1, i)).ravel()).pin_memory())
     budget = 64 << 30
 
-    def run(arrivals, grow_now, graph=True):
+    def run(arrivals, grow_now, graph=True, inner="fp32"):
         for sp in specs:
             sp.grow = grow if grow_now else 0
-        srv = serve.Server(specs, inner="fp32", tol=tol, hbm_budget=budget, graph=graph)
+        srv = serve.Server(specs, inner=inner, tol=tol, hbm_budget=budget, graph=graph)
         reqs = [serve.Request(i, int(o), float(t), sources[i]) for i, (t, o) in enumerate(zip(arrivals, which))]
         torch.cuda.synchronize()
         res = srv.run(reqs)
@@ -451,27 +452,31 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
         return res, summ
 
     out = {"operators": [{"dims": list(d), "kappa": k, "share": w, "even_odd": True} for d, k, w in SERVING_OPS],
-           "requests": n_req, "slots": slots, "inner": "fp32", "tol": tol, "hbm_budget_bytes": budget,
+           "requests": n_req, "slots": slots, "inner": inner, "tol": tol, "hbm_budget_bytes": budget,
            "growth": {"eigbicg_requests_per_operator": grow, "nev": nev, "m": m}}
     # 1. a burst with online growth of the spaces: the eigBiCG phase and then the sessions
-    res, summ = run(np.zeros(n_req), True)
+    res, summ = run(np.zeros(n_req), True, inner=inner)
     out["burst_with_growth"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
     out["deflation_space_K"] = [eb.defl_info(sp.op)[0] for sp in specs]
     log(f"[bench] serving burst with growth: {out['burst_with_growth']}")
     # 2. a burst on the grown spaces: the saturation throughput of the sessions
-    res, summ = run(np.zeros(n_req), False)
+    res, summ = run(np.zeros(n_req), False, inner=inner)
     sat = summ["solves_per_s"]
     out["burst"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
     log(f"[bench] serving burst: {out['burst']}")
-    # the same burst with every chunk launched kernel by kernel (no hipGraph replay)
-    res, summ = run(np.zeros(n_req), False, graph=False)
+    # the same burst with every chunk launched kernel by kernel (no hipGraph replay),
+    # and with FP32-stored inner solves
+    res, summ = run(np.zeros(n_req), False, graph=False, inner=inner)
     out["burst_direct_launches"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
     log(f"[bench] serving burst, direct launches: {out['burst_direct_launches']}")
+    res, summ = run(np.zeros(n_req), False, inner="fp32")
+    out["burst_fp32_inner"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+    log(f"[bench] serving burst, FP32 inner: {out['burst_fp32_inner']}")
     # 3. Poisson streams at fractions of the saturation rate
     out["poisson"] = []
     for f in rel_rates:
         t, _ = serve.poisson_arrivals(n_req, f * sat, mix, seed=7)
-        res, summ = run(t, False)
+        res, summ = run(t, False, inner=inner)
         rec = {"rate_fraction": f, "arrival_rate_per_s": round(f * sat, 3)}
         rec.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()})
         out["poisson"].append(rec)
