@@ -268,7 +268,8 @@ typedef struct {
  * the batch autotuner for the operator and `inner` once (eb_op_batch_tune), so the slots'
  * stencils use the tuned tile form. */
 eb_status eb_session_create(eb_op *op, const eb_session_params *p, void *stream, eb_session **out);
-/* Wait for the work in flight and free the session (requests still running are dropped). */
+/* Wait for the work in flight and free the session (requests still running are dropped).
+ * A session must be destroyed before its operator. */
 eb_status eb_session_destroy(eb_session *s);
 /* Reserve a free slot for the request (b, x: device FP64 canonical spinors; x holds x0 and
  * receives the solution; tag: the caller's id).  Host-only: the request starts at the next

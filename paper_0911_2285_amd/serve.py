@@ -186,9 +186,11 @@ class Server:
                 self.max_resident = max(self.max_resident, self.resident_bytes() + inflight)
             # step only the sessions whose chunk has finished: a small operator's
             # slots turn over at its own pace, not at the largest operator's
+            stepped = False
             for i, sess in enumerate(self.sessions):
                 if active[i] and sess.ready():
                     sess.step()
+                    stepped = True
             for i, sess in enumerate(self.sessions):
                 for tag, status, st in sess.poll():
                     a = active[i].pop(tag)
@@ -197,6 +199,8 @@ class Server:
                                           a.x if self.keep else None))
             if not any(active) and not any(waiting) and qi < len(queue):
                 time.sleep(max(0.0, queue[qi].arrival - clock()))
+            elif not stepped and not admitted:
+                time.sleep(20e-6)   # every chunk still in flight: yield the core briefly
         return results
 
     def close(self):
