@@ -306,3 +306,48 @@ def test_session_full_size_even_odd(gpu_lib):
     sess.close()
     torch.cuda.synchronize()
     assert torch.equal(xa, x[3])
+
+
+def test_growth_between_chunks_leaves_running_requests_untouched(gpu_lib, cfg0):
+    """eigBiCG grows the space on the session's operator and stream while two
+    requests are in flight (between chunks): those requests, deflated with
+    the empty space at admission, finish bit for bit as in a run without the
+    growth, and a request admitted afterwards is deflated with the new pairs."""
+    import torch
+
+    dims, kappa, U, D = cfg0
+    V = synth.volume(dims)
+    B = [synth.z2_source(V, synth.rhs_seed(0, 120 + i)).ravel() for i in range(3)]
+    stream = torch.cuda.Stream()
+
+    def serve_two(grow):
+        op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8)
+        sess = gpu_lib.Session(op, slots=2, inner="fp32", tol=1e-10, chunk=4, stream=stream)
+        b = [torch.from_numpy(v).to("cuda:0") for v in B]
+        x = [torch.zeros_like(v) for v in b]
+        torch.cuda.synchronize()
+        sess.admit(b[0], x[0], 0)
+        sess.admit(b[1], x[1], 1)
+        sess.step()
+        sess.step()
+        if grow:
+            bg = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(9, 5))).to("cuda:0")
+            torch.cuda.synchronize()
+            gpu_lib.eigbicg_solve(op, bg, torch.zeros_like(bg), nev=4, m=16, tol=1e-10, stream=stream)
+        done = _drain(sess, 2)
+        K_after = gpu_lib.defl_info(op)[0]
+        sess.admit(b[2], x[2], 2)
+        done.update(_drain(sess, 1))
+        sess.close()
+        torch.cuda.synchronize()
+        return [xi.cpu().numpy() for xi in x], done, K_after
+
+    x_plain, d_plain, K0 = serve_two(False)
+    x_grow, d_grow, K1 = serve_two(True)
+    assert K0 == 0 and K1 == 4
+    for i in (0, 1):
+        assert d_grow[i][0] == "EB_OK" and np.array_equal(x_grow[i], x_plain[i]), i
+    for i in range(3):
+        assert _resid(U, kappa, dims, B[i], x_grow[i]) <= 1e-10
+    print("third request iterations: without space", d_plain[2][1]["iters"], "with 4 pairs", d_grow[2][1]["iters"])
+    assert not np.array_equal(x_grow[2], x_plain[2])   # its start was deflated with the new pairs
