@@ -4,7 +4,9 @@ budget, latency records.
 
 Each operator keeps its gauge field and its deflation space on the device.
 The first requests of an operator are solved by eigBiCG one at a time
-(Alg. Incremental eigBiCG, step 2: each absorbs nev pairs); later requests go
+(Alg. Incremental eigBiCG, step 2: each absorbs nev pairs), on a worker
+thread per operator so that the loop keeps stepping the other operators'
+sessions meanwhile; later requests go
 to the operator's session (the library's eb_session), which batches them as
 slots of the multi-RHS BiCGStab with their starts deflated by the space as it
 is when they start (step 3).  Requests that arrive while others run are
@@ -17,6 +19,7 @@ from __future__ import annotations
 
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -92,10 +95,27 @@ class Server:
         self.grow_left = [sp.grow for sp in self.specs]
         self.max_resident = 0
         self.deferred = 0   # admissions postponed by the memory budget
+        # growth solves run on a worker per operator; while one runs, its
+        # operator is not queried (its buffers may be growing): the last
+        # measured size stands in for it
+        self._pool = ThreadPoolExecutor(max_workers=max(1, len(self.specs)))
+        self._growing = [None] * len(self.specs)
+        self._op_bytes = [self.eb.op_device_bytes(sp.op) for sp in self.specs]
 
     def resident_bytes(self):
-        return (sum(self.eb.op_device_bytes(sp.op) for sp in self.specs)
-                + sum(s.info()["device_bytes"] for s in self.sessions))
+        for i, sp in enumerate(self.specs):
+            if self._growing[i] is None:
+                self._op_bytes[i] = self.eb.op_device_bytes(sp.op)
+        return sum(self._op_bytes) + sum(s.info()["device_bytes"] for s in self.sessions)
+
+    def _grow(self, i, b, x):
+        sp = self.specs[i]
+        try:
+            st, _ = self.eb.eigbicg_solve(sp.op, b, x, sp.nev, sp.m, self.tol, maxiter=self.maxiter,
+                                          stream=self.streams[i])
+            return st, "EB_OK"
+        except self.eb.EbicgError as e:
+            return e.stats or {}, self.eb.STATUS.get(e.status, str(e.status))
 
     def _new_stream(self):
         import torch
@@ -133,7 +153,7 @@ class Server:
                 return True
             return self.resident_bytes() + inflight + nbytes <= self.budget
 
-        while qi < len(queue) or any(waiting) or any(active):
+        while qi < len(queue) or any(waiting) or any(active) or any(g is not None for g in self._growing):
             now = clock()
             while qi < len(queue) and queue[qi].arrival <= now:
                 waiting[queue[qi].op].append(queue[qi])
@@ -141,30 +161,23 @@ class Server:
             blocked = False   # a request waits for memory
             admitted = False
             for i, sp in enumerate(self.specs):
-                # growth phase: eigBiCG solves one at a time, each absorbing nev pairs
-                if self.grow_left[i] > 0 and waiting[i] and not active[i]:
-                    req = waiting[i][0]
-                    nb = self._request_bytes(sp.op)
-                    if not fits(nb):
-                        self.deferred += 1
-                        blocked = True
-                    else:
-                        waiting[i].popleft()
-                        admitted = True
-                        self.max_resident = max(self.max_resident, self.resident_bytes() + inflight + nb)
-                        start, K = clock(), self._defl_K(i)
-                        b, x = self._upload(i, req)
-                        try:
-                            st, _ = self.eb.eigbicg_solve(sp.op, b, x, sp.nev, sp.m, self.tol, maxiter=self.maxiter,
-                                                          stream=self.streams[i])
-                            status = "EB_OK"
-                        except self.eb.EbicgError as e:
-                            st, status = e.stats or {}, self.eb.STATUS.get(e.status, str(e.status))
-                        self.grow_left[i] -= 1
-                        results.append(Result(req.rid, i, "eigbicg", req.arrival, start, clock(), status, st, K,
-                                              x if self.keep else None))
-                    continue
+                # growth phase: eigBiCG solves one at a time per operator, each
+                # absorbing nev pairs, on the operator's worker
                 if self.grow_left[i] > 0:
+                    if self._growing[i] is None and waiting[i]:
+                        nb = self._request_bytes(sp.op)
+                        if not fits(nb):
+                            self.deferred += 1
+                            blocked = True
+                        else:
+                            req = waiting[i].popleft()
+                            admitted = True
+                            inflight += nb
+                            self.max_resident = max(self.max_resident, self.resident_bytes() + inflight)
+                            start, K = clock(), self._defl_K(i)
+                            b, x = self._upload(i, req)
+                            fut = self._pool.submit(self._grow, i, b, x)
+                            self._growing[i] = (fut, req, x, start, K, nb)
                     continue
                 sess = self.sessions[i]
                 while waiting[i] and len(active[i]) < sp.slots:
@@ -180,7 +193,7 @@ class Server:
                     active[i][req.rid] = _Active(req, b, x, clock(), self._defl_K(i), nb)
                     inflight += nb
                     admitted = True
-            if blocked and not any(active):
+            if blocked and not any(active) and not any(g is not None for g in self._growing):
                 raise RuntimeError("a waiting request does not fit the device-memory budget with nothing running")
             if admitted:
                 self.max_resident = max(self.max_resident, self.resident_bytes() + inflight)
@@ -191,19 +204,30 @@ class Server:
                 if active[i] and sess.ready():
                     sess.step()
                     stepped = True
+            for i, g in enumerate(self._growing):
+                if g is not None and g[0].done():
+                    fut, req, x, start, K, nb = g
+                    st, status = fut.result()
+                    self._growing[i] = None
+                    self.grow_left[i] -= 1
+                    inflight -= nb
+                    stepped = True
+                    results.append(Result(req.rid, i, "eigbicg", req.arrival, start, clock(), status, st, K,
+                                          x if self.keep else None))
             for i, sess in enumerate(self.sessions):
                 for tag, status, st in sess.poll():
                     a = active[i].pop(tag)
                     inflight -= a.nbytes
                     results.append(Result(tag, i, "session", a.req.arrival, a.start, clock(), status, st, a.K,
                                           a.x if self.keep else None))
-            if not any(active) and not any(waiting) and qi < len(queue):
+            if not any(active) and not any(waiting) and qi < len(queue) and all(g is None for g in self._growing):
                 time.sleep(max(0.0, queue[qi].arrival - clock()))
             elif not stepped and not admitted:
                 time.sleep(20e-6)   # every chunk still in flight: yield the core briefly
         return results
 
     def close(self):
+        self._pool.shutdown(wait=True)
         for s in self.sessions:
             s.close()
 
