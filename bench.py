@@ -458,10 +458,10 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
         sources.append(torch.from_numpy(synth.z2_source(V, synth.rhs_seed(int(o) + 1, i)).ravel()).pin_memory())
     budget = 64 << 30
 
-    def run(arrivals, grow_now, graph=True, inner="fp32"):
+    def run(arrivals, grow_now, graph=True, inner="fp32", hbm_budget=None):
         for sp in specs:
             sp.grow = grow if grow_now else 0
-        srv = serve.Server(specs, inner=inner, tol=tol, hbm_budget=budget, graph=graph)
+        srv = serve.Server(specs, inner=inner, tol=tol, hbm_budget=hbm_budget or budget, graph=graph)
         reqs = [serve.Request(i, int(o), float(t), sources[i]) for i, (t, o) in enumerate(zip(arrivals, which))]
         torch.cuda.synchronize()
         res = srv.run(reqs)
@@ -506,6 +506,19 @@ def serving(eb, n_req=48, rel_rates=(0.25, 0.5, 1.0), slots=8, grow=4, nev=8, m=
         rec.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()})
         out["poisson"].append(rec)
         log(f"[bench] serving poisson {f}: {rec}")
+    # 4. the saturation-rate stream under a memory budget that binds: what the
+    # operators and sessions hold plus room for the b and x of four requests
+    # of the largest operator; admissions wait for memory instead of failing
+    probe = serve.Server(specs, inner=inner, tol=tol)
+    resident = probe.resident_bytes()
+    probe.close()
+    tight = resident + 4 * 2 * 16 * max(sp.op.N for sp in specs)
+    t, _ = serve.poisson_arrivals(n_req, sat, mix, seed=7)
+    res, summ = run(t, False, inner=inner, hbm_budget=tight)
+    rec = {"rate_fraction": 1.0, "hbm_budget_bytes": tight}
+    rec.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()})
+    out["poisson_tight_budget"] = rec
+    log(f"[bench] serving poisson under a tight budget: {rec}")
     for sp in specs:
         eb.op_destroy(sp.op)
     return out
