@@ -132,6 +132,8 @@ def cpu_baseline(W, U, b_np, eig_iters, stab_iters, n_eig_it=5, n_stab_it=3):
         t1 = time.perf_counter()
         K.bicgstab(A, b, np.zeros_like(b), W["tol"], maxiter=n_stab_it)
         t2 = time.perf_counter()
+        A(b)
+        t3 = time.perf_counter()
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
@@ -148,6 +150,9 @@ def cpu_baseline(W, U, b_np, eig_iters, stab_iters, n_eig_it=5, n_stab_it=3):
                    f"step's iteration counts ({eig_iters} eigBiCG + {stab_iters} BiCGStab)"),
         "seconds_per_eigbicg_iter": t_eig,
         "seconds_per_bicgstab_iter": t_stab,
+        # one application of the oracle's D, in the GPU's byte model (960 B per site)
+        "dslash_seconds": round(t3 - t2, 4),
+        "dslash_GBps": round(960 * V / (t3 - t2) / 1e9, 3),
     }
 
 
