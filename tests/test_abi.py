@@ -92,3 +92,31 @@ def test_invalid_arguments_are_rejected_on_the_host(eb):
     assert eb.lib().eb_op_create(U.ctypes.data, float("nan"), dims, -1, 0, ctypes.byref(h)) == -1
     assert eb.lib().eb_op_create(U.ctypes.data, 0.1, dims, 0, 0, ctypes.byref(h)) == -1
     assert eb.lib().eb_op_create(None, 0.1, dims, -1, 0, ctypes.byref(h)) == -1
+
+
+def test_session_and_tuning_calls_reject_null_handles_on_the_host(eb):
+    """The serving and autotuning entry points validate their arguments before
+    touching a device: null handles and null outputs give EB_ERR_INVALID with a
+    message, and destroying a null session is a no-op."""
+    import ctypes
+
+    L = eb.lib()
+    n = ctypes.c_int32(0)
+    r = ctypes.c_int32(0)
+    nb = ctypes.c_uint64(0)
+    params = eb._SessionParams(4, 1, 1e-10, 0.0, 100, 8, 1)
+    out = ctypes.c_void_p()
+    assert L.eb_session_create(None, ctypes.byref(params), None, ctypes.byref(out)) == -1
+    assert L.eb_session_admit(None, None, None, 0, None) == -1
+    assert L.eb_session_step(None) == -1
+    assert L.eb_session_ready(None, ctypes.byref(r)) == -1
+    assert L.eb_session_poll(None, 0, None, None, None, ctypes.byref(n)) == -1
+    assert L.eb_session_info(None, None, None, None, None) == -1
+    assert L.eb_session_destroy(None) == 0
+    assert L.eb_op_device_bytes(None, ctypes.byref(nb)) == -1
+    assert L.eb_op_trim(None, None) == -1
+    assert L.eb_op_batch_set_tile(None, 1, 4, 0) == -1
+    assert L.eb_op_batch_tune(None, 1, None, ctypes.byref(n), None, None) == -1
+    buf = ctypes.create_string_buffer(256)
+    L.eb_last_error(buf, 256)
+    assert buf.value  # the last call left a message
