@@ -277,7 +277,10 @@ eb_status eb_session_destroy(eb_session *s);
 eb_status eb_session_admit(eb_session *s, const void *b, void *x, int64_t tag, int32_t *slot);
 /* Wait for the chunk in flight; harvest the slots whose inner solve stopped (finish them or
  * start their next refinement step); start the admitted requests; launch the next chunk of
- * iterations and return without waiting for it.  Finished requests become pollable. */
+ * iterations and return without waiting for it.  Finished requests become pollable.  A
+ * request's own failure (maxiter, breakdown) is reported through eb_session_poll; a non-OK
+ * status from this call (a HIP error) leaves the slots in an unknown state: destroy the
+ * session. */
 eb_status eb_session_step(eb_session *s);
 /* *ready = 1 when eb_session_step would not wait (no chunk in flight, or it has finished),
  * else 0.  Does not wait: a loop over several sessions steps the ready ones only. */
