@@ -400,6 +400,121 @@ __global__ void __launch_bounds__(kBlock)
     Store<S>::st(p, u, Store<S>::ld(r, u) + b * (Store<S>::ld(p, u) - w * Store<S>::ld(v, u)));
 }
 
+// ---- consumer-side scalars for small grids ------------------------------------
+// When the producer's records are few (nblk NV KC doubles), every block of the
+// consuming pass sums them itself, in the same fixed order as the one-block
+// finish kernels, and block 0 stores the scalar and any stop in the history
+// and state; the separate finish launch between the passes goes away.  Other
+// blocks decide from their own (identical) totals, never from state that
+// block 0 may be writing during the launch.
+constexpr int kFuseMaxDoubles = 4096;
+inline bool fuse_finish(int nblk, int nv, int kc) { return size_t(nblk) * nv * kc <= size_t(kFuseMaxDoubles); }
+
+// alpha_j = rho_{j-1} / (rhat, v); s = r - alpha v
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_s_f(S *__restrict__ sv, const S *__restrict__ r, const S *__restrict__ v, size_t n, int j,
+                KrylovState *K, KrylovHistory h, const double *__restrict__ part, int nblk) {
+  using R = typename Store<S>::R;
+  double d[2 * KC];
+  sum_partials<2 * KC, kBlock>(part, nblk, d);
+  const int col = threadIdx.x % KC;
+  if (!col_active(K, col, j)) return;
+  const cx<double> den{pick(d, 2 * col), pick(d, 2 * col + 1)};
+  const double dd = den.x * den.x + den.y * den.y;
+  const bool lead = blockIdx.x == 0 && threadIdx.x < KC;
+  if (!(dd > 0.0) || !isfinite(dd)) {  // breakdown
+    if (lead) {
+      K[col].stopped = 1;
+      K[col].stop_at = j - 1;
+      K[col].reason = 2;
+    }
+    return;
+  }
+  const cx<double> al = cdiv(c2(h.rho[(j - 1) * KC + col]), den);
+  if (lead) h.alpha[j * KC + col] = d2(al);
+  const cx<R> a{R(al.x), R(al.y)};
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock)
+    Store<S>::st(sv, u, Store<S>::ld(r, u) - a * Store<S>::ld(v, u));
+}
+// omega_j = (t, s) / (t, t); x += alpha p + omega s; r = s - omega t; records of (rhat, r), ||r||^2
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_xr_f(S *__restrict__ x, S *__restrict__ r, const S *__restrict__ p, const S *__restrict__ sv,
+                 const S *__restrict__ t, const S *__restrict__ rhat, size_t n, int j, KrylovState *K,
+                 KrylovHistory h, const double *__restrict__ part_t, int nblk, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  double d[3 * KC];
+  sum_partials<3 * KC, kBlock>(part_t, nblk, d);
+  const int col = threadIdx.x % KC;
+  double e[3] = {0.0, 0.0, 0.0};
+  if (col_active(K, col, j)) {
+    const double tt = pick(d, 3 * col + 2);
+    const bool lead = blockIdx.x == 0 && threadIdx.x < KC;
+    if (!(tt > 0.0)) {  // breakdown
+      if (lead) {
+        K[col].stopped = 1;
+        K[col].stop_at = j - 1;
+        K[col].reason = 2;
+      }
+    } else {
+      const cx<double> om{pick(d, 3 * col) / tt, pick(d, 3 * col + 1) / tt};
+      if (lead) h.omega[j * KC + col] = d2(om);
+      const cx<double> al = c2(h.alpha[j * KC + col]);
+      const cx<R> a{R(al.x), R(al.y)}, w{R(om.x), R(om.y)};
+      for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock) {
+        const cx<R> si = Store<S>::ld(sv, u);
+        Store<S>::st(x, u, Store<S>::ld(x, u) + a * Store<S>::ld(p, u) + w * si);
+        const cx<R> ri = si - w * Store<S>::ld(t, u);
+        Store<S>::st(r, u, ri);
+        const cx<R> hh = Store<S>::ld(rhat, u);
+        e[0] += double(hh.x) * ri.x + double(hh.y) * ri.y;
+        e[1] += double(hh.x) * ri.y - double(hh.y) * ri.x;
+        e[2] += double(ri.x) * ri.x + double(ri.y) * ri.y;
+      }
+    }
+  }
+  block_partial_cols<3, KC, kBlock>(e, part, blockIdx.x);
+}
+// rho_j, ||r_j||, beta_j and the stop tests; p = r + beta (p - omega v) for the
+// columns that go on
+template <typename S, int KC>
+__global__ void __launch_bounds__(kBlock)
+    k_bstab_p_f(S *__restrict__ p, const S *__restrict__ r, const S *__restrict__ v, size_t n, int j,
+                KrylovState *K, KrylovHistory h, const double *__restrict__ part, int nblk) {
+  using R = typename Store<S>::R;
+  double d[3 * KC];
+  sum_partials<3 * KC, kBlock>(part, nblk, d);
+  const int col = threadIdx.x % KC;
+  if (!col_active(K, col, j)) return;
+  const cx<double> rho{pick(d, 3 * col), pick(d, 3 * col + 1)};
+  const cx<double> be =
+      cdiv(rho, c2(h.rho[(j - 1) * KC + col])) * cdiv(c2(h.alpha[j * KC + col]), c2(h.omega[j * KC + col]));
+  const double rnorm = sqrt(pick(d, 3 * col + 2));
+  int reason = 0;
+  if (rnorm <= K[col].tol_abs)
+    reason = 1;
+  else if (rho.x == 0.0 && rho.y == 0.0)
+    reason = 2;
+  else if (j >= K[col].maxiter)
+    reason = 4;
+  if (blockIdx.x == 0 && threadIdx.x < KC) {
+    h.rho[j * KC + col] = d2(rho);
+    h.beta[j * KC + col] = d2(be);
+    h.rn[j * KC + col] = rnorm;
+    K[col].rnorm = rnorm;
+    if (reason) {
+      K[col].stopped = 1;
+      K[col].stop_at = j;
+      K[col].reason = reason;
+    }
+  }
+  if (reason) return;  // the column stopped at this j: p keeps its value
+  const cx<double> om = c2(h.omega[j * KC + col]);
+  const cx<R> b{R(be.x), R(be.y)}, w{R(om.x), R(om.y)};
+  for (size_t u = size_t(blockIdx.x) * kBlock + threadIdx.x; u < n; u += size_t(gridDim.x) * kBlock)
+    Store<S>::st(p, u, Store<S>::ld(r, u) + b * (Store<S>::ld(p, u) - w * Store<S>::ld(v, u)));
+}
 // FP64 columns (column col at src + col N) <-> a batch in storage S
 template <typename S, int KC>
 __global__ void __launch_bounds__(kBlock)
@@ -580,8 +695,13 @@ void launch_bstab_s(S *sv, const S *r, const S *v, const Geom &g, int j, int kc,
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    EB_LAUNCH(k_bfin_alpha<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_V), batch_stencil_grid(g.V, KC, 2), j, K,
-              h);
+    const int nblk = batch_stencil_grid(g.V, KC, 2);
+    if (fuse_finish(nblk, 2, KC)) {
+      EB_LAUNCH((k_bstab_s_f<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, sv, r, v, n, j, K, h,
+                region(rs, RG_V), nblk);
+      return;
+    }
+    EB_LAUNCH(k_bfin_alpha<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_V), nblk, j, K, h);
     EB_LAUNCH((k_bstab_s<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, sv, r, v, n, j, K, h);
   });
 }
@@ -604,8 +724,13 @@ void launch_bstab_xr(S *x, S *r, const S *p, const S *sv, const S *t, const S *r
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    EB_LAUNCH(k_bfin_omega<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_T), batch_stencil_grid(g.V, KC, 3), j, K,
-              h);
+    const int nblk = batch_stencil_grid(g.V, KC, 3);
+    if (fuse_finish(nblk, 3, KC)) {
+      EB_LAUNCH((k_bstab_xr_f<S, KC>), dim3(batch_red_grid(n, KC, 3)), dim3(kBlock), 0, st, x, r, p, sv, t, rhat, n,
+                j, K, h, region(rs, RG_T), nblk, region(rs, RG_XR));
+      return;
+    }
+    EB_LAUNCH(k_bfin_omega<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_T), nblk, j, K, h);
     EB_LAUNCH((k_bstab_xr<S, KC>), dim3(batch_red_grid(n, KC, 3)), dim3(kBlock), 0, st, x, r, p, sv, t, rhat, n, j, K,
               h, region(rs, RG_XR));
   });
@@ -617,7 +742,13 @@ void launch_bstab_p(S *p, const S *r, const S *v, const Geom &g, int j, int kc, 
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    EB_LAUNCH(k_bfin_beta<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_XR), batch_red_grid(n, KC, 3), j, K, h);
+    const int nblk = batch_red_grid(n, KC, 3);
+    if (fuse_finish(nblk, 3, KC)) {
+      EB_LAUNCH((k_bstab_p_f<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, p, r, v, n, j, K, h,
+                region(rs, RG_XR), nblk);
+      return;
+    }
+    EB_LAUNCH(k_bfin_beta<KC>, dim3(1), dim3(kBlock), 0, st, region(rs, RG_XR), nblk, j, K, h);
     EB_LAUNCH((k_bstab_p<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, p, r, v, n, j, K, h);
   });
 }
