@@ -79,7 +79,8 @@ typedef struct {
   int32_t maxiter;  /* cap on inner iterations summed over restarts and refinement steps */
   int32_t method;   /* 0: BiCGStab (the paper's choice), 1: BiCG */
   eb_prec inner;    /* working precision of the inner iteration; FP32/BF16 run inside FP64 refinement */
-  double inner_tol; /* relative residual reduction per refinement step (ignored for EB_FP64) */
+  double inner_tol; /* relative residual reduction per refinement step, < 1; <= 0 selects the
+                       default (1e-6 FP32, 1e-2 BF16); ignored for EB_FP64 */
   int32_t nrhs;     /* right-hand sides (b, x hold nrhs spinors back to back) */
   int32_t batch;    /* columns per batched iteration: 1 = one at a time; 2, 4, 8, 16; 0 = the
                        library's choice (timed once per operator and precision). Batching needs
@@ -257,7 +258,9 @@ typedef struct {
   int32_t slots;    /* columns of the batch: 1, 2, 4, 8 or 16 */
   eb_prec inner;    /* storage of the inner iteration (EB_FP64, EB_FP32, EB_BF16) */
   double tol;       /* target ||b - A x|| / ||b|| per request */
-  double inner_tol; /* residual reduction per refinement step; <= 0: 1e-6 (FP32), 1e-2 (BF16), none (FP64) */
+  double inner_tol; /* residual reduction per refinement step, < 1; <= 0: 1e-6 (FP32), 1e-2 (BF16),
+                       none (FP64).  A refinement step that makes no inner iteration ends the
+                       request with EB_ERR_NOT_CONVERGED. */
   int32_t maxiter;  /* inner iterations per request, summed over refinement steps */
   int32_t chunk;    /* iterations launched between slot updates, 1..1024 */
   int32_t graph;    /* 1: the chunk's launches are captured once as a hipGraph and replayed
@@ -321,6 +324,12 @@ eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage
  * links, the deflation space or the reduction scratch) after waiting for `stream` and the
  * device; later calls allocate what they need again.  Sessions keep their own buffers. */
 eb_status eb_op_trim(eb_op *op, void *stream);
+/* Testing knob: cap on the grid of the stencil kernels that produce reduction
+ * partials (default 1024 blocks of 256 sites; 0 restores it).  Beyond the
+ * cap each block loops over several site tiles, which large lattices do by
+ * default (V > 262144); a small cap makes a small lattice take that path.
+ * Results agree to rounding with any cap.  Host-only. */
+eb_status eb_op_set_grid_cap(eb_op *op, int32_t max_blocks);
 /* Device bytes the operator holds (links, deflation space, work buffers). */
 eb_status eb_op_device_bytes(eb_op *op, uint64_t *bytes);
 

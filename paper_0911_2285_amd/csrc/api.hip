@@ -131,6 +131,7 @@ struct eb_op {
   double kappa = 0;
   int bc_t = -1;
   int device = 0;
+  int grid_cap = kDefaultStencilCap;  // grid cap of the reducing stencil kernels (eb_op_set_grid_cap)
   DevBuf U64, U32, U16;  // links: FP64, and FP32 / BF16 copies made on first use
   // deflation space: Ul, Ur hold Kcap FP64 SoA spinors each; H = Ul^+ A Ur on the host
   int Kcap = 0, K = 0;
@@ -253,7 +254,12 @@ struct eb_op {
 
 namespace {
 
-void set_device(eb_op *op) { HIPCHK(hipSetDevice(op->device)); }
+// Every entry point starts here: the operator's device, and its grid cap for
+// the stencil launches this thread makes.
+void set_device(eb_op *op) {
+  HIPCHK(hipSetDevice(op->device));
+  stencil_block_cap() = op->grid_cap;
+}
 
 // Launch through `f`, bracketed by timing events when the op records kernel times.
 template <typename F>
@@ -1700,6 +1706,7 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     if (!op || !b_can || !x_can || !P) fail(EB_ERR_INVALID, "null argument");
     if (!(P->tol > 0) || P->maxiter < 1 || P->nrhs < 1) fail(EB_ERR_INVALID, "tol > 0, maxiter >= 1, nrhs >= 1");
     if (P->deftol < 0 || P->deftol >= 1) fail(EB_ERR_INVALID, "deftol must be in [0, 1)");
+    if (!(P->inner_tol < 1)) fail(EB_ERR_INVALID, "inner_tol must be < 1 (<= 0 selects the default)");
     if (P->method != 0) fail(EB_ERR_INVALID, "only method 0 (BiCGStab) is available");
     if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
       fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
@@ -2215,6 +2222,12 @@ void session_advance(eb_session *ss, const std::vector<int> &cols, const std::ve
       session_finish(ss, c, EB_ERR_BREAKDOWN, rel / q.scale);
       continue;
     }
+    if (q.outer > 0 && q.step_iters == 0) {
+      // a refinement step that stopped at initialisation leaves x unchanged:
+      // the next one would do the same, so the request cannot progress
+      session_finish(ss, c, EB_ERR_NOT_CONVERGED, rel / q.scale);
+      continue;
+    }
     const double target = std::max(ss->inner_tol * rn, 0.5 * tolc * bn);
     session_dispatch(ss->prec, [&](auto ops) { decltype(ops)::start(ss, c, target, ss->maxiter - q.iters); });
     q.step_iters = 0;
@@ -2324,6 +2337,7 @@ eb_status eb_session_create(eb_op *op, const eb_session_params *P, void *stream,
       fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
     if (!(P->tol > 0) || P->maxiter < 1) fail(EB_ERR_INVALID, "tol > 0 and maxiter >= 1 required");
     if (P->chunk < 1 || P->chunk > 1024) fail(EB_ERR_INVALID, "chunk must be in [1, 1024]");
+    if (!(P->inner_tol < 1)) fail(EB_ERR_INVALID, "inner_tol must be < 1 (<= 0 selects the default)");
     set_device(op);
     std::unique_ptr<eb_session> ss(new eb_session);
     ss->op = op;
@@ -2493,6 +2507,14 @@ eb_status eb_op_trim(eb_op *op, void *stream) {
     op->bufs.clear();
     op->hist.release();
     op->hist_cap = 0;
+  });
+}
+
+eb_status eb_op_set_grid_cap(eb_op *op, int32_t max_blocks) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    if (max_blocks < 0) fail(EB_ERR_INVALID, "max_blocks must be >= 0");
+    op->grid_cap = max_blocks == 0 ? kDefaultStencilCap : max_blocks;
   });
 }
 

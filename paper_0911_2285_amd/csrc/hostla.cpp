@@ -270,7 +270,9 @@ bool lu_solve(const CMat &Ain, std::vector<cd> &b) {
     int p = k;
     for (int i = k + 1; i < n; ++i)
       if (std::abs(A(i, k)) > std::abs(A(p, k))) p = i;
-    if (std::abs(A(p, k)) <= 1e-300 + 1e-15 * amax * 1e-3) return false;
+    // relative pivot test: a pivot at rounding level of the largest entry
+    // means H is singular to working precision
+    if (!(std::abs(A(p, k)) > n * std::numeric_limits<double>::epsilon() * amax)) return false;
     if (p != k) {
       for (int j = 0; j < n; ++j) std::swap(A(k, j), A(p, j));
       std::swap(b[k], b[p]);

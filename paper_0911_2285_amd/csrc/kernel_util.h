@@ -25,12 +25,12 @@ inline int red_grid(size_t n) {
   int nb = nblocks_for(n, 4);
   return nb < 1 ? 1 : (nb > kMaxRedBlocks ? kMaxRedBlocks : nb);
 }
-// stencil kernels with reductions: one block per kBlock sites, capped; the
-// kernels loop over site blocks beyond the cap
-constexpr int kMaxStencilBlocks = 1024;
+// stencil kernels with reductions: one block per kBlock sites, capped at
+// stencil_block_cap(); the kernels loop over site blocks beyond the cap
 inline int stencil_grid(int V) {
   int nb = nblocks_for(size_t(V));
-  return nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
+  const int cap = stencil_block_cap();
+  return nb > cap ? cap : nb;
 }
 // the BiCG matvec: one work item per (tile, pass)
 inline int matvec_grid(int V) { return 2 * stencil_grid(V); }
@@ -43,7 +43,8 @@ inline int stream_grid(size_t n) {
 inline int batch_stencil_grid(int V, int kc, int nv) {
   int nb = nblocks_for(size_t(V) * kc);
   const int cap = int(kRegion / size_t(kc * nv));
-  nb = nb > kMaxStencilBlocks ? kMaxStencilBlocks : nb;
+  const int scap = stencil_block_cap();
+  nb = nb > scap ? scap : nb;
   return nb > cap ? cap : nb;
 }
 inline int batch_red_grid(size_t n, int kc, int nv) {

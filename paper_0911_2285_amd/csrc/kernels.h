@@ -22,6 +22,12 @@ struct LaunchStamp {
 };
 LaunchStamp &launch_stamp();
 
+// Grid cap of the stencil kernels that carry reductions (their blocks loop
+// over the site tiles beyond it); per host thread, set from the operator by
+// every entry point before its launches.  Default kDefaultStencilCap.
+constexpr int kDefaultStencilCap = 1024;
+int &stencil_block_cap();
+
 #define EB_LAUNCH(kernel, grid, block, shmem, st, ...)                                                       \
   do {                                                                                                       \
     ::ebicg::LaunchStamp &eb_ls_ = ::ebicg::launch_stamp();                                                 \

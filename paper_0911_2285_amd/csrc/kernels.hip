@@ -636,6 +636,10 @@ LaunchStamp &launch_stamp() {
   static thread_local LaunchStamp ls;
   return ls;
 }
+int &stencil_block_cap() {
+  static thread_local int cap = kDefaultStencilCap;
+  return cap;
+}
 
 void launch_to_soa_f64(double2 *d, const double2 *s, const Geom &g, hipStream_t st) {
   EB_LAUNCH(k_to_soa<double2>, dim3(nblocks_for(size_t(g.V) * 12)), dim3(kBlock), 0, st, d, s, g.V);

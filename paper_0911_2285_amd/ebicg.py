@@ -128,6 +128,7 @@ _SIGNATURES = [
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]),
     ("eb_op_device_bytes", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
     ("eb_op_trim", ctypes.c_int, [_P, _P]),
+    ("eb_op_set_grid_cap", ctypes.c_int, [_P, ctypes.c_int32]),
     ("eb_op_batch_tune", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int32), _P, _P]),
     ("eb_op_batch_set_tile", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -385,6 +386,12 @@ def op_device_bytes(op):
     n = ctypes.c_uint64(0)
     _check(lib().eb_op_device_bytes(op.handle, ctypes.byref(n)))
     return n.value
+
+
+def op_set_grid_cap(op, max_blocks):
+    """Cap the grid of the reducing stencil kernels (0 restores the default of 1024 blocks); with a
+    small cap every block loops over several site tiles, the path large lattices take."""
+    _check(lib().eb_op_set_grid_cap(op.handle, int(max_blocks)))
 
 
 def op_trim(op, stream=None):

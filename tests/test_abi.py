@@ -117,6 +117,7 @@ def test_session_and_tuning_calls_reject_null_handles_on_the_host(eb):
     assert L.eb_op_trim(None, None) == -1
     assert L.eb_op_batch_set_tile(None, 1, 4, 0) == -1
     assert L.eb_op_batch_tune(None, 1, None, ctypes.byref(n), None, None) == -1
+    assert L.eb_op_set_grid_cap(None, 4) == -1
     buf = ctypes.create_string_buffer(256)
     L.eb_last_error(buf, 256)
     assert buf.value  # the last call left a message

@@ -1,0 +1,241 @@
+"""GPU parity at the workloads' full sizes and on the grid-stride paths of the solver stencils.
+
+* 16^3 x 32 (the incremental workload): the first eigBiCG solve against the
+  oracle's run of the same solve (Alg. eigBiCG with Alg. BiCG-eigen), read from
+  tests/golden/cfg1_eigbicg_16x16x16x32.json (written by make_cfg1_eigbicg.py,
+  which calls only the oracle).
+* 8^4 with the stencil grid capped at 3 blocks: every block of the reducing
+  stencils loops over several site tiles, the path that lattices beyond
+  262 144 sites take by default; eigBiCG, deflated BiCGStab (full and
+  even-odd) and batched solves against the oracle.
+* 24^3 x 64 (the precision workload, fields beyond the Infinity Cache): one
+  FP64 eigBiCG solve and one deflated BiCGStab solve, each checked with the
+  oracle's D over the whole lattice; FP32- and BF16-inner solves of two more
+  sources, each with its error against an FP64 solution whose residual the
+  oracle's D verified.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov as K
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _ops(U, kappa, dims):
+    V = synth.volume(dims)
+    A = lambda v: W.apply_D(U, v.reshape(V, 4, 3), kappa, dims).ravel()
+    Ad = lambda v: W.apply_Ddag(U, v.reshape(V, 4, 3), kappa, dims).ravel()
+    return A, Ad
+
+
+def _rel_match(a, b):
+    """max over a of min_b |a - b| / |a| (nearest-neighbour relative distance)."""
+    return max(np.min(np.abs(np.asarray(b) - v)) / abs(v) for v in a)
+
+
+def _oracle_rel_resid(A, b, x):
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(b - A(np.asarray(x).ravel())) / np.linalg.norm(b))
+
+
+# --------------------------------------------------------------------------- 16^3 x 32
+def test_eigbicg_16x32_first_solve_matches_oracle(gpu_lib):
+    import torch
+
+    with open(os.path.join(GOLDEN, "cfg1_eigbicg_16x16x16x32.json")) as f:
+        g = json.load(f)
+    dims, kappa = tuple(g["dims"]), g["kappa"]
+    V = synth.volume(dims)
+    _say("16^3x32 eigBiCG vs oracle: building links")
+    U = synth.random_su3_links(dims, g["eps"], g["gauge_seed"])
+    b_np = synth.z2_source(V, g["rhs_seed"])
+    op = gpu_lib.op_create(U, kappa, dims, bc_t=g["bc_t"], defl_capacity=g["nev"])
+    b = torch.from_numpy(b_np).to("cuda:0")
+    x = torch.zeros_like(b)
+    st, ritz = gpu_lib.eigbicg_solve(op, b, x, nev=g["nev"], m=g["m"], tol=g["tol"])
+    torch.cuda.synchronize()
+    _say("gpu", st["iters"], "iterations,", st["window_restarts"], "restarts; oracle", g["iters"], g["restarts"])
+    assert abs(st["iters"] - g["iters"]) <= 1
+    assert st["window_restarts"] == g["restarts"]
+    A, _ = _ops(U, kappa, dims)
+    xg = x.cpu().numpy().ravel()
+    tr = _oracle_rel_resid(A, b_np, xg)
+    _say("true residual (oracle D)", tr)
+    assert tr <= 1e-10
+    # the solution at the stored sample entries: both solves reach 1e-10, and
+    # ||x_gpu - x_oracle|| / ||x|| <= ||D|| ||D^-1|| 2e-10 stays below 1e-8 here
+    idx = np.asarray(g["x_sample_index"])
+    xs = np.asarray(g["x_sample"]) @ np.array([1, 1j])
+    err = np.linalg.norm(xg[idx] - xs) / np.linalg.norm(xs)
+    _say("solution at sampled entries, rel. diff", err, "; ||x|| gpu", np.linalg.norm(xg), "oracle", g["x_norm"])
+    assert err < 1e-8
+    assert abs(np.linalg.norm(xg) - g["x_norm"]) / g["x_norm"] < 1e-8
+    # Ritz values: converged ones (right and left residuals <= 1e-6 max(|theta|, 1e-3))
+    # to 1e-8 relative; the others are reported, and must agree to 1e-6
+    lam = np.asarray(g["ritz"]) @ np.array([1, 1j])
+    conv = [max(r, l) <= 1e-6 * max(abs(t), 1e-3) for t, r, l in zip(lam, g["ritz_res_right"], g["ritz_res_left"])]
+    d = [np.min(np.abs(ritz - t)) / abs(t) for t in lam]
+    for t, dd, c, r in zip(lam, d, conv, g["ritz_res_right"]):
+        _say(f"  oracle {t:.10f}  rel diff {dd:.2e}  ritz residual {r:.2e}  {'converged' if c else ''}")
+    for dd, c in zip(d, conv):
+        assert dd < (1e-8 if c else 1e-6)
+    assert _rel_match(ritz, lam) < 1e-6
+
+
+# --------------------------------------------------------------------------- grid-stride paths
+@pytest.fixture(scope="module")
+def lat8(gpu_lib):
+    dims, kappa = (8, 8, 8, 8), 0.12
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(5))
+    return dims, kappa, U
+
+
+def test_grid_stride_loops_match_oracle(gpu_lib, lat8):
+    """8^4 (16 tiles of 256 sites) with the reducing stencils capped at 3 blocks."""
+    import torch
+
+    dims, kappa, U = lat8
+    V = synth.volume(dims)
+    A, Ad = _ops(U, kappa, dims)
+    B = [synth.z2_source(V, synth.rhs_seed(5, i)) for i in range(6)]
+    orc = K.eigbicg(A, Ad, B[0].ravel(), np.zeros(12 * V, complex), 5, 24, 1e-10)
+    ops = {}
+    for cap in (3, 0):
+        op = gpu_lib.op_create(U, kappa, dims, defl_capacity=10)
+        gpu_lib.op_set_grid_cap(op, cap)
+        ops[cap] = op
+    res = {}
+    for cap, op in ops.items():
+        b = torch.from_numpy(B[0]).to("cuda:0")
+        x = torch.zeros_like(b)
+        st, ritz = gpu_lib.eigbicg_solve(op, b, x, nev=5, m=24, tol=1e-10)
+        tr = _oracle_rel_resid(A, B[0], x.cpu().numpy())
+        _say(f"cap {cap}: eigBiCG {st['iters']} it, {st['window_restarts']} restarts, residual {tr:.2e}; "
+             f"oracle {orc.iters} it, {len(orc.restarts)} restarts; Ritz rel {_rel_match(ritz, orc.lam):.2e}")
+        assert abs(st["iters"] - orc.iters) <= 1 and st["window_restarts"] == len(orc.restarts)
+        assert tr <= 1e-10
+        assert _rel_match(ritz, orc.lam) < 1e-8 and _rel_match(orc.lam, ritz) < 1e-8
+        res[cap] = {"x": x.cpu().numpy()}
+        # deflated BiCGStab one at a time (FP64) and batched (FP32 inner, k = 4)
+        b1 = torch.from_numpy(B[1]).to("cuda:0")
+        x1 = torch.zeros_like(b1)
+        st1 = gpu_lib.deflated_bicg_solve(op, b1, x1, tol=1e-10)
+        tr1 = _oracle_rel_resid(A, B[1], x1.cpu().numpy())
+        Bb = torch.stack([torch.from_numpy(B[i]) for i in range(2, 6)]).to("cuda:0")
+        Xb = torch.zeros_like(Bb)
+        stb = gpu_lib.deflated_bicg_solve(op, Bb, Xb, tol=1e-10, inner="fp32", nrhs=4, batch=4)
+        trb = [_oracle_rel_resid(A, B[2 + i], Xb[i].cpu().numpy()) for i in range(4)]
+        _say(f"cap {cap}: BiCGStab {st1['iters']} it residual {tr1:.2e}; batched FP32 {stb['iters']} it, "
+             f"residuals {max(trb):.2e}")
+        assert tr1 <= 1e-10 and max(trb) <= 1e-10
+        res[cap].update(it1=st1["iters"], itb=stb["iters"], x1=x1.cpu().numpy())
+    # the capped and uncapped launches sum their partials in different orders only
+    assert abs(res[3]["it1"] - res[0]["it1"]) <= 1
+    d = np.linalg.norm(res[3]["x"] - res[0]["x"]) / np.linalg.norm(res[0]["x"])
+    _say("capped vs default eigBiCG solution rel diff", d)
+    assert d < 1e-9
+
+
+def test_grid_stride_loops_even_odd(gpu_lib, lat8):
+    """The even-odd operator's hops with the grid capped: eigBiCG and deflated solves on Dhat."""
+    import torch
+
+    dims, kappa, U = lat8
+    V = synth.volume(dims)
+    A, _ = _ops(U, kappa, dims)
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=8, eo=True)
+    gpu_lib.op_set_grid_cap(op, 3)
+    for i, (inner, batch) in enumerate([("eig", 1), ("fp64", 1), ("bf16", 2)]):
+        bn = [synth.z2_source(V, synth.rhs_seed(6, 2 * i + c)) for c in range(batch)]
+        b = torch.stack([torch.from_numpy(v) for v in bn]).to("cuda:0")
+        x = torch.zeros_like(b)
+        if inner == "eig":
+            st, _ = gpu_lib.eigbicg_solve(op, b[0], x[0], nev=4, m=16, tol=1e-10)
+        else:
+            st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, inner=inner, nrhs=batch, batch=batch)
+        tr = max(_oracle_rel_resid(A, bn[c], x[c].cpu().numpy()) for c in range(batch))
+        _say(f"even-odd, cap 3, {inner}: {st['iters']} it, full residual (oracle D) {tr:.2e}")
+        assert tr <= 1e-10
+
+
+# --------------------------------------------------------------------------- 24^3 x 64
+@pytest.fixture(scope="module")
+def lat24(gpu_lib):
+    dims, kappa = (24, 24, 24, 64), 0.123
+    _say("24^3x64: building links")
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(2))
+    op = gpu_lib.op_create(U, kappa, dims, defl_capacity=10)
+    yield dims, kappa, U, op
+    gpu_lib.op_destroy(op)
+
+
+def test_24x64_fp64_solves_checked_with_oracle(gpu_lib, lat24):
+    """One FP64 eigBiCG solve (it grows the space) and one deflated BiCGStab solve; each
+    solution's residual with the oracle's D over the whole lattice."""
+    import torch
+
+    dims, kappa, U, op = lat24
+    V = synth.volume(dims)
+    A, _ = _ops(U, kappa, dims)
+    b0 = synth.z2_source(V, synth.rhs_seed(2, 0))
+    x = torch.zeros(V, 4, 3, dtype=torch.complex128, device="cuda:0")
+    st, ritz = gpu_lib.eigbicg_solve(op, torch.from_numpy(b0).to("cuda:0"), x, nev=10, m=40, tol=1e-10)
+    tr = _oracle_rel_resid(A, b0, x.cpu().numpy())
+    _say(f"24^3x64 eigBiCG: {st['iters']} it, {st['window_restarts']} restarts, library residual "
+         f"{st['true_rel_resid']:.2e}, oracle D residual {tr:.2e}")
+    assert tr <= 1e-10 and gpu_lib.defl_info(op)[0] == 10
+    assert abs(tr - st["true_rel_resid"]) <= 1e-3 * tr + 1e-14
+    b1 = synth.z2_source(V, synth.rhs_seed(2, 1))
+    x1 = torch.zeros_like(x)
+    st1 = gpu_lib.deflated_bicg_solve(op, torch.from_numpy(b1).to("cuda:0"), x1, tol=1e-10)
+    tr1 = _oracle_rel_resid(A, b1, x1.cpu().numpy())
+    _say(f"24^3x64 deflated BiCGStab: {st1['iters']} it, library residual {st1['true_rel_resid']:.2e}, "
+         f"oracle D residual {tr1:.2e}")
+    assert tr1 <= 1e-10
+    assert abs(tr1 - st1["true_rel_resid"]) <= 1e-3 * tr1 + 1e-14
+
+
+def test_24x64_mixed_precision_error_per_solve(gpu_lib, lat24):
+    """Two sources solved with FP32- and with BF16-stored inner iterations (FP64 refinement to
+    1e-10, batched and one at a time); each solution's error against an FP64 solution (tol 1e-12)
+    whose residual the oracle's D verified.  Bound: D e = r_ref - r, so ||e|| / ||x|| <=
+    ||D|| ||D^-1|| (1e-10 + 1e-12) with ||D|| <= 1 + 8 kappa < 2; 1e-8 holds while the smallest
+    singular value of D exceeds 0.02 (the lowest |lambda| of these links is ~0.07)."""
+    import torch
+
+    dims, kappa, U, op = lat24
+    V = synth.volume(dims)
+    A, _ = _ops(U, kappa, dims)
+    bn = [synth.z2_source(V, synth.rhs_seed(2, 2 + i)) for i in range(2)]
+    B = torch.stack([torch.from_numpy(v) for v in bn]).to("cuda:0")
+    Xref = torch.zeros_like(B)
+    gpu_lib.deflated_bicg_solve(op, B, Xref, tol=1e-12, nrhs=2, batch=1)
+    xref = Xref.cpu().numpy()
+    for i in range(2):
+        r = _oracle_rel_resid(A, bn[i], xref[i])
+        _say(f"FP64 reference {i}: oracle D residual {r:.2e}")
+        assert r <= 2e-12
+    for inner in ("fp32", "bf16"):
+        for batch in (2, 1):
+            X = torch.zeros_like(B)
+            st = gpu_lib.deflated_bicg_solve(op, B, X, tol=1e-10, inner=inner, nrhs=2, batch=batch)
+            xs = X.cpu().numpy()
+            for i in range(2):
+                err = np.linalg.norm(xs[i] - xref[i]) / np.linalg.norm(xref[i])
+                r = _oracle_rel_resid(A, bn[i], xs[i])
+                _say(f"{inner} inner, batch {batch}, source {i}: oracle D residual {r:.2e}, "
+                     f"error vs FP64 {err:.2e} ({st['outer_steps']} refinement steps)")
+                assert r <= 1e-10 and err <= 1e-8

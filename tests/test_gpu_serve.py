@@ -138,7 +138,7 @@ def test_session_edge_cases(gpu_lib, cfg0):
     res = _drain(short, 1)
     assert res[5][0] == "EB_ERR_NOT_CONVERGED" and res[5][1]["iters"] >= 3
     short.close()
-    for bad in (dict(slots=3), dict(chunk=0), dict(tol=0.0)):
+    for bad in (dict(slots=3), dict(chunk=0), dict(tol=0.0), dict(inner_tol=1.0), dict(inner_tol=float("nan"))):
         kw = dict(slots=2, inner="fp32", tol=1e-10, chunk=4)
         kw.update(bad)
         with pytest.raises(gpu_lib.EbicgError) as e:
