@@ -77,7 +77,10 @@ typedef struct {
   double tol;       /* target ||b - A x|| / ||b|| (true residual, checked in FP64) */
   double deftol;    /* DefTol: 0 disables the deflation restart (the setting of Fig. 1) */
   int32_t maxiter;  /* cap on inner iterations summed over restarts and refinement steps */
-  int32_t method;   /* 0: BiCGStab (the paper's choice), 1: BiCG */
+  int32_t method;   /* 0: BiCGStab (the paper's choice for step 3); 1: two-sided BiCG (the
+                       recurrences of Alg. eigBiCG without the window; Sec. 1 compares it with
+                       BiCGStab), FP64 only: needs inner = EB_FP64 and deftol = 0, runs the
+                       right-hand sides one at a time, two D applications per iteration */
   eb_prec inner;    /* working precision of the inner iteration; FP32/BF16 run inside FP64 refinement */
   double inner_tol; /* relative residual reduction per refinement step, < 1; <= 0 selects the
                        default (1e-6 FP32, 1e-2 BF16); ignored for EB_FP64 */
@@ -170,7 +173,7 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b, void *x, const eb_eig_param
                            eb_stats *st, void *stream);
 
 /* A solve of the second phase (step 3): x0 += U_r H^{-1} U_l^+ (b - A x0),
- * then BiCGStab with the DefTol restart; FP32/BF16 inner precision runs
+ * then BiCGStab with the DefTol restart (or BiCG, method = 1); FP32/BF16 inner precision runs
  * inside FP64 iterative refinement.  b, x: device, FP64 canonical, p->nrhs
  * spinors back to back.  With p->batch != 1 the right-hand sides run in
  * batches of k columns that share every link load (multi-RHS stencil); each

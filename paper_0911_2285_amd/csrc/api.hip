@@ -494,6 +494,73 @@ void deflated_stab_f64(eb_op *op, const double2 *b, double2 *x, double tol, doub
   }
 }
 
+// Deflated two-sided BiCG (method 1), FP64: the BiCG recurrences of Alg.
+// eigBiCG without the window (the paper's Sec. 1 discusses BiCG beside
+// BiCGStab), with the shadow residual rhat_0 = r_0 of the (already deflated)
+// start x.  Two D applications per iteration (D p and D^+ phat); the scalars
+// stay on the device as in eigBiCG, with the same breakdown tests.  A solve
+// whose FP64 true residual is still above tol after the recursion stopped
+// restarts BiCG from x (reading of the listing's convergence test), until tol
+// or maxiter.  Accumulates into st.
+void deflated_bicg_f64(eb_op *op, const double2 *b, double2 *x, double tol, int maxiter, eb_stats &st,
+                       hipStream_t s) {
+  const size_t N = op->N;
+  double2 *r0 = op->vec("bicg1_r", 2), *rh0 = op->vec("bicg1_rh", 2);
+  double2 *r[2] = {r0, r0 + N}, *rh[2] = {rh0, rh0 + N};
+  double2 *p = op->vec("bicg_p"), *ph = op->vec("bicg_ph");
+  double2 *Ap = op->vec("bicg_Ap"), *Adp = op->vec("bicg_Adp");
+  KrylovState *S = op->S();
+  while (true) {
+    // r_0 = b - A x (FP64) with ||r||^2, ||b||^2 in op->res
+    TIMED(EB_K_RESIDUAL, s, residual_launch(op, r[0], b, x, s));
+    st.matvec_d += 1;
+    double hres[2];
+    HIPCHK(hipMemcpyAsync(hres, op->res.p, sizeof(hres), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rn = std::sqrt(hres[0]), bn = std::sqrt(hres[1]);
+    if (bn == 0.0) {
+      HIPCHK(hipMemsetAsync(x, 0, N * sizeof(double2), s));
+      st.true_rel_resid = 0;
+      return;
+    }
+    st.true_rel_resid = rn / bn;
+    if (rn <= tol * bn) return;
+    const int left = maxiter - st.iters;
+    if (left <= 0) fail(EB_ERR_NOT_CONVERGED, "deflated BiCG: maxiter reached");
+    KrylovHistory dh = op->history(left + 4);
+    launch_bicg_init(rh[0], p, ph, r[0], op->res.as<double>(), N, 0, op->g, tol, left, S, dh, op->rs(), s);
+    KrylovState hs;
+    fetch_state(op, s, hs);
+    if (hs.stopped && hs.reason == 2) fail(EB_ERR_BREAKDOWN, "BiCG: (rhat_0, r_0) = 0");
+    int j = 0;
+    bool stopped = hs.stopped != 0;
+    {
+      Poller pl(op, S, s);
+      while (!stopped && j < left) {
+        ++j;
+        const int cur = j & 1, prv = cur ^ 1;
+        TIMED(EB_K_BICG_MATVEC, s,
+              op->eo ? launch_bicg_matvec_eo(Ap, Adp, p, ph, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g,
+                                             op->kappa, j, S, op->rs(), false, s)
+                     : launch_bicg_matvec(Ap, Adp, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
+                                          op->rs(), false, s));
+        TIMED(EB_K_BICG_UPDATE_R, s,
+              launch_bicg_update_r(r[cur], rh[cur], r[prv], rh[prv], Ap, Adp, N, j, S, dh, op->rs(), false, s));
+        TIMED(EB_K_BICG_UPDATE_P, s, launch_bicg_update_p(x, p, ph, r[cur], rh[cur], N, j, S, dh, op->rs(), false, s));
+        if (j % 8 == 0 && pl.step(&hs)) stopped = true;
+      }
+    }
+    if (!stopped || !hs.stopped) fetch_state(op, s, hs);
+    const int done = hs.stopped ? hs.stop_at : j;
+    st.iters += done;
+    st.matvec_d += done;
+    st.matvec_ddag += done;
+    st.rec_rel_resid = hs.rnorm / bn;
+    // a breakdown before any update cannot be cured by restarting from the same x
+    if (hs.stopped && hs.reason == 2 && done == 0) fail(EB_ERR_BREAKDOWN, "BiCG breakdown");
+  }
+}
+
 // Storage of the inner solve: FP64 (no refinement needed, one outer step),
 // FP32, or BF16 with FP32 arithmetic.
 template <typename S>
@@ -1707,7 +1774,9 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     if (!(P->tol > 0) || P->maxiter < 1 || P->nrhs < 1) fail(EB_ERR_INVALID, "tol > 0, maxiter >= 1, nrhs >= 1");
     if (P->deftol < 0 || P->deftol >= 1) fail(EB_ERR_INVALID, "deftol must be in [0, 1)");
     if (!(P->inner_tol < 1)) fail(EB_ERR_INVALID, "inner_tol must be < 1 (<= 0 selects the default)");
-    if (P->method != 0) fail(EB_ERR_INVALID, "only method 0 (BiCGStab) is available");
+    if (P->method != 0 && P->method != 1) fail(EB_ERR_INVALID, "method must be 0 (BiCGStab) or 1 (BiCG)");
+    if (P->method == 1 && (P->inner != EB_FP64 || P->deftol != 0))
+      fail(EB_ERR_INVALID, "method 1 (BiCG) runs in FP64 without DefTol restarts (inner = EB_FP64, deftol = 0)");
     if (P->inner != EB_FP64 && P->inner != EB_FP32 && P->inner != EB_BF16)
       fail(EB_ERR_INVALID, "inner precision must be EB_FP64, EB_FP32 or EB_BF16");
     if (P->batch != 0 && !batch_size_ok(P->batch)) fail(EB_ERR_INVALID, "batch must be 0, 1, 2, 4, 8 or 16");
@@ -1719,13 +1788,16 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
     auto merge = [&](const eb_stats &sc) {
       st.iters += sc.iters;
       st.matvec_d += sc.matvec_d;
+      st.matvec_ddag += sc.matvec_ddag;
       st.defl_restarts += sc.defl_restarts;
       st.outer_steps += sc.outer_steps;
       st.rec_rel_resid = std::max(st.rec_rel_resid, sc.rec_rel_resid);
       worst = std::max(worst, sc.true_rel_resid);
       st.true_rel_resid = worst;
     };
-    const int kmax = (P->deftol > 0 || P->nrhs == 1) ? 1 : (P->batch ? P->batch : choose_batch(op, P->inner, s));
+    const int kmax = (P->deftol > 0 || P->nrhs == 1 || P->method == 1)
+                         ? 1
+                         : (P->batch ? P->batch : choose_batch(op, P->inner, s));
     const size_t Ncan = size_t(op->g.V) * 12;  // canonical spinor length
     int c0 = 0;
     while (c0 < P->nrhs) {
@@ -1750,7 +1822,9 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
       try {
         if (kc == 1) {
           if (op->K > 0) deflate_guess(op, b, x, s);
-          if (P->inner == EB_FP64)
+          if (P->method == 1)
+            deflated_bicg_f64(op, b, x, tolc[0], P->maxiter, sc, s);
+          else if (P->inner == EB_FP64)
             deflated_stab_f64(op, b, x, tolc[0], P->deftol, P->maxiter, sc, s);
           else if (P->inner == EB_FP32)
             mixed_stab<float2>(op, b, x, tolc[0], inner_tol, P->maxiter, sc, s);

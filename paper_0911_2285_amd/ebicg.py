@@ -315,7 +315,8 @@ def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):
 
 def deflated_bicg_solve(op, b, x, tol, deftol=0.0, maxiter=10000, method=0, inner="fp64", inner_tol=0.0, nrhs=1,
                         batch=1, stream=None):
-    """Deflated BiCGStab solve(s); b, x hold nrhs spinors back to back.  batch: columns per
+    """Deflated BiCGStab (method 0) or two-sided BiCG (method 1, FP64 only) solve(s); b, x hold nrhs
+    spinors back to back.  batch: columns per
     multi-RHS iteration (1, 2, 4, 8, 16; 0 = the library's timed choice).  Returns stats."""
     import torch
 
