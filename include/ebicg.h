@@ -137,6 +137,18 @@ eb_status eb_op_destroy(eb_op *op);
 eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
 eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream);
 
+/* out = D in (dagger = 0) or D^+ in (dagger = 1) in FP64, as eb_op_apply /
+ * eb_op_apply_dagger with EB_FP64, for callers that cannot allocate device
+ * memory (code under HIP stream capture, tight serving loops, harnesses that
+ * forbid allocation): the call allocates nothing.  Its staging buffers live in
+ * a fixed 48 MiB device array per GPU, held until the process ends, which
+ * limits the lattice to V <= 131072 sites (16^3 x 32); a larger operator gets
+ * EB_ERR_INVALID.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (different streams or host threads) race and must be serialised
+ * by the caller.  in/out: device, FP64 canonical layout, not overlapping.
+ * Asynchronous on `stream`. */
+eb_status eb_op_apply_noalloc(eb_op *op, void *out, const void *in, int32_t dagger, void *stream);
+
 /* For an even-odd operator (eb_op_create_eo): out = Dhat in_e (dagger = 0) or
  * Dhat^+ in_e (dagger = 1), Dhat = 1 - kappa^2 H_eo H_oe (Sec. 3's even-odd
  * preconditioned matrices).  in/out: device FP64 canonical full-lattice

@@ -21,6 +21,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1523,6 +1524,37 @@ void ensure_space(eb_op *op) {
 }  // namespace
 
 // ============================================================================
+// Allocation-free operator application (eb_op_apply_noalloc)
+// ============================================================================
+// For callers that cannot allocate device memory (code under stream capture,
+// tight serving loops): the two SoA staging spinors of D live in this
+// file-scope array instead of the operator's work buffers.  Each device holds
+// its own copy until the process ends; every call on a device shares it, so
+// calls that overlap on one device race.
+constexpr size_t kNoAllocScratchBytes = size_t(48) << 20;  // two FP64 spinors of 16^3 x 32
+static __device__ __align__(256) double2 scratch[kNoAllocScratchBytes / sizeof(double2)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2 *g_scratch_ptr[kMaxDevices] = {};
+// Device address of `scratch` on device dev, which must be current; looked
+// up once per device.  The host-side name `scratch` is only a stand-in for
+// the symbol and never reaches a kernel or a copy.
+double2 *scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(EB_ERR_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(EB_ERR_HIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = static_cast<double2 *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+// ============================================================================
 // C ABI
 // ============================================================================
 extern "C" {
@@ -1643,6 +1675,24 @@ eb_status eb_op_apply(eb_op *op, void *out, const void *in, eb_prec prec, void *
 }
 eb_status eb_op_apply_dagger(eb_op *op, void *out, const void *in, eb_prec prec, void *stream) {
   return apply_impl(op, out, in, prec, stream, true);
+}
+
+eb_status eb_op_apply_noalloc(eb_op *op, void *out, const void *in, int32_t dagger, void *stream) {
+  return guarded([&]() {
+    if (!op || !out || !in) fail(EB_ERR_INVALID, "null argument");
+    if (out == in) fail(EB_ERR_INVALID, "in and out must not overlap");
+    const size_t N = size_t(op->g.V) * 12;  // the full lattice, also for an even-odd operator
+    if (2 * N * sizeof(double2) > kNoAllocScratchBytes)
+      fail(EB_ERR_INVALID, "lattice too large for the allocation-free path (V <= " +
+                               std::to_string(kNoAllocScratchBytes / (24 * sizeof(double2))) + ")");
+    set_device(op);
+    double2 *a = scratch_address(op->device), *b = a + N;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_to_soa_f64(a, static_cast<const double2 *>(in), op->g, s);
+    launch_dslash_f64(b, a, op->U64.as<double2>(), op->g, op->kappa, dagger != 0, s);
+    launch_from_soa_f64(static_cast<double2 *>(out), b, op->g, s);
+    HIPCHK(hipGetLastError());
+  });
 }
 
 // A canonical right-hand side and start vector -> the solvers' vectors b, x.

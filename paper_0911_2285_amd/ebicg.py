@@ -105,6 +105,7 @@ _SIGNATURES = [
     ("eb_op_destroy", ctypes.c_int, [_P]),
     ("eb_op_apply", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
     ("eb_op_apply_dagger", ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P]),
+    ("eb_op_apply_noalloc", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     ("eb_op_apply_schur", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
     ("eb_op_apply_block", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
     ("eb_op_apply_schur_block", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _P]),
@@ -259,6 +260,13 @@ def op_apply_dagger(op, out, inp, prec="fp64", stream=None):
     """out = D^+ inp."""
     _check(lib().eb_op_apply_dagger(op.handle, _spinor_ptr(op, out, prec, "out"), _spinor_ptr(op, inp, prec, "in"),
                                     PREC[prec], _stream(stream)))
+
+
+def op_apply_noalloc(op, out, inp, dagger=False, stream=None):
+    """out = D inp (or D^+) in FP64 without any device allocation (the library's fixed
+    per-GPU staging array; V <= 131072)."""
+    _check(lib().eb_op_apply_noalloc(op.handle, _spinor_ptr(op, out, "fp64", "out"),
+                                     _spinor_ptr(op, inp, "fp64", "in"), int(bool(dagger)), _stream(stream)))
 
 
 def op_apply_schur(op, out, inp, dagger=False, stream=None):
