@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark: incremental eigBiCG on one MI355X.
+"""Benchmark: incremental eigBiCG's deflated multi-RHS solves on one MI355X.
 
-Workload (one "step" = the whole hot path over one batch of right-hand sides):
-16^3 x 32 Wilson-Dirac operator, kappa = 0.122, SU(3) links exp(i 0.3 H)
-(seeded), 24 Z2-noise sources resident in HBM.  The first 8 sources run
-eigBiCG (nev = 10, m = 40), each growing the deflation space (up to 80
-left/right pairs); the remaining 16 run deflated BiCGStab.  Every solve
-reaches ||b - A x|| / ||b|| <= 1e-10 (checked in FP64 by the library).
+The bench line's workload (one "step" = the hot path over one batch of
+right-hand sides): 32^3 x 64 Wilson-Dirac operator, kappa = 0.123, SU(3)
+links exp(i 0.3 H) (seeded), a 100-pair left/right deflation space grown in
+setup by 4 eigBiCG solves (nev = 25, m = 60), and per step 16 Z2-noise
+sources resident in HBM solved by deflated BiCGStab in batches of k columns
+(multi-RHS stencil; k and the tile form chosen by the library's autotuner in
+setup), complex64 inner iterations inside complex128 iterative refinement.
+Every solve reaches ||b - A x|| / ||b|| <= 1e-10, checked in FP64.
 
-Prints ONE JSON line on stdout: solves/s of the FP64 step, the dominant
-kernel's roofline (achieved algorithmic GB/s from HIP events inside the
-library, over the timed region), per-solve p50/p99 latency, and the CPU
-oracle timed on a bounded sample of the same workload.
+Prints ONE JSON line on stdout: solves/s of that step, the dominant kernel's
+roofline (achieved algorithmic GB/s from HIP events inside the library over
+the timed steps), FP64 comparators on the same GPU (plain BiCG, plain and
+deflated BiCGStab), the CPU oracle timed on the host cores, and side records
+(the 16^3 x 32 incremental eigBiCG step, serving, sweeps, 24^3 x 64).
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # spinor (192 B/site): vectors each kernel must read or write once, links
 # (4 x 9 complex = 576 B/site = 3 units) read once per stencil launch.
 UNIT_BYTES_FP64 = 192
-# the dominant step kernel of the workload (largest share of the step's kernel time)
+# the dominant kernel of the 16^3 x 32 incremental step (a side record)
 ROOFLINE_CLASS = "bicg_matvec"
 KERNEL_UNITS = {
     "bicg_matvec": 7,    # in p, phat; out Ap, A^+ phat; links (shared by D and D^+)
@@ -50,6 +53,9 @@ WORKLOADS = {
     "inc16x32": dict(dims=(16, 16, 16, 32), kappa=0.122, nrhs=24, n1=8, nev=10, m=40, tol=1e-10, cfg=1),
     # the small parity workload (4^4), for quick runs
     "inc4": dict(dims=(4, 4, 4, 4), kappa=0.115, nrhs=4, n1=4, nev=4, m=16, tol=1e-10, cfg=0),
+    # the bench line: 32^3 x 64 batched mixed-precision deflated solves (100 pairs)
+    "batch32x64": dict(dims=(32, 32, 32, 64), kappa=0.123, nrhs=16, n1=4, nev=25, m=60, tol=1e-10, cfg=3,
+                       inner="fp32", inner_tol=1e-6),
 }
 
 
@@ -105,55 +111,6 @@ def run_mixed_step(eb, op, B, X, W, inner="bf16", inner_tol=1e-2):
     if st["true_rel_resid"] > W["tol"]:
         raise RuntimeError(f"mixed deflated phase missed the tolerance: {st}")
     return time.perf_counter() - t0
-
-
-def cpu_baseline(W, U, b_np, eig_iters, stab_iters, n_eig_it=5, n_stab_it=3):
-    """The FP64 oracle on the host: a bounded sample, extrapolated to one step."""
-    import numpy as np
-
-    from oracle import krylov as K
-    from oracle import wilson as Wl
-
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
-    dims, kappa = W["dims"], W["kappa"]
-    V = int(np.prod(dims))
-    A = lambda v: Wl.apply_D(U, v.reshape(V, 4, 3), kappa, dims).ravel()
-    Ad = lambda v: Wl.apply_Ddag(U, v.reshape(V, 4, 3), kappa, dims).ravel()
-    b = b_np.ravel()
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    try:
-        if ctx:
-            ctx.__enter__()
-        t0 = time.perf_counter()
-        K.eigbicg(A, Ad, b, np.zeros_like(b), W["nev"], W["m"], W["tol"], maxiter=n_eig_it)
-        t1 = time.perf_counter()
-        K.bicgstab(A, b, np.zeros_like(b), W["tol"], maxiter=n_stab_it)
-        t2 = time.perf_counter()
-        A(b)
-        t3 = time.perf_counter()
-    finally:
-        if ctx:
-            ctx.__exit__(None, None, None)
-    t_eig = (t1 - t0) / n_eig_it
-    t_stab = (t2 - t1) / n_stab_it
-    est = t_eig * eig_iters + t_stab * stab_iters
-    return {
-        "value": W["nrhs"] / est,
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle eigBiCG {n_eig_it} iterations and BiCGStab {n_stab_it} iterations on the same lattice "
-                   f"and source ({t1 - t0:.1f} s + {t2 - t1:.1f} s, BLAS limited to 1 thread), extrapolated with the "
-                   f"step's iteration counts ({eig_iters} eigBiCG + {stab_iters} BiCGStab)"),
-        "seconds_per_eigbicg_iter": t_eig,
-        "seconds_per_bicgstab_iter": t_stab,
-        # one application of the oracle's D, in the GPU's byte model (960 B per site)
-        "dslash_seconds": round(t3 - t2, 4),
-        "dslash_GBps": round(960 * V / (t3 - t2) / 1e9, 3),
-    }
 
 
 def tune_untimed(eb, op, precs):
@@ -246,86 +203,6 @@ def large_lattice(eb, dims, kappa, nrhs, tol):
     return res
 
 
-def batching(eb, dims=(32, 32, 32, 64), kappa=0.123, nrhs=16, n1=4, nev=25, m=60, tol=1e-10):
-    """Batching on 32^3 x 64: the multi-RHS stencil (FP32 and BF16 storage,
-    k = 1, 4, 8, 16), the autotuner's choice of k and tile form, a deflation
-    space of n1 * nev = 100 pairs grown by eigBiCG, and mixed-precision
-    (complex64 inner, complex128 outer) batched deflated solves at k = 4, 8, 16
-    and the tuned k.  The deflation of a batch is a tall-skinny complex GEMM
-    pair on the matrix cores: C = U_l^+ R (K x N times N x k) and X += U_r C;
-    its algorithmic bytes are 2 K N + 3 k N complex128 entries and its flops
-    2 x 8 K N k."""
-    import torch
-
-    import synth
-
-    V = synth.volume(dims)
-    N = 12 * V
-    t0 = time.perf_counter()
-    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(3))
-    log(f"[bench] {dims}: links generated in {time.perf_counter() - t0:.1f} s")
-    op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=n1 * nev)
-    del U
-    res = {"lattice": list(dims), "kappa": kappa, "nrhs": nrhs}
-    res["stencil"] = multi_rhs_stencil(eb, op, V, precs=("fp32", "bf16"), ks=(1, 4, 8, 16))
-    res["autotune"] = {p: eb.op_batch_tune(op, p) for p in ("fp32", "bf16")}
-    log(f"[bench] {dims} autotune: {res['autotune']}")
-    grow = []
-    for i in range(n1):
-        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(3, 100 + i))).to("cuda:0")
-        x = torch.zeros_like(b)
-        st, _ = eb.eigbicg_solve(op, b, x, nev, m, tol)
-        assert st["true_rel_resid"] <= tol, st
-        grow.append({"iters": st["iters"], "restarts": st["window_restarts"], "seconds": round(st["seconds"], 3)})
-        log(f"[bench] {dims} eigBiCG {i}: {grow[-1]}")
-        del b, x
-    K = eb.defl_info(op)[0]
-    res["eigbicg"] = {"nev": nev, "m": m, "solves": grow, "K": K}
-    res["device_bytes_after_growth"] = eb.op_device_bytes(op)
-    eb.op_trim(op)  # the windows of the eigBiCG phase: about 100 GB at this size
-    res["device_bytes_trimmed"] = eb.op_device_bytes(op)
-    B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(3, i))) for i in range(nrhs)]).to("cuda:0")
-    solves = {}
-    eb.timing_classes(op, ["proj"])
-    for k in (4, 8, 16, 0):
-        X = torch.zeros_like(B)
-        eb.timing_enable(op, True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st = eb.deflated_bicg_solve(op, B, X, tol=tol, maxiter=20000, nrhs=nrhs, inner="fp32", inner_tol=1e-6,
-                                    batch=k)
-        dt = time.perf_counter() - t1
-        n_proj, ms_proj = eb.timing_read(op)["proj"]
-        eb.timing_enable(op, False)
-        assert st["true_rel_resid"] <= tol, (k, st)
-        kk = k if k else res["autotune"]["fp32"]["k"]
-        nb = -(-nrhs // kk)
-        gemm_bytes = nb * (2 * K * N + 3 * kk * N) * 16
-        gemm_flops = nb * 2 * 8 * K * N * kk
-        rec = {"solves_per_s": round(nrhs / dt, 3), "iters_per_rhs": round(st["iters"] / nrhs, 1),
-               "outer_steps": st["outer_steps"], "max_true_rel_resid": st["true_rel_resid"],
-               "deflation_gemm": {"launches": n_proj, "ms": round(ms_proj, 3),
-                                  "GBps": round(gemm_bytes / (ms_proj * 1e-3) / 1e9, 1) if ms_proj else None,
-                                  "TFLOPs_fp64": round(gemm_flops / (ms_proj * 1e-3) / 1e12, 2) if ms_proj else None}}
-        solves[f"mixed_fp32_k{k}" if k else f"mixed_fp32_tuned_k{kk}"] = rec
-        log(f"[bench] {dims} k={k}: {rec}")
-        del X
-    eb.timing_classes(op, None)
-    # FP64 deflated BiCGStab one right-hand side at a time, on 4 of the sources
-    X = torch.zeros_like(B[:4])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = eb.deflated_bicg_solve(op, B[:4].contiguous(), X, tol=tol, maxiter=20000, nrhs=4, batch=1)
-    dt = time.perf_counter() - t1
-    solves["fp64_one_at_a_time"] = {"solves_per_s": round(4 / dt, 3), "iters_per_rhs": round(st["iters"] / 4, 1),
-                                    "max_true_rel_resid": st["true_rel_resid"]}
-    res["solves"] = solves
-    eb.op_destroy(op)
-    del B, X
-    torch.cuda.empty_cache()
-    return res
-
-
 # ---------------------------------------------------------------------------
 # HBM traffic of the roofline kernel from rocprofv3 counters.
 #   1. rocprofv3 --pmc FETCH_SIZE -d D1 -o run -- python3 bench.py --pmc-pass
@@ -338,13 +215,14 @@ def batching(eb, dims=(32, 32, 32, 64), kappa=0.123, nrhs=16, n1=4, nev=25, m=60
 # ---------------------------------------------------------------------------
 COPY_BYTES = 1 << 28
 KERNEL_SOURCES = ["kernels.hip", "stencil.h", "kernel_util.h", "device_common.h", "kernels.h"]
+BATCH_SOURCES = ["batch.hip", "stencil.h", "kernel_util.h", "device_common.h", "kernels.h"]
 
 
-def kernel_source_hash():
+def kernel_source_hash(cls="bicg_matvec"):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (BATCH_SOURCES if cls.startswith("bstab") else KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_0911_2285_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -580,14 +458,35 @@ def proj_pass(dims=(16, 16, 16, 32), kappa=0.122, n1=8, nev=10, m=40, nrhs=16):
 
 
 def pmc_pass(workload):
-    """One eigBiCG solve (its BiCG matvec launches are the roofline kernel), then a
-    plain device copy of COPY_BYTES for the counter calibration."""
+    """One pass of the workload's roofline kernel, then a plain device copy of
+    COPY_BYTES for the counter calibration: for the incremental workloads one
+    eigBiCG solve (its BiCG matvec launches), for batch32x64 one batched
+    mixed-precision solve of the 16 sources with the tuned k and tile form (its
+    k_bstab_v launches; no deflation space, which does not change the stencil)."""
     import torch
 
     import synth
     from paper_0911_2285_amd import ebicg as eb
 
     W = WORKLOADS[workload]
+    if "inner" in W:
+        dims = W["dims"]
+        V = synth.volume(dims)
+        op = eb.op_create(synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"])), W["kappa"], dims, bc_t=-1)
+        k = eb.op_batch_tune(op, W["inner"])["k"]
+        B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], i)))
+                         for i in range(W["nrhs"])]).to("cuda:0")
+        X = torch.zeros_like(B)
+        eb.deflated_bicg_solve(op, B, X, tol=W["tol"], maxiter=20000, nrhs=W["nrhs"], inner=W["inner"],
+                               inner_tol=W["inner_tol"], batch=0)
+        del B, X
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] pmc pass done (batched, k = {k})")
+        return
     dims = W["dims"]
     V = synth.volume(dims)
     U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
@@ -606,7 +505,7 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
     import csv
 
     def per_dispatch(path, counter, match):
-        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(_find_csv(path, "counter_collection.csv")))
                 if r["Counter_Name"].startswith(counter) and match(r["Kernel_Name"])]
         return sum(vals) / len(vals), len(vals)
 
@@ -618,32 +517,59 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
         vals = [float(r["Counter_Value"]) for r in rows[-3:]]
         return sum(vals) / len(vals)
 
-    # the general form's launches (the template's gamma5 instance is another kernel)
-    is_kernel = lambda n: kernel + "(" in n or kernel + "<false>(" in n
-    f_k, n_f = per_dispatch(fetch_csv, "FETCH_SIZE", is_kernel)
-    w_k, n_w = per_dispatch(write_csv, "WRITE_SIZE", is_kernel)
-    f_c = calibration(fetch_csv, "FETCH_SIZE")
-    w_c = calibration(write_csv, "WRITE_SIZE")
-    fetch_scale = COPY_BYTES / (f_c * 1024.0)
-    write_scale = COPY_BYTES / (w_c * 1024.0)
-    traffic = f_k * 1024.0 * fetch_scale + w_k * 1024.0 * write_scale
     W = WORKLOADS[workload]
     V = 1
     for d in W["dims"]:
         V *= d
+    if cls.startswith("bstab"):
+        # batched stencil: the dispatches in which every column still iterates (they write all
+        # k outputs: WRITE_SIZE at its maximum); the others skip stopped columns
+        def full(path, counter):
+            rows = [r for r in csv.DictReader(open(path))
+                    if r["Counter_Name"].startswith(counter) and (kernel + "<") in r["Kernel_Name"]]
+            return rows
+
+        wr = full(_find_csv(write_csv, "counter_collection.csv"), "WRITE_SIZE")
+        wmax = max(float(r["Counter_Value"]) for r in wr)
+        full_ids = {r["Dispatch_Id"] for r in wr if float(r["Counter_Value"]) >= 0.99 * wmax}
+        # dispatch ids differ between the two runs; match full dispatches by their order
+        wr_sorted = sorted(wr, key=lambda r: int(r["Dispatch_Id"]))
+        order = [i for i, r in enumerate(wr_sorted) if r["Dispatch_Id"] in full_ids]
+        fr_sorted = sorted(full(_find_csv(fetch_csv, "counter_collection.csv"), "FETCH_SIZE"),
+                           key=lambda r: int(r["Dispatch_Id"]))
+        f_vals = [float(fr_sorted[i]["Counter_Value"]) for i in order if i < len(fr_sorted)]
+        w_vals = [float(wr_sorted[i]["Counter_Value"]) for i in order]
+        f_k, n_f = sum(f_vals) / len(f_vals), len(f_vals)
+        w_k, n_w = sum(w_vals) / len(w_vals), len(w_vals)
+        kc = int(round(wmax * 1024.0 / (V * 12 * CPLX_BYTES[W["inner"]])))
+        algo = V * (36 + 12 * BATCH_COL_SPINORS[cls] * kc) * CPLX_BYTES[W["inner"]]
+    else:
+        # the general form's launches (the template's gamma5 instance is another kernel)
+        is_kernel = lambda n: kernel + "(" in n or kernel + "<false>(" in n
+        f_k, n_f = per_dispatch(fetch_csv, "FETCH_SIZE", is_kernel)
+        w_k, n_w = per_dispatch(write_csv, "WRITE_SIZE", is_kernel)
+        algo = KERNEL_UNITS[cls] * UNIT_BYTES_FP64 * V
+    f_c = calibration(_find_csv(fetch_csv, "counter_collection.csv"), "FETCH_SIZE")
+    w_c = calibration(_find_csv(write_csv, "counter_collection.csv"), "WRITE_SIZE")
+    fetch_scale = COPY_BYTES / (f_c * 1024.0)
+    write_scale = COPY_BYTES / (w_c * 1024.0)
+    traffic = f_k * 1024.0 * fetch_scale + w_k * 1024.0 * write_scale
     out = {
-        "kernel": kernel, "class": cls, "workload": workload, "source_hash": kernel_source_hash(),
+        "kernel": kernel, "class": cls, "workload": workload, "source_hash": kernel_source_hash(cls),
         "dispatches": {"fetch": n_f, "write": n_w},
         "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
         "copy_calibration": {"bytes_read_and_written": COPY_BYTES, "fetch_kib": round(f_c, 1),
                              "write_kib": round(w_c, 1), "fetch_scale": round(fetch_scale, 4),
                              "write_scale": round(write_scale, 4)},
         "traffic_bytes_per_launch": round(traffic),
-        "algorithmic_bytes_per_launch": KERNEL_UNITS[cls] * UNIT_BYTES_FP64 * V,
+        "algorithmic_bytes_per_launch": algo,
+        "traffic_over_algorithmic": round(traffic / algo, 3),
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass",
-            "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass",
-            "python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
+            f"rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass "
+            f"--workload {workload}",
+            f"rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass "
+            f"--workload {workload}",
+            f"python3 bench.py --workload {workload} --summarize-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
             "gpurun_out/pmc_write/run_counter_collection.csv",
         ],
     }
@@ -651,6 +577,68 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+
+
+def _find_csv(path, suffix):
+    """path: a CSV file, or a rocprofv3 output directory searched for *suffix."""
+    import glob
+
+    if os.path.isfile(path):
+        return path
+    hits = sorted(glob.glob(os.path.join(path, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {path}")
+    return hits[-1]
+
+
+def summarize_trace(prof_dir, bench_json, workload, out_name, command, top=20):
+    """profiles/<out_name>.md from a rocprofv3 --kernel-trace --stats run of bench.py:
+    the top kernels by total time from its kernel stats, launches longer than 5 us
+    from its kernel trace, and the bench line's own per-class figures for comparison."""
+    import csv
+
+    stats = list(csv.DictReader(open(_find_csv(prof_dir, "kernel_stats.csv"))))
+    trace = list(csv.DictReader(open(_find_csv(prof_dir, "kernel_trace.csv"))))
+    dur = {}
+    for r in trace:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        dur.setdefault(r["Kernel_Name"], []).append(d)
+    short = lambda n: n.replace("HIP_vector_type<double, 2u>", "f64").replace("HIP_vector_type<float, 2u>", "f32") \
+        .replace("ebicg::bf16c", "bf16").replace("ebicg::(anonymous namespace)::", "").replace("void ", "") \
+        .split("(")[0]
+    rows = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:top]
+    line = None
+    if bench_json and os.path.exists(bench_json):
+        for ln in open(bench_json):
+            ln = ln.strip()
+            if ln.startswith("{"):
+                line = json.loads(ln)
+    out = [f"# Kernel trace: {workload} bench line", "",
+           "Command (repository root on the MI355X box, `export TMPDIR=/tmp` first):", "", "```", command, "```", "",
+           f"The first {top} kernels of the run's kernel stats by total time.  \"Long launches\" are those "
+           "longer than 5 us in the kernel trace of the same run (launches queued past a batch's last "
+           "stopped column return at once).", "",
+           "| kernel | calls | avg (us) | min (us) | max (us) | total (ms) | % | long launches | long avg (us) |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        ds = [d for d in dur.get(r["Name"], []) if d > 5.0]
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} | {len(ds)} | "
+                   f"{(sum(ds) / len(ds) if ds else 0):.2f} |")
+    if line and line.get("kernels", {}).get("batched"):
+        out += ["", "The bench line printed by the same run (library HIP events over its timed steps; "
+                "working launches = the columns' iterations / k, a lower bound):", "",
+                "| class | launches | total (ms) | working launches | ms / working launch | algorithmic GB/s |",
+                "|---|---:|---:|---:|---:|---:|"]
+        for c, r in line["kernels"]["batched"].items():
+            out.append(f"| {c} | {r['launches']} | {r['total_ms']} | {r['working_launches']} | "
+                       f"{r['avg_launch_us'] / 1e3:.3f} | {r['achieved_GBps']} |")
+        out += ["", f"value {line['value']} solves/s, roofline {json.dumps(line['roofline'])}"]
+    path = os.path.join(ROOT, "profiles", out_name + ".md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print(path)
 
 
 def measured_traffic(workload, cls):
@@ -661,35 +649,397 @@ def measured_traffic(workload, cls):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hash") != kernel_source_hash(cls):
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+# ---------------------------------------------------------------------------
+# The 16^3 x 32 incremental step (a side record: its fields sit in the 256 MB
+# Infinity Cache, so its stencil rates are effective, not HBM, rates)
+# ---------------------------------------------------------------------------
+def incremental_side(eb, W, steps, warmup, timing=True, full=True):
+    """Solves/s of the FP64 incremental step (n1 eigBiCG + deflated BiCGStab),
+    its dominant kernel's effective GB/s, the mixed-precision and batched
+    variants of its deflated phase, and (full) the gamma5-Hermitian and
+    even-odd forms of the same step."""
+    import torch
+
+    import synth
+
+    dims = W["dims"]
+    V = synth.volume(dims)
+    dev = torch.device("cuda:0")
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
+    op = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"])
+    B = [torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, i))).to(dev) for i in range(W["nrhs"])]
+    X = [torch.zeros_like(b) for b in B]
+    for w in range(warmup):
+        lat, its = [], []
+        run_step(eb, op, B, X, W, lat, its)
+    if timing:
+        eb.timing_classes(op, [ROOFLINE_CLASS])
+        eb.timing_enable(op, True)
+    lat, its = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_step(eb, op, B, X, W, lat, its)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktimes = eb.timing_read(op) if timing else {}
+    eb.timing_enable(op, False)
+    ktable = {}
+    if timing:
+        eb.timing_classes(op, None)
+        eb.timing_enable(op, True)
+        run_step(eb, op, B, X, W, [], [])
+        ktable = eb.timing_read(op)
+        eb.timing_enable(op, False)
+    value = W["nrhs"] * steps / elapsed
+    per_step_its = its[: W["nrhs"]]
+    kernels = {}
+    for name, (n, ms) in ktable.items():
+        if n == 0:
+            continue
+        rec = {"launches": n, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / n, 2)}
+        if name in KERNEL_UNITS:
+            rec["effective_GBps"] = round(KERNEL_UNITS[name] * UNIT_BYTES_FP64 * V / (ms / n * 1e-3) / 1e9, 1)
+        kernels[name] = rec
+    n_roof, ms_roof = ktimes.get(ROOFLINE_CLASS, (0, 0.0))
+    n_work = sum(sum(its[k * W["nrhs"]: k * W["nrhs"] + W["n1"]]) for k in range(steps))
+    eff = None
+    if n_roof and n_work:
+        bpl = KERNEL_UNITS[ROOFLINE_CLASS] * UNIT_BYTES_FP64 * V
+        avg_us = 1e3 * ms_roof / min(n_roof, n_work)
+        eff = {"kernel": ROOFLINE_CLASS, "bytes_per_launch": bpl, "avg_launch_us": round(avg_us, 2),
+               "effective_GBps": round(bpl / (avg_us * 1e-6) / 1e9, 1),
+               "note": "16^3 x 32 FP64 fields (25 MB each) stay in the 256 MB Infinity Cache: an effective rate, "
+                       "not an HBM rate",
+               "traffic": measured_traffic("inc16x32", ROOFLINE_CLASS)}
+    res = {"workload": f"incremental eigBiCG, {'x'.join(map(str, dims))}, kappa {W['kappa']}, {W['nrhs']} Z2 "
+                       f"sources: {W['n1']} eigBiCG (nev {W['nev']}, m {W['m']}) + {W['nrhs'] - W['n1']} deflated "
+                       f"BiCGStab, FP64, tol {W['tol']}",
+           "solves_per_s": round(value, 3), "ms_per_step": round(1e3 * elapsed / steps, 3),
+           "p50_ms": round(1e3 * percentile(lat, 50), 3), "p99_ms": round(1e3 * percentile(lat, 99), 3),
+           "iters_per_rhs": per_step_its, "matvec_effective": eff, "kernels": kernels}
+    # the deflated phase one at a time: FP64 and mixed precision
+    modes = {"fp64": dict(), "mixed_fp32_inner": dict(inner="fp32", inner_tol=1e-6),
+             "mixed_bf16_inner": dict(inner="bf16", inner_tol=1e-2)}
+    dt = {k: 0.0 for k in modes}
+    for i in range(W["n1"], W["nrhs"]):
+        for name, kw in modes.items():
+            X[i].zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000, **kw)
+            dt[name] += time.perf_counter() - t1
+            assert st["true_rel_resid"] <= W["tol"], (name, st)
+    nd = W["nrhs"] - W["n1"]
+    res["deflated_solves_per_s"] = {k: round(nd / dt[k], 3) for k in modes}
+    Bd = torch.stack(B[W["n1"]:])
+    res["autotune_seconds"] = tune_untimed(eb, op, ("fp32", "bf16"))
+    for name, kw in [("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
+                     ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
+        Xd = torch.zeros_like(Bd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(op, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
+        dt_b = time.perf_counter() - t1
+        assert st["true_rel_resid"] <= W["tol"], (name, st)
+        res["deflated_solves_per_s"][name] = round(nd / dt_b, 3)
+    res["mixed_step"] = {}
+    for name, inner, itol in (("bf16_inner_batched", "bf16", 1e-2), ("fp32_inner_batched", "fp32", 1e-6)):
+        dts = [run_mixed_step(eb, op, B, X, W, inner, itol) for _ in range(max(1, min(steps, 2)))]
+        res["mixed_step"][name] = {"solves_per_s": round(W["nrhs"] * len(dts) / sum(dts), 3),
+                                   "ms_per_step": round(1e3 * sum(dts) / len(dts), 3)}
+    if full:
+        res["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
+        lat5, its5 = [], []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_step(eb, op, B, X, W, lat5, its5, g5=True)
+        torch.cuda.synchronize()
+        dt5 = time.perf_counter() - t1
+        n1 = W["n1"]
+        last = slice((steps - 1) * W["nrhs"], steps * W["nrhs"])
+        lat_g, its_g = lat[last], its[last]
+        res["gamma5_form"] = {
+            "solves_per_s": round(W["nrhs"] / dt5, 3),
+            "iters_per_rhs": its5,
+            "eigbicg_ms_per_iter_solves_2_to_n1": {
+                "general": round(1e3 * sum(lat_g[1:n1]) / sum(its_g[1:n1]), 4),
+                "gamma5": round(1e3 * sum(lat5[1:n1]) / sum(its5[1:n1]), 4),
+            },
+        }
+        op_eo = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"], eo=True)
+        run_step(eb, op_eo, B, X, W, [], [])
+        lat_e, its_e = [], []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_step(eb, op_eo, B, X, W, lat_e, its_e)
+        torch.cuda.synchronize()
+        dt_e = time.perf_counter() - t1
+        eo_tune = tune_untimed(eb, op_eo, ("fp64", "fp32", "bf16"))
+        eo_defl = {}
+        for name, kw in [("fp64_batched", dict()), ("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
+                         ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
+            Xd = torch.zeros_like(Bd)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            st = eb.deflated_bicg_solve(op_eo, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
+            torch.cuda.synchronize()
+            assert st["true_rel_resid"] <= W["tol"], (name, st)
+            eo_defl[name] = round(nd / (time.perf_counter() - t2), 3)
+        eb.op_destroy(op_eo)
+        res["even_odd"] = {"solves_per_s": round(W["nrhs"] / dt_e, 3), "ms_per_step": round(1e3 * dt_e, 3),
+                           "iters_per_rhs": its_e, "p50_ms": round(1e3 * percentile(lat_e, 50), 3),
+                           "deflated_solves_per_s": eo_defl, "autotune_seconds": eo_tune}
+    eb.defl_reset(op)
+    plain = []
+    for i in range(W["n1"], min(W["nrhs"], W["n1"] + 4)):
+        X[i].zero_()
+        plain.append(eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000)["iters"])
+    res["undeflated_bicgstab_iters"] = plain
+    eb.op_destroy(op)
+    del B, X
+    torch.cuda.empty_cache()
+    log(f"[bench] incremental 16^3x32 side record: {res['solves_per_s']} solves/s")
+    return res
+
+
+# ---------------------------------------------------------------------------
+# The headline: 32^3 x 64 batched, mixed-precision, deflated solves
+# ---------------------------------------------------------------------------
+# Algorithmic bytes of the batched BiCGStab kernels, per site: complex entries
+# per column (12 per spinor read or written once) and per launch (the 36 link
+# entries, read once for all columns by the two stencils).
+BATCH_COL_SPINORS = {"bstab_v": 3, "bstab_s": 3, "bstab_t": 2, "bstab_xr": 7, "bstab_p": 4}
+BATCH_STENCILS = ("bstab_v", "bstab_t")
+CPLX_BYTES = {"fp64": 16, "fp32": 8, "bf16": 4}
+
+
+def batch_roofline(ktable, col_iters, k, V, prec):
+    """Achieved algorithmic GB/s of each batched kernel class over the timed steps.
+
+    A launch of class c moves 12 * BATCH_COL_SPINORS[c] complex entries per site
+    for each column still iterating (stopped columns are skipped), plus the
+    36 link entries per site for the stencils.  col_iters (the columns'
+    iterations summed) counts the column passes of every class; the stencils'
+    working launches are at least col_iters / k, and the link bytes are
+    counted for that many (the launches queued past the last column's stop
+    return at once).  Returns {class: record}."""
+    cb = CPLX_BYTES[prec]
+    n_work = -(-col_iters // k)
+    out = {}
+    for c, ncol in BATCH_COL_SPINORS.items():
+        n, ms = ktable.get(c, (0, 0.0))
+        if not n or not ms:
+            continue
+        total = col_iters * V * 12 * ncol * cb + (n_work * V * 36 * cb if c in BATCH_STENCILS else 0)
+        out[c] = {"launches": n, "working_launches": n_work, "total_ms": round(ms, 3),
+                  "bytes_per_launch": round(total / n_work), "avg_launch_us": round(1e3 * ms / n_work, 2),
+                  "avg_us_all_launches": round(1e3 * ms / n, 2),
+                  "achieved_GBps": round(total / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
+_CPU = {}
+
+
+def _oracle_d_once(i):
+    """Worker: one application of the oracle's D to source i (links inherited from the parent)."""
+    import synth
+    from oracle import wilson as Wl
+
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+    dims, kappa, U = _CPU["dims"], _CPU["kappa"], _CPU["U"]
+    V = synth.volume(dims)
+    b = synth.z2_source(V, synth.rhs_seed(3, i))
+    t0 = time.perf_counter()
+    Wl.apply_D(U, b, kappa, dims)
+    return time.perf_counter() - t0
+
+
+def oracle_dslash_parallel(U, dims, kappa):
+    """One application of the oracle's D per host core in forked worker processes (before
+    this process touches the GPU); returns (mean seconds, workers)."""
+    import multiprocessing as mp
+
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except Exception:  # pragma: no cover
+        ncpu = os.cpu_count() or 1
+    nproc = max(1, min(16, ncpu))
+    _CPU.update(dims=dims, kappa=kappa, U=U)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(nproc) as pool:
+        times = pool.map(_oracle_d_once, range(nproc))
+    _CPU.clear()
+    return sum(times) / len(times), nproc, time.perf_counter() - t0
+
+
+def headline_batch(eb, W, U, args):
+    """The workload of the bench line: 32^3 x 64, a 100-pair deflation space grown
+    by eigBiCG (setup), then each step solves the 16 resident Z2 sources by
+    deflated BiCGStab in batches (multi-RHS stencil, k and tile form chosen by
+    the library's autotuner during setup), complex64 inner iterations inside
+    complex128 refinement, every solve to ||b - A x|| <= 1e-10 ||b|| in FP64."""
+    import torch
+
+    import synth
+
+    dims = W["dims"]
+    V = synth.volume(dims)
+    dev = torch.device("cuda:0")
+    setup = {}
+    op = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"])
+    t0 = time.perf_counter()
+    grow = []
+    for i in range(W["n1"]):
+        b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], 100 + i))).to(dev)
+        x = torch.zeros_like(b)
+        st, _ = eb.eigbicg_solve(op, b, x, W["nev"], W["m"], W["tol"], maxiter=20000)
+        assert st["true_rel_resid"] <= W["tol"], st
+        grow.append({"iters": st["iters"], "restarts": st["window_restarts"], "seconds": round(st["seconds"], 3)})
+        log(f"[bench] growth eigBiCG {i}: {grow[-1]}")
+        del b, x
+    setup["eigbicg_growth"] = {"nev": W["nev"], "m": W["m"], "solves": grow, "K": eb.defl_info(op)[0],
+                               "seconds": round(time.perf_counter() - t0, 3)}
+    setup["device_bytes_after_growth"] = eb.op_device_bytes(op)
+    eb.op_trim(op)  # the eigBiCG windows and absorb buffers
+    setup["device_bytes_trimmed"] = eb.op_device_bytes(op)
+    setup["autotune_seconds"] = tune_untimed(eb, op, (W["inner"], "bf16"))
+    tune = {p: eb.op_batch_tune(op, p) for p in (W["inner"], "bf16")}
+    setup["autotune"] = tune
+    k = tune[W["inner"]]["k"]
+    log(f"[bench] autotuner: k = {k}, forms {tune[W['inner']]['stage']}")
+    nrhs = W["nrhs"]
+    B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], i))) for i in range(nrhs)]).to(dev)
+    X = torch.zeros_like(B)
+
+    def step():
+        X.zero_()
+        st = eb.deflated_bicg_solve(op, B, X, tol=W["tol"], maxiter=20000, nrhs=nrhs, inner=W["inner"],
+                                    inner_tol=W["inner_tol"], batch=0)
+        if st["true_rel_resid"] > W["tol"]:
+            raise RuntimeError(f"a solve missed the tolerance: {st}")
+        return st
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {w} done")
+    timing = not args.no_timing
+    if timing:
+        eb.timing_classes(op, None)
+        eb.timing_enable(op, True)
+    lat, sts = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        t1 = time.perf_counter()
+        sts.append(step())
+        lat.append(time.perf_counter() - t1)
+        log(f"[bench] step {i}: {lat[-1]:.3f} s, {sts[-1]['iters'] / nrhs:.1f} iterations per source")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktable = eb.timing_read(op) if timing else {}
+    eb.timing_enable(op, False)
+    col_iters = sum(s["iters"] for s in sts)
+    kern = batch_roofline(ktable, col_iters, k, V, W["inner"])
+    others = {n: {"launches": c, "total_ms": round(ms, 3)} for n, (c, ms) in ktable.items()
+              if c and n not in kern}
+    total_ms = sum(ms for _, ms in ktable.values())
+    dom = max(kern, key=lambda c: kern[c]["total_ms"]) if kern else None
+    roof = None
+    if dom:
+        rk = kern[dom]
+        roof = {"kernel": dom, "bound": "hbm", "achieved": rk["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(rk["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                "traffic": measured_traffic("batch32x64", dom),
+                "bytes_per_launch": rk["bytes_per_launch"], "avg_launch_us": rk["avg_launch_us"],
+                "launches": rk["launches"], "working_launches": rk["working_launches"],
+                "share_of_kernel_time": round(rk["total_ms"] / total_ms, 4) if total_ms else None}
+    value = nrhs * args.steps / elapsed
+    st0 = sts[0]
+    head = {"value": value, "elapsed": elapsed, "lat": lat, "k": k, "roofline": roof,
+            "kernels": {"batched": kern, "other": others},
+            "iters_per_rhs": round(st0["iters"] / nrhs, 1), "outer_steps": st0["outer_steps"],
+            "max_true_rel_resid": max(s["true_rel_resid"] for s in sts),
+            "matvec_d_per_rhs": round(st0["matvec_d"] / nrhs, 1), "setup": setup}
+    # the same sources on the same GPU: FP64 deflated BiCGStab, plain (undeflated)
+    # FP64 BiCG and BiCGStab, BF16-stored inner, one at a time / batched
+    comp = {"mixed_fp32_batched_deflated": {"solves_per_s": round(value, 3), "k": k,
+                                            "iters_per_rhs": head["iters_per_rhs"]}}
+    nc = 4
+
+    def run(name, o, n, **kw):
+        Xc = torch.zeros_like(B[:n])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = eb.deflated_bicg_solve(o, B[:n].contiguous(), Xc, tol=W["tol"], maxiter=20000, nrhs=n, **kw)
+        dt = time.perf_counter() - t1
+        assert st["true_rel_resid"] <= W["tol"], (name, st)
+        comp[name] = {"solves_per_s": round(n / dt, 3), "iters_per_rhs": round(st["iters"] / n, 1),
+                      "max_true_rel_resid": st["true_rel_resid"]}
+        log(f"[bench] {name}: {comp[name]}")
+        del Xc
+
+    run("mixed_bf16_batched_deflated", op, nrhs, inner="bf16", inner_tol=1e-2, batch=0)
+    run("fp64_bicgstab_deflated", op, nc, batch=1)
+    op2 = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=0)  # no deflation space
+    run("fp64_bicg_plain", op2, nc, method=1)
+    run("fp64_bicgstab_plain", op2, nc, batch=1)
+    run("mixed_fp32_batched_plain", op2, nrhs, inner=W["inner"], inner_tol=W["inner_tol"], batch=0)
+    eb.op_destroy(op2)
+    head["comparators"] = comp
+    head["speedup_vs_fp64_bicg_plain"] = round(value / comp["fp64_bicg_plain"]["solves_per_s"], 3)
+    head["speedup_vs_fp64_bicgstab_deflated"] = round(value / comp["fp64_bicgstab_deflated"]["solves_per_s"], 3)
+    head["fp64_bicgstab_iters_per_rhs"] = comp["fp64_bicgstab_deflated"]["iters_per_rhs"]
+    head["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V, precs=("fp32", "bf16"), ks=(1, 4, 8, 16))
+    eb.op_destroy(op)
+    del B, X
+    torch.cuda.empty_cache()
+    return head
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="inc16x32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch32x64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
-    ap.add_argument("--no-large", action="store_true", help="skip the 24^3 x 64 multi-RHS / precision section")
-    ap.add_argument("--no-side", action="store_true",
-                    help="skip the side records (multi-RHS table, gamma5 and even-odd forms, sweeps)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 24^3 x 64 precision section")
+    ap.add_argument("--no-side", action="store_true", help="the headline workload only (e.g. to profile it)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (continuous batching) section")
-    ap.add_argument("--no-batching", action="store_true", help="skip the 32^3 x 64 batching section")
-    ap.add_argument("--batching-only", action="store_true", help="run only the 32^3 x 64 batching section")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving section and print it")
     ap.add_argument("--proj-pass", action="store_true", help="deflation projections on the matrix cores, for --pmc")
     ap.add_argument("--stencil-pass", action="store_true", help="multi-RHS FP32 stencil launches for rocprofv3 --pmc")
     ap.add_argument("--stencil-form", type=int, default=0, help="tile form of the k > 1 launches of --stencil-pass")
-    ap.add_argument("--pmc-pass", action="store_true", help="one eigBiCG solve and a calibration copy, for rocprofv3 --pmc")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="one pass of the workload's roofline kernel and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("PROF_DIR", "BENCH_JSON", "NAME", "COMMAND"),
+                    help="write profiles/NAME.md from a rocprofv3 --kernel-trace --stats run of bench.py")
     args = ap.parse_args()
+    if args.summarize_trace:
+        d, bj, name, cmd = args.summarize_trace
+        summarize_trace(d, bj, args.workload, name, cmd)
+        return
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
+        if args.workload == "batch32x64":
+            summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, kernel="k_bstab_v",
+                          cls="bstab_v")
+        else:
+            summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
         return
     if args.pmc_pass:
         pmc_pass(args.workload)
@@ -704,275 +1054,107 @@ def main():
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the multi-GPU path is design-only",
               file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
+    W = WORKLOADS[args.workload]
+    if "inner" not in W:
+        print("the bench line runs the batch32x64 workload; the incremental workloads are side records",
+              file=sys.stderr)
+        sys.exit(2)
 
     import synth
+
+    dims = W["dims"]
+    log(f"[bench] workload {args.workload}: dims={dims} kappa={W['kappa']} nrhs={W['nrhs']}")
+    t0 = time.perf_counter()
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
+    log(f"[bench] links generated in {time.perf_counter() - t0:.1f} s")
+    # the CPU oracle leg runs first, in forked workers, before this process touches the GPU
+    cpu_d = None
+    if not args.no_cpu_baseline and not args.serving_only:
+        log("[bench] timing the CPU oracle (one D application per host core) ...")
+        cpu_d = oracle_dslash_parallel(U, dims, W["kappa"])
+        log(f"[bench] oracle D: {cpu_d[0]:.2f} s per application, {cpu_d[1]} workers")
+
+    import torch
+
     from paper_0911_2285_amd import ebicg as eb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serving_only:
         print(json.dumps({"serving": serving(eb)}), flush=True)
         return
-    if args.batching_only:
-        print(json.dumps({"batching": batching(eb)}), flush=True)
-        return
-    W = WORKLOADS[args.workload]
-    dims = W["dims"]
+    head = headline_batch(eb, W, U, args)
+    del U
     V = synth.volume(dims)
-    dev = torch.device("cuda:0")
-    log(f"[bench] workload {args.workload}: dims={dims} kappa={W['kappa']} nrhs={W['nrhs']} n1={W['n1']}")
-    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
-    op = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"])
-    B_np = [synth.z2_source(V, synth.rhs_seed(0, i)) for i in range(W["nrhs"])]
-    B = [torch.from_numpy(b).to(dev) for b in B_np]
-    X = [torch.zeros_like(b) for b in B]
-    torch.cuda.synchronize()
-
-    for w in range(args.warmup):
-        lat, its = [], []
-        run_step(eb, op, B, X, W, lat, its)
-        log(f"[bench] warmup step {w}: {sum(lat):.3f} s, iterations {its}")
-
-    # In the timed steps only the roofline kernel's launches carry HIP events
-    # (each recorded launch costs two host-side event records); the per-kernel
-    # table comes from one more, separately instrumented step below.
-    if not args.no_timing:
-        eb.timing_classes(op, [ROOFLINE_CLASS])
-        eb.timing_enable(op, True)
-    lat, its = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        run_step(eb, op, B, X, W, lat, its)
-        log(f"[bench] step {k} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ktimes = eb.timing_read(op) if not args.no_timing else {}
-    eb.timing_enable(op, False)
-    # per-kernel table: one more step with every class instrumented (not timed)
-    ktable = {}
-    if not args.no_timing:
-        eb.timing_classes(op, None)
-        eb.timing_enable(op, True)
-        run_step(eb, op, B, X, W, [], [])
-        ktable = eb.timing_read(op)
-        eb.timing_enable(op, False)
-
-    n_solves = W["nrhs"] * args.steps
-    value = n_solves / elapsed
-    per_step_its = its[: W["nrhs"]]
-    eig_its = sum(per_step_its[: W["n1"]])
-    stab_its = sum(per_step_its[W["n1"]:])
-    log(f"[bench] {n_solves} solves in {elapsed:.3f} s -> {value:.2f} solves/s; iterations/RHS {per_step_its}")
-
-    # roofline of the dominant kernel: algorithmic bytes / average launch time
-    roof = None
-    kernels = {}
-    for name, (n, ms) in ktable.items():
-        if n == 0:
-            continue
-        rec = {"launches": n, "total_ms": round(ms, 3), "avg_us": round(1e3 * ms / n, 2)}
-        if name in KERNEL_UNITS:
-            bytes_per_launch = KERNEL_UNITS[name] * UNIT_BYTES_FP64 * V
-            rec["GBps"] = round(bytes_per_launch / (ms / n * 1e-3) / 1e9, 1)
-        kernels[name] = rec
-    n_roof, ms_roof = ktimes.get(ROOFLINE_CLASS, (0, 0.0))
-    # launches that did work: one BiCG matvec per eigBiCG iteration.  The host
-    # queues iterations ahead of the convergence test, and the few launched
-    # past it return at once; they are recorded too but do no work, so the
-    # average is taken over the working launches (their ~1 us is included in
-    # the total, which only lowers the figure).
-    n_work = sum(sum(its[k * W["nrhs"]: k * W["nrhs"] + W["n1"]]) for k in range(args.steps))
-    if n_roof:
-        dom = ROOFLINE_CLASS
-        bpl = KERNEL_UNITS[dom] * UNIT_BYTES_FP64 * V
-        avg_us = 1e3 * ms_roof / min(n_roof, n_work) if n_work else 1e3 * ms_roof / n_roof
-        ach = round(bpl / (avg_us * 1e-6) / 1e9, 1)
-        roof = {
-            "kernel": dom,
-            "bound": "hbm",
-            "achieved": ach,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic(args.workload, dom),
-            "bytes_per_launch": bpl,
-            "avg_launch_us": round(avg_us, 2),
-            "launches": n_roof,
-            "working_launches": n_work,
-        }
-        log(f"[bench] kernel times: {json.dumps(kernels)}")
-
-    # deflated phase in mixed precision (FP32 inner, FP64 refinement) vs FP64,
-    # with the space grown by the last step still in place
     extra = {}
-    modes = {"fp64": dict(), "mixed_fp32_inner": dict(inner="fp32", inner_tol=1e-6),
-             "mixed_bf16_inner": dict(inner="bf16", inner_tol=1e-2)}
-    dt = {k: 0.0 for k in modes}
-    mode_its = {k: [] for k in modes}
-    for i in range(W["n1"], W["nrhs"]):
-        for name, kw in modes.items():
-            X[i].zero_()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000, **kw)
-            dt[name] += time.perf_counter() - t1
-            assert st["true_rel_resid"] <= W["tol"], (name, st)
-            mode_its[name].append((st["iters"], st["outer_steps"]))
-    nd = W["nrhs"] - W["n1"]
-    extra["deflated_solves_per_s"] = {k: round(nd / dt[k], 3) for k in modes}
-    extra["deflated_iters_outer"] = {k: mode_its[k][:4] for k in modes}
-    # multi-RHS: the 16 deflated sources in batches (FP32 / BF16 inner, batch chosen by the library)
-    nd = W["nrhs"] - W["n1"]
-    Bd = torch.stack(B[W["n1"]:])
-    extra["autotune_seconds"] = tune_untimed(eb, op, ("fp32", "bf16"))
-    for name, kw in [("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
-                     ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
-        Xd = torch.zeros_like(Bd)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st = eb.deflated_bicg_solve(op, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
-        dt_b = time.perf_counter() - t1
-        assert st["true_rel_resid"] <= W["tol"], (name, st)
-        extra["deflated_solves_per_s"][name] = round(nd / dt_b, 3)
-    # the batch autotuner's choice on this operator (k and tile form per precision)
-    extra["autotune"] = {p: eb.op_batch_tune(op, p) for p in ("fp32", "bf16")}
-    # the whole step with its deflated phase mixed (BF16 / FP32 inner, batched)
-    # against the FP64 step above; every solve still at the FP64 true residual tol
-    extra["mixed_step"] = {}
-    for name, inner, itol in (("bf16_inner_batched", "bf16", 1e-2), ("fp32_inner_batched", "fp32", 1e-6)):
-        dts = [run_mixed_step(eb, op, B, X, W, inner, itol) for _ in range(args.steps)]
-        extra["mixed_step"][name] = {"solves_per_s": round(W["nrhs"] * len(dts) / sum(dts), 3),
-                                     "ms_per_step": round(1e3 * sum(dts) / len(dts), 3)}
-    extra["mixed_step"]["fp64_step_solves_per_s"] = round(value, 3)
-    log(f"[bench] mixed step: {extra['mixed_step']}")
-    # the side records (skipped with --no-side, e.g. to profile the headline workload alone)
     if not args.no_side:
-        extra["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
-        # the same step with eigBiCG solves 2..n1 in the gamma5-Hermitian form
-        # (Sec. 4: one D per iteration, shadow vectors implicit)
-        lat5, its5 = [], []
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        run_step(eb, op, B, X, W, lat5, its5, g5=True)
-        torch.cuda.synchronize()
-        dt5 = time.perf_counter() - t1
-        n1 = W["n1"]
-        last = slice((args.steps - 1) * W["nrhs"], args.steps * W["nrhs"])
-        lat_g, its_g = lat[last], its[last]
-        extra["gamma5_form"] = {
-            "solves_per_s": round(W["nrhs"] / dt5, 3),
-            "iters_per_rhs": its5,
-            "eigbicg_ms_per_iter_solves_2_to_n1": {
-                "general": round(1e3 * sum(lat_g[1:n1]) / sum(its_g[1:n1]), 4),
-                "gamma5": round(1e3 * sum(lat5[1:n1]) / sum(its5[1:n1]), 4),
-            },
-        }
-        log(f"[bench] gamma5 form: {extra['gamma5_form']}")
-        # the same step on the even-odd (Schur) form: the paper's test matrices are
-        # even-odd preconditioned; every solve still reaches ||b - D x|| <= tol ||b||
-        op_eo = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["n1"] * W["nev"], eo=True)
-        run_step(eb, op_eo, B, X, W, [], [])
-        lat_e, its_e = [], []
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        run_step(eb, op_eo, B, X, W, lat_e, its_e)
-        torch.cuda.synchronize()
-        dt_e = time.perf_counter() - t1
-        # its deflated solves with FP32 / BF16-stored inner BiCGStab in FP64 refinement
-        eo_defl = {}
-        for name, kw in [("fp64", dict()), ("mixed_fp32_inner", dict(inner="fp32", inner_tol=1e-6)),
-                         ("mixed_bf16_inner", dict(inner="bf16", inner_tol=1e-2))]:
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            for i in range(W["n1"], W["nrhs"]):
-                X[i].zero_()
-                st = eb.deflated_bicg_solve(op_eo, B[i], X[i], tol=W["tol"], maxiter=20000, **kw)
-                assert st["true_rel_resid"] <= W["tol"], (name, st)
-            torch.cuda.synchronize()
-            eo_defl[name] = round((W["nrhs"] - W["n1"]) / (time.perf_counter() - t2), 3)
-        # and in batches (batch chosen by the library's autotuner, run before the timed solves)
-        eo_tune = tune_untimed(eb, op_eo, ("fp64", "fp32", "bf16"))
-        for name, kw in [("fp64_batched", dict()), ("mixed_fp32_batched", dict(inner="fp32", inner_tol=1e-6)),
-                         ("mixed_bf16_batched", dict(inner="bf16", inner_tol=1e-2))]:
-            Xd = torch.zeros_like(Bd)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            st = eb.deflated_bicg_solve(op_eo, Bd, Xd, tol=W["tol"], maxiter=20000, nrhs=nd, batch=0, **kw)
-            torch.cuda.synchronize()
-            assert st["true_rel_resid"] <= W["tol"], (name, st)
-            eo_defl[name] = round(nd / (time.perf_counter() - t2), 3)
-        eb.op_destroy(op_eo)
-        extra["even_odd"] = {
-            "solves_per_s": round(W["nrhs"] / dt_e, 3),
-            "ms_per_step": round(1e3 * dt_e, 3),
-            "iters_per_rhs": its_e,
-            "p50_ms": round(1e3 * percentile(lat_e, 50), 3),
-            "deflated_solves_per_s": eo_defl,
-            "autotune_seconds": eo_tune,
-        }
-        log(f"[bench] even-odd form: {extra['even_odd']}")
+        extra["incremental_16x32"] = incremental_side(eb, WORKLOADS["inc16x32"], max(1, min(args.steps, 2)), 1)
         if not args.no_serving:
             extra["serving"] = serving(eb)
         extra["deflation_sweep"] = deflation_sweep(eb)
         extra["table1_analogue"] = table1_analogue(eb)
-        log(f"[bench] deflation sweep: {extra['deflation_sweep']}")
-    # undeflated FP64 BiCGStab on the same sources, for the deflation speed-up
-    eb.defl_reset(op)
-    plain_its = []
-    for i in range(W["n1"], min(W["nrhs"], W["n1"] + 4)):
-        X[i].zero_()
-        st = eb.deflated_bicg_solve(op, B[i], X[i], tol=W["tol"], maxiter=20000)
-        plain_its.append(st["iters"])
-    extra["undeflated_bicgstab_iters"] = plain_its
-
-    if not args.no_large:
-        extra["large_lattice"] = large_lattice(eb, (24, 24, 24, 64), 0.123, 16, W["tol"])
-    if not args.no_batching:
-        extra["batching"] = batching(eb)
+        if not args.no_large:
+            extra["large_lattice"] = large_lattice(eb, (24, 24, 24, 64), 0.123, 16, W["tol"])
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(W, U, B_np[0], eig_its, stab_its)
-        log(f"[bench] cpu baseline {cpu['value']:.4g} solves/s")
+    if cpu_d:
+        t_d, nproc, wall = cpu_d
+        # the oracle's deflated FP64 BiCGStab solve: 2 D per iteration at the GPU's FP64
+        # iteration count, plus the initial and final residuals
+        d_per_solve = 2 * head["fp64_bicgstab_iters_per_rhs"] + 2
+        cpu = {"value": round(nproc / (t_d * d_per_solve), 6), "unit": "solves/s", "cores": nproc, "kind": "oracle",
+               "sample": (f"one application of the oracle's D on the {'x'.join(map(str, dims))} lattice in each of "
+                          f"{nproc} forked worker processes, one per host core (1 thread each; {t_d:.2f} s per "
+                          f"application, {wall:.1f} s wall); a deflated FP64 BiCGStab solve of the oracle is costed "
+                          f"at {d_per_solve:.0f} D applications (2 per iteration at the GPU's FP64 iteration count "
+                          f"plus two residuals), its vector operations and deflation projections not counted, so "
+                          f"this is an upper bound on the oracle's rate"),
+               "dslash_seconds": round(t_d, 3), "dslash_GBps_per_core": round(960 * V / t_d / 1e9, 3)}
 
+    lat = head["lat"]
     out = {
         "metric": "solves/s at 1e-10 rel. resid (mixed vs FP64), dslash HBM GB/s, p50/p99",
-        "value": round(value, 4),
+        "value": round(head["value"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "ms_per_step": round(1e3 * head["elapsed"] / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "c64 inner / c128 outer",
         "data": "synthetic",
         "config": {
-            "workload": f"incremental eigBiCG, Wilson-Dirac {'x'.join(map(str, dims))}, kappa {W['kappa']}, "
-                        f"eps 0.3 SU(3) links, {W['nrhs']} Z2 sources: {W['n1']} eigBiCG (nev {W['nev']}, "
-                        f"m {W['m']}) + {W['nrhs'] - W['n1']} deflated BiCGStab, tol {W['tol']}",
+            "workload": (f"batched mixed-precision deflated solves, Wilson-Dirac {'x'.join(map(str, dims))}, "
+                         f"kappa {W['kappa']}, eps 0.3 SU(3) links, {W['nrhs']} Z2 sources per step, "
+                         f"{W['n1'] * W['nev']}-pair deflation space grown by {W['n1']} eigBiCG solves "
+                         f"(nev {W['nev']}, m {W['m']}) in setup, multi-RHS BiCGStab with autotuned k "
+                         f"({head['k']}) and tile form, complex64 inner / complex128 refinement, tol {W['tol']}"),
             "lattice": list(dims),
             "nrhs": W["nrhs"],
+            "k": head["k"],
+            "deflation_pairs": W["n1"] * W["nev"],
             "parallelism": "single GPU",
         },
-        "roofline": roof,
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "dslash_GBps": roof["achieved"] if roof else None,
+        "dslash_GBps": head["roofline"]["achieved"] if head["roofline"] else None,
         "p50_ms": round(1e3 * percentile(lat, 50), 3),
         "p99_ms": round(1e3 * percentile(lat, 99), 3),
-        "iters_per_rhs": per_step_its,
-        "kernels": kernels,
-        "kernels_note": "per-kernel HIP-event times from one extra step with every kernel class instrumented (averages include the launches queued past convergence, which return at once); "
-                        "the timed steps instrument only the roofline kernel",
+        "latency_note": "p50/p99 of the step (16 solves in one batched call, all finishing together); per-request "
+                        "latency under continuous batching is in serving",
+        "iters_per_rhs": head["iters_per_rhs"],
+        "outer_steps": head["outer_steps"],
+        "max_true_rel_resid": head["max_true_rel_resid"],
+        "comparators": head["comparators"],
+        "speedup_vs_fp64_bicg_plain": head["speedup_vs_fp64_bicg_plain"],
+        "speedup_vs_fp64_bicgstab_deflated": head["speedup_vs_fp64_bicgstab_deflated"],
+        "kernels": head["kernels"],
+        "setup": head["setup"],
+        "multi_rhs_stencil": head["multi_rhs_stencil"],
         **extra,
     }
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()
