@@ -70,6 +70,13 @@ typedef struct {
                       as 1 in exact arithmetic.  A source with (gamma5 r_0, r_0) = 0, such as a
                       Z2 source (entries +-1) with x_0 = 0, breaks down at once in modes 1 and
                       2 (EB_ERR_BREAKDOWN). */
+  int32_t window;  /* storage of the window's vectors: EB_FP64, or EB_FP32 (the BiCG recurrence,
+                      its scalars, H and the Ritz problem stay FP64; the window holds FP32 copies of
+                      r_j, rhat_j and its rotations read FP32 and sum in FP64; the pairs absorbed
+                      into the deflation space are FP64) */
+  int32_t device_eig; /* 0: the window eigenproblems of Alg. BiCG-eigen on a host thread; 1: on the
+                      GPU by one workgroup on a side stream, from the device-resident BiCG scalars
+                      (the host reads back only the number of pairs kept and the Ritz values) */
 } eb_eig_params;
 
 /* Parameters of a deflated solve (Alg. Incremental eigBiCG, step 3). */
@@ -214,6 +221,13 @@ eb_status eb_defl_reset(eb_op *op);
  * by imaginary part descending; ||y_i|| = 1 and z_i^+ y_i = 1.  Host-only,
  * needs no GPU.  EB_ERR_EIG if the QR iteration does not converge. */
 eb_status eb_small_eig(int32_t n, const double *C, double *lambda, double *y, double *z);
+
+/* The same eigenproblem on the current GPU by one workgroup (the device solver
+ * that restarts the window of an eigBiCG solve with eb_eig_params.device_eig;
+ * Alg. BiCG-eigen), with the same arguments, conventions and order as
+ * eb_small_eig; n <= 128.  Synchronous; allocates and frees its own device
+ * buffers.  EB_ERR_EIG if the QR iteration does not converge. */
+eb_status eb_small_eig_device(int32_t n, const double *C, double *lambda, double *y, double *z);
 
 /* Kernel timing, for benchmarks.  While enabled, every launch of the solver
  * kernels is bracketed by HIP events on the solve's stream; eb_timing_read

@@ -33,6 +33,7 @@ SOURCES = [
     ("tsmm.hip", "hip"),
     ("batch.hip", "hip"),
     ("eo.hip", "hip"),
+    ("winrestart.hip", "hip"),
     ("hostla.cpp", "host"),
 ]
 

@@ -133,6 +133,7 @@ struct eb_op {
   int bc_t = -1;
   int device = 0;
   int grid_cap = kDefaultStencilCap;  // grid cap of the reducing stencil kernels (eb_op_set_grid_cap)
+  hipStream_t side = nullptr;         // side stream of the device window restarts (default priority)
   DevBuf U64, U32, U16;  // links: FP64, and FP32 / BF16 copies made on first use
   // deflation space: Ul, Ur hold Kcap FP64 SoA spinors each; H = Ul^+ A Ur on the host
   int Kcap = 0, K = 0;
@@ -225,6 +226,8 @@ struct eb_op {
     return h;
   }
   void free_all() {
+    if (side) (void)hipStreamDestroy(side);
+    side = nullptr;
     U64.release();
     Ueo.release();
     Ueo32.release();
@@ -1076,16 +1079,46 @@ struct EigBiCGOut {
   int nvec = 0;  // Ritz pairs written to Ur[:, K..), Ul[:, K..)
 };
 
+// Window storage of an eigBiCG solve: FP64 slots that hold the recurrence's
+// residuals themselves, or FP32 slots that hold copies of them (the FP64
+// recurrence vectors then live in two ping-pong buffers).  Both windows sit in
+// one allocation, so a rotation reads right-window slot s and left-window
+// slot nslots + s from one base.
+template <typename T>
+struct Window {
+  T *base = nullptr;
+  int nslots = 0;
+  size_t N = 0;
+  T *V(int slot) const { return base + size_t(slot) * N; }
+  T *W(int slot) const { return base + size_t(nslots + slot) * N; }
+};
+
+// The device restart of one window (Alg. BiCG-eigen on the GPU, side stream):
+// which window it was started on and which ring slot holds its results.
+struct DevJob {
+  int jr = 0;
+  int ring = 0;
+  std::vector<Col> cols;
+};
+
 EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_params &P, hipStream_t s) {
   const size_t N = op->N;
   const int m = P.m, nev = P.nev;
   const int lag = 8;
   const int nslots = m + 1 + lag + 2 * nev;
   const size_t ncoef = size_t(m + 1) * 2 * nev;  // one coefficient block (m x 2nev complex)
-  // one allocation for both windows, so that a rotation can read right-window
-  // columns (slot s) and left-window columns (slot nslots + s) from one base
-  double2 *Vw = op->vec("win_VW", 2 * size_t(nslots));
-  double2 *Ww = Vw + size_t(nslots) * N;
+  const bool w32 = P.window == EB_FP32;          // FP32 window: FP32 copies of r, rhat in the slots
+  const bool dev = P.device_eig != 0;            // window eigenproblems on the device
+  Window<double2> win64;
+  Window<float2> win32;
+  double2 *R64 = nullptr, *RH64 = nullptr;  // FP32 window: the recurrence's r, rhat (two each)
+  if (w32) {
+    win32 = Window<float2>{op->raw<float2>("win_VW32", 2 * size_t(nslots) * N * sizeof(float2)), nslots, N};
+    R64 = op->vec("win_r64", 2);
+    RH64 = op->vec("win_rh64", 2);
+  } else {
+    win64 = Window<double2>{op->vec("win_VW", 2 * size_t(nslots)), nslots, N};
+  }
   // gamma5-Hermitian form (Sec. 4): rhat_j = gamma5 r_j is never formed; the
   // left window's stored residuals are read as gamma5 times the right window's
   const bool g5 = P.rhat == 2;
@@ -1098,14 +1131,20 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   const KrylovHistory hv = op->view(op->hhist.p);
   const HostHist hh{hv.alpha, hv.beta, hv.rho, hv.rn};
   KrylovState *S = op->S();
-  auto V = [&](int slot) { return Vw + size_t(slot) * N; };
-  auto W = [&](int slot) { return Ww + size_t(slot) * N; };
+  // the recurrence's r_i and rhat_i (FP64): in window slot `slot` (FP64
+  // window), or in ping-pong buffer i & 1 (FP32 window)
+  auto Rrec = [&](int i, int slot) { return w32 ? R64 + size_t(i & 1) * N : win64.V(slot); };
+  auto RHrec = [&](int i, int slot) { return w32 ? RH64 + size_t(i & 1) * N : win64.W(slot); };
 
   EigBiCGOut out;
   // r_0 in V slot 0, rhat_0 in W slot 0
-  residual_launch(op, V(0), b, x, s);
-  launch_bicg_init(g5 ? nullptr : W(0), p, g5 ? nullptr : ph, V(0), op->res.as<double>(), N, P.rhat, op->g, P.tol,
-                   P.maxiter, S, dh, op->rs(), s);
+  residual_launch(op, Rrec(0, 0), b, x, s);
+  launch_bicg_init(g5 ? nullptr : RHrec(0, 0), p, g5 ? nullptr : ph, Rrec(0, 0), op->res.as<double>(), N, P.rhat,
+                   op->g, P.tol, P.maxiter, S, dh, op->rs(), s);
+  if (w32) {
+    launch_convert_f64_f32(win32.V(0), Rrec(0, 0), N, s);
+    if (!g5) launch_convert_f64_f32(win32.W(0), RHrec(0, 0), N, s);
+  }
   KrylovState hs;
   fetch_state(op, s, hs);
   if (hs.stopped) {
@@ -1122,33 +1161,64 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   std::vector<Col> cols;
   RitzBlock rb;
   std::unique_ptr<RestartJob> job;
+  std::unique_ptr<DevJob> djob;
   // host mirror of the history: after iteration j the device holds alpha, beta
   // for indices < j and rho, rn for indices <= j
   int ab_copied = 0, rr_copied = 0;
 
   // pinned staging: [0] state at a restart point, [1..] arrow dots, coefficient ring
-  PinnedBuf pstate, pdots, pcoef;
+  PinnedBuf pstate, pdots, pcoef, pdev;
   pstate.ensure(sizeof(KrylovState));
   pdots.ensure(2 * size_t(2 * nev) * sizeof(double2));
   pcoef.ensure(4 * ncoef * sizeof(double2));
-  hipEvent_t ev_hist = nullptr, ev_coef[2] = {nullptr, nullptr};
+  hipEvent_t ev_hist = nullptr, ev_coef[2] = {nullptr, nullptr}, ev_go[2] = {nullptr, nullptr},
+             ev_done[2] = {nullptr, nullptr};
   bool coef_used[2] = {false, false};
   int coef_ring = 0;
   HIPCHK(hipEventCreateWithFlags(&ev_hist, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&ev_coef[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&ev_coef[1], hipEventDisableTiming));
+  // device restarts: workspace, Ritz values and kept counts per ring slot
+  // (slot 2: the final extraction), their pinned mirror, a side stream
+  constexpr int kLamStride = 64;
+  double2 *wsd = nullptr, *lamd = nullptr;
+  int *keptd = nullptr;
+  int dring = 0, last_lam = 0;
+  struct DevMirror {
+    int kept;
+    int pad[3];
+    double2 lam[kLamStride];
+  };
+  if (dev) {
+    wsd = op->raw<double2>("win_ws", window_restart_ws_entries(m + 1, nev) * sizeof(double2));
+    lamd = op->raw<double2>("win_lam", 3 * kLamStride * sizeof(double2));
+    keptd = op->raw<int>("win_kept", 3 * sizeof(int));
+    pdev.ensure(3 * sizeof(DevMirror));
+    if (!op->side) HIPCHK(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));
+    for (int r = 0; r < 2; ++r) {
+      HIPCHK(hipEventCreateWithFlags(&ev_go[r], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev_done[r], hipEventDisableTiming));
+    }
+  }
+  DevMirror *mir = dev ? pdev.as<DevMirror>() : nullptr;
   struct Cleanup {
     std::function<void()> f;
     ~Cleanup() { f(); }
   } cleanup{[&]() {
     if (job && job->th.joinable()) job->th.join();
     (void)hipStreamSynchronize(s);
+    if (dev && op->side) (void)hipStreamSynchronize(op->side);
     (void)hipEventDestroy(ev_hist);
     (void)hipEventDestroy(ev_coef[0]);
     (void)hipEventDestroy(ev_coef[1]);
+    for (int r = 0; r < 2; ++r) {
+      if (ev_go[r]) (void)hipEventDestroy(ev_go[r]);
+      if (ev_done[r]) (void)hipEventDestroy(ev_done[r]);
+    }
     pstate.release();
     pdots.release();
     pcoef.release();
+    pdev.release();
   }};
 
   // Upload a (V, W) pair of coefficient blocks through the pinned ring; returns device pointers.
@@ -1196,9 +1266,18 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       rb.dW[k] = c2(pd[2 * nev + k]);
     }
   };
-  // Inputs of a left-window rotation over the columns cols: in_base = Vw, a
-  // column at window slot s is nslots + s; in the gamma5 form a stored
-  // residual is -(s + 1), i.e. gamma5 times right-window slot s.
+  auto win_cols = [&](const std::vector<Col> &cs) {
+    WinCols wc{};
+    wc.n = int(cs.size());
+    for (int c = 0; c < wc.n; ++c) {
+      wc.idx[c] = cs[c].idx;
+      wc.ritz[c] = static_cast<unsigned char>(cs[c].ritz);
+    }
+    return wc;
+  };
+  // Inputs of a left-window rotation over the columns cols: in_base = the
+  // window's base, a column at window slot s is nslots + s; in the gamma5 form
+  // a stored residual is -(s + 1), i.e. gamma5 times right-window slot s.
   auto left_inputs = [&](const std::vector<Col> &cs) {
     SlotList in{};
     in.n = int(cs.size());
@@ -1206,39 +1285,87 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       in.idx[c] = (g5 && !cs[c].ritz) ? -(cs[c].slot + 1) : nslots + cs[c].slot;
     return in;
   };
+  // the window rotations V <- V C_V, W <- W C_W into the slots outl, with the arrow dots
+  auto rotate_window = [&](const SlotList &outl, const std::vector<Col> &incols, const double2 *cV, const double2 *cW,
+                           int jr) {
+    SlotList in{};
+    in.n = int(incols.size());
+    for (int c = 0; c < in.n; ++c) in.idx[c] = incols[c].slot;
+    const SlotList inl = left_inputs(incols);
+    if (w32) {
+      TIMED(EB_K_ROTATE, s, launch_rotate(win32.base, outl, win32.base, in, cV, N, GA, 0, dots, jr, S, op->rs(), s));
+      TIMED(EB_K_ROTATE, s,
+            launch_rotate(win32.W(0), outl, win32.base, inl, cW, N, GB, 1, dots + 2 * nev, jr, S, op->rs(), s));
+    } else {
+      TIMED(EB_K_ROTATE, s, launch_rotate(win64.base, outl, win64.base, in, cV, N, GA, 0, dots, jr, S, op->rs(), s));
+      TIMED(EB_K_ROTATE, s,
+            launch_rotate(win64.W(0), outl, win64.base, inl, cW, N, GB, 1, dots + 2 * nev, jr, S, op->rs(), s));
+    }
+  };
   // Apply a finished restart: rotate the old window into `kept` fresh slots
   // (with the arrow dots), free the old slots, replace the placeholders.
-  auto apply_job = [&]() {
-    if (!job) return;
-    if (job->th.joinable()) job->th.join();
-    if (!job->ok) fail(EB_ERR_EIG, "window restart: " + job->err);
-    const int kept = job->kept, mm = int(job->cols.size());
-    SlotList in{}, outl{};
-    in.n = mm;
-    for (int c = 0; c < mm; ++c) in.idx[c] = job->cols[c].slot;
+  auto finish_restart = [&](int kept, const std::vector<Col> &old, const double2 *cV, const double2 *cW, int jr,
+                            const std::vector<cd> &lam) {
+    const int mm = int(old.size());
+    SlotList outl{};
     outl.n = kept;
     for (int k = 0; k < kept; ++k) {
       if (free_slots.empty()) fail(EB_ERR_INVALID, "window slots exhausted");
       outl.idx[k] = free_slots.front();
       free_slots.pop_front();
     }
-    const auto coef = upload_coef(job->CVraw, job->CWraw);
-    double2 *const cV = coef.first, *const cW = coef.second;
-    TIMED(EB_K_ROTATE, s, launch_rotate(Vw, outl, Vw, in, cV, N, GA, 0, dots, job->jr, S, op->rs(), s));
-    const SlotList inl = left_inputs(job->cols);
-    TIMED(EB_K_ROTATE, s, launch_rotate(Ww, outl, Vw, inl, cW, N, GB, 1, dots + 2 * nev, job->jr, S, op->rs(), s));
-    for (int c = 0; c < mm; ++c) free_slots.push_back(job->cols[c].slot);
+    rotate_window(outl, old, cV, cW, jr);
+    for (int c = 0; c < mm; ++c) free_slots.push_back(old[c].slot);
     std::vector<Col> nc;
     for (int k = 0; k < kept; ++k) nc.push_back(Col{1, k, outl.idx[k]});
     for (const Col &c : cols)
       if (!(c.ritz && c.slot < 0)) nc.push_back(c);
     cols.swap(nc);
-    rb.jr = job->jr;
-    rb.lam = job->lam;
+    rb.jr = jr;
+    rb.lam = lam;
     rb.dV.clear();
     rb.dW.clear();
     out.restarts += 1;
+  };
+  auto apply_job = [&]() {
+    if (djob) {  // device restart: wait for its results (usually done already)
+      const int r = djob->ring;
+      HIPCHK(hipEventSynchronize(ev_done[r]));
+      const DevMirror &mr = mir[r];
+      if (mr.kept == -2) {
+        // skipped: the solve stopped before the restart's iteration; the old
+        // window stands (the columns after the stop are dropped later)
+        std::vector<Col> nc = djob->cols;
+        for (const Col &c : cols)
+          if (!(c.ritz && c.slot < 0)) nc.push_back(c);
+        cols.swap(nc);
+        djob.reset();
+        return;
+      }
+      if (mr.kept < 1) fail(EB_ERR_EIG, "window restart on the device: an eigenproblem did not converge");
+      std::vector<cd> lam(mr.kept);
+      for (int k = 0; k < mr.kept; ++k) lam[k] = c2(mr.lam[k]);
+      HIPCHK(hipStreamWaitEvent(s, ev_done[r], 0));
+      const double2 *cV = coef + size_t(r) * 2 * ncoef, *cW = cV + ncoef;
+      finish_restart(mr.kept, djob->cols, cV, cW, djob->jr, lam);
+      last_lam = r;
+      djob.reset();
+      return;
+    }
+    if (!job) return;
+    if (job->th.joinable()) job->th.join();
+    if (!job->ok) fail(EB_ERR_EIG, "window restart: " + job->err);
+    const auto cf = upload_coef(job->CVraw, job->CWraw);
+    finish_restart(job->kept, job->cols, cf.first, cf.second, job->jr, job->lam);
     job.reset();
+  };
+  auto job_done = [&]() {
+    if (djob) {
+      const hipError_t e = hipEventQuery(ev_done[djob->ring]);
+      if (e != hipSuccess && e != hipErrorNotReady) hipchk(e, "hipEventQuery");
+      return e == hipSuccess;
+    }
+    return job && job->done.load(std::memory_order_acquire);
   };
 
   const int poll = 8;
@@ -1263,25 +1390,46 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
         // from iteration j-1 (vs = m-1) in the other buffer.
         launch_arrow_vectors(GA, GB, g5 ? nullptr : Adp + cur * N, g5 ? nullptr : Adp + prv * N, Ap + cur * N,
                              Ap + prv * N, N, j, S, dh, g5, s);
-        // history through j-1 was shipped at the end of iteration j-1; the GPU
-        // keeps working on this iteration's matvec meanwhile
-        HIPCHK(hipEventSynchronize(ev_hist));
-        const KrylovState *ps = pstate.as<KrylovState>();
-        if (ps->stopped) {
-          stopped = true;
-          stop_at = ps->stop_at;
-          reason = ps->reason;
-          rnorm = ps->rnorm;
-          break;
+        if (dev) {
+          // Alg. BiCG-eigen on the device, on the side stream: it reads the
+          // history through j-1, the last restart's Ritz values and arrow dots,
+          // and skips itself if the solve stopped before iteration j
+          const int r = dring;
+          dring ^= 1;
+          HIPCHK(hipEventRecord(ev_go[r], s));
+          HIPCHK(hipStreamWaitEvent(op->side, ev_go[r], 0));
+          double2 *cV = coef + size_t(r) * 2 * ncoef, *cW = cV + ncoef;
+          launch_window_eig(win_cols(cols), nev, 0, dh, lamd + size_t(last_lam) * kLamStride, dots, cV, cW,
+                            lamd + size_t(r) * kLamStride, keptd + r, wsd, j, S, op->side);
+          HIPCHK(hipMemcpyAsync(&mir[r].kept, keptd + r, sizeof(int), hipMemcpyDeviceToHost, op->side));
+          HIPCHK(hipMemcpyAsync(mir[r].lam, lamd + size_t(r) * kLamStride, kLamStride * sizeof(double2),
+                                hipMemcpyDeviceToHost, op->side));
+          HIPCHK(hipEventRecord(ev_done[r], op->side));
+          djob.reset(new DevJob);
+          djob->jr = j;
+          djob->ring = r;
+          djob->cols = cols;
+        } else {
+          // history through j-1 was shipped at the end of iteration j-1; the GPU
+          // keeps working on this iteration's matvec meanwhile
+          HIPCHK(hipEventSynchronize(ev_hist));
+          const KrylovState *ps = pstate.as<KrylovState>();
+          if (ps->stopped) {
+            stopped = true;
+            stop_at = ps->stop_at;
+            reason = ps->reason;
+            rnorm = ps->rnorm;
+            break;
+          }
+          load_dots();
+          job.reset(new RestartJob);
+          job->jr = j;
+          job->nev = nev;
+          job->cols = cols;
+          job->prev = rb;
+          job->h = hh;
+          job->th = std::thread([jp = job.get()]() { jp->run(); });
         }
-        load_dots();
-        job.reset(new RestartJob);
-        job->jr = j;
-        job->nev = nev;
-        job->cols = cols;
-        job->prev = rb;
-        job->h = hh;
-        job->th = std::thread([jp = job.get()]() { jp->run(); });
         cols.clear();
         for (int k = 0; k < 2 * nev; ++k) cols.push_back(Col{1, k, -1});
       }
@@ -1289,25 +1437,27 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
       cols.push_back(Col{0, j - 1, slot_of_r[j - 1]});
       // a pending restart needs 2 nev free slots for its rotated columns: once
       // the lag has used up the spare slots, wait for it
-      if (job && free_slots.size() <= size_t(2 * nev)) apply_job();
+      if ((job || djob) && free_slots.size() <= size_t(2 * nev)) apply_job();
       if (free_slots.empty()) fail(EB_ERR_INVALID, "window slots exhausted");
       const int snew = free_slots.front();
       free_slots.pop_front();
       slot_of_r[j] = snew;
       const int sold = slot_of_r[j - 1];
       TIMED(EB_K_BICG_UPDATE_R, s,
-            launch_bicg_update_r(V(snew), g5 ? nullptr : W(snew), V(sold), g5 ? nullptr : W(sold), Ap + cur * N,
-                                 g5 ? nullptr : Adp + cur * N, N, j, S, dh, op->rs(), g5, s));
-      if (job && job->done.load(std::memory_order_acquire)) apply_job();
+            launch_bicg_update_r(Rrec(j, snew), g5 ? nullptr : RHrec(j, snew), Rrec(j - 1, sold),
+                                 g5 ? nullptr : RHrec(j - 1, sold), Ap + cur * N, g5 ? nullptr : Adp + cur * N, N, j,
+                                 S, dh, op->rs(), g5, s, w32 ? win32.V(snew) : nullptr,
+                                 (w32 && !g5) ? win32.W(snew) : nullptr));
+      if (job_done()) apply_job();
       TIMED(EB_K_BICG_UPDATE_P, s,
-            launch_bicg_update_p(x, p, g5 ? nullptr : ph, V(snew), g5 ? nullptr : W(snew), N, j, S, dh, op->rs(), g5,
-                                 s));
+            launch_bicg_update_p(x, p, g5 ? nullptr : ph, Rrec(j, snew), g5 ? nullptr : RHrec(j, snew), N, j, S, dh,
+                                 op->rs(), g5, s));
       if (int(cols.size()) == m) {
         // the next iteration restarts: the previous restart must be applied
-        // first; then ship the history through j (complete after update_p)
-        // and the arrow dots
+        // first; then (host restarts) ship the history through j (complete
+        // after update_p) and the arrow dots
         apply_job();
-        if (int(cols.size()) == m) {
+        if (int(cols.size()) == m && !dev) {
           copy_history(j);
           copy_dots();
           HIPCHK(hipMemcpyAsync(pstate.p, S, sizeof(KrylovState), hipMemcpyDeviceToHost, s));
@@ -1329,54 +1479,76 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
     reason = hs.stopped ? hs.reason : 4;
     rnorm = hs.rnorm;
   }
-  // roll the window back to iteration stop_at: columns r_i with i >= stop_at
+  if (job || djob) apply_job();
+  // roll back the window to iteration stop_at: columns r_i with i >= stop_at
   // were appended by iterations that did not run
   {
     std::vector<Col> nc;
     for (const Col &c : cols)
-      if (c.ritz || c.idx < stop_at) nc.push_back(c);
+      if ((c.ritz && c.slot >= 0) || (!c.ritz && c.idx < stop_at)) nc.push_back(c);
     cols.swap(nc);
   }
-  if (job) apply_job();
   out.iters = stop_at;
   out.reason = reason;
   out.rnorm = rnorm;
   if (reason == 2) return out;
   // final eigenpairs from V^(vs), W^(vs), H^(vs) (Alg. eigBiCG, last step)
-  copy_history(stop_at);
-  copy_dots();
-  HIPCHK(hipStreamSynchronize(s));
-  load_dots();
   const int vs = int(cols.size());
-  if (vs > 0) {
+  if (vs == 0) return out;
+  const int k = std::min(nev, vs);
+  const double2 *cV = nullptr, *cW = nullptr;
+  if (dev) {
+    const int rf = 2;
+    double2 *fV = coef + size_t(dring) * 2 * ncoef, *fW = fV + ncoef;
+    launch_window_eig(win_cols(cols), nev, 1, dh, lamd + size_t(last_lam) * kLamStride, dots, fV, fW,
+                      lamd + size_t(rf) * kLamStride, keptd + rf, wsd, 0, nullptr, s);
+    HIPCHK(hipMemcpyAsync(&mir[rf].kept, keptd + rf, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(mir[rf].lam, lamd + size_t(rf) * kLamStride, kLamStride * sizeof(double2),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (mir[rf].kept != k) fail(EB_ERR_EIG, "final eig(H^(vs)) on the device did not converge");
+    for (int c = 0; c < k; ++c) out.ritz.push_back(c2(mir[rf].lam[c]));
+    cV = fV;
+    cW = fW;
+  } else {
+    copy_history(stop_at);
+    copy_dots();
+    HIPCHK(hipStreamSynchronize(s));
+    load_dots();
     CMat H = build_H(cols, hh, rb);
     std::vector<cd> lam;
     CMat y, z;
     if (!eig_small(H, lam, y, z)) fail(EB_ERR_EIG, "final eig(H^(vs)) failed");
-    const int k = std::min(nev, vs);
     out.ritz.assign(lam.begin(), lam.begin() + k);
-    if (op->Kcap - op->K >= k) {
-      std::vector<cd> eta, zeta;
-      col_scales(cols, hh, eta, zeta);
-      std::vector<double2> cv(size_t(vs) * k), cw(size_t(vs) * k);
-      for (int c = 0; c < k; ++c)
-        for (int i = 0; i < vs; ++i) {
-          cv[i + size_t(c) * vs] = d2(eta[i] * y(i, c));
-          cw[i + size_t(c) * vs] = d2(zeta[i] * z(i, c));
-        }
-      const auto coef = upload_coef(cv, cw);
-      double2 *const cV = coef.first, *const cW = coef.second;
-      SlotList in{}, o1{};
-      in.n = vs;
-      for (int c = 0; c < vs; ++c) in.idx[c] = cols[c].slot;
-      o1.n = k;
-      for (int c = 0; c < k; ++c) o1.idx[c] = op->K + c;
-      launch_rotate(op->Ur.as<double2>(), o1, Vw, in, cV, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
-      launch_rotate(op->Ul.as<double2>(), o1, Vw, left_inputs(cols), cW, N, nullptr, 0, nullptr, 0, nullptr, op->rs(),
-                    s);
-      HIPCHK(hipStreamSynchronize(s));
-      out.nvec = k;
+    std::vector<cd> eta, zeta;
+    col_scales(cols, hh, eta, zeta);
+    std::vector<double2> cv(size_t(vs) * k), cw(size_t(vs) * k);
+    for (int c = 0; c < k; ++c)
+      for (int i = 0; i < vs; ++i) {
+        cv[i + size_t(c) * vs] = d2(eta[i] * y(i, c));
+        cw[i + size_t(c) * vs] = d2(zeta[i] * z(i, c));
+      }
+    const auto cf = upload_coef(cv, cw);
+    cV = cf.first;
+    cW = cf.second;
+  }
+  if (op->Kcap - op->K >= k) {
+    SlotList in{}, o1{};
+    in.n = vs;
+    for (int c = 0; c < vs; ++c) in.idx[c] = cols[c].slot;
+    o1.n = k;
+    for (int c = 0; c < k; ++c) o1.idx[c] = op->K + c;
+    if (w32) {
+      launch_rotate(op->Ur.as<double2>(), o1, win32.base, in, cV, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
+      launch_rotate(op->Ul.as<double2>(), o1, win32.base, left_inputs(cols), cW, N, nullptr, 0, nullptr, 0, nullptr,
+                    op->rs(), s);
+    } else {
+      launch_rotate(op->Ur.as<double2>(), o1, win64.base, in, cV, N, nullptr, 0, nullptr, 0, nullptr, op->rs(), s);
+      launch_rotate(op->Ul.as<double2>(), o1, win64.base, left_inputs(cols), cW, N, nullptr, 0, nullptr, 0, nullptr,
+                    op->rs(), s);
     }
+    HIPCHK(hipStreamSynchronize(s));
+    out.nvec = k;
   }
   return out;
 }
@@ -1759,6 +1931,8 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     if (P->m + 1 > kMaxCols || 2 * P->nev > 64) fail(EB_ERR_INVALID, "window too large (m <= 127, nev <= 32)");
     if (!(P->tol > 0) || P->maxiter < 1) fail(EB_ERR_INVALID, "tol > 0 and maxiter >= 1 required");
     if (P->rhat < 0 || P->rhat > 2) fail(EB_ERR_INVALID, "rhat must be 0, 1 or 2");
+    if (P->window != EB_FP64 && P->window != EB_FP32) fail(EB_ERR_INVALID, "window must be EB_FP64 or EB_FP32");
+    if (P->device_eig != 0 && P->device_eig != 1) fail(EB_ERR_INVALID, "device_eig must be 0 or 1");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
@@ -2090,6 +2264,46 @@ eb_status eb_small_eig(int32_t n, const double *Cin, double *lambda, double *y, 
           z[2 * (i * n + j) + 1] = Z(i, j).imag();
         }
       }
+  });
+}
+
+eb_status eb_small_eig_device(int32_t n, const double *Cin, double *lambda, double *y, double *z) {
+  return guarded([&]() {
+    if (n < 1 || n > kMaxCols || !Cin || !lambda) fail(EB_ERR_INVALID, "need 1 <= n <= 128 and non-null C, lambda");
+    const size_t nn = size_t(n) * n;
+    std::vector<double2> hc(nn), hy(nn), hz(nn), hl(n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) hc[i + size_t(j) * n] = make_double2(Cin[2 * (i * n + j)], Cin[2 * (i * n + j) + 1]);
+    DevBuf d;
+    d.ensure((3 * nn + n + window_eig_ws_entries(n)) * sizeof(double2) + 256);
+    double2 *dc = d.as<double2>(), *dy = dc + nn, *dz = dy + nn, *dl = dz + nn, *ws = dl + n;
+    int *dst = reinterpret_cast<int *>(ws + window_eig_ws_entries(n));
+    hipStream_t s = nullptr;
+    HIPCHK(hipMemcpyAsync(dc, hc.data(), nn * sizeof(double2), hipMemcpyHostToDevice, s));
+    launch_small_eig(dc, n, dl, dy, dz, ws, dst, s);
+    HIPCHK(hipGetLastError());
+    int status = 0;
+    HIPCHK(hipMemcpyAsync(hy.data(), dy, nn * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hz.data(), dz, nn * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hl.data(), dl, n * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&status, dst, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    d.release();
+    if (status != 1) fail(EB_ERR_EIG, "device QR iteration did not converge");
+    for (int i = 0; i < n; ++i) {
+      lambda[2 * i] = hl[i].x;
+      lambda[2 * i + 1] = hl[i].y;
+      for (int j = 0; j < n; ++j) {
+        if (y) {
+          y[2 * (i * n + j)] = hy[i + size_t(j) * n].x;
+          y[2 * (i * n + j) + 1] = hy[i + size_t(j) * n].y;
+        }
+        if (z) {
+          z[2 * (i * n + j)] = hz[i + size_t(j) * n].x;
+          z[2 * (i * n + j) + 1] = hz[i + size_t(j) * n].y;
+        }
+      }
+    }
   });
 }
 

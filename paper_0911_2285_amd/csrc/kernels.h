@@ -138,10 +138,12 @@ void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const doubl
                         const Geom &g, double kappa, int j, KrylovState *S, KrylovHistory h, const RedScratch &rs,
                         bool g5, hipStream_t st);
 // alpha_{j-1} = rho_{j-1} / sigma; r_out = r_in - alpha Ap; rhat_out = rhat_in - conj(alpha) Adp;
-// partials of rho_j and ||r_j||^2.
+// partials of rho_j and ||r_j||^2.  w32r / w32rh (may be null): FP32 copies of
+// r_out / rhat_out (the window of an FP32-window eigBiCG).
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                          const RedScratch &rs, bool g5, hipStream_t st);
+                          const RedScratch &rs, bool g5, hipStream_t st, float2 *w32r = nullptr,
+                          float2 *w32rh = nullptr);
 // beta_{j-1}, rho_j, ||r_j|| and the stop test; x += alpha p; p = r + beta p; phat = rhat + conj(beta) phat.
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
                           KrylovState *S, KrylovHistory h, const RedScratch &rs, bool g5, hipStream_t st);
@@ -155,6 +157,14 @@ void launch_arrow_vectors(double2 *GA, double2 *GB, const double2 *Adp, const do
 // N = 12 V: components 6..11 flip sign).
 // If g != null: dots[k] = g^+ out[k] (conj_out = 0) or out[k]^+ g (conj_out = 1).
 void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *in_base, const SlotList &in_slots,
+                   const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
+                   const KrylovState *S, const RedScratch &rs, hipStream_t st);
+// The same for an FP32 window: FP32 columns in, FP32 (window) or FP64 (the
+// deflation space) columns out; coefficients, sums and dots in FP64.
+void launch_rotate(float2 *out_base, const SlotList &out_slots, const float2 *in_base, const SlotList &in_slots,
+                   const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
+                   const KrylovState *S, const RedScratch &rs, hipStream_t st);
+void launch_rotate(double2 *out_base, const SlotList &out_slots, const float2 *in_base, const SlotList &in_slots,
                    const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
                    const KrylovState *S, const RedScratch &rs, hipStream_t st);
 
@@ -229,6 +239,12 @@ void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, co
                     const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
                     const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
                     size_t part_cap, hipStream_t st);
+void launch_combine(float2 *out_base, const SlotList &out_slots, size_t ldo, const float2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, size_t N, const double2 *g, int conj_out,
+                    double2 *dots, int jtag, const KrylovState *S, double *part, size_t part_cap, hipStream_t st);
+void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, const float2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, size_t N, const double2 *g, int conj_out,
+                    double2 *dots, int jtag, const KrylovState *S, double *part, size_t part_cap, hipStream_t st);
 
 // ---- BLAS-1 (FP64) ---------------------------------------------------------------
 void launch_copy_f64(double2 *dst, const double2 *src, size_t n, hipStream_t st);
@@ -261,6 +277,31 @@ void launch_stab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rha
 template <typename S>
 void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
                    const RedScratch &rs, hipStream_t st);
+
+// ---- window eigenproblems on the device (winrestart.hip) -----------------------------
+// eig(C) of an n x n column-major matrix by one workgroup (conventions of the
+// host eig_small); ws: window_eig_ws_entries(n) complex; *status = 1 on success.
+size_t window_eig_ws_entries(int n);
+void launch_small_eig(const double2 *C, int n, double2 *lam, double2 *y, double2 *z, double2 *ws, int *status,
+                      hipStream_t st);
+// The columns of an eigBiCG window: column c is Ritz vector idx[c] of the last
+// restart (ritz[c] = 1) or the stored residual r_idx[c] (ritz[c] = 0).
+struct WinCols {
+  int n;
+  int idx[kMaxCols];
+  unsigned char ritz[kMaxCols];
+};
+// Alg. BiCG-eigen (mode 0) or the final extraction (mode 1) of the window
+// `cols` by one workgroup, from the device history h, the last restart's Ritz
+// values lam_prev and raw arrow dots dots_prev (dV at [0, 2nev), dW at [2nev,
+// 4nev)).  Outputs: cV, cW (cols.n x kout coefficient blocks with the stored
+// residuals' scales folded in; kout = 2 nev, or min(nev, n) in mode 1), lam_out,
+// *kept_out (-1 if an eigenproblem failed).  Skipped when the solve stopped
+// before iteration jtag.  ws: window_restart_ws_entries(cols.n, nev) complex.
+size_t window_restart_ws_entries(int m, int nev);
+void launch_window_eig(const WinCols &cols, int nev, int mode, const KrylovHistory &h, const double2 *lam_prev,
+                       const double2 *dots_prev, double2 *cV, double2 *cW, double2 *lam_out, int *kept_out,
+                       double2 *ws, int jtag, const KrylovState *S, hipStream_t st);
 
 // ---- multi-RHS batches (batch.hip) ------------------------------------------------
 // A batch holds kc right-hand sides interleaved as the fastest index: element

@@ -243,7 +243,8 @@ __global__ void __launch_bounds__(kBlock)
     k_bicg_update_r(double2 *__restrict__ r_out, double2 *__restrict__ rh_out, const double2 *__restrict__ r_in,
                     const double2 *__restrict__ rh_in, const double2 *__restrict__ Ap,
                     const double2 *__restrict__ Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                    const double *__restrict__ part_sigma, int nb_sigma, double *__restrict__ part) {
+                    const double *__restrict__ part_sigma, int nb_sigma, double *__restrict__ part,
+                    float2 *__restrict__ w32r, float2 *__restrict__ w32rh) {
   if (skip_iter(S, j)) return;
   double sg[2];
   sum_partials<2, kBlock>(part_sigma, nb_sigma, sg);
@@ -265,12 +266,14 @@ __global__ void __launch_bounds__(kBlock)
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < N; i += size_t(gridDim.x) * kBlock) {
     cx<double> r = Store<double2>::ld(r_in, i) - a * Store<double2>::ld(Ap, i);
     Store<double2>::st(r_out, i, r);
+    if (w32r) Store<float2>::st(w32r, i, r);
     const double rr = r.x * r.x + r.y * r.y;
     if constexpr (G5) {
       v[0] += i < half ? rr : -rr;
     } else {
       cx<double> rh = Store<double2>::ld(rh_in, i) - ac * Store<double2>::ld(Adp, i);
       Store<double2>::st(rh_out, i, rh);
+      if (w32rh) Store<float2>::st(w32rh, i, rh);
       cx<double> d = cmulc(rh, r);
       v[0] += d.x;
       v[1] += d.y;
@@ -719,15 +722,15 @@ void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const doubl
 }
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                          const RedScratch &rs, bool g5, hipStream_t st) {
+                          const RedScratch &rs, bool g5, hipStream_t st, float2 *w32r, float2 *w32rh) {
   // the matvec wrote one sigma record per block of its grid; N = 12 V
   const int V = int(N / 12);
   if (g5)
     EB_LAUNCH(k_bicg_update_r<true>, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N,
-              j, S, h, region(rs, RG_SIGMA), stencil_grid(V), region(rs, RG_RR));
+              j, S, h, region(rs, RG_SIGMA), stencil_grid(V), region(rs, RG_RR), w32r, w32rh);
   else
     EB_LAUNCH(k_bicg_update_r<false>, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N,
-              j, S, h, region(rs, RG_SIGMA), matvec_grid(V), region(rs, RG_RR));
+              j, S, h, region(rs, RG_SIGMA), matvec_grid(V), region(rs, RG_RR), w32r, w32rh);
 }
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
                           KrylovState *S, KrylovHistory h, const RedScratch &rs, bool g5, hipStream_t st) {
@@ -752,6 +755,18 @@ void launch_rotate(double2 *out_base, const SlotList &out_slots, const double2 *
                    const KrylovState *S, const RedScratch &rs, hipStream_t st) {
   launch_combine(out_base, out_slots, N, in_base, in_slots, N, C, 1.0, false, N, g, conj_out, dots, jtag, S,
                       region(rs, RG_GEN), kMaxPartials - size_t(RG_GEN) * kRegion, st);
+}
+void launch_rotate(float2 *out_base, const SlotList &out_slots, const float2 *in_base, const SlotList &in_slots,
+                   const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
+                   const KrylovState *S, const RedScratch &rs, hipStream_t st) {
+  launch_combine(out_base, out_slots, N, in_base, in_slots, N, C, N, g, conj_out, dots, jtag, S, region(rs, RG_GEN),
+                 kMaxPartials - size_t(RG_GEN) * kRegion, st);
+}
+void launch_rotate(double2 *out_base, const SlotList &out_slots, const float2 *in_base, const SlotList &in_slots,
+                   const double2 *C, size_t N, const double2 *g, int conj_out, double2 *dots, int jtag,
+                   const KrylovState *S, const RedScratch &rs, hipStream_t st) {
+  launch_combine(out_base, out_slots, N, in_base, in_slots, N, C, N, g, conj_out, dots, jtag, S, region(rs, RG_GEN),
+                 kMaxPartials - size_t(RG_GEN) * kRegion, st);
 }
 
 template <int XT, int YT>

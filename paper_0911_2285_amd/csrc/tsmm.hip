@@ -159,9 +159,11 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 // G5IN: an input slot -(slot + 1) is read as gamma5 times that column (spinor
 // columns of length N = 12 V: the second half, components 6..11, flips sign).
-template <int NT, bool ADD, bool DOTS, bool G5IN>
+// TI, TO: storage of the input and output columns (double2, or float2 for an
+// FP32 window); coefficients, accumulation and dots stay FP64.
+template <typename TI, typename TO, int NT, bool ADD, bool DOTS, bool G5IN>
 __global__ void __launch_bounds__(kBlock)
-    k_combine(double2 *out_base, SlotList out_slots, size_t ldo, const double2 *in_base, SlotList in_slots,
+    k_combine(TO *out_base, SlotList out_slots, size_t ldo, const TI *in_base, SlotList in_slots,
               size_t ldi, const double2 *__restrict__ C, double sgn, size_t N, const double2 *__restrict__ g,
               int conj_out, double *__restrict__ part, int jtag, const KrylovState *S) {
   if (S && S->stopped && jtag > S->stop_at) return;
@@ -175,11 +177,11 @@ __global__ void __launch_bounds__(kBlock)
     if constexpr (G5IN) {
       const bool flip = sc < 0;
       if (flip) sc = -sc - 1;
-      const double2 t = in_base[size_t(sc) * ldi + i];
-      return (flip && i >= half) ? cx<double>{-t.x, -t.y} : cx<double>{t.x, t.y};
+      const TI t = in_base[size_t(sc) * ldi + i];
+      return (flip && i >= half) ? cx<double>{-double(t.x), -double(t.y)} : cx<double>{double(t.x), double(t.y)};
     } else {
-      const double2 t = in_base[size_t(sc) * ldi + i];
-      return {t.x, t.y};
+      const TI t = in_base[size_t(sc) * ldi + i];
+      return {double(t.x), double(t.y)};
     }
   };
   cx<double> acc[NT];
@@ -209,14 +211,17 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       if (k >= nk) continue;
-      double2 *oc = out_base + size_t(out_slots.idx[k0 + k]) * ldo;
-      double2 o = make_double2(sgn * acc[k].x, sgn * acc[k].y);
-      if (ADD) {
-        const double2 old = oc[i];
-        o = make_double2(old.x + o.x, old.y + o.y);
+      TO *oc = out_base + size_t(out_slots.idx[k0 + k]) * ldo;
+      cx<double> o = {sgn * acc[k].x, sgn * acc[k].y};
+      if constexpr (ADD) {
+        const TO old = oc[i];
+        o = {double(old.x) + o.x, double(old.y) + o.y};
       }
-      oc[i] = o;
-      acc[k] = {o.x, o.y};
+      if constexpr (std::is_same<TO, double2>::value)
+        oc[i] = make_double2(o.x, o.y);
+      else
+        oc[i] = make_float2(float(o.x), float(o.y));
+      acc[k] = o;
     }
   };
   if constexpr (!DOTS) {
@@ -259,9 +264,9 @@ __global__ void __launch_bounds__(kBlock)
 // Partial dots of g with NT output columns of a rotation (column group
 // blockIdx.y): g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1); records
 // element-major, part[(blockIdx.y 2NT + e) gridDim.x + blockIdx.x].
-template <int NT>
+template <typename TO, int NT>
 __global__ void __launch_bounds__(kBlock)
-    k_slot_dots(const double2 *base, SlotList slots, size_t ld, const double2 *__restrict__ g, size_t N, int conj_out,
+    k_slot_dots(const TO *base, SlotList slots, size_t ld, const double2 *__restrict__ g, size_t N, int conj_out,
                 int jtag, const KrylovState *S, double *__restrict__ part) {
   if (S && S->stopped && jtag > S->stop_at) return;
   const int k0 = blockIdx.y * NT;
@@ -274,7 +279,8 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       if (k >= nk) continue;
-      const double2 o = base[size_t(slots.idx[k0 + k]) * ld + i];
+      const TO ov = base[size_t(slots.idx[k0 + k]) * ld + i];
+      const double2 o = make_double2(double(ov.x), double(ov.y));
       if (conj_out) {  // conj(o) g
         dv[2 * k] += o.x * gv.x + o.y * gv.y;
         dv[2 * k + 1] += o.x * gv.y - o.y * gv.x;
@@ -337,10 +343,11 @@ void launch_gram_mfma(double2 *out, const double2 *X, size_t ldx, int nx, const 
   EB_LAUNCH(k_gram_finish, dim3(TA * TB, kTile), dim3(kBlock), 0, st, out, part, int(nb), TA, nx, ny);
 }
 
-void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
-                    const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
-                    const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
-                    size_t part_cap, hipStream_t st) {
+template <typename TI, typename TO>
+void launch_combine_t(TO *out_base, const SlotList &out_slots, size_t ldo, const TI *in_base,
+                      const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
+                      const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
+                      size_t part_cap, hipStream_t st) {
   const int nin = in_slots.n, nout = out_slots.n;
   if (nin < 1 || nout < 1 || N == 0) return;
   auto go = [&](auto nt_tag) {
@@ -354,8 +361,12 @@ void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, co
     for (int c = 0; c < nin; ++c) g5in = g5in || in_slots.idx[c] < 0;
     auto launch = [&](auto add_tag, auto dots_tag, auto g5_tag, dim3 gr) {
       constexpr bool A = decltype(add_tag)::value, D = decltype(dots_tag)::value, G = decltype(g5_tag)::value;
-      EB_LAUNCH((k_combine<NT, A, D, G>), gr, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base, in_slots, ldi,
-                C, sgn, N, g, conj_out, part, jtag, S);
+      if constexpr (A && !std::is_same<TO, double2>::value) {
+        return;  // accumulating outputs are FP64 only (the host never asks for FP32 ones)
+      } else {
+        EB_LAUNCH((k_combine<TI, TO, NT, A, D, G>), gr, dim3(kBlock), 0, st, out_base, out_slots, ldo, in_base,
+                  in_slots, ldi, C, sgn, N, g, conj_out, part, jtag, S);
+      }
     };
     using T = std::true_type;
     using F = std::false_type;
@@ -385,8 +396,8 @@ void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, co
       dcap = dcap < 1024 ? dcap : 1024;
       nd = nd < dcap ? nd : dcap;
       if (nd < 1) nd = 1;
-      EB_LAUNCH(k_slot_dots<NT>, dim3(unsigned(nd), unsigned(groups)), dim3(kBlock), 0, st, out_base, out_slots, ldo,
-                g, N, conj_out, jtag, S, part);
+      EB_LAUNCH((k_slot_dots<TO, NT>), dim3(unsigned(nd), unsigned(groups)), dim3(kBlock), 0, st, out_base,
+                out_slots, ldo, g, N, conj_out, jtag, S, part);
       EB_LAUNCH(k_combine_dots<NT>, dim3(groups * 2 * NT), dim3(kBlock), 0, st, part, int(nd), nout, dots, jtag, S);
     }
   };
@@ -402,6 +413,26 @@ void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, co
     go(std::integral_constant<int, 20>{});
   else
     go(std::integral_constant<int, 24>{});
+}
+
+void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, const double2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, double sgn, bool add, size_t N,
+                    const double2 *g, int conj_out, double2 *dots, int jtag, const KrylovState *S, double *part,
+                    size_t part_cap, hipStream_t st) {
+  launch_combine_t(out_base, out_slots, ldo, in_base, in_slots, ldi, C, sgn, add, N, g, conj_out, dots, jtag, S, part,
+                   part_cap, st);
+}
+void launch_combine(float2 *out_base, const SlotList &out_slots, size_t ldo, const float2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, size_t N, const double2 *g, int conj_out,
+                    double2 *dots, int jtag, const KrylovState *S, double *part, size_t part_cap, hipStream_t st) {
+  launch_combine_t(out_base, out_slots, ldo, in_base, in_slots, ldi, C, 1.0, false, N, g, conj_out, dots, jtag, S,
+                   part, part_cap, st);
+}
+void launch_combine(double2 *out_base, const SlotList &out_slots, size_t ldo, const float2 *in_base,
+                    const SlotList &in_slots, size_t ldi, const double2 *C, size_t N, const double2 *g, int conj_out,
+                    double2 *dots, int jtag, const KrylovState *S, double *part, size_t part_cap, hipStream_t st) {
+  launch_combine_t(out_base, out_slots, ldo, in_base, in_slots, ldi, C, 1.0, false, N, g, conj_out, dots, jtag, S,
+                   part, part_cap, st);
 }
 
 }  // namespace ebicg

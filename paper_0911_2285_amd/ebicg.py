@@ -48,6 +48,8 @@ class _EigParams(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("maxiter", ctypes.c_int32),
         ("rhat", ctypes.c_int32),
+        ("window", ctypes.c_int32),
+        ("device_eig", ctypes.c_int32),
     ]
 
 
@@ -115,6 +117,7 @@ _SIGNATURES = [
     ("eb_defl_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
     ("eb_defl_reset", ctypes.c_int, [_P]),
     ("eb_small_eig", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
+    ("eb_small_eig_device", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P]),
     ("eb_timing_enable", ctypes.c_int, [_P, ctypes.c_int32]),
     ("eb_timing_classes", ctypes.c_int, [_P, ctypes.c_uint32]),
     ("eb_timing_read", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
@@ -196,6 +199,17 @@ def small_eig(C):
     y = np.zeros((n, n), np.complex128)
     z = np.zeros((n, n), np.complex128)
     _check(lib().eb_small_eig(n, C.ctypes.data, lam.ctypes.data, y.ctypes.data, z.ctypes.data))
+    return y, z, lam
+
+
+def small_eig_device(C):
+    """The same eigenproblem solved by the library's one-workgroup device solver."""
+    C = np.ascontiguousarray(C, dtype=np.complex128)
+    n = C.shape[0]
+    lam = np.zeros(n, np.complex128)
+    y = np.zeros((n, n), np.complex128)
+    z = np.zeros((n, n), np.complex128)
+    _check(lib().eb_small_eig_device(n, C.ctypes.data, lam.ctypes.data, y.ctypes.data, z.ctypes.data))
     return y, z, lam
 
 
@@ -298,14 +312,15 @@ def op_apply_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
     _check(lib().eb_op_apply_block(op.handle, po, pi, int(k), int(bool(dagger)), PREC[prec], _stream(stream)))
 
 
-def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, stream=None):
+def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, window="fp64", device_eig=False, stream=None):
     """One eigBiCG solve that grows the deflation space; returns (stats, ritz values).
 
     rhat: 0 -> rhat_0 = r_0; 1 -> gamma5 r_0; 2 -> the gamma5-Hermitian form
-    (shadow vectors implicit, one D per iteration)."""
+    (shadow vectors implicit, one D per iteration).  window: "fp64" or "fp32"
+    storage of the window vectors; device_eig: the window eigenproblems on the GPU."""
     import torch
 
-    p = _EigParams(int(nev), int(m), float(tol), int(maxiter), int(rhat))
+    p = _EigParams(int(nev), int(m), float(tol), int(maxiter), int(rhat), PREC[window], int(bool(device_eig)))
     st = _Stats()
     ritz = np.zeros(int(nev), np.complex128)
     rc = lib().eb_eigbicg_solve(
