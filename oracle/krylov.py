@@ -93,21 +93,22 @@ def _biorth_gs(Y, Z, start, passes=2, tol=1e-12):
     return np.stack(ys, axis=1), np.stack(zs, axis=1)
 
 
-def bicg_eigen(nev, m, H):
-    """Alg. BiCG-eigen in coefficient space.
+def bicg_eigen(nev, m, H, which="SM"):
+    """Alg. BiCG-eigen in coefficient space; ``which`` is the sort criterion of
+    every eig() call (oracle.eig.sort_order).
 
     Returns (CV, CW, Lam): the restarted bases are V_old @ CV and W_old @ CW,
     and the restarted H is diag(Lam).
     """
-    y, z, _ = eig(H[:m, :m])
-    y1, z1, _ = eig(H[: m - 1, : m - 1])
+    y, z, _ = eig(H[:m, :m], which)
+    y1, z1, _ = eig(H[: m - 1, : m - 1], which)
     y1 = np.vstack([y1, np.zeros((1, m - 1))])  # append a zero to each vector
     z1 = np.vstack([z1, np.zeros((1, m - 1))])
     Y = np.hstack([y[:, :nev], y1[:, :nev]])
     Z = np.hstack([z[:, :nev], z1[:, :nev]])
     Yt, Zt = _biorth_gs(Y, Z, start=nev)
     T = Zt.conj().T @ H[:m, :m] @ Yt
-    u, q, Lam = eig(T)
+    u, q, Lam = eig(T, which)
     CV = Yt @ u
     CW = Zt @ q
     sc = np.linalg.norm(CV, axis=0)
@@ -135,11 +136,13 @@ class EigBiCGResult:
     matvecs: int = 0
 
 
-def eigbicg(A, Ad, b, x0, nev, m, tol, maxiter=10000, rhat0=None, keep_restarts=False):
+def eigbicg(A, Ad, b, x0, nev, m, tol, maxiter=10000, rhat0=None, keep_restarts=False, which="SM"):
     """Alg. eigBiCG: two-sided BiCG that keeps a window of m residuals.
 
     With m >= iterations + 1 no restart occurs and this is the un-restarted
-    BiCG that stores every residual (the comparison run of Table 1).
+    BiCG that stores every residual (the comparison run of Table 1).  ``which``
+    selects the eigenpairs kept at each restart and returned (the sort
+    criterion of eig(), Sec. 1, end).
     """
     if m <= 2 * nev:
         raise ValueError("eigBiCG needs m > 2 nev")
@@ -179,7 +182,7 @@ def eigbicg(A, Ad, b, x0, nev, m, tol, maxiter=10000, rhat0=None, keep_restarts=
             q, s = Ap.copy(), Adp.copy()
         if vs == m:
             rec = RestartRecord(H_before=H.copy(), CV=None, CW=None, Lam=None)
-            CV, CW, Lam = bicg_eigen(nev, m, H)
+            CV, CW, Lam = bicg_eigen(nev, m, H, which)
             kept = CV.shape[1]
             Vn, Wn = V @ CV, W @ CW
             V[:] = 0
@@ -235,7 +238,7 @@ def eigbicg(A, Ad, b, x0, nev, m, tol, maxiter=10000, rhat0=None, keep_restarts=
     res.x, res.iters, res.matvecs = x, j, matvecs
     # final nev eigenpairs from V^(vs), W^(vs), H^(vs)
     if vs > 0:
-        y, z, lam = eig(H[:vs, :vs])
+        y, z, lam = eig(H[:vs, :vs], which)
         k = min(nev, vs)
         U = V[:, :vs] @ y[:, :k]
         Q = W[:, :vs] @ z[:, :k]

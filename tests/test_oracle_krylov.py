@@ -61,6 +61,39 @@ def test_sort_ties_imag_descending():
     assert [lam[i] for i in order] == [0.5, -0.5j, 1 + 1j, 1 - 1j]
 
 
+def test_sort_criteria():
+    """The three criteria of eig()'s sort (Sec. 1, end: a user-chosen criterion)."""
+    lam = np.array([2 + 0.1j, -0.3, 0.5j, 1.0, -1 - 1j, 0.2 + 1j, 0.2 - 1j])
+    got = {w: [lam[i] for i in sort_order(lam, w)] for w in ("SM", "SR", "LM")}
+    assert got["SM"] == [-0.3, 0.5j, 1.0, 0.2 + 1j, 0.2 - 1j, -1 - 1j, 2 + 0.1j]
+    assert got["SR"] == [-1 - 1j, -0.3, 0.5j, 0.2 + 1j, 0.2 - 1j, 1.0, 2 + 0.1j]
+    assert got["LM"] == [2 + 0.1j, -1 - 1j, 0.2 + 1j, 0.2 - 1j, 1.0, 0.5j, -0.3]
+    with pytest.raises(ValueError):
+        sort_order(lam, "LR")
+
+
+@pytest.mark.parametrize("normal", [True, False])
+def test_bicg_eigen_keeps_the_criterion_pairs(normal):
+    """Alg. BiCG-eigen on an H with a known spectrum: the eigenvectors of H^(m) it keeps
+    are exact, so the restarted H = diag(Lam) leads with the nev eigenvalues the
+    criterion selects (smallest modulus, smallest real part, largest modulus)."""
+    rng = np.random.default_rng(2)
+    m, nev = 16, 4
+    left = [0.05 + 1.5j, 0.05 - 1.5j, 0.08 + 1.6j, 0.08 - 1.6j]  # smallest real parts, |lambda| ~ 1.5
+    small = [0.3, 0.35, 0.4 + 0.05j, 0.4 - 0.05j]  # smallest moduli
+    large = [4.0, 4.5 + 0.2j, 4.5 - 0.2j, 5.0]
+    mu = np.array(left + small + large + [1.0 + 0.1j, 1.5, 2.0 - 0.2j, 2.5])
+    X = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    S = np.linalg.qr(X)[0] if normal else np.eye(m) + 0.2 * X / np.sqrt(m)
+    H = S @ np.diag(mu) @ np.linalg.inv(S)
+    for which, want in (("SM", small), ("SR", left), ("LM", large)):
+        CV, CW, Lam = K.bicg_eigen(nev, m, H, which)
+        assert len(Lam) == 2 * nev
+        assert sorted(np.round(Lam[:nev], 10), key=lambda z: (z.real, z.imag)) == sorted(
+            np.round(np.array(want), 10), key=lambda z: (z.real, z.imag))
+        assert np.abs(CW.conj().T @ H @ CV - np.diag(Lam)).max() < 1e-12
+
+
 # ------------------------------------------------------------------------- BiCG core
 @pytest.mark.parametrize("dims,kappa", [((2, 2, 2, 2), 0.13), ((4, 4, 4, 4), 0.115)])
 def test_bicg_matches_lapack_solve(dims, kappa):
