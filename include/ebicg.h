@@ -56,6 +56,17 @@ typedef enum {
 
 typedef enum { EB_FP64 = 0, EB_FP32 = 1, EB_BF16 = 2 } eb_prec;
 
+/* Sort criterion of the small dense eigenproblem eig(C) (Sec. 1, end: sorted by a
+ * user-chosen criterion; Sec. 2 names the smallest absolute value).  An eigBiCG
+ * solve keeps, at every restart of its window (Alg. BiCG-eigen), and returns the
+ * nev pairs that come first.  Keys equal to 1e-12 relative (to the larger modulus)
+ * are ordered by imaginary part descending. */
+typedef enum {
+  EB_SORT_SMALLEST_MAG = 0,  /* |lambda| ascending (the deflation target; the default) */
+  EB_SORT_SMALLEST_REAL = 1, /* real part ascending (the left edge of the Wilson-Dirac spectrum) */
+  EB_SORT_LARGEST_MAG = 2    /* |lambda| descending */
+} eb_sort;
+
 /* Parameters of one eigBiCG solve (Alg. eigBiCG). */
 typedef struct {
   int32_t nev;     /* eigenpairs kept per restart and returned (2 nev < m) */
@@ -77,6 +88,8 @@ typedef struct {
   int32_t device_eig; /* 0: the window eigenproblems of Alg. BiCG-eigen on a host thread; 1: on the
                       GPU by one workgroup on a side stream, from the device-resident BiCG scalars
                       (the host reads back only the number of pairs kept and the Ritz values) */
+  int32_t sort;       /* eb_sort: which Ritz pairs the window keeps and the solve returns (and absorbs
+                         into the deflation space); ritz[] comes out in this order */
 } eb_eig_params;
 
 /* Parameters of a deflated solve (Alg. Incremental eigBiCG, step 3). */
@@ -325,27 +338,31 @@ eb_status eb_session_poll(eb_session *s, int32_t max, int64_t *tags, int32_t *st
 eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int32_t *done, uint64_t *device_bytes);
 /* ---- Batch autotuning (multi-RHS tile shapes) ------------------------------
  * The batched solvers' operator (the stencil, or Dhat for an even-odd operator)
- * has tile forms for each k: stage = 0 reads every neighbour from global
- * memory with the sites in order; 1 stages each block's tile of 256 / k sites
- * in LDS; 2, 3 and 4 read from global memory with the sites visited in bricks
- * of 8 x 8 x 4 x 4, 8 x 8 x 8 x 8 and 4 x 4 x 4 x 4 sites (full-lattice stencil
- * only, extents divisible by the brick), which keeps more of a site's
+ * has EB_TILE_FORMS tile forms for each k: stage = 0 reads every neighbour from
+ * global memory with the sites in order; 1 stages each block's tile of 256 / k
+ * sites in LDS; 2, 3 and 4 read from global memory with the sites visited in
+ * bricks of 8 x 8 x 4 x 4, 8 x 8 x 8 x 8 and 4 x 4 x 4 x 4 sites (full-lattice
+ * stencil only, extents divisible by the brick), which keeps more of a site's
  * neighbours in L2 when k columns make each site's record large; 5 reads from
  * global memory in site order with the loads of several hops in flight
- * (full-lattice stencil only).  eb_op_batch_tune runs the
+ * (full-lattice stencil only); 6 walks boxes of sites (up to 32 x 16 x 8, 16 x
+ * 16 x 8 for k = 16, 32 x 32 x 8 for k = 1) through chunks of time slices with
+ * the t neighbours held in registers (full-lattice stencil only, a box of a
+ * whole number of 256-thread blocks for k).  eb_op_batch_tune runs the
  * autotuner once per operator and precision (it times every form the
  * operator admits for k = 2, 4, 8, 16, and the LDS-staged form for k = 1,
  * the form of the one-at-a-time solver that a single column runs, on
  * `stream`, three repetitions after a warm-up, and keeps per k the fastest
  * form and overall the k with the lowest time per right-hand side) and reports: *k_best; stage[5] (may be
- * NULL) the form used for k = 1, 2, 4, 8, 16; ms_per_rhs[30] (may be NULL) the
- * measured time per right-hand side, [6 i + form] for k = 2^i (0 for a form
+ * NULL) the form used for k = 1, 2, 4, 8, 16; ms_per_rhs[5 * EB_TILE_FORMS] (may be NULL) the
+ * measured time per right-hand side, [EB_TILE_FORMS i + form] for k = 2^i (0 for a form
  * not admitted).  Batched solves with batch = 0, sessions and
  * eb_op_apply_block / eb_op_apply_schur_block use the forms chosen here
  * (before tuning: LDS staging for k = 1 and for BF16, else form 0). */
+#define EB_TILE_FORMS 7
 eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_best, int32_t *stage,
                            double *ms_per_rhs);
-/* Set the tile form for one precision and k (0..5 as above, or -1 for the built-in rule);
+/* Set the tile form for one precision and k (0..6 as above, or -1 for the built-in rule);
  * results agree to rounding between the forms.  EB_ERR_INVALID for a form the operator does
  * not admit.  Host-only; a later first run of the tuner replaces it. */
 eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage);

@@ -154,6 +154,7 @@ struct eb_op {
   // each form
   int batch_stage[3][kMaxBatch + 1];
   double batch_stage_ms[3][kMaxBatch + 1][kTileForms] = {};
+  static_assert(kTileForms == EB_TILE_FORMS, "the header counts the tile forms");
   eb_op() {
     for (auto &row : batch_stage)
       for (int &v : row) v = -1;
@@ -729,7 +730,7 @@ int tune_batch(eb_op *op, hipStream_t s) {
   for (int kc = 1; kc <= kMaxBatch; kc *= 2) {
     double t_kc = HUGE_VAL;
     for (int stage = 0; stage < kTileForms; ++stage) {  // every tile form this operator admits
-      if (!batch_tile_ok(op->g, op->eo, stage)) continue;
+      if (!batch_tile_ok(op->g, op->eo, stage, kc)) continue;
       // one column runs the one-at-a-time solver, whose stencils stage their
       // tiles in LDS: time k = 1 in that form only
       if (kc == 1 && stage != 1) continue;
@@ -801,13 +802,13 @@ void run_bicgstab_batch(eb_op *op, const S *U, S *x, S *r, int kc, const double 
               launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
       else
         TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
-      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, op->rs(), s));
+      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, op->rs(), s, stage));
       if (op->eo)
         TIMED(EB_K_BSTAB_T, s,
               launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
       else
         TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, op->rs(), s, stage));
-      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, op->rs(), s));
+      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, op->rs(), s, stage));
       TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, gv, j, kc, K, h, op->rs(), s));
     }
   }
@@ -1008,7 +1009,7 @@ void col_scales(const std::vector<Col> &cols, const HostHist &h, std::vector<cd>
 }
 
 struct RestartJob {
-  int jr = 0, nev = 0;
+  int jr = 0, nev = 0, which = 0;
   std::vector<Col> cols;
   RitzBlock prev;
   HostHist h{};
@@ -1027,11 +1028,11 @@ struct RestartJob {
       CMat H = build_H(cols, h, prev);
       std::vector<cd> l1, l2;
       CMat y1, z1, y2, z2;
-      if (!eig_small(H, l1, y1, z1)) throw std::runtime_error("eig(H^(m)) failed");
+      if (!eig_small(H, l1, y1, z1, which)) throw std::runtime_error("eig(H^(m)) failed");
       CMat Hm1(m - 1, m - 1);
       for (int jj = 0; jj < m - 1; ++jj)
         for (int i = 0; i < m - 1; ++i) Hm1(i, jj) = H(i, jj);
-      if (!eig_small(Hm1, l2, y2, z2)) throw std::runtime_error("eig(H^(m-1)) failed");
+      if (!eig_small(Hm1, l2, y2, z2, which)) throw std::runtime_error("eig(H^(m-1)) failed");
       // [y^(m)_1..nev, y^(m-1)_1..nev] with a zero appended to the latter
       CMat Y(m, 2 * nev), Z(m, 2 * nev);
       for (int k = 0; k < nev; ++k)
@@ -1045,7 +1046,7 @@ struct RestartJob {
       // T = Zt^+ H Yt, [u, q, Lambda] = eig(T)
       CMat T = matmul(adjoint(Z), matmul(H, Y));
       CMat u, q;
-      if (!eig_small(T, lam, u, q)) throw std::runtime_error("eig(T) failed");
+      if (!eig_small(T, lam, u, q, which)) throw std::runtime_error("eig(T) failed");
       CMat CV = matmul(Y, u), CW = matmul(Z, q);
       kept = CV.cols;
       std::vector<cd> eta, zeta;
@@ -1104,11 +1105,15 @@ struct DevJob {
 EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_params &P, hipStream_t s) {
   const size_t N = op->N;
   const int m = P.m, nev = P.nev;
-  const int lag = 8;
+  const bool w32 = P.window == EB_FP32;  // FP32 window: FP32 copies of r, rhat in the slots
+  const bool dev = P.device_eig != 0;    // window eigenproblems on the device
+  // iterations a restart may run behind before the solve waits for it (spare
+  // window slots); the device restart (one workgroup per eigenproblem) takes
+  // longer than the host thread and may lag until just before the next
+  // restart is due (m - 2 nev iterations later)
+  const int lag = dev ? std::max(8, std::min(24, m - 2 * nev - 1)) : 8;
   const int nslots = m + 1 + lag + 2 * nev;
   const size_t ncoef = size_t(m + 1) * 2 * nev;  // one coefficient block (m x 2nev complex)
-  const bool w32 = P.window == EB_FP32;          // FP32 window: FP32 copies of r, rhat in the slots
-  const bool dev = P.device_eig != 0;            // window eigenproblems on the device
   Window<double2> win64;
   Window<float2> win32;
   double2 *R64 = nullptr, *RH64 = nullptr;  // FP32 window: the recurrence's r, rhat (two each)
@@ -1399,7 +1404,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
           HIPCHK(hipEventRecord(ev_go[r], s));
           HIPCHK(hipStreamWaitEvent(op->side, ev_go[r], 0));
           double2 *cV = coef + size_t(r) * 2 * ncoef, *cW = cV + ncoef;
-          launch_window_eig(win_cols(cols), nev, 0, dh, lamd + size_t(last_lam) * kLamStride, dots, cV, cW,
+          launch_window_eig(win_cols(cols), nev, 0, P.sort, dh, lamd + size_t(last_lam) * kLamStride, dots, cV, cW,
                             lamd + size_t(r) * kLamStride, keptd + r, wsd, j, S, op->side);
           HIPCHK(hipMemcpyAsync(&mir[r].kept, keptd + r, sizeof(int), hipMemcpyDeviceToHost, op->side));
           HIPCHK(hipMemcpyAsync(mir[r].lam, lamd + size_t(r) * kLamStride, kLamStride * sizeof(double2),
@@ -1425,6 +1430,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
           job.reset(new RestartJob);
           job->jr = j;
           job->nev = nev;
+          job->which = P.sort;
           job->cols = cols;
           job->prev = rb;
           job->h = hh;
@@ -1500,7 +1506,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   if (dev) {
     const int rf = 2;
     double2 *fV = coef + size_t(dring) * 2 * ncoef, *fW = fV + ncoef;
-    launch_window_eig(win_cols(cols), nev, 1, dh, lamd + size_t(last_lam) * kLamStride, dots, fV, fW,
+    launch_window_eig(win_cols(cols), nev, 1, P.sort, dh, lamd + size_t(last_lam) * kLamStride, dots, fV, fW,
                       lamd + size_t(rf) * kLamStride, keptd + rf, wsd, 0, nullptr, s);
     HIPCHK(hipMemcpyAsync(&mir[rf].kept, keptd + rf, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(mir[rf].lam, lamd + size_t(rf) * kLamStride, kLamStride * sizeof(double2),
@@ -1518,7 +1524,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
     CMat H = build_H(cols, hh, rb);
     std::vector<cd> lam;
     CMat y, z;
-    if (!eig_small(H, lam, y, z)) fail(EB_ERR_EIG, "final eig(H^(vs)) failed");
+    if (!eig_small(H, lam, y, z, P.sort)) fail(EB_ERR_EIG, "final eig(H^(vs)) failed");
     out.ritz.assign(lam.begin(), lam.begin() + k);
     std::vector<cd> eta, zeta;
     col_scales(cols, hh, eta, zeta);
@@ -1933,6 +1939,7 @@ eb_status eb_eigbicg_solve(eb_op *op, const void *b_can, void *x_can, const eb_e
     if (P->rhat < 0 || P->rhat > 2) fail(EB_ERR_INVALID, "rhat must be 0, 1 or 2");
     if (P->window != EB_FP64 && P->window != EB_FP32) fail(EB_ERR_INVALID, "window must be EB_FP64 or EB_FP32");
     if (P->device_eig != 0 && P->device_eig != 1) fail(EB_ERR_INVALID, "device_eig must be 0 or 1");
+    if (P->sort < EB_SORT_SMALLEST_MAG || P->sort > EB_SORT_LARGEST_MAG) fail(EB_ERR_INVALID, "unknown sort criterion");
     set_device(op);
     hipStream_t s = static_cast<hipStream_t>(stream);
     ensure_space(op);
@@ -2456,12 +2463,12 @@ struct SessionOps {
         TIMED(EB_K_BSTAB_V, s, launch_bstab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, kc, K, rs, s, stage));
       else
         TIMED(EB_K_BSTAB_V, s, launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, kc, K, rs, s, stage));
-      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, rs, s));
+      TIMED(EB_K_BSTAB_S, s, launch_bstab_s<S>(sv, r, v, gv, j, kc, K, h, rs, s, stage));
       if (op->eo)
         TIMED(EB_K_BSTAB_T, s, launch_bstab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, kc, K, rs, s, stage));
       else
         TIMED(EB_K_BSTAB_T, s, launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, kc, K, rs, s, stage));
-      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, rs, s));
+      TIMED(EB_K_BSTAB_XR, s, launch_bstab_xr<S>(x, r, p, sv, t, rhat, gv, j, kc, K, h, rs, s, stage));
       TIMED(EB_K_BSTAB_P, s, launch_bstab_p<S>(p, r, v, gv, j, kc, K, h, rs, s));
     }
   }
@@ -2829,8 +2836,9 @@ eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage
     if (!op) fail(EB_ERR_INVALID, "null argument");
     if (prec != EB_FP64 && prec != EB_FP32 && prec != EB_BF16) fail(EB_ERR_INVALID, "unknown precision");
     if (!batch_size_ok(k)) fail(EB_ERR_INVALID, "k must be 1, 2, 4, 8 or 16");
-    if (!batch_tile_ok(op->g, op->eo, stage))
-      fail(EB_ERR_INVALID, "tile form must be -1, 0 or 1, or 2 / 3 on a full-lattice operator whose extents the brick divides");
+    if (!batch_tile_ok(op->g, op->eo, stage, k))
+      fail(EB_ERR_INVALID,
+           "tile form must be -1, 0 or 1, or 2..6 on a full-lattice operator whose extents the form's brick or box fits");
     op->batch_stage[prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2)][k] = stage;
   });
 }

@@ -134,6 +134,142 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// ---- tile form 6: t-marching ---------------------------------------------------
+// A unit of work is a box of rx x ry x rz sites (x fastest) times a chunk of
+// tc consecutive time slices.  Its threads, one per (site of the box,
+// column) with the columns fastest, walk the chunk in t.  A thread keeps its
+// site's spinor at the current and the next slice in registers, so the t
+// hops read no neighbour: the forward hop projects the next slice, and the
+// backward hop of slice t + 1 (U_t^+ times the projection of slice t) is
+// formed while slice t is in registers and carried to the next step.  The
+// x, y, z neighbours come from global memory; the threads of one box step
+// through the same slices together, so those reads hit the slices the box
+// itself has just loaded into L2 and only the box's faces come from beyond
+// it.  The blocks of one unit are consecutive in the XCD-remapped order, so
+// a unit runs on one XCD (at 32^3 x 64 each XCD holds one box).
+struct March {
+  int rx, ry, rz, tc;  // rx = 0: the form does not fit the lattice and k
+};
+constexpr int kMarchForm = 6;
+// Largest divisor of n not above cap.
+inline int divisor_below(int n, int cap) {
+  for (int d = cap < n ? cap : n; d > 1; --d)
+    if (n % d == 0) return d;
+  return 1;
+}
+// Box and chunk for k columns.  The box caps are the fastest measured on
+// MI355X at 32^3 x 64 (FP32): 16 x 16 x 8 sites for k = 16, 32 x 16 x 8 for
+// k = 2 .. 8, 32 x 32 x 8 for one column; each extent is the largest divisor
+// of the lattice extent within its cap.  A box must hold a whole number of
+// blocks; chunks are cut from the full t extent until the launch has at least
+// 512 blocks (two per CU), but no shorter than 4 slices.  The records of the
+// reducing variants (three per column and block) must fit one region.
+inline March march_shape(const Geom &g, int kc) {
+  const int cy = kc == 1 ? 32 : 16, cx = kc >= 16 ? 16 : 32;
+  March m{divisor_below(g.lx, cx), divisor_below(g.ly, cy), divisor_below(g.lz, 8), g.lt};
+  const long long box = (long long)m.rx * m.ry * m.rz;
+  if ((box * kc) % kBlock != 0) return March{};
+  auto blocks = [&](int tc) { return (long long)g.V / tc * kc / kBlock; };
+  while (m.tc % 2 == 0 && m.tc > 4 && blocks(m.tc) < 512) m.tc /= 2;
+  if (blocks(m.tc) * kc * 3 > (long long)kRegion) return March{};
+  return m;
+}
+inline int march_blocks(const Geom &g, int kc, const March &m) { return int((long long)g.V / m.tc * kc / kBlock); }
+// Records (blocks) a batched stencil pass of tile form `stage` writes with nv
+// partials per column: what its consumer sums.
+inline int stencil_records(const Geom &g, int kc, int nv, int stage) {
+  return stage == kMarchForm ? march_blocks(g, kc, march_shape(g, kc)) : batch_stencil_grid(g.V, kc, nv);
+}
+
+// EPI 0: out = in - kappa hop (the operator); 1: also the partials of
+// (rhat, out) per column (the v pass of BiCGStab); 2: also (out, in) and
+// (out, out) (the t pass).  Stopped columns skip the work (EPI > 0).
+template <typename S, int KC, int SF, int EPI>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2)))
+    k_bmarch(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U, Geom g, double kappa, March m,
+             const S *__restrict__ rhat, int j, const KrylovState *K, double *__restrict__ part) {
+  using R = typename Store<S>::R;
+  constexpr int NV = EPI == 2 ? 3 : 2;
+  const R k = R(kappa);
+  const int bpu = m.rx * m.ry * m.rz * KC / kBlock;  // blocks per unit
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int unit = lb / bpu, u = (lb - unit * bpu) * kBlock + threadIdx.x;
+  const int nch = g.lt / m.tc, box = unit / nch, chunk = unit - box * nch;
+  const int col = u % KC, q = u / KC;
+  const int nbx = g.lx / m.rx, nby = g.ly / m.ry;
+  const int x = (box % nbx) * m.rx + q % m.rx;
+  const int y = ((box / nbx) % nby) * m.ry + (q / m.rx) % m.ry;
+  const int z = (box / (nbx * nby)) * m.rz + q / (m.rx * m.ry);
+  double d[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) d[i] = 0.0;
+  bool act = true;
+  if constexpr (EPI != 0) act = col_active(K, col, j);
+  if (act) {
+    const int Vs = g.lx * g.ly * g.lz, xyz = x + g.lx * (y + g.ly * z);
+    const int sy = g.lx, sz = g.lx * g.ly;
+    const int xf = x == g.lx - 1 ? -(g.lx - 1) : 1, xb = x == 0 ? g.lx - 1 : -1;
+    const int yf = y == g.ly - 1 ? -(g.ly - 1) * sy : sy, yb = y == 0 ? (g.ly - 1) * sy : -sy;
+    const int zf = z == g.lz - 1 ? -(g.lz - 1) * sz : sz, zb = z == 0 ? (g.lz - 1) * sz : -sz;
+    const S *inc = in + col;
+    auto xyz_hops = [&](cx<R> (&acc)[12], int s) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+      hop_dir<2, SF, S, KC, true>(acc, inc, U, g.V, s, s + zf, s + zb);
+      hop_dir<0, SF, S, KC, true>(acc, inc, U, g.V, s, s + xf, s + xb);
+      hop_dir<1, SF, S, KC, true>(acc, inc, U, g.V, s, s + yf, s + yb);
+    };
+    const int t0 = chunk * m.tc, t1 = t0 + m.tc;
+    cx<R> cen[12], acc[12], carry[6];
+    {
+      const int s = xyz + Vs * t0, sp = xyz + Vs * (t0 == 0 ? g.lt - 1 : t0 - 1);
+      load_spinor<S, KC>(cen, inc, g.V, s);
+      cx<R> h[6];
+      load_project<3, -SF, S, KC>(h, inc, g.V, sp);
+      mult_t<true, S>(carry, h, U, g.V, sp);
+      xyz_hops(acc, s);
+    }
+    for (int t = t0; t < t1; ++t) {
+      int s = xyz + Vs * t, sn = xyz + Vs * (t == g.lt - 1 ? 0 : t + 1);
+      // opaque site indices: the addresses are formed from them in each step
+      // instead of being carried across steps in registers
+      asm volatile("" : "+v"(s), "+v"(sn));
+      cx<R> nxt[12];
+      load_spinor<S, KC>(nxt, inc, g.V, sn);
+      {
+        cx<R> h[6], w[6];
+        project_t<SF>(h, nxt);
+        mult_t<false, S>(w, h, U, g.V, s);
+        recon_t<SF>(acc, w);
+        recon_t<-SF>(acc, carry);
+        project_t<-SF>(h, cen);
+        mult_t<true, S>(carry, h, U, g.V, s);
+      }
+      hop_fence();
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const size_t i = (size_t(c) * g.V + s) * KC + col;
+        const cx<R> o = cen[c] - k * acc[c];
+        Store<S>::st(out, i, o);
+        if constexpr (EPI == 1) {
+          const cx<R> hh = Store<S>::ld(rhat, i);
+          d[0] += double(hh.x) * o.x + double(hh.y) * o.y;
+          d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
+        } else if constexpr (EPI == 2) {
+          const cx<R> si = cen[c];
+          d[0] += double(o.x) * si.x + double(o.y) * si.y;
+          d[1] += double(o.x) * si.y - double(o.y) * si.x;
+          d[NV - 1] += double(o.x) * o.x + double(o.y) * o.y;
+        }
+      }
+      if (t + 1 < t1) xyz_hops(acc, sn);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) cen[c] = nxt[c];
+    }
+  }
+  if constexpr (EPI != 0) block_partial_cols<NV, KC, kBlock>(d, part, blockIdx.x);
+}
+
 // rhat = p = r; partials of ||r_col||^2
 template <typename S, int KC>
 __global__ void __launch_bounds__(kBlock)
@@ -640,10 +776,11 @@ __global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
 }  // namespace
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
-bool batch_tile_ok(const Geom &g, bool eo, int stage) {
+bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc) {
   if (stage < -1 || stage >= kTileForms) return false;
   if (stage < 2) return true;
   if (stage == 5) return !eo;
+  if (stage == kMarchForm) return !eo && march_shape(g, kc).rx > 0;
   const Brick b = brick_of(stage);  // bricked forms: full-lattice stencil, extents divisible by the brick
   return !eo && g.lx % b.bx == 0 && g.ly % b.by == 0 && g.lz % b.bz == 0 && g.lt % b.bt == 0;
 }
@@ -653,6 +790,17 @@ void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa
                     int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
+    if (stage == kMarchForm) {
+      const March m = march_shape(g, KC);
+      const dim3 grid(march_blocks(g, KC, m));
+      if (dagger)
+        EB_LAUNCH((k_bmarch<S, KC, +1, 0>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, m, nullptr, 0, nullptr,
+                  nullptr);
+      else
+        EB_LAUNCH((k_bmarch<S, KC, -1, 0>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, m, nullptr, 0, nullptr,
+                  nullptr);
+      return;
+    }
     dispatch_stage<S, KC>(stage, [&](auto sg, auto fg) {
       constexpr bool STG = decltype(sg)::value, FENCE = decltype(fg)::value;
       const dim3 grid(nblocks_for(size_t(g.V) * KC));
@@ -682,6 +830,12 @@ void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, 
                     KrylovState *K, const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
+    if (stage == kMarchForm) {
+      const March m = march_shape(g, KC);
+      EB_LAUNCH((k_bmarch<S, KC, -1, 1>), dim3(march_blocks(g, KC, m)), dim3(kBlock), 0, st, v, p, U, g, kappa, m,
+                rhat, j, K, region(rs, RG_V));
+      return;
+    }
     dispatch_stage<S, KC>(stage, [&](auto sg, auto fg) {
       EB_LAUNCH((k_bstab_v<S, KC, decltype(sg)::value, decltype(fg)::value>), dim3(batch_stencil_grid(g.V, KC, 2)), dim3(kBlock), 0, st,
                 v, p, rhat, U, g, kappa, j, K, region(rs, RG_V), brick_of(stage));
@@ -691,11 +845,11 @@ void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, 
 
 template <typename S>
 void launch_bstab_s(S *sv, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
-                    const RedScratch &rs, hipStream_t st) {
+                    const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    const int nblk = batch_stencil_grid(g.V, KC, 2);
+    const int nblk = stencil_records(g, KC, 2, stage);
     if (fuse_finish(nblk, 2, KC)) {
       EB_LAUNCH((k_bstab_s_f<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, sv, r, v, n, j, K, h,
                 region(rs, RG_V), nblk);
@@ -711,6 +865,12 @@ void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, 
                     const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
+    if (stage == kMarchForm) {
+      const March m = march_shape(g, KC);
+      EB_LAUNCH((k_bmarch<S, KC, -1, 2>), dim3(march_blocks(g, KC, m)), dim3(kBlock), 0, st, t, sv, U, g, kappa, m,
+                nullptr, j, K, region(rs, RG_T));
+      return;
+    }
     dispatch_stage<S, KC>(stage, [&](auto sg, auto fg) {
       EB_LAUNCH((k_bstab_t<S, KC, decltype(sg)::value, decltype(fg)::value>), dim3(batch_stencil_grid(g.V, KC, 3)), dim3(kBlock), 0, st,
                 t, sv, U, g, kappa, j, K, region(rs, RG_T), brick_of(stage));
@@ -720,11 +880,11 @@ void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, 
 
 template <typename S>
 void launch_bstab_xr(S *x, S *r, const S *p, const S *sv, const S *t, const S *rhat, const Geom &g, int j, int kc,
-                     KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+                     KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st, int stage) {
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    const int nblk = batch_stencil_grid(g.V, KC, 3);
+    const int nblk = stencil_records(g, KC, 3, stage);
     if (fuse_finish(nblk, 3, KC)) {
       EB_LAUNCH((k_bstab_xr_f<S, KC>), dim3(batch_red_grid(n, KC, 3)), dim3(kBlock), 0, st, x, r, p, sv, t, rhat, n,
                 j, K, h, region(rs, RG_T), nblk, region(rs, RG_XR));
@@ -821,11 +981,11 @@ void launch_batch_rebase(KrylovState *K, KrylovHistory h, int kc, int jl, hipStr
   template void launch_bstab_v<S>(S *, const S *, const S *, const S *, const Geom &, double, int, int,            \
                                   KrylovState *, const RedScratch &, hipStream_t, int);                            \
   template void launch_bstab_s<S>(S *, const S *, const S *, const Geom &, int, int, KrylovState *, KrylovHistory, \
-                                  const RedScratch &, hipStream_t);                                                \
+                                  const RedScratch &, hipStream_t, int);                                           \
   template void launch_bstab_t<S>(S *, const S *, const S *, const Geom &, double, int, int, KrylovState *,        \
                                   const RedScratch &, hipStream_t, int);                                           \
   template void launch_bstab_xr<S>(S *, S *, const S *, const S *, const S *, const S *, const Geom &, int, int,   \
-                                   KrylovState *, KrylovHistory, const RedScratch &, hipStream_t);                 \
+                                   KrylovState *, KrylovHistory, const RedScratch &, hipStream_t, int);            \
   template void launch_bstab_p<S>(S *, const S *, const S *, const Geom &, int, int, KrylovState *, KrylovHistory, \
                                   const RedScratch &, hipStream_t);                                                \
   template void launch_pack_batch<S>(S *, const double2 *, size_t, int, hipStream_t);                              \

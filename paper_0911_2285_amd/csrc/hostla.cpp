@@ -177,19 +177,23 @@ CMat adjoint(const CMat &A) {
   return B;
 }
 
-std::vector<int> eig_sort_order(const std::vector<cd> &lam) {
+std::vector<int> eig_sort_order(const std::vector<cd> &lam, int which) {
   std::vector<int> idx(lam.size());
   std::iota(idx.begin(), idx.end(), 0);
+  auto key = [&](int i) {
+    return which == 1 ? lam[i].real() : (which == 2 ? -std::abs(lam[i]) : std::abs(lam[i]));
+  };
   std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) {
-    double ai = std::abs(lam[i]), aj = std::abs(lam[j]);
-    if (std::fabs(ai - aj) > 1e-12 * std::max({ai, aj, 1e-300})) return ai < aj;
+    const double ki = key(i), kj = key(j);
+    const double scale = std::max({std::abs(lam[i]), std::abs(lam[j]), 1e-300});
+    if (std::fabs(ki - kj) > 1e-12 * scale) return ki < kj;
     if (lam[i].imag() != lam[j].imag()) return lam[i].imag() > lam[j].imag();
     return i < j;
   });
   return idx;
 }
 
-bool eig_small(const CMat &C, std::vector<cd> &lam, CMat &y, CMat &z) {
+bool eig_small(const CMat &C, std::vector<cd> &lam, CMat &y, CMat &z, int which) {
   const int n = C.rows;
   lam.assign(n, 0.0);
   y = CMat(n, n);
@@ -248,7 +252,7 @@ bool eig_small(const CMat &C, std::vector<cd> &lam, CMat &y, CMat &z) {
       Zl(i, k) = tz[i] / std::conj(d);
     }
   }
-  std::vector<int> ord = eig_sort_order(lam);
+  std::vector<int> ord = eig_sort_order(lam, which);
   std::vector<cd> ls(n);
   for (int c = 0; c < n; ++c) {
     ls[c] = lam[ord[c]];

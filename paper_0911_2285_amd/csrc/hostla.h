@@ -27,16 +27,18 @@ struct CMat {
 CMat matmul(const CMat &A, const CMat &B);
 CMat adjoint(const CMat &A);
 
-// Sort order of eigenvalues: |lambda| ascending; moduli equal to 1e-12 relative
-// are ordered by imaginary part descending.
-std::vector<int> eig_sort_order(const std::vector<cd> &lam);
+// Sort order of eigenvalues by a criterion (Sec. 1, end: a user-chosen one):
+// which = 0 |lambda| ascending, 1 real part ascending, 2 |lambda| descending.
+// Keys equal to 1e-12 relative (to the larger modulus) are ordered by
+// imaginary part descending.
+std::vector<int> eig_sort_order(const std::vector<cd> &lam, int which = 0);
 
 // [y, z, lam] = eig(C): right vectors y, left vectors z (z_i^+ C = lam_i z_i^+),
 // ||y_i|| = 1, z_i^+ y_i = 1, sorted by eig_sort_order.  Householder
 // Hessenberg reduction, complex single-shift QR (Wilkinson shifts), and
 // triangular back/forward substitution for the eigenvectors of the Schur form.
 // Returns false if the QR iteration fails to converge.
-bool eig_small(const CMat &C, std::vector<cd> &lam, CMat &y, CMat &z);
+bool eig_small(const CMat &C, std::vector<cd> &lam, CMat &y, CMat &z, int which = 0);
 
 // Solve A x = b (A square) by Gaussian elimination with partial pivoting.
 // Returns false if A is numerically singular.

@@ -80,7 +80,7 @@ struct RedScratch {
 };
 constexpr size_t kMaxPartials = size_t(1) << 23;
 constexpr int kMaxRedBlocks = 2048;         // grid cap of the streaming reducing kernels
-constexpr size_t kRegionDoubles = 1 << 16;  // partial records per producer region (doubles)
+constexpr size_t kRegionDoubles = 1 << 17;  // partial records per producer region (doubles)
 // Largest volume the library accepts: the window rotation keeps one partial
 // record of up to 40 doubles per block of 256 entries of a spinor (12 V
 // entries) in the general region of the scratch.
@@ -297,11 +297,13 @@ struct WinCols {
 // 4nev)).  Outputs: cV, cW (cols.n x kout coefficient blocks with the stored
 // residuals' scales folded in; kout = 2 nev, or min(nev, n) in mode 1), lam_out,
 // *kept_out (-1 if an eigenproblem failed).  Skipped when the solve stopped
-// before iteration jtag.  ws: window_restart_ws_entries(cols.n, nev) complex.
+// before iteration jtag.  which: the sort criterion of every eig() (0
+// |lambda| ascending, 1 real part ascending, 2 |lambda| descending).  ws:
+// window_restart_ws_entries(cols.n, nev) complex.
 size_t window_restart_ws_entries(int m, int nev);
-void launch_window_eig(const WinCols &cols, int nev, int mode, const KrylovHistory &h, const double2 *lam_prev,
-                       const double2 *dots_prev, double2 *cV, double2 *cW, double2 *lam_out, int *kept_out,
-                       double2 *ws, int jtag, const KrylovState *S, hipStream_t st);
+void launch_window_eig(const WinCols &cols, int nev, int mode, int which, const KrylovHistory &h,
+                       const double2 *lam_prev, const double2 *dots_prev, double2 *cV, double2 *cW, double2 *lam_out,
+                       int *kept_out, double2 *ws, int jtag, const KrylovState *S, hipStream_t st);
 
 // ---- multi-RHS batches (batch.hip) ------------------------------------------------
 // A batch holds kc right-hand sides interleaved as the fastest index: element
@@ -315,9 +317,12 @@ bool batch_size_ok(int kc);
 // 8 x 8 x 4 x 4, 8 x 8 x 8 x 8 and 4 x 4 x 4 x 4 sites (full-lattice operator,
 // extents divisible by the brick), 5 global reads in site order with the
 // loads of several hops in flight (no fence between hops; full-lattice
-// operator); < 0 the built-in rule (LDS staging for k = 1 and for BF16).
-constexpr int kTileForms = 6;
-bool batch_tile_ok(const Geom &g, bool eo, int stage);
+// operator), 6 t-marching (boxes of sites walked through a chunk of time
+// slices, the t neighbours in registers; full-lattice operator, a box of a
+// whole number of blocks for k); < 0 the built-in rule (LDS staging for k = 1
+// and for BF16).
+constexpr int kTileForms = 7;
+bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc);
 // stage: tile form of the batched stencils (kTileForms above)
 template <typename S>
 void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,
@@ -329,15 +334,17 @@ void launch_bstab_init(S *rhat, S *p, const S *r, size_t N, int kc, const double
 template <typename S>
 void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, int kc,
                     KrylovState *K, const RedScratch &rs, hipStream_t st, int stage = -1);
+// stage: the tile form of the v pass whose records this pass sums
 template <typename S>
 void launch_bstab_s(S *s, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
-                    const RedScratch &rs, hipStream_t st);
+                    const RedScratch &rs, hipStream_t st, int stage);
 template <typename S>
 void launch_bstab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, int kc, KrylovState *K,
                     const RedScratch &rs, hipStream_t st, int stage = -1);
+// stage: the tile form of the t pass whose records this pass sums
 template <typename S>
 void launch_bstab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, const Geom &g, int j, int kc,
-                     KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st);
+                     KrylovState *K, KrylovHistory h, const RedScratch &rs, hipStream_t st, int stage);
 template <typename S>
 void launch_bstab_p(S *p, const S *r, const S *v, const Geom &g, int j, int kc, KrylovState *K, KrylovHistory h,
                     const RedScratch &rs, hipStream_t st);

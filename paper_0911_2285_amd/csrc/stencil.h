@@ -248,4 +248,71 @@ __device__ __forceinline__ void hopping_t(cx<typename Store<S>::R> (&acc)[12], c
                       y == 0 ? s + (g.ly - 1) * sy : s - sy);
 }
 
+// ---------------------------------------------------------------------------
+// Pieces of the t-marching form (batched stencils).  A thread that walks its
+// site through consecutive time slices holds the site's full spinor at the
+// current and the next slice in registers; the t hops then project those
+// registers instead of loading neighbours.
+// ---------------------------------------------------------------------------
+// all 12 components of this thread's column at site sn
+template <typename S, int KC>
+__device__ __forceinline__ void load_spinor(cx<typename Store<S>::R> (&p)[12], const S *__restrict__ in, int V,
+                                            int sn) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c] = Store<S>::ld(in, (size_t(c) * V + sn) * KC);
+}
+// the t projector (1 + SG gamma_t) of a spinor in registers (the MU = 3 case of load_project)
+template <int SG, typename R>
+__device__ __forceinline__ void project_t(cx<R> (&h)[6], const cx<R> (&p)[12]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h[a] = p[a] + sgn<SG>(p[6 + a]);
+    h[3 + a] = p[3 + a] + sgn<SG>(p[9 + a]);
+  }
+}
+// u = U_t h (ADJ: U_t^+ h) at site sl, the half spinor not yet reconstructed
+template <bool ADJ, typename S>
+__device__ __forceinline__ void mult_t(cx<typename Store<S>::R> (&u)[6], const cx<typename Store<S>::R> (&h)[6],
+                                       const S *__restrict__ U, int V, int sl) {
+  using R = typename Store<S>::R;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> t0, t1;
+    if constexpr (!ADJ) {
+      const cx<R> u0 = Store<S>::ld(U, size_t(27 + a * 3 + 0) * V + sl);
+      const cx<R> u1 = Store<S>::ld(U, size_t(27 + a * 3 + 1) * V + sl);
+      const cx<R> u2 = Store<S>::ld(U, size_t(27 + a * 3 + 2) * V + sl);
+      t0 = u0 * h[0];
+      cfma(t0, u1, h[1]);
+      cfma(t0, u2, h[2]);
+      t1 = u0 * h[3];
+      cfma(t1, u1, h[4]);
+      cfma(t1, u2, h[5]);
+    } else {
+      const cx<R> u0 = Store<S>::ld(U, size_t(27 + 0 + a) * V + sl);
+      const cx<R> u1 = Store<S>::ld(U, size_t(27 + 3 + a) * V + sl);
+      const cx<R> u2 = Store<S>::ld(U, size_t(27 + 6 + a) * V + sl);
+      t0 = cmulc(u0, h[0]);
+      cfmac(t0, u1, h[1]);
+      cfmac(t0, u2, h[2]);
+      t1 = cmulc(u0, h[3]);
+      cfmac(t1, u1, h[4]);
+      cfmac(t1, u2, h[5]);
+    }
+    u[a] = t0;
+    u[3 + a] = t1;
+  }
+}
+// acc += the spin reconstruction of a t half spinor with projector sign SG
+template <int SG, typename R>
+__device__ __forceinline__ void recon_t(cx<R> (&acc)[12], const cx<R> (&u)[6]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] = acc[a] + u[a];
+    acc[3 + a] = acc[3 + a] + u[3 + a];
+    acc[6 + a] = acc[6 + a] + sgn<SG>(u[a]);
+    acc[9 + a] = acc[9 + a] + sgn<SG>(u[3 + a]);
+  }
+}
+
 }  // namespace ebicg

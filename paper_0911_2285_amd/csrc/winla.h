@@ -2,24 +2,44 @@
 // one workgroup of kWinThreads threads (one wavefront): eig(C) of Sec. 1 (end)
 // for the m x m window matrices of Alg. BiCG-eigen, with the conventions of
 // the host solver (hostla.h): right vectors y_i with ||y_i|| = 1, left
-// vectors z_i with z_i^+ C = lambda_i z_i^+ and z_i^+ y_i = 1, sorted by
-// |lambda| ascending (ties: imaginary part descending).
+// vectors z_i with z_i^+ C = lambda_i z_i^+ and z_i^+ y_i = 1, sorted by a
+// criterion (|lambda| ascending by default; ties: imaginary part descending).
 //
 // Method, as on the host: Householder reduction to Hessenberg form, complex
 // single-shift QR with Wilkinson shifts (an exceptional shift every tenth
 // sweep) to the Schur form T = Q^+ C Q, and eigenvectors of T by triangular
-// substitution, mapped back with Q.  Matrices are column-major with leading
-// dimension ld in global memory (the workgroup's own scratch); the Schur
-// chase keeps T in LDS when it fits (n <= kWinLdsN).  Every thread of the
-// workgroup calls these functions; they synchronise internally.
+// substitution, mapped back with Q.  Every step is a chain of small dependent
+// updates, so latency decides the time: the working matrices (T, Q and the
+// right and left eigenvectors of T) live in a 150 KB LDS pool when it holds
+// all four (n <= 48), or T and Q alone (n <= 69); the rest go to the
+// workgroup's global scratch.  In LDS
+// the leading dimension is odd, so that the lanes of a row-wise sweep (one
+// column per lane) fall in different banks.  Every lane computes each Givens
+// rotation of the QR chase itself from the same entries, with no broadcast.
+// Every thread of the workgroup calls these functions; they synchronise
+// internally.
 #pragma once
 
 #include "device_common.h"
 
 namespace ebicg {
 
-constexpr int kWinThreads = 64;  // one wavefront
-constexpr int kWinLdsN = 56;     // largest n whose Schur chase runs on an LDS copy of T
+constexpr int kWinThreads = 64;      // one wavefront
+constexpr int kWinMaxN = 128;        // largest matrix
+constexpr int kWinLdsEntries = 9600;  // complex entries of the LDS matrix pool (150 KB)
+
+// The workgroup's LDS: the matrix pool and three vectors of kWinMaxN.  One
+// variable at namespace scope, so that every access compiles to an LDS
+// instruction (a pointer handed through a call would be a generic one).
+struct WinLds {
+  double2 pool[kWinLdsEntries];
+  double2 vec[kWinMaxN];  // Householder vector
+  double2 lm[kWinMaxN];   // unsorted eigenvalues
+  int ord[kWinMaxN];      // sort order
+};
+namespace {
+__shared__ WinLds win_lds;
+}
 
 using wcx = cx<double>;
 
@@ -54,8 +74,9 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// Householder reduction A = Q Hs Q^+ (A overwritten by Hs, Q set).  v: scratch of n.
-__device__ void win_hessenberg(double2 *A, double2 *Q, int n, int ld, double2 *v) {
+// Householder reduction A = Q Hs Q^+ (A overwritten by Hs, Q set); leading
+// dimension ld for both.  v: scratch of n.
+__device__ __forceinline__ void win_hessenberg(double2 *A, double2 *Q, int n, int ld, double2 *v) {
   const int t = threadIdx.x;
   for (int j = 0; j < n; ++j)
     for (int i = t; i < n; i += kWinThreads) Q[i + j * ld] = make_double2(i == j ? 1.0 : 0.0, 0.0);
@@ -73,23 +94,28 @@ __device__ void win_hessenberg(double2 *A, double2 *Q, int n, int ld, double2 *v
     const wcx ph = ax0 == 0.0 ? wcx{1.0, 0.0} : wcx{x0.x / ax0, x0.y / ax0};
     const wcx alpha = {-ph.x * xn, -ph.y * xn};
     double vs = 0.0;
-    for (int i = k + 1 + t; i < n; i += kWinThreads) {
-      wcx a = ld2(A + i + k * ld);
-      if (i == k + 1) a = a - alpha;
-      st2(v + i, a);
-      vs += a.x * a.x + a.y * a.y;
+    wcx vi[2];  // this lane's entries of v (n <= 128)
+    for (int r = 0; r < 2; ++r) {
+      const int i = k + 1 + t + r * kWinThreads;
+      vi[r] = {0.0, 0.0};
+      if (i < n) {
+        wcx a = ld2(A + i + k * ld);
+        if (i == k + 1) a = a - alpha;
+        vi[r] = a;
+        vs += a.x * a.x + a.y * a.y;
+      }
     }
     const double vn = sqrt(wsum(vs));
-    __syncthreads();
     if (vn == 0.0) continue;
-    for (int i = k + 1 + t; i < n; i += kWinThreads) {
-      const wcx a = ld2(v + i);
-      st2(v + i, wcx{a.x / vn, a.y / vn});
+    for (int r = 0; r < 2; ++r) {
+      const int i = k + 1 + t + r * kWinThreads;
+      if (i < n) st2(v + i, wcx{vi[r].x / vn, vi[r].y / vn});
     }
     __syncthreads();
     // A <- (I - 2 v v^+) A, one column per lane
     for (int j = t; j < n; j += kWinThreads) {
       wcx s = {0.0, 0.0};
+#pragma unroll 4
       for (int i = k + 1; i < n; ++i) cfmac(s, ld2(v + i), ld2(A + i + j * ld));
       s = 2.0 * s;
       for (int i = k + 1; i < n; ++i) st2(A + i + j * ld, ld2(A + i + j * ld) - ld2(v + i) * s);
@@ -98,6 +124,7 @@ __device__ void win_hessenberg(double2 *A, double2 *Q, int n, int ld, double2 *v
     // A <- A (I - 2 v v^+), Q <- Q (I - 2 v v^+), one row per lane
     for (int i = t; i < n; i += kWinThreads) {
       wcx s = {0.0, 0.0}, u = {0.0, 0.0};
+#pragma unroll 4
       for (int j = k + 1; j < n; ++j) {
         const wcx vj = ld2(v + j);
         cfma(s, ld2(A + i + j * ld), vj);
@@ -111,24 +138,60 @@ __device__ void win_hessenberg(double2 *A, double2 *Q, int n, int ld, double2 *v
         st2(Q + i + j * ld, ld2(Q + i + j * ld) - u * vc);
       }
     }
-    __syncthreads();
     for (int i = k + 2 + t; i < n; i += kWinThreads) st2(A + i + k * ld, wcx{0.0, 0.0});
     __syncthreads();
   }
 }
 
+// Givens rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0]:
+// c = |x| / r, s = (x / |x|) conj(y) / r, r = sqrt(|x|^2 + |y|^2).  The
+// rotation lies on the serial path of the QR chase, so it is formed from the
+// squares of the entries (two square roots and one reciprocal, no hypot);
+// entries whose squares would leave the FP64 range are first scaled by the
+// largest component.  Every lane takes the same branch.
+__device__ __forceinline__ void win_givens(wcx x, wcx y, double &c, wcx &s) {
+  double ax2 = x.x * x.x + x.y * x.y, ay2 = y.x * y.x + y.y * y.y;
+  const double r2 = ax2 + ay2;
+  if (!(r2 > 1e-280 && r2 < 1e280)) {  // rare: rescale (or y = 0 among tiny entries)
+    const double sc = fmax(fmax(fabs(x.x), fabs(x.y)), fmax(fabs(y.x), fabs(y.y)));
+    if (sc == 0.0) {
+      c = 1.0;
+      s = {0.0, 0.0};
+      return;
+    }
+    const double is = 1.0 / sc;
+    x = is * x;
+    y = is * y;
+    ax2 = x.x * x.x + x.y * x.y;
+    ay2 = y.x * y.x + y.y * y.y;
+  }
+  if (ay2 == 0.0) {
+    c = 1.0;
+    s = {0.0, 0.0};
+    return;
+  }
+  if (ax2 == 0.0) {
+    const double iay = 1.0 / sqrt(ay2);
+    c = 0.0;
+    s = {y.x * iay, -y.y * iay};
+    return;
+  }
+  const double ax = sqrt(ax2), r = sqrt(ax2 + ay2);
+  const double inv = 1.0 / (ax * r);
+  c = ax2 * inv;
+  s = inv * (x * cconj(y));
+}
+
 // Complex Schur form of the Hessenberg T (upper triangular on return), the
-// similarity accumulated into Z (A = Z T Z^+).  T is column-major with leading
-// dimension ldt (in LDS or global memory).  Returns false if the iteration did
-// not converge.  Control decisions are taken by lane 0 and broadcast through
-// `ctl` (LDS).
-template <typename TP>
-__device__ bool win_schur(TP T, int ldt, double2 *Z, int ldz, int n, double *ctl) {
+// similarity accumulated into Z (A = Z T Z^+); leading dimension ld for both.
+// Returns false if the iteration did not converge.  Every lane takes the
+// same decisions from the same (settled) entries.
+__device__ __forceinline__ bool win_schur(double2 *T, double2 *Z, int n, int ld) {
   const int t = threadIdx.x;
   const double eps = 2.220446049250313e-16;
   double anorm = 0.0;
   for (int j = 0; j < n; ++j)
-    for (int i = t; i < n; i += kWinThreads) anorm = fmax(anorm, wabs1(ld2(T + i + j * ldt)));
+    for (int i = t; i < n; i += kWinThreads) anorm = fmax(anorm, wabs1(ld2(T + i + j * ld)));
 #pragma unroll
   for (int off = kWinThreads / 2; off > 0; off >>= 1) anorm = fmax(anorm, __shfl_xor(anorm, off, kWinThreads));
   if (anorm == 0.0) anorm = 1.0;
@@ -136,18 +199,22 @@ __device__ bool win_schur(TP T, int ldt, double2 *Z, int ldz, int n, double *ctl
   const int max_total = 100 * (n > 1 ? n : 1);
   bool ok = true;
   while (ihi > 0) {
-    // deflation point: every lane reads the same (settled) entries
+    // deflation point: the largest k <= ihi with a negligible T(k, k-1), one
+    // k per lane and a ballot per 64 of them
     int l = 0;
-    for (int k = ihi; k >= 1; --k) {
-      double tst = wabs1(ld2(T + (k - 1) + (k - 1) * ldt)) + wabs1(ld2(T + k + k * ldt));
-      if (tst == 0.0) tst = anorm;
-      if (wabs1(ld2(T + k + (k - 1) * ldt)) <= eps * tst) {
-        l = k;
-        break;
+    for (int base = 0; base < ihi; base += kWinThreads) {
+      const int k = base + 1 + t;
+      bool small = false;
+      if (k <= ihi) {
+        double tst = wabs1(ld2(T + (k - 1) + (k - 1) * ld)) + wabs1(ld2(T + k + k * ld));
+        if (tst == 0.0) tst = anorm;
+        small = wabs1(ld2(T + k + (k - 1) * ld)) <= eps * tst;
       }
+      const unsigned long long mask = __ballot(small);
+      if (mask) l = base + 1 + (63 - __clzll(mask));
     }
     __syncthreads();
-    if (l > 0 && t == 0) st2(T + l + (l - 1) * ldt, wcx{0.0, 0.0});
+    if (l > 0 && t == 0) st2(T + l + (l - 1) * ld, wcx{0.0, 0.0});
     __syncthreads();
     if (l == ihi) {
       --ihi;
@@ -161,158 +228,126 @@ __device__ bool win_schur(TP T, int ldt, double2 *Z, int ldz, int n, double *ctl
     ++its;
     wcx mu;
     if (its % 10 == 0) {
-      mu = ld2(T + ihi + ihi * ldt);
-      mu.x += fabs(ld2(T + ihi + (ihi - 1) * ldt).x) + (ihi >= 2 ? fabs(ld2(T + (ihi - 1) + (ihi - 2) * ldt).x) : 0.0);
+      mu = ld2(T + ihi + ihi * ld);
+      mu.x += fabs(ld2(T + ihi + (ihi - 1) * ld).x) + (ihi >= 2 ? fabs(ld2(T + (ihi - 1) + (ihi - 2) * ld).x) : 0.0);
     } else {
-      const wcx a = ld2(T + (ihi - 1) + (ihi - 1) * ldt), b = ld2(T + (ihi - 1) + ihi * ldt);
-      const wcx c = ld2(T + ihi + (ihi - 1) * ldt), d = ld2(T + ihi + ihi * ldt);
+      const wcx a = ld2(T + (ihi - 1) + (ihi - 1) * ld), b = ld2(T + (ihi - 1) + ihi * ld);
+      const wcx c = ld2(T + ihi + (ihi - 1) * ld), d = ld2(T + ihi + ihi * ld);
       const wcx hm = 0.5 * (a - d);
       const wcx disc = wsqrt(hm * hm + b * c);
       const wcx avg = 0.5 * (a + d);
       const wcx m1 = avg + disc, m2 = avg - disc;
       mu = wabs(m1 - d) < wabs(m2 - d) ? m1 : m2;
     }
-    __syncthreads();
     for (int k = l; k < ihi; ++k) {
-      // rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0], by lane 0
-      if (t == 0) {
-        wcx x, y;
-        if (k == l) {
-          x = ld2(T + k + k * ldt) - mu;
-          y = ld2(T + (k + 1) + k * ldt);
-        } else {
-          x = ld2(T + k + (k - 1) * ldt);
-          y = ld2(T + (k + 1) + (k - 1) * ldt);
-        }
-        const double ax = wabs(x), ay = wabs(y);
-        double c;
-        wcx s;
-        if (ay == 0.0) {
-          c = 1.0;
-          s = {0.0, 0.0};
-        } else if (ax == 0.0) {
-          c = 0.0;
-          s = {y.x / ay, -y.y / ay};
-        } else {
-          const double r = hypot(ax, ay);
-          c = ax / r;
-          const wcx xs = {x.x / ax, x.y / ax};
-          s = (1.0 / r) * (xs * cconj(y));
-        }
-        ctl[0] = c;
-        ctl[1] = s.x;
-        ctl[2] = s.y;
+      double c;
+      wcx s;
+      {
+        const int col = k == l ? k : k - 1;  // the first rotation makes the bulge
+        wcx x = ld2(T + k + col * ld);
+        if (k == l) x = x - mu;
+        win_givens(x, ld2(T + (k + 1) + col * ld), c, s);
       }
-      __syncthreads();
-      const double c = ctl[0];
-      const wcx s = {ctl[1], ctl[2]};
       const wcx sc = cconj(s);
+      // rows k, k+1 (every lane has read the entries above: nobody writes them before the barrier)
+      __syncthreads();
       const int j0 = k == l ? k : k - 1;
       for (int j = j0 + t; j < n; j += kWinThreads) {
-        const wcx a = ld2(T + k + j * ldt), b = ld2(T + (k + 1) + j * ldt);
-        st2(T + k + j * ldt, c * a + s * b);
-        st2(T + (k + 1) + j * ldt, c * b - sc * a);
+        const wcx a = ld2(T + k + j * ld), b = ld2(T + (k + 1) + j * ld);
+        st2(T + k + j * ld, c * a + s * b);
+        st2(T + (k + 1) + j * ld, c * b - sc * a);
       }
       __syncthreads();
-      if (k > l && t == 0) st2(T + (k + 1) + (k - 1) * ldt, wcx{0.0, 0.0});
+      if (k > l && t == 0) st2(T + (k + 1) + (k - 1) * ld, wcx{0.0, 0.0});
+      // columns k, k+1 of T and of Z
       const int i1 = k + 2 < ihi ? k + 2 : ihi;
       for (int i = t; i <= i1; i += kWinThreads) {
-        const wcx a = ld2(T + i + k * ldt), b = ld2(T + i + (k + 1) * ldt);
-        st2(T + i + k * ldt, c * a + b * sc);
-        st2(T + i + (k + 1) * ldt, c * b - a * s);
+        const wcx a = ld2(T + i + k * ld), b = ld2(T + i + (k + 1) * ld);
+        st2(T + i + k * ld, c * a + b * sc);
+        st2(T + i + (k + 1) * ld, c * b - a * s);
       }
       for (int i = t; i < n; i += kWinThreads) {
-        const wcx a = ld2(Z + i + k * ldz), b = ld2(Z + i + (k + 1) * ldz);
-        st2(Z + i + k * ldz, c * a + b * sc);
-        st2(Z + i + (k + 1) * ldz, c * b - a * s);
+        const wcx a = ld2(Z + i + k * ld), b = ld2(Z + i + (k + 1) * ld);
+        st2(Z + i + k * ld, c * a + b * sc);
+        st2(Z + i + (k + 1) * ld, c * b - a * s);
       }
       __syncthreads();
     }
   }
   __syncthreads();
   for (int j = 0; j < n; ++j)
-    for (int i = j + 1 + t; i < n; i += kWinThreads) st2(T + i + j * ldt, wcx{0.0, 0.0});
+    for (int i = j + 1 + t; i < n; i += kWinThreads) st2(T + i + j * ld, wcx{0.0, 0.0});
   __syncthreads();
   return ok;
 }
 
-// [y, z, lam] = eig(C) for the n x n matrix C (column-major, leading dimension
-// ld, global).  Workspace ws: 4 ld x ld complex plus 4 ld; tlds: LDS space for
-// kWinLdsN^2 complex (used when n <= kWinLdsN); ctl: 4 doubles of LDS.
-// Outputs y, z: n x n (leading dimension ld), lam: n.  Returns false on a
-// QR failure (on every lane).
-__device__ bool win_eig(const double2 *C, int n, int ld, double2 *lam, double2 *y, double2 *z, double2 *ws,
-                        double2 *tlds, double *ctl) {
+// [y, z, lam] = eig(C) with the first PL of T, Q, X, W in the LDS pool and
+// the rest in ws (leading dimension n | 1 for all four).
+template <int PL>
+__device__ __attribute__((noinline)) bool win_eig_pl(const double2 *C, int n, int ld, double2 *lam, double2 *y,
+                                                     double2 *z, double2 *ws, int which) {
   const int t = threadIdx.x;
-  double2 *A = ws, *Q = ws + size_t(ld) * ld, *X = ws + 2 * size_t(ld) * ld, *W = ws + 3 * size_t(ld) * ld;
-  double2 *v = ws + 4 * size_t(ld) * ld;  // n
-  double2 *lm = v + ld;                   // n unsorted eigenvalues
-  int *ord = reinterpret_cast<int *>(lm + ld);  // n
+  const int lw = n | 1;  // odd leading dimension
+  const size_t nn = size_t(lw) * n;
+  double2 *A, *Q, *X, *W;
+  if constexpr (PL >= 1) A = win_lds.pool; else A = ws;
+  if constexpr (PL >= 2) Q = win_lds.pool + nn; else Q = ws + nn;
+  if constexpr (PL >= 3) X = win_lds.pool + 2 * nn; else X = ws + 2 * nn;
+  if constexpr (PL >= 4) W = win_lds.pool + 3 * nn; else W = ws + 3 * nn;
+  double2 *lm = win_lds.lm;
+  int *ord = win_lds.ord;
   for (int j = 0; j < n; ++j)
-    for (int i = t; i < n; i += kWinThreads) A[i + j * ld] = C[i + j * ld];
+    for (int i = t; i < n; i += kWinThreads) A[i + j * lw] = C[i + j * ld];
   __syncthreads();
-  if (n == 0) return true;
-  win_hessenberg(A, Q, n, ld, v);
-  bool ok;
-  if (n <= kWinLdsN) {
-    for (int j = 0; j < n; ++j)
-      for (int i = t; i < n; i += kWinThreads) tlds[i + j * kWinLdsN] = A[i + j * ld];
-    __syncthreads();
-    ok = win_schur(tlds, kWinLdsN, Q, ld, n, ctl);
-    for (int j = 0; j < n; ++j)
-      for (int i = t; i < n; i += kWinThreads) A[i + j * ld] = tlds[i + j * kWinLdsN];
-    __syncthreads();
-  } else {
-    ok = win_schur(A, ld, Q, ld, n, ctl);
-  }
-  if (!ok) return false;
+  win_hessenberg(A, Q, n, lw, win_lds.vec);
+  if (!win_schur(A, Q, n, lw)) return false;
   double tmax = 0.0;
   for (int j = 0; j < n; ++j)
-    for (int i = t; i <= j && i < n; i += kWinThreads) tmax = fmax(tmax, wabs(ld2(A + i + j * ld)));
+    for (int i = t; i <= j && i < n; i += kWinThreads) tmax = fmax(tmax, wabs(ld2(A + i + j * lw)));
 #pragma unroll
   for (int off = kWinThreads / 2; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off, kWinThreads));
   const double smin = fmax(2.220446049250313e-16 * tmax, 2.2250738585072014e-308);
   // eigenvectors of T, one per lane: right x (x_k = 1, x_j = 0 for j > k) in
   // column k of X, left w (w_k = 1, w_j = 0 for j < k) in column k of W
   for (int k = t; k < n; k += kWinThreads) {
-    const wcx lk = ld2(A + k + k * ld);
+    const wcx lk = ld2(A + k + k * lw);
     lm[k] = make_double2(lk.x, lk.y);
-    double2 *x = X + size_t(k) * ld, *w = W + size_t(k) * ld;
-    for (int i = 0; i < n; ++i) {
-      x[i] = make_double2(0.0, 0.0);
-      w[i] = make_double2(0.0, 0.0);
-    }
+    double2 *x = X + size_t(k) * lw, *w = W + size_t(k) * lw;
     x[k] = make_double2(1.0, 0.0);
     for (int i = k - 1; i >= 0; --i) {
       wcx s = {0.0, 0.0};
-      for (int j = i + 1; j <= k; ++j) cfma(s, ld2(A + i + j * ld), ld2(x + j));
-      wcx d = ld2(A + i + i * ld) - lk;
+#pragma unroll 4
+      for (int j = i + 1; j <= k; ++j) cfma(s, ld2(A + i + j * lw), ld2(x + j));
+      wcx d = ld2(A + i + i * lw) - lk;
       if (wabs(d) < smin) d = {smin, 0.0};
       st2(x + i, -wdiv(s, d));
     }
     w[k] = make_double2(1.0, 0.0);
     for (int i = k + 1; i < n; ++i) {
       wcx s = {0.0, 0.0};
-      for (int j = k; j < i; ++j) cfmac(s, ld2(A + j + i * ld), ld2(w + j));
-      wcx d = cconj(ld2(A + i + i * ld) - lk);
+#pragma unroll 4
+      for (int j = k; j < i; ++j) cfmac(s, ld2(A + j + i * lw), ld2(w + j));
+      wcx d = cconj(ld2(A + i + i * lw) - lk);
       if (wabs(d) < smin) d = {smin, 0.0};
       st2(w + i, -wdiv(s, d));
     }
   }
   __syncthreads();
-  // sort order (lane 0): |lambda| ascending, ties by imaginary part descending
+  // sort order (lane 0): the criterion's key ascending, ties (to 1e-12 of the
+  // larger modulus) by imaginary part descending
   if (t == 0) {
+    auto sort_key = [which](wcx l) { return which == 1 ? l.x : (which == 2 ? -wabs(l) : wabs(l)); };
     for (int i = 0; i < n; ++i) ord[i] = i;
     for (int i = 1; i < n; ++i) {
       const int key = ord[i];
       const wcx lk = ld2(lm + key);
-      const double ak = wabs(lk);
+      const double ak = sort_key(lk);
       int p = i - 1;
       while (p >= 0) {
         const wcx lp = ld2(lm + ord[p]);
-        const double ap = wabs(lp);
+        const double ap = sort_key(lp);
         bool after;  // does ord[p] come after key?
-        if (fabs(ap - ak) > 1e-12 * fmax(fmax(ap, ak), 1e-300))
+        if (fabs(ap - ak) > 1e-12 * fmax(fmax(wabs(lp), wabs(lk)), 1e-300))
           after = ap > ak;
         else if (lp.y != lk.y)
           after = lp.y < lk.y;
@@ -326,32 +361,55 @@ __device__ bool win_eig(const double2 *C, int n, int ld, double2 *lam, double2 *
     }
   }
   __syncthreads();
-  // back to the original basis: y = Q x, z = Q w, normalised; one output column per lane
+  // back to the original basis: y = Q x, z = Q w, one output column per lane;
+  // a first pass for ||y|| and z^+ y, a second that writes the normalised
+  // vectors (||y|| = 1, z^+ y = 1)
   for (int c = t; c < n; c += kWinThreads) {
     const int k = ord[c];
     lam[c] = lm[k];
-    const double2 *x = X + size_t(k) * ld, *w = W + size_t(k) * ld;
+    const double2 *x = X + size_t(k) * lw, *w = W + size_t(k) * lw;
     double yn = 0.0;
-    for (int i = 0; i < n; ++i) {
-      wcx sy = {0.0, 0.0}, sz = {0.0, 0.0};
-      for (int j = 0; j <= k; ++j) cfma(sy, ld2(Q + i + j * ld), ld2(x + j));
-      for (int j = k; j < n; ++j) cfma(sz, ld2(Q + i + j * ld), ld2(w + j));
-      st2(y + i + c * ld, sy);
-      st2(z + i + c * ld, sz);
-      yn += sy.x * sy.x + sy.y * sy.y;
-    }
-    yn = sqrt(yn);
     wcx d = {0.0, 0.0};
     for (int i = 0; i < n; ++i) {
-      const wcx yi = (1.0 / yn) * ld2(y + i + c * ld);
-      st2(y + i + c * ld, yi);
-      cfmac(d, ld2(z + i + c * ld), yi);
+      wcx sy = {0.0, 0.0}, sz = {0.0, 0.0};
+#pragma unroll 4
+      for (int j = 0; j <= k; ++j) cfma(sy, ld2(Q + i + j * lw), ld2(x + j));
+#pragma unroll 4
+      for (int j = k; j < n; ++j) cfma(sz, ld2(Q + i + j * lw), ld2(w + j));
+      yn += sy.x * sy.x + sy.y * sy.y;
+      cfmac(d, sz, sy);
     }
-    const wcx dc = cconj(d);
-    for (int i = 0; i < n; ++i) st2(z + i + c * ld, wdiv(ld2(z + i + c * ld), dc));
+    yn = sqrt(yn);
+    const double inv = 1.0 / yn;
+    const wcx dc = cconj(inv * d);  // conj(z^+ y) after y is scaled by 1 / ||y||
+    for (int i = 0; i < n; ++i) {
+      wcx sy = {0.0, 0.0}, sz = {0.0, 0.0};
+#pragma unroll 4
+      for (int j = 0; j <= k; ++j) cfma(sy, ld2(Q + i + j * lw), ld2(x + j));
+#pragma unroll 4
+      for (int j = k; j < n; ++j) cfma(sz, ld2(Q + i + j * lw), ld2(w + j));
+      st2(y + i + c * ld, inv * sy);
+      st2(z + i + c * ld, wdiv(sz, dc));
+    }
   }
   __syncthreads();
   return true;
+}
+
+// [y, z, lam] = eig(C) for the n x n matrix C (column-major, leading dimension
+// ld, global; 1 <= n <= kWinMaxN).  Workspace ws (global):
+// window_eig_ws_entries(n) complex, for the matrices the LDS pool does not
+// hold (all four fit up to n = 48, T and Q up to n = 69).  Outputs y, z: n x n
+// (leading dimension ld), lam: n, in the order of the criterion which (0
+// |lambda| ascending, 1 real part ascending, 2 |lambda| descending).  Returns
+// false on a QR failure (on every lane).
+__device__ bool win_eig(const double2 *C, int n, int ld, double2 *lam, double2 *y, double2 *z, double2 *ws,
+                        int which) {
+  if (n <= 0) return true;
+  const size_t nn = size_t(n | 1) * n;
+  if (4 * nn <= size_t(kWinLdsEntries)) return win_eig_pl<4>(C, n, ld, lam, y, z, ws, which);
+  if (2 * nn <= size_t(kWinLdsEntries)) return win_eig_pl<2>(C, n, ld, lam, y, z, ws, which);
+  return win_eig_pl<0>(C, n, ld, lam, y, z, ws, which);
 }
 
 }  // namespace ebicg

@@ -8,15 +8,15 @@
 #include "winla.h"
 
 namespace ebicg {
+static_assert(kWinMaxN >= kMaxCols, "the device eigensolver takes every window size");
 namespace {
 
-__host__ __device__ constexpr size_t window_eig_ws_entries_dev(int n) { return 4 * size_t(n) * n + 3 * size_t(n) + 8; }
+// win_eig's global fallback: four matrices of leading dimension n | 1
+__host__ __device__ constexpr size_t window_eig_ws_entries_dev(int n) { return 4 * size_t(n | 1) * n + 8; }
 
 __global__ void __launch_bounds__(kWinThreads)
     k_small_eig(const double2 *C, int n, double2 *lam, double2 *y, double2 *z, double2 *ws, int *status) {
-  __shared__ double2 tlds[kWinLdsN * kWinLdsN];
-  __shared__ double ctl[4];
-  const bool ok = win_eig(C, n, n, lam, y, z, ws, tlds, ctl);
+  const bool ok = win_eig(C, n, n, lam, y, z, ws, 0);
   if (threadIdx.x == 0) *status = ok ? 1 : 0;
 }
 
@@ -64,56 +64,90 @@ __device__ void win_build_H(double2 *H, int ld, const WinCols &cols, const Krylo
   __syncthreads();
 }
 
-// Alg. BiCG-eigen (mode 0) or the final extraction of Alg. eigBiCG (mode 1)
-// on the device.  Mode 0: [y, z] = eig(H^(m)), [y', z'] = eig(H^(m-1)) with a
-// zero appended, the 2 nev coefficient vectors biorthogonalised (two-sided
+// Scratch layout of the window kernels (complex entries of ws), for an
+// n-column window and k2 = 2 nev: offsets in the order of the members.
+struct WinWs {
+  double2 *H, *eta, *zeta, *y1, *z1, *lam1, *ews1;     // block 0: H^(n), eig(H^(n)), eig workspace
+  double2 *H2, *eta2, *zeta2, *y2, *z2, *lam2, *ews2;  // block 1: its own H, eig(H^(n-1))
+  int *ok;                                             // eig status of the two blocks
+  double2 *Y, *Z, *HY, *T, *u, *q, *lamT, *yv, *zv;    // the restart's second phase
+  // the sizes, in member order; ok takes one entry
+  static constexpr int kParts = 25;
+  __host__ __device__ static void sizes(int n, int nev, size_t (&sz)[kParts]) {
+    const size_t nn = size_t(n) * n, k2 = 2 * size_t(nev), E = window_eig_ws_entries_dev(n);
+    const size_t v[kParts] = {nn, size_t(n), size_t(n), nn, nn, size_t(n), E,  // block 0
+                              nn, size_t(n), size_t(n), nn, nn, size_t(n), E,  // block 1
+                              1,                                               // ok
+                              n * k2, n * k2, n * k2, k2 * k2, k2 * k2, k2 * k2, k2, size_t(n), size_t(n), 0};
+    for (int i = 0; i < kParts; ++i) sz[i] = v[i];
+  }
+  __host__ __device__ static size_t total(int n, int nev) {
+    size_t sz[kParts], t = 0;
+    sizes(n, nev, sz);
+    for (int i = 0; i < kParts; ++i) t += sz[i];
+    return t;
+  }
+  __device__ WinWs(double2 *ws, int n, int nev) {
+    size_t sz[kParts];
+    sizes(n, nev, sz);
+    double2 *p[kParts];
+    size_t off = 0;
+    for (int i = 0; i < kParts; ++i) {
+      p[i] = ws + off;
+      off += sz[i];
+    }
+    H = p[0], eta = p[1], zeta = p[2], y1 = p[3], z1 = p[4], lam1 = p[5], ews1 = p[6];
+    H2 = p[7], eta2 = p[8], zeta2 = p[9], y2 = p[10], z2 = p[11], lam2 = p[12], ews2 = p[13];
+    ok = reinterpret_cast<int *>(p[14]);
+    Y = p[15], Z = p[16], HY = p[17], T = p[18], u = p[19], q = p[20], lamT = p[21], yv = p[22], zv = p[23];
+  }
+};
+
+__device__ __forceinline__ bool win_skipped(const KrylovState *S, int jtag) { return S && S->stopped && jtag > S->stop_at; }
+
+// Alg. BiCG-eigen on the device, first phase: block 0 solves [y, z] =
+// eig(H^(m)), block 1 [y', z'] = eig(H^(m-1)) (the leading block of its own
+// copy of H); the two run on two CUs at once.  Skipped when the solve stopped
+// before iteration jtag.
+__global__ void __launch_bounds__(kWinThreads)
+    k_window_pair(WinCols cols, int nev, int which, KrylovHistory h, const double2 *lam_prev,
+                  const double2 *dots_prev, double2 *ws, int jtag, const KrylovState *S) {
+  if (win_skipped(S, jtag)) return;
+  const int m = cols.n;
+  const WinWs w(ws, m, nev);
+  const bool second = blockIdx.x == 1;
+  double2 *H = second ? w.H2 : w.H;
+  win_build_H(H, m, cols, h, lam_prev, dots_prev, dots_prev + 2 * nev, second ? w.eta2 : w.eta,
+              second ? w.zeta2 : w.zeta);
+  const bool ok = second ? win_eig(H, m - 1, m, w.lam2, w.y2, w.z2, w.ews2, which)
+                         : win_eig(H, m, m, w.lam1, w.y1, w.z1, w.ews1, which);
+  if (threadIdx.x == 0) w.ok[blockIdx.x] = ok ? 1 : 0;
+}
+
+// Alg. BiCG-eigen, second phase (one block): the 2 nev coefficient vectors
+// [y_1..nev, y'_1..nev with a zero appended] biorthogonalised (two-sided
 // Gram-Schmidt, twice; a pair with pivot below 1e-12 |y||z| is dropped),
 // T = Zt^+ H Yt, [u, q, Lambda] = eig(T), CV = Yt u, CW = Zt q with
 // ||CV_k|| = 1, CW_k^+ CV_k = 1, written with the stored residuals' scales
-// folded in (cV = diag(eta) CV, cW = diag(zeta) CW), columns >= kept zero,
-// lam_out = Lambda, *kept_out = kept.  Mode 1: eig(H^(vs)), the first
-// min(nev, vs) pairs, cV = diag(eta) y, cW = diag(zeta) z.  Coefficient blocks
-// are n x kout column-major (kout = 2 nev in mode 0, min(nev, n) in mode 1).
+// folded in (cV = diag(eta) CV, cW = diag(zeta) CW; m x 2 nev column-major,
+// columns >= kept zero), lam_out = Lambda, *kept_out = kept (-1 if an
+// eigenproblem failed, -2 if skipped).
 __global__ void __launch_bounds__(kWinThreads)
-    k_window_eig(WinCols cols, int nev, int mode, KrylovHistory h, const double2 *lam_prev, const double2 *dots_prev,
-                 double2 *cV, double2 *cW, double2 *lam_out, int *kept_out, double2 *ws, int jtag,
-                 const KrylovState *S) {
-  if (S && S->stopped && jtag > S->stop_at) {  // the restart's iteration did not run
+    k_window_restart(WinCols cols, int nev, int which, double2 *cV, double2 *cW, double2 *lam_out, int *kept_out,
+                     double2 *ws, int jtag, const KrylovState *S) {
+  if (win_skipped(S, jtag)) {  // the restart's iteration did not run
     if (threadIdx.x == 0) *kept_out = -2;
     return;
   }
-  __shared__ double2 tlds[kWinLdsN * kWinLdsN];
-  __shared__ double ctl[4];
-  const int n = cols.n, t = threadIdx.x, ld = n;
-  const int nn = n * n;
-  double2 *H = ws, *eta = H + nn, *zeta = eta + n, *y1 = zeta + n, *z1 = y1 + nn, *lam1 = z1 + nn;
-  double2 *ews = lam1 + n;  // eig workspace
-  double2 *after_ews = ews + window_eig_ws_entries_dev(n);
-  win_build_H(H, ld, cols, h, lam_prev, dots_prev, dots_prev + 2 * nev, eta, zeta);
-  if (mode == 1) {
-    const bool ok = win_eig(H, n, ld, lam1, y1, z1, ews, tlds, ctl);
-    const int k = nev < n ? nev : n;
-    for (int c = 0; c < k; ++c)
-      for (int i = t; i < n; i += kWinThreads) {
-        st2(cV + i + c * n, ld2(eta + i) * ld2(y1 + i + c * ld));
-        st2(cW + i + c * n, ld2(zeta + i) * ld2(z1 + i + c * ld));
-      }
-    for (int c = t; c < k; c += kWinThreads) lam_out[c] = lam1[c];
-    if (t == 0) *kept_out = ok ? k : -1;
-    return;
-  }
-  const int m = n, k2 = 2 * nev;
-  // eig(H^(m)) and eig(H^(m-1)) (the leading block, same leading dimension)
-  double2 *y2 = after_ews, *z2 = y2 + nn, *lam2 = z2 + nn;
-  double2 *Y = lam2 + n, *Z = Y + size_t(m) * k2, *HY = Z + size_t(m) * k2;
-  double2 *T = HY + size_t(m) * k2, *u = T + k2 * k2, *q = u + k2 * k2, *lamT = q + k2 * k2;
-  double2 *yv = lamT + k2, *zv = yv + m;
-  bool ok = win_eig(H, m, ld, lam1, y1, z1, ews, tlds, ctl);
-  ok = win_eig(H, m - 1, ld, lam2, y2, z2, ews, tlds, ctl) && ok;
-  if (!ok) {
+  const int m = cols.n, t = threadIdx.x, ld = m, k2 = 2 * nev;
+  const WinWs w(ws, m, nev);
+  if (!(w.ok[0] == 1 && w.ok[1] == 1)) {
     if (t == 0) *kept_out = -1;
     return;
   }
+  double2 *H = w.H, *eta = w.eta, *zeta = w.zeta, *y1 = w.y1, *z1 = w.z1, *y2 = w.y2, *z2 = w.z2;
+  double2 *Y = w.Y, *Z = w.Z, *HY = w.HY, *T = w.T, *u = w.u, *q = w.q, *lamT = w.lamT, *yv = w.yv, *zv = w.zv;
+  double2 *ews = w.ews1;
   for (int k = 0; k < nev; ++k)
     for (int i = t; i < m; i += kWinThreads) {
       Y[i + k * m] = y1[i + k * ld];
@@ -188,7 +222,7 @@ __global__ void __launch_bounds__(kWinThreads)
     st2(T + p + c * kept, s);
   }
   __syncthreads();
-  if (!win_eig(T, kept, kept, lamT, u, q, ews, tlds, ctl)) {
+  if (!win_eig(T, kept, kept, lamT, u, q, ews, which)) {
     if (t == 0) *kept_out = -1;
     return;
   }
@@ -218,20 +252,44 @@ __global__ void __launch_bounds__(kWinThreads)
   if (t == 0) *kept_out = kept;
 }
 
+// The final extraction of Alg. eigBiCG on the device (one block):
+// eig(H^(vs)) of the n-column window, the first min(nev, n) pairs, cV =
+// diag(eta) y, cW = diag(zeta) z (n x kout column-major), lam_out, *kept_out
+// (-1 if the eigenproblem failed).
+__global__ void __launch_bounds__(kWinThreads)
+    k_window_final(WinCols cols, int nev, int which, KrylovHistory h, const double2 *lam_prev,
+                   const double2 *dots_prev, double2 *cV, double2 *cW, double2 *lam_out, int *kept_out, double2 *ws) {
+  const int n = cols.n, t = threadIdx.x, ld = n;
+  const WinWs w(ws, n, nev);
+  win_build_H(w.H, ld, cols, h, lam_prev, dots_prev, dots_prev + 2 * nev, w.eta, w.zeta);
+  const bool ok = win_eig(w.H, n, ld, w.lam1, w.y1, w.z1, w.ews1, which);
+  const int k = nev < n ? nev : n;
+  for (int c = 0; c < k; ++c)
+    for (int i = t; i < n; i += kWinThreads) {
+      st2(cV + i + c * n, ld2(w.eta + i) * ld2(w.y1 + i + c * ld));
+      st2(cW + i + c * n, ld2(w.zeta + i) * ld2(w.z1 + i + c * ld));
+    }
+  for (int c = t; c < k; c += kWinThreads) lam_out[c] = w.lam1[c];
+  if (t == 0) *kept_out = ok ? k : -1;
+}
+
 }  // namespace
 
 size_t window_eig_ws_entries(int n) { return window_eig_ws_entries_dev(n); }
 
-size_t window_restart_ws_entries(int m, int nev) {
-  const size_t nn = size_t(m) * m, k2 = 2 * size_t(nev);
-  return nn + 2 * m + 2 * nn + m + window_eig_ws_entries(m) + 2 * nn + m + 3 * m * k2 + 3 * k2 * k2 + k2 + 2 * m + 64;
-}
+size_t window_restart_ws_entries(int m, int nev) { return WinWs::total(m, nev) + 64; }
 
-void launch_window_eig(const WinCols &cols, int nev, int mode, const KrylovHistory &h, const double2 *lam_prev,
-                       const double2 *dots_prev, double2 *cV, double2 *cW, double2 *lam_out, int *kept_out,
-                       double2 *ws, int jtag, const KrylovState *S, hipStream_t st) {
-  EB_LAUNCH(k_window_eig, dim3(1), dim3(kWinThreads), 0, st, cols, nev, mode, h, lam_prev, dots_prev, cV, cW,
-            lam_out, kept_out, ws, jtag, S);
+void launch_window_eig(const WinCols &cols, int nev, int mode, int which, const KrylovHistory &h,
+                       const double2 *lam_prev, const double2 *dots_prev, double2 *cV, double2 *cW, double2 *lam_out,
+                       int *kept_out, double2 *ws, int jtag, const KrylovState *S, hipStream_t st) {
+  if (mode == 1) {
+    EB_LAUNCH(k_window_final, dim3(1), dim3(kWinThreads), 0, st, cols, nev, which, h, lam_prev, dots_prev, cV, cW,
+              lam_out, kept_out, ws);
+    return;
+  }
+  EB_LAUNCH(k_window_pair, dim3(2), dim3(kWinThreads), 0, st, cols, nev, which, h, lam_prev, dots_prev, ws, jtag, S);
+  EB_LAUNCH(k_window_restart, dim3(1), dim3(kWinThreads), 0, st, cols, nev, which, cV, cW, lam_out, kept_out, ws,
+            jtag, S);
 }
 
 void launch_small_eig(const double2 *C, int n, double2 *lam, double2 *y, double2 *z, double2 *ws, int *status,

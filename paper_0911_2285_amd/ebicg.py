@@ -50,6 +50,7 @@ class _EigParams(ctypes.Structure):
         ("rhat", ctypes.c_int32),
         ("window", ctypes.c_int32),
         ("device_eig", ctypes.c_int32),
+        ("sort", ctypes.c_int32),
     ]
 
 
@@ -312,15 +313,22 @@ def op_apply_block(op, out, inp, k, dagger=False, prec="fp64", stream=None):
     _check(lib().eb_op_apply_block(op.handle, po, pi, int(k), int(bool(dagger)), PREC[prec], _stream(stream)))
 
 
-def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, window="fp64", device_eig=False, stream=None):
+SORT = {"SM": 0, "SR": 1, "LM": 2}
+
+
+def eigbicg_solve(op, b, x, nev, m, tol, maxiter=10000, rhat=0, window="fp64", device_eig=False, sort="SM",
+                  stream=None):
     """One eigBiCG solve that grows the deflation space; returns (stats, ritz values).
 
     rhat: 0 -> rhat_0 = r_0; 1 -> gamma5 r_0; 2 -> the gamma5-Hermitian form
     (shadow vectors implicit, one D per iteration).  window: "fp64" or "fp32"
-    storage of the window vectors; device_eig: the window eigenproblems on the GPU."""
+    storage of the window vectors; device_eig: the window eigenproblems on the GPU.
+    sort: the pairs kept and returned, "SM" smallest |lambda|, "SR" smallest real
+    part, "LM" largest |lambda| (or the eb_sort value)."""
     import torch
 
-    p = _EigParams(int(nev), int(m), float(tol), int(maxiter), int(rhat), PREC[window], int(bool(device_eig)))
+    srt = SORT[sort] if isinstance(sort, str) else int(sort)
+    p = _EigParams(int(nev), int(m), float(tol), int(maxiter), int(rhat), PREC[window], int(bool(device_eig)), srt)
     st = _Stats()
     ritz = np.zeros(int(nev), np.complex128)
     rc = lib().eb_eigbicg_solve(
@@ -423,24 +431,30 @@ def op_trim(op, stream=None):
     _check(lib().eb_op_trim(op.handle, _stream(stream)))
 
 
+TILE_FORMS = 7  # EB_TILE_FORMS
+
+
 def op_batch_tune(op, prec="fp32", stream=None):
     """The batch autotuner's choice for one precision: {"k": best k, "stage": {k: tile form},
-    "ms_per_rhs": {k: [global reads, LDS-staged, bricks 8x8x4x4, 8x8x8x8, 4x4x4x4, unfenced]}} (0 for a form the
-    operator does not admit; runs the tuner once per operator and precision)."""
+    "ms_per_rhs": {k: [global reads, LDS-staged, bricks 8x8x4x4, 8x8x8x8, 4x4x4x4, unfenced,
+    t-marching]}} (0 for a form the operator does not admit; runs the tuner once per operator
+    and precision)."""
     kb = ctypes.c_int32(0)
     stage = np.zeros(5, np.int32)
-    ms = np.zeros(30, np.float64)
+    ms = np.zeros(5 * TILE_FORMS, np.float64)
     _check(lib().eb_op_batch_tune(op.handle, PREC[prec], _stream(stream), ctypes.byref(kb), stage.ctypes.data,
                                   ms.ctypes.data))
     ks = [1, 2, 4, 8, 16]
+    F = TILE_FORMS
     return {"k": kb.value, "stage": {k: int(stage[i]) for i, k in enumerate(ks)},
-            "ms_per_rhs": {k: [float(v) for v in ms[6 * i: 6 * i + 6]] for i, k in enumerate(ks)}}
+            "ms_per_rhs": {k: [float(v) for v in ms[F * i: F * i + F]] for i, k in enumerate(ks)}}
 
 
 def op_batch_set_tile(op, prec, k, stage):
     """Force the tile form of the batched stencil for (prec, k): 0 global reads, 1 LDS-staged,
-    2 / 3 / 4 global reads in bricks, 5 global reads without fences between hops (full-lattice
-    operators), -1 built-in rule."""
+    2 / 3 / 4 global reads in bricks, 5 global reads without fences between hops, 6 t-marching
+    boxes (full-lattice operators; the box must hold a whole number of blocks for k), -1
+    built-in rule."""
     _check(lib().eb_op_batch_set_tile(op.handle, PREC[prec], int(k), int(stage)))
 
 

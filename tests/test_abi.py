@@ -1,4 +1,5 @@
 """The C-ABI library loads and exports every declared symbol; host-only calls work without a GPU."""
+import ctypes
 import os
 import re
 
@@ -40,6 +41,34 @@ def test_library_exports_every_declared_symbol(eb):
         assert hasattr(L, name), name
     assert set(_declared()) == set(eb.SYMBOLS)
     assert "gfx950" in eb.version()
+
+
+def _header_structs():
+    """Field (C type, name) lists of the header's typedef'd parameter structs."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(eb_[a-z_]+)\s*;", txt, flags=re.S):
+        out[name] = [tuple(f.split()) for f in body.split(";") if f.strip()]
+    return out
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes mirrors of the parameter and statistics structs have the header's
+    fields, in its order, with the same widths (a field added to one side only
+    would shift every later field)."""
+    from paper_0911_2285_amd import ebicg
+
+    ctype = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "eb_prec": ctypes.c_int32,
+             "uint64_t": ctypes.c_uint64, "int64_t": ctypes.c_int64}
+    mirrors = {"eb_eig_params": ebicg._EigParams, "eb_solve_params": ebicg._SolveParams, "eb_stats": ebicg._Stats,
+               "eb_session_params": ebicg._SessionParams}
+    structs = _header_structs()
+    assert set(mirrors) <= set(structs)
+    for name, cls in mirrors.items():
+        fields = structs[name]
+        assert [f[1] for f in fields] == [f[0] for f in cls._fields_], name
+        for (ct, fname), (_, pyt) in zip(fields, cls._fields_):
+            assert ctypes.sizeof(ctype[ct]) == ctypes.sizeof(pyt), (name, fname)
 
 
 @pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (16, 3), (40, 4), (64, 5)])

@@ -255,8 +255,9 @@ def test_dslash_block_parity(gpu_lib, k):
 @pytest.mark.parametrize("eo", [False, True])
 def test_block_tile_forms_and_tuner(gpu_lib, eo):
     """Every tile form of the multi-RHS stencil (global reads in site order,
-    LDS-staged tile, global reads in 8x8x4x4, 8x8x8x8 and 4x4x4x4 bricks;
-    the even-odd hop has the first two), forced per precision and k, against
+    LDS-staged tile, global reads in 8x8x4x4, 8x8x8x8 and 4x4x4x4 bricks,
+    unfenced global reads, t-marching boxes; the even-odd hop has the first
+    two), forced per precision and k, against
     the oracle: FP64 at 1e-12 (D, or Dhat for an even-odd operator), FP32 / BF16
     storage against the first form within their rounding; forms the operator
     does not admit are rejected; then the autotuner's table names a form per k
@@ -268,7 +269,7 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
     U = synth.random_su3_links(dims, 0.3, 91)
     op = gpu_lib.op_create(U, kappa, dims, eo=eo)
     par = W.parity(dims)
-    forms = (0, 1) if eo else (0, 1, 2, 3, 4, 5)
+    forms = (0, 1) if eo else (0, 1, 2, 3, 4, 5, 6)
     for k in (2, 16):
         psi = np.stack([synth.gaussian_spinor(V, 70 + c) for c in range(k)])
         x = torch.from_numpy(psi).to("cuda:0")
@@ -305,13 +306,16 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
             print(f"eo={eo} k={k} {prec}: largest difference between tile forms {d:.2e}")
             assert d <= bound, (k, prec, d)
             gpu_lib.op_batch_set_tile(op, prec, k, -1)
-    for bad in ((3, 1), (4, 2) if eo else (4, 6)):
+    for bad in ((3, 1), (4, 2) if eo else (4, 7), (4, 6) if eo else (4, -2)):
         with pytest.raises(gpu_lib.EbicgError):
             gpu_lib.op_batch_set_tile(op, "fp32", *bad)
     odd = gpu_lib.op_create(synth.random_su3_links((4, 4, 4, 8), 0.3, 92), kappa, (4, 4, 4, 8))
     with pytest.raises(gpu_lib.EbicgError):
         gpu_lib.op_batch_set_tile(odd, "fp32", 4, 2)  # the 8-wide brick does not divide Lx = 4
+    with pytest.raises(gpu_lib.EbicgError):
+        gpu_lib.op_batch_set_tile(odd, "fp32", 2, 6)  # a 4 x 4 x 4 box of 2 columns is half a block
     gpu_lib.op_batch_set_tile(odd, "fp32", 4, 4)
+    gpu_lib.op_batch_set_tile(odd, "fp32", 4, 6)
     for prec in ("fp32", "bf16"):
         t = gpu_lib.op_batch_tune(op, prec)
         print(prec, t)
@@ -319,7 +323,7 @@ def test_block_tile_forms_and_tuner(gpu_lib, eo):
         assert all(s in forms for s in t["stage"].values())
         for kk, ms in t["ms_per_rhs"].items():
             timed = (1,) if kk == 1 else forms   # one column: the staged form of the one-at-a-time solver
-            assert all(ms[f] > 0 for f in timed) and all(ms[f] == 0 for f in range(6) if f not in timed)
+            assert all(ms[f] > 0 for f in timed) and all(ms[f] == 0 for f in range(7) if f not in timed)
             assert ms[t["stage"][kk]] == min(ms[f] for f in timed)
 
 
@@ -339,7 +343,7 @@ def test_block_tile_forms_full_size_sampled(gpu_lib):
     sites = _sample_sites(dims, n=12)
     refs = [W.apply_D_sites(U, psi[c], kappa, dims, sites) for c in range(k)]
     scale = max(np.abs(r).max() for r in refs)
-    for stage in (0, 1, 2, 3, 4, 5):
+    for stage in (0, 1, 2, 3, 4, 5, 6):
         gpu_lib.op_batch_set_tile(op, "fp64", k, stage)
         y = torch.empty_like(x)
         gpu_lib.op_apply_block(op, y, x, k)
@@ -351,7 +355,7 @@ def test_block_tile_forms_full_size_sampled(gpu_lib):
 
 def test_dslash_block_32x64_sampled(gpu_lib):
     """32^3 x 64 (the batching lattice), FP32 storage, k = 16 columns: the
-    form the autotuner picks there (8x8x8x8 bricks) and form 0, at sampled
+    8x8x8x8 bricks, form 0, the unfenced form and the t-marching boxes, at sampled
     sites of every column against the per-site oracle on the rounded input
     (FP32 rounding bound 5e-7 of the largest entry)."""
     import torch
@@ -367,7 +371,7 @@ def test_dslash_block_32x64_sampled(gpu_lib):
     U32 = U.astype(np.complex64).astype(np.complex128)
     refs = [W.apply_D_sites(U32, psi[c].astype(np.complex128), kappa, dims, sites) for c in range(k)]
     scale = max(np.abs(r).max() for r in refs)
-    for stage in (3, 0, 5):
+    for stage in (3, 0, 5, 6):
         gpu_lib.op_batch_set_tile(op, "fp32", k, stage)
         y = torch.empty_like(x)
         gpu_lib.op_apply_block(op, y, x, k, prec="fp32")
