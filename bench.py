@@ -231,7 +231,8 @@ def kernel_source_hash(cls="bicg_matvec"):
 def deflation_sweep(eb):
     """Deflation speed-up on small near-critical lattices with rough links (the
     analogue of the paper's Fig. 1): BiCGStab iterations per right-hand side
-    after n1 = 8 eigBiCG solves, against the same sources undeflated.  The
+    after n1 = 8 eigBiCG solves for three (nev, m), and for (10, 40) after
+    n1 = 2, 4, 8, 12 solves, against the same sources undeflated.  The
     bench workload's eps = 0.3 links give a dense near-free low spectrum where
     80 vectors do not change the iteration count; eps = 1.0 near the critical
     kappa separates the low modes."""
@@ -269,6 +270,21 @@ def deflation_sweep(eb):
             if dt is not None:
                 rec["with_deftol"] = dt
             out.append(rec)
+        # the n1 axis of Fig. 1: (nev, m) = (10, 40), the space after n1 = 2, 4, 8, 12
+        # eigBiCG solves, each tried on the same four further sources
+        B2 = [torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, i))).to("cuda:0") for i in range(12, 16)]
+        op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=120)
+        und2 = [eb.deflated_bicg_solve(op, b, torch.zeros_like(b), tol=1e-8, maxiter=20000)["iters"] for b in B2]
+        axis = []
+        for i in range(12):
+            eb.eigbicg_solve(op, B[i], torch.zeros_like(B[i]), nev=10, m=40, tol=1e-8, maxiter=20000)
+            if i + 1 in (2, 4, 8, 12):
+                it = [eb.deflated_bicg_solve(op, b, torch.zeros_like(b), tol=1e-8, maxiter=20000)["iters"] for b in B2]
+                axis.append({"n1": i + 1, "K": eb.defl_info(op)[0], "deflated_iters": it,
+                             "speedup": round(float(np.mean(und2) / np.mean(it)), 3)})
+        eb.op_destroy(op)
+        out.append({"lattice": list(dims), "eps": 1.0, "kappa": kappa, "nev": 10, "m": 40,
+                    "undeflated_iters": und2, "n1_axis": axis})
     return out
 
 
@@ -460,9 +476,9 @@ def proj_pass(dims=(16, 16, 16, 32), kappa=0.122, n1=8, nev=10, m=40, nrhs=16):
 def pmc_pass(workload):
     """One pass of the workload's roofline kernel, then a plain device copy of
     COPY_BYTES for the counter calibration: for the incremental workloads one
-    eigBiCG solve (its BiCG matvec launches), for batch32x64 one batched
-    mixed-precision solve of the 16 sources with the tuned k and tile form (its
-    k_bstab_v launches; no deflation space, which does not change the stencil)."""
+    eigBiCG solve (its BiCG matvec launches), for batch32x64 batched
+    mixed-precision solves of the 16 sources at k = 2, 4, 8 and 16, each k in
+    its tuned tile form (no deflation space, which does not change the passes)."""
     import torch
 
     import synth
@@ -473,13 +489,16 @@ def pmc_pass(workload):
         dims = W["dims"]
         V = synth.volume(dims)
         op = eb.op_create(synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"])), W["kappa"], dims, bc_t=-1)
-        k = eb.op_batch_tune(op, W["inner"])["k"]
+        tuned = eb.op_batch_tune(op, W["inner"])
         B = torch.stack([torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], i)))
                          for i in range(W["nrhs"])]).to("cuda:0")
-        X = torch.zeros_like(B)
-        eb.deflated_bicg_solve(op, B, X, tol=W["tol"], maxiter=20000, nrhs=W["nrhs"], inner=W["inner"],
-                               inner_tol=W["inner_tol"], batch=0)
-        del B, X
+        for kk in (2, 4, 8, 16):  # every k the tuner may pick, each in its tuned tile form
+            X = torch.zeros_like(B)
+            eb.deflated_bicg_solve(op, B, X, tol=W["tol"], maxiter=20000, nrhs=W["nrhs"], inner=W["inner"],
+                                   inner_tol=W["inner_tol"], batch=kk)
+            del X
+        k = tuned["k"]
+        del B
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -501,18 +520,40 @@ def pmc_pass(workload):
     log("[bench] pmc pass done")
 
 
+def _template_args(name, kernel):
+    """Top-level template arguments of kernel<...> in a demangled kernel name."""
+    i = name.find(kernel + "<")
+    if i < 0:
+        return None
+    j, depth, args, cur = i + len(kernel) + 1, 1, [], ""
+    while j < len(name) and depth:
+        ch = name[j]
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+            if depth == 0:
+                break
+        if ch == "," and depth == 1:
+            args.append(cur.strip())
+            cur = ""
+        else:
+            cur += ch
+        j += 1
+    args.append(cur.strip())
+    return args
+
+
 def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="bicg_matvec"):
     import csv
 
-    def per_dispatch(path, counter, match):
-        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(_find_csv(path, "counter_collection.csv")))
-                if r["Counter_Name"].startswith(counter) and match(r["Kernel_Name"])]
-        return sum(vals) / len(vals), len(vals)
+    def rows_of(path, counter):
+        return [r for r in csv.DictReader(open(_find_csv(path, "counter_collection.csv")))
+                if r["Counter_Name"].startswith(counter)]
 
     def calibration(path, counter):
         # the pass ends with three device-to-device copies of COPY_BYTES (the runtime's blit kernel)
-        rows = [r for r in csv.DictReader(open(path))
-                if r["Counter_Name"].startswith(counter) and "copyBuffer" in r["Kernel_Name"]]
+        rows = [r for r in rows_of(path, counter) if "copyBuffer" in r["Kernel_Name"]]
         rows.sort(key=lambda r: int(r["Dispatch_Id"]))
         vals = [float(r["Counter_Value"]) for r in rows[-3:]]
         return sum(vals) / len(vals)
@@ -521,58 +562,68 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
     V = 1
     for d in W["dims"]:
         V *= d
+    f_c = calibration(fetch_csv, "FETCH_SIZE")
+    w_c = calibration(write_csv, "WRITE_SIZE")
+    fetch_scale = COPY_BYTES / (f_c * 1024.0)
+    write_scale = COPY_BYTES / (w_c * 1024.0)
+    out = {"kernel": kernel, "class": cls, "workload": workload, "source_hash": kernel_source_hash(cls)}
     if cls.startswith("bstab"):
-        # batched stencil: the dispatches in which every column still iterates (they write all
-        # k outputs: WRITE_SIZE at its maximum); the others skip stopped columns
-        def full(path, counter):
-            rows = [r for r in csv.DictReader(open(path))
-                    if r["Counter_Name"].startswith(counter) and (kernel + "<") in r["Kernel_Name"]]
-            return rows
+        # batched pass: its kernel is k_bstab_* (or the t-marching k_bmarch with epilogue 1 for
+        # v, 2 for t); the columns per batch k is the kernel's second template argument.  Per k,
+        # the dispatches in which every column still iterates (WRITE_SIZE at its maximum; the
+        # others skip stopped columns), matched between the two runs by their order.
+        epi = {"bstab_v": "1", "bstab_t": "2"}.get(cls)
 
-        wr = full(_find_csv(write_csv, "counter_collection.csv"), "WRITE_SIZE")
-        wmax = max(float(r["Counter_Value"]) for r in wr)
-        full_ids = {r["Dispatch_Id"] for r in wr if float(r["Counter_Value"]) >= 0.99 * wmax}
-        # dispatch ids differ between the two runs; match full dispatches by their order
-        wr_sorted = sorted(wr, key=lambda r: int(r["Dispatch_Id"]))
-        order = [i for i, r in enumerate(wr_sorted) if r["Dispatch_Id"] in full_ids]
-        fr_sorted = sorted(full(_find_csv(fetch_csv, "counter_collection.csv"), "FETCH_SIZE"),
-                           key=lambda r: int(r["Dispatch_Id"]))
-        f_vals = [float(fr_sorted[i]["Counter_Value"]) for i in order if i < len(fr_sorted)]
-        w_vals = [float(wr_sorted[i]["Counter_Value"]) for i in order]
-        f_k, n_f = sum(f_vals) / len(f_vals), len(f_vals)
-        w_k, n_w = sum(w_vals) / len(w_vals), len(w_vals)
-        kc = int(round(wmax * 1024.0 / (V * 12 * CPLX_BYTES[W["inner"]])))
-        algo = V * (36 + 12 * BATCH_COL_SPINORS[cls] * kc) * CPLX_BYTES[W["inner"]]
+        def k_of(name):
+            a = _template_args(name, kernel)
+            if a is None and epi is not None:
+                a = _template_args(name, "k_bmarch")
+                if a is None or a[-1] != epi:
+                    return None
+            return int(a[1]) if a else None
+
+        cb = CPLX_BYTES[W["inner"]]
+        writes = 2 if cls == "bstab_xr" else 1  # spinors written per column
+        links = 36 if cls in BATCH_STENCILS else 0
+        fr, wr = rows_of(fetch_csv, "FETCH_SIZE"), rows_of(write_csv, "WRITE_SIZE")
+        per_k = {}
+        for kc in sorted({k_of(r["Kernel_Name"]) for r in wr} - {None}):
+            wk = sorted((r for r in wr if k_of(r["Kernel_Name"]) == kc), key=lambda r: int(r["Dispatch_Id"]))
+            fk = sorted((r for r in fr if k_of(r["Kernel_Name"]) == kc), key=lambda r: int(r["Dispatch_Id"]))
+            wmax = max(float(r["Counter_Value"]) for r in wk)
+            order = [i for i, r in enumerate(wk) if float(r["Counter_Value"]) >= 0.99 * wmax and i < len(fk)]
+            f_k = sum(float(fk[i]["Counter_Value"]) for i in order) / len(order)
+            w_k = sum(float(wk[i]["Counter_Value"]) for i in order) / len(order)
+            traffic = f_k * 1024.0 * fetch_scale + w_k * 1024.0 * write_scale
+            algo = V * (links + 12 * BATCH_COL_SPINORS[cls] * kc) * cb
+            per_k[str(kc)] = {"dispatches": len(order), "fetch_kib_per_dispatch": round(f_k, 1),
+                              "write_kib_per_dispatch": round(w_k, 1), "traffic_bytes_per_launch": round(traffic),
+                              "algorithmic_bytes_per_launch": algo,
+                              "traffic_over_algorithmic": round(traffic / algo, 3),
+                              "expected_write_kib": V * 12 * writes * kc * cb / 1024.0}
+        out["per_k"] = per_k
     else:
         # the general form's launches (the template's gamma5 instance is another kernel)
         is_kernel = lambda n: kernel + "(" in n or kernel + "<false>(" in n
-        f_k, n_f = per_dispatch(fetch_csv, "FETCH_SIZE", is_kernel)
-        w_k, n_w = per_dispatch(write_csv, "WRITE_SIZE", is_kernel)
+        fv = [float(r["Counter_Value"]) for r in rows_of(fetch_csv, "FETCH_SIZE") if is_kernel(r["Kernel_Name"])]
+        wv = [float(r["Counter_Value"]) for r in rows_of(write_csv, "WRITE_SIZE") if is_kernel(r["Kernel_Name"])]
+        f_k, w_k = sum(fv) / len(fv), sum(wv) / len(wv)
         algo = KERNEL_UNITS[cls] * UNIT_BYTES_FP64 * V
-    f_c = calibration(_find_csv(fetch_csv, "counter_collection.csv"), "FETCH_SIZE")
-    w_c = calibration(_find_csv(write_csv, "counter_collection.csv"), "WRITE_SIZE")
-    fetch_scale = COPY_BYTES / (f_c * 1024.0)
-    write_scale = COPY_BYTES / (w_c * 1024.0)
-    traffic = f_k * 1024.0 * fetch_scale + w_k * 1024.0 * write_scale
-    out = {
-        "kernel": kernel, "class": cls, "workload": workload, "source_hash": kernel_source_hash(cls),
-        "dispatches": {"fetch": n_f, "write": n_w},
-        "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
-        "copy_calibration": {"bytes_read_and_written": COPY_BYTES, "fetch_kib": round(f_c, 1),
-                             "write_kib": round(w_c, 1), "fetch_scale": round(fetch_scale, 4),
-                             "write_scale": round(write_scale, 4)},
-        "traffic_bytes_per_launch": round(traffic),
-        "algorithmic_bytes_per_launch": algo,
-        "traffic_over_algorithmic": round(traffic / algo, 3),
-        "commands": [
-            f"rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass "
-            f"--workload {workload}",
-            f"rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass "
-            f"--workload {workload}",
-            f"python3 bench.py --workload {workload} --summarize-pmc gpurun_out/pmc_fetch/run_counter_collection.csv "
-            "gpurun_out/pmc_write/run_counter_collection.csv",
-        ],
-    }
+        traffic = f_k * 1024.0 * fetch_scale + w_k * 1024.0 * write_scale
+        out.update({"dispatches": {"fetch": len(fv), "write": len(wv)},
+                    "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
+                    "traffic_bytes_per_launch": round(traffic), "algorithmic_bytes_per_launch": algo,
+                    "traffic_over_algorithmic": round(traffic / algo, 3)})
+    out["copy_calibration"] = {"bytes_read_and_written": COPY_BYTES, "fetch_kib": round(f_c, 1),
+                               "write_kib": round(w_c, 1), "fetch_scale": round(fetch_scale, 4),
+                               "write_scale": round(write_scale, 4)}
+    out["commands"] = [
+        f"rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- python3 bench.py --pmc-pass "
+        f"--workload {workload}",
+        f"rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- python3 bench.py --pmc-pass "
+        f"--workload {workload}",
+        f"python3 bench.py --workload {workload} --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write",
+    ]
     path = os.path.join(ROOT, "profiles", f"pmc_{cls}_{workload}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -589,6 +640,130 @@ def _find_csv(path, suffix):
     if not hits:
         raise FileNotFoundError(f"no *{suffix} under {path}")
     return hits[-1]
+
+
+def eigbicg_pass(eb, mode):
+    """The eigBiCG gap workload for a kernel trace: 16^3 x 32 (nev 10, m 40, tol
+    1e-10, FP64 window, host or device restart), one warm-up solve, three
+    marker launches (D on a 2^4 operator), two timed solves from an empty
+    space, three more markers.  Prints iterations, restarts and ms per iteration."""
+    import torch
+
+    import synth
+
+    W = WORKLOADS["inc16x32"]
+    dims, kappa = W["dims"], W["kappa"]
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
+    op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=40)
+    mdims = (2, 2, 2, 2)
+    mk = eb.op_create(synth.unit_links(mdims), 0.1, mdims)
+    mb = torch.ones(16, 4, 3, dtype=torch.complex128, device="cuda:0")
+    mo = torch.empty_like(mb)
+    B = [torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], i))).to("cuda:0") for i in range(3)]
+    kw = dict(nev=10, m=40, tol=1e-10, window="fp64", device_eig=(mode == "device"))
+    eb.eigbicg_solve(op, B[0], torch.zeros_like(B[0]), **kw)
+    eb.defl_reset(op)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        eb.op_apply(mk, mo, mb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = rst = 0
+    for i in (1, 2):
+        st, _ = eb.eigbicg_solve(op, B[i], torch.zeros_like(B[i]), **kw)
+        its += st["iters"]
+        rst += st["window_restarts"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for _ in range(3):
+        eb.op_apply(mk, mo, mb)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": mode, "iters": its, "restarts": rst, "ms_per_iter": round(1e3 * dt / its, 4)}),
+          flush=True)
+
+
+GAP_CLASSES = [  # (label, kernel-name prefixes)
+    ("BiCG step (matvec, r update, x/p update)", ("k_bicg_matvec", "k_bicg_update_r", "k_bicg_update_p")),
+    ("window restart rotations (V and W, with the arrow dots)", ("k_combine<HIP_vector_type<double, 2u>, "
+                                                                  "HIP_vector_type<double, 2u>, 20,",)),
+    ("window eigenproblems on the device", ("k_window_pair", "k_window_restart", "k_window_final")),
+    ("arrow vectors", ("k_arrow_vectors",)),
+    ("final extraction and absorb (Ritz vectors, D and D^+ on them, Gram blocks, "
+     "projections, residual)", ("k_combine", "k_gram", "k_dslash", "k_ts_", "k_residual", "k_to_soa",
+                                "k_from_soa")),
+    ("copies (scalar history to the host, coefficients to the device)", ("__amd_rocclr_copyBuffer",)),
+]
+
+
+def summarize_gap(trace_dirs, out_name, command):
+    """profiles/<out_name>.md: where an eigBiCG iteration's time goes, from
+    rocprofv3 kernel traces of `bench.py --eigbicg-pass MODE` (one directory per
+    mode): the window between the marker launches, the time some kernel runs
+    (union over streams), the idle rest, and the kernels by class."""
+    import csv
+
+    def kname(n):
+        return n.replace("(anonymous namespace)::", "").replace("void ", "").replace("ebicg::", "").split("(")[0]
+
+    out = ["# eigBiCG iteration time at 16^3 x 32, attributed from kernel traces", "",
+           "Command (repository root on the MI355X box, `export TMPDIR=/tmp` first), once per mode:", "",
+           "```", command, "```", "",
+           "Each run: one warm-up solve, then two eigBiCG solves (nev 10, m 40, tol 1e-10, FP64 window) "
+           "between marker launches.  Window = first to last kernel between the markers; busy = the "
+           "union of all kernels' intervals (the device restart runs on a side stream, overlapping the "
+           "iterations); idle = window - busy.", ""]
+    for mode, d in trace_dirs:
+        rows = list(csv.DictReader(open(_find_csv(d, "kernel_trace.csv"))))
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        mk = [i for i, r in enumerate(rows) if kname(r["Kernel_Name"]).startswith("k_dslash") and dur(r) < 20000]
+        groups = []
+        for i in mk:
+            if groups and i - groups[-1][-1] <= 3:
+                groups[-1].append(i)
+            else:
+                groups.append([i])
+        g = [x for x in groups if len(x) >= 3]
+        win = rows[g[-2][-1] + 1:g[-1][0]]
+        t0, t1 = int(win[0]["Start_Timestamp"]), int(win[-1]["End_Timestamp"])
+        iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in win)
+        busy, (cs, ce) = 0, iv[0]
+        for a, b in iv[1:]:
+            if a > ce:
+                busy += ce - cs
+                cs, ce = a, b
+            else:
+                ce = max(ce, b)
+        busy += ce - cs
+        iters = sum(1 for r in win if kname(r["Kernel_Name"]).startswith("k_bicg_update_p"))
+        cls = {lab: 0 for lab, _ in GAP_CLASSES}
+        other = 0
+        for r in win:
+            n = kname(r["Kernel_Name"])
+            for lab, pre in GAP_CLASSES:
+                if any(n.startswith(p.replace("ebicg::", "")) for p in pre):
+                    cls[lab] += dur(r)
+                    break
+            else:
+                other += dur(r)
+        us = lambda ns: ns / 1e3
+        out += [f"## {mode} restart", "",
+                f"Window {us(t1 - t0) / 1e3:.2f} ms for {iters} iterations: {us(t1 - t0) / iters:.1f} us per "
+                f"iteration; some kernel running {us(busy) / 1e3:.2f} ms ({100 * busy / (t1 - t0):.1f} %), "
+                f"idle {us(t1 - t0 - busy) / 1e3:.2f} ms ({us(t1 - t0 - busy) / iters:.1f} us per iteration).", "",
+                "| class | total (ms) | us per iteration | share of the window |", "|---|---:|---:|---:|"]
+        for lab, _ in GAP_CLASSES:
+            if cls[lab]:
+                out.append(f"| {lab} | {us(cls[lab]) / 1e3:.2f} | {us(cls[lab]) / iters:.1f} | "
+                           f"{100 * cls[lab] / (t1 - t0):.1f} % |")
+        if other:
+            out.append(f"| other | {us(other) / 1e3:.2f} | {us(other) / iters:.1f} | {100 * other / (t1 - t0):.1f} % |")
+        out.append("")
+    path = os.path.join(ROOT, "profiles", out_name + ".md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("wrote", path)
 
 
 def summarize_trace(prof_dir, bench_json, workload, out_name, command, top=20):
@@ -641,9 +816,10 @@ def summarize_trace(prof_dir, bench_json, workload, out_name, command, top=20):
     print(path)
 
 
-def measured_traffic(workload, cls):
+def measured_traffic(workload, cls, k=None):
     """Traffic per launch from the committed counter summary, if the kernel sources
-    are unchanged since it was taken; else None."""
+    are unchanged since it was taken (and, for a batched pass, it was taken at the
+    same k); else None."""
     path = os.path.join(ROOT, "profiles", f"pmc_{cls}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -651,6 +827,9 @@ def measured_traffic(workload, cls):
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash(cls):
         return None
+    if "per_k" in rec:
+        r = rec["per_k"].get(str(k))
+        return r["traffic_bytes_per_launch"] if r else None
     return rec["traffic_bytes_per_launch"]
 
 
@@ -658,6 +837,36 @@ def measured_traffic(workload, cls):
 # The 16^3 x 32 incremental step (a side record: its fields sit in the 256 MB
 # Infinity Cache, so its stencil rates are effective, not HBM, rates)
 # ---------------------------------------------------------------------------
+def eigbicg_modes(eb, op, B, W, n, modes=(("fp64", False), ("fp64", True), ("fp32", True))):
+    """eigBiCG on the first n sources in each (window storage, device restart) mode,
+    from an empty space each time, after one untimed solve of the mode:
+    milliseconds per iteration, iterations, restarts."""
+    import torch
+
+    out = {}
+    for window, dev in modes:
+        # one untimed solve first: the mode's window buffers are allocated there
+        eb.defl_reset(op)
+        eb.eigbicg_solve(op, B[0], torch.zeros_like(B[0]), nev=W["nev"], m=W["m"], tol=W["tol"], maxiter=20000,
+                         window=window, device_eig=dev)
+        eb.defl_reset(op)
+        its = rst = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            x = torch.zeros_like(B[i])
+            st, _ = eb.eigbicg_solve(op, B[i], x, nev=W["nev"], m=W["m"], tol=W["tol"], maxiter=20000,
+                                     window=window, device_eig=dev)
+            assert st["true_rel_resid"] <= W["tol"], st
+            its += st["iters"]
+            rst += st["window_restarts"]
+        dt = time.perf_counter() - t0
+        out[f"{window}_window_{'device' if dev else 'host'}_restart"] = {
+            "ms_per_iter": round(1e3 * dt / its, 4), "iters": its, "restarts": rst, "solves": n}
+    eb.defl_reset(op)
+    return out
+
+
 def incremental_side(eb, W, steps, warmup, timing=True, full=True):
     """Solves/s of the FP64 incremental step (n1 eigBiCG + deflated BiCGStab),
     its dominant kernel's effective GB/s, the mixed-precision and batched
@@ -753,6 +962,8 @@ def incremental_side(eb, W, steps, warmup, timing=True, full=True):
         dts = [run_mixed_step(eb, op, B, X, W, inner, itol) for _ in range(max(1, min(steps, 2)))]
         res["mixed_step"][name] = {"solves_per_s": round(W["nrhs"] * len(dts) / sum(dts), 3),
                                    "ms_per_step": round(1e3 * sum(dts) / len(dts), 3)}
+    res["eigbicg_modes"] = eigbicg_modes(eb, op, B, W, W["n1"])
+    log(f"[bench] eigBiCG modes 16^3x32: {res['eigbicg_modes']}")
     if full:
         res["multi_rhs_stencil"] = multi_rhs_stencil(eb, op, V)
         lat5, its5 = [], []
@@ -961,7 +1172,7 @@ def headline_batch(eb, W, U, args):
         rk = kern[dom]
         roof = {"kernel": dom, "bound": "hbm", "achieved": rk["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(rk["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                "traffic": measured_traffic("batch32x64", dom),
+                "traffic": measured_traffic("batch32x64", dom, k),
                 "bytes_per_launch": rk["bytes_per_launch"], "avg_launch_us": rk["avg_launch_us"],
                 "launches": rk["launches"], "working_launches": rk["working_launches"],
                 "share_of_kernel_time": round(rk["total_ms"] / total_ms, 4) if total_ms else None}
@@ -992,7 +1203,17 @@ def headline_batch(eb, W, U, args):
 
     run("mixed_bf16_batched_deflated", op, nrhs, inner="bf16", inner_tol=1e-2, batch=0)
     run("fp64_bicgstab_deflated", op, nc, batch=1)
+    eb.op_trim(op)  # the batch buffers (reallocated on use): room for an FP64 window at this size
     op2 = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=0)  # no deflation space
+    # eigBiCG at this size with the FP64 window and host restarts against the device
+    # restart and the FP32 window (no space to absorb into: the solves alone)
+    head["eigbicg_modes"] = None
+    if not args.no_side:  # (a profiled run of the headline leaves them out)
+        gsrc = [torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], 100))).to(dev)]
+        head["eigbicg_modes"] = eigbicg_modes(eb, op2, gsrc, W, 1)
+        log(f"[bench] eigBiCG modes {dims}: {head['eigbicg_modes']}")
+        eb.op_trim(op2)
+        del gsrc
     run("fp64_bicg_plain", op2, nc, method=1)
     run("fp64_bicgstab_plain", op2, nc, batch=1)
     run("mixed_fp32_batched_plain", op2, nrhs, inner=W["inner"], inner_tol=W["inner_tol"], batch=0)
@@ -1027,6 +1248,10 @@ def main():
                     help="one pass of the workload's roofline kernel and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
+    ap.add_argument("--eigbicg-pass", choices=("host", "device"),
+                    help="two eigBiCG solves at 16^3 x 32 between marker launches, for rocprofv3 --kernel-trace")
+    ap.add_argument("--summarize-gap", nargs=4, metavar=("HOST_TRACE_DIR", "DEVICE_TRACE_DIR", "NAME", "COMMAND"),
+                    help="write profiles/NAME.md from the kernel traces of --eigbicg-pass host / device")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("PROF_DIR", "BENCH_JSON", "NAME", "COMMAND"),
                     help="write profiles/NAME.md from a rocprofv3 --kernel-trace --stats run of bench.py")
     args = ap.parse_args()
@@ -1035,14 +1260,23 @@ def main():
         summarize_trace(d, bj, args.workload, name, cmd)
         return
     if args.summarize_pmc:
-        if args.workload == "batch32x64":
-            summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, kernel="k_bstab_v",
-                          cls="bstab_v")
+        if args.workload == "batch32x64":  # the two passes that take the most time
+            for kern, cls in (("k_bstab_v", "bstab_v"), ("k_bstab_xr", "bstab_xr")):
+                summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, kernel=kern, cls=cls)
         else:
             summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
         return
+    if args.summarize_gap:
+        h, d, name, cmd = args.summarize_gap
+        summarize_gap([("host", h), ("device", d)], name, cmd)
+        return
     if args.pmc_pass:
         pmc_pass(args.workload)
+        return
+    if args.eigbicg_pass:
+        from paper_0911_2285_amd import ebicg as eb
+
+        eigbicg_pass(eb, args.eigbicg_pass)
         return
     if args.stencil_pass:
         stencil_pass(form=args.stencil_form)
@@ -1152,6 +1386,7 @@ def main():
         "kernels": head["kernels"],
         "setup": head["setup"],
         "multi_rhs_stencil": head["multi_rhs_stencil"],
+        "eigbicg_modes": head["eigbicg_modes"],
         **extra,
     }
     print(json.dumps(out), flush=True)
