@@ -576,6 +576,8 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
 
         def k_of(name):
             a = _template_args(name, kernel)
+            if a is None:  # the variant that sums its producer's records itself (small grids)
+                a = _template_args(name, kernel + "_f")
             if a is None and epi is not None:
                 a = _template_args(name, "k_bmarch")
                 if a is None or a[-1] != epi:
