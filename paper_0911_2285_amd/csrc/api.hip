@@ -2030,45 +2030,58 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
                          ? 1
                          : (P->batch ? P->batch : choose_batch(op, P->inner, s));
     const size_t Ncan = size_t(op->g.V) * 12;  // canonical spinor length
+    // Columns go in groups of up to kMaxBatch: a group is loaded and deflated
+    // at once (one pass over U_l and U_r for all its columns), then solved in
+    // batches of the chosen k (the largest power of two that fits; a single
+    // leftover column runs the one-at-a-time solver, already deflated).
+    const int gmax = kmax > 1 ? kMaxBatch : 1;
     int c0 = 0;
     while (c0 < P->nrhs) {
-      int kc = 1;
-      while (kc * 2 <= kmax && c0 + kc * 2 <= P->nrhs) kc *= 2;
+      const int gsz = std::min(gmax, P->nrhs - c0);
       const double2 *bc = static_cast<const double2 *>(b_can) + size_t(c0) * Ncan;
       double2 *xc = static_cast<double2 *>(x_can) + size_t(c0) * Ncan;
-      double2 *b = op->vec("solve_b", kc), *x = op->vec("solve_x", kc);
-      double2 *bo = op->eo ? op->vec("eo_bo", kc) : nullptr;
+      double2 *b = op->vec("solve_b", gsz), *x = op->vec("solve_x", gsz);
+      double2 *bo = op->eo ? op->vec("eo_bo", gsz) : nullptr;
       // per column: the tolerance on the solvers' system (even-odd: scaled by ||b|| / ||b_hat||)
       double scale[kMaxBatch], tolc[kMaxBatch];
-      for (int c = 0; c < kc; ++c) {
+      for (int c = 0; c < gsz; ++c) {
         scale[c] = load_system(op, bc + c * Ncan, xc + c * Ncan, b + c * op->N, x + c * op->N,
                                bo ? bo + c * op->N : nullptr, s);
         tolc[c] = P->tol * scale[c];
       }
       eb_stats sc = zero_stats();
       auto store = [&]() {
-        for (int c = 0; c < kc; ++c)
+        for (int c = 0; c < gsz; ++c)
           store_solution(op, x + c * op->N, bo ? bo + c * op->N : nullptr, xc + c * Ncan, s);
       };
       try {
-        if (kc == 1) {
+        if (gsz == 1) {
           if (op->K > 0) deflate_guess(op, b, x, s);
-          if (P->method == 1)
-            deflated_bicg_f64(op, b, x, tolc[0], P->maxiter, sc, s);
-          else if (P->inner == EB_FP64)
-            deflated_stab_f64(op, b, x, tolc[0], P->deftol, P->maxiter, sc, s);
-          else if (P->inner == EB_FP32)
-            mixed_stab<float2>(op, b, x, tolc[0], inner_tol, P->maxiter, sc, s);
-          else
-            mixed_stab<bf16c>(op, b, x, tolc[0], inner_tol, P->maxiter, sc, s);
         } else {
-          deflate_block(op, b, x, kc, s);
-          if (P->inner == EB_FP64)
-            mixed_stab_batch<double2>(op, b, x, kc, tolc, 0.5 * P->tol, P->maxiter, sc, s);
-          else if (P->inner == EB_FP32)
-            mixed_stab_batch<float2>(op, b, x, kc, tolc, inner_tol, P->maxiter, sc, s);
-          else
-            mixed_stab_batch<bf16c>(op, b, x, kc, tolc, inner_tol, P->maxiter, sc, s);
+          deflate_block(op, b, x, gsz, s);
+        }
+        int off = 0;
+        while (off < gsz) {
+          int kc = 1;
+          while (kc * 2 <= kmax && off + kc * 2 <= gsz) kc *= 2;
+          double2 *bb = b + size_t(off) * op->N, *xx = x + size_t(off) * op->N;
+          if (kc == 1) {
+            if (P->method == 1)
+              deflated_bicg_f64(op, bb, xx, tolc[off], P->maxiter, sc, s);
+            else if (P->inner == EB_FP64)
+              deflated_stab_f64(op, bb, xx, tolc[off], P->deftol, P->maxiter, sc, s);
+            else if (P->inner == EB_FP32)
+              mixed_stab<float2>(op, bb, xx, tolc[off], inner_tol, P->maxiter, sc, s);
+            else
+              mixed_stab<bf16c>(op, bb, xx, tolc[off], inner_tol, P->maxiter, sc, s);
+          } else if (P->inner == EB_FP64) {
+            mixed_stab_batch<double2>(op, bb, xx, kc, tolc + off, 0.5 * P->tol, P->maxiter, sc, s);
+          } else if (P->inner == EB_FP32) {
+            mixed_stab_batch<float2>(op, bb, xx, kc, tolc + off, inner_tol, P->maxiter, sc, s);
+          } else {
+            mixed_stab_batch<bf16c>(op, bb, xx, kc, tolc + off, inner_tol, P->maxiter, sc, s);
+          }
+          off += kc;
         }
       } catch (...) {
         // x holds the last iterate and the stats are filled
@@ -2080,13 +2093,13 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
       store();
       if (op->eo) {  // the full system's residuals; the recursive one relative to ||b||
         double worst_full = 0;
-        for (int c = 0; c < kc; ++c)
+        for (int c = 0; c < gsz; ++c)
           worst_full = std::max(worst_full, full_rel_residual(op, bc + c * Ncan, xc + c * Ncan, s));
         sc.true_rel_resid = worst_full;
-        if (kc == 1) sc.rec_rel_resid /= scale[0];
+        if (gsz == 1) sc.rec_rel_resid /= scale[0];
       }
       merge(sc);
-      c0 += kc;
+      c0 += gsz;
     }
     st.true_rel_resid = worst;
     HIPCHK(hipGetLastError());

@@ -261,6 +261,133 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// ---------------------------------------------------------------------------
+// rotate on the matrix cores: out_k = sgn sum_c in_c C[c + k nin] for all
+// nout <= 16 OT output columns in one pass over the inputs (the window
+// rotation of Alg. BiCG-eigen at large windows, e.g. 60 columns into 50).
+// The transposed product out^T = C^T in^T is tiled: a wave takes 16 entries
+// i and 16 outputs k per tile, K over the input columns in steps of 4, so that
+// lane (r = l % 16, q = l / 16) loads entry i0 + r of input column c0 + q
+// (16 consecutive entries per column: one 256-byte read) and holds the
+// results for entry i0 + r of outputs q + 4 v (16 consecutive entries per
+// output column in one store).  C^T sits in LDS ([c][k], k fastest), the
+// slot lists too.  A complex product is four real MFMAs into a real and an
+// imaginary tile.  DOTS: the block's partial dots of g with the outputs
+// (g^+ out_k, or out_k^+ g with conj_out), element-major records
+// part[(2 k + {re, im}) gridDim.x + blockIdx.x] for k < 16 OT.
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO, int OT, bool DOTS, bool G5IN>
+__global__ void __launch_bounds__(kBlock)
+    k_rotate_mfma(TO *out_base, SlotList out_slots, size_t ldo, const TI *in_base, SlotList in_slots, size_t ldi,
+                  const double2 *__restrict__ C, double sgn, size_t N, const double2 *__restrict__ g, int conj_out,
+                  double *__restrict__ part, int jtag, const KrylovState *S) {
+  if (S && S->stopped && jtag > S->stop_at) return;
+  constexpr int KP = kTile * OT;
+  extern __shared__ double2 cs[];  // C^T: cs[c KP + k]
+  __shared__ int islot[kMaxCols], oslot[KP];
+  __shared__ double sd[DOTS ? kBlock / kWave : 1][DOTS ? 2 * KP : 1];
+  const int nin = in_slots.n, nout = out_slots.n, nin4 = (nin + 3) & ~3;
+  for (int e = threadIdx.x; e < nin4 * KP; e += kBlock) {
+    const int c = e / KP, k = e % KP;
+    cs[e] = (c < nin && k < nout) ? C[c + size_t(k) * nin] : make_double2(0.0, 0.0);
+  }
+  for (int c = threadIdx.x; c < kMaxCols; c += kBlock) islot[c] = c < nin ? in_slots.idx[c] : 0;
+  for (int k = threadIdx.x; k < KP; k += kBlock) oslot[k] = k < nout ? out_slots.idx[k] : 0;
+  __syncthreads();
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int r = lane % kTile, q = lane / kTile;
+  const size_t half = N / 2, nch = (N + kTile - 1) / kTile;
+  double dre[OT][4], dim[OT][4];
+#pragma unroll
+  for (int t = 0; t < OT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dre[t][v] = dim[t][v] = 0.0;
+  for (size_t ch = size_t(blockIdx.x) * (kBlock / kWave) + w; ch < nch; ch += size_t(gridDim.x) * (kBlock / kWave)) {
+    const size_t i = ch * kTile + r;
+    const bool in = i < N;
+    dx4 re[OT], im[OT];
+#pragma unroll
+    for (int t = 0; t < OT; ++t) re[t] = im[t] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < nin4; c0 += 4) {
+      const int c = c0 + q;
+      double br = 0.0, bi = 0.0;
+      if (c < nin && in) {
+        int sc = islot[c];
+        bool flip = false;
+        if constexpr (G5IN) {
+          flip = sc < 0;
+          if (flip) sc = -sc - 1;
+        }
+        const TI x = in_base[size_t(sc) * ldi + i];
+        br = double(x.x);
+        bi = double(x.y);
+        if (flip && i >= half) {
+          br = -br;
+          bi = -bi;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < OT; ++t) {
+        const double2 a = cs[c * KP + kTile * t + r];
+        re[t] = mfma16(a.x, br, re[t]);
+        re[t] = mfma16(-a.y, bi, re[t]);
+        im[t] = mfma16(a.x, bi, im[t]);
+        im[t] = mfma16(a.y, br, im[t]);
+      }
+    }
+    double2 gv = make_double2(0.0, 0.0);
+    if (DOTS && in) gv = g[i];
+#pragma unroll
+    for (int t = 0; t < OT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kTile * t + q + 4 * v;
+        const double ox = sgn * re[t][v], oy = sgn * im[t][v];
+        if (in && k < nout) {
+          TO *oc = out_base + size_t(oslot[k]) * ldo;
+          if constexpr (std::is_same<TO, double2>::value)
+            oc[i] = make_double2(ox, oy);
+          else
+            oc[i] = make_float2(float(ox), float(oy));
+        }
+        if constexpr (DOTS) {
+          if (conj_out) {  // conj(o) g
+            dre[t][v] += ox * gv.x + oy * gv.y;
+            dim[t][v] += ox * gv.y - oy * gv.x;
+          } else {  // conj(g) o
+            dre[t][v] += gv.x * ox + gv.y * oy;
+            dim[t][v] += gv.x * oy - gv.y * ox;
+          }
+        }
+      }
+  }
+  if constexpr (DOTS) {
+    // sum over the 16 lanes of each q (the entries), then over the waves
+#pragma unroll
+    for (int t = 0; t < OT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int off = kTile / 2; off > 0; off >>= 1) {
+          dre[t][v] += __shfl_xor(dre[t][v], off, kWave);
+          dim[t][v] += __shfl_xor(dim[t][v], off, kWave);
+        }
+        if (r == 0) {
+          const int k = kTile * t + q + 4 * v;
+          sd[w][2 * k] = dre[t][v];
+          sd[w][2 * k + 1] = dim[t][v];
+        }
+      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * KP; e += kBlock) {
+      double s = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < kBlock / kWave; ++ww) s += sd[ww][e];
+      part[size_t(e) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
 // Partial dots of g with NT output columns of a rotation (column group
 // blockIdx.y): g^+ out_k (conj_out = 0) or out_k^+ g (conj_out = 1); records
 // element-major, part[(blockIdx.y 2NT + e) gridDim.x + blockIdx.x].
@@ -350,6 +477,53 @@ void launch_combine_t(TO *out_base, const SlotList &out_slots, size_t ldo, const
                       size_t part_cap, hipStream_t st) {
   const int nin = in_slots.n, nout = out_slots.n;
   if (nin < 1 || nout < 1 || N == 0) return;
+  if (!add && nout > 24 && nout <= 4 * kTile && sgn == 1.0) {
+    // a rotation into more than 24 columns: the matrix cores, the inputs read once
+    bool g5in = false;
+    for (int c = 0; c < nin; ++c) g5in = g5in || in_slots.idx[c] < 0;
+    const int OT = (nout + kTile - 1) / kTile;
+    const size_t nch = (N + kTile - 1) / kTile;
+    size_t nb = (nch + 3) / 4;
+    nb = nb < 2048 ? nb : 2048;
+    if (g) {  // the dot records of 2 KW rows, KW = 16 OT
+      const size_t rcap = part_cap / (2 * size_t(kTile) * OT);
+      nb = nb < rcap ? nb : rcap;
+    }
+    if (nb < 1) nb = 1;
+    auto go = [&](auto ot_tag, auto dots_tag, auto g5_tag) {
+      constexpr int T = decltype(ot_tag)::value;
+      constexpr bool D = decltype(dots_tag)::value, G = decltype(g5_tag)::value;
+      const size_t lds = size_t((nin + 3) & ~3) * kTile * T * sizeof(double2);
+      // the kernel's static LDS (slot lists, dot sums) comes on top of this; past 64 KB in
+      // all a workgroup needs the larger limit set (gfx950 holds 160 KB per workgroup)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rotate_mfma<TI, TO, T, D, G>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));  // a failure shows at launch
+      EB_LAUNCH((k_rotate_mfma<TI, TO, T, D, G>), dim3(unsigned(nb)), dim3(kBlock), lds, st, out_base, out_slots, ldo,
+                in_base, in_slots, ldi, C, sgn, N, g, conj_out, part, jtag, S);
+      if constexpr (D)
+        EB_LAUNCH(k_combine_dots<kTile * T>, dim3(2 * kTile * T), dim3(kBlock), 0, st, part, int(nb), nout, dots,
+                  jtag, S);
+    };
+    using Tt = std::true_type;
+    using Ff = std::false_type;
+    auto by_flags = [&](auto ot_tag) {
+      if (g && g5in)
+        go(ot_tag, Tt{}, Tt{});
+      else if (g)
+        go(ot_tag, Tt{}, Ff{});
+      else if (g5in)
+        go(ot_tag, Ff{}, Tt{});
+      else
+        go(ot_tag, Ff{}, Ff{});
+    };
+    if (OT == 2)
+      by_flags(std::integral_constant<int, 2>{});
+    else if (OT == 3)
+      by_flags(std::integral_constant<int, 3>{});
+    else
+      by_flags(std::integral_constant<int, 4>{});
+    return;
+  }
   auto go = [&](auto nt_tag) {
     constexpr int NT = decltype(nt_tag)::value;
     const int groups = (nout + NT - 1) / NT;
