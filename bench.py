@@ -644,26 +644,28 @@ def _find_csv(path, suffix):
     return hits[-1]
 
 
-def eigbicg_pass(eb, mode):
-    """The eigBiCG gap workload for a kernel trace: 16^3 x 32 (nev 10, m 40, tol
-    1e-10, FP64 window, host or device restart), one warm-up solve, three
-    marker launches (D on a 2^4 operator), two timed solves from an empty
-    space, three more markers.  Prints iterations, restarts and ms per iteration."""
+def eigbicg_pass(eb, mode, workload="inc16x32"):
+    """The eigBiCG gap workload for a kernel trace: the workload's lattice, nev and
+    m (16^3 x 32: nev 10, m 40; 32^3 x 64: nev 25, m 60), tol 1e-10, FP64 window,
+    host or device restart; one warm-up solve, three marker launches (D on a 2^4
+    operator), two timed solves from an empty space, three more markers.  Prints
+    iterations, restarts and ms per iteration."""
     import torch
 
     import synth
 
-    W = WORKLOADS["inc16x32"]
+    W = WORKLOADS[workload]
     dims, kappa = W["dims"], W["kappa"]
     V = synth.volume(dims)
     U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
-    op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=40)
+    op = eb.op_create(U, kappa, dims, bc_t=-1, defl_capacity=2 * W["nev"])
+    del U
     mdims = (2, 2, 2, 2)
     mk = eb.op_create(synth.unit_links(mdims), 0.1, mdims)
     mb = torch.ones(16, 4, 3, dtype=torch.complex128, device="cuda:0")
     mo = torch.empty_like(mb)
     B = [torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], i))).to("cuda:0") for i in range(3)]
-    kw = dict(nev=10, m=40, tol=1e-10, window="fp64", device_eig=(mode == "device"))
+    kw = dict(nev=W["nev"], m=W["m"], tol=1e-10, window="fp64", device_eig=(mode == "device"))
     eb.eigbicg_solve(op, B[0], torch.zeros_like(B[0]), **kw)
     eb.defl_reset(op)
     torch.cuda.synchronize()
@@ -681,14 +683,15 @@ def eigbicg_pass(eb, mode):
     for _ in range(3):
         eb.op_apply(mk, mo, mb)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": mode, "iters": its, "restarts": rst, "ms_per_iter": round(1e3 * dt / its, 4)}),
-          flush=True)
+    print(json.dumps({"workload": workload, "mode": mode, "iters": its, "restarts": rst,
+                      "ms_per_iter": round(1e3 * dt / its, 4)}), flush=True)
 
 
 GAP_CLASSES = [  # (label, kernel-name prefixes)
     ("BiCG step (matvec, r update, x/p update)", ("k_bicg_matvec", "k_bicg_update_r", "k_bicg_update_p")),
     ("window restart rotations (V and W, with the arrow dots)", ("k_combine<HIP_vector_type<double, 2u>, "
-                                                                  "HIP_vector_type<double, 2u>, 20,",)),
+                                                                  "HIP_vector_type<double, 2u>, 20,",
+                                                                  "k_rotate_mfma")),
     ("window eigenproblems on the device", ("k_window_pair", "k_window_restart", "k_window_final")),
     ("arrow vectors", ("k_arrow_vectors",)),
     ("final extraction and absorb (Ritz vectors, D and D^+ on them, Gram blocks, "
@@ -698,7 +701,7 @@ GAP_CLASSES = [  # (label, kernel-name prefixes)
 ]
 
 
-def summarize_gap(trace_dirs, out_name, command):
+def summarize_gap(trace_dirs, out_name, command, workload="inc16x32"):
     """profiles/<out_name>.md: where an eigBiCG iteration's time goes, from
     rocprofv3 kernel traces of `bench.py --eigbicg-pass MODE` (one directory per
     mode): the window between the marker launches, the time some kernel runs
@@ -708,10 +711,13 @@ def summarize_gap(trace_dirs, out_name, command):
     def kname(n):
         return n.replace("(anonymous namespace)::", "").replace("void ", "").replace("ebicg::", "").split("(")[0]
 
-    out = ["# eigBiCG iteration time at 16^3 x 32, attributed from kernel traces", "",
+    W = WORKLOADS[workload]
+    lat = "x".join(map(str, W["dims"][:3])) + " x " + str(W["dims"][3])
+    out = [f"# eigBiCG iteration time at {lat}, attributed from kernel traces", "",
            "Command (repository root on the MI355X box, `export TMPDIR=/tmp` first), once per mode:", "",
            "```", command, "```", "",
-           "Each run: one warm-up solve, then two eigBiCG solves (nev 10, m 40, tol 1e-10, FP64 window) "
+           f"Each run: one warm-up solve, then two eigBiCG solves (nev {W['nev']}, m {W['m']}, tol 1e-10, "
+           "FP64 window) "
            "between marker launches.  Window = first to last kernel between the markers; busy = the "
            "union of all kernels' intervals (the device restart runs on a side stream, overlapping the "
            "iterations); idle = window - busy.", ""]
@@ -1251,7 +1257,9 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
     ap.add_argument("--eigbicg-pass", choices=("host", "device"),
-                    help="two eigBiCG solves at 16^3 x 32 between marker launches, for rocprofv3 --kernel-trace")
+                    help="two eigBiCG solves between marker launches, for rocprofv3 --kernel-trace")
+    ap.add_argument("--eigbicg-workload", default="inc16x32", choices=sorted(WORKLOADS),
+                    help="lattice, nev and m of --eigbicg-pass and --summarize-gap")
     ap.add_argument("--summarize-gap", nargs=4, metavar=("HOST_TRACE_DIR", "DEVICE_TRACE_DIR", "NAME", "COMMAND"),
                     help="write profiles/NAME.md from the kernel traces of --eigbicg-pass host / device")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("PROF_DIR", "BENCH_JSON", "NAME", "COMMAND"),
@@ -1270,7 +1278,7 @@ def main():
         return
     if args.summarize_gap:
         h, d, name, cmd = args.summarize_gap
-        summarize_gap([("host", h), ("device", d)], name, cmd)
+        summarize_gap([("host", h), ("device", d)], name, cmd, args.eigbicg_workload)
         return
     if args.pmc_pass:
         pmc_pass(args.workload)
@@ -1278,7 +1286,7 @@ def main():
     if args.eigbicg_pass:
         from paper_0911_2285_amd import ebicg as eb
 
-        eigbicg_pass(eb, args.eigbicg_pass)
+        eigbicg_pass(eb, args.eigbicg_pass, args.eigbicg_workload)
         return
     if args.stencil_pass:
         stencil_pass(form=args.stencil_form)
