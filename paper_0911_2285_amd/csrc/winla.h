@@ -182,6 +182,147 @@ __device__ __forceinline__ void win_givens(wcx x, wcx y, double &c, wcx &s) {
   s = inv * (x * cconj(y));
 }
 
+// Lane l's value of v (l uniform across the wave).
+__device__ __forceinline__ double win_readlane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b), lane), hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ wcx win_readlane(wcx v, int lane) { return {win_readlane(v.x, lane), win_readlane(v.y, lane)}; }
+
+// 1 / sqrt(v) for v in [1e-280, 1e280]: the hardware estimate and two Newton
+// steps r <- r (3/2 - v r^2 / 2).
+__device__ __forceinline__ double win_rsq(double v) {
+  double r = __builtin_amdgcn_rsq(v);
+  const double h = 0.5 * v;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
+// The rotation of win_givens on the serial path of the QR chase: where |x|^2
+// and r^2 lie in [1e-150, 1e150] (every step but the rarest), c = |x|^2 q and
+// s = x conj(y) q with q = 1 / (|x| r) from one reciprocal square root of
+// |x|^2 r^2 (y = 0 gives c = 1, s = 0); elsewhere win_givens itself.
+__device__ __forceinline__ void win_givens_fast(wcx x, wcx y, double &c, wcx &s) {
+  const double ax2 = x.x * x.x + x.y * x.y, ay2 = y.x * y.x + y.y * y.y;
+  const double r2 = ax2 + ay2;
+  if (ax2 > 1e-150 && r2 < 1e150) {
+    const double q = win_rsq(ax2 * r2);
+    c = ax2 * q;
+    s = q * (x * cconj(y));
+    return;
+  }
+  win_givens(x, y, c, s);
+}
+
+// One implicit single-shift QR sweep over the active block l..ihi of the
+// Hessenberg T (n <= kWinThreads), with the same rotations applied to the
+// same entries in the same order as the entry-by-entry chase, but with the
+// serial path cut to the rotation and a few products.  The 2 x 2 block of
+// rows and columns k, k+1 at step k is held by every lane (uniform values),
+// so the next rotation follows from it without a round trip through LDS or
+// across lanes.  Lane j > k+1 owns column j and carries in a register the
+// entry of its column in the row that the next row rotation mixes; the row
+// below is original (untouched by earlier steps) and read one step ahead.
+// The column rotations of the entries above the block (rows < k) and of Z
+// commute with the rest of the chase and are applied after it, one row per
+// lane, from the rotations kept in LDS.
+__device__ __forceinline__ void win_sweep_lanes(double2 *T, double2 *Z, int n, int ld, int l, int ihi, wcx mu) {
+  const int j = threadIdx.x;
+  const bool own = j < n;
+  double *cs_c = &win_lds.lm[0].x;  // free during the Schur iteration: c_k at stride 2
+  double2 *cs_s = win_lds.vec;      // s_k
+  // uniform: ua0 = T(k,k), ua1 = T(k,k+1), ub0 = T(k+1,k), ub1 = T(k+1,k+1), current
+  wcx ua0 = ld2(T + l + l * ld), ua1 = ld2(T + l + (l + 1) * ld);
+  wcx ub0 = ld2(T + (l + 1) + l * ld), ub1 = ld2(T + (l + 1) + (l + 1) * ld);
+  wcx cur = {0.0, 0.0}, bnx = {0.0, 0.0};  // lane j > k+1: T(k, j) current, T(k+1, j) original
+  if (own && j >= l + 2) {
+    cur = ld2(T + l + j * ld);
+    bnx = ld2(T + (l + 1) + j * ld);
+  }
+  wcx x = ua0 - mu, y = ub0;
+  for (int k = l; k < ihi; ++k) {
+    const bool more = k + 2 <= ihi;
+    // original entries of row k+2 (F = T(k+2,k+1), G = T(k+2,k+2), lanes: T(k+2, j))
+    wcx F = {0.0, 0.0}, G = {0.0, 0.0}, bn2 = {0.0, 0.0};
+    if (more) {
+      F = ld2(T + (k + 2) + (k + 1) * ld);
+      G = ld2(T + (k + 2) + (k + 2) * ld);
+    }
+    if (own && k + 2 < n) bn2 = ld2(T + (k + 2) + j * ld);
+    double c;
+    wcx s;
+    win_givens_fast(x, y, c, s);
+    const wcx sc = cconj(s);
+    // row rotation k: the 2 x 2 block (every lane) and the far columns (own lane)
+    const wcx A = c * ua0 + s * ub0, C = c * ub0 - sc * ua0;
+    const wcx B = c * ua1 + s * ub1, D = c * ub1 - sc * ua1;
+    if (own && j >= k + 2) {
+      const wcx top = c * cur + s * bnx;
+      cur = c * bnx - sc * cur;
+      st2(T + k + j * ld, top);
+    }
+    // column rotation k on rows k, k+1 and k+2 of columns k, k+1
+    const wcx xn = c * C + D * sc, dn = c * D - C * s;
+    if (j == 0) {
+      cs_c[2 * (k - l)] = c;
+      st2(cs_s + (k - l), s);
+      if (k > l) {  // the bulge column k-1: T(k,k-1) final, T(k+1,k-1) = 0
+        st2(T + k + (k - 1) * ld, c * x + s * y);
+        st2(T + (k + 1) + (k - 1) * ld, wcx{0.0, 0.0});
+      }
+      st2(T + k + k * ld, c * A + B * sc);
+      st2(T + k + (k + 1) * ld, c * B - A * s);
+    }
+    x = xn;
+    ua0 = dn;
+    if (more) {
+      y = F * sc;
+      ub0 = c * F;
+      ub1 = G;
+      ua1 = win_readlane(cur, k + 2);  // T(k+1, k+2) after this row rotation
+    }
+    bnx = bn2;
+  }
+  if (j == 0) {
+    st2(T + ihi + (ihi - 1) * ld, x);
+    st2(T + ihi + ihi * ld, ua0);
+  }
+  if (own && j > ihi) st2(T + ihi + j * ld, cur);
+  __syncthreads();
+  // deferred column rotations: rows i < k of columns k, k+1 for every k (T),
+  // and every row of Z; each step's operands are read one step ahead
+  const int k0 = l > j + 1 ? l : j + 1;
+  const bool tdo = j <= ihi && k0 < ihi;
+  if (own) {
+    wcx tc = tdo ? ld2(T + j + k0 * ld) : wcx{0.0, 0.0};
+    wcx zc = ld2(Z + j + l * ld);
+    double cn = cs_c[0];
+    wcx sn = ld2(cs_s), zbn = ld2(Z + j + (l + 1) * ld);
+    wcx tbn = tdo && l >= k0 ? ld2(T + j + (l + 1) * ld) : wcx{0.0, 0.0};
+    for (int k = l; k < ihi; ++k) {
+      const double c = cn;
+      const wcx s = sn, sc = cconj(s), zb = zbn, tb = tbn;
+      if (k + 1 < ihi) {
+        cn = cs_c[2 * (k + 1 - l)];
+        sn = ld2(cs_s + (k + 1 - l));
+        zbn = ld2(Z + j + (k + 2) * ld);
+        if (tdo && k + 1 >= k0) tbn = ld2(T + j + (k + 2) * ld);
+      }
+      st2(Z + j + k * ld, c * zc + zb * sc);
+      zc = c * zb - zc * s;
+      if (tdo && k >= k0) {
+        st2(T + j + k * ld, c * tc + tb * sc);
+        tc = c * tb - tc * s;
+      }
+    }
+    st2(Z + j + ihi * ld, zc);
+    if (tdo) st2(T + j + ihi * ld, tc);
+  }
+  __syncthreads();
+}
+
 // Complex Schur form of the Hessenberg T (upper triangular on return), the
 // similarity accumulated into Z (A = Z T Z^+); leading dimension ld for both.
 // Returns false if the iteration did not converge.  Every lane takes the
@@ -239,6 +380,10 @@ __device__ __forceinline__ bool win_schur(double2 *T, double2 *Z, int n, int ld)
       const wcx m1 = avg + disc, m2 = avg - disc;
       mu = wabs(m1 - d) < wabs(m2 - d) ? m1 : m2;
     }
+    if (n <= kWinThreads) {
+      win_sweep_lanes(T, Z, n, ld, l, ihi, mu);
+      continue;
+    }
     for (int k = l; k < ihi; ++k) {
       double c;
       wcx s;
@@ -286,6 +431,10 @@ __device__ __forceinline__ bool win_schur(double2 *T, double2 *Z, int n, int ld)
 template <int PL>
 __device__ __attribute__((noinline)) bool win_eig_pl(const double2 *C, int n, int ld, double2 *lam, double2 *y,
                                                      double2 *z, double2 *ws, int which) {
+  // the same on every lane: scalar registers, uniform loops and branches
+  n = __builtin_amdgcn_readfirstlane(n);
+  ld = __builtin_amdgcn_readfirstlane(ld);
+  which = __builtin_amdgcn_readfirstlane(which);
   const int t = threadIdx.x;
   const int lw = n | 1;  // odd leading dimension
   const size_t nn = size_t(lw) * n;
@@ -333,31 +482,73 @@ __device__ __attribute__((noinline)) bool win_eig_pl(const double2 *C, int n, in
     }
   }
   __syncthreads();
-  // sort order (lane 0): the criterion's key ascending, ties (to 1e-12 of the
-  // larger modulus) by imaginary part descending
-  if (t == 0) {
-    auto sort_key = [which](wcx l) { return which == 1 ? l.x : (which == 2 ? -wabs(l) : wabs(l)); };
-    for (int i = 0; i < n; ++i) ord[i] = i;
+  // sort order: the criterion's key ascending, ties (to 1e-12 of the larger
+  // modulus) by imaginary part descending, then by index; an insertion sort
+  // (the order the host solver produces, also where near-ties make the
+  // comparison intransitive).  Does entry (kp, mp, ip, op) come after (kk, mk, ik, ok)?
+  auto after = [](double kp, double mp, double ip, int op, double kk, double mk, double ik, int ok) {
+    if (fabs(kp - kk) > 1e-12 * fmax(fmax(mp, mk), 1e-300)) return kp > kk;
+    if (ip != ik) return ip < ik;
+    return op > ok;
+  };
+  if (n <= kWinThreads) {
+    // lane p holds sorted position p; each insertion finds its place with a
+    // ballot (the highest p whose entry does not come after the new one, as
+    // the scan from the right stops there) and shifts the tail up one lane
+    double key = 0.0, mod = 0.0, im = 0.0;
+    if (t < n) {
+      const wcx li = ld2(lm + t);
+      mod = wabs(li);
+      key = which == 1 ? li.x : (which == 2 ? -mod : mod);
+      im = li.y;
+    }
+    double sk = key, sm = mod, si = im;
+    int so = t;
     for (int i = 1; i < n; ++i) {
-      const int key = ord[i];
-      const wcx lk = ld2(lm + key);
-      const double ak = sort_key(lk);
-      int p = i - 1;
-      while (p >= 0) {
-        const wcx lp = ld2(lm + ord[p]);
-        const double ap = sort_key(lp);
-        bool after;  // does ord[p] come after key?
-        if (fabs(ap - ak) > 1e-12 * fmax(fmax(wabs(lp), wabs(lk)), 1e-300))
-          after = ap > ak;
-        else if (lp.y != lk.y)
-          after = lp.y < lk.y;
-        else
-          after = ord[p] > key;
-        if (!after) break;
-        ord[p + 1] = ord[p];
-        --p;
+      const double kk = win_readlane(key, i), mk = win_readlane(mod, i), ik = win_readlane(im, i);
+      const bool stay = t < i && !after(sk, sm, si, so, kk, mk, ik, i);
+      const unsigned long long m = __ballot(stay);
+      const int pos = m ? 64 - __clzll(m) : 0;
+      const double uk = __shfl_up(sk, 1), um = __shfl_up(sm, 1), ui = __shfl_up(si, 1);
+      const int uo = __shfl_up(so, 1);
+      if (t == pos) {
+        sk = kk;
+        sm = mk;
+        si = ik;
+        so = i;
+      } else if (t > pos && t <= i) {
+        sk = uk;
+        sm = um;
+        si = ui;
+        so = uo;
       }
-      ord[p + 1] = key;
+    }
+    if (t < n) ord[t] = so;
+  } else {
+    // keys and moduli first, one value per lane (vec is free here); lane 0 sorts
+    for (int i = t; i < n; i += kWinThreads) {
+      const wcx li = ld2(lm + i);
+      const double a = wabs(li);
+      win_lds.vec[i] = make_double2(which == 1 ? li.x : (which == 2 ? -a : a), a);
+    }
+    __syncthreads();
+    if (t == 0) {
+      const double2 *km = win_lds.vec;
+      for (int i = 0; i < n; ++i) ord[i] = i;
+      for (int i = 1; i < n; ++i) {
+        const int key = ord[i];
+        const double2 kk = km[key];
+        const double lky = lm[key].y;
+        int p = i - 1;
+        while (p >= 0) {
+          const int op = ord[p];
+          const double2 kp = km[op];
+          if (!after(kp.x, kp.y, lm[op].y, op, kk.x, kk.y, lky, key)) break;
+          ord[p + 1] = op;
+          --p;
+        }
+        ord[p + 1] = key;
+      }
     }
   }
   __syncthreads();
