@@ -350,21 +350,27 @@ eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int
  * the t neighbours held in registers (full-lattice stencil only, a box of a
  * whole number of 256-thread blocks for k).  eb_op_batch_tune runs the
  * autotuner once per operator and precision (it times every form the
- * operator admits for k = 2, 4, 8, 16, and the LDS-staged form for k = 1,
- * the form of the one-at-a-time solver that a single column runs, on
- * `stream`, three repetitions after a warm-up, and keeps per k the fastest
- * form and overall the k with the lowest time per right-hand side) and reports: *k_best; stage[5] (may be
+ * operator admits for k = 2, 4, 8, 16, and for k = 1 the two forms of the
+ * one-at-a-time solver that a single column runs, LDS-staged (1) and
+ * t-marching (6), on `stream`, three repetitions after a warm-up, and keeps
+ * per k the fastest form and overall the k with the lowest time per
+ * right-hand side) and reports: *k_best; stage[5] (may be
  * NULL) the form used for k = 1, 2, 4, 8, 16; ms_per_rhs[5 * EB_TILE_FORMS] (may be NULL) the
  * measured time per right-hand side, [EB_TILE_FORMS i + form] for k = 2^i (0 for a form
  * not admitted).  Batched solves with batch = 0, sessions and
  * eb_op_apply_block / eb_op_apply_schur_block use the forms chosen here
- * (before tuning: LDS staging for k = 1 and for BF16, else form 0). */
+ * (before tuning: LDS staging for k = 1 and for BF16, else form 0).  The
+ * one-at-a-time BiCGStab (batch = 1, every precision) on a full-lattice
+ * operator runs its two stencil passes in the k = 1 form: 6 if that is the
+ * entry, else 1; with no entry yet it times both once on its first solve and
+ * records the faster. */
 #define EB_TILE_FORMS 7
 eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_best, int32_t *stage,
                            double *ms_per_rhs);
 /* Set the tile form for one precision and k (0..6 as above, or -1 for the built-in rule);
  * results agree to rounding between the forms.  EB_ERR_INVALID for a form the operator does
- * not admit.  Host-only; a later first run of the tuner replaces it. */
+ * not admit.  For k = 1 it also sets the one-at-a-time solver's form (6, or 1 for any
+ * other form).  Host-only; a later first run of the tuner replaces it. */
 eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage);
 /* Release the operator's work buffers (eigBiCG windows, batch and scratch vectors; not the
  * links, the deflation space or the reduction scratch) after waiting for `stream` and the

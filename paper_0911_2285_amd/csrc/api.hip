@@ -406,6 +406,44 @@ struct StabResult {
   double rnorm = 0;
 };
 
+// Stencil form of the one-column BiCGStab on a full-lattice operator: the
+// LDS-staged tiles (1) or t-marching boxes (kMarchTile), whichever the k = 1
+// entry of the batch tuning table names; if the table has none, both are timed
+// once (D on src into dst, three launches each after one) and the faster is
+// kept there.  Even-odd operators run Dhat (form 1).
+template <typename S>
+int single_stab_form(eb_op *op, const S *U, const S *src, S *dst, hipStream_t s) {
+  if (op->eo) return 1;
+  const int pi = std::is_same<S, double2>::value ? 0 : (std::is_same<S, float2>::value ? 1 : 2);
+  int &f = op->batch_stage[pi][1];
+  if (f < 0) {
+    f = 1;
+    if (batch_tile_ok(op->g, false, kMarchTile, 1)) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      double best = HUGE_VAL;
+      for (int stage : {1, kMarchTile}) {
+        launch_bdslash<S>(dst, src, U, op->g, op->kappa, false, 1, s, stage);
+        HIPCHK(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 3; ++rep) launch_bdslash<S>(dst, src, U, op->g, op->kappa, false, 1, s, stage);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        op->batch_stage_ms[pi][1][stage] = ms / 3.0;
+        if (ms < best) {
+          best = ms;
+          f = stage;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+  }
+  return f == kMarchTile ? kMarchTile : 1;
+}
+
 template <typename S>
 StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, double def_thr, int maxiter,
                         const std::string &tag, hipStream_t s) {
@@ -417,6 +455,8 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
   S *t = op->raw<S>(tag + "t", N * sizeof(S));
   KrylovState *K = op->S();
   KrylovHistory h = op->history(maxiter + 4);
+  const int form = single_stab_form<S>(op, U, r, v, s);
+  const int nrec = form == kMarchTile ? march_records(op->g, 1) : 0;
   launch_stab_init<S>(rhat, p, r, N, tol_abs, def_thr, maxiter, K, h, op->rs(), s);
   KrylovState hs;
   fetch_state(op, s, hs);
@@ -432,12 +472,16 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
   auto stab_v = [&](int j) {
     if (op->eo)
       launch_stab_v_eo<S>(v, p, rhat, tmp, U, op->g, op->kappa, j, K, op->rs(), s);
+    else if (form == kMarchTile)
+      launch_bstab_v<S>(v, p, rhat, U, op->g, op->kappa, j, 1, K, op->rs(), s, kMarchTile);
     else
       launch_stab_v<S>(v, p, rhat, U, op->g, op->kappa, j, K, h, op->rs(), s);
   };
   auto stab_t = [&](int j) {
     if (op->eo)
       launch_stab_t_eo<S>(t, sv, tmp, U, op->g, op->kappa, j, K, op->rs(), s);
+    else if (form == kMarchTile)
+      launch_bstab_t<S>(t, sv, U, op->g, op->kappa, j, 1, K, op->rs(), s, kMarchTile);
     else
       launch_stab_t<S>(t, sv, U, op->g, op->kappa, j, K, h, op->rs(), s);
   };
@@ -449,9 +493,9 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
     while (j < maxiter) {
       ++j;
       TIMED(EB_K_STAB_V, s, stab_v(j));
-      TIMED(EB_K_STAB_S, s, launch_stab_s<S>(sv, r, v, N, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_S, s, launch_stab_s<S>(sv, r, v, N, j, K, h, op->rs(), s, nrec));
       TIMED(EB_K_STAB_T, s, stab_t(j));
-      TIMED(EB_K_STAB_XR, s, launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, h, op->rs(), s));
+      TIMED(EB_K_STAB_XR, s, launch_stab_xr<S>(x, r, p, sv, t, rhat, N, j, K, h, op->rs(), s, nrec));
       TIMED(EB_K_STAB_P, s, launch_stab_p<S>(p, r, v, N, j, K, h, op->rs(), s));
       if (j % poll == 0 && pl.step(&hs)) {
         stopped = true;
@@ -731,9 +775,9 @@ int tune_batch(eb_op *op, hipStream_t s) {
     double t_kc = HUGE_VAL;
     for (int stage = 0; stage < kTileForms; ++stage) {  // every tile form this operator admits
       if (!batch_tile_ok(op->g, op->eo, stage, kc)) continue;
-      // one column runs the one-at-a-time solver, whose stencils stage their
-      // tiles in LDS: time k = 1 in that form only
-      if (kc == 1 && stage != 1) continue;
+      // one column runs the one-at-a-time solver, whose stencils take the
+      // LDS-staged or the t-marching form: time k = 1 in those
+      if (kc == 1 && stage != 1 && stage != kMarchTile) continue;
       apply(kc, stage);
       HIPCHK(hipEventRecord(e0, s));
       for (int rep = 0; rep < 3; ++rep) apply(kc, stage);

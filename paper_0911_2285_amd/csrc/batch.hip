@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(kBlock)
 struct March {
   int rx, ry, rz, tc;  // rx = 0: the form does not fit the lattice and k
 };
-constexpr int kMarchForm = 6;
+constexpr int kMarchForm = kMarchTile;
 // Largest divisor of n not above cap.
 inline int divisor_below(int n, int cap) {
   for (int d = cap < n ? cap : n; d > 1; --d)
@@ -776,6 +776,7 @@ __global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
 }  // namespace
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
+int march_records(const Geom &g, int kc) { return march_blocks(g, kc, march_shape(g, kc)); }
 bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc) {
   if (stage < -1 || stage >= kTileForms) return false;
   if (stage < 2) return true;

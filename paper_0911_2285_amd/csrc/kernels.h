@@ -261,18 +261,20 @@ void launch_stab_init(S *rhat, S *p, const S *r, size_t N, double tol_abs, doubl
 template <typename S>
 void launch_stab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, KrylovState *K,
                    KrylovHistory h, const RedScratch &rs, hipStream_t st);
-// alpha_j = rho_{j-1} / (rhat, v); s = r - alpha v
+// alpha_j = rho_{j-1} / (rhat, v); s = r - alpha v.  nrec: the records of the
+// v pass (launch_stab_v: 0; the t-marching pass: march_records(g, 1)).
 template <typename S>
 void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
-                   const RedScratch &rs, hipStream_t st);
+                   const RedScratch &rs, hipStream_t st, int nrec = 0);
 // t = D s; partials of (t, s), (t, t)
 template <typename S>
 void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, KrylovState *K, KrylovHistory h,
                    const RedScratch &rs, hipStream_t st);
-// omega_j; x += alpha p + omega s; r = s - omega t; partials of (rhat, r), ||r||^2
+// omega_j; x += alpha p + omega s; r = s - omega t; partials of (rhat, r), ||r||^2.
+// nrec: the records of the t pass, as for launch_stab_s.
 template <typename S>
 void launch_stab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, size_t N, int j, KrylovState *K,
-                    KrylovHistory h, const RedScratch &rs, hipStream_t st);
+                    KrylovHistory h, const RedScratch &rs, hipStream_t st, int nrec = 0);
 // rho_j, beta_j, the stop tests; p = r + beta (p - omega v)
 template <typename S>
 void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
@@ -322,7 +324,10 @@ bool batch_size_ok(int kc);
 // whole number of blocks for k); < 0 the built-in rule (LDS staging for k = 1
 // and for BF16).
 constexpr int kTileForms = 7;
+constexpr int kMarchTile = 6;
 bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc);
+// Records (blocks) of a t-marching pass on kc columns (the form must fit).
+int march_records(const Geom &g, int kc);
 // stage: tile form of the batched stencils (kTileForms above)
 template <typename S>
 void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,

@@ -838,9 +838,9 @@ void launch_stab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, d
 }
 template <typename S>
 void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
-                   const RedScratch &rs, hipStream_t st) {
+                   const RedScratch &rs, hipStream_t st, int nrec) {
   EB_LAUNCH(k_stab_s<S>, dim3(stream_grid(N)), dim3(kBlock), 0, st, s, r, v, N, j, K, h, region(rs, RG_V),
-            stencil_grid(int(N / 12)));
+            nrec > 0 ? nrec : stencil_grid(int(N / 12)));
 }
 template <typename S>
 void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, int j, KrylovState *K, KrylovHistory,
@@ -849,9 +849,9 @@ void launch_stab_t(S *t, const S *s, const S *U, const Geom &g, double kappa, in
 }
 template <typename S>
 void launch_stab_xr(S *x, S *r, const S *p, const S *s, const S *t, const S *rhat, size_t N, int j, KrylovState *K,
-                    KrylovHistory h, const RedScratch &rs, hipStream_t st) {
+                    KrylovHistory h, const RedScratch &rs, hipStream_t st, int nrec) {
   EB_LAUNCH(k_stab_xr<S>, dim3(red_grid(N)), dim3(kBlock), 0, st, x, r, p, s, t, rhat, N, j, K, h, region(rs, RG_T),
-            stencil_grid(int(N / 12)), region(rs, RG_XR));
+            nrec > 0 ? nrec : stencil_grid(int(N / 12)), region(rs, RG_XR));
 }
 template <typename S>
 void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
@@ -866,11 +866,11 @@ void launch_stab_p(S *p, const S *r, const S *v, size_t N, int j, KrylovState *K
   template void launch_stab_v<S>(S *, const S *, const S *, const S *, const Geom &, double, int, KrylovState *,    \
                                  KrylovHistory, const RedScratch &, hipStream_t);                                    \
   template void launch_stab_s<S>(S *, const S *, const S *, size_t, int, KrylovState *, KrylovHistory,              \
-                                 const RedScratch &, hipStream_t);                                                   \
+                                 const RedScratch &, hipStream_t, int);                                              \
   template void launch_stab_t<S>(S *, const S *, const S *, const Geom &, double, int, KrylovState *, KrylovHistory, \
                                  const RedScratch &, hipStream_t);                                                   \
   template void launch_stab_xr<S>(S *, S *, const S *, const S *, const S *, const S *, size_t, int, KrylovState *, \
-                                  KrylovHistory, const RedScratch &, hipStream_t);                                   \
+                                  KrylovHistory, const RedScratch &, hipStream_t, int);                              \
   template void launch_stab_p<S>(S *, const S *, const S *, size_t, int, KrylovState *, KrylovHistory,              \
                                  const RedScratch &, hipStream_t);
 EB_STAB_INST(double2)

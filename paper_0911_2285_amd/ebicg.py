@@ -454,7 +454,8 @@ def op_batch_set_tile(op, prec, k, stage):
     """Force the tile form of the batched stencil for (prec, k): 0 global reads, 1 LDS-staged,
     2 / 3 / 4 global reads in bricks, 5 global reads without fences between hops, 6 t-marching
     boxes (full-lattice operators; the box must hold a whole number of blocks for k), -1
-    built-in rule."""
+    built-in rule.  For k = 1 it also picks the one-at-a-time solver's stencil form (6, or 1
+    for any other form)."""
     _check(lib().eb_op_batch_set_tile(op.handle, PREC[prec], int(k), int(stage)))
 
 

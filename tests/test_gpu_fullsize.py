@@ -4,6 +4,9 @@
   oracle's run of the same solve (Alg. eigBiCG with Alg. BiCG-eigen), read from
   tests/golden/cfg1_eigbicg_16x16x16x32.json (written by make_cfg1_eigbicg.py,
   which calls only the oracle).
+* 16^3 x 32, the one-column BiCGStab (FP64, FP32 and BF16 inner) with its
+  stencil passes in the t-marching and in the LDS-staged form, each solve
+  checked with the oracle's D and the two forms against each other.
 * 8^4 with the stencil grid capped at 3 blocks: every block of the reducing
   stencils loops over several site tiles, the path that lattices beyond
   262 144 sites take by default; eigBiCG, deflated BiCGStab (full and
@@ -122,6 +125,38 @@ def test_batched_solve_tile_forms_16x32(gpu_lib, prec, k):
              f"steps, largest residual (oracle D) {tr:.2e}")
         assert tr <= 1e-10
     assert max(its.values()) <= 1.1 * min(its.values()) + 2 * k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_one_column_solve_stencil_forms_16x32(gpu_lib, prec):
+    """The one-column BiCGStab (FP64, or FP32 / BF16 inner with FP64 refinement) with
+    its two stencil passes in the t-marching boxes and in the LDS-staged tiles (the
+    k = 1 entry of the tuning table): each solve reaches 1e-10 in the oracle's D, the
+    iteration counts agree to within 10%, and the two solutions to 1e-8."""
+    import torch
+
+    dims, kappa = (16, 16, 16, 32), 0.122
+    V = synth.volume(dims)
+    U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(1))
+    A, _ = _ops(U, kappa, dims)
+    op = gpu_lib.op_create(U, kappa, dims)
+    b_np = synth.z2_source(V, synth.rhs_seed(1, 450))
+    b = torch.from_numpy(b_np).to("cuda:0")
+    its, xs = {}, {}
+    for stage in (6, 1):
+        gpu_lib.op_batch_set_tile(op, prec, 1, stage)
+        x = torch.zeros_like(b)
+        st = gpu_lib.deflated_bicg_solve(op, b, x, tol=1e-10, inner=prec, nrhs=1, batch=1)
+        xs[stage] = x.cpu().numpy().ravel()
+        tr = _oracle_rel_resid(A, b_np, xs[stage])
+        its[stage] = st["iters"]
+        _say(f"16^3x32 one column, {prec}, stencil form {stage}: {st['iters']} iterations, "
+             f"{st['outer_steps']} refinement steps, residual (oracle D) {tr:.2e}")
+        assert tr <= 1e-10
+    diff = np.linalg.norm(xs[6] - xs[1]) / np.linalg.norm(xs[1])
+    _say(f"  solutions differ by {diff:.1e}")
+    assert max(its.values()) <= 1.1 * min(its.values()) + 2
+    assert diff < 1e-8
 
 
 # --------------------------------------------------------------------------- grid-stride paths
