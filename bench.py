@@ -53,6 +53,8 @@ WORKLOADS = {
     "inc16x32": dict(dims=(16, 16, 16, 32), kappa=0.122, nrhs=24, n1=8, nev=10, m=40, tol=1e-10, cfg=1),
     # the small parity workload (4^4), for quick runs
     "inc4": dict(dims=(4, 4, 4, 4), kappa=0.115, nrhs=4, n1=4, nev=4, m=16, tol=1e-10, cfg=0),
+    # the precision lattice, 24^3 x 64 (fields beyond the Infinity Cache): counters of its BiCG matvec
+    "prec24x64": dict(dims=(24, 24, 24, 64), kappa=0.123, nrhs=32, n1=8, nev=10, m=40, tol=1e-10, cfg=2),
     # the bench line: 32^3 x 64 batched mixed-precision deflated solves (100 pairs)
     "batch32x64": dict(dims=(32, 32, 32, 64), kappa=0.123, nrhs=16, n1=4, nev=25, m=60, tol=1e-10, cfg=3,
                        inner="fp32", inner_tol=1e-6),

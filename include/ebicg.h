@@ -372,6 +372,20 @@ eb_status eb_op_batch_tune(eb_op *op, eb_prec prec, void *stream, int32_t *k_bes
  * not admit.  For k = 1 it also sets the one-at-a-time solver's form (6, or 1 for any
  * other form).  Host-only; a later first run of the tuner replaces it. */
 eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage);
+/* Form of the BiCG matvec pair of eigBiCG and deflated BiCG (D p with the
+ * partials of (phat, D p), and D^+ phat; Alg. eigBiCG, the products of each
+ * iteration): 1 LDS-staged tiles (a work item per tile and product), 6
+ * t-marching units (the D and D^+ units of one box and chunk on one XCD at the
+ * same time, sharing the link loads; full-lattice operator whose box of
+ * 32 x 32 x 8 sites or less holds a whole number of 256-site blocks), -1
+ * (default) time both once at the next solve and keep the faster.  Results
+ * agree to rounding.  EB_ERR_INVALID for another value or a form the operator
+ * does not admit.  Host-only. */
+eb_status eb_op_set_matvec_form(eb_op *op, int32_t form);
+/* The matvec form in use (-1 before the first solve has chosen; 1 for an
+ * even-odd operator) and, in ms[2] (may be NULL), the milliseconds per launch
+ * the choice measured for forms 1 and 6 (0 if not timed). */
+eb_status eb_op_get_matvec_form(eb_op *op, int32_t *form, double *ms);
 /* Release the operator's work buffers (eigBiCG windows, batch and scratch vectors; not the
  * links, the deflation space or the reduction scratch) after waiting for `stream` and the
  * device; later calls allocate what they need again.  Sessions keep their own buffers. */

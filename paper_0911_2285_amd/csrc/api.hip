@@ -147,6 +147,10 @@ struct eb_op {
   // multi-RHS: chosen columns per batch per precision (0: not tuned yet) and
   // the measured stencil time per right-hand side of each candidate
   int batch_choice[3] = {0, 0, 0};
+  // form of the BiCG matvec pair: 1 LDS-staged tiles, kMarchTile t-marching
+  // boxes, -1 not chosen yet (timed at the next solve); matvec_ms[form]
+  int matvec_form = -1;
+  double matvec_ms[kTileForms] = {};
   double batch_ms[3][kMaxBatch + 1] = {};
   // tile form of the batched stencils per precision and k (1: LDS-staged
   // tile, 0: global neighbour reads, -1: the built-in rule), chosen by the
@@ -444,6 +448,50 @@ int single_stab_form(eb_op *op, const S *U, const S *src, S *dst, hipStream_t s)
   return f == kMarchTile ? kMarchTile : 1;
 }
 
+// Form of the BiCG matvec pair (D p with sigma, D^+ phat) on a full-lattice
+// operator: the LDS-staged work items or the t-marching units, as set, or
+// else both timed once (three launches each after one, on the solve's p,
+// phat and product buffers, before its first iteration) and the faster kept.
+// Even-odd operators run Dhat.
+int bicg_matvec_form(eb_op *op, double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, KrylovState *S,
+                     hipStream_t s) {
+  if (op->eo) return 1;
+  if (op->matvec_form < 0) {
+    op->matvec_form = 1;
+    if (batch_tile_ok(op->g, false, kMarchTile, 1)) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      double best = HUGE_VAL;
+      const double2 *U = op->U64.as<double2>();
+      KrylovHistory none{};
+      for (int form : {1, kMarchTile}) {
+        auto run = [&]() {  // j = 0: no stop flag of an earlier solve skips it
+          if (form == kMarchTile)
+            launch_bicg_matvec_march(Ap, Adp, p, ph, U, op->g, op->kappa, 0, S, op->rs(), false, s);
+          else
+            launch_bicg_matvec(Ap, Adp, p, ph, U, op->g, op->kappa, 0, S, none, op->rs(), false, s);
+        };
+        run();
+        HIPCHK(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 3; ++rep) run();
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        op->matvec_ms[form] = ms / 3.0;
+        if (ms < best) {
+          best = ms;
+          op->matvec_form = form;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+  }
+  return op->matvec_form;
+}
+
 template <typename S>
 StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, double def_thr, int maxiter,
                         const std::string &tag, hipStream_t s) {
@@ -583,6 +631,8 @@ void deflated_bicg_f64(eb_op *op, const double2 *b, double2 *x, double tol, int 
     if (hs.stopped && hs.reason == 2) fail(EB_ERR_BREAKDOWN, "BiCG: (rhat_0, r_0) = 0");
     int j = 0;
     bool stopped = hs.stopped != 0;
+    const int mvf = stopped ? 1 : bicg_matvec_form(op, Ap, Adp, p, ph, S, s);
+    const int nsig = mvf == kMarchTile ? bicg_matvec_march_records(op->g, false) : 0;
     {
       Poller pl(op, S, s);
       while (!stopped && j < left) {
@@ -591,10 +641,14 @@ void deflated_bicg_f64(eb_op *op, const double2 *b, double2 *x, double tol, int 
         TIMED(EB_K_BICG_MATVEC, s,
               op->eo ? launch_bicg_matvec_eo(Ap, Adp, p, ph, op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g,
                                              op->kappa, j, S, op->rs(), false, s)
-                     : launch_bicg_matvec(Ap, Adp, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
-                                          op->rs(), false, s));
+              : mvf == kMarchTile
+                  ? launch_bicg_matvec_march(Ap, Adp, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S,
+                                             op->rs(), false, s)
+                  : launch_bicg_matvec(Ap, Adp, p, ph, op->U64.as<double2>(), op->g, op->kappa, j, S, dh,
+                                       op->rs(), false, s));
         TIMED(EB_K_BICG_UPDATE_R, s,
-              launch_bicg_update_r(r[cur], rh[cur], r[prv], rh[prv], Ap, Adp, N, j, S, dh, op->rs(), false, s));
+              launch_bicg_update_r(r[cur], rh[cur], r[prv], rh[prv], Ap, Adp, N, j, S, dh, op->rs(), false, s,
+                                   nullptr, nullptr, nsig));
         TIMED(EB_K_BICG_UPDATE_P, s, launch_bicg_update_p(x, p, ph, r[cur], rh[cur], N, j, S, dh, op->rs(), false, s));
         if (j % 8 == 0 && pl.step(&hs)) stopped = true;
       }
@@ -1422,6 +1476,9 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
   bool stopped = false;
   int stop_at = 0, reason = 0;
   double rnorm = 0;
+  // (the timing, if any, runs the pair on p, phat into the second product buffers)
+  const int mvf = bicg_matvec_form(op, Ap + N, Adp + N, p, g5 ? p : ph, S, s);
+  const int nsig = mvf == kMarchTile ? bicg_matvec_march_records(op->g, g5) : 0;
   {
     Poller pl(op, S, s);
     while (true) {
@@ -1432,8 +1489,11 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
             op->eo ? launch_bicg_matvec_eo(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
                                            op->vec("eo_tmp"), op->Ueo.as<double2>(), op->g, op->kappa, j, S,
                                            op->rs(), g5, s)
-                   : launch_bicg_matvec(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
-                                        op->U64.as<double2>(), op->g, op->kappa, j, S, dh, op->rs(), g5, s));
+            : mvf == kMarchTile
+                ? launch_bicg_matvec_march(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
+                                           op->U64.as<double2>(), op->g, op->kappa, j, S, op->rs(), g5, s)
+                : launch_bicg_matvec(Ap + cur * N, g5 ? nullptr : Adp + cur * N, p, g5 ? nullptr : ph,
+                                     op->U64.as<double2>(), op->g, op->kappa, j, S, dh, op->rs(), g5, s));
       if (int(cols.size()) == m) {
         // Restart at iteration j (vs = m).  q = A p and s = A^+ phat were kept
         // from iteration j-1 (vs = m-1) in the other buffer.
@@ -1497,7 +1557,7 @@ EigBiCGOut run_eigbicg(eb_op *op, const double2 *b, double2 *x, const eb_eig_par
             launch_bicg_update_r(Rrec(j, snew), g5 ? nullptr : RHrec(j, snew), Rrec(j - 1, sold),
                                  g5 ? nullptr : RHrec(j - 1, sold), Ap + cur * N, g5 ? nullptr : Adp + cur * N, N, j,
                                  S, dh, op->rs(), g5, s, w32 ? win32.V(snew) : nullptr,
-                                 (w32 && !g5) ? win32.W(snew) : nullptr));
+                                 (w32 && !g5) ? win32.W(snew) : nullptr, nsig));
       if (job_done()) apply_job();
       TIMED(EB_K_BICG_UPDATE_P, s,
             launch_bicg_update_p(x, p, g5 ? nullptr : ph, Rrec(j, snew), g5 ? nullptr : RHrec(j, snew), N, j, S, dh,
@@ -2897,6 +2957,27 @@ eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage
       fail(EB_ERR_INVALID,
            "tile form must be -1, 0 or 1, or 2..6 on a full-lattice operator whose extents the form's brick or box fits");
     op->batch_stage[prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2)][k] = stage;
+  });
+}
+
+eb_status eb_op_set_matvec_form(eb_op *op, int32_t form) {
+  return guarded([&]() {
+    if (!op) fail(EB_ERR_INVALID, "null argument");
+    if (form != -1 && form != 1 && form != kMarchTile) fail(EB_ERR_INVALID, "matvec form must be -1, 1 or 6");
+    if (form == kMarchTile && !batch_tile_ok(op->g, op->eo, kMarchTile, 1))
+      fail(EB_ERR_INVALID, "the t-marching matvec needs a full-lattice operator whose box fits");
+    op->matvec_form = form;
+  });
+}
+
+eb_status eb_op_get_matvec_form(eb_op *op, int32_t *form, double *ms) {
+  return guarded([&]() {
+    if (!op || !form) fail(EB_ERR_INVALID, "null argument");
+    *form = op->eo ? 1 : op->matvec_form;
+    if (ms) {
+      ms[0] = op->matvec_ms[1];
+      ms[1] = op->matvec_ms[kMarchTile];
+    }
   });
 }
 

@@ -162,7 +162,9 @@ inline int divisor_below(int n, int cap) {
 // k = 2 .. 8, 32 x 32 x 8 for one column; each extent is the largest divisor
 // of the lattice extent within its cap.  A box must hold a whole number of
 // blocks; chunks are cut from the full t extent until the launch has at least
-// 512 blocks (two per CU), but no shorter than 4 slices.  The records of the
+// 512 blocks (two per CU), but no shorter than 8 slices: a chunk re-reads the
+// slice before it, and at 24^3 x 64 (FP64, one column) 8-slice chunks on 432
+// blocks beat 4-slice chunks on 864 (264 against 286 us).  The records of the
 // reducing variants (three per column and block) must fit one region.
 inline March march_shape(const Geom &g, int kc) {
   const int cy = kc == 1 ? 32 : 16, cx = kc >= 16 ? 16 : 32;
@@ -170,7 +172,7 @@ inline March march_shape(const Geom &g, int kc) {
   const long long box = (long long)m.rx * m.ry * m.rz;
   if ((box * kc) % kBlock != 0) return March{};
   auto blocks = [&](int tc) { return (long long)g.V / tc * kc / kBlock; };
-  while (m.tc % 2 == 0 && m.tc > 4 && blocks(m.tc) < 512) m.tc /= 2;
+  while (m.tc % 2 == 0 && m.tc > 8 && blocks(m.tc) < 512) m.tc /= 2;
   if (blocks(m.tc) * kc * 3 > (long long)kRegion) return March{};
   return m;
 }
@@ -179,6 +181,80 @@ inline int march_blocks(const Geom &g, int kc, const March &m) { return int((lon
 // partials per column: what its consumer sums.
 inline int stencil_records(const Geom &g, int kc, int nv, int stage) {
   return stage == kMarchForm ? march_blocks(g, kc, march_shape(g, kc)) : batch_stencil_grid(g.V, kc, nv);
+}
+
+// One thread's walk of the t-marching form: site (x, y, z) of its box, column
+// col, through the slices of chunk `chunk`: out = in - kappa hop at every
+// slice, and epi(c, i, o, in_c) for each of the 12 components (i the entry's
+// index, o the output, in_c the input at the site).
+template <typename S, int KC, int SF, typename Epi>
+__device__ __forceinline__ void march_walk(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U,
+                                           const Geom &g, typename Store<S>::R k, const March &m, int x, int y, int z,
+                                           int col, int chunk, Epi &&epi) {
+  using R = typename Store<S>::R;
+  const int Vs = g.lx * g.ly * g.lz, xyz = x + g.lx * (y + g.ly * z);
+  const int sy = g.lx, sz = g.lx * g.ly;
+  const int xf = x == g.lx - 1 ? -(g.lx - 1) : 1, xb = x == 0 ? g.lx - 1 : -1;
+  const int yf = y == g.ly - 1 ? -(g.ly - 1) * sy : sy, yb = y == 0 ? (g.ly - 1) * sy : -sy;
+  const int zf = z == g.lz - 1 ? -(g.lz - 1) * sz : sz, zb = z == 0 ? (g.lz - 1) * sz : -sz;
+  const S *inc = in + col;
+  auto xyz_hops = [&](cx<R> (&acc)[12], int s) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+    hop_dir<2, SF, S, KC, true>(acc, inc, U, g.V, s, s + zf, s + zb);
+    hop_dir<0, SF, S, KC, true>(acc, inc, U, g.V, s, s + xf, s + xb);
+    hop_dir<1, SF, S, KC, true>(acc, inc, U, g.V, s, s + yf, s + yb);
+  };
+  const int t0 = chunk * m.tc, t1 = t0 + m.tc;
+  cx<R> cen[12], acc[12], carry[6];
+  {
+    const int s = xyz + Vs * t0, sp = xyz + Vs * (t0 == 0 ? g.lt - 1 : t0 - 1);
+    load_spinor<S, KC>(cen, inc, g.V, s);
+    cx<R> h[6];
+    load_project<3, -SF, S, KC>(h, inc, g.V, sp);
+    mult_t<true, S>(carry, h, U, g.V, sp);
+    xyz_hops(acc, s);
+  }
+  for (int t = t0; t < t1; ++t) {
+    int s = xyz + Vs * t, sn = xyz + Vs * (t == g.lt - 1 ? 0 : t + 1);
+    // opaque site indices: the addresses are formed from them in each step
+    // instead of being carried across steps in registers
+    asm volatile("" : "+v"(s), "+v"(sn));
+    cx<R> nxt[12];
+    load_spinor<S, KC>(nxt, inc, g.V, sn);
+    {
+      cx<R> h[6], w[6];
+      project_t<SF>(h, nxt);
+      mult_t<false, S>(w, h, U, g.V, s);
+      recon_t<SF>(acc, w);
+      recon_t<-SF>(acc, carry);
+      project_t<-SF>(h, cen);
+      mult_t<true, S>(carry, h, U, g.V, s);
+    }
+    hop_fence();
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const size_t i = (size_t(c) * g.V + s) * KC + col;
+      const cx<R> o = cen[c] - k * acc[c];
+      Store<S>::st(out, i, o);
+      epi(c, i, o, cen[c]);
+    }
+    if (t + 1 < t1) xyz_hops(acc, sn);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) cen[c] = nxt[c];
+  }
+}
+
+// Box coordinates of thread u (columns fastest) of a unit of box `box`.
+struct MarchSite {
+  int x, y, z, col;
+};
+template <int KC>
+__device__ __forceinline__ MarchSite march_site(const Geom &g, const March &m, int box, int u) {
+  const int col = u % KC, q = u / KC;
+  const int nbx = g.lx / m.rx, nby = g.ly / m.ry;
+  return {(box % nbx) * m.rx + q % m.rx, ((box / nbx) % nby) * m.ry + (q / m.rx) % m.ry,
+          (box / (nbx * nby)) * m.rz + q / (m.rx * m.ry), col};
 }
 
 // EPI 0: out = in - kappa hop (the operator); 1: also the partials of
@@ -190,84 +266,68 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
              const S *__restrict__ rhat, int j, const KrylovState *K, double *__restrict__ part) {
   using R = typename Store<S>::R;
   constexpr int NV = EPI == 2 ? 3 : 2;
-  const R k = R(kappa);
   const int bpu = m.rx * m.ry * m.rz * KC / kBlock;  // blocks per unit
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int unit = lb / bpu, u = (lb - unit * bpu) * kBlock + threadIdx.x;
   const int nch = g.lt / m.tc, box = unit / nch, chunk = unit - box * nch;
-  const int col = u % KC, q = u / KC;
-  const int nbx = g.lx / m.rx, nby = g.ly / m.ry;
-  const int x = (box % nbx) * m.rx + q % m.rx;
-  const int y = ((box / nbx) % nby) * m.ry + (q / m.rx) % m.ry;
-  const int z = (box / (nbx * nby)) * m.rz + q / (m.rx * m.ry);
+  const MarchSite ms = march_site<KC>(g, m, box, u);
   double d[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) d[i] = 0.0;
   bool act = true;
-  if constexpr (EPI != 0) act = col_active(K, col, j);
-  if (act) {
-    const int Vs = g.lx * g.ly * g.lz, xyz = x + g.lx * (y + g.ly * z);
-    const int sy = g.lx, sz = g.lx * g.ly;
-    const int xf = x == g.lx - 1 ? -(g.lx - 1) : 1, xb = x == 0 ? g.lx - 1 : -1;
-    const int yf = y == g.ly - 1 ? -(g.ly - 1) * sy : sy, yb = y == 0 ? (g.ly - 1) * sy : -sy;
-    const int zf = z == g.lz - 1 ? -(g.lz - 1) * sz : sz, zb = z == 0 ? (g.lz - 1) * sz : -sz;
-    const S *inc = in + col;
-    auto xyz_hops = [&](cx<R> (&acc)[12], int s) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-      hop_dir<2, SF, S, KC, true>(acc, inc, U, g.V, s, s + zf, s + zb);
-      hop_dir<0, SF, S, KC, true>(acc, inc, U, g.V, s, s + xf, s + xb);
-      hop_dir<1, SF, S, KC, true>(acc, inc, U, g.V, s, s + yf, s + yb);
-    };
-    const int t0 = chunk * m.tc, t1 = t0 + m.tc;
-    cx<R> cen[12], acc[12], carry[6];
-    {
-      const int s = xyz + Vs * t0, sp = xyz + Vs * (t0 == 0 ? g.lt - 1 : t0 - 1);
-      load_spinor<S, KC>(cen, inc, g.V, s);
-      cx<R> h[6];
-      load_project<3, -SF, S, KC>(h, inc, g.V, sp);
-      mult_t<true, S>(carry, h, U, g.V, sp);
-      xyz_hops(acc, s);
-    }
-    for (int t = t0; t < t1; ++t) {
-      int s = xyz + Vs * t, sn = xyz + Vs * (t == g.lt - 1 ? 0 : t + 1);
-      // opaque site indices: the addresses are formed from them in each step
-      // instead of being carried across steps in registers
-      asm volatile("" : "+v"(s), "+v"(sn));
-      cx<R> nxt[12];
-      load_spinor<S, KC>(nxt, inc, g.V, sn);
-      {
-        cx<R> h[6], w[6];
-        project_t<SF>(h, nxt);
-        mult_t<false, S>(w, h, U, g.V, s);
-        recon_t<SF>(acc, w);
-        recon_t<-SF>(acc, carry);
-        project_t<-SF>(h, cen);
-        mult_t<true, S>(carry, h, U, g.V, s);
-      }
-      hop_fence();
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const size_t i = (size_t(c) * g.V + s) * KC + col;
-        const cx<R> o = cen[c] - k * acc[c];
-        Store<S>::st(out, i, o);
-        if constexpr (EPI == 1) {
-          const cx<R> hh = Store<S>::ld(rhat, i);
-          d[0] += double(hh.x) * o.x + double(hh.y) * o.y;
-          d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
-        } else if constexpr (EPI == 2) {
-          const cx<R> si = cen[c];
-          d[0] += double(o.x) * si.x + double(o.y) * si.y;
-          d[1] += double(o.x) * si.y - double(o.y) * si.x;
-          d[NV - 1] += double(o.x) * o.x + double(o.y) * o.y;
-        }
-      }
-      if (t + 1 < t1) xyz_hops(acc, sn);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) cen[c] = nxt[c];
-    }
-  }
+  if constexpr (EPI != 0) act = col_active(K, ms.col, j);
+  if (act)
+    march_walk<S, KC, SF>(out, in, U, g, R(kappa), m, ms.x, ms.y, ms.z, ms.col, chunk,
+                          [&](int, size_t i, cx<R> o, cx<R> si) {
+                            if constexpr (EPI == 1) {
+                              const cx<R> hh = Store<S>::ld(rhat, i);
+                              d[0] += double(hh.x) * o.x + double(hh.y) * o.y;
+                              d[1] += double(hh.x) * o.y - double(hh.y) * o.x;
+                            } else if constexpr (EPI == 2) {
+                              d[0] += double(o.x) * si.x + double(o.y) * si.y;
+                              d[1] += double(o.x) * si.y - double(o.y) * si.x;
+                              d[NV - 1] += double(o.x) * o.x + double(o.y) * o.y;
+                            }
+                          });
   if constexpr (EPI != 0) block_partial_cols<NV, KC, kBlock>(d, part, blockIdx.x);
+}
+
+// The BiCG matvec in the t-marching form: Ap = D p with the partials of
+// sigma = (phat, Ap), and Adp = D^+ phat.  Work item w is a unit (box and
+// chunk) of D for even w and the same unit of D^+ for odd w, so the two walk
+// the same slices on the same XCD at the same time and share the link loads
+// in its L2.  G5 (the gamma5-Hermitian form): D units only, sigma =
+// (gamma5 p, Ap) from the input at the site.  One record per block.
+template <bool G5>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2)))
+    k_bicg_matvec_march(double2 *__restrict__ Ap, double2 *__restrict__ Adp, const double2 *__restrict__ p,
+                        const double2 *__restrict__ ph, const double2 *__restrict__ U, Geom g, double kappa, March m,
+                        int j, const KrylovState *S, double *__restrict__ part) {
+  if (skip_iter(S, j)) return;
+  const int bpu = m.rx * m.ry * m.rz / kBlock;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int item = lb / bpu, u = (lb - item * bpu) * kBlock + threadIdx.x;
+  const int unit = G5 ? item : item >> 1;
+  const bool adj = !G5 && (item & 1) != 0;
+  const int nch = g.lt / m.tc, box = unit / nch, chunk = unit - box * nch;
+  const MarchSite ms = march_site<1>(g, m, box, u);
+  double d[2] = {0.0, 0.0};
+  if (!adj) {
+    march_walk<double2, 1, -1>(Ap, p, U, g, kappa, m, ms.x, ms.y, ms.z, 0, chunk,
+                               [&](int c, size_t i, cx<double> o, cx<double> pv) {
+                                 cx<double> dd;
+                                 if constexpr (G5)
+                                   dd = c < 6 ? cmulc(pv, o) : -cmulc(pv, o);
+                                 else
+                                   dd = cmulc(Store<double2>::ld(ph, i), o);
+                                 d[0] += dd.x;
+                                 d[1] += dd.y;
+                               });
+  } else {
+    march_walk<double2, 1, +1>(Adp, ph, U, g, kappa, m, ms.x, ms.y, ms.z, 0, chunk,
+                               [](int, size_t, cx<double>, cx<double>) {});
+  }
+  block_partial<2, kBlock>(d, part, blockIdx.x);
 }
 
 // rhat = p = r; partials of ||r_col||^2
@@ -777,6 +837,19 @@ __global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
 int march_records(const Geom &g, int kc) { return march_blocks(g, kc, march_shape(g, kc)); }
+int bicg_matvec_march_records(const Geom &g, bool g5) { return march_records(g, 1) * (g5 ? 1 : 2); }
+void launch_bicg_matvec_march(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
+                              const Geom &g, double kappa, int j, KrylovState *S, const RedScratch &rs, bool g5,
+                              hipStream_t st) {
+  const March m = march_shape(g, 1);
+  const dim3 grid(bicg_matvec_march_records(g, g5));
+  if (g5)
+    EB_LAUNCH(k_bicg_matvec_march<true>, grid, dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, m, j, S,
+              region(rs, RG_SIGMA));
+  else
+    EB_LAUNCH(k_bicg_matvec_march<false>, grid, dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, m, j, S,
+              region(rs, RG_SIGMA));
+}
 bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc) {
   if (stage < -1 || stage >= kTileForms) return false;
   if (stage < 2) return true;

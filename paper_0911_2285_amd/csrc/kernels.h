@@ -139,11 +139,12 @@ void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const doubl
                         bool g5, hipStream_t st);
 // alpha_{j-1} = rho_{j-1} / sigma; r_out = r_in - alpha Ap; rhat_out = rhat_in - conj(alpha) Adp;
 // partials of rho_j and ||r_j||^2.  w32r / w32rh (may be null): FP32 copies of
-// r_out / rhat_out (the window of an FP32-window eigBiCG).
+// r_out / rhat_out (the window of an FP32-window eigBiCG).  nrec: the sigma
+// records of the matvec (0: those of launch_bicg_matvec).
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
                           const RedScratch &rs, bool g5, hipStream_t st, float2 *w32r = nullptr,
-                          float2 *w32rh = nullptr);
+                          float2 *w32rh = nullptr, int nrec = 0);
 // beta_{j-1}, rho_j, ||r_j|| and the stop test; x += alpha p; p = r + beta p; phat = rhat + conj(beta) phat.
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
                           KrylovState *S, KrylovHistory h, const RedScratch &rs, bool g5, hipStream_t st);
@@ -328,6 +329,13 @@ constexpr int kMarchTile = 6;
 bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc);
 // Records (blocks) of a t-marching pass on kc columns (the form must fit).
 int march_records(const Geom &g, int kc);
+// The BiCG matvec pair (as launch_bicg_matvec) in the t-marching form with one
+// column (full-lattice operator, batch_tile_ok(g, false, kMarchTile, 1)); it
+// writes bicg_matvec_march_records(g, g5) sigma records.
+void launch_bicg_matvec_march(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
+                              const Geom &g, double kappa, int j, KrylovState *S, const RedScratch &rs, bool g5,
+                              hipStream_t st);
+int bicg_matvec_march_records(const Geom &g, bool g5);
 // stage: tile form of the batched stencils (kTileForms above)
 template <typename S>
 void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa, bool dagger, int kc, hipStream_t st,

@@ -722,15 +722,15 @@ void launch_bicg_matvec(double2 *Ap, double2 *Adp, const double2 *p, const doubl
 }
 void launch_bicg_update_r(double2 *r_out, double2 *rh_out, const double2 *r_in, const double2 *rh_in,
                           const double2 *Ap, const double2 *Adp, size_t N, int j, KrylovState *S, KrylovHistory h,
-                          const RedScratch &rs, bool g5, hipStream_t st, float2 *w32r, float2 *w32rh) {
+                          const RedScratch &rs, bool g5, hipStream_t st, float2 *w32r, float2 *w32rh, int nrec) {
   // the matvec wrote one sigma record per block of its grid; N = 12 V
   const int V = int(N / 12);
   if (g5)
     EB_LAUNCH(k_bicg_update_r<true>, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N,
-              j, S, h, region(rs, RG_SIGMA), stencil_grid(V), region(rs, RG_RR), w32r, w32rh);
+              j, S, h, region(rs, RG_SIGMA), nrec > 0 ? nrec : stencil_grid(V), region(rs, RG_RR), w32r, w32rh);
   else
     EB_LAUNCH(k_bicg_update_r<false>, dim3(red_grid(N)), dim3(kBlock), 0, st, r_out, rh_out, r_in, rh_in, Ap, Adp, N,
-              j, S, h, region(rs, RG_SIGMA), matvec_grid(V), region(rs, RG_RR), w32r, w32rh);
+              j, S, h, region(rs, RG_SIGMA), nrec > 0 ? nrec : matvec_grid(V), region(rs, RG_RR), w32r, w32rh);
 }
 void launch_bicg_update_p(double2 *x, double2 *p, double2 *ph, const double2 *r, const double2 *rh, size_t N, int j,
                           KrylovState *S, KrylovHistory h, const RedScratch &rs, bool g5, hipStream_t st) {

@@ -136,6 +136,8 @@ _SIGNATURES = [
     ("eb_op_set_grid_cap", ctypes.c_int, [_P, ctypes.c_int32]),
     ("eb_op_batch_tune", ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_int32), _P, _P]),
     ("eb_op_batch_set_tile", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+    ("eb_op_set_matvec_form", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("eb_op_get_matvec_form", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
     ("eb_last_error", None, [ctypes.c_char_p, ctypes.c_size_t]),
     ("eb_version", ctypes.c_char_p, []),
 ]
@@ -448,6 +450,20 @@ def op_batch_tune(op, prec="fp32", stream=None):
     F = TILE_FORMS
     return {"k": kb.value, "stage": {k: int(stage[i]) for i, k in enumerate(ks)},
             "ms_per_rhs": {k: [float(v) for v in ms[F * i: F * i + F]] for i, k in enumerate(ks)}}
+
+
+def op_set_matvec_form(op, form):
+    """Form of the BiCG matvec pair (eigBiCG, deflated BiCG): 1 LDS-staged tiles, 6
+    t-marching units, -1 time both at the next solve."""
+    _check(lib().eb_op_set_matvec_form(op.handle, int(form)))
+
+
+def op_get_matvec_form(op):
+    """(form in use, {1: ms, 6: ms} measured by the choice)."""
+    f = ctypes.c_int32(0)
+    ms = np.zeros(2, np.float64)
+    _check(lib().eb_op_get_matvec_form(op.handle, ctypes.byref(f), ms.ctypes.data))
+    return f.value, {1: float(ms[0]), 6: float(ms[1])}
 
 
 def op_batch_set_tile(op, prec, k, stage):
