@@ -2153,7 +2153,18 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
                                bo ? bo + c * op->N : nullptr, s);
         tolc[c] = P->tol * scale[c];
       }
-      eb_stats sc = zero_stats();
+      eb_stats sc = zero_stats();  // the group's: the sum (and the worst residuals) of its batches'
+      eb_stats sb = zero_stats();  // the batch in flight
+      auto add_batch = [&]() {
+        sc.iters += sb.iters;
+        sc.matvec_d += sb.matvec_d;
+        sc.matvec_ddag += sb.matvec_ddag;
+        sc.defl_restarts += sb.defl_restarts;
+        sc.outer_steps += sb.outer_steps;
+        sc.rec_rel_resid = std::max(sc.rec_rel_resid, sb.rec_rel_resid);
+        sc.true_rel_resid = std::max(sc.true_rel_resid, sb.true_rel_resid);
+        sb = zero_stats();
+      };
       auto store = [&]() {
         for (int c = 0; c < gsz; ++c)
           store_solution(op, x + c * op->N, bo ? bo + c * op->N : nullptr, xc + c * Ncan, s);
@@ -2171,24 +2182,26 @@ eb_status eb_deflated_bicg_solve(eb_op *op, const void *b_can, void *x_can, cons
           double2 *bb = b + size_t(off) * op->N, *xx = x + size_t(off) * op->N;
           if (kc == 1) {
             if (P->method == 1)
-              deflated_bicg_f64(op, bb, xx, tolc[off], P->maxiter, sc, s);
+              deflated_bicg_f64(op, bb, xx, tolc[off], P->maxiter, sb, s);
             else if (P->inner == EB_FP64)
-              deflated_stab_f64(op, bb, xx, tolc[off], P->deftol, P->maxiter, sc, s);
+              deflated_stab_f64(op, bb, xx, tolc[off], P->deftol, P->maxiter, sb, s);
             else if (P->inner == EB_FP32)
-              mixed_stab<float2>(op, bb, xx, tolc[off], inner_tol, P->maxiter, sc, s);
+              mixed_stab<float2>(op, bb, xx, tolc[off], inner_tol, P->maxiter, sb, s);
             else
-              mixed_stab<bf16c>(op, bb, xx, tolc[off], inner_tol, P->maxiter, sc, s);
+              mixed_stab<bf16c>(op, bb, xx, tolc[off], inner_tol, P->maxiter, sb, s);
           } else if (P->inner == EB_FP64) {
-            mixed_stab_batch<double2>(op, bb, xx, kc, tolc + off, 0.5 * P->tol, P->maxiter, sc, s);
+            mixed_stab_batch<double2>(op, bb, xx, kc, tolc + off, 0.5 * P->tol, P->maxiter, sb, s);
           } else if (P->inner == EB_FP32) {
-            mixed_stab_batch<float2>(op, bb, xx, kc, tolc + off, inner_tol, P->maxiter, sc, s);
+            mixed_stab_batch<float2>(op, bb, xx, kc, tolc + off, inner_tol, P->maxiter, sb, s);
           } else {
-            mixed_stab_batch<bf16c>(op, bb, xx, kc, tolc + off, inner_tol, P->maxiter, sc, s);
+            mixed_stab_batch<bf16c>(op, bb, xx, kc, tolc + off, inner_tol, P->maxiter, sb, s);
           }
+          add_batch();
           off += kc;
         }
       } catch (...) {
         // x holds the last iterate and the stats are filled
+        add_batch();
         store();
         (void)hipStreamSynchronize(s);
         merge(sc);

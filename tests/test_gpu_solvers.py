@@ -183,6 +183,33 @@ def test_batched_deflated_solves(gpu_lib, cfg0, space8, inner, batch):
     assert st["iters"] <= 1.5 * st1["iters"] + 8
 
 
+@pytest.mark.parametrize("inner", ["fp32", "fp64"])
+def test_group_stats_sum_over_batches(gpu_lib, cfg0, inner):
+    """One call on 6 sources in batches of 2 (one group of columns) reports the sums of
+    iterations and refinement steps and the worst residual of three separate calls on
+    2 sources each (no deflation space, so the batches are the same solves)."""
+    import torch
+
+    dims, kappa, U = cfg0
+    V = synth.volume(dims)
+    op = gpu_lib.op_create(U, kappa, dims)
+    B = torch.from_numpy(np.stack([synth.z2_source(V, synth.rhs_seed(0, 60 + c)) for c in range(6)])).to("cuda:0")
+    X = torch.zeros_like(B)
+    st = gpu_lib.deflated_bicg_solve(op, B, X, tol=1e-10, inner=inner, nrhs=6, batch=2)
+    parts = []
+    for c in range(0, 6, 2):
+        x = torch.zeros_like(B[c:c + 2])
+        parts.append(gpu_lib.deflated_bicg_solve(op, B[c:c + 2].contiguous(), x, tol=1e-10, inner=inner, nrhs=2,
+                                                 batch=2))
+        assert torch.equal(x, X[c:c + 2])
+    gpu_lib.op_destroy(op)
+    print(inner, st, [p["outer_steps"] for p in parts])
+    assert st["iters"] == sum(p["iters"] for p in parts)
+    assert st["outer_steps"] == sum(p["outer_steps"] for p in parts)
+    assert st["true_rel_resid"] == max(p["true_rel_resid"] for p in parts)
+    assert st["matvec_d"] == sum(p["matvec_d"] for p in parts)
+
+
 def test_batched_ragged_and_zero_column(gpu_lib, cfg0, space8):
     """5 right-hand sides with batch 4 (a batch of 4, then one column alone),
     one of them zero, and a non-zero start: the zero column returns x = 0."""
