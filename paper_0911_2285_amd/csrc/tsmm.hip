@@ -1,7 +1,8 @@
 // Tall-skinny complex products.
 //
 //   gram:    out = X^+ Y              X: N x nx, Y: N x ny, out: nx x ny  (FP64 matrix cores)
-//   combine: out = [out +] In C       In: N x nin, C: nin x nout, out: N x nout  (FP64 VALU)
+//   combine: out = [out +] In C       In: N x nin, C: nin x nout, out: N x nout  (FP64 VALU;
+//            rotations into more than 24 columns on the matrix cores, FP32 for FP32 windows)
 //
 // N is the length of a spinor (12 V complex entries) and the other sizes are
 // at most 128, so both products are long contractions into small tiles or
@@ -33,6 +34,12 @@ typedef double dx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ dx4 mfma16(double a, double b, dx4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// FP32: v_mfma_f32_16x16x4f32 (one block) takes A and B as the FP64 form does,
+// but lane l holds D[4 (l / 16) + v][l % 16] in component v (a lane probe).
+typedef float fx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ fx4 mfma16(float a, float b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 constexpr int kTile = 16;                    // MFMA tile edge
@@ -272,9 +279,12 @@ __global__ void __launch_bounds__(kBlock)
 // results for entry i0 + r of outputs q + 4 v (16 consecutive entries per
 // output column in one store).  C^T sits in LDS ([c][k], k fastest), the
 // slot lists too.  A complex product is four real MFMAs into a real and an
-// imaginary tile.  DOTS: the block's partial dots of g with the outputs
-// (g^+ out_k, or out_k^+ g with conj_out), element-major records
-// part[(2 k + {re, im}) gridDim.x + blockIdx.x] for k < 16 OT.
+// imaginary tile.  With FP32 inputs and outputs (the FP32 window) the
+// products and sums run in FP32 on the FP32 matrix instructions (twice the
+// FP64 rate on gfx950); otherwise in FP64.  DOTS: the block's partial dots
+// of g with the outputs (g^+ out_k, or out_k^+ g with conj_out), in FP64,
+// element-major records part[(2 k + {re, im}) gridDim.x + blockIdx.x] for
+// k < 16 OT.
 // ---------------------------------------------------------------------------
 template <typename TI, typename TO, int OT, bool DOTS, bool G5IN>
 __global__ void __launch_bounds__(kBlock)
@@ -283,6 +293,11 @@ __global__ void __launch_bounds__(kBlock)
                   double *__restrict__ part, int jtag, const KrylovState *S) {
   if (S && S->stopped && jtag > S->stop_at) return;
   constexpr int KP = kTile * OT;
+  constexpr bool F32 = std::is_same<TI, float2>::value && std::is_same<TO, float2>::value;
+  using E = typename std::conditional<F32, float, double>::type;  // product and sum type
+  using Acc = typename std::conditional<F32, fx4, dx4>::type;
+  // output row of component v of lane (r, q) in a 16 x 16 tile
+  auto orow = [](int q, int v) { return F32 ? 4 * q + v : q + 4 * v; };
   extern __shared__ double2 cs[];  // C^T: cs[c KP + k]
   __shared__ int islot[kMaxCols], oslot[KP];
   __shared__ double sd[DOTS ? kBlock / kWave : 1][DOTS ? 2 * KP : 1];
@@ -305,12 +320,12 @@ __global__ void __launch_bounds__(kBlock)
   for (size_t ch = size_t(blockIdx.x) * (kBlock / kWave) + w; ch < nch; ch += size_t(gridDim.x) * (kBlock / kWave)) {
     const size_t i = ch * kTile + r;
     const bool in = i < N;
-    dx4 re[OT], im[OT];
+    Acc re[OT], im[OT];
 #pragma unroll
-    for (int t = 0; t < OT; ++t) re[t] = im[t] = dx4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < OT; ++t) re[t] = im[t] = Acc{E(0), E(0), E(0), E(0)};
     for (int c0 = 0; c0 < nin4; c0 += 4) {
       const int c = c0 + q;
-      double br = 0.0, bi = 0.0;
+      E br = E(0), bi = E(0);
       if (c < nin && in) {
         int sc = islot[c];
         bool flip = false;
@@ -319,8 +334,8 @@ __global__ void __launch_bounds__(kBlock)
           if (flip) sc = -sc - 1;
         }
         const TI x = in_base[size_t(sc) * ldi + i];
-        br = double(x.x);
-        bi = double(x.y);
+        br = E(x.x);
+        bi = E(x.y);
         if (flip && i >= half) {
           br = -br;
           bi = -bi;
@@ -329,10 +344,11 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int t = 0; t < OT; ++t) {
         const double2 a = cs[c * KP + kTile * t + r];
-        re[t] = mfma16(a.x, br, re[t]);
-        re[t] = mfma16(-a.y, bi, re[t]);
-        im[t] = mfma16(a.x, bi, im[t]);
-        im[t] = mfma16(a.y, br, im[t]);
+        const E ax = E(a.x), ay = E(a.y);
+        re[t] = mfma16(ax, br, re[t]);
+        re[t] = mfma16(-ay, bi, re[t]);
+        im[t] = mfma16(ax, bi, im[t]);
+        im[t] = mfma16(ay, br, im[t]);
       }
     }
     double2 gv = make_double2(0.0, 0.0);
@@ -341,8 +357,8 @@ __global__ void __launch_bounds__(kBlock)
     for (int t = 0; t < OT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int k = kTile * t + q + 4 * v;
-        const double ox = sgn * re[t][v], oy = sgn * im[t][v];
+        const int k = kTile * t + orow(q, v);
+        const double ox = sgn * double(re[t][v]), oy = sgn * double(im[t][v]);
         if (in && k < nout) {
           TO *oc = out_base + size_t(oslot[k]) * ldo;
           if constexpr (std::is_same<TO, double2>::value)
@@ -373,7 +389,7 @@ __global__ void __launch_bounds__(kBlock)
           dim[t][v] += __shfl_xor(dim[t][v], off, kWave);
         }
         if (r == 0) {
-          const int k = kTile * t + q + 4 * v;
+          const int k = kTile * t + orow(q, v);
           sd[w][2 * k] = dre[t][v];
           sd[w][2 * k + 1] = dim[t][v];
         }

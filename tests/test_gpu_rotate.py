@@ -1,6 +1,7 @@
 """Window rotations into more than 24 columns (2 nev > 24), which run on the matrix
 cores (k_rotate_mfma: the transposed product C^T In^T in 16 x 16 tiles, the
-inputs read once, the arrow dots fused), against the oracle's eigBiCG (Alg.
+inputs read once, the arrow dots fused; FP64 products and sums for the FP64
+window, FP32 for the FP32 window), against the oracle's eigBiCG (Alg.
 eigBiCG with Alg. BiCG-eigen) on 8^4: nev 14 / m 36 (two output tiles),
 20 / 48 (three), 25 / 60 (four: the window of the 32^3 x 64 batching
 workload), FP64 and FP32 windows, host and device restart, and the
@@ -10,8 +11,11 @@ the right window's, the flag the kernel applies on input).
 Bounds: iterations +-1 and equal restart counts; true residual <= 1e-10; the
 nev - 5 Ritz values of smallest modulus within 1e-8 relative for the FP64 window
 (a relative change of 1e-13 in the source moves the oracle's own values by
-2.5e-10 and 1.8e-10 on the 14 / 36 and 25 / 60 configurations), 1e-5 for the
-FP32 window (as in the mixed-precision eigBiCG tests).  The last few values are
+2.5e-10 and 1.8e-10 on the 14 / 36 and 25 / 60 configurations: an
+amplification of ~2e3), 1e-4 for the FP32 window, whose rotations here sum in
+FP32 on the matrix cores: every stored entry and every step of a rotation sum
+is rounded at 2^-24 ~ 6e-8, which that amplification turns into ~1e-4
+(measured: up to 3.1e-5; 1e-5 with FP64 sums).  The last few values are
 the least converged (Ritz residuals up to 0.5 on this lattice), and which value
 appears there depends on rounding: at 25 / 60 the 25th value of one run is
 0.198 + 0.456i where the oracle's is 0.538 + 0.047i while the other 24 agree
@@ -81,7 +85,7 @@ def test_large_window_rotation_matches_oracle(gpu_lib, lat8, nev, m, modes):
               f"Ritz values vs oracle {err:.1e}; each value's distance: " + " ".join(f"{e:.0e}" for e in each))
         assert abs(st["iters"] - orc.iters) <= 1 and st["window_restarts"] == len(orc.restarts) >= 2
         assert tr <= 1e-10
-        assert err < (1e-8 if window == "fp64" else 1e-5)
+        assert err < (1e-8 if window == "fp64" else 1e-4)
 
 
 def test_large_window_rotation_gamma5_form(gpu_lib, lat8):
