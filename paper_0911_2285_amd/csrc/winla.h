@@ -231,8 +231,6 @@ __device__ __forceinline__ void win_givens_fast(wcx x, wcx y, double &c, wcx &s)
 __device__ __forceinline__ void win_sweep_lanes(double2 *T, double2 *Z, int n, int ld, int l, int ihi, wcx mu) {
   const int j = threadIdx.x;
   const bool own = j < n;
-  double *cs_c = &win_lds.lm[0].x;  // free during the Schur iteration: c_k at stride 2
-  double2 *cs_s = win_lds.vec;      // s_k
   // uniform: ua0 = T(k,k), ua1 = T(k,k+1), ub0 = T(k+1,k), ub1 = T(k+1,k+1), current
   wcx ua0 = ld2(T + l + l * ld), ua1 = ld2(T + l + (l + 1) * ld);
   wcx ub0 = ld2(T + (l + 1) + l * ld), ub1 = ld2(T + (l + 1) + (l + 1) * ld);
@@ -242,6 +240,8 @@ __device__ __forceinline__ void win_sweep_lanes(double2 *T, double2 *Z, int n, i
     bnx = ld2(T + (l + 1) + j * ld);
   }
   wcx x = ua0 - mu, y = ub0;
+  double rc = 1.0;  // this lane's rotation of the sweep (lane i: rotation l + i)
+  wcx rs = {0.0, 0.0};
   for (int k = l; k < ihi; ++k) {
     const bool more = k + 2 <= ihi;
     // original entries of row k+2 (F = T(k+2,k+1), G = T(k+2,k+2), lanes: T(k+2, j))
@@ -265,9 +265,11 @@ __device__ __forceinline__ void win_sweep_lanes(double2 *T, double2 *Z, int n, i
     }
     // column rotation k on rows k, k+1 and k+2 of columns k, k+1
     const wcx xn = c * C + D * sc, dn = c * D - C * s;
+    if (j == k - l) {  // rotation k - l of the sweep, kept by lane k - l
+      rc = c;
+      rs = s;
+    }
     if (j == 0) {
-      cs_c[2 * (k - l)] = c;
-      st2(cs_s + (k - l), s);
       if (k > l) {  // the bulge column k-1: T(k,k-1) final, T(k+1,k-1) = 0
         st2(T + k + (k - 1) * ld, c * x + s * y);
         st2(T + (k + 1) + (k - 1) * ld, wcx{0.0, 0.0});
@@ -292,29 +294,39 @@ __device__ __forceinline__ void win_sweep_lanes(double2 *T, double2 *Z, int n, i
   if (own && j > ihi) st2(T + ihi + j * ld, cur);
   __syncthreads();
   // deferred column rotations: rows i < k of columns k, k+1 for every k (T),
-  // and every row of Z; each step's operands are read one step ahead
+  // and every row of Z.  The rotations come from the lanes that kept them
+  // (readlane); the row entries are read four steps at a time ahead of use
+  // (each is the value from before the pass: step k reads column k + 1 and
+  // writes column k).
   const int k0 = l > j + 1 ? l : j + 1;
   const bool tdo = j <= ihi && k0 < ihi;
   if (own) {
     wcx tc = tdo ? ld2(T + j + k0 * ld) : wcx{0.0, 0.0};
     wcx zc = ld2(Z + j + l * ld);
-    double cn = cs_c[0];
-    wcx sn = ld2(cs_s), zbn = ld2(Z + j + (l + 1) * ld);
-    wcx tbn = tdo && l >= k0 ? ld2(T + j + (l + 1) * ld) : wcx{0.0, 0.0};
-    for (int k = l; k < ihi; ++k) {
-      const double c = cn;
-      const wcx s = sn, sc = cconj(s), zb = zbn, tb = tbn;
-      if (k + 1 < ihi) {
-        cn = cs_c[2 * (k + 1 - l)];
-        sn = ld2(cs_s + (k + 1 - l));
-        zbn = ld2(Z + j + (k + 2) * ld);
-        if (tdo && k + 1 >= k0) tbn = ld2(T + j + (k + 2) * ld);
+    for (int kb = l; kb < ihi; kb += 4) {
+      wcx zb[4], tb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = kb + u;
+        zb[u] = tb[u] = wcx{0.0, 0.0};
+        if (k < ihi) {
+          zb[u] = ld2(Z + j + (k + 1) * ld);
+          if (tdo && k >= k0) tb[u] = ld2(T + j + (k + 1) * ld);
+        }
       }
-      st2(Z + j + k * ld, c * zc + zb * sc);
-      zc = c * zb - zc * s;
-      if (tdo && k >= k0) {
-        st2(T + j + k * ld, c * tc + tb * sc);
-        tc = c * tb - tc * s;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = kb + u;
+        if (k < ihi) {
+          const double c = win_readlane(rc, k - l);
+          const wcx s = win_readlane(rs, k - l), sc = cconj(s);
+          st2(Z + j + k * ld, c * zc + zb[u] * sc);
+          zc = c * zb[u] - zc * s;
+          if (tdo && k >= k0) {
+            st2(T + j + k * ld, c * tc + tb[u] * sc);
+            tc = c * tb[u] - tc * s;
+          }
+        }
       }
     }
     st2(Z + j + ihi * ld, zc);
