@@ -186,12 +186,16 @@ inline int stencil_records(const Geom &g, int kc, int nv, int stage) {
 // One thread's walk of the t-marching form: site (x, y, z) of its box, column
 // col, through the slices of chunk `chunk`: out = in - kappa hop at every
 // slice, and epi(c, i, o, in_c) for each of the 12 components (i the entry's
-// index, o the output, in_c the input at the site).
+// index, o the output, in_c the input at the site).  FP64: the spinor of the
+// current slice waits in the block's LDS (cbuf: [12][kBlock], each thread its
+// own column) instead of registers, which keeps the walk's live state within
+// the registers of two waves per SIMD.
 template <typename S, int KC, int SF, typename Epi>
 __device__ __forceinline__ void march_walk(S *__restrict__ out, const S *__restrict__ in, const S *__restrict__ U,
                                            const Geom &g, typename Store<S>::R k, const March &m, int x, int y, int z,
-                                           int col, int chunk, Epi &&epi) {
+                                           int col, int chunk, double2 *cbuf, Epi &&epi) {
   using R = typename Store<S>::R;
+  constexpr bool kL = std::is_same<R, double>::value;
   const int Vs = g.lx * g.ly * g.lz, xyz = x + g.lx * (y + g.ly * z);
   const int sy = g.lx, sz = g.lx * g.ly;
   const int xf = x == g.lx - 1 ? -(g.lx - 1) : 1, xb = x == 0 ? g.lx - 1 : -1;
@@ -205,11 +209,32 @@ __device__ __forceinline__ void march_walk(S *__restrict__ out, const S *__restr
     hop_dir<0, SF, S, KC, true>(acc, inc, U, g.V, s, s + xf, s + xb);
     hop_dir<1, SF, S, KC, true>(acc, inc, U, g.V, s, s + yf, s + yb);
   };
+  // the current slice's spinor: registers (FP32, BF16) or the LDS column (FP64)
+  cx<R> creg[kL ? 1 : 12];
+  auto cen = [&](int c) -> cx<R> {
+    if constexpr (kL) {
+      const double2 v = cbuf[c * kBlock + threadIdx.x];
+      return {v.x, v.y};
+    } else {
+      return creg[c];
+    }
+  };
+  auto set_cen = [&](const cx<R> (&p)[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      if constexpr (kL)
+        cbuf[c * kBlock + threadIdx.x] = make_double2(p[c].x, p[c].y);
+      else
+        creg[c] = p[c];
+    }
+  };
   const int t0 = chunk * m.tc, t1 = t0 + m.tc;
-  cx<R> cen[12], acc[12], carry[6];
+  cx<R> acc[12], carry[6];
   {
     const int s = xyz + Vs * t0, sp = xyz + Vs * (t0 == 0 ? g.lt - 1 : t0 - 1);
-    load_spinor<S, KC>(cen, inc, g.V, s);
+    cx<R> c0[12];
+    load_spinor<S, KC>(c0, inc, g.V, s);
+    set_cen(c0);
     cx<R> h[6];
     load_project<3, -SF, S, KC>(h, inc, g.V, sp);
     mult_t<true, S>(carry, h, U, g.V, sp);
@@ -228,20 +253,24 @@ __device__ __forceinline__ void march_walk(S *__restrict__ out, const S *__restr
       mult_t<false, S>(w, h, U, g.V, s);
       recon_t<SF>(acc, w);
       recon_t<-SF>(acc, carry);
-      project_t<-SF>(h, cen);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {  // the t projector (1 - SF gamma_t) of the current slice
+        h[a] = cen(a) + sgn<-SF>(cen(6 + a));
+        h[3 + a] = cen(3 + a) + sgn<-SF>(cen(9 + a));
+      }
       mult_t<true, S>(carry, h, U, g.V, s);
     }
     hop_fence();
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       const size_t i = (size_t(c) * g.V + s) * KC + col;
-      const cx<R> o = cen[c] - k * acc[c];
+      const cx<R> ci = cen(c);
+      const cx<R> o = ci - k * acc[c];
       Store<S>::st(out, i, o);
-      epi(c, i, o, cen[c]);
+      epi(c, i, o, ci);
     }
+    set_cen(nxt);
     if (t + 1 < t1) xyz_hops(acc, sn);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) cen[c] = nxt[c];
   }
 }
 
@@ -276,8 +305,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
   for (int i = 0; i < NV; ++i) d[i] = 0.0;
   bool act = true;
   if constexpr (EPI != 0) act = col_active(K, ms.col, j);
+  __shared__ double2 cbuf[std::is_same<R, double>::value ? 12 * kBlock : 1];
   if (act)
-    march_walk<S, KC, SF>(out, in, U, g, R(kappa), m, ms.x, ms.y, ms.z, ms.col, chunk,
+    march_walk<S, KC, SF>(out, in, U, g, R(kappa), m, ms.x, ms.y, ms.z, ms.col, chunk, cbuf,
                           [&](int, size_t i, cx<R> o, cx<R> si) {
                             if constexpr (EPI == 1) {
                               const cx<R> hh = Store<S>::ld(rhat, i);
@@ -312,8 +342,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
   const int nch = g.lt / m.tc, box = unit / nch, chunk = unit - box * nch;
   const MarchSite ms = march_site<1>(g, m, box, u);
   double d[2] = {0.0, 0.0};
+  __shared__ double2 cbuf[12 * kBlock];
   if (!adj) {
-    march_walk<double2, 1, -1>(Ap, p, U, g, kappa, m, ms.x, ms.y, ms.z, 0, chunk,
+    march_walk<double2, 1, -1>(Ap, p, U, g, kappa, m, ms.x, ms.y, ms.z, 0, chunk, cbuf,
                                [&](int c, size_t i, cx<double> o, cx<double> pv) {
                                  cx<double> dd;
                                  if constexpr (G5)
@@ -324,7 +355,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                                  d[1] += dd.y;
                                });
   } else {
-    march_walk<double2, 1, +1>(Adp, ph, U, g, kappa, m, ms.x, ms.y, ms.z, 0, chunk,
+    march_walk<double2, 1, +1>(Adp, ph, U, g, kappa, m, ms.x, ms.y, ms.z, 0, chunk, cbuf,
                                [](int, size_t, cx<double>, cx<double>) {});
   }
   block_partial<2, kBlock>(d, part, blockIdx.x);
