@@ -347,7 +347,7 @@ eb_status eb_session_info(eb_session *s, int32_t *free_slots, int32_t *busy, int
  * global memory in site order with the loads of several hops in flight
  * (full-lattice stencil only); 6 walks boxes of sites (up to 32 x 16 x 8, 16 x
  * 16 x 8 for k = 16, 32 x 32 x 8 for k = 1) through chunks of time slices with
- * the t neighbours held in registers (full-lattice stencil only, a box of a
+ * the t neighbours held by each thread (full-lattice stencil only, a box of a
  * whole number of 256-thread blocks for k).  eb_op_batch_tune runs the
  * autotuner once per operator and precision (it times every form the
  * operator admits for k = 2, 4, 8, 16, and for k = 1 the two forms of the

@@ -138,10 +138,11 @@ __global__ void __launch_bounds__(kBlock)
 // A unit of work is a box of rx x ry x rz sites (x fastest) times a chunk of
 // tc consecutive time slices.  Its threads, one per (site of the box,
 // column) with the columns fastest, walk the chunk in t.  A thread keeps its
-// site's spinor at the current and the next slice in registers, so the t
-// hops read no neighbour: the forward hop projects the next slice, and the
-// backward hop of slice t + 1 (U_t^+ times the projection of slice t) is
-// formed while slice t is in registers and carried to the next step.  The
+// site's spinor at the current and the next slice at hand (registers; the
+// current one in the block's LDS for FP64), so the t hops read no
+// neighbour: the forward hop projects the next slice, and the backward hop
+// of slice t + 1 (U_t^+ times the projection of slice t) is formed while
+// slice t is at hand and carried to the next step.  The
 // x, y, z neighbours come from global memory; the threads of one box step
 // through the same slices together, so those reads hit the slices the box
 // itself has just loaded into L2 and only the box's faces come from beyond
