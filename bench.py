@@ -1135,7 +1135,8 @@ def headline_batch(eb, W, U, args):
     setup["device_bytes_after_growth"] = eb.op_device_bytes(op)
     eb.op_trim(op)  # the eigBiCG windows and absorb buffers
     setup["device_bytes_trimmed"] = eb.op_device_bytes(op)
-    setup["autotune_seconds"] = tune_untimed(eb, op, (W["inner"], "bf16"))
+    # (FP64 too: its k = 1 entry is the stencil form of the one-at-a-time FP64 comparator)
+    setup["autotune_seconds"] = tune_untimed(eb, op, (W["inner"], "bf16", "fp64"))
     tune = {p: eb.op_batch_tune(op, p) for p in (W["inner"], "bf16")}
     setup["autotune"] = tune
     k = tune[W["inner"]]["k"]
@@ -1215,6 +1216,7 @@ def headline_batch(eb, W, U, args):
     run("fp64_bicgstab_deflated", op, nc, batch=1)
     eb.op_trim(op)  # the batch buffers (reallocated on use): room for an FP64 window at this size
     op2 = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=0)  # no deflation space
+    tune_untimed(eb, op2, (W["inner"], "fp64"))  # as for op: the tuning is setup, not part of a solve
     # eigBiCG at this size with the FP64 window and host restarts against the device
     # restart and the FP32 window (no space to absorb into: the solves alone)
     head["eigbicg_modes"] = None
@@ -1384,7 +1386,8 @@ def main():
         },
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "dslash_GBps": head["roofline"]["achieved"] if head["roofline"] else None,
+        # the batched solve's dslash: the v stencil pass (D on k columns with its dots)
+        "dslash_GBps": head["kernels"]["batched"].get("bstab_v", {}).get("achieved_GBps"),
         "p50_ms": round(1e3 * percentile(lat, 50), 3),
         "p99_ms": round(1e3 * percentile(lat, 99), 3),
         "latency_note": "p50/p99 of the step (16 solves in one batched call, all finishing together); per-request "
