@@ -154,6 +154,44 @@ def test_dslash_24x64_sampled(gpu_lib, lattice_24x64):
         assert err <= 1e-12, err
 
 
+def _boundary_sites(dims, n=32, seed=0):
+    """Sites on the t slices where chunks of 8, 16 and 32 slices meet and on the
+    z planes where boxes of 8 meet, at random x, y; then random sites."""
+    lx, ly, lz, lt = dims
+    rng = np.random.default_rng(seed)
+    ts = sorted({t % lt for c in (8, 16, 32) for t in range(0, lt, c) for t in (t - 1, t)})
+    zs = sorted({z % lz for z in range(0, lz, 8) for z in (z - 1, z)})
+    fixed = [W.site_index(int(rng.integers(lx)), int(rng.integers(ly)), z, t, dims) for t in ts for z in zs]
+    return np.concatenate([fixed, rng.integers(0, synth.volume(dims), n)])
+
+
+def _one_column_march_fp64(gpu_lib, op, U, dims, kappa, seed):
+    """FP64 D and D^+ with one column in the t-marching form (16-slice chunks at
+    24^3 x 64, 32-slice chunks at 32^3 x 64) and in the LDS-staged form, at the
+    chunk- and box-boundary sites, against the per-site oracle (1e-12)."""
+    import torch
+
+    V = synth.volume(dims)
+    psi = synth.gaussian_spinor(V, seed)
+    x = torch.from_numpy(psi).to("cuda:0")
+    sites = _boundary_sites(dims, seed=seed)
+    for dag in (False, True):
+        ref = W.apply_D_sites(U, psi, kappa, dims, sites, dagger=dag)
+        for stage in (6, 1):
+            gpu_lib.op_batch_set_tile(op, "fp64", 1, stage)
+            y = torch.empty_like(x)
+            gpu_lib.op_apply_block(op, y, x, 1, dagger=dag)
+            err = np.abs(y.cpu().numpy()[sites] - ref).max() / np.abs(ref).max()
+            print(f"{dims} one column FP64 form {stage} dagger={dag}: {len(sites)} sites, max rel err {err:.2e}")
+            assert err <= 1e-12, (stage, dag, err)
+    gpu_lib.op_batch_set_tile(op, "fp64", 1, -1)
+
+
+def test_one_column_march_fp64_24x64_sampled(gpu_lib, lattice_24x64):
+    dims, kappa, U, op = lattice_24x64
+    _one_column_march_fp64(gpu_lib, op, U, dims, kappa, 13)
+
+
 def test_dslash_block_24x64_sampled(gpu_lib, lattice_24x64):
     """FP32 multi-RHS stencil (k = 4) on 24^3 x 64: every column at sampled sites
     against the oracle on the rounded inputs; timing of the block stencil class."""
@@ -358,7 +396,8 @@ def test_dslash_block_32x64_sampled(gpu_lib):
     """32^3 x 64 (the batching lattice), FP32 storage, k = 16 columns: the
     8x8x8x8 bricks, form 0, the unfenced form and the t-marching boxes, at sampled
     sites of every column against the per-site oracle on the rounded input
-    (FP32 rounding bound 5e-7 of the largest entry)."""
+    (FP32 rounding bound 5e-7 of the largest entry); then FP64 with one column
+    in the t-marching and the staged form at the chunk and box boundaries."""
     import torch
 
     dims, kappa = (32, 32, 32, 64), 0.123
@@ -380,4 +419,6 @@ def test_dslash_block_32x64_sampled(gpu_lib):
         err = max(np.abs(got[c][sites] - refs[c]).max() for c in range(k)) / scale
         print(f"32^3 x 64, tile form {stage}: {err:.2e}")
         assert err <= 5e-7, (stage, err)
+    del x, y
+    _one_column_march_fp64(gpu_lib, op, U, dims, kappa, 14)
     gpu_lib.op_destroy(op)
