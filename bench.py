@@ -46,6 +46,7 @@ KERNEL_UNITS = {
     "stab_xr": 7,        # in x, p, s, t, rhat; out x, r
     "stab_p": 4,         # in r, p, v; out p
     "residual": 6,       # in x, b; out r; links
+    "dslash1_march": 5,  # D on one FP64 column in the t-marching form: in; out; links
 }
 
 WORKLOADS = {
@@ -224,7 +225,7 @@ def kernel_source_hash(cls="bicg_matvec"):
     import hashlib
 
     h = hashlib.sha256()
-    for f in (BATCH_SOURCES if cls.startswith("bstab") else KERNEL_SOURCES):
+    for f in (BATCH_SOURCES if cls.startswith("bstab") or cls == "dslash1_march" else KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_0911_2285_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -478,7 +479,8 @@ def proj_pass(dims=(16, 16, 16, 32), kappa=0.122, n1=8, nev=10, m=40, nrhs=16):
 def pmc_pass(workload):
     """One pass of the workload's roofline kernel, then a plain device copy of
     COPY_BYTES for the counter calibration: for the incremental workloads one
-    eigBiCG solve (its BiCG matvec launches), for batch32x64 batched
+    eigBiCG solve (its BiCG matvec launches) and three applications of D to one
+    FP64 column in the t-marching form, for batch32x64 batched
     mixed-precision solves of the 16 sources at k = 2, 4, 8 and 16, each k in
     its tuned tile form (no deflation space, which does not change the passes)."""
     import torch
@@ -512,8 +514,14 @@ def pmc_pass(workload):
     V = synth.volume(dims)
     U = synth.random_su3_links(dims, 0.3, synth.gauge_seed(W["cfg"]))
     op = eb.op_create(U, W["kappa"], dims, bc_t=-1, defl_capacity=W["nev"])
+    eb.op_set_matvec_form(op, 1)  # the staged pair, whatever a timing under the profiler would pick
     b = torch.from_numpy(synth.z2_source(V, synth.rhs_seed(0, 0))).to("cuda:0")
     eb.eigbicg_solve(op, b, torch.zeros_like(b), nev=W["nev"], m=W["m"], tol=W["tol"])
+    # D on one FP64 column in the t-marching form (the one-at-a-time solver's stencil)
+    eb.op_batch_set_tile(op, "fp64", 1, 6)
+    y = torch.empty_like(b)
+    for _ in range(3):
+        eb.op_apply_block(op, y, b, 1)
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -607,8 +615,13 @@ def summarize_pmc(fetch_csv, write_csv, workload, kernel="k_bicg_matvec", cls="b
                               "expected_write_kib": V * 12 * writes * kc * cb / 1024.0}
         out["per_k"] = per_k
     else:
-        # the general form's launches (the template's gamma5 instance is another kernel)
-        is_kernel = lambda n: kernel + "(" in n or kernel + "<false>(" in n
+        # the general form's launches (the template's gamma5 instance is another kernel);
+        # the one-column march: k_bmarch<double2, 1, -1, 0> (FP64, one column, D, no epilogue)
+        def is_kernel(n):
+            if cls == "dslash1_march":
+                a = _template_args(n, kernel)
+                return a is not None and "double" in a[0] and a[1:] == ["1", "-1", "0"]
+            return kernel + "(" in n or kernel + "<false>(" in n
         fv = [float(r["Counter_Value"]) for r in rows_of(fetch_csv, "FETCH_SIZE") if is_kernel(r["Kernel_Name"])]
         wv = [float(r["Counter_Value"]) for r in rows_of(write_csv, "WRITE_SIZE") if is_kernel(r["Kernel_Name"])]
         f_k, w_k = sum(fv) / len(fv), sum(wv) / len(wv)
@@ -1279,6 +1292,8 @@ def main():
                 summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, kernel=kern, cls=cls)
         else:
             summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
+            summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, kernel="k_bmarch",
+                          cls="dslash1_march")
         return
     if args.summarize_gap:
         h, d, name, cmd = args.summarize_gap

@@ -504,7 +504,7 @@ StabResult run_bicgstab(eb_op *op, const S *U, S *x, S *r, double tol_abs, doubl
   KrylovState *K = op->S();
   KrylovHistory h = op->history(maxiter + 4);
   const int form = single_stab_form<S>(op, U, r, v, s);
-  const int nrec = form == kMarchTile ? march_records(op->g, 1, int(sizeof(S))) : 0;
+  const int nrec = form == kMarchTile ? march_records(op->g, 1) : 0;
   launch_stab_init<S>(rhat, p, r, N, tol_abs, def_thr, maxiter, K, h, op->rs(), s);
   KrylovState hs;
   fetch_state(op, s, hs);

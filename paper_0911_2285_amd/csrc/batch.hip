@@ -158,39 +158,30 @@ inline int divisor_below(int n, int cap) {
     if (n % d == 0) return d;
   return 1;
 }
-// Box and chunk for k columns of cbytes-byte complex entries.  The box caps
-// are the fastest measured on MI355X at 32^3 x 64 (FP32): 16 x 16 x 8 sites
-// for k = 16, 32 x 16 x 8 for k = 2 .. 8, 32 x 32 x 8 for one column; each
-// extent is the largest divisor of the lattice extent within its cap.  A box
-// must hold a whole number of blocks; chunks are cut from the full t extent
-// until the launch has at least `target` blocks, but no shorter than 8
-// slices: a chunk re-reads the slice before it, and at 24^3 x 64 (FP64, one
-// column) 8-slice chunks on 432 blocks beat 4-slice chunks on 864 (264
-// against 286 us).  The target is 512 blocks (two per CU), except for one
-// FP64 column, where fewer, longer chunks keep fewer slices of the same XCD
-// in flight in its L2 and 192 (three quarters of the CUs) is enough: 16-slice
-// chunks at 24^3 x 64 (216 blocks) 227-239 against 253-255 us for 8-slice
-// ones, 32-slice chunks at 32^3 x 64 (256 blocks) 492 against 510-530 us;
-// halving the blocks again (108 at 24^3 x 64) costs 50 %, and FP32 gains
-// nothing (146 against 147-154 us).  The matvec pair runs two walks per box
-// and chunk and keeps the 512 target (`pair`).  The records of the reducing
-// variants (three per column and block) must fit one region.
-inline March march_shape(const Geom &g, int kc, int cbytes, bool pair = false) {
+// Box and chunk for k columns.  The box caps are the fastest measured on
+// MI355X at 32^3 x 64 (FP32): 16 x 16 x 8 sites for k = 16, 32 x 16 x 8 for
+// k = 2 .. 8, 32 x 32 x 8 for one column; each extent is the largest divisor
+// of the lattice extent within its cap.  A box must hold a whole number of
+// blocks; chunks are cut from the full t extent until the launch has at least
+// 512 blocks (two per CU), but no shorter than 8 slices: a chunk re-reads the
+// slice before it, and at 24^3 x 64 (FP64, one column) 8-slice chunks on 432
+// blocks beat 4-slice chunks on 864 (264 against 286 us).  The records of the
+// reducing variants (three per column and block) must fit one region.
+inline March march_shape(const Geom &g, int kc) {
   const int cy = kc == 1 ? 32 : 16, cx = kc >= 16 ? 16 : 32;
   March m{divisor_below(g.lx, cx), divisor_below(g.ly, cy), divisor_below(g.lz, 8), g.lt};
   const long long box = (long long)m.rx * m.ry * m.rz;
   if ((box * kc) % kBlock != 0) return March{};
   auto blocks = [&](int tc) { return (long long)g.V / tc * kc / kBlock; };
-  const long long target = kc == 1 && cbytes == 16 && !pair ? 192 : 512;
-  while (m.tc % 2 == 0 && m.tc > 8 && blocks(m.tc) < target) m.tc /= 2;
+  while (m.tc % 2 == 0 && m.tc > 8 && blocks(m.tc) < 512) m.tc /= 2;
   if (blocks(m.tc) * kc * 3 > (long long)kRegion) return March{};
   return m;
 }
 inline int march_blocks(const Geom &g, int kc, const March &m) { return int((long long)g.V / m.tc * kc / kBlock); }
 // Records (blocks) a batched stencil pass of tile form `stage` writes with nv
 // partials per column: what its consumer sums.
-inline int stencil_records(const Geom &g, int kc, int cbytes, int nv, int stage) {
-  return stage == kMarchForm ? march_blocks(g, kc, march_shape(g, kc, cbytes)) : batch_stencil_grid(g.V, kc, nv);
+inline int stencil_records(const Geom &g, int kc, int nv, int stage) {
+  return stage == kMarchForm ? march_blocks(g, kc, march_shape(g, kc)) : batch_stencil_grid(g.V, kc, nv);
 }
 
 // One thread's walk of the t-marching form: site (x, y, z) of its box, column
@@ -877,14 +868,12 @@ __global__ void k_batch_rebase(KrylovState *K, KrylovHistory h, int jl) {
 }  // namespace
 
 bool batch_size_ok(int kc) { return kc == 1 || kc == 2 || kc == 4 || kc == 8 || kc == 16; }
-int march_records(const Geom &g, int kc, int cbytes) { return march_blocks(g, kc, march_shape(g, kc, cbytes)); }
-int bicg_matvec_march_records(const Geom &g, bool g5) {
-  return march_blocks(g, 1, march_shape(g, 1, 16, true)) * (g5 ? 1 : 2);
-}
+int march_records(const Geom &g, int kc) { return march_blocks(g, kc, march_shape(g, kc)); }
+int bicg_matvec_march_records(const Geom &g, bool g5) { return march_records(g, 1) * (g5 ? 1 : 2); }
 void launch_bicg_matvec_march(double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, const double2 *U,
                               const Geom &g, double kappa, int j, KrylovState *S, const RedScratch &rs, bool g5,
                               hipStream_t st) {
-  const March m = march_shape(g, 1, 16, true);
+  const March m = march_shape(g, 1);
   const dim3 grid(bicg_matvec_march_records(g, g5));
   if (g5)
     EB_LAUNCH(k_bicg_matvec_march<true>, grid, dim3(kBlock), 0, st, Ap, Adp, p, ph, U, g, kappa, m, j, S,
@@ -897,7 +886,7 @@ bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc) {
   if (stage < -1 || stage >= kTileForms) return false;
   if (stage < 2) return true;
   if (stage == 5) return !eo;
-  if (stage == kMarchForm) return !eo && march_shape(g, kc, 8).rx > 0;  // the box does not depend on the precision
+  if (stage == kMarchForm) return !eo && march_shape(g, kc).rx > 0;
   const Brick b = brick_of(stage);  // bricked forms: full-lattice stencil, extents divisible by the brick
   return !eo && g.lx % b.bx == 0 && g.ly % b.by == 0 && g.lz % b.bz == 0 && g.lt % b.bt == 0;
 }
@@ -908,7 +897,7 @@ void launch_bdslash(S *out, const S *in, const S *U, const Geom &g, double kappa
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     if (stage == kMarchForm) {
-      const March m = march_shape(g, KC, int(sizeof(S)));
+      const March m = march_shape(g, KC);
       const dim3 grid(march_blocks(g, KC, m));
       if (dagger)
         EB_LAUNCH((k_bmarch<S, KC, +1, 0>), grid, dim3(kBlock), 0, st, out, in, U, g, kappa, m, nullptr, 0, nullptr,
@@ -948,7 +937,7 @@ void launch_bstab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, 
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     if (stage == kMarchForm) {
-      const March m = march_shape(g, KC, int(sizeof(S)));
+      const March m = march_shape(g, KC);
       EB_LAUNCH((k_bmarch<S, KC, -1, 1>), dim3(march_blocks(g, KC, m)), dim3(kBlock), 0, st, v, p, U, g, kappa, m,
                 rhat, j, K, region(rs, RG_V));
       return;
@@ -966,7 +955,7 @@ void launch_bstab_s(S *sv, const S *r, const S *v, const Geom &g, int j, int kc,
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    const int nblk = stencil_records(g, KC, int(sizeof(S)), 2, stage);
+    const int nblk = stencil_records(g, KC, 2, stage);
     if (fuse_finish(nblk, 2, KC)) {
       EB_LAUNCH((k_bstab_s_f<S, KC>), dim3(stream_grid(n)), dim3(kBlock), 0, st, sv, r, v, n, j, K, h,
                 region(rs, RG_V), nblk);
@@ -983,7 +972,7 @@ void launch_bstab_t(S *t, const S *sv, const S *U, const Geom &g, double kappa, 
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     if (stage == kMarchForm) {
-      const March m = march_shape(g, KC, int(sizeof(S)));
+      const March m = march_shape(g, KC);
       EB_LAUNCH((k_bmarch<S, KC, -1, 2>), dim3(march_blocks(g, KC, m)), dim3(kBlock), 0, st, t, sv, U, g, kappa, m,
                 nullptr, j, K, region(rs, RG_T));
       return;
@@ -1001,7 +990,7 @@ void launch_bstab_xr(S *x, S *r, const S *p, const S *sv, const S *t, const S *r
   dispatch_kc(kc, [&](auto kt) {
     constexpr int KC = decltype(kt)::value;
     const size_t n = size_t(12) * g.V * KC;
-    const int nblk = stencil_records(g, KC, int(sizeof(S)), 3, stage);
+    const int nblk = stencil_records(g, KC, 3, stage);
     if (fuse_finish(nblk, 3, KC)) {
       EB_LAUNCH((k_bstab_xr_f<S, KC>), dim3(batch_red_grid(n, KC, 3)), dim3(kBlock), 0, st, x, r, p, sv, t, rhat, n,
                 j, K, h, region(rs, RG_T), nblk, region(rs, RG_XR));

@@ -263,7 +263,7 @@ template <typename S>
 void launch_stab_v(S *v, const S *p, const S *rhat, const S *U, const Geom &g, double kappa, int j, KrylovState *K,
                    KrylovHistory h, const RedScratch &rs, hipStream_t st);
 // alpha_j = rho_{j-1} / (rhat, v); s = r - alpha v.  nrec: the records of the
-// v pass (launch_stab_v: 0; the t-marching pass: march_records(g, 1, sizeof(S))).
+// v pass (launch_stab_v: 0; the t-marching pass: march_records(g, 1)).
 template <typename S>
 void launch_stab_s(S *s, const S *r, const S *v, size_t N, int j, KrylovState *K, KrylovHistory h,
                    const RedScratch &rs, hipStream_t st, int nrec = 0);
@@ -327,9 +327,8 @@ bool batch_size_ok(int kc);
 constexpr int kTileForms = 7;
 constexpr int kMarchTile = 6;
 bool batch_tile_ok(const Geom &g, bool eo, int stage, int kc);
-// Records (blocks) of a t-marching pass on kc columns of cbytes-byte complex
-// entries (the form must fit).
-int march_records(const Geom &g, int kc, int cbytes);
+// Records (blocks) of a t-marching pass on kc columns (the form must fit).
+int march_records(const Geom &g, int kc);
 // The BiCG matvec pair (as launch_bicg_matvec) in the t-marching form with one
 // column (full-lattice operator, batch_tile_ok(g, false, kMarchTile, 1)); it
 // writes bicg_matvec_march_records(g, g5) sigma records.

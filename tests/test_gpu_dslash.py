@@ -166,9 +166,10 @@ def _boundary_sites(dims, n=32, seed=0):
 
 
 def _one_column_march_fp64(gpu_lib, op, U, dims, kappa, seed):
-    """FP64 D and D^+ with one column in the t-marching form (16-slice chunks at
-    24^3 x 64, 32-slice chunks at 32^3 x 64) and in the LDS-staged form, at the
-    chunk- and box-boundary sites, against the per-site oracle (1e-12)."""
+    """FP64 D and D^+ with one column in the t-marching form (8-slice chunks at
+    24^3 x 64, 16-slice chunks at 32^3 x 64, boxes of 8 z planes) and in the
+    LDS-staged form, at the chunk- and box-boundary sites, against the per-site
+    oracle (1e-12)."""
     import torch
 
     V = synth.volume(dims)

@@ -248,8 +248,8 @@ def lat24(gpu_lib):
 
 def test_24x64_fp64_solves_checked_with_oracle(gpu_lib, lat24):
     """One FP64 eigBiCG solve (it grows the space) and one deflated BiCGStab solve (its
-    stencil passes in the t-marching form, 16-slice chunks); each solution's residual
-    with the oracle's D over the whole lattice."""
+    stencil passes in the t-marching form); each solution's residual with the oracle's
+    D over the whole lattice."""
     import torch
 
     dims, kappa, U, op = lat24
