@@ -16,13 +16,17 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libebicg.so")
 ARCH = "gfx950"
 
-# device code: no packed-FP32 instructions (some of their forms gave wrong results on MI355X)
+# device code: no packed-FP32 instructions (some of their forms gave wrong results on MI355X);
+# matrix instructions with their accumulators in ordinary VGPRs: left to its heuristics the
+# compiler kept the accumulators of the tiled products in VGPRs but issued the AGPR form,
+# copying 8 registers in and out around every pair of MFMAs and draining the pipeline between them
 HIP_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
     f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result",
 ]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fcx-limited-range"]

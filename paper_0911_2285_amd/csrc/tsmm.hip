@@ -301,8 +301,10 @@ __global__ void __launch_bounds__(kBlock)
   extern __shared__ double2 cs[];  // C^T: cs[c KP + k]
   __shared__ int islot[kMaxCols], oslot[KP];
   __shared__ double sd[DOTS ? kBlock / kWave : 1][DOTS ? 2 * KP : 1];
-  const int nin = in_slots.n, nout = out_slots.n, nin4 = (nin + 3) & ~3;
-  for (int e = threadIdx.x; e < nin4 * KP; e += kBlock) {
+  // the K loop runs in steps of 8 input columns (two buffers of 4): C^T is
+  // zero-padded to a multiple of 8 rows
+  const int nin = in_slots.n, nout = out_slots.n, nin8 = (nin + 7) & ~7;
+  for (int e = threadIdx.x; e < nin8 * KP; e += kBlock) {
     const int c = e / KP, k = e % KP;
     cs[e] = (c < nin && k < nout) ? C[c + size_t(k) * nin] : make_double2(0.0, 0.0);
   }
@@ -323,24 +325,30 @@ __global__ void __launch_bounds__(kBlock)
     Acc re[OT], im[OT];
 #pragma unroll
     for (int t = 0; t < OT; ++t) re[t] = im[t] = Acc{E(0), E(0), E(0), E(0)};
-    for (int c0 = 0; c0 < nin4; c0 += 4) {
-      const int c = c0 + q;
-      E br = E(0), bi = E(0);
-      if (c < nin && in) {
-        int sc = islot[c];
-        bool flip = false;
-        if constexpr (G5IN) {
-          flip = sc < 0;
-          if (flip) sc = -sc - 1;
-        }
-        const TI x = in_base[size_t(sc) * ldi + i];
-        br = E(x.x);
-        bi = E(x.y);
-        if (flip && i >= half) {
-          br = -br;
-          bi = -bi;
-        }
+    // entry i of input column c, gamma5 applied on request.  Past the inputs
+    // (c >= nin) or past N a valid entry (column slot islot[0], entry 0) is
+    // read instead: the padded rows of C^T are zero, and rows past N are
+    // neither stored nor dotted (g is taken as 0 there), so every load is
+    // unconditional and nothing but the products reads its value
+    const size_t ii = in ? i : 0;
+    auto load = [&](int c, E &br, E &bi) {
+      int sc = islot[c < nin ? c : 0];
+      bool flip = false;
+      if constexpr (G5IN) {
+        flip = sc < 0;
+        if (flip) sc = -sc - 1;
       }
+      const TI x = in_base[size_t(sc) * ldi + ii];
+      br = E(x.x);
+      bi = E(x.y);
+      if (flip && i >= half) {
+        br = -br;
+        bi = -bi;
+      }
+    };
+    // the products of input columns c0 .. c0 + 3 (this lane's column c0 + q)
+    auto step = [&](int c0, E br, E bi) {
+      const int c = c0 + q;
 #pragma unroll
       for (int t = 0; t < OT; ++t) {
         const double2 a = cs[c * KP + kTile * t + r];
@@ -349,6 +357,24 @@ __global__ void __launch_bounds__(kBlock)
         re[t] = mfma16(-ay, bi, re[t]);
         im[t] = mfma16(ax, bi, im[t]);
         im[t] = mfma16(ay, br, im[t]);
+      }
+    };
+    // two input buffers: the next step's entry is requested before this
+    // step's products, so a load is in flight while the matrix instructions
+    // run (the scheduling barriers keep the compiler from gathering the loads
+    // at the top of the loop, where each would be waited for at once)
+    if (nin > 0) {
+      E ar, ai, br, bi;
+      load(q, ar, ai);
+      for (int c0 = 0; c0 < nin8; c0 += 8) {
+        load(c0 + 4 + q, br, bi);
+        __builtin_amdgcn_sched_barrier(0);
+        step(c0, ar, ai);
+        __builtin_amdgcn_sched_barrier(0);
+        load(c0 + 8 + q, ar, ai);
+        __builtin_amdgcn_sched_barrier(0);
+        step(c0 + 4, br, bi);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     double2 gv = make_double2(0.0, 0.0);
@@ -509,7 +535,7 @@ void launch_combine_t(TO *out_base, const SlotList &out_slots, size_t ldo, const
     auto go = [&](auto ot_tag, auto dots_tag, auto g5_tag) {
       constexpr int T = decltype(ot_tag)::value;
       constexpr bool D = decltype(dots_tag)::value, G = decltype(g5_tag)::value;
-      const size_t lds = size_t((nin + 3) & ~3) * kTile * T * sizeof(double2);
+      const size_t lds = size_t((nin + 7) & ~7) * kTile * T * sizeof(double2);
       // the kernel's static LDS (slot lists, dot sums) comes on top of this; past 64 KB in
       // all a workgroup needs the larger limit set (gfx950 holds 160 KB per workgroup)
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rotate_mfma<TI, TO, T, D, G>),
