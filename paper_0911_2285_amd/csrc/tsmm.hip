@@ -298,7 +298,11 @@ __global__ void __launch_bounds__(kBlock)
   using Acc = typename std::conditional<F32, fx4, dx4>::type;
   // output row of component v of lane (r, q) in a 16 x 16 tile
   auto orow = [](int q, int v) { return F32 ? 4 * q + v : q + 4 * v; };
-  extern __shared__ double2 cs[];  // C^T: cs[c KP + k]
+  // C^T: cs[c KP + k], in the product type (FP32 coefficients for the FP32
+  // window: half the LDS, so more blocks fit a CU)
+  using CS = typename std::conditional<F32, float2, double2>::type;
+  extern __shared__ double2 cs_lds[];
+  CS *cs = reinterpret_cast<CS *>(cs_lds);
   __shared__ int islot[kMaxCols], oslot[KP];
   __shared__ double sd[DOTS ? kBlock / kWave : 1][DOTS ? 2 * KP : 1];
   // the K loop runs in steps of 8 input columns (two buffers of 4): C^T is
@@ -306,7 +310,8 @@ __global__ void __launch_bounds__(kBlock)
   const int nin = in_slots.n, nout = out_slots.n, nin8 = (nin + 7) & ~7;
   for (int e = threadIdx.x; e < nin8 * KP; e += kBlock) {
     const int c = e / KP, k = e % KP;
-    cs[e] = (c < nin && k < nout) ? C[c + size_t(k) * nin] : make_double2(0.0, 0.0);
+    const double2 a = (c < nin && k < nout) ? C[c + size_t(k) * nin] : make_double2(0.0, 0.0);
+    cs[e] = CS{E(a.x), E(a.y)};
   }
   for (int c = threadIdx.x; c < kMaxCols; c += kBlock) islot[c] = c < nin ? in_slots.idx[c] : 0;
   for (int k = threadIdx.x; k < KP; k += kBlock) oslot[k] = k < nout ? out_slots.idx[k] : 0;
@@ -351,8 +356,8 @@ __global__ void __launch_bounds__(kBlock)
       const int c = c0 + q;
 #pragma unroll
       for (int t = 0; t < OT; ++t) {
-        const double2 a = cs[c * KP + kTile * t + r];
-        const E ax = E(a.x), ay = E(a.y);
+        const CS a = cs[c * KP + kTile * t + r];
+        const E ax = a.x, ay = a.y;
         re[t] = mfma16(ax, br, re[t]);
         re[t] = mfma16(-ay, bi, re[t]);
         im[t] = mfma16(ax, bi, im[t]);
@@ -535,7 +540,8 @@ void launch_combine_t(TO *out_base, const SlotList &out_slots, size_t ldo, const
     auto go = [&](auto ot_tag, auto dots_tag, auto g5_tag) {
       constexpr int T = decltype(ot_tag)::value;
       constexpr bool D = decltype(dots_tag)::value, G = decltype(g5_tag)::value;
-      const size_t lds = size_t((nin + 7) & ~7) * kTile * T * sizeof(double2);
+      constexpr bool F32 = std::is_same<TI, float2>::value && std::is_same<TO, float2>::value;
+      const size_t lds = size_t((nin + 7) & ~7) * kTile * T * (F32 ? sizeof(float2) : sizeof(double2));
       // the kernel's static LDS (slot lists, dot sums) comes on top of this; past 64 KB in
       // all a workgroup needs the larger limit set (gfx950 holds 160 KB per workgroup)
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rotate_mfma<TI, TO, T, D, G>),
