@@ -305,10 +305,8 @@ __global__ void __launch_bounds__(kBlock)
   CS *cs = reinterpret_cast<CS *>(cs_lds);
   __shared__ int islot[kMaxCols], oslot[KP];
   __shared__ double sd[DOTS ? kBlock / kWave : 1][DOTS ? 2 * KP : 1];
-  // the K loop runs in steps of 8 input columns (two buffers of 4): C^T is
-  // zero-padded to a multiple of 8 rows
-  const int nin = in_slots.n, nout = out_slots.n, nin8 = (nin + 7) & ~7;
-  for (int e = threadIdx.x; e < nin8 * KP; e += kBlock) {
+  const int nin = in_slots.n, nout = out_slots.n, nin4 = (nin + 3) & ~3;
+  for (int e = threadIdx.x; e < nin4 * KP; e += kBlock) {
     const int c = e / KP, k = e % KP;
     const double2 a = (c < nin && k < nout) ? C[c + size_t(k) * nin] : make_double2(0.0, 0.0);
     cs[e] = CS{E(a.x), E(a.y)};
@@ -371,7 +369,8 @@ __global__ void __launch_bounds__(kBlock)
     if (nin > 0) {
       E ar, ai, br, bi;
       load(q, ar, ai);
-      for (int c0 = 0; c0 < nin8; c0 += 8) {
+      int c0 = 0;
+      for (; c0 + 8 <= nin4; c0 += 8) {
         load(c0 + 4 + q, br, bi);
         __builtin_amdgcn_sched_barrier(0);
         step(c0, ar, ai);
@@ -381,6 +380,7 @@ __global__ void __launch_bounds__(kBlock)
         step(c0 + 4, br, bi);
         __builtin_amdgcn_sched_barrier(0);
       }
+      if (c0 < nin4) step(c0, ar, ai);  // the last 4 columns when nin4 is not a multiple of 8
     }
     double2 gv = make_double2(0.0, 0.0);
     if (DOTS && in) gv = g[i];
@@ -541,7 +541,7 @@ void launch_combine_t(TO *out_base, const SlotList &out_slots, size_t ldo, const
       constexpr int T = decltype(ot_tag)::value;
       constexpr bool D = decltype(dots_tag)::value, G = decltype(g5_tag)::value;
       constexpr bool F32 = std::is_same<TI, float2>::value && std::is_same<TO, float2>::value;
-      const size_t lds = size_t((nin + 7) & ~7) * kTile * T * (F32 ? sizeof(float2) : sizeof(double2));
+      const size_t lds = size_t((nin + 3) & ~3) * kTile * T * (F32 ? sizeof(float2) : sizeof(double2));
       // the kernel's static LDS (slot lists, dot sums) comes on top of this; past 64 KB in
       // all a workgroup needs the larger limit set (gfx950 holds 160 KB per workgroup)
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rotate_mfma<TI, TO, T, D, G>),
