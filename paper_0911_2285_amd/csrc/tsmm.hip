@@ -329,9 +329,9 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int t = 0; t < OT; ++t) re[t] = im[t] = Acc{E(0), E(0), E(0), E(0)};
     // entry i of input column c, gamma5 applied on request.  Past the inputs
-    // (c >= nin) or past N a valid entry (column slot islot[0], entry 0) is
-    // read instead: the padded rows of C^T are zero, and rows past N are
-    // neither stored nor dotted (g is taken as 0 there), so every load is
+    // (c >= nin) the first input column is read instead, and past N its
+    // entry 0: the padded rows of C^T are zero, and rows past N are neither
+    // stored nor dotted (g is taken as 0 there), so every load is
     // unconditional and nothing but the products reads its value
     const size_t ii = in ? i : 0;
     auto load = [&](int c, E &br, E &bi) {
