@@ -661,8 +661,9 @@ def _find_csv(path, suffix):
 
 def eigbicg_pass(eb, mode, workload="inc16x32"):
     """The eigBiCG gap workload for a kernel trace: the workload's lattice, nev and
-    m (16^3 x 32: nev 10, m 40; 32^3 x 64: nev 25, m 60), tol 1e-10, FP64 window,
-    host or device restart; one warm-up solve, three marker launches (D on a 2^4
+    m (16^3 x 32: nev 10, m 40; 32^3 x 64: nev 25, m 60), tol 1e-10, FP64 window
+    with the host or the device restart, or (fp32) the FP32 window with the device
+    restart; one warm-up solve, three marker launches (D on a 2^4
     operator), two timed solves from an empty space, three more markers.  Prints
     iterations, restarts and ms per iteration."""
     import torch
@@ -680,7 +681,9 @@ def eigbicg_pass(eb, mode, workload="inc16x32"):
     mb = torch.ones(16, 4, 3, dtype=torch.complex128, device="cuda:0")
     mo = torch.empty_like(mb)
     B = [torch.from_numpy(synth.z2_source(V, synth.rhs_seed(W["cfg"], i))).to("cuda:0") for i in range(3)]
-    kw = dict(nev=W["nev"], m=W["m"], tol=1e-10, window="fp64", device_eig=(mode == "device"))
+    # fp32: the FP32 window with the device restart
+    kw = dict(nev=W["nev"], m=W["m"], tol=1e-10, window="fp32" if mode == "fp32" else "fp64",
+              device_eig=(mode != "host"))
     eb.eigbicg_solve(op, B[0], torch.zeros_like(B[0]), **kw)
     eb.defl_reset(op)
     torch.cuda.synchronize()
@@ -1273,7 +1276,7 @@ def main():
                     help="one pass of the workload's roofline kernel and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_<kernel>_<workload>.json from two counter runs")
-    ap.add_argument("--eigbicg-pass", choices=("host", "device"),
+    ap.add_argument("--eigbicg-pass", choices=("host", "device", "fp32"),
                     help="two eigBiCG solves between marker launches, for rocprofv3 --kernel-trace")
     ap.add_argument("--eigbicg-workload", default="inc16x32", choices=sorted(WORKLOADS),
                     help="lattice, nev and m of --eigbicg-pass and --summarize-gap")
