@@ -863,7 +863,7 @@ def measured_traffic(workload, cls, k=None):
 # The 16^3 x 32 incremental step (a side record: its fields sit in the 256 MB
 # Infinity Cache, so its stencil rates are effective, not HBM, rates)
 # ---------------------------------------------------------------------------
-def eigbicg_modes(eb, op, B, W, n, modes=(("fp64", False), ("fp64", True), ("fp32", True))):
+def eigbicg_modes(eb, op, B, W, n, modes=(("fp64", False), ("fp64", True), ("fp32", False), ("fp32", True))):
     """eigBiCG on the first n sources in each (window storage, device restart) mode,
     from an empty space each time, after one untimed solve of the mode:
     milliseconds per iteration, iterations, restarts."""
