@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(kBlock)
     Acc re[OT], im[OT];
 #pragma unroll
     for (int t = 0; t < OT; ++t) re[t] = im[t] = Acc{E(0), E(0), E(0), E(0)};
-    // entry i of input column c, gamma5 applied on request.  Past the inputs
+    // entry i of input column c.  Past the inputs
     // (c >= nin) the first input column is read instead, and past N its
     // entry 0: the padded rows of C^T are zero, and rows past N are neither
     // stored nor dotted (g is taken as 0 there), so every load is
@@ -336,22 +336,23 @@ __global__ void __launch_bounds__(kBlock)
     const size_t ii = in ? i : 0;
     auto load = [&](int c, E &br, E &bi) {
       int sc = islot[c < nin ? c : 0];
-      bool flip = false;
       if constexpr (G5IN) {
-        flip = sc < 0;
-        if (flip) sc = -sc - 1;
+        if (sc < 0) sc = -sc - 1;
       }
       const TI x = in_base[size_t(sc) * ldi + ii];
       br = E(x.x);
       bi = E(x.y);
-      if (flip && i >= half) {
-        br = -br;
-        bi = -bi;
-      }
     };
-    // the products of input columns c0 .. c0 + 3 (this lane's column c0 + q)
+    // the products of input columns c0 .. c0 + 3 (this lane's column c0 + q);
+    // gamma5 is applied here, where the entry is used, not where it is loaded
     auto step = [&](int c0, E br, E bi) {
       const int c = c0 + q;
+      if constexpr (G5IN) {
+        if (islot[c < nin ? c : 0] < 0 && i >= half) {
+          br = -br;
+          bi = -bi;
+        }
+      }
 #pragma unroll
       for (int t = 0; t < OT; ++t) {
         const CS a = cs[c * KP + kTile * t + r];
