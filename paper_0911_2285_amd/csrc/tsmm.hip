@@ -328,11 +328,11 @@ __global__ void __launch_bounds__(kBlock)
     Acc re[OT], im[OT];
 #pragma unroll
     for (int t = 0; t < OT; ++t) re[t] = im[t] = Acc{E(0), E(0), E(0), E(0)};
-    // entry i of input column c.  Past the inputs
-    // (c >= nin) the first input column is read instead, and past N its
-    // entry 0: the padded rows of C^T are zero, and rows past N are neither
-    // stored nor dotted (g is taken as 0 there), so every load is
-    // unconditional and nothing but the products reads its value
+    // entry i of input column c.  Past the inputs (c >= nin) the first input
+    // column is read instead, and past N its entry 0: the padded rows of C^T
+    // are zero, and rows past N are neither stored nor dotted (g is taken as
+    // 0 there), so every load is unconditional and nothing but the products
+    // reads its value
     const size_t ii = in ? i : 0;
     auto load = [&](int c, E &br, E &bi) {
       int sc = islot[c < nin ? c : 0];
