@@ -150,6 +150,8 @@ struct eb_op {
   // form of the BiCG matvec pair: 1 LDS-staged tiles, kMarchTile t-marching
   // boxes, -1 not chosen yet (timed at the next solve); matvec_ms[form]
   int matvec_form = -1;
+  // grid cap of the staged pair, chosen with its form (0: grid_cap)
+  int matvec_cap = 0;
   double matvec_ms[kTileForms] = {};
   double batch_ms[3][kMaxBatch + 1] = {};
   // tile form of the batched stencils per precision and k (1: LDS-staged
@@ -450,14 +452,21 @@ int single_stab_form(eb_op *op, const S *U, const S *src, S *dst, hipStream_t s)
 
 // Form of the BiCG matvec pair (D p with sigma, D^+ phat) on a full-lattice
 // operator: the LDS-staged work items or the t-marching units, as set, or
-// else both timed once (three launches each after one, on the solve's p,
-// phat and product buffers, before its first iteration) and the faster kept.
-// Even-odd operators run Dhat.
+// else timed once (three launches each after one, on the solve's p, phat and
+// product buffers, before its first iteration) and the fastest kept.  The
+// staged pair is timed at the operator's grid cap and, unless a test set
+// that cap, also with one tile per block, as many as the sigma record region
+// holds: at 24^3 x 64 that
+// grid ran the pair in 392 against 473-489 us, at 32^3 x 64 it was slower
+// (995-1037 against 925-954 us).  A chosen wider grid is made this entry
+// point's stencil cap, so the records the matvec writes and the count its
+// consumer sums stay the same.  Even-odd operators run Dhat.
 int bicg_matvec_form(eb_op *op, double2 *Ap, double2 *Adp, const double2 *p, const double2 *ph, KrylovState *S,
                      hipStream_t s) {
   if (op->eo) return 1;
   if (op->matvec_form < 0) {
     op->matvec_form = 1;
+    op->matvec_cap = 0;
     if (batch_tile_ok(op->g, false, kMarchTile, 1)) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
@@ -465,9 +474,21 @@ int bicg_matvec_form(eb_op *op, double2 *Ap, double2 *Adp, const double2 *p, con
       double best = HUGE_VAL;
       const double2 *U = op->U64.as<double2>();
       KrylovHistory none{};
-      for (int form : {1, kMarchTile}) {
+      // one tile per block up to the blocks whose sigma records (two per tile
+      // in the general form, of two doubles each) fill a record region; on
+      // lattices of at most kDefaultStencilCap tiles this is the same grid
+      const int wide = int(kRegionDoubles / 4);
+      struct Cand {
+        int form, cap;
+      };
+      std::vector<Cand> cands{{1, 0}};
+      if (op->grid_cap == kDefaultStencilCap) cands.push_back({1, wide});
+      cands.push_back({kMarchTile, 0});
+      op->matvec_ms[1] = op->matvec_ms[kMarchTile] = 0.0;
+      for (const Cand &cd : cands) {
+        stencil_block_cap() = cd.cap > 0 ? cd.cap : op->grid_cap;
         auto run = [&]() {  // j = 0: no stop flag of an earlier solve skips it
-          if (form == kMarchTile)
+          if (cd.form == kMarchTile)
             launch_bicg_matvec_march(Ap, Adp, p, ph, U, op->g, op->kappa, 0, S, op->rs(), false, s);
           else
             launch_bicg_matvec(Ap, Adp, p, ph, U, op->g, op->kappa, 0, S, none, op->rs(), false, s);
@@ -479,16 +500,20 @@ int bicg_matvec_form(eb_op *op, double2 *Ap, double2 *Adp, const double2 *p, con
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        op->matvec_ms[form] = ms / 3.0;
+        double &slot = op->matvec_ms[cd.form];  // the staged pair: its faster grid
+        if (slot == 0.0 || ms / 3.0 < slot) slot = ms / 3.0;
         if (ms < best) {
           best = ms;
-          op->matvec_form = form;
+          op->matvec_form = cd.form;
+          op->matvec_cap = cd.cap;
         }
       }
+      stencil_block_cap() = op->grid_cap;
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }
   }
+  if (op->matvec_form == 1 && op->matvec_cap > 0) stencil_block_cap() = op->matvec_cap;
   return op->matvec_form;
 }
 
@@ -2980,6 +3005,7 @@ eb_status eb_op_set_matvec_form(eb_op *op, int32_t form) {
     if (form == kMarchTile && !batch_tile_ok(op->g, op->eo, kMarchTile, 1))
       fail(EB_ERR_INVALID, "the t-marching matvec needs a full-lattice operator whose box fits");
     op->matvec_form = form;
+    op->matvec_cap = 0;  // a forced staged pair runs at the operator's grid cap
   });
 }
 
