@@ -152,6 +152,9 @@ struct eb_op {
   int matvec_form = -1;
   // grid cap of the staged pair, chosen with its form (0: grid_cap)
   int matvec_cap = 0;
+  // grid cap of the staged one-column BiCGStab passes per storage (FP64, FP32,
+  // BF16), chosen with the k = 1 form (0: grid_cap)
+  int stab_cap[3] = {0, 0, 0};
   double matvec_ms[kTileForms] = {};
   double batch_ms[3][kMaxBatch + 1] = {};
   // tile form of the batched stencils per precision and k (1: LDS-staged
@@ -412,41 +415,82 @@ struct StabResult {
   double rnorm = 0;
 };
 
+// Time of the one-column t pass (t = D s with its dots) in tile form
+// `stage`: 1 the LDS-staged pass at grid cap `cap` (0: the operator's),
+// kMarchTile the t-marching walk; one launch, then the mean of three.
+template <typename S>
+double one_column_pass_ms(eb_op *op, const S *U, const S *src, S *dst, int stage, int cap, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
+  stencil_block_cap() = cap > 0 ? cap : op->grid_cap;
+  KrylovHistory none{};
+  auto run = [&]() {  // j = 0: no stop flag of an earlier solve skips it
+    if (stage == kMarchTile)
+      launch_bstab_t<S>(dst, src, U, op->g, op->kappa, 0, 1, op->S(), op->rs(), s, kMarchTile);
+    else
+      launch_stab_t<S>(dst, src, U, op->g, op->kappa, 0, op->S(), none, op->rs(), s);
+  };
+  run();
+  HIPCHK(hipEventRecord(e0, s));
+  for (int rep = 0; rep < 3; ++rep) run();
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  stencil_block_cap() = op->grid_cap;
+  return ms / 3.0;
+}
+
+// The k = 1 entry of the tuning table for storage index pi on a full-lattice
+// operator, from the solver's own t pass (D alone misleads: at 32^3 x 64 the
+// staged D runs 701 us against 510 us marching, while the staged t pass runs
+// 492 us against 571): the staged pass at the operator's grid cap, the staged
+// pass with one tile per block (unless a test set the cap; up to the 32 768
+// blocks whose records fill a region), and the t-marching walk.  The fastest
+// goes into batch_stage[pi][1] with its cap in stab_cap[pi]; the times into
+// batch_stage_ms[pi][1] (the staged entry: its faster grid).
+template <typename S>
+void tune_one_column(eb_op *op, int pi, const S *U, const S *src, S *dst, hipStream_t s) {
+  struct Cand {
+    int stage, cap;
+  };
+  std::vector<Cand> cands{{1, 0}};
+  if (op->grid_cap == kDefaultStencilCap) cands.push_back({1, int(kRegionDoubles / 4)});
+  if (batch_tile_ok(op->g, false, kMarchTile, 1)) cands.push_back({kMarchTile, 0});
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  op->batch_stage_ms[pi][1][1] = op->batch_stage_ms[pi][1][kMarchTile] = 0.0;
+  op->batch_stage[pi][1] = 1;
+  op->stab_cap[pi] = 0;
+  double best = HUGE_VAL;
+  for (const Cand &cd : cands) {
+    const double t = one_column_pass_ms<S>(op, U, src, dst, cd.stage, cd.cap, s, e0, e1);
+    double &slot = op->batch_stage_ms[pi][1][cd.stage];
+    if (slot == 0.0 || t < slot) slot = t;
+    if (t < best) {
+      best = t;
+      op->batch_stage[pi][1] = cd.stage;
+      op->stab_cap[pi] = cd.cap;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 // Stencil form of the one-column BiCGStab on a full-lattice operator: the
-// LDS-staged tiles (1) or t-marching boxes (kMarchTile), whichever the k = 1
-// entry of the batch tuning table names; if the table has none, both are timed
-// once (D on src into dst, three launches each after one) and the faster is
-// kept there.  Even-odd operators run Dhat (form 1).
+// LDS-staged passes (1) or the t-marching walk (kMarchTile), whichever the
+// k = 1 entry of the batch tuning table names, timed on the t pass
+// (tune_one_column) when the table has none.  A staged choice with a wider
+// grid becomes this entry point's stencil cap, so the records each pass
+// writes and the count its consumer sums stay the same.  Even-odd operators
+// run Dhat (form 1).
 template <typename S>
 int single_stab_form(eb_op *op, const S *U, const S *src, S *dst, hipStream_t s) {
   if (op->eo) return 1;
   const int pi = std::is_same<S, double2>::value ? 0 : (std::is_same<S, float2>::value ? 1 : 2);
-  int &f = op->batch_stage[pi][1];
-  if (f < 0) {
-    f = 1;
-    if (batch_tile_ok(op->g, false, kMarchTile, 1)) {
-      hipEvent_t e0, e1;
-      HIPCHK(hipEventCreate(&e0));
-      HIPCHK(hipEventCreate(&e1));
-      double best = HUGE_VAL;
-      for (int stage : {1, kMarchTile}) {
-        launch_bdslash<S>(dst, src, U, op->g, op->kappa, false, 1, s, stage);
-        HIPCHK(hipEventRecord(e0, s));
-        for (int rep = 0; rep < 3; ++rep) launch_bdslash<S>(dst, src, U, op->g, op->kappa, false, 1, s, stage);
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        op->batch_stage_ms[pi][1][stage] = ms / 3.0;
-        if (ms < best) {
-          best = ms;
-          f = stage;
-        }
-      }
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-    }
-  }
+  if (op->batch_stage[pi][1] < 0) tune_one_column<S>(op, pi, U, src, dst, s);
+  const int f = op->batch_stage[pi][1];
+  if (f == 1 && op->stab_cap[pi] > 0) stencil_block_cap() = op->stab_cap[pi];
   return f == kMarchTile ? kMarchTile : 1;
 }
 
@@ -852,6 +896,13 @@ int tune_batch(eb_op *op, hipStream_t s) {
   const int pi = Inner<S>::index;
   for (int kc = 1; kc <= kMaxBatch; kc *= 2) {
     double t_kc = HUGE_VAL;
+    if (kc == 1 && !op->eo) {  // one column runs the one-at-a-time solver: its own pass
+      tune_one_column<S>(op, pi, U, a, b, s);
+      t_kc = op->batch_stage_ms[pi][1][op->batch_stage[pi][1]];
+      op->batch_ms[pi][kc] = t_kc;
+      best_t = t_kc;
+      continue;
+    }
     for (int stage = 0; stage < kTileForms; ++stage) {  // every tile form this operator admits
       if (!batch_tile_ok(op->g, op->eo, stage, kc)) continue;
       // one column runs the one-at-a-time solver, whose stencils take the
@@ -2995,6 +3046,7 @@ eb_status eb_op_batch_set_tile(eb_op *op, eb_prec prec, int32_t k, int32_t stage
       fail(EB_ERR_INVALID,
            "tile form must be -1, 0 or 1, or 2..6 on a full-lattice operator whose extents the form's brick or box fits");
     op->batch_stage[prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2)][k] = stage;
+    if (k == 1) op->stab_cap[prec == EB_FP64 ? 0 : (prec == EB_FP32 ? 1 : 2)] = 0;  // a forced form: the grid cap
   });
 }
 
